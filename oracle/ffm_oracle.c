@@ -1,0 +1,882 @@
+/*
+ * ffm_oracle.c -- FP64 CPU oracle for the Fast Free Memory method.
+ *
+ * TEST INFRASTRUCTURE: only the tests, the smoke check and the CPU baseline
+ * leg of the benchmark load this file's library.  It shares no code with the
+ * GPU library.  Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off (the
+ * geometry steps must round every operation separately).
+ *
+ * The FFM approximates the discrete convolution of Sec. 1 (eqs.
+ * convolution_discrete / convolution_matrix) by a descent over two octrees
+ * with cubic roots of the same edge (Sec. 2.1, 2.2.1).  At every level the
+ * admissible ("far") box pairs are compressed either by Chebyshev/Lagrange
+ * interpolation (Sec. 2.2.2) or, for oscillatory Helmholtz levels, by the
+ * Gegenbauer plane-wave form (Sec. 2.2.3); the other pairs are split into
+ * their children.  The descent stops by the rule of Sec. 2.2.4 and the
+ * remaining pairs are summed densely.
+ *
+ * Readings where the paper is silent or ambiguous (each also listed in the
+ * design notes):
+ *   R1  each root cube is centred on its set's bounding box; the cube edge d_0
+ *       is the largest bounding-box edge over both sets (d_0 = 1 if zero).
+ *   R2  a pair is admissible iff the max-norm distance of the box centres is
+ *       >= 2 d_l.  This reproduces the 2-D counts of the proof of Prop. 1
+ *       (27 interactions of an interior box, 40 distinct translations).
+ *   R3  the root pair is near; classification starts at level 1.
+ *   R4  stop at the first level l >= 1 whose near list is empty, or whose
+ *       average occupancy (N_X+N_Y)/(nb_X+nb_Y) is <= n_leaf (integer test),
+ *       or at the depth cap.
+ *   R5  Chebyshev nodes of the first kind, r1 = ceil(ln(1/eps)/ln(3+sqrt 8))
+ *       per axis (+ ceil(k d_l / 2) at Helmholtz Lagrange levels).
+ *   R6  Helmholtz levels use the Gegenbauer form iff k d_l >= kappa (pi).
+ *   R7  L = floor(k sqrt(3) d_l - ln eps) with the natural log, L >= 1.
+ *   R8  the Gegenbauer series starts at p = 0.
+ *   R9  box-centred coordinates and no extra phase factor:
+ *       G ~ sum_q e^{ik s_q.(x-x0)} D(q) e^{-ik s_q.(y-y0)},
+ *       D(q) = (ik/4pi) w_q T_{L,r0}(s_q), r0 = x0 - y0.
+ *   R10 quadrature: (L+1) Gauss-Legendre nodes in cos(theta) times 2L
+ *       equispaced phi = pi n / L, weight w_m pi / L  (n_Q = 2L(L+1)).
+ *   R11 coincident points (r == 0) contribute nothing.
+ *   R12 Morton keys: 21 bits per axis, x in the highest bit of each triple.
+ */
+#include "ffm_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define BITS 21
+#define QMAX ((int64_t)1 << BITS)
+#define ORC_PI 3.14159265358979323846
+
+/* =========================================================================
+ * Kernels (Sec. 4.1 eq. laplaceGreenKernel; Sec. 2.2.3 eq. helmholtzKernel)
+ * ========================================================================= */
+static double complex green(int kernel, double k, double r)
+{
+    if (kernel == ORC_LAPLACE) return 1.0 / (4.0 * ORC_PI * r);
+    return cexp(I * (k * r)) / (4.0 * ORC_PI * r);
+}
+
+static double complex cload(const double *a, int64_t i) { return a[2 * i] + I * a[2 * i + 1]; }
+
+/* The plain definition (Sec. 1, eq. convolution_discrete) on sampled rows. */
+void orc_dense_rows(const double *X, const double *Y, int64_t ny, const double *wu,
+                    int kernel, double k, const int64_t *rows, int64_t nrows, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t a = 0; a < nrows; ++a) {
+        const double *x = X + 3 * rows[a];
+        double complex acc = 0.0;
+        for (int64_t j = 0; j < ny; ++j) {
+            double dx = x[0] - Y[3 * j], dy = x[1] - Y[3 * j + 1], dz = x[2] - Y[3 * j + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;                       /* R11 */
+            acc += green(kernel, k, sqrt(r2)) * cload(wu, j);
+        }
+        out[2 * a] = creal(acc);
+        out[2 * a + 1] = cimag(acc);
+    }
+}
+
+/* =========================================================================
+ * Special functions and quadratures
+ * ========================================================================= */
+
+/* Legendre polynomials by Bonnet's recurrence. */
+void orc_legendre_p(int L, double t, double *P)
+{
+    P[0] = 1.0;
+    if (L >= 1) P[1] = t;
+    for (int p = 1; p < L; ++p) P[p + 1] = ((2.0 * p + 1.0) * t * P[p] - p * P[p - 1]) / (p + 1.0);
+}
+
+/* Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_n. */
+void orc_gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(ORC_PI * (i + 0.75) / (n + 0.5));
+        double pn = 0.0, pm = 0.0, dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            pm = 1.0;
+            pn = z;
+            for (int j = 1; j < n; ++j) {
+                double nx = ((2.0 * j + 1.0) * z * pn - j * pm) / (j + 1.0);
+                pm = pn;
+                pn = nx;
+            }
+            dp = n * (z * pn - pm) / (z * z - 1.0);
+            double dz = pn / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        /* re-evaluate the derivative at the converged node for the weight */
+        pm = 1.0;
+        pn = z;
+        for (int j = 1; j < n; ++j) {
+            double nx = ((2.0 * j + 1.0) * z * pn - j * pm) / (j + 1.0);
+            pm = pn;
+            pn = nx;
+        }
+        dp = n * (z * pn - pm) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* Spherical Hankel functions of the first kind h_p = j_p + i y_p, p = 0..L, by upward
+ * recurrence from h_0 = -i e^{iz}/z and h_1 = -e^{iz}(z + i)/z^2. */
+void orc_sph_hankel1(int L, double z, double *h)
+{
+    double complex e = cexp(I * z);
+    double complex hm = -I * e / z;
+    h[0] = creal(hm);
+    h[1] = cimag(hm);
+    if (L < 1) return;
+    double complex hp = -e * (z + I) / (z * z);
+    h[2] = creal(hp);
+    h[3] = cimag(hp);
+    for (int p = 1; p < L; ++p) {
+        double complex hn = (2.0 * p + 1.0) / z * hp - hm;
+        hm = hp;
+        hp = hn;
+        h[2 * (p + 1)] = creal(hp);
+        h[2 * (p + 1) + 1] = cimag(hp);
+    }
+}
+
+/* Chebyshev nodes of the first kind, t_a = cos((2a-1) pi / (2 r1)), a = 1..r1 (R5). */
+void orc_cheb_nodes(int r1, double *t)
+{
+    for (int a = 1; a <= r1; ++a) t[a - 1] = cos((2.0 * a - 1.0) * ORC_PI / (2.0 * r1));
+}
+
+/* One-dimensional Lagrange polynomials on the Chebyshev nodes evaluated at t. */
+void orc_lagrange_basis(int r1, double t, double *ell)
+{
+    double nodes[64];
+    orc_cheb_nodes(r1, nodes);
+    for (int a = 0; a < r1; ++a) {
+        double v = 1.0;
+        for (int b = 0; b < r1; ++b)
+            if (b != a) v *= (t - nodes[b]) / (nodes[a] - nodes[b]);
+        ell[a] = v;
+    }
+}
+
+/* Truncation rank of the Gegenbauer series, eq. (gegenbauerRank) with the natural log (R7). */
+int orc_gegenbauer_rank(double k, double d_l, double eps)
+{
+    int L = (int)floor(k * sqrt(3.0) * d_l - log(eps));
+    return L < 1 ? 1 : L;
+}
+
+/* Spherical quadrature of Sec. 3.3 (n_Q = 2L(L+1)), laid out theta-major (R10). */
+int64_t orc_sphere_quadrature(int L, double *s, double *w)
+{
+    int nth = L + 1, nph = 2 * L;
+    double *xm = malloc(sizeof(double) * nth), *wm = malloc(sizeof(double) * nth);
+    orc_gauss_legendre(nth, xm, wm);
+    for (int m = 0; m < nth; ++m) {
+        double ct = xm[m], st = sqrt(1.0 - ct * ct);
+        for (int n = 0; n < nph; ++n) {
+            double ph = ORC_PI * n / L;
+            int64_t q = (int64_t)m * nph + n;
+            s[3 * q] = st * cos(ph);
+            s[3 * q + 1] = st * sin(ph);
+            s[3 * q + 2] = ct;
+            w[q] = wm[m] * ORC_PI / L;
+        }
+    }
+    free(xm);
+    free(wm);
+    return (int64_t)nth * nph;
+}
+
+/* D(q) = (ik/4pi) w_q T_{L,r0}(s_q), with the Gegenbauer series of eq. (gegenbauerSerie)
+ * summed from p = 0 (R8):  T_{L,r0}(s) = sum_p (2p+1) i^p h_p(k|r0|) P_p(s . r0/|r0|) / (4 pi). */
+static void gegenbauer_diag_q(int L, double k, const double r0[3], const double *s, const double *w,
+                              int64_t nq, double complex *D)
+{
+    double rn = sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
+    double *h = malloc(sizeof(double) * 2 * (L + 1));
+    double *P = malloc(sizeof(double) * (L + 1));
+    double complex *c = malloc(sizeof(double complex) * (L + 1));
+    orc_sph_hankel1(L, k * rn, h);
+    double complex ip = 1.0;
+    for (int p = 0; p <= L; ++p) {
+        c[p] = (2.0 * p + 1.0) * ip * (h[2 * p] + I * h[2 * p + 1]) / (4.0 * ORC_PI);
+        ip *= I;
+    }
+    for (int64_t q = 0; q < nq; ++q) {
+        double t = (s[3 * q] * r0[0] + s[3 * q + 1] * r0[1] + s[3 * q + 2] * r0[2]) / rn;
+        orc_legendre_p(L, t, P);
+        double complex T = 0.0;
+        for (int p = 0; p <= L; ++p) T += c[p] * P[p];
+        D[q] = (I * k / (4.0 * ORC_PI)) * w[q] * T;
+    }
+    free(h);
+    free(P);
+    free(c);
+}
+
+void orc_gegenbauer_diag(int L, double k, const double r0[3], double *D)
+{
+    int64_t nq = 2 * (int64_t)L * (L + 1);
+    double *s = malloc(sizeof(double) * 3 * nq), *w = malloc(sizeof(double) * nq);
+    orc_sphere_quadrature(L, s, w);
+    gegenbauer_diag_q(L, k, r0, s, w, nq, (double complex *)D);
+    free(s);
+    free(w);
+}
+
+/* =========================================================================
+ * Trees (Sec. 2.1, 2.2.1, 3.1)
+ * ========================================================================= */
+typedef struct {
+    int64_t n;
+    double corner[3];
+    uint64_t *key;     /* sorted Morton keys                 */
+    int64_t *perm;     /* sorted position -> user index      */
+    double *P;         /* sorted coordinates, n x 3          */
+    int64_t nbox[BITS + 1];
+    int64_t *start[BITS + 1];   /* box b holds sorted points [start[b], start[b+1]) */
+    int32_t *ijk[BITS + 1];     /* integer box coordinates, nbox x 3                */
+    double *ctr[BITS + 1];      /* box centres, nbox x 3                            */
+    int64_t *child[BITS + 1];   /* children of box b at l+1: [child[b], child[b+1]) */
+    int built;                  /* deepest level built so far                       */
+} tree_t;
+
+typedef struct {
+    int64_t n;
+    int64_t *t, *s;
+    int32_t *off;   /* far pairs: integer offset ijk_t - ijk_s */
+} pairs_t;
+
+struct orc_plan {
+    int kernel;
+    double k, eps;
+    orc_options opt;
+    int empty;                 /* one of the sets is empty: v = 0 */
+    int aligned;               /* both corners bitwise equal      */
+    double d0, S;
+    tree_t T[2];               /* 0 = targets X, 1 = sources Y    */
+    int leaf;
+    pairs_t far[BITS + 1];
+    pairs_t near[BITS + 1];
+    int method[BITS + 1];      /* 0 none, 1 Lagrange, 2 Gegenbauer */
+    int order[BITS + 1];       /* r1 or L                          */
+};
+
+/* Morton key: 21 bits per axis interleaved, x in the highest bit of each triple (R12). */
+static uint64_t interleave(int64_t qx, int64_t qy, int64_t qz)
+{
+    uint64_t key = 0;
+    for (int b = 0; b < BITS; ++b) {
+        key |= (uint64_t)((qx >> b) & 1) << (3 * b + 2);
+        key |= (uint64_t)((qy >> b) & 1) << (3 * b + 1);
+        key |= (uint64_t)((qz >> b) & 1) << (3 * b);
+    }
+    return key;
+}
+
+static void deinterleave(uint64_t prefix, int l, int32_t *ijk)
+{
+    int32_t i = 0, j = 0, m = 0;
+    for (int b = 0; b < l; ++b) {
+        i |= (int32_t)((prefix >> (3 * b + 2)) & 1) << b;
+        j |= (int32_t)((prefix >> (3 * b + 1)) & 1) << b;
+        m |= (int32_t)((prefix >> (3 * b)) & 1) << b;
+    }
+    ijk[0] = i;
+    ijk[1] = j;
+    ijk[2] = m;
+}
+
+static int64_t quantise(double p, double corner, double S)
+{
+    double t = (p - corner) * S;
+    double f = floor(t);
+    if (!(f >= 0.0)) return 0;
+    if (f >= (double)(QMAX - 1)) return QMAX - 1;
+    return (int64_t)f;
+}
+
+typedef struct { uint64_t key; int64_t idx; } kv_t;
+
+static int kv_cmp(const void *a, const void *b)
+{
+    const kv_t *x = a, *y = b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+static void tree_build(tree_t *T, const double *P, int64_t n, const double corner[3], double S)
+{
+    T->n = n;
+    memcpy(T->corner, corner, sizeof(double) * 3);
+    kv_t *kv = malloc(sizeof(kv_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        kv[i].key = interleave(quantise(P[3 * i], corner[0], S), quantise(P[3 * i + 1], corner[1], S),
+                               quantise(P[3 * i + 2], corner[2], S));
+        kv[i].idx = i;
+    }
+    qsort(kv, (size_t)n, sizeof(kv_t), kv_cmp);   /* ascending key, ties by original index */
+    T->key = malloc(sizeof(uint64_t) * (size_t)n);
+    T->perm = malloc(sizeof(int64_t) * (size_t)n);
+    T->P = malloc(sizeof(double) * 3 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        T->key[i] = kv[i].key;
+        T->perm[i] = kv[i].idx;
+        memcpy(T->P + 3 * i, P + 3 * kv[i].idx, sizeof(double) * 3);
+    }
+    free(kv);
+    T->built = -1;
+}
+
+/* Boxes of level l: the runs of equal key prefixes key >> 3(21 - l) in sorted order, with
+ * integer coordinates and centres c = corner + (2i + 1) d_0 2^-(l+1) (Sec. 2.2.1, 3.1).
+ * Also links level l-1 to its children. */
+static void tree_level(tree_t *T, int l, double d0)
+{
+    int64_t n = T->n;
+    int sh = 3 * (BITS - l);
+    int64_t nb = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (i == 0 || (T->key[i] >> sh) != (T->key[i - 1] >> sh)) ++nb;
+    T->nbox[l] = nb;
+    T->start[l] = malloc(sizeof(int64_t) * (size_t)(nb + 1));
+    T->ijk[l] = malloc(sizeof(int32_t) * 3 * (size_t)nb);
+    T->ctr[l] = malloc(sizeof(double) * 3 * (size_t)nb);
+    double h = ldexp(d0, -(l + 1));   /* half the box edge at level l */
+    int64_t b = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (i == 0 || (T->key[i] >> sh) != (T->key[i - 1] >> sh)) {
+            T->start[l][b] = i;
+            deinterleave(T->key[i] >> sh, l, T->ijk[l] + 3 * b);
+            for (int d = 0; d < 3; ++d)
+                T->ctr[l][3 * b + d] = T->corner[d] + (double)(2 * T->ijk[l][3 * b + d] + 1) * h;
+            ++b;
+        }
+    }
+    T->start[l][nb] = n;
+    T->child[l] = NULL;
+    if (l > 0) {
+        int64_t np = T->nbox[l - 1];
+        T->child[l - 1] = malloc(sizeof(int64_t) * (size_t)(np + 1));
+        int64_t c = 0;
+        for (int64_t pb = 0; pb < np; ++pb) {
+            while (T->start[l][c] < T->start[l - 1][pb]) ++c;
+            T->child[l - 1][pb] = c;
+        }
+        T->child[l - 1][np] = nb;
+    }
+    T->built = l;
+}
+
+static void tree_free(tree_t *T)
+{
+    free(T->key);
+    free(T->perm);
+    free(T->P);
+    for (int l = 0; l <= T->built; ++l) {
+        free(T->start[l]);
+        free(T->ijk[l]);
+        free(T->ctr[l]);
+        free(T->child[l]);
+    }
+}
+
+/* =========================================================================
+ * Plan: root cubes, trees, descent lists, stopping rule
+ * ========================================================================= */
+typedef struct { int64_t t, s; int32_t o[3]; } pr_t;
+
+static int pr_cmp(const void *a, const void *b)
+{
+    const pr_t *x = a, *y = b;
+    if (x->t != y->t) return x->t < y->t ? -1 : 1;
+    return (x->s > y->s) - (x->s < y->s);
+}
+
+static void pairs_set(pairs_t *P, pr_t *v, int64_t n, int with_off)
+{
+    qsort(v, (size_t)n, sizeof(pr_t), pr_cmp);
+    P->n = n;
+    P->t = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    P->s = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    P->off = with_off ? malloc(sizeof(int32_t) * 3 * (size_t)(n + 1)) : NULL;
+    for (int64_t i = 0; i < n; ++i) {
+        P->t[i] = v[i].t;
+        P->s[i] = v[i].s;
+        if (with_off) memcpy(P->off + 3 * i, v[i].o, sizeof(int32_t) * 3);
+    }
+}
+
+/* Admissibility (Sec. 2.2.2; reading R2): centres at max-norm distance >= 2 d_l. */
+static int is_far(const orc_plan *p, int l, int64_t t, int64_t s)
+{
+    const tree_t *X = &p->T[0], *Y = &p->T[1];
+    if (p->aligned) {
+        int m = 0;
+        for (int d = 0; d < 3; ++d) {
+            int o = abs(X->ijk[l][3 * t + d] - Y->ijk[l][3 * s + d]);
+            if (o > m) m = o;
+        }
+        return m >= 2;
+    }
+    double dl2 = 2.0 * ldexp(p->d0, -l), m = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double o = fabs(X->ctr[l][3 * t + d] - Y->ctr[l][3 * s + d]);
+        if (o > m) m = o;
+    }
+    return m >= dl2;
+}
+
+orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t ny,
+                          int kernel, double k, double eps, const orc_options *opt)
+{
+    orc_plan *p = calloc(1, sizeof(orc_plan));
+    p->kernel = kernel;
+    p->k = k;
+    p->eps = eps;
+    p->opt.n_leaf = (opt && opt->n_leaf > 0) ? opt->n_leaf : 64;
+    p->opt.kappa = (opt && opt->kappa > 0) ? opt->kappa : ORC_PI;
+    p->opt.r1_override = opt ? opt->r1_override : 0;
+    p->opt.max_level = (opt && opt->max_level > 0 && opt->max_level <= 20) ? opt->max_level : 20;
+    if (nx <= 0 || ny <= 0) {
+        p->empty = 1;
+        p->T[0].n = nx > 0 ? nx : 0;
+        p->T[1].n = ny > 0 ? ny : 0;
+        return p;
+    }
+    int maxlev = p->opt.max_level;
+
+    /* Root cubes (Sec. 2.2.1; reading R1). */
+    const double *PS[2] = {X, Y};
+    int64_t NS[2] = {nx, ny};
+    double lo[2][3], hi[2][3], d0 = 0.0;
+    for (int e = 0; e < 2; ++e) {
+        for (int d = 0; d < 3; ++d) {
+            lo[e][d] = PS[e][d];
+            hi[e][d] = PS[e][d];
+        }
+        for (int64_t i = 1; i < NS[e]; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double v = PS[e][3 * i + d];
+                if (v < lo[e][d]) lo[e][d] = v;
+                if (v > hi[e][d]) hi[e][d] = v;
+            }
+        for (int d = 0; d < 3; ++d)
+            if (hi[e][d] - lo[e][d] > d0) d0 = hi[e][d] - lo[e][d];
+    }
+    if (d0 == 0.0) d0 = 1.0;
+    p->d0 = d0;
+    p->S = (double)QMAX / d0;
+    double corner[2][3];
+    for (int e = 0; e < 2; ++e)
+        for (int d = 0; d < 3; ++d) corner[e][d] = (lo[e][d] + hi[e][d]) * 0.5 - d0 * 0.5;
+    p->aligned = memcmp(corner[0], corner[1], sizeof(double) * 3) == 0;
+
+    /* Two octrees with the same cubic boxes at every level (Sec. 2.1). */
+    for (int e = 0; e < 2; ++e) {
+        tree_build(&p->T[e], PS[e], NS[e], corner[e], p->S);
+        tree_level(&p->T[e], 0, d0);
+    }
+
+    /* Descent (Sec. 2.2.2, 2.2.4, 3.2): near_0 = {(root, root)}; the child pairs of every near
+     * pair of level l-1 are split into far_l and near_l. */
+    pr_t *root = malloc(sizeof(pr_t));
+    root->t = 0;
+    root->s = 0;
+    pairs_set(&p->near[0], root, 1, 0);
+    free(root);
+    p->leaf = maxlev;
+    for (int l = 1; l <= maxlev; ++l) {
+        for (int e = 0; e < 2; ++e) tree_level(&p->T[e], l, d0);
+        const pairs_t *pn = &p->near[l - 1];
+        const tree_t *TX = &p->T[0], *TY = &p->T[1];
+        int64_t cap = 0;
+        for (int64_t i = 0; i < pn->n; ++i)
+            cap += (TX->child[l - 1][pn->t[i] + 1] - TX->child[l - 1][pn->t[i]]) *
+                   (TY->child[l - 1][pn->s[i] + 1] - TY->child[l - 1][pn->s[i]]);
+        pr_t *vf = malloc(sizeof(pr_t) * (size_t)(cap + 1));
+        pr_t *vn = malloc(sizeof(pr_t) * (size_t)(cap + 1));
+        int64_t nf = 0, nn = 0;
+        for (int64_t i = 0; i < pn->n; ++i)
+            for (int64_t ct = TX->child[l - 1][pn->t[i]]; ct < TX->child[l - 1][pn->t[i] + 1]; ++ct)
+                for (int64_t cs = TY->child[l - 1][pn->s[i]]; cs < TY->child[l - 1][pn->s[i] + 1]; ++cs) {
+                    if (is_far(p, l, ct, cs)) {
+                        vf[nf].t = ct;
+                        vf[nf].s = cs;
+                        for (int d = 0; d < 3; ++d)
+                            vf[nf].o[d] = TX->ijk[l][3 * ct + d] - TY->ijk[l][3 * cs + d];
+                        ++nf;
+                    } else {
+                        vn[nn].t = ct;
+                        vn[nn].s = cs;
+                        ++nn;
+                    }
+                }
+        pairs_set(&p->far[l], vf, nf, 1);
+        pairs_set(&p->near[l], vn, nn, 0);
+        free(vf);
+        free(vn);
+        /* Stopping rule (Sec. 2.2.4; reading R4). */
+        int64_t nb = p->T[0].nbox[l] + p->T[1].nbox[l];
+        if (nn == 0 || nx + ny <= (int64_t)p->opt.n_leaf * nb) {
+            p->leaf = l;
+            break;
+        }
+    }
+    /* Compression form per level (Sec. 2.2.2-2.2.3; readings R5-R7). */
+    for (int l = 1; l <= p->leaf; ++l) {
+        double dl = ldexp(d0, -l);
+        if (p->far[l].n == 0) continue;
+        if (kernel == ORC_HELMHOLTZ && k * dl >= p->opt.kappa) {
+            p->method[l] = 2;
+            p->order[l] = orc_gegenbauer_rank(k, dl, eps);
+        } else {
+            p->method[l] = 1;
+            int r1 = (int)ceil(log(1.0 / eps) / log(3.0 + sqrt(8.0)));
+            if (kernel == ORC_HELMHOLTZ) r1 += (int)ceil(k * dl / 2.0);
+            if (p->opt.r1_override > 0) r1 = p->opt.r1_override;
+            if (r1 < 1) r1 = 1;
+            p->order[l] = r1;
+        }
+    }
+    return p;
+}
+
+void orc_plan_free(orc_plan *p)
+{
+    if (!p) return;
+    if (!p->empty) {
+        for (int e = 0; e < 2; ++e) tree_free(&p->T[e]);
+        for (int l = 0; l <= BITS; ++l) {
+            free(p->far[l].t);
+            free(p->far[l].s);
+            free(p->far[l].off);
+            free(p->near[l].t);
+            free(p->near[l].s);
+        }
+    }
+    free(p);
+}
+
+/* =========================================================================
+ * Apply
+ * ========================================================================= */
+
+/* CSR view of a sorted pair list by target. */
+static int64_t *pairs_by_target(const pairs_t *P, int64_t ntgt)
+{
+    int64_t *ptr = calloc((size_t)(ntgt + 1), sizeof(int64_t));
+    for (int64_t i = 0; i < P->n; ++i) ptr[P->t[i] + 1]++;
+    for (int64_t t = 0; t < ntgt; ++t) ptr[t + 1] += ptr[t];
+    return ptr;
+}
+
+/* Translation classes of a level: far pairs with equal integer offsets share one
+ * transfer (proof of Prop. 1).  Classes are indexed through a dense window spanning
+ * the offsets that occur at the level. */
+typedef struct { int base[3], ext[3]; int32_t *id; int n; double (*r0)[3]; } classes_t;
+
+static void classes_build(classes_t *C, const orc_plan *p, int l)
+{
+    double dl = ldexp(p->d0, -l);
+    const pairs_t *F = &p->far[l];
+    int hi[3];
+    for (int d = 0; d < 3; ++d) {
+        C->base[d] = F->n ? F->off[d] : 0;
+        hi[d] = C->base[d];
+    }
+    for (int64_t i = 0; i < F->n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            if (F->off[3 * i + d] < C->base[d]) C->base[d] = F->off[3 * i + d];
+            if (F->off[3 * i + d] > hi[d]) hi[d] = F->off[3 * i + d];
+        }
+    for (int d = 0; d < 3; ++d) C->ext[d] = hi[d] - C->base[d] + 1;
+    size_t nw = (size_t)C->ext[0] * C->ext[1] * C->ext[2];
+    C->id = malloc(sizeof(int32_t) * nw);
+    C->r0 = malloc(sizeof(double[3]) * nw);
+    for (size_t i = 0; i < nw; ++i) C->id[i] = -1;
+    C->n = 0;
+    for (int64_t i = 0; i < F->n; ++i) {
+        size_t idx = 0;
+        for (int d = 0; d < 3; ++d) idx = idx * C->ext[d] + (F->off[3 * i + d] - C->base[d]);
+        if (C->id[idx] < 0) {
+            C->id[idx] = C->n;
+            /* r0 = x0 - y0 = (corner_X - corner_Y) + o d_l */
+            for (int d = 0; d < 3; ++d)
+                C->r0[C->n][d] = (p->T[0].corner[d] - p->T[1].corner[d]) + (double)F->off[3 * i + d] * dl;
+            C->n++;
+        }
+    }
+}
+
+static void classes_free(classes_t *C)
+{
+    free(C->id);
+    free(C->r0);
+}
+
+static int class_of(const classes_t *C, const int32_t *o)
+{
+    size_t idx = 0;
+    for (int d = 0; d < 3; ++d) idx = idx * C->ext[d] + (o[d] - C->base[d]);
+    return C->id[idx];
+}
+
+/* Lagrange level (Sec. 2.2.2): v_t += L_X^T (sum_s T_{ts} (L_Y u_s)). */
+static void level_lagrange(const orc_plan *p, int l, const double complex *u, double complex *v,
+                           int64_t stride)
+{
+    const tree_t *TX = &p->T[0], *TY = &p->T[1];
+    const pairs_t *F = &p->far[l];
+    int r1 = p->order[l], r = r1 * r1 * r1;
+    double dl = ldexp(p->d0, -l), nodes[64];
+    orc_cheb_nodes(r1, nodes);
+    int64_t nbx = TX->nbox[l], nby = TY->nbox[l];
+
+    /* sources that take part in a far pair (of a sampled target when stride > 1) */
+    char *need = calloc((size_t)nby, 1);
+    for (int64_t i = 0; i < F->n; ++i)
+        if ((F->t[i] % stride) == 0) need[F->s[i]] = 1;
+
+    /* interpolated source vectors u~_s = L_Y u_s */
+    double complex *ut = calloc((size_t)nby * r, sizeof(double complex));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < nby; ++s) {
+        if (!need[s]) continue;
+        double ex[64], ey[64], ez[64];
+        for (int64_t j = TY->start[l][s]; j < TY->start[l][s + 1]; ++j) {
+            orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j] - TY->ctr[l][3 * s]) / dl, ex);
+            orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j + 1] - TY->ctr[l][3 * s + 1]) / dl, ey);
+            orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j + 2] - TY->ctr[l][3 * s + 2]) / dl, ez);
+            for (int a = 0; a < r1; ++a)
+                for (int b = 0; b < r1; ++b)
+                    for (int c = 0; c < r1; ++c) ut[s * r + (a * r1 + b) * r1 + c] += ex[a] * ey[b] * ez[c] * u[j];
+        }
+    }
+
+    /* transfer matrices T[(abc),(a'b'c')] = G(xi_t - xi_s), one per translation */
+    classes_t C;
+    classes_build(&C, p, l);
+    double complex *Tm = malloc(sizeof(double complex) * (size_t)C.n * r * r);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < C.n; ++c)
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) {
+                int ia[3] = {i / (r1 * r1), (i / r1) % r1, i % r1};
+                int ja[3] = {j / (r1 * r1), (j / r1) % r1, j % r1};
+                double dd[3];
+                for (int d = 0; d < 3; ++d) dd[d] = C.r0[c][d] + 0.5 * dl * (nodes[ia[d]] - nodes[ja[d]]);
+                Tm[((size_t)c * r + i) * r + j] =
+                    green(p->kernel, p->k, sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
+            }
+
+    /* v~_t = sum_{s in far(t)} T_ts u~_s ;  v_i += sum L_i(x) v~_t */
+    int64_t *ptr = pairs_by_target(F, nbx);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nbx; ++t) {
+        if (ptr[t] == ptr[t + 1] || (t % stride) != 0) continue;
+        double complex *vt = calloc((size_t)r, sizeof(double complex));
+        for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+            const double complex *Tc = Tm + (size_t)class_of(&C, F->off + 3 * e) * r * r;
+            const double complex *us = ut + F->s[e] * r;
+            for (int i = 0; i < r; ++i) {
+                double complex acc = 0.0;
+                for (int j = 0; j < r; ++j) acc += Tc[i * r + j] * us[j];
+                vt[i] += acc;
+            }
+        }
+        double ex[64], ey[64], ez[64];
+        for (int64_t i = TX->start[l][t]; i < TX->start[l][t + 1]; ++i) {
+            orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i] - TX->ctr[l][3 * t]) / dl, ex);
+            orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i + 1] - TX->ctr[l][3 * t + 1]) / dl, ey);
+            orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i + 2] - TX->ctr[l][3 * t + 2]) / dl, ez);
+            double complex acc = 0.0;
+            for (int a = 0; a < r1; ++a)
+                for (int b = 0; b < r1; ++b)
+                    for (int c = 0; c < r1; ++c) acc += ex[a] * ey[b] * ez[c] * vt[(a * r1 + b) * r1 + c];
+            v[i] += acc;
+        }
+        free(vt);
+    }
+    free(ptr);
+    free(Tm);
+    classes_free(&C);
+    free(ut);
+    free(need);
+}
+
+/* Gegenbauer level (Sec. 2.2.3): v = F_{s->X} (D (F_{Y->s} u)) in box-centred coordinates (R9). */
+static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, double complex *v,
+                             int64_t stride)
+{
+    const tree_t *TX = &p->T[0], *TY = &p->T[1];
+    const pairs_t *F = &p->far[l];
+    int L = p->order[l];
+    double k = p->k;
+    int64_t nq = 2 * (int64_t)L * (L + 1);
+    double *s = malloc(sizeof(double) * 3 * nq), *w = malloc(sizeof(double) * nq);
+    orc_sphere_quadrature(L, s, w);
+    int64_t nbx = TX->nbox[l], nby = TY->nbox[l];
+
+    char *need = calloc((size_t)nby, 1);
+    int64_t *ptr = pairs_by_target(F, nbx);
+    for (int64_t t = 0; t < nbx; ++t)
+        if (ptr[t] < ptr[t + 1] && (t % stride) == 0)
+            for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) need[F->s[e]] = 1;
+
+    /* forward transform u~_s(q) = sum_j e^{-ik s_q.(y_j - c_s)} u_j */
+    double complex *ut = calloc((size_t)nby * nq, sizeof(double complex));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nby; ++b) {
+        if (!need[b]) continue;
+        const double *c = TY->ctr[l] + 3 * b;
+        for (int64_t j = TY->start[l][b]; j < TY->start[l][b + 1]; ++j) {
+            double y0 = TY->P[3 * j] - c[0], y1 = TY->P[3 * j + 1] - c[1], y2 = TY->P[3 * j + 2] - c[2];
+            for (int64_t q = 0; q < nq; ++q)
+                ut[b * nq + q] += cexp(-I * k * (s[3 * q] * y0 + s[3 * q + 1] * y1 + s[3 * q + 2] * y2)) * u[j];
+        }
+    }
+
+    /* diagonal transfer per translation class */
+    classes_t C;
+    classes_build(&C, p, l);
+    double complex *D = malloc(sizeof(double complex) * (size_t)C.n * nq);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < C.n; ++c) gegenbauer_diag_q(L, k, C.r0[c], s, w, nq, D + (size_t)c * nq);
+
+    /* v~_t(q) = sum_s D_ts(q) u~_s(q);  v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q) */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nbx; ++t) {
+        if (ptr[t] == ptr[t + 1] || (t % stride) != 0) continue;
+        double complex *vt = calloc((size_t)nq, sizeof(double complex));
+        for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+            const double complex *Dc = D + (size_t)class_of(&C, F->off + 3 * e) * nq;
+            const double complex *us = ut + F->s[e] * nq;
+            for (int64_t q = 0; q < nq; ++q) vt[q] += Dc[q] * us[q];
+        }
+        const double *c = TX->ctr[l] + 3 * t;
+        for (int64_t i = TX->start[l][t]; i < TX->start[l][t + 1]; ++i) {
+            double x0 = TX->P[3 * i] - c[0], x1 = TX->P[3 * i + 1] - c[1], x2 = TX->P[3 * i + 2] - c[2];
+            double complex acc = 0.0;
+            for (int64_t q = 0; q < nq; ++q)
+                acc += cexp(I * k * (s[3 * q] * x0 + s[3 * q + 1] * x1 + s[3 * q + 2] * x2)) * vt[q];
+            v[i] += acc;
+        }
+        free(vt);
+    }
+    free(D);
+    classes_free(&C);
+    free(ut);
+    free(ptr);
+    free(need);
+    free(s);
+    free(w);
+}
+
+/* Dense remainder at the leaf (Sec. 2.2.4). */
+static void near_field(const orc_plan *p, const double complex *u, double complex *v, int64_t stride)
+{
+    const tree_t *TX = &p->T[0], *TY = &p->T[1];
+    int l = p->leaf;
+    const pairs_t *N = &p->near[l];
+    int64_t nbx = TX->nbox[l];
+    int64_t *ptr = pairs_by_target(N, nbx);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nbx; ++t) {
+        if ((t % stride) != 0) continue;
+        for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+            int64_t sb = N->s[e];
+            for (int64_t i = TX->start[l][t]; i < TX->start[l][t + 1]; ++i) {
+                double complex acc = 0.0;
+                for (int64_t j = TY->start[l][sb]; j < TY->start[l][sb + 1]; ++j) {
+                    double dx = TX->P[3 * i] - TY->P[3 * j], dy = TX->P[3 * i + 1] - TY->P[3 * j + 1],
+                           dz = TX->P[3 * i + 2] - TY->P[3 * j + 2];
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 == 0.0) continue;   /* R11 */
+                    acc += green(p->kernel, p->k, sqrt(r2)) * u[j];
+                }
+                v[i] += acc;
+            }
+        }
+    }
+    free(ptr);
+}
+
+void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride)
+{
+    if (stride < 1) stride = 1;
+    int64_t nx = p->T[0].n, ny = p->T[1].n;
+    memset(v, 0, sizeof(double) * 2 * (size_t)nx);
+    if (p->empty) return;
+    /* permute the input into source tree order */
+    double complex *u = malloc(sizeof(double complex) * (size_t)ny);
+    for (int64_t j = 0; j < ny; ++j) u[j] = cload(wu, p->T[1].perm[j]);
+    double complex *vs = calloc((size_t)nx, sizeof(double complex));
+    /* descent: every level's far pairs, in order (Sec. 2.2) */
+    for (int l = 1; l <= p->leaf; ++l) {
+        if (p->method[l] == 1) level_lagrange(p, l, u, vs, stride);
+        else if (p->method[l] == 2) level_gegenbauer(p, l, u, vs, stride);
+    }
+    near_field(p, u, vs, stride);
+    /* back to the user's target order */
+    for (int64_t i = 0; i < nx; ++i) {
+        v[2 * p->T[0].perm[i]] = creal(vs[i]);
+        v[2 * p->T[0].perm[i] + 1] = cimag(vs[i]);
+    }
+    free(vs);
+    free(u);
+}
+
+/* =========================================================================
+ * Queries
+ * ========================================================================= */
+int orc_leaf(const orc_plan *p) { return p->empty ? 0 : p->leaf; }
+double orc_d0(const orc_plan *p) { return p->d0; }
+void orc_corner(const orc_plan *p, int set, double *c3) { memcpy(c3, p->T[set].corner, sizeof(double) * 3); }
+int64_t orc_npoints(const orc_plan *p, int set) { return p->T[set].n; }
+void orc_keys(const orc_plan *p, int set, uint64_t *keys)
+{
+    memcpy(keys, p->T[set].key, sizeof(uint64_t) * (size_t)p->T[set].n);
+}
+void orc_perm(const orc_plan *p, int set, int64_t *perm)
+{
+    memcpy(perm, p->T[set].perm, sizeof(int64_t) * (size_t)p->T[set].n);
+}
+int64_t orc_nbox(const orc_plan *p, int set, int l) { return p->empty ? 0 : p->T[set].nbox[l]; }
+void orc_box_start(const orc_plan *p, int set, int l, int64_t *start)
+{
+    memcpy(start, p->T[set].start[l], sizeof(int64_t) * (size_t)(p->T[set].nbox[l] + 1));
+}
+void orc_box_ijk(const orc_plan *p, int set, int l, int32_t *ijk)
+{
+    memcpy(ijk, p->T[set].ijk[l], sizeof(int32_t) * 3 * (size_t)p->T[set].nbox[l]);
+}
+void orc_box_centre(const orc_plan *p, int set, int l, double *c)
+{
+    memcpy(c, p->T[set].ctr[l], sizeof(double) * 3 * (size_t)p->T[set].nbox[l]);
+}
+int64_t orc_nfar(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->far[l].n; }
+void orc_far(const orc_plan *p, int l, int64_t *t, int64_t *s, int32_t *off)
+{
+    const pairs_t *F = &p->far[l];
+    memcpy(t, F->t, sizeof(int64_t) * (size_t)F->n);
+    memcpy(s, F->s, sizeof(int64_t) * (size_t)F->n);
+    memcpy(off, F->off, sizeof(int32_t) * 3 * (size_t)F->n);
+}
+int64_t orc_nnear(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->near[l].n; }
+void orc_near(const orc_plan *p, int l, int64_t *t, int64_t *s)
+{
+    const pairs_t *N = &p->near[l];
+    memcpy(t, N->t, sizeof(int64_t) * (size_t)N->n);
+    memcpy(s, N->s, sizeof(int64_t) * (size_t)N->n);
+}
+int orc_level_method(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->method[l]; }
+int orc_level_order(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->order[l]; }

@@ -1,0 +1,90 @@
+/*
+ * ffm_oracle.h -- FP64 CPU oracle for the Fast Free Memory (FFM) method.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product library
+ * never calls it, and the two share no code.
+ *
+ * Everything is plain, slow and direct: FP64 real arithmetic, C99 complex
+ * (complex128) accumulation, OpenMP only over independent boxes or rows.
+ *
+ * Paper: Aussal & Bakry, "The Fast and Free Memory Method for the efficient
+ * computation of convolution kernels" (arXiv:1909.05600).
+ *   - operator v_i = sum_j w_j G(x_i, y_j) u_j         : Sec. 1, eqs. (convolution_discrete), (convolution_matrix)
+ *   - root cubes, d_l = d_0 / 2^l                       : Sec. 2.2.1
+ *   - admissibility and Lagrange interpolation          : Sec. 2.2.2
+ *   - Gegenbauer plane-wave form for Helmholtz          : Sec. 2.2.3, eqs. (gegenbauerIntegral..gegenbauerQuadrature)
+ *   - stopping criterion and dense remainder            : Sec. 2.2.4
+ *   - descent-only traversal, reuse per translation     : Sec. 3.1-3.2 (proof of Prop. 1)
+ *   - kernels: Laplace (laplaceGreenKernel), Helmholtz (helmholtzKernel)
+ *
+ * Complex arrays are interleaved (re, im) doubles.  Coordinates are n x 3
+ * row-major doubles.  All indices are 64-bit.
+ */
+#ifndef FFM_ORACLE_H
+#define FFM_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_LAPLACE 0
+#define ORC_HELMHOLTZ 1
+
+/* ---- plain definition ---------------------------------------------------- */
+/* out[a] = sum_{j : |x_rows[a] - y_j| > 0} G(|x_rows[a] - y_j|) * wu[j]  (complex128 out) */
+void orc_dense_rows(const double *X, const double *Y, int64_t ny, const double *wu,
+                    int kernel, double k, const int64_t *rows, int64_t nrows, double *out);
+
+/* ---- building blocks, exported so the tests can pin them ----------------- */
+void orc_gauss_legendre(int n, double *x, double *w);
+void orc_legendre_p(int L, double t, double *P);                 /* P_0..P_L at t            */
+void orc_sph_hankel1(int L, double z, double *h);                 /* h_0..h_L (complex) at z>0 */
+void orc_cheb_nodes(int r1, double *t);                           /* first-kind nodes         */
+void orc_lagrange_basis(int r1, double t, double *ell);            /* l_1..l_r1 at t           */
+int  orc_gegenbauer_rank(double k, double d_l, double eps);
+/* quadrature of a Gegenbauer level: s (nq x 3), w (nq); returns nq = 2L(L+1) */
+int64_t orc_sphere_quadrature(int L, double *s, double *w);
+/* transfer diagonal D(q) = (ik/4pi) w_q T_{L,r0}(s_q) for one translation r0 (complex out, nq) */
+void orc_gegenbauer_diag(int L, double k, const double r0[3], double *D);
+
+/* ---- plan ----------------------------------------------------------------- */
+typedef struct orc_plan orc_plan;
+
+typedef struct {
+    int32_t n_leaf;       /* occupancy threshold of the stopping rule (default 64) */
+    double  kappa;        /* Gegenbauer iff k*d_l >= kappa (default pi)             */
+    int32_t r1_override;  /* > 0: Chebyshev nodes per axis at every Lagrange level */
+    int32_t max_level;    /* depth cap (default 20)                                 */
+} orc_options;
+
+orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t ny,
+                          int kernel, double k, double eps, const orc_options *opt);
+void orc_plan_free(orc_plan *p);
+
+/* apply: v (complex, user target order) = FFM(wu (complex, user source order)).
+ * stride > 1 evaluates only every stride-th box in every per-box loop (timing samples). */
+void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride);
+
+/* ---- queries for bit-exact comparison ------------------------------------- */
+int     orc_leaf(const orc_plan *p);
+double  orc_d0(const orc_plan *p);
+void    orc_corner(const orc_plan *p, int set, double *c3);        /* set 0 = X (targets), 1 = Y */
+int64_t orc_npoints(const orc_plan *p, int set);
+void    orc_keys(const orc_plan *p, int set, uint64_t *keys);       /* sorted keys               */
+void    orc_perm(const orc_plan *p, int set, int64_t *perm);        /* sorted pos -> user index  */
+int64_t orc_nbox(const orc_plan *p, int set, int l);
+void    orc_box_start(const orc_plan *p, int set, int l, int64_t *start);  /* nbox+1 entries */
+void    orc_box_ijk(const orc_plan *p, int set, int l, int32_t *ijk);      /* nbox x 3       */
+void    orc_box_centre(const orc_plan *p, int set, int l, double *c);      /* nbox x 3       */
+int64_t orc_nfar(const orc_plan *p, int l);
+void    orc_far(const orc_plan *p, int l, int64_t *t, int64_t *s, int32_t *off); /* off: nfar x 3 */
+int64_t orc_nnear(const orc_plan *p, int l);                        /* near_l (valid l <= leaf) */
+void    orc_near(const orc_plan *p, int l, int64_t *t, int64_t *s);
+int     orc_level_method(const orc_plan *p, int l);                 /* 0 none, 1 Lagrange, 2 Gegenbauer */
+int     orc_level_order(const orc_plan *p, int l);                  /* r1 or L                   */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,206 @@
+"""Pins of the oracle's octrees and descent lists by brute force and by the paper's counts.
+
+Paper: Sec. 2.1 (two octrees with equal cubic boxes), Sec. 2.2.1 (root cubes, d_l = d_0/2^l),
+Sec. 2.2.2 (admissibility), Sec. 2.2.4 (stopping rule), Sec. 3.2 proof of Prop. 1 (27 interactions
+of an interior box and 7^2 - 3^2 = 40 translations in 2-D).
+"""
+import numpy as np
+import pytest
+
+import ffm_workloads as W
+
+
+def _deinterleave(prefix, l):
+    ijk = np.zeros((prefix.size, 3), dtype=np.int64)
+    for b in range(l):
+        ijk[:, 0] |= ((prefix >> np.uint64(3 * b + 2)) & np.uint64(1)).astype(np.int64) << b
+        ijk[:, 1] |= ((prefix >> np.uint64(3 * b + 1)) & np.uint64(1)).astype(np.int64) << b
+        ijk[:, 2] |= ((prefix >> np.uint64(3 * b)) & np.uint64(1)).astype(np.int64) << b
+    return ijk
+
+
+def _two_sets(n, seed):
+    rng = np.random.default_rng(seed)
+    X = W.sphere_points(n, rng)
+    Y = W.sphere_points(n + 37, rng) * 0.9 + 0.05
+    return X, Y
+
+
+@pytest.mark.parametrize("same", [True, False])
+def test_points_lie_in_their_boxes(orc, same):
+    X, Y = _two_sets(3000, 5)
+    if same:
+        Y = X
+    p = orc.Plan(X, Y, 0, 0.0, 1e-3, n_leaf=8)
+    d0 = p.d0
+    # d_0 is the largest bounding-box edge over both sets (Sec. 2.2.1)
+    assert d0 == max(np.ptp(X, axis=0).max(), np.ptp(Y, axis=0).max())
+    for s, P in ((0, X), (1, Y)):
+        keys = p.keys(s)
+        perm = p.perm(s)
+        assert np.all(keys[1:] >= keys[:-1])
+        assert np.array_equal(np.sort(perm), np.arange(P.shape[0]))
+        # stable: equal keys keep the original order
+        eq = keys[1:] == keys[:-1]
+        assert np.all(perm[1:][eq] > perm[:-1][eq])
+        Ps = P[perm]
+        for l in range(0, p.leaf + 1):
+            st = p.box_start(s, l)
+            assert st[0] == 0 and st[-1] == P.shape[0] and np.all(np.diff(st) > 0)
+            c = p.box_centre(s, l)
+            ijk = p.box_ijk(s, l)
+            box = np.repeat(np.arange(len(st) - 1), np.diff(st))
+            dl = d0 / 2 ** l
+            dev = np.abs(Ps - c[box]).max(axis=1)
+            assert np.all(dev <= 0.5 * dl * (1 + 1e-9)), dev.max() / dl
+            # the same cell index as a direct floor of the coordinates (away from cell faces)
+            cell = np.floor((Ps - p.corner(s)) / dl).astype(np.int64)
+            cell = np.clip(cell, 0, 2 ** l - 1)
+            frac = (Ps - p.corner(s)) / dl - np.floor((Ps - p.corner(s)) / dl)
+            safe = np.all((frac > 1e-9) & (frac < 1 - 1e-9), axis=1)
+            assert np.array_equal(cell[safe], ijk[box][safe])
+            # box coordinates equal the de-interleaved key prefix
+            pref = keys[st[:-1]] >> np.uint64(3 * (21 - l))
+            assert np.array_equal(_deinterleave(pref, l), ijk)
+            # boxes are exactly the distinct cells
+            assert len(st) - 1 == len({tuple(r) for r in ijk[box]})
+
+
+def _brute_lists(p, nl):
+    """Far/near sets from the definition: a pair is far at level l iff its centres are >= 2 d_l apart
+    (max norm) and all its ancestor pairs are near; computed over all box pairs, no descent lists."""
+    d0 = p.d0
+    aligned = np.array_equal(p.corner(0), p.corner(1))
+    out = {}
+    anc_t = [None] * (nl + 1)
+    anc_s = [None] * (nl + 1)
+    for s, anc in ((0, anc_t), (1, anc_s)):
+        for l in range(nl + 1):
+            st = p.box_start(s, l)
+            anc[l] = st   # point ranges define nesting
+    for l in range(1, nl + 1):
+        ct, cs = p.box_centre(0, l), p.box_centre(1, l)
+        it, is_ = p.box_ijk(0, l), p.box_ijk(1, l)
+        if aligned:
+            far_l = np.abs(it[:, None, :] - is_[None, :, :]).max(axis=2) >= 2
+        else:
+            far_l = np.abs(ct[:, None, :] - cs[None, :, :]).max(axis=2) >= 2 * (d0 / 2 ** l)
+        # ancestors near at every coarser level m in [1, l-1]
+        ok = np.ones_like(far_l)
+        for m in range(1, l):
+            par_t = np.searchsorted(p.box_start(0, m), p.box_start(0, l)[:-1], side="right") - 1
+            par_s = np.searchsorted(p.box_start(1, m), p.box_start(1, l)[:-1], side="right") - 1
+            if aligned:
+                fm = np.abs(p.box_ijk(0, m)[:, None, :] - p.box_ijk(1, m)[None, :, :]).max(axis=2) >= 2
+            else:
+                fm = np.abs(p.box_centre(0, m)[:, None, :] - p.box_centre(1, m)[None, :, :]).max(axis=2) \
+                    >= 2 * (d0 / 2 ** m)
+            ok &= ~fm[par_t][:, par_s]
+        out[l] = (far_l & ok, ~far_l & ok)
+    return out
+
+
+@pytest.mark.parametrize("same", [True, False])
+def test_lists_match_brute_force(orc, same):
+    X, Y = _two_sets(1500, 9)
+    if same:
+        Y = X
+    p = orc.Plan(X, Y, 0, 0.0, 1e-3, n_leaf=6)
+    bl = _brute_lists(p, p.leaf)
+    for l in range(1, p.leaf + 1):
+        t, s, off = p.far(l)
+        F, N = bl[l]
+        ft, fs = np.nonzero(F)
+        assert np.array_equal(t, ft) and np.array_equal(s, fs)     # np.nonzero is (t, s) sorted
+        assert np.array_equal(off, p.box_ijk(0, l)[t] - p.box_ijk(1, l)[s])
+        nt, ns = p.near(l)
+        bt, bs = np.nonzero(N)
+        assert np.array_equal(nt, bt) and np.array_equal(ns, bs)
+
+
+@pytest.mark.parametrize("same", [True, False])
+def test_every_point_pair_covered_exactly_once(orc, same):
+    X, Y = _two_sets(900, 13)
+    if same:
+        Y = X
+    p = orc.Plan(X, Y, 1, 7.0, 1e-3, n_leaf=5)
+    nx, ny = X.shape[0], Y.shape[0]
+    cover = np.zeros((nx, ny), dtype=np.int32)
+    px, py = p.perm(0), p.perm(1)
+
+    def add(l, t, s):
+        stx, sty = p.box_start(0, l), p.box_start(1, l)
+        for a, b in zip(t, s):
+            cover[np.ix_(px[stx[a]:stx[a + 1]], py[sty[b]:sty[b + 1]])] += 1
+
+    for l in range(1, p.leaf + 1):
+        t, s, _ = p.far(l)
+        add(l, t, s)
+    add(p.leaf, *p.near(p.leaf))
+    assert cover.min() == 1 and cover.max() == 1
+
+
+def test_stopping_rule(orc):
+    X, _ = _two_sets(5000, 17)
+    for n_leaf in (8, 30, 64, 200):
+        p = orc.Plan(X, X, 0, 0.0, 1e-3, n_leaf=n_leaf)
+        nb = [len({tuple(r) for r in np.floor((X - p.corner(0)) / (p.d0 / 2 ** l)).clip(0, 2 ** l - 1)
+                   .astype(int)}) for l in range(0, 12)]
+        expect = next(l for l in range(1, 12) if 2 * X.shape[0] <= n_leaf * 2 * nb[l])
+        assert p.leaf == expect, (n_leaf, p.leaf, expect)
+
+
+def _grid_points(m, dim, seed):
+    """One random point inside every cell of an m^dim grid on [0,1]^dim (z = 0 in 2-D), plus the
+    corners so that the bounding box is exactly the unit square/cube."""
+    rng = np.random.default_rng(seed)
+    idx = np.stack(np.meshgrid(*[np.arange(m)] * dim, indexing="ij"), axis=-1).reshape(-1, dim)
+    P = (idx + 0.1 + 0.8 * rng.random(idx.shape)) / m
+    corners = np.stack(np.meshgrid(*[[0.0, 1.0]] * dim, indexing="ij"), axis=-1).reshape(-1, dim)
+    P = np.concatenate([P, corners])
+    if dim == 2:
+        P = np.concatenate([P, np.zeros((P.shape[0], 1))], axis=1)
+    return P
+
+
+def test_quadtree_counts_of_the_paper(orc):
+    """Points on a plane make the octree a quadtree: an interior box has 27 far interactions and a
+    level has 7^2 - 3^2 = 40 distinct translations (proof of Prop. 1)."""
+    P = _grid_points(16, 2, 3)
+    p = orc.Plan(P, P, 0, 0.0, 1e-3, n_leaf=1, max_level=5)
+    assert p.leaf >= 4
+    l = 4
+    t, s, off = p.far(l)
+    ijk = p.box_ijk(0, l)
+    assert np.all(off[:, 2] == 0)
+    counts = np.bincount(t, minlength=p.nbox(0, l))
+    interior = np.all((ijk[:, :2] // 2 >= 1) & (ijk[:, :2] // 2 <= 6), axis=1)
+    assert np.all(counts[interior] == 27)
+    assert counts.max() == 27
+    assert len({tuple(o) for o in off}) == 40
+
+
+def test_octree_counts(orc):
+    """3-D analogues: 6^3 - 3^3 = 189 interactions of an interior box, 7^3 - 3^3 = 316 translations."""
+    P = _grid_points(16, 3, 4)
+    p = orc.Plan(P, P, 0, 0.0, 1e-3, n_leaf=1, max_level=5)
+    l = 4
+    t, s, off = p.far(l)
+    ijk = p.box_ijk(0, l)
+    counts = np.bincount(t, minlength=p.nbox(0, l))
+    interior = np.all((ijk // 2 >= 1) & (ijk // 2 <= 6), axis=1)
+    assert np.all(counts[interior] == 189)
+    assert len({tuple(o) for o in off}) == 316
+
+
+def test_sphere_workload_sizes(orc):
+    """The N=4096 sphere workload: leaf at level 3 (average occupancy 73 > 64 at level 2)."""
+    w = W.laplace_sphere()
+    p = orc.Plan(w.X, w.X, 0, 0.0, 1e-3)
+    assert p.leaf == 3
+    assert p.nbox(0, 1) == 8
+    assert len(p.far(1)[0]) == 0
+    for l in (2, 3):
+        t, s, off = p.far(l)
+        assert len({tuple(o) for o in off}) <= 316
+        assert np.abs(off).max() == 3 and np.abs(off).max(axis=1).min() == 2
