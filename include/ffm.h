@@ -1,0 +1,188 @@
+/*
+ * ffm.h -- C ABI of the MI355X (gfx950) Fast Free Memory library.
+ *
+ * The library evaluates the discrete convolution of Aussal & Bakry,
+ * "The Fast and Free Memory Method for the efficient computation of
+ * convolution kernels" (arXiv:1909.05600), Sec. 1 eqs. (convolution_discrete)
+ * and (convolution_matrix):
+ *
+ *     v_i = sum_j  G(x_i - y_j) * wu_j ,      wu_j = w_j u_j,
+ *
+ * to a prescribed accuracy eps, for the Laplace kernel 1/(4 pi r)
+ * (Sec. 4.1, eq. laplaceGreenKernel) and the Helmholtz kernel
+ * e^{ikr}/(4 pi r) (Sec. 2.2.3, eq. helmholtzKernel).  Pairs of coincident
+ * points (r == 0) contribute nothing.
+ *
+ * The method (Sec. 2) builds two octrees whose root cubes have the same edge
+ * d_0 (Sec. 2.2.1), descends them once (descent-only, Sec. 2.1 and the
+ * remark closing Sec. 2.2.3), compresses every admissible box pair at the
+ * level where it first becomes admissible (Sec. 2.2.2: Lagrange
+ * interpolation on Chebyshev nodes; Sec. 2.2.3: Gegenbauer plane-wave
+ * expansion for oscillatory Helmholtz levels), and sums the remaining leaf
+ * pairs densely (Sec. 2.2.4).
+ *
+ * Conventions for every entry point:
+ *   - all pointers named as device pointers must be HIP device memory of the
+ *     current device; host pointers are plain host memory;
+ *   - coordinates are FP64, n x 3, row-major (x0 y0 z0 x1 y1 z1 ...);
+ *   - complex data is interleaved (re, im);
+ *   - a hip_stream argument is a hipStream_t (NULL = the null stream);
+ *   - every call returns an ffm_status_t; nothing throws across the ABI; on
+ *     FFM_EINVAL nothing is written; ffm_last_error() gives a message
+ *     (thread-local, valid until the next call on the same thread).
+ */
+#ifndef FFM_H
+#define FFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffm_plan_s *ffm_plan_t;
+
+typedef enum { FFM_LAPLACE = 0, FFM_HELMHOLTZ = 1 } ffm_kernel_t;
+
+typedef enum {
+    FFM_OK = 0,
+    FFM_EINVAL = -1,     /* invalid argument (null pointer, NaN coordinate, eps, k, sizes) */
+    FFM_ENOMEM = -2,     /* a device or host allocation failed; nothing is leaked           */
+    FFM_EDEVICE = -3,    /* a HIP runtime call failed; the message names it                 */
+    FFM_EBUSY = -4,      /* the plan still has applies in flight                            */
+    FFM_EINTERNAL = -5   /* an internal consistency check failed                           */
+} ffm_status_t;
+
+/* Element type of the input vector wu. */
+typedef enum { FFM_C64 = 0, FFM_F32 = 1, FFM_F64 = 2, FFM_C128 = 3 } ffm_dtype_t;
+
+/* Precision of the compressed transfers (the near field is always FP32). */
+typedef enum {
+    FFM_PREC_FP32 = 0,   /* FP32 everywhere, FP64 geometry and coarse-level phase reduction   */
+    FFM_PREC_MIXED = 1   /* Lagrange transfers on FP16 MFMA with FP32 accumulation            */
+} ffm_precision_t;
+
+/* Plan options; an all-zero struct (or NULL) selects the defaults. */
+typedef struct {
+    int32_t n_leaf;       /* stopping rule: stop when the average box occupancy <= n_leaf (64)  */
+    int32_t precision;    /* ffm_precision_t (FFM_PREC_FP32)                                    */
+    double  kd_switch;    /* Helmholtz levels use the Gegenbauer form iff k d_l >= kd_switch (pi) */
+    int32_t r1_override;  /* > 0: Chebyshev nodes per axis at every Lagrange level              */
+    int32_t max_level;    /* depth cap, 1..20 (20)                                              */
+    uint32_t flags;       /* FFM_FLAG_* bits; other bits must be 0                              */
+} ffm_options_t;
+
+/* options.flags: record HIP events between the phases of every apply (see ffm_plan_timing). */
+#define FFM_FLAG_TIMING 1u
+
+/*
+ * ffm_plan -- build the two octrees, the descent lists and the transfer
+ * tables (Sec. 2.2.1-2.2.4; translations shared per class as in the proof
+ * of Prop. 1).
+ *   X      device, FP64 [n_x][3]: targets x_i.
+ *   Y      device, FP64 [n_y][3]: sources y_j.  Y == X with n_y == n_x means
+ *          the same set: one tree serves both.
+ *   kernel FFM_LAPLACE or FFM_HELMHOLTZ; k >= 0 is the wavenumber (ignored for
+ *          Laplace; Helmholtz with k = 0 equals Laplace).
+ *   eps    prescribed accuracy, 1e-7 <= eps < 0.5.
+ *   opts   host pointer or NULL.
+ *   hip_stream  stream for the planning kernels.
+ *   out    host pointer receiving the plan handle.
+ * Host-synchronous: when it returns, X and Y may be freed.  The plan owns its
+ * device memory until ffm_destroy.  n_x == 0 or n_y == 0 gives a plan whose
+ * apply writes zeros.  Limits: n_x, n_y < 2^31.
+ */
+ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y,
+                      ffm_kernel_t kernel, double k, double eps, const ffm_options_t *opts,
+                      void *hip_stream, ffm_plan_t *out);
+
+/*
+ * ffm_apply -- v = FFM(wu): one descent over the plan's levels (per level:
+ * source transform, transfer, target transform) and the leaf near field.
+ *   wu     device, n_y elements of in_dtype, in the caller's source order.
+ *          Real inputs are taken as complex with zero imaginary part.
+ *   v      device, complex64 [n_x], in the caller's target order; overwritten.
+ * Asynchronous on hip_stream: the caller keeps wu and v alive until the
+ * stream passes the apply.  One apply per plan may be in flight at a time
+ * (the plan's workspace is reused); a second apply on the same stream is
+ * ordered after the first.  No allocation happens inside apply.
+ */
+ffm_status_t ffm_apply(ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, void *v, void *hip_stream);
+
+/* ffm_destroy -- release the plan.  FFM_EBUSY (and nothing released) if an
+ * apply on it has not completed yet.  NULL is accepted. */
+ffm_status_t ffm_destroy(ffm_plan_t plan);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *ffm_last_error(void);
+
+/* Library version string. */
+const char *ffm_version(void);
+
+/* ---------------------------------------------------------------- statistics */
+#define FFM_MAX_LEVELS 21
+
+typedef struct {
+    int32_t leaf;                          /* leaf level                                  */
+    int32_t same_set;                      /* 1 if sources and targets are one set        */
+    double  d0;                            /* root cube edge                              */
+    double  corner_x[3], corner_y[3];      /* root cube corners of the two sets           */
+    int64_t nbox_x[FFM_MAX_LEVELS], nbox_y[FFM_MAX_LEVELS];
+    int64_t nfar[FFM_MAX_LEVELS];          /* far pairs first admissible at level l        */
+    int64_t nnear[FFM_MAX_LEVELS];         /* near pairs of level l                        */
+    int32_t method[FFM_MAX_LEVELS];        /* 0 none, 1 Lagrange, 2 Gegenbauer             */
+    int32_t order[FFM_MAX_LEVELS];         /* r1 (Lagrange) or L (Gegenbauer)              */
+    int32_t nclass[FFM_MAX_LEVELS];        /* distinct translations at level l             */
+    int64_t nq[FFM_MAX_LEVELS];            /* quadrature directions (Gegenbauer levels)    */
+    double  fwd_points[FFM_MAX_LEVELS];    /* points of the source boxes transformed at level l */
+    double  bwd_points[FFM_MAX_LEVELS];    /* points of the target boxes transformed at level l */
+    double  transform_terms;               /* sum over Gegenbauer levels of points x n_Q, both transforms */
+    double  transfer_macs;                 /* complex multiply-adds of all transfers      */
+    double  near_pairs;                    /* point pairs of the leaf near field          */
+    double  plan_bytes;                    /* device memory held by the plan              */
+    double  workspace_bytes;               /* device memory of the apply workspace        */
+} ffm_stats_t;
+
+ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out);
+
+/*
+ * ffm_plan_export -- copy tree and list data to host memory for bit-exact
+ * comparison (tests).  what selects the array; set 0 = targets, 1 = sources;
+ * level l.  Returns the element count in *count; if dst is non-NULL it must
+ * hold that many elements of the listed type.
+ *   FFM_EXPORT_KEYS      uint64  sorted Morton keys (set)
+ *   FFM_EXPORT_PERM      int64   sorted position -> caller index (set)
+ *   FFM_EXPORT_BOX_START int64   [nbox+1] point ranges of level l (set)
+ *   FFM_EXPORT_BOX_IJK   int32   [nbox][3] integer box coordinates (set, l)
+ *   FFM_EXPORT_BOX_CTR   double  [nbox][3] box centres (set, l)
+ *   FFM_EXPORT_FAR       int64   [nfar][5] (t, s, ox, oy, oz) sorted by (t, s) (l)
+ *   FFM_EXPORT_NEAR      int64   [nnear][2] (t, s) sorted by (t, s) (l)
+ */
+typedef enum {
+    FFM_EXPORT_KEYS = 0, FFM_EXPORT_PERM = 1, FFM_EXPORT_BOX_START = 2, FFM_EXPORT_BOX_IJK = 3,
+    FFM_EXPORT_BOX_CTR = 4, FFM_EXPORT_FAR = 5, FFM_EXPORT_NEAR = 6
+} ffm_export_t;
+
+ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t level,
+                             void *dst, int64_t *count);
+
+/*
+ * ffm_plan_timing -- per-phase durations (milliseconds, HIP events on the
+ * apply's stream) of the most recent apply of a plan made with
+ * FFM_FLAG_TIMING; waits for that apply to finish.  ms has n >= 64 slots:
+ *   [0] input permutation, [1 + 3(l-1) + 0/1/2] level l source transform /
+ *   transfer / target transform, [61] near field, [62] output permutation.
+ * Phases that did not run read 0.  FFM_EINVAL without FFM_FLAG_TIMING.
+ */
+#define FFM_TIMING_SLOTS 64
+ffm_status_t ffm_plan_timing(ffm_plan_t plan, float *ms, int32_t n);
+
+/* Device bytes held by the plan, and by its apply workspace. */
+size_t ffm_plan_bytes(ffm_plan_t plan);
+size_t ffm_workspace_bytes(ffm_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -56,6 +56,7 @@ def lib():
             "orc_plan_free": (None, [P]),
             "orc_apply": (None, [P, P, P, i64]),
             "orc_leaf": (C.c_int, [P]),
+            "orc_num_threads": (C.c_int, []),
             "orc_d0": (dbl, [P]),
             "orc_corner": (None, [P, C.c_int, P]),
             "orc_npoints": (i64, [P, C.c_int]),
@@ -78,6 +79,10 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 class _Options(C.Structure):

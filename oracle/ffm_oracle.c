@@ -43,6 +43,9 @@
 
 #include <complex.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -641,10 +644,10 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
     orc_cheb_nodes(r1, nodes);
     int64_t nbx = TX->nbox[l], nby = TY->nbox[l];
 
-    /* sources that take part in a far pair (of a sampled target when stride > 1) */
+    /* sources that take part in a far pair (every stride-th of them when timing a sample) */
     char *need = calloc((size_t)nby, 1);
     for (int64_t i = 0; i < F->n; ++i)
-        if ((F->t[i] % stride) == 0) need[F->s[i]] = 1;
+        if ((F->s[i] % stride) == 0) need[F->s[i]] = 1;
 
     /* interpolated source vectors u~_s = L_Y u_s */
     double complex *ut = calloc((size_t)nby * r, sizeof(double complex));
@@ -726,11 +729,11 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     orc_sphere_quadrature(L, s, w);
     int64_t nbx = TX->nbox[l], nby = TY->nbox[l];
 
+    /* sources that take part in a far pair (every stride-th of them when timing a sample) */
     char *need = calloc((size_t)nby, 1);
     int64_t *ptr = pairs_by_target(F, nbx);
-    for (int64_t t = 0; t < nbx; ++t)
-        if (ptr[t] < ptr[t + 1] && (t % stride) == 0)
-            for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) need[F->s[e]] = 1;
+    for (int64_t i = 0; i < F->n; ++i)
+        if ((F->s[i] % stride) == 0) need[F->s[i]] = 1;
 
     /* forward transform u~_s(q) = sum_j e^{-ik s_q.(y_j - c_s)} u_j */
     double complex *ut = calloc((size_t)nby * nq, sizeof(double complex));
@@ -838,6 +841,15 @@ void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride)
 /* =========================================================================
  * Queries
  * ========================================================================= */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int orc_leaf(const orc_plan *p) { return p->empty ? 0 : p->leaf; }
 double orc_d0(const orc_plan *p) { return p->d0; }
 void orc_corner(const orc_plan *p, int set, double *c3) { memcpy(c3, p->T[set].corner, sizeof(double) * 3); }

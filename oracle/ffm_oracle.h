@@ -63,10 +63,12 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
 void orc_plan_free(orc_plan *p);
 
 /* apply: v (complex, user target order) = FFM(wu (complex, user source order)).
- * stride > 1 evaluates only every stride-th box in every per-box loop (timing samples). */
+ * stride > 1 evaluates only every stride-th box in every per-box loop: a bounded
+ * timing sample whose result is not the product. */
 void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride);
 
 /* ---- queries for bit-exact comparison ------------------------------------- */
+int     orc_num_threads(void);                                     /* OpenMP threads used      */
 int     orc_leaf(const orc_plan *p);
 double  orc_d0(const orc_plan *p);
 void    orc_corner(const orc_plan *p, int set, double *c3);        /* set 0 = X (targets), 1 = Y */

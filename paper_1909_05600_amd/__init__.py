@@ -1,0 +1,235 @@
+"""Python binding of the gfx950 Fast Free Memory library (libffm.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI declared in ``include/ffm.h``.  PyTorch provides device
+memory and streams.  Importing this package does not build anything; a
+missing library raises at first use, loudly (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffm.so")
+
+FFM_LAPLACE = 0
+FFM_HELMHOLTZ = 1
+FFM_C64, FFM_F32, FFM_F64, FFM_C128 = 0, 1, 2, 3
+FFM_PREC_FP32, FFM_PREC_MIXED = 0, 1
+FFM_EXPORT_KEYS, FFM_EXPORT_PERM, FFM_EXPORT_BOX_START, FFM_EXPORT_BOX_IJK = 0, 1, 2, 3
+FFM_EXPORT_BOX_CTR, FFM_EXPORT_FAR, FFM_EXPORT_NEAR = 4, 5, 6
+MAX_LEVELS = 21
+
+STATUS = {0: "FFM_OK", -1: "FFM_EINVAL", -2: "FFM_ENOMEM", -3: "FFM_EDEVICE", -4: "FFM_EBUSY", -5: "FFM_EINTERNAL"}
+
+# every symbol the C ABI exports (include/ffm.h)
+EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_version", "ffm_plan_stats",
+            "ffm_plan_export", "ffm_plan_timing", "ffm_plan_bytes", "ffm_workspace_bytes"]
+FFM_FLAG_TIMING = 1
+TIMING_SLOTS = 64
+
+
+class FFMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(code, str(code)), msg))
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("n_leaf", C.c_int32), ("precision", C.c_int32), ("kd_switch", C.c_double),
+                ("r1_override", C.c_int32), ("max_level", C.c_int32), ("flags", C.c_uint32)]
+
+
+_L = MAX_LEVELS
+
+
+class Stats(C.Structure):
+    _fields_ = [("leaf", C.c_int32), ("same_set", C.c_int32), ("d0", C.c_double),
+                ("corner_x", C.c_double * 3), ("corner_y", C.c_double * 3),
+                ("nbox_x", C.c_int64 * _L), ("nbox_y", C.c_int64 * _L), ("nfar", C.c_int64 * _L),
+                ("nnear", C.c_int64 * _L), ("method", C.c_int32 * _L), ("order", C.c_int32 * _L),
+                ("nclass", C.c_int32 * _L), ("nq", C.c_int64 * _L), ("fwd_points", C.c_double * _L),
+                ("bwd_points", C.c_double * _L), ("transform_terms", C.c_double),
+                ("transfer_macs", C.c_double), ("near_pairs", C.c_double), ("plan_bytes", C.c_double),
+                ("workspace_bytes", C.c_double)]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+_lib = None
+
+
+def lib():
+    """Load libffm.so (built by paper_1909_05600_amd.build); raise if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libffm.so is not built: run paper_1909_05600_amd.build.build() "
+                               "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        sig = {
+            "ffm_plan": (C.c_int, [P, i64, P, i64, C.c_int, dbl, dbl, P, P, P]),
+            "ffm_apply": (C.c_int, [P, P, C.c_int, P, P]),
+            "ffm_destroy": (C.c_int, [P]),
+            "ffm_last_error": (C.c_char_p, []),
+            "ffm_version": (C.c_char_p, []),
+            "ffm_plan_stats": (C.c_int, [P, P]),
+            "ffm_plan_export": (C.c_int, [P, i32, i32, i32, P, P]),
+            "ffm_plan_timing": (C.c_int, [P, P, i32]),
+            "ffm_plan_bytes": (C.c_size_t, [P]),
+            "ffm_workspace_bytes": (C.c_size_t, [P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise FFMError(rc, lib().ffm_last_error().decode(errors="replace"))
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# ---------------------------------------------------------------- thin C-ABI mirrors
+def ffm_plan(X_ptr: int, n_x: int, Y_ptr: int, n_y: int, kernel: int, k: float, eps: float,
+             opts: Options | None = None, stream: int = 0) -> int:
+    h = C.c_void_p()
+    _check(lib().ffm_plan(X_ptr, n_x, Y_ptr, n_y, kernel, k, eps, C.byref(opts) if opts else None,
+                          stream, C.byref(h)))
+    return h.value
+
+
+def ffm_apply(plan: int, wu_ptr: int, in_dtype: int, v_ptr: int, stream: int = 0) -> None:
+    _check(lib().ffm_apply(plan, wu_ptr, in_dtype, v_ptr, stream))
+
+
+def ffm_destroy(plan: int) -> None:
+    _check(lib().ffm_destroy(plan))
+
+
+def ffm_version() -> str:
+    return lib().ffm_version().decode()
+
+
+# ---------------------------------------------------------------- torch-facing helper
+_DTYPES = None
+
+
+def _dtype_code(t) -> int:
+    import torch
+    global _DTYPES
+    if _DTYPES is None:
+        _DTYPES = {torch.complex64: FFM_C64, torch.float32: FFM_F32, torch.float64: FFM_F64,
+                   torch.complex128: FFM_C128}
+    if t.dtype not in _DTYPES:
+        raise TypeError("wu must be complex64, complex128, float32 or float64")
+    return _DTYPES[t.dtype]
+
+
+class Plan:
+    """An FFM plan over device coordinates X (targets) and Y (sources).
+
+    ``Plan(X, Y, kernel, k, eps)`` with X, Y FP64 CUDA tensors of shape (n, 3);
+    pass the same tensor object twice for one set.  ``apply(wu)`` returns v as
+    complex64 on the device, in the caller's order.
+    """
+
+    def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 0, precision: int = 0,
+                 kd_switch: float = 0.0, r1_override: int = 0, max_level: int = 0, timing: bool = False,
+                 stream=None):
+        import torch
+        same = Y is X
+        X = X.detach().contiguous()
+        if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != 3 or not X.is_cuda:
+            raise TypeError("X must be a CUDA float64 tensor of shape (n, 3)")
+        if same:
+            Y = X
+        else:
+            Y = Y.detach().contiguous()
+            if Y.dtype != torch.float64 or Y.dim() != 2 or Y.shape[1] != 3 or not Y.is_cuda:
+                raise TypeError("Y must be a CUDA float64 tensor of shape (n, 3)")
+        self.n_x, self.n_y = int(X.shape[0]), int(Y.shape[0])
+        self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
+        self.device = X.device
+        opts = Options(int(n_leaf), int(precision), float(kd_switch), int(r1_override), int(max_level),
+                       FFM_FLAG_TIMING if timing else 0)
+        self._h = None
+        with torch.cuda.device(self.device):
+            self._h = ffm_plan(X.data_ptr(), self.n_x, Y.data_ptr(), self.n_y, self.kernel, self.k, self.eps,
+                               opts, _stream(stream))
+
+    def apply(self, wu, out=None, stream=None):
+        import torch
+        if wu.shape[0] != self.n_y or not wu.is_cuda:
+            raise ValueError("wu must be a CUDA tensor of length n_y")
+        wu = wu.contiguous()
+        if out is None:
+            out = torch.empty(self.n_x, dtype=torch.complex64, device=self.device)
+        elif out.dtype != torch.complex64 or out.shape[0] != self.n_x or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 tensor of length n_x")
+        ffm_apply(self._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(), _stream(stream))
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().ffm_plan_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def export(self, what: int, set_: int = 0, level: int = 0):
+        import numpy as np
+        cnt = C.c_int64()
+        _check(lib().ffm_plan_export(self._h, what, set_, level, None, C.byref(cnt)))
+        dt = {FFM_EXPORT_KEYS: np.uint64, FFM_EXPORT_BOX_IJK: np.int32, FFM_EXPORT_BOX_CTR: np.float64}.get(
+            what, np.int64)
+        a = np.zeros(cnt.value, dtype=dt)
+        if cnt.value:
+            _check(lib().ffm_plan_export(self._h, what, set_, level, a.ctypes.data_as(C.c_void_p),
+                                         C.byref(cnt)))
+        if what in (FFM_EXPORT_BOX_IJK, FFM_EXPORT_BOX_CTR):
+            a = a.reshape(-1, 3)
+        elif what == FFM_EXPORT_FAR:
+            a = a.reshape(-1, 5)
+        elif what == FFM_EXPORT_NEAR:
+            a = a.reshape(-1, 2)
+        return a
+
+    def timing(self) -> list:
+        """Per-phase milliseconds of the last apply (plans made with timing=True)."""
+        buf = (C.c_float * TIMING_SLOTS)()
+        _check(lib().ffm_plan_timing(self._h, buf, TIMING_SLOTS))
+        return list(buf)
+
+    def plan_bytes(self) -> int:
+        return int(lib().ffm_plan_bytes(self._h))
+
+    def workspace_bytes(self) -> int:
+        return int(lib().ffm_workspace_bytes(self._h))
+
+    def destroy(self):
+        if self._h:
+            ffm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().ffm_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass

@@ -1,0 +1,596 @@
+// Apply: v = FFM(w u), one descent over the plan's levels, then the leaf near field.
+//
+// Paper: Sec. 2.2.2 (v ~ L_X^T (T (L_Y u)), Lagrange levels), Sec. 2.2.3 (v ~ F_{s->X} (T_L (F_{Y->s} u)),
+// Gegenbauer levels, eqs. gegenbauerQuadrature and the three products that follow it), Sec. 2.2.4 (dense
+// remainder), remark closing Sec. 2.2.3 (transforms evaluated on the fly at every level, no upward pass).
+//
+// Every output element is owned by exactly one thread of each kernel and accumulated in a fixed order,
+// so results are bitwise reproducible run to run.
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ffm {
+
+namespace {
+
+constexpr int kThreads = 256;
+inline int nblocks(int64_t n, int per = kThreads) { return (int)((n + per - 1) / per); }
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// sin(2 pi x), cos(2 pi x) for x in revolutions, x already reduced to [0, 1)
+__device__ __forceinline__ void sincos_rev(float x, float &s, float &c) {
+    s = __builtin_amdgcn_sinf(x);
+    c = __builtin_amdgcn_cosf(x);
+}
+
+// ------------------------------------------------------------------ permutations
+__global__ void __launch_bounds__(kThreads)
+k_perm_in(const void *wu, int dtype, const int32_t *perm, int64_t n, float2 *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    float2 r;
+    switch (dtype) {
+        case FFM_C64: r = static_cast<const float2 *>(wu)[j]; break;
+        case FFM_F32: r = make_float2(static_cast<const float *>(wu)[j], 0.f); break;
+        case FFM_F64: r = make_float2((float)static_cast<const double *>(wu)[j], 0.f); break;
+        default: {
+            const double2 d = static_cast<const double2 *>(wu)[j];
+            r = make_float2((float)d.x, (float)d.y);
+        }
+    }
+    out[i] = r;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_perm_out(const float2 *vs, const int32_t *perm, int64_t n, float2 *v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[perm[i]] = vs[i];
+}
+
+// ------------------------------------------------------------------ Gegenbauer levels
+// Forward transform u~_s(q) = sum_{j in s} e^{-ik s_q.(y_j - c_s)} u_j for an antipodal pair
+// (q, -q): with S = sum cos(th) u, T = sum sin(th) u, u~(q) = S - iT and u~(-q) = S + iT.
+// Block: one source box and 256*PPT direction pairs; the box's points stream through LDS.
+template <int PPT, bool P64>
+__global__ void __launch_bounds__(kThreads)
+k_pw_forward(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+             const float2 *__restrict__ u, const int32_t *__restrict__ start, const double *__restrict__ ctr,
+             const int32_t *__restrict__ boxes, const float4 *__restrict__ dirs, const double *__restrict__ dirs64,
+             int64_t npair, int ntile, float4 *__restrict__ out) {
+    const int b = boxes[blockIdx.x / ntile];
+    const int tile = blockIdx.x % ntile;
+    const int tid = threadIdx.x;
+    const int64_t p0 = (int64_t)tile * kThreads * PPT + tid;
+    typedef typename std::conditional<P64, double, float>::type real;
+    real sx[PPT], sy[PPT], sz[PPT];
+    float Sre[PPT], Sim[PPT], Tre[PPT], Tim[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int64_t p = p0 + (int64_t)j * kThreads;
+        const int64_t pc = p < npair ? p : npair - 1;
+        if (P64) {
+            sx[j] = dirs64[3 * pc]; sy[j] = dirs64[3 * pc + 1]; sz[j] = dirs64[3 * pc + 2];
+        } else {
+            const float4 d = dirs[pc];
+            sx[j] = d.x; sy[j] = d.y; sz[j] = d.z;
+        }
+        Sre[j] = Sim[j] = Tre[j] = Tim[j] = 0.f;
+    }
+    const double cx = ctr[3 * b], cy = ctr[3 * b + 1], cz = ctr[3 * b + 2];
+    __shared__ real px[kThreads], py[kThreads], pz[kThreads];
+    __shared__ float2 us[kThreads];
+    const int i0 = start[b], i1 = start[b + 1];
+    for (int s0 = i0; s0 < i1; s0 += kThreads) {
+        const int cnt = min(kThreads, i1 - s0);
+        __syncthreads();
+        if (tid < cnt) {
+            const int i = s0 + tid;
+            px[tid] = (real)(xs[i] - cx);
+            py[tid] = (real)(ys[i] - cy);
+            pz[tid] = (real)(zs[i] - cz);
+            us[tid] = u[i];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; ++jj) {
+            const real x = px[jj], y = py[jj], z = pz[jj];
+            const float2 uu = us[jj];
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                float f;
+                if (P64) {
+                    const double ph = fma(sx[j], x, fma(sy[j], y, (double)sz[j] * z));
+                    f = (float)__builtin_amdgcn_fract(ph);
+                } else {
+                    const float ph = fmaf(sx[j], x, fmaf(sy[j], y, (float)sz[j] * z));
+                    f = __builtin_amdgcn_fractf(ph);
+                }
+                float sn, cs;
+                sincos_rev(f, sn, cs);
+                Sre[j] = fmaf(cs, uu.x, Sre[j]);
+                Sim[j] = fmaf(cs, uu.y, Sim[j]);
+                Tre[j] = fmaf(sn, uu.x, Tre[j]);
+                Tim[j] = fmaf(sn, uu.y, Tim[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int64_t p = p0 + (int64_t)j * kThreads;
+        if (p < npair)
+            out[(int64_t)b * npair + p] = make_float4(Sre[j] + Tim[j], Sim[j] - Tre[j], Sre[j] - Tim[j], Sim[j] + Tre[j]);
+    }
+}
+
+// Diagonal transfer v~_t(q) = sum_{s in far(t)} D_{c(t,s)}(q) u~_s(q) (both directions of a pair).
+template <int PPT>
+__global__ void __launch_bounds__(kThreads)
+k_pw_transfer(const int32_t *__restrict__ tboxes, const int64_t *__restrict__ far_ptr,
+              const int32_t *__restrict__ far_src, const int32_t *__restrict__ far_cls, const float4 *__restrict__ D,
+              const float4 *__restrict__ ut, int64_t npair, int ntile, float4 *__restrict__ vt) {
+    const int t = tboxes[blockIdx.x / ntile];
+    const int tile = blockIdx.x % ntile;
+    const int64_t p0 = (int64_t)tile * kThreads * PPT + threadIdx.x;
+    float4 acc[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t e0 = far_ptr[t], e1 = far_ptr[t + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t s = far_src[e], c = far_cls[e];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int64_t p = p0 + (int64_t)j * kThreads;
+            if (p < npair) {
+                const float4 d = D[c * npair + p];
+                const float4 w = ut[s * npair + p];
+                acc[j].x = fmaf(d.x, w.x, fmaf(-d.y, w.y, acc[j].x));
+                acc[j].y = fmaf(d.x, w.y, fmaf(d.y, w.x, acc[j].y));
+                acc[j].z = fmaf(d.z, w.z, fmaf(-d.w, w.w, acc[j].z));
+                acc[j].w = fmaf(d.z, w.w, fmaf(d.w, w.z, acc[j].w));
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int64_t p = p0 + (int64_t)j * kThreads;
+        if (p < npair) vt[(int64_t)t * npair + p] = acc[j];
+    }
+}
+
+// Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q)
+// and B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Thread per target point.
+template <bool P64>
+__global__ void __launch_bounds__(kThreads)
+k_pw_backward(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+              const int32_t *__restrict__ start, const double *__restrict__ ctr, const int2 *__restrict__ work,
+              const float4 *__restrict__ dirs, const double *__restrict__ dirs64, const float4 *__restrict__ vt,
+              int64_t npair, float2 *__restrict__ v) {
+    const int2 wk = work[blockIdx.x];
+    const int t = wk.x;
+    const int tid = threadIdx.x;
+    const int i = wk.y + tid;
+    const bool valid = i < start[t + 1];
+    typedef typename std::conditional<P64, double, float>::type real;
+    real x = 0, y = 0, z = 0;
+    if (valid) {
+        x = (real)(xs[i] - ctr[3 * t]);
+        y = (real)(ys[i] - ctr[3 * t + 1]);
+        z = (real)(zs[i] - ctr[3 * t + 2]);
+    }
+    float are = 0.f, aim = 0.f;
+    __shared__ real sdx[kThreads], sdy[kThreads], sdz[kThreads];
+    __shared__ float4 ab[kThreads];
+    const float4 *vb = vt + (int64_t)t * npair;
+    for (int64_t q0 = 0; q0 < npair; q0 += kThreads) {
+        const int cnt = (int)min<int64_t>(kThreads, npair - q0);
+        __syncthreads();
+        if (tid < cnt) {
+            const int64_t q = q0 + tid;
+            if (P64) {
+                sdx[tid] = dirs64[3 * q]; sdy[tid] = dirs64[3 * q + 1]; sdz[tid] = dirs64[3 * q + 2];
+            } else {
+                const float4 d = dirs[q];
+                sdx[tid] = d.x; sdy[tid] = d.y; sdz[tid] = d.z;
+            }
+            const float4 w = vb[q];
+            ab[tid] = make_float4(w.x + w.z, w.y + w.w, w.x - w.z, w.y - w.w);
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; ++jj) {
+            float f;
+            if (P64) {
+                const double ph = fma((double)sdx[jj], x, fma((double)sdy[jj], y, (double)sdz[jj] * z));
+                f = (float)__builtin_amdgcn_fract(ph);
+            } else {
+                const float ph = fmaf((float)sdx[jj], x, fmaf((float)sdy[jj], y, (float)sdz[jj] * z));
+                f = __builtin_amdgcn_fractf(ph);
+            }
+            float sn, cs;
+            sincos_rev(f, sn, cs);
+            const float4 w = ab[jj];
+            are = fmaf(cs, w.x, fmaf(-sn, w.w, are));
+            aim = fmaf(cs, w.y, fmaf(sn, w.z, aim));
+        }
+    }
+    if (valid) {
+        float2 o = v[i];
+        o.x += are;
+        o.y += aim;
+        v[i] = o;
+    }
+}
+
+// ------------------------------------------------------------------ Lagrange levels
+constexpr int kMaxR1 = 8;
+constexpr int kAnterpChunk = 64;
+
+// One-dimensional Lagrange polynomials on the Chebyshev nodes at t (denominators precomputed).
+__device__ __forceinline__ void lagrange_1d(float t, int r1, const float *nodes, const float *inv_den, float *ell) {
+    for (int a = 0; a < r1; ++a) {
+        float v = inv_den[a];
+        for (int b = 0; b < r1; ++b)
+            if (b != a) v *= (t - nodes[b]);
+        ell[a] = v;
+    }
+}
+
+// u~_s = L_Y u_s: u~_s[(a r1 + b) r1 + c] = sum_j l_a(t_x) l_b(t_y) l_c(t_z) u_j, t = 2 (y - c_s) / d_l.
+__global__ void __launch_bounds__(kThreads)
+k_lag_anterp(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+             const float2 *__restrict__ u, const int32_t *__restrict__ start, const double *__restrict__ ctr,
+             const int32_t *__restrict__ boxes, int r1, int rp, const float *__restrict__ nodes_g,
+             const float *__restrict__ den_g, double two_over_dl, float2 *__restrict__ ut) {
+    const int b = boxes[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int r = r1 * r1 * r1;
+    __shared__ float ell[kAnterpChunk][3 * kMaxR1];
+    __shared__ float2 us[kAnterpChunk];
+    __shared__ float nodes[kMaxR1], den[kMaxR1];
+    if (tid < r1) {
+        nodes[tid] = nodes_g[tid];
+        den[tid] = den_g[tid];
+    }
+    constexpr int kOut = (kMaxR1 * kMaxR1 * kMaxR1 + kThreads - 1) / kThreads;
+    float2 acc[kOut];
+    int ia[kOut], ib[kOut], ic[kOut];
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) {
+        const int i = tid + o * kThreads;
+        acc[o] = make_float2(0.f, 0.f);
+        const int ii = i < r ? i : 0;
+        ia[o] = ii / (r1 * r1);
+        ib[o] = (ii / r1) % r1;
+        ic[o] = ii % r1;
+    }
+    const int nout = (r + kThreads - 1) / kThreads;
+    const double cx = ctr[3 * b], cy = ctr[3 * b + 1], cz = ctr[3 * b + 2];
+    const int i0 = start[b], i1 = start[b + 1];
+    for (int s0 = i0; s0 < i1; s0 += kAnterpChunk) {
+        const int cnt = min(kAnterpChunk, i1 - s0);
+        __syncthreads();
+        if (tid < cnt) {
+            const int j = s0 + tid;
+            lagrange_1d((float)((xs[j] - cx) * two_over_dl), r1, nodes, den, &ell[tid][0]);
+            lagrange_1d((float)((ys[j] - cy) * two_over_dl), r1, nodes, den, &ell[tid][r1]);
+            lagrange_1d((float)((zs[j] - cz) * two_over_dl), r1, nodes, den, &ell[tid][2 * r1]);
+            us[tid] = u[j];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; ++jj) {
+            const float2 uu = us[jj];
+#pragma unroll
+            for (int o = 0; o < kOut; ++o) {
+                if (o < nout) {
+                    const float w = ell[jj][ia[o]] * ell[jj][r1 + ib[o]] * ell[jj][2 * r1 + ic[o]];
+                    acc[o].x = fmaf(w, uu.x, acc[o].x);
+                    acc[o].y = fmaf(w, uu.y, acc[o].y);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) {
+        const int i = tid + o * kThreads;
+        if (o < nout && i < rp) ut[(int64_t)b * rp + i] = (i < r) ? acc[o] : make_float2(0.f, 0.f);
+    }
+    for (int i = r + tid; i < rp; i += kThreads) ut[(int64_t)b * rp + i] = make_float2(0.f, 0.f);
+}
+
+// Transfer products of one class group on MFMA: Z_e = T_c u~_{s(e)} for up to 16 pairs e.
+// C (rp x 32) = T_c (rp x rp) x U (rp x 32), U[k][2m + part] = part of u~_{s(e_m)}[k].
+// v_mfma_f32_32x32x2f32 operands: A[i][k] from lane i + 32 k, B[k][j] from lane j + 32 k,
+// D[i][j] in lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8).
+__global__ void __launch_bounds__(64)
+k_lag_mfma(const float *__restrict__ T, int helm, const float2 *__restrict__ ut, const int32_t *__restrict__ far_src,
+           const int32_t *__restrict__ grp_pair, const int32_t *__restrict__ grp_cls, int rp, float2 *__restrict__ Z) {
+    extern __shared__ float U[];   // [rp][32]
+    const int g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c = grp_cls[g];
+    __shared__ int pe[16], ps[16];
+    if (lane < 16) {
+        const int e = grp_pair[(int64_t)g * 16 + lane];
+        pe[lane] = e;
+        ps[lane] = e >= 0 ? far_src[e] : -1;
+    }
+    __syncthreads();
+    for (int idx = lane; idx < rp * 32; idx += 64) {
+        const int k = idx >> 5, col = idx & 31, m = col >> 1;
+        float val = 0.f;
+        if (ps[m] >= 0) {
+            const float2 w = ut[(int64_t)ps[m] * rp + k];
+            val = (col & 1) ? w.y : w.x;
+        }
+        U[idx] = val;
+    }
+    __syncthreads();
+    const int64_t per = (int64_t)rp * rp;
+    const float *Tre = T + (int64_t)c * (helm ? 2 : 1) * per;
+    const float *Tim = Tre + per;
+    const int col = lane & 31, kh = lane >> 5;
+    const int m = col >> 1;
+    const int e = pe[m];
+    for (int mt = 0; mt < rp / 32; ++mt) {
+        floatx16 acc1, acc2;
+        for (int v = 0; v < 16; ++v) {
+            acc1[v] = 0.f;
+            acc2[v] = 0.f;
+        }
+        for (int kk = 0; kk < rp / 2; ++kk) {
+            const int k = 2 * kk + kh;
+            const float bval = U[k * 32 + col];
+            const float a1 = Tre[(int64_t)k * rp + mt * 32 + col];
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bval, acc1, 0, 0, 0);
+            if (helm) {
+                const float a2 = Tim[(int64_t)k * rp + mt * 32 + col];
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bval, acc2, 0, 0, 0);
+            }
+        }
+        for (int v = 0; v < 16; ++v) {
+            const int i = mt * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+            float val = acc1[v];
+            if (helm) {
+                const float sw = __shfl_xor(acc2[v], 1, 64);
+                val = (col & 1) ? val + sw : val - sw;
+            }
+            if (e >= 0) reinterpret_cast<float *>(Z + (int64_t)e * rp + i)[col & 1] = val;
+        }
+    }
+}
+
+// v_i += L_X^T v~_t with v~_t = sum_{e in far(t)} Z_e (fixed order), t = 2 (x - c_t) / d_l.
+__global__ void __launch_bounds__(kThreads)
+k_lag_interp(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+             const int32_t *__restrict__ start, const double *__restrict__ ctr, const int32_t *__restrict__ tboxes,
+             const int64_t *__restrict__ far_ptr, const float2 *__restrict__ Z, int r1, int rp,
+             const float *__restrict__ nodes_g, const float *__restrict__ den_g, double two_over_dl,
+             float2 *__restrict__ v) {
+    extern __shared__ float2 vt[];   // [r]
+    __shared__ float nodes[kMaxR1], den[kMaxR1];
+    const int t = tboxes[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int r = r1 * r1 * r1;
+    if (tid < r1) {
+        nodes[tid] = nodes_g[tid];
+        den[tid] = den_g[tid];
+    }
+    const int64_t e0 = far_ptr[t], e1 = far_ptr[t + 1];
+    for (int i = tid; i < r; i += kThreads) {
+        float2 a = make_float2(0.f, 0.f);
+        for (int64_t e = e0; e < e1; ++e) {
+            const float2 z = Z[e * rp + i];
+            a.x += z.x;
+            a.y += z.y;
+        }
+        vt[i] = a;
+    }
+    __syncthreads();
+    const double cx = ctr[3 * t], cy = ctr[3 * t + 1], cz = ctr[3 * t + 2];
+    for (int i = start[t] + tid; i < start[t + 1]; i += kThreads) {
+        float lx[kMaxR1], ly[kMaxR1], lz[kMaxR1];
+        lagrange_1d((float)((xs[i] - cx) * two_over_dl), r1, nodes, den, lx);
+        lagrange_1d((float)((ys[i] - cy) * two_over_dl), r1, nodes, den, ly);
+        lagrange_1d((float)((zs[i] - cz) * two_over_dl), r1, nodes, den, lz);
+        float sre = 0.f, sim = 0.f;
+        for (int a = 0; a < r1; ++a) {
+            float bre = 0.f, bim = 0.f;
+            for (int bb = 0; bb < r1; ++bb) {
+                float cre = 0.f, cim = 0.f;
+                const float2 *row = vt + (a * r1 + bb) * r1;
+                for (int c = 0; c < r1; ++c) {
+                    cre = fmaf(lz[c], row[c].x, cre);
+                    cim = fmaf(lz[c], row[c].y, cim);
+                }
+                bre = fmaf(ly[bb], cre, bre);
+                bim = fmaf(ly[bb], cim, bim);
+            }
+            sre = fmaf(lx[a], bre, sre);
+            sim = fmaf(lx[a], bim, sim);
+        }
+        float2 o = v[i];
+        o.x += sre;
+        o.y += sim;
+        v[i] = o;
+    }
+}
+
+// ------------------------------------------------------------------ near field (leaf)
+// v_i += sum_{s in near(t)} sum_{j in s, r_ij > 0} G(r_ij) u_j.  One 64-lane block per target box;
+// source points are staged through LDS relative to the target centre, in FP32.
+template <bool HELM>
+__global__ void __launch_bounds__(64)
+k_near(const double *__restrict__ txs, const double *__restrict__ tys, const double *__restrict__ tzs,
+       const int32_t *__restrict__ tstart, const double *__restrict__ tctr, const double *__restrict__ sxs,
+       const double *__restrict__ sys, const double *__restrict__ szs, const int32_t *__restrict__ sstart,
+       const float2 *__restrict__ u, const int32_t *__restrict__ tboxes, const int64_t *__restrict__ near_ptr,
+       const int32_t *__restrict__ near_src, float k_rev, float2 *__restrict__ v) {
+    const int t = tboxes[blockIdx.x];
+    const int lane = threadIdx.x;
+    const double cx = tctr[3 * t], cy = tctr[3 * t + 1], cz = tctr[3 * t + 2];
+    __shared__ float4 sp[64];   // x, y, z relative to c_t; unused
+    __shared__ float2 su[64];   // u / (4 pi)
+    const float inv4pi = (float)(1.0 / (4.0 * M_PI));
+    const int64_t e0 = near_ptr[t], e1 = near_ptr[t + 1];
+    for (int i0 = tstart[t]; i0 < tstart[t + 1]; i0 += 64) {
+        const int i = i0 + lane;
+        const bool valid = i < tstart[t + 1];
+        float x = 0.f, y = 0.f, z = 0.f;
+        if (valid) {
+            x = (float)(txs[i] - cx);
+            y = (float)(tys[i] - cy);
+            z = (float)(tzs[i] - cz);
+        }
+        float are = 0.f, aim = 0.f;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int s = near_src[e];
+            const int j0 = sstart[s], j1 = sstart[s + 1];
+            for (int c0 = j0; c0 < j1; c0 += 64) {
+                const int cnt = min(64, j1 - c0);
+                __syncthreads();
+                if (lane < cnt) {
+                    const int j = c0 + lane;
+                    sp[lane] = make_float4((float)(sxs[j] - cx), (float)(sys[j] - cy), (float)(szs[j] - cz), 0.f);
+                    const float2 uu = u[j];
+                    su[lane] = make_float2(uu.x * inv4pi, uu.y * inv4pi);
+                }
+                __syncthreads();
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const float4 p = sp[jj];
+                    const float2 uu = su[jj];
+                    const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                    if (HELM) {
+                        const float ph = r2 * inv * k_rev;
+                        float sn, cs;
+                        sincos_rev(__builtin_amdgcn_fractf(ph), sn, cs);
+                        const float gr = cs * inv, gi = sn * inv;
+                        are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
+                        aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
+                    } else {
+                        are = fmaf(inv, uu.x, are);
+                        aim = fmaf(inv, uu.y, aim);
+                    }
+                }
+            }
+        }
+        if (valid) {
+            float2 o = v[i];
+            o.x += are;
+            o.y += aim;
+            v[i] = o;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_zero2(float2 *a, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = make_float2(0.f, 0.f);
+}
+
+template <int PPT, bool P64>
+void launch_forward(const Plan &P, const Level &LV, const Tree &TY, int l, hipStream_t st) {
+    const int ntile = (int)((LV.npair + kThreads * PPT - 1) / (kThreads * PPT));
+    const int64_t nb = (int64_t)LV.fwd_boxes.n * ntile;
+    FFM_CHECK(nb < (int64_t)1 << 31, FFM_EINTERNAL, "forward grid too large");
+    FFM_LAUNCH((k_pw_forward<PPT, P64>), (int)nb, kThreads, 0, st, TY.xs.p, TY.ys.p, TY.zs.p, P.u_sorted.p,
+               TY.lev[l].start.p, TY.lev[l].ctr.p, LV.fwd_boxes.p, (const float4 *)LV.dirs.p, LV.dirs64.p, LV.npair,
+               ntile, P.wsrc.p);
+}
+
+template <int PPT>
+void launch_transfer(const Plan &P, const Level &LV, hipStream_t st) {
+    const int ntile = (int)((LV.npair + kThreads * PPT - 1) / (kThreads * PPT));
+    const int64_t nb = (int64_t)LV.tgt_boxes.n * ntile;
+    FFM_CHECK(nb < (int64_t)1 << 31, FFM_EINTERNAL, "transfer grid too large");
+    FFM_LAUNCH((k_pw_transfer<PPT>), (int)nb, kThreads, 0, st, LV.tgt_boxes.p, LV.far_ptr.p, LV.far_src.p,
+               LV.far_cls.p, LV.D.p, P.wsrc.p, LV.npair, ntile, P.wtgt.p);
+}
+
+}  // namespace
+
+// Record the end of a phase (timing plans only): the first call opens the apply.
+void Plan::mark(int phase, hipStream_t st) {
+    if (tev.empty()) return;
+    FFM_CHECK(tused < (int)tev.size(), FFM_EINTERNAL, "timing events exhausted");
+    FFM_HIP(hipEventRecord(tev[tused], st));
+    tphase[tused] = phase;
+    ++tused;
+}
+
+void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
+    P.tused = 0;
+    P.mark(-1, st);
+    if (P.empty) {
+        FFM_LAUNCH(k_zero2, nblocks(P.nx), kThreads, 0, st, v, P.nx);
+        return;
+    }
+    Tree &TX = *P.tx, &TY = *P.ty;
+    FFM_LAUNCH(k_perm_in, nblocks(P.ny), kThreads, 0, st, wu, dtype, TY.perm.p, P.ny, P.u_sorted.p);
+    FFM_LAUNCH(k_zero2, nblocks(P.nx), kThreads, 0, st, P.v_sorted.p, P.nx);
+    P.mark(0, st);
+    const bool helm = P.kernel == FFM_HELMHOLTZ;
+    for (int l = 1; l <= P.leaf; ++l) {
+        const Level &LV = P.lev[l];
+        if (LV.method == kGegenbauer) {
+            // source transform, diagonal transfer, target transform (Sec. 2.2.3)
+            if (LV.npair >= 4 * kThreads) {
+                if (LV.phase64) launch_forward<4, true>(P, LV, TY, l, st);
+                else launch_forward<4, false>(P, LV, TY, l, st);
+            } else if (LV.npair >= 2 * kThreads) {
+                if (LV.phase64) launch_forward<2, true>(P, LV, TY, l, st);
+                else launch_forward<2, false>(P, LV, TY, l, st);
+            } else {
+                if (LV.phase64) launch_forward<1, true>(P, LV, TY, l, st);
+                else launch_forward<1, false>(P, LV, TY, l, st);
+            }
+            P.mark(1 + 3 * (l - 1), st);
+            if (LV.npair >= 2 * kThreads) launch_transfer<2>(P, LV, st);
+            else launch_transfer<1>(P, LV, st);
+            P.mark(2 + 3 * (l - 1), st);
+            if (LV.phase64)
+                FFM_LAUNCH(k_pw_backward<true>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p, TX.zs.p,
+                           TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, (const float4 *)LV.dirs.p, LV.dirs64.p,
+                           P.wtgt.p, LV.npair, P.v_sorted.p);
+            else
+                FFM_LAUNCH(k_pw_backward<false>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p, TX.zs.p,
+                           TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, (const float4 *)LV.dirs.p, LV.dirs64.p,
+                           P.wtgt.p, LV.npair, P.v_sorted.p);
+            P.mark(3 + 3 * (l - 1), st);
+        } else if (LV.method == kLagrange) {
+            // interpolation, MFMA transfer, interpolation back (Sec. 2.2.2)
+            const double dl = std::ldexp(P.d0, -l);
+            float2 *ut = reinterpret_cast<float2 *>(P.wsrc.p);
+            FFM_LAUNCH(k_lag_anterp, (int)LV.fwd_boxes.n, kThreads, 0, st, TY.xs.p, TY.ys.p, TY.zs.p, P.u_sorted.p,
+                       TY.lev[l].start.p, TY.lev[l].ctr.p, LV.fwd_boxes.p, LV.r1, LV.rp, LV.lnodes.p, LV.lden.p,
+                       2.0 / dl, ut);
+            FFM_LAUNCH(k_lag_mfma, LV.ngrp, 64, sizeof(float) * LV.rp * 32, st, LV.T.p, helm ? 1 : 0, ut,
+                       LV.far_src.p, LV.grp_pair.p, LV.grp_cls.p, LV.rp, P.wz.p);
+            P.mark(1 + 3 * (l - 1), st);   // interpolation and transfer share the first two slots
+            P.mark(2 + 3 * (l - 1), st);
+            FFM_LAUNCH(k_lag_interp, (int)LV.tgt_boxes.n, kThreads, sizeof(float2) * LV.r, st, TX.xs.p, TX.ys.p,
+                       TX.zs.p, TX.lev[l].start.p, TX.lev[l].ctr.p, LV.tgt_boxes.p, LV.far_ptr.p, P.wz.p, LV.r1,
+                       LV.rp, LV.lnodes.p, LV.lden.p, 2.0 / dl, P.v_sorted.p);
+            P.mark(3 + 3 * (l - 1), st);
+        }
+    }
+    // dense remainder at the leaf (Sec. 2.2.4)
+    const Level &LL = P.lev[P.leaf];
+    const float k_rev = (float)(P.k / (2.0 * M_PI));
+    if (helm)
+        FFM_LAUNCH(k_near<true>, (int)LL.near_boxes.n, 64, 0, st, TX.xs.p, TX.ys.p, TX.zs.p, TX.lev[P.leaf].start.p,
+                   TX.lev[P.leaf].ctr.p, TY.xs.p, TY.ys.p, TY.zs.p, TY.lev[P.leaf].start.p, P.u_sorted.p,
+                   LL.near_boxes.p, LL.near_ptr.p, LL.near_src.p, k_rev, P.v_sorted.p);
+    else
+        FFM_LAUNCH(k_near<false>, (int)LL.near_boxes.n, 64, 0, st, TX.xs.p, TX.ys.p, TX.zs.p, TX.lev[P.leaf].start.p,
+                   TX.lev[P.leaf].ctr.p, TY.xs.p, TY.ys.p, TY.zs.p, TY.lev[P.leaf].start.p, P.u_sorted.p,
+                   LL.near_boxes.p, LL.near_ptr.p, LL.near_src.p, k_rev, P.v_sorted.p);
+    P.mark(61, st);
+    FFM_LAUNCH(k_perm_out, nblocks(P.nx), kThreads, 0, st, P.v_sorted.p, TX.perm.p, P.nx, v);
+    P.mark(62, st);
+}
+
+}  // namespace ffm

@@ -1,0 +1,939 @@
+// Planner: root cubes, Morton-sorted octrees, descent lists and transfer tables.
+//
+// Paper: Sec. 2.2.1 (root cubes with a common edge d_0, d_l = d_0 / 2^l),
+// Sec. 2.1 (two octrees whose boxes are translates of each other), Sec. 2.2.2
+// (admissibility; Lagrange interpolation on Chebyshev nodes), Sec. 2.2.3
+// (Gegenbauer series eq. gegenbauerSerie, rank eq. gegenbauerRank, quadrature
+// eq. gegenbauerQuadrature), Sec. 2.2.4 (stopping rule), Sec. 3.2 proof of
+// Prop. 1 (one transfer per translation class, descent-only lists).
+//
+// Geometry that must match an FP64 reference bit for bit (quantisation, box
+// centres, the far test of shifted trees) is computed without FMA contraction.
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+
+namespace ffm {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int nblocks(int64_t n, int per = kThreads) { return (int)((n + per - 1) / per); }
+
+// ------------------------------------------------------------------ bounding boxes
+__global__ void __launch_bounds__(kThreads) k_bbox_partial(const double *P, int64_t n, double *part, int *bad) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int nbad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int d = 0; d < 3; ++d) {
+            double v = P[3 * i + d];
+            if (!isfinite(v)) nbad = 1;
+            lo[d] = fmin(lo[d], v);
+            hi[d] = fmax(hi[d], v);
+        }
+    }
+    __shared__ double s[6][kThreads];
+    for (int d = 0; d < 3; ++d) {
+        s[d][threadIdx.x] = lo[d];
+        s[3 + d][threadIdx.x] = hi[d];
+    }
+    if (nbad) atomicOr(bad, 1);
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int d = 0; d < 3; ++d) {
+                s[d][threadIdx.x] = fmin(s[d][threadIdx.x], s[d][threadIdx.x + o]);
+                s[3 + d][threadIdx.x] = fmax(s[3 + d][threadIdx.x], s[3 + d][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_bbox_final(const double *part, int nb, double *out) {
+    __shared__ double s[6][kThreads];
+    for (int d = 0; d < 6; ++d) {
+        double v = d < 3 ? INFINITY : -INFINITY;
+        for (int b = threadIdx.x; b < nb; b += kThreads) v = d < 3 ? fmin(v, part[6 * b + d]) : fmax(v, part[6 * b + d]);
+        s[d][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int d = 0; d < 6; ++d)
+                s[d][threadIdx.x] = d < 3 ? fmin(s[d][threadIdx.x], s[d][threadIdx.x + o])
+                                          : fmax(s[d][threadIdx.x], s[d][threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------------ Morton keys
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ __forceinline__ int32_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (int32_t)v;
+}
+
+// q = clamp(floor((p - corner) * S), 0, 2^21 - 1): one rounded subtraction, one rounded product.
+__device__ __forceinline__ uint64_t quantise(double p, double c, double S) {
+#pragma clang fp contract(off)
+    double t = (p - c) * S;
+    double f = floor(t);
+    if (!(f >= 0.0)) return 0;
+    if (f >= (double)((1 << kBits) - 1)) return (uint64_t)((1 << kBits) - 1);
+    return (uint64_t)f;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_morton(const double *P, int64_t n, double cx, double cy, double cz, double S, uint64_t *key, int32_t *idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t qx = quantise(P[3 * i], cx, S), qy = quantise(P[3 * i + 1], cy, S), qz = quantise(P[3 * i + 2], cz, S);
+    key[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    idx[i] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_gather(const double *P, int64_t n, const int32_t *perm, double *xs, double *ys, double *zs) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    xs[i] = P[3 * j];
+    ys[i] = P[3 * j + 1];
+    zs[i] = P[3 * j + 2];
+}
+
+// First level at which point i starts a box: boxes of level l are the runs of key >> 3(21 - l).
+// 22 = never (equal keys).  Also a histogram of those levels (block-local, then one add per bin).
+__global__ void __launch_bounds__(kThreads)
+k_first_level(const uint64_t *key, int64_t n, int8_t *f, int32_t *hist) {
+    __shared__ int32_t h[23];
+    if (threadIdx.x < 23) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        int lev;
+        if (i == 0) {
+            lev = 0;
+        } else {
+            const uint64_t x = key[i] ^ key[i - 1];
+            if (x == 0) {
+                lev = 22;
+            } else {
+                const int b = 63 - __clzll((long long)x);   // highest differing bit, 0..62
+                lev = (63 - b + 2) / 3;                     // smallest l with b >= 3 (21 - l)
+            }
+        }
+        f[i] = (int8_t)lev;
+        atomicAdd(&h[lev], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 23 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_flags(const int8_t *f, int64_t n, int l, int32_t *flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = (f[i] <= l) ? 1 : 0;
+}
+
+// Boxes of level l from the scanned start flags; centres c = corner + (2i + 1) * (d_0 2^-(l+1)).
+__global__ void __launch_bounds__(kThreads)
+k_level_boxes(const uint64_t *key, const int8_t *f, const int32_t *pos, int64_t n, int l, double cx, double cy,
+              double cz, double h, int32_t *start, int32_t *ijk, double *ctr, int32_t *boxid, int32_t nbox) {
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool st = f[i] <= l;
+    const int32_t b = pos[i] + (st ? 0 : -1);
+    boxid[i] = b;
+    if (!st) return;
+    start[b] = (int32_t)i;
+    const uint64_t pre = key[i] >> (3 * (kBits - l));
+    const int32_t a0 = compact3(pre >> 2), a1 = compact3(pre >> 1), a2 = compact3(pre);
+    ijk[3 * b] = a0;
+    ijk[3 * b + 1] = a1;
+    ijk[3 * b + 2] = a2;
+    // product and sum rounded separately (no FMA)
+    ctr[3 * b] = cx + (double)(2 * a0 + 1) * h;
+    ctr[3 * b + 1] = cy + (double)(2 * a1 + 1) * h;
+    ctr[3 * b + 2] = cz + (double)(2 * a2 + 1) * h;
+    if (i == 0) start[nbox] = (int32_t)n;
+}
+
+// parent of box b (level l) and children of box B (level l-1)
+__global__ void __launch_bounds__(kThreads)
+k_link(const int32_t *start_l, int32_t nb_l, const int32_t *boxid_prev, int32_t *parent_l,
+       const int32_t *start_p, int32_t nb_p, const int32_t *boxid_cur, int32_t *child_p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb_l) parent_l[i] = boxid_prev[start_l[i]];
+    if (i < nb_p) child_p[i] = boxid_cur[start_p[i]];
+    if (i == 0) child_p[nb_p] = nb_l;
+}
+
+// ------------------------------------------------------------------ descent lists
+struct FarTest {
+    const int32_t *ijk_t, *ijk_s;
+    const double *ctr_t, *ctr_s;
+    double two_dl;
+    int aligned;
+    int32_t base[3];
+};
+
+// Admissibility (Sec. 2.2.2): max-norm centre distance >= 2 d_l.  Aligned trees use the
+// integer box offsets (exact); shifted trees compare FP64 centre differences.
+__device__ __forceinline__ bool is_far(const FarTest &ft, int32_t t, int32_t s) {
+    if (ft.aligned) {
+        int m = 0;
+        for (int d = 0; d < 3; ++d) m = max(m, abs(ft.ijk_t[3 * t + d] - ft.ijk_s[3 * s + d]));
+        return m >= 2;
+    }
+    double m = 0.0;
+    for (int d = 0; d < 3; ++d) m = fmax(m, fabs(ft.ctr_t[3 * t + d] - ft.ctr_s[3 * s + d]));
+    return m >= ft.two_dl;
+}
+
+// For every target box t of level l: the children of the near sources of its parent.
+__global__ void __launch_bounds__(kThreads)
+k_list_count(int32_t nbx, const int32_t *parent_x, const int64_t *pnear_ptr, const int32_t *pnear_src,
+             const int32_t *child_y, FarTest ft, int64_t *nfar, int64_t *nnear) {
+    int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbx) return;
+    const int32_t T = parent_x[t];
+    int64_t cf = 0, cn = 0;
+    for (int64_t e = pnear_ptr[T]; e < pnear_ptr[T + 1]; ++e) {
+        const int32_t S = pnear_src[e];
+        for (int32_t cs = child_y[S]; cs < child_y[S + 1]; ++cs) {
+            if (is_far(ft, t, cs)) ++cf;
+            else ++cn;
+        }
+    }
+    nfar[t] = cf;
+    nnear[t] = cn;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_list_fill(int32_t nbx, const int32_t *parent_x, const int64_t *pnear_ptr, const int32_t *pnear_src,
+            const int32_t *child_y, FarTest ft, const int64_t *far_ptr, const int64_t *near_ptr, int32_t *far_src,
+            int32_t *far_win, int32_t *near_src, int32_t *win_used, int *bad) {
+    int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbx) return;
+    const int32_t T = parent_x[t];
+    int64_t pf = far_ptr[t], pn = near_ptr[t];
+    for (int64_t e = pnear_ptr[T]; e < pnear_ptr[T + 1]; ++e) {
+        const int32_t S = pnear_src[e];
+        for (int32_t cs = child_y[S]; cs < child_y[S + 1]; ++cs) {
+            if (is_far(ft, t, cs)) {
+                int w = 0;
+                for (int d = 0; d < 3; ++d) {
+                    int o = ft.ijk_t[3 * t + d] - ft.ijk_s[3 * cs + d] - ft.base[d];
+                    if (o < 0 || o >= kWin) {
+                        atomicOr(bad, 1);
+                        o = 0;
+                    }
+                    w = w * kWin + o;
+                }
+                far_src[pf] = cs;
+                far_win[pf] = w;
+                win_used[w] = 1;
+                ++pf;
+            } else {
+                near_src[pn++] = cs;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_mark_sources(const int32_t *far_src, int64_t n, uint8_t *active) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) active[far_src[i]] = 1;
+}
+
+__global__ void __launch_bounds__(kThreads) k_remap(int32_t *cls, int64_t n, const int32_t *map) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cls[i] = map[cls[i]];
+}
+
+// ------------------------------------------------------------------ Lagrange tables
+// T_c[i][j] = G(|r0_c + (d_l / 2)(xi_i - xi_j)|), xi on the tensor Chebyshev grid; stored transposed
+// (column j contiguous over i) for the MFMA A operand; zero padding beyond r.
+__global__ void __launch_bounds__(kThreads)
+k_lagrange_T(int ncls, const double *r0, int r1, int rp, const double *nodes, double half_dl, int helm, double k,
+             float *T) {
+    const int64_t per = (int64_t)rp * rp;
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= per * ncls) return;
+    const int c = (int)(g / per);
+    const int64_t e = g % per;
+    const int j = (int)(e / rp), i = (int)(e % rp);   // element (i, j) at [c][j][i]
+    const int r = r1 * r1 * r1;
+    float re = 0.f, im = 0.f;
+    if (i < r && j < r) {
+        const int ia[3] = {i / (r1 * r1), (i / r1) % r1, i % r1};
+        const int ja[3] = {j / (r1 * r1), (j / r1) % r1, j % r1};
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double dd = r0[3 * c + d] + half_dl * (nodes[ia[d]] - nodes[ja[d]]);
+            d2 += dd * dd;
+        }
+        const double rr = sqrt(d2);
+        const double inv = 1.0 / (4.0 * M_PI * rr);
+        if (helm) {
+            double sn, cs;
+            sincos(k * rr, &sn, &cs);
+            re = (float)(cs * inv);
+            im = (float)(sn * inv);
+        } else {
+            re = (float)inv;
+        }
+    }
+    if (helm) {
+        T[(int64_t)c * 2 * per + e] = re;
+        T[(int64_t)c * 2 * per + per + e] = im;
+    } else {
+        T[(int64_t)c * per + e] = re;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_count_cls(const int32_t *cls, int64_t n, int32_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[cls[i]], 1);
+}
+
+// Pairs of one class go to consecutive 16-slot groups (order inside a class is free: every
+// pair's product is computed on its own and written to its own slot).
+__global__ void __launch_bounds__(kThreads)
+k_fill_groups(const int32_t *cls, int64_t n, const int32_t *gstart, int32_t *cursor, int32_t *grp_pair) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cls[i];
+    const int slot = atomicAdd(&cursor[c], 1);
+    grp_pair[(int64_t)gstart[c] * 16 + slot] = (int32_t)i;
+}
+
+// ------------------------------------------------------------------ Gegenbauer tables
+// D_c(+-s_p) = (ik / 4pi) w_p T_{L,r0}(+-s_p),  T_{L,r0}(s) = sum_{p=0..L} coef_p P_p(s . r0 / |r0|),
+// coef_p = (2p + 1) i^p h_p(k |r0|) / (4 pi).  P_p(-t) = (-1)^p P_p(t) gives the antipode.
+__global__ void __launch_bounds__(kThreads)
+k_gegen_D(int64_t npair, int L, const double *dirs /*[npair][3] unit*/, const double *wts, const double *rhat,
+          const double2 *coef /*[ncls][L+1]*/, double k, float4 *D) {
+    extern __shared__ double2 sm[];
+    double2 *sc = sm;               // series coefficients of this class
+    double2 *rc = sm + (L + 1);     // Bonnet recurrence: P_{p+1} = a_p t P_p - b_p P_{p-1}
+    const int c = blockIdx.y;
+    for (int p = threadIdx.x; p <= L; p += blockDim.x) {
+        sc[p] = coef[(int64_t)c * (L + 1) + p];
+        rc[p] = make_double2((2.0 * p + 1.0) / (p + 1.0), p / (p + 1.0));
+    }
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npair) return;
+    const double t = dirs[3 * q] * rhat[3 * c] + dirs[3 * q + 1] * rhat[3 * c + 1] + dirs[3 * q + 2] * rhat[3 * c + 2];
+    double pm = 1.0, pc = t;                 // P_0, P_1
+    double er = sc[0].x, ei = sc[0].y;       // even-p part of the series
+    double orr = 0.0, oi = 0.0;              // odd-p part
+    if (L >= 1) {
+        orr = sc[1].x * pc;
+        oi = sc[1].y * pc;
+    }
+    for (int p = 1; p < L; ++p) {
+        const double pn = rc[p].x * t * pc - rc[p].y * pm;
+        pm = pc;
+        pc = pn;
+        if (p & 1) {   // p + 1 even
+            er += sc[p + 1].x * pc;
+            ei += sc[p + 1].y * pc;
+        } else {
+            orr += sc[p + 1].x * pc;
+            oi += sc[p + 1].y * pc;
+        }
+    }
+    // T(t) = even + odd, T(-t) = even - odd;  (ik/4pi) w (a + ib) = (w k / 4pi) (-b + ia)
+    const double f = wts[q] * k / (4.0 * M_PI);
+    D[(int64_t)c * npair + q] = make_float4((float)(-f * (ei + oi)), (float)(f * (er + orr)),
+                                            (float)(-f * (ei - oi)), (float)(f * (er - orr)));
+}
+
+// ------------------------------------------------------------------ host helpers
+void gauss_legendre_host(int n, std::vector<double> &x, std::vector<double> &w) {
+    // Newton iteration on P_n from the Chebyshev-like initial guesses; nodes x_m in descending
+    // order with exact mirror symmetry x_{n-1-m} = -x_m.
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int m = 0; m < (n + 1) / 2; ++m) {
+        double z = std::cos(M_PI * (m + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 200; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p0 = 1.0; p1 = z; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) <= 1e-16) {
+                p0 = 1.0; p1 = z;
+                for (int j = 2; j <= n; ++j) {
+                    double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = n * (z * p1 - p0) / (z * z - 1.0);
+                break;
+            }
+        }
+        if (2 * m + 1 == n) z = 0.0;
+        x[m] = z;
+        x[n - 1 - m] = -z;
+        w[m] = w[n - 1 - m] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// h_p^(1)(z), p = 0..L, upward recurrence from h_0 = -i e^{iz} / z, h_1 = -e^{iz}(z + i) / z^2.
+void hankel_host(int L, double z, std::vector<std::complex<double>> &h) {
+    using C = std::complex<double>;
+    h.assign(L + 1, C(0, 0));
+    const C I(0, 1), e = std::exp(I * z);
+    h[0] = -I * e / z;
+    if (L >= 1) h[1] = -e * (z + I) / (z * z);
+    for (int p = 1; p < L; ++p) h[p + 1] = (2.0 * p + 1.0) / z * h[p] - h[p - 1];
+}
+
+int lagrange_r1(int kernel, double k, double dl, double eps, int override_r1) {
+    if (override_r1 > 0) return override_r1;
+    int r1 = (int)std::ceil(std::log(1.0 / eps) / std::log(3.0 + std::sqrt(8.0)));
+    if (kernel == FFM_HELMHOLTZ) r1 += (int)std::ceil(k * dl / 2.0);
+    return std::max(r1, 1);
+}
+
+int gegenbauer_L(double k, double dl, double eps) {
+    int L = (int)std::floor(k * std::sqrt(3.0) * dl - std::log(eps));
+    return std::max(L, 1);
+}
+
+template <class T>
+void upload(DevBuf<T> &b, const std::vector<T> &h, hipStream_t st) {
+    b.alloc(h.size());
+    if (!h.empty()) FFM_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+template <class T>
+T fetch(const T *dev, hipStream_t st) {
+    T v;
+    FFM_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, st));
+    FFM_HIP(hipStreamSynchronize(st));
+    return v;
+}
+
+// ------------------------------------------------------------------ tree construction
+void build_tree(Tree &T, const double *P, int64_t n, const double corner[3], double S, hipStream_t st) {
+    T.n = n;
+    std::memcpy(T.corner, corner, sizeof(double) * 3);
+    T.key.alloc(n);
+    T.perm.alloc(n);
+    FFM_LAUNCH(k_morton, nblocks(n), kThreads, 0, st, P, n, corner[0], corner[1], corner[2], S, T.key.p, T.perm.p);
+    radix_sort_u64_u32(T.key.p, T.perm.p, n, st);
+    T.xs.alloc(n);
+    T.ys.alloc(n);
+    T.zs.alloc(n);
+    FFM_LAUNCH(k_gather, nblocks(n), kThreads, 0, st, P, n, T.perm.p, T.xs.p, T.ys.p, T.zs.p);
+}
+
+struct LevelScratch {
+    DevBuf<int8_t> f;
+    DevBuf<int32_t> flag, pos, boxid_prev;
+    std::vector<int64_t> cum;   // boxes per level (cumulative start counts)
+};
+
+void first_levels(Tree &T, LevelScratch &S, hipStream_t st) {
+    const int64_t n = T.n;
+    S.f.alloc(n);
+    DevBuf<int32_t> hist(23);
+    FFM_HIP(hipMemsetAsync(hist.p, 0, 23 * sizeof(int32_t), st));
+    FFM_LAUNCH(k_first_level, nblocks(n), kThreads, 0, st, T.key.p, n, S.f.p, hist.p);
+    std::vector<int32_t> h(23);
+    FFM_HIP(hipMemcpyAsync(h.data(), hist.p, 23 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FFM_HIP(hipStreamSynchronize(st));
+    S.cum.assign(23, 0);
+    int64_t acc = 0;
+    for (int l = 0; l < 23; ++l) {
+        acc += h[l];
+        S.cum[l] = acc;
+    }
+    S.flag.alloc(n + 1);
+    S.pos.alloc(n + 1);
+    T.boxid.alloc(n);
+    S.boxid_prev.alloc(n);
+}
+
+void build_level(Tree &T, LevelScratch &S, int l, double d0, hipStream_t st) {
+    const int64_t n = T.n;
+    TreeLevel &L = T.lev[l];
+    L.nbox = (int32_t)S.cum[l];
+    FFM_LAUNCH(k_flags, nblocks(n), kThreads, 0, st, S.f.p, n, l, S.flag.p);
+    exclusive_scan_i32(S.flag.p, S.pos.p, n, st);
+    L.start.alloc(L.nbox + 1);
+    L.ijk.alloc((size_t)3 * L.nbox);
+    L.ctr.alloc((size_t)3 * L.nbox);
+    if (l > 0) std::swap(S.boxid_prev, T.boxid);
+    const double h = std::ldexp(d0, -(l + 1));
+    FFM_LAUNCH(k_level_boxes, nblocks(n), kThreads, 0, st, T.key.p, S.f.p, S.pos.p, n, l, T.corner[0], T.corner[1],
+               T.corner[2], h, L.start.p, L.ijk.p, L.ctr.p, T.boxid.p, L.nbox);
+    if (l > 0) {
+        TreeLevel &Pl = T.lev[l - 1];
+        L.parent.alloc(L.nbox);
+        Pl.child.alloc(Pl.nbox + 1);
+        FFM_LAUNCH(k_link, nblocks(std::max<int64_t>(L.nbox, Pl.nbox)), kThreads, 0, st, L.start.p, L.nbox,
+                   S.boxid_prev.p, L.parent.p, Pl.start.p, Pl.nbox, T.boxid.p, Pl.child.p);
+    }
+    T.built = l;
+}
+
+
+// Work lists of a level, built on the host from the box sizes and list pointers: largest boxes
+// first so that the longest blocks start early.
+void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &LY, bool near, hipStream_t st) {
+    std::vector<int32_t> sx(LX.nbox + 1), sy(LY.nbox + 1);
+    FFM_HIP(hipMemcpyAsync(sx.data(), LX.start.p, sizeof(int32_t) * sx.size(), hipMemcpyDeviceToHost, st));
+    FFM_HIP(hipMemcpyAsync(sy.data(), LY.start.p, sizeof(int32_t) * sy.size(), hipMemcpyDeviceToHost, st));
+    std::vector<int64_t> ptr(LX.nbox + 1);
+    const DevBuf<int64_t> &dptr = near ? LV.near_ptr : LV.far_ptr;
+    FFM_HIP(hipMemcpyAsync(ptr.data(), dptr.p, sizeof(int64_t) * ptr.size(), hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> src;
+    std::vector<uint8_t> act;
+    if (near && LV.nnear) {
+        src.resize(LV.nnear);
+        FFM_HIP(hipMemcpyAsync(src.data(), LV.near_src.p, sizeof(int32_t) * LV.nnear, hipMemcpyDeviceToHost, st));
+    }
+    if (!near) {
+        DevBuf<uint8_t> dact(LY.nbox);
+        FFM_HIP(hipMemsetAsync(dact.p, 0, LY.nbox, st));
+        FFM_LAUNCH(k_mark_sources, nblocks(LV.nfar), kThreads, 0, st, LV.far_src.p, LV.nfar, dact.p);
+        act.resize(LY.nbox);
+        FFM_HIP(hipMemcpyAsync(act.data(), dact.p, LY.nbox, hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipStreamSynchronize(st));
+    }
+    FFM_HIP(hipStreamSynchronize(st));
+    auto by_size = [](const std::vector<int32_t> &start, std::vector<int32_t> &boxes) {
+        std::stable_sort(boxes.begin(), boxes.end(), [&](int32_t a, int32_t b) {
+            return start[a + 1] - start[a] > start[b + 1] - start[b];
+        });
+    };
+    std::vector<int32_t> tgt;
+    for (int32_t t = 0; t < LX.nbox; ++t)
+        if (ptr[t + 1] > ptr[t]) tgt.push_back(t);
+    by_size(sx, tgt);
+    if (near) {
+        upload(LV.near_boxes, tgt, st);
+        double pairs = 0;
+        for (int32_t t : tgt)
+            for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e)
+                pairs += (double)(sx[t + 1] - sx[t]) * (double)(sy[src[e] + 1] - sy[src[e]]);
+        P.stats.near_pairs = pairs;
+        FFM_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    upload(LV.tgt_boxes, tgt, st);
+    std::vector<int2> work;
+    for (int32_t t : tgt) {
+        LV.max_tgt_pts = std::max(LV.max_tgt_pts, sx[t + 1] - sx[t]);
+        for (int32_t i = sx[t]; i < sx[t + 1]; i += 256) work.push_back(make_int2(t, i));
+    }
+    upload(LV.bwd_work, work, st);
+    std::vector<int32_t> fwd;
+    for (int32_t s = 0; s < LY.nbox; ++s)
+        if (act[s]) {
+            fwd.push_back(s);
+            LV.max_src_pts = std::max(LV.max_src_pts, sy[s + 1] - sy[s]);
+        }
+    by_size(sy, fwd);
+    upload(LV.fwd_boxes, fwd, st);
+    double npts_src = 0, npts_tgt = 0;
+    for (int32_t s : fwd) npts_src += sy[s + 1] - sy[s];
+    for (int32_t t : tgt) npts_tgt += sx[t + 1] - sx[t];
+    LV.pts_src = npts_src;
+    LV.pts_tgt = npts_tgt;
+    FFM_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+// =========================================================================== plan
+void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
+    const int64_t nx = P.nx, ny = P.ny;
+    if (P.empty) return;
+
+    // --- root cubes (Sec. 2.2.1)
+    double lo[2][3], hi[2][3];
+    {
+        const double *PS[2] = {X, Y};
+        const int64_t NS[2] = {nx, ny};
+        const int nsets = P.same ? 1 : 2;
+        DevBuf<double> part(6 * 1024 * 2), out(12);
+        DevBuf<int> bad(1);
+        FFM_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+        for (int e = 0; e < nsets; ++e) {
+            int nb = (int)std::min<int64_t>(1024, (NS[e] + kThreads - 1) / kThreads);
+            FFM_LAUNCH(k_bbox_partial, nb, kThreads, 0, st, PS[e], NS[e], part.p + 6 * 1024 * e, bad.p);
+            FFM_LAUNCH(k_bbox_final, 1, kThreads, 0, st, part.p + 6 * 1024 * e, nb, out.p + 6 * e);
+        }
+        double h6[12];
+        int hbad = 0;
+        FFM_HIP(hipMemcpyAsync(h6, out.p, sizeof(double) * 6 * nsets, hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipStreamSynchronize(st));
+        FFM_CHECK(!hbad, FFM_EINVAL, "ffm_plan: a coordinate is NaN or infinite");
+        if (P.same) std::memcpy(h6 + 6, h6, sizeof(double) * 6);
+        for (int e = 0; e < 2; ++e)
+            for (int d = 0; d < 3; ++d) {
+                lo[e][d] = h6[6 * e + d];
+                hi[e][d] = h6[6 * e + 3 + d];
+            }
+    }
+    double d0 = 0.0;
+    for (int e = 0; e < 2; ++e)
+        for (int d = 0; d < 3; ++d) d0 = std::max(d0, hi[e][d] - lo[e][d]);
+    if (d0 == 0.0) d0 = 1.0;
+    double corner[2][3];
+    {
+#pragma clang fp contract(off)
+        for (int e = 0; e < 2; ++e)
+            for (int d = 0; d < 3; ++d) corner[e][d] = (lo[e][d] + hi[e][d]) * 0.5 - d0 * 0.5;
+    }
+    P.d0 = d0;
+    P.S = (double)(1 << kBits) / d0;
+    P.aligned = std::memcmp(corner[0], corner[1], sizeof(double) * 3) == 0;
+
+    // --- Morton-sorted trees (Sec. 2.1)
+    P.tx.reset(new Tree());
+    build_tree(*P.tx, X, nx, corner[0], P.S, st);
+    if (P.same) {
+        P.ty = P.tx.get();
+    } else {
+        P.ty_own.reset(new Tree());
+        build_tree(*P.ty_own, Y, ny, corner[1], P.S, st);
+        P.ty = P.ty_own.get();
+    }
+    Tree &TX = *P.tx, &TY = *P.ty;
+    LevelScratch SX, SY;
+    first_levels(TX, SX, st);
+    if (!P.same) first_levels(TY, SY, st);
+    const int maxlev = P.opt.max_level;
+    build_level(TX, SX, 0, d0, st);
+    if (!P.same) build_level(TY, SY, 0, d0, st);
+
+    // --- descent lists (Sec. 2.2.2, 2.2.4; Prop. 1)
+    DevBuf<int64_t> pnear_ptr(2), cnt_f, cnt_n;
+    DevBuf<int32_t> pnear_src(1);
+    {
+        const int64_t h_ptr[2] = {0, 1};
+        const int32_t h_src[1] = {0};
+        FFM_HIP(hipMemcpyAsync(pnear_ptr.p, h_ptr, sizeof(h_ptr), hipMemcpyHostToDevice, st));
+        FFM_HIP(hipMemcpyAsync(pnear_src.p, h_src, sizeof(h_src), hipMemcpyHostToDevice, st));
+    }
+    DevBuf<int> bad(1);
+    DevBuf<int32_t> win_used(kWin3);
+    P.leaf = maxlev;
+    for (int l = 1; l <= maxlev; ++l) {
+        build_level(TX, SX, l, d0, st);
+        if (!P.same) build_level(TY, SY, l, d0, st);
+        const int32_t nbx = TX.lev[l].nbox;
+        Level &LV = P.lev[l];
+        const double dl = std::ldexp(d0, -l);
+        FarTest ft;
+        ft.ijk_t = TX.lev[l].ijk.p;
+        ft.ijk_s = TY.lev[l].ijk.p;
+        ft.ctr_t = TX.lev[l].ctr.p;
+        ft.ctr_s = TY.lev[l].ctr.p;
+        ft.two_dl = 2.0 * dl;
+        ft.aligned = P.aligned ? 1 : 0;
+        for (int d = 0; d < 3; ++d) {
+            // offsets of level-1 pairs lie in [-1, 1]; deeper ones within [f - 4, f + 5],
+            // f = floor(-(corner_X - corner_Y) / d_l): window [f - 5, f + 6]
+            ft.base[d] = (l == 1) ? -1 : (int32_t)std::floor(-(corner[0][d] - corner[1][d]) / dl) - 5;
+            LV.win_base[d] = ft.base[d];
+        }
+        cnt_f.alloc(nbx + 1);
+        cnt_n.alloc(nbx + 1);
+        FFM_LAUNCH(k_list_count, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, pnear_ptr.p, pnear_src.p,
+                   TY.lev[l - 1].child.p, ft, cnt_f.p, cnt_n.p);
+        LV.far_ptr.alloc(nbx + 1);
+        LV.near_ptr.alloc(nbx + 1);
+        exclusive_scan_i64(cnt_f.p, LV.far_ptr.p, nbx, st);
+        exclusive_scan_i64(cnt_n.p, LV.near_ptr.p, nbx, st);
+        LV.nfar = fetch(LV.far_ptr.p + nbx, st);
+        LV.nnear = fetch(LV.near_ptr.p + nbx, st);
+        LV.far_src.alloc(LV.nfar);
+        LV.far_cls.alloc(LV.nfar);
+        LV.near_src.alloc(LV.nnear);
+        FFM_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+        FFM_HIP(hipMemsetAsync(win_used.p, 0, sizeof(int32_t) * kWin3, st));
+        FFM_LAUNCH(k_list_fill, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, pnear_ptr.p, pnear_src.p,
+                   TY.lev[l - 1].child.p, ft, LV.far_ptr.p, LV.near_ptr.p, LV.far_src.p, LV.far_cls.p,
+                   LV.near_src.p, win_used.p, bad.p);
+        std::vector<int32_t> used(kWin3);
+        int hbad = 0;
+        FFM_HIP(hipMemcpyAsync(used.data(), win_used.p, sizeof(int32_t) * kWin3, hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipStreamSynchronize(st));
+        FFM_CHECK(!hbad, FFM_EINTERNAL, "ffm_plan: translation outside its window");
+        // compact translation classes
+        std::vector<int32_t> map(kWin3, 0);
+        LV.cls_off.clear();
+        LV.ncls = 0;
+        for (int w = 0; w < kWin3; ++w)
+            if (used[w]) {
+                map[w] = LV.ncls++;
+                LV.cls_off.push_back(w / (kWin * kWin) + LV.win_base[0]);
+                LV.cls_off.push_back((w / kWin) % kWin + LV.win_base[1]);
+                LV.cls_off.push_back(w % kWin + LV.win_base[2]);
+            }
+        if (LV.nfar) {
+            DevBuf<int32_t> dmap;
+            upload(dmap, map, st);
+            FFM_LAUNCH(k_remap, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, dmap.p);
+            FFM_HIP(hipStreamSynchronize(st));
+        }
+        // next level's parent lists are this level's near lists
+        pnear_ptr = std::move(LV.near_ptr);
+        pnear_src = std::move(LV.near_src);
+        LV.near_ptr = DevBuf<int64_t>();
+        LV.near_src = DevBuf<int32_t>();
+        // stopping rule (Sec. 2.2.4)
+        const int64_t nb = (int64_t)TX.lev[l].nbox + TY.lev[l].nbox;
+        const bool stop = LV.nnear == 0 || nx + ny <= (int64_t)P.opt.n_leaf * nb || l == maxlev;
+        if (stop) {
+            P.leaf = l;
+            LV.near_ptr = std::move(pnear_ptr);
+            LV.near_src = std::move(pnear_src);
+            break;
+        }
+        // keep the near lists of inner levels only for export
+        LV.near_ptr.alloc(nbx + 1);
+        LV.near_src.alloc(std::max<int64_t>(LV.nnear, 1));
+        FFM_HIP(hipMemcpyAsync(LV.near_ptr.p, pnear_ptr.p, sizeof(int64_t) * (nbx + 1), hipMemcpyDeviceToDevice, st));
+        if (LV.nnear)
+            FFM_HIP(hipMemcpyAsync(LV.near_src.p, pnear_src.p, sizeof(int32_t) * LV.nnear, hipMemcpyDeviceToDevice, st));
+    }
+
+    // --- compression form and tables per level (Sec. 2.2.2, 2.2.3)
+    size_t ws_src = 0, ws_tgt = 0, ws_z = 0;
+    for (int l = 1; l <= P.leaf; ++l) {
+        Level &LV = P.lev[l];
+        if (LV.nfar == 0) continue;
+        const double dl = std::ldexp(d0, -l);
+        std::vector<double> r0(3 * (size_t)LV.ncls);
+        for (int c = 0; c < LV.ncls; ++c)
+            for (int d = 0; d < 3; ++d)
+                r0[3 * c + d] = (corner[0][d] - corner[1][d]) + (double)LV.cls_off[3 * c + d] * dl;
+        const int32_t nby = TY.lev[l].nbox, nbx = TX.lev[l].nbox;
+        build_work_lists(P, LV, TX.lev[l], TY.lev[l], false, st);
+        const bool geg = P.kernel == FFM_HELMHOLTZ && P.k * dl >= P.opt.kd_switch;
+        if (geg) {
+            LV.method = kGegenbauer;
+            LV.L = gegenbauer_L(P.k, dl, P.eps);
+            FFM_CHECK(LV.L <= 1000, FFM_EINVAL, "ffm_plan: k * d_0 too large (Gegenbauer rank above 1000)");
+            const int L = LV.L, nth = L + 1, nph = 2 * L;
+            LV.nq = 2 * (int64_t)L * (L + 1);
+            LV.npair = LV.nq / 2;
+            std::vector<double> xm, wm;
+            gauss_legendre_host(nth, xm, wm);
+            std::vector<double> dirs, wts;
+            dirs.reserve(3 * LV.npair);
+            wts.reserve(LV.npair);
+            auto add = [&](int m, int n) {
+                const double ct = xm[m], stt = std::sqrt(1.0 - ct * ct), ph = M_PI * n / L;
+                dirs.push_back(stt * std::cos(ph));
+                dirs.push_back(stt * std::sin(ph));
+                dirs.push_back(ct);
+                wts.push_back(wm[m] * M_PI / L);
+            };
+            for (int m = 0; m < nth / 2; ++m)
+                for (int n = 0; n < nph; ++n) add(m, n);
+            if (nth & 1)
+                for (int n = 0; n < L; ++n) add(nth / 2, n);
+            FFM_CHECK((int64_t)wts.size() == LV.npair, FFM_EINTERNAL, "quadrature pair count");
+            const double kr = P.k / (2.0 * M_PI);
+            std::vector<float4> dirs32(LV.npair);
+            std::vector<double> dirs64(3 * LV.npair);
+            for (int64_t q = 0; q < LV.npair; ++q) {
+                for (int d = 0; d < 3; ++d) dirs64[3 * q + d] = dirs[3 * q + d] * kr;
+                dirs32[q] = make_float4((float)dirs64[3 * q], (float)dirs64[3 * q + 1], (float)dirs64[3 * q + 2], 0.f);
+            }
+            upload(LV.dirs, dirs32, st);
+            upload(LV.dirs64, dirs64, st);
+            // FP64 phase reduction where a box spans more than 8 wavelengths of phase
+            LV.phase64 = P.k * dl * std::sqrt(3.0) * 0.5 / (2.0 * M_PI) > 8.0;
+            // per-class series coefficients (host FP64), unit directions r0/|r0|
+            std::vector<double> rhat(3 * (size_t)LV.ncls);
+            std::vector<double2> coef((size_t)LV.ncls * (L + 1));
+            std::vector<std::complex<double>> h;
+            for (int c = 0; c < LV.ncls; ++c) {
+                const double rn = std::sqrt(r0[3 * c] * r0[3 * c] + r0[3 * c + 1] * r0[3 * c + 1] + r0[3 * c + 2] * r0[3 * c + 2]);
+                for (int d = 0; d < 3; ++d) rhat[3 * c + d] = r0[3 * c + d] / rn;
+                hankel_host(L, P.k * rn, h);
+                std::complex<double> ip(1, 0);
+                for (int p = 0; p <= L; ++p) {
+                    std::complex<double> v = (2.0 * p + 1.0) * ip * h[p] / (4.0 * M_PI);
+                    coef[(size_t)c * (L + 1) + p] = make_double2(v.real(), v.imag());
+                    ip *= std::complex<double>(0, 1);
+                }
+            }
+            DevBuf<double> ddirs, dwts, drhat;
+            DevBuf<double2> dcoef;
+            upload(ddirs, dirs, st);
+            upload(dwts, wts, st);
+            upload(drhat, rhat, st);
+            upload(dcoef, coef, st);
+            LV.D.alloc((size_t)LV.ncls * LV.npair);
+            dim3 grid((unsigned)nblocks(LV.npair), (unsigned)LV.ncls);
+            hipLaunchKernelGGL(k_gegen_D, grid, dim3(kThreads), 2 * sizeof(double2) * (L + 1), st, LV.npair, L, ddirs.p,
+                               dwts.p, drhat.p, dcoef.p, P.k, LV.D.p);
+            FFM_HIP(hipGetLastError());
+            FFM_HIP(hipStreamSynchronize(st));
+            ws_src = std::max(ws_src, (size_t)nby * LV.npair);
+            ws_tgt = std::max(ws_tgt, (size_t)nbx * LV.npair);
+        } else {
+            LV.method = kLagrange;
+            LV.r1 = lagrange_r1(P.kernel, P.k, dl, P.eps, P.opt.r1_override);
+            FFM_CHECK(LV.r1 <= 8, FFM_EINVAL, "ffm_plan: eps too small for the Lagrange levels (r1 > 8)");
+            LV.r = LV.r1 * LV.r1 * LV.r1;
+            LV.rp = (LV.r + 31) / 32 * 32;
+            std::vector<double> nodes(LV.r1);
+            for (int a = 1; a <= LV.r1; ++a) nodes[a - 1] = std::cos((2.0 * a - 1.0) * M_PI / (2.0 * LV.r1));
+            std::vector<float> nf(LV.r1), df(LV.r1);
+            for (int a = 0; a < LV.r1; ++a) {
+                double den = 1.0;
+                for (int b = 0; b < LV.r1; ++b)
+                    if (b != a) den *= nodes[a] - nodes[b];
+                nf[a] = (float)nodes[a];
+                df[a] = (float)(1.0 / den);
+            }
+            upload(LV.lnodes, nf, st);
+            upload(LV.lden, df, st);
+            DevBuf<double> dnodes, dr0;
+            upload(dnodes, nodes, st);
+            upload(dr0, r0, st);
+            const int helm = P.kernel == FFM_HELMHOLTZ ? 1 : 0;
+            const int64_t per = (int64_t)LV.rp * LV.rp;
+            LV.T.alloc((size_t)per * LV.ncls * (helm ? 2 : 1));
+            FFM_LAUNCH(k_lagrange_T, nblocks(per * LV.ncls), kThreads, 0, st, LV.ncls, dr0.p, LV.r1, LV.rp, dnodes.p,
+                       0.5 * dl, helm, P.k, LV.T.p);
+            // class groups of 16 pairs for the MFMA transfer
+            DevBuf<int32_t> cnt(LV.ncls), cursor(LV.ncls);
+            FFM_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * LV.ncls, st));
+            FFM_LAUNCH(k_count_cls, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, cnt.p);
+            std::vector<int32_t> hc(LV.ncls), gstart(LV.ncls), gcls;
+            FFM_HIP(hipMemcpyAsync(hc.data(), cnt.p, sizeof(int32_t) * LV.ncls, hipMemcpyDeviceToHost, st));
+            FFM_HIP(hipStreamSynchronize(st));
+            int32_t g = 0;
+            for (int c = 0; c < LV.ncls; ++c) {
+                gstart[c] = g;
+                const int ng = (hc[c] + 15) / 16;
+                for (int q = 0; q < ng; ++q) gcls.push_back(c);
+                g += ng;
+            }
+            LV.ngrp = g;
+            DevBuf<int32_t> dgs;
+            upload(dgs, gstart, st);
+            upload(LV.grp_cls, gcls, st);
+            LV.grp_pair.alloc((size_t)16 * std::max(g, 1));
+            FFM_HIP(hipMemsetAsync(LV.grp_pair.p, 0xff, sizeof(int32_t) * 16 * std::max(g, 1), st));
+            FFM_HIP(hipMemsetAsync(cursor.p, 0, sizeof(int32_t) * LV.ncls, st));
+            FFM_LAUNCH(k_fill_groups, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, dgs.p, cursor.p,
+                       LV.grp_pair.p);
+            FFM_HIP(hipStreamSynchronize(st));
+            ws_src = std::max(ws_src, ((size_t)nby * LV.rp + 1) / 2);
+            ws_z = std::max(ws_z, (size_t)LV.nfar * LV.rp);
+        }
+    }
+    build_work_lists(P, P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st);
+    P.ws_src = ws_src;
+    P.ws_tgt = ws_tgt;
+    P.ws_z = ws_z;
+    P.u_sorted.alloc(ny);
+    P.v_sorted.alloc(nx);
+    P.wsrc.alloc(ws_src);
+    P.wtgt.alloc(ws_tgt);
+    P.wz.alloc(ws_z);
+    FFM_HIP(hipStreamSynchronize(st));
+
+    // --- statistics
+    ffm_stats_t &s = P.stats;
+    const double near_pairs = s.near_pairs;
+    std::memset(&s, 0, sizeof(s));
+    s.near_pairs = near_pairs;
+    s.leaf = P.leaf;
+    s.same_set = P.same ? 1 : 0;
+    s.d0 = d0;
+    for (int d = 0; d < 3; ++d) {
+        s.corner_x[d] = corner[0][d];
+        s.corner_y[d] = corner[1][d];
+    }
+    for (int l = 0; l <= P.leaf; ++l) {
+        s.nbox_x[l] = TX.lev[l].nbox;
+        s.nbox_y[l] = TY.lev[l].nbox;
+        const Level &LV = P.lev[l];
+        s.nfar[l] = LV.nfar;
+        s.nnear[l] = LV.nnear;
+        s.method[l] = LV.method;
+        s.order[l] = LV.method == kGegenbauer ? LV.L : LV.r1;
+        s.nclass[l] = LV.ncls;
+        s.nq[l] = LV.nq;
+        s.fwd_points[l] = LV.pts_src;
+        s.bwd_points[l] = LV.pts_tgt;
+        if (LV.method == kGegenbauer) {
+            s.transform_terms += (LV.pts_src + LV.pts_tgt) * (double)LV.nq;
+            s.transfer_macs += (double)LV.nfar * (double)LV.nq;
+        } else if (LV.method == kLagrange) {
+            s.transfer_macs += (double)LV.nfar * (double)LV.r * (double)LV.r;
+        }
+    }
+    (void)ws_tgt;
+}
+
+size_t plan_device_bytes(const Plan &P) {
+    size_t b = 0;
+    auto tree = [&](const Tree &T) {
+        b += T.key.bytes() + T.perm.bytes() + T.xs.bytes() + T.ys.bytes() + T.zs.bytes() + T.boxid.bytes();
+        for (int l = 0; l <= T.built; ++l) {
+            const TreeLevel &L = T.lev[l];
+            b += L.start.bytes() + L.ijk.bytes() + L.ctr.bytes() + L.parent.bytes() + L.child.bytes();
+        }
+    };
+    if (P.tx) tree(*P.tx);
+    if (P.ty_own) tree(*P.ty_own);
+    for (int l = 0; l <= kMaxLev; ++l) {
+        const Level &L = P.lev[l];
+        b += L.far_ptr.bytes() + L.near_ptr.bytes() + L.far_src.bytes() + L.far_cls.bytes() + L.near_src.bytes() +
+             L.T.bytes() + L.grp_pair.bytes() + L.grp_cls.bytes() + L.dirs.bytes() + L.dirs64.bytes() + L.D.bytes() +
+             L.lnodes.bytes() + L.lden.bytes() + L.fwd_boxes.bytes() + L.tgt_boxes.bytes() + L.bwd_work.bytes() +
+             L.near_boxes.bytes();
+    }
+    b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes();
+    return b;
+}
+
+}  // namespace ffm

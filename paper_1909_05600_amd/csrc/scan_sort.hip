@@ -1,0 +1,192 @@
+// Device scans and the stable LSD radix sort of Morton keys (plan time).
+//
+// The sort orders (key, index) pairs by the full 63-bit key with ties kept in
+// index order: eight 8-bit passes, each a histogram, a digit-major scan and a
+// stable scatter.  Stability inside a tile comes from ranking a wavefront's
+// lanes by ballot matching of their digits, wave by wave and round by round in
+// element order, so equal keys leave in the order they came in.
+#include "common.h"
+
+namespace ffm {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <class T>
+__device__ T block_inclusive_sum(T v, T *lds_wave, T &block_total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    if (lane == 63) lds_wave[wave] = v;
+    __syncthreads();
+    T off = 0, tot = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        T s = lds_wave[w];
+        if (w < wave) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    block_total = tot;
+    return v + off;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const T *in, int64_t n, T *bsum) {
+    __shared__ T lw[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + (int64_t)j * kScanThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    T tot;
+    block_inclusive_sum(s, lw, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// out[i] = boff[block] + exclusive prefix within the tile; the last block writes out[n].
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const T *in, T *out, int64_t n, const T *boff) {
+    __shared__ T lw[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T loc[kScanItems];
+    T s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        loc[j] = (i < n) ? in[i] : T(0);
+        s += loc[j];
+    }
+    T tot;
+    T incl = block_inclusive_sum(s, lw, tot);
+    T run = (boff ? boff[blockIdx.x] : T(0)) + incl - s;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += loc[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (boff ? boff[blockIdx.x] : T(0)) + tot;
+}
+
+template <class T>
+void exclusive_scan(const T *in, T *out, int64_t n, hipStream_t st) {
+    if (n <= 0) {
+        FFM_HIP(hipMemsetAsync(out, 0, sizeof(T), st));
+        return;
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        FFM_LAUNCH(k_scan_apply<T>, 1, kScanThreads, 0, st, in, out, n, (const T *)nullptr);
+        return;
+    }
+    DevBuf<T> bsum(nb + 1), boff(nb + 1);
+    FFM_LAUNCH(k_scan_reduce<T>, nb, kScanThreads, 0, st, in, n, bsum.p);
+    exclusive_scan<T>(bsum.p, boff.p, nb, st);
+    FFM_LAUNCH(k_scan_apply<T>, nb, kScanThreads, 0, st, in, out, n, (const T *)boff.p);
+    // the temporaries are released only after the stream has consumed them
+    FFM_HIP(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__global__ void __launch_bounds__(kRsThreads)
+k_rs_hist(const uint64_t *keys, int64_t n, int shift, int32_t *counts, int nblk) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int j = 0; j < kRsItems; ++j) {
+        int64_t i = base + (int64_t)j * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & 255u)], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kRsThreads)
+k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout, int64_t n, int shift,
+             const int32_t *offs, int nblk) {
+    __shared__ int run[256];
+    __shared__ int wc[kRsThreads / 64][256];
+    __shared__ int gbase[256];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    run[t] = 0;
+    gbase[t] = offs[(int64_t)t * nblk + blockIdx.x];
+    for (int ww = 0; ww < kRsThreads / 64; ++ww) wc[ww][t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t i = base + (int64_t)r * kRsThreads + t;
+        const bool valid = i < n;
+        const uint64_t key = valid ? kin[i] : 0ull;
+        const int32_t val = valid ? vin[i] : 0;
+        const int d = (int)((key >> shift) & 255u);
+        uint64_t mask = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bal = __ballot(bit);
+            mask &= bit ? bal : ~bal;
+        }
+        const int rank = __popcll(mask & lt);
+        if (valid && rank == 0) wc[w][d] = __popcll(mask);
+        __syncthreads();
+        {
+            int acc = run[t];
+            for (int ww = 0; ww < kRsThreads / 64; ++ww) {
+                int c = wc[ww][t];
+                wc[ww][t] = acc;
+                acc += c;
+            }
+            run[t] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const int pos = gbase[d] + wc[w][d] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        for (int ww = 0; ww < kRsThreads / 64; ++ww) wc[ww][t] = 0;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
+    exclusive_scan<int64_t>(in, out, n, st);
+}
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) {
+    exclusive_scan<int32_t>(in, out, n, st);
+}
+
+void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st) {
+    if (n <= 1) return;
+    FFM_CHECK(n < (int64_t(1) << 31), FFM_EINVAL, "radix sort: too many keys");
+    const int nblk = (int)((n + kRsTile - 1) / kRsTile);
+    DevBuf<uint64_t> k2(n);
+    DevBuf<int32_t> v2(n);
+    DevBuf<int32_t> counts((size_t)256 * nblk + 1), offs((size_t)256 * nblk + 1);
+    uint64_t *ka = keys, *kb = k2.p;
+    int32_t *va = vals, *vb = v2.p;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        FFM_LAUNCH(k_rs_hist, nblk, kRsThreads, 0, st, ka, n, shift, counts.p, nblk);
+        exclusive_scan<int32_t>(counts.p, offs.p, (int64_t)256 * nblk, st);
+        FFM_LAUNCH(k_rs_scatter, nblk, kRsThreads, 0, st, ka, va, kb, vb, n, shift, offs.p, nblk);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    // eight passes: the result is back in (keys, vals)
+    FFM_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace ffm

@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every symbol include/ffm.h declares (no GPU needed).
+
+Also checks that the host-side argument validation rejects bad calls before touching a device.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ffm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffm_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1909_05600_amd as ffm
+    if not os.path.exists(ffm.LIB_PATH):
+        from paper_1909_05600_amd import build
+        build.build()
+    return ffm.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    import paper_1909_05600_amd as ffm
+    decl = _declared_functions()
+    assert set(decl) == set(ffm.EXPORTED), decl
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_version_and_last_error(L):
+    assert L.ffm_version().decode().startswith("ffm-gfx950")
+    assert L.ffm_last_error() is not None
+
+
+def test_invalid_arguments_are_rejected_before_any_device_work(L):
+    import paper_1909_05600_amd as ffm
+    h = C.c_void_p()
+    dummy = C.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    cases = [
+        (dummy, 10, dummy, 10, 0, 0.0, 1e-3, None, None, None),         # out == NULL
+        (dummy, -1, dummy, 10, 0, 0.0, 1e-3, None, None, C.byref(h)),   # negative size
+        (None, 10, dummy, 10, 0, 0.0, 1e-3, None, None, C.byref(h)),    # NULL X
+        (dummy, 10, dummy, 10, 7, 0.0, 1e-3, None, None, C.byref(h)),   # unknown kernel
+        (dummy, 10, dummy, 10, 1, -2.0, 1e-3, None, None, C.byref(h)),  # k < 0
+        (dummy, 10, dummy, 10, 1, float("nan"), 1e-3, None, None, C.byref(h)),
+        (dummy, 10, dummy, 10, 0, 0.0, 0.0, None, None, C.byref(h)),    # eps <= 0
+        (dummy, 10, dummy, 10, 0, 0.0, 1e-9, None, None, C.byref(h)),   # eps too small
+        (dummy, 10, dummy, 10, 0, 0.0, 0.7, None, None, C.byref(h)),    # eps too large
+        (dummy, 1 << 31, dummy, 10, 0, 0.0, 1e-3, None, None, C.byref(h)),
+    ]
+    for args in cases:
+        assert L.ffm_plan(*args) == -1, args
+        assert L.ffm_last_error().decode() != ""
+    bad = ffm.Options(0, 0, 0.0, 0, 0, 6)       # unknown flag bits
+    assert L.ffm_plan(dummy, 10, dummy, 10, 0, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1
+    bad = ffm.Options(0, 5, 0.0, 0, 0, 0)       # unknown precision
+    assert L.ffm_plan(dummy, 10, dummy, 10, 0, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1
+    bad = ffm.Options(0, 0, 0.0, 0, 25, 0)      # depth cap above 20
+    assert L.ffm_plan(dummy, 10, dummy, 10, 0, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1
+    assert L.ffm_apply(None, dummy, 0, dummy, None) == -1
+    assert L.ffm_destroy(None) == 0
+    assert L.ffm_plan_stats(None, None) == -1
+    cnt = C.c_int64()
+    assert L.ffm_plan_export(None, 0, 0, 0, None, C.byref(cnt)) == -1
+
+
+def test_oracle_is_not_linked_into_the_product():
+    """The GPU library and its binding never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_1909_05600_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), os.path.join(dirpath, f)
