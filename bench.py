@@ -27,9 +27,11 @@ sys.path.insert(0, ROOT)
 # the form this library is built for); reported as FMA-equivalent TFLOP/s = 2 x slots/s.
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 PEAK_ALU_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12          # 78.6
-# Minimal VALU slots per (point, antipodal direction pair) of a plane-wave transform:
-# 3 (phase) + 1 (fract) + 4 + 4 (sin, cos at quarter rate) + 4 (two complex accumulations).
-SLOTS_PER_PAIR_POINT = 16
+# Minimal non-transcendental VALU slots of the plane-wave transforms (sin/cos co-issue on the
+# transcendental unit at half rate and are not the bound; see profiles/peaks_mi355x.txt):
+#   direction-pair form: per (point, antipodal pair)   3 phase + 1 fract + 4 accumulate = 8 slots / 2 directions
+#   ring-pair form:      per (point, group of 4 dirs)   2 phase + 1 fract + 8 accumulate = 11 slots / 4 directions
+SLOTS_PER_DIRECTION = {1: 8 / 2, 2: 11 / 4}
 
 
 def parse():
@@ -131,13 +133,13 @@ def main():
     for l in range(1, leaf + 1):
         if st["method"][l] != 2:
             continue
-        npair = st["nq"][l] / 2
+        per_dir = SLOTS_PER_DIRECTION[st["tform"][l]]
         fwd_ms += ph[:, 1 + 3 * (l - 1)].sum()
         bwd_ms += ph[:, 3 + 3 * (l - 1)].sum()
-        fwd_slots += args.steps * st["fwd_points"][l] * npair * SLOTS_PER_PAIR_POINT
-        bwd_slots += args.steps * st["bwd_points"][l] * npair * SLOTS_PER_PAIR_POINT
+        fwd_slots += args.steps * st["fwd_points"][l] * st["nq"][l] * per_dir
+        bwd_slots += args.steps * st["bwd_points"][l] * st["nq"][l] * per_dir
         nlaunch += args.steps
-    dom = "k_pw_forward" if fwd_ms >= bwd_ms else "k_pw_backward"
+    dom = "plane-wave forward transform" if fwd_ms >= bwd_ms else "plane-wave backward transform"
     d_ms, d_slots = (fwd_ms, fwd_slots) if fwd_ms >= bwd_ms else (bwd_ms, bwd_slots)
     achieved = 2 * d_slots / (d_ms * 1e-3) / 1e12 if d_ms > 0 else 0.0
     phase_mean = ph.mean(axis=0)
@@ -173,10 +175,12 @@ def main():
             "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
             "launches": nlaunch, "avg_launch_ms": d_ms / max(nlaunch, 1),
-            "work": "VALU issue slots x 2 (FMA-equivalent flops): %d slots per point and antipodal direction "
-                    "pair; peak = 256 CU x 64 lanes x 2.4 GHz x 2" % SLOTS_PER_PAIR_POINT,
+            "work": "non-transcendental VALU issue slots x 2 (FMA-equivalent flops) of the implemented form: "
+                    "11 per (point, 4 directions) in ring-pair levels, 8 per (point, 2 directions) otherwise; "
+                    "peak = 256 CU x 64 lanes x 2.4 GHz x 2",
         },
         "levels": {"leaf": leaf, "nq": [int(x) for x in st["nq"][:leaf + 1]],
+                   "transform_form": [int(x) for x in st["tform"][:leaf + 1]],
                    "nfar": [int(x) for x in st["nfar"][:leaf + 1]], "near_pairs": st["near_pairs"],
                    "transform_terms": st["transform_terms"]},
     }

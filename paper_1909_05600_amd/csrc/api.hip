@@ -174,7 +174,7 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         }
         P.stats.plan_bytes = (double)plan_device_bytes(P);
         P.stats.workspace_bytes = (double)(P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() +
-                                           P.wtgt.bytes() + P.wz.bytes());
+                                           P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes());
         h = p.release();
     });
     if (rc == FFM_OK) *out = h;
@@ -329,7 +329,8 @@ size_t ffm_plan_bytes(ffm_plan_t plan) { return plan ? plan_device_bytes(plan->P
 size_t ffm_workspace_bytes(ffm_plan_t plan) {
     if (!plan) return 0;
     const Plan &P = plan->P;
-    return P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes();
+    return P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() +
+           P.wpart.bytes();
 }
 
 }  // extern "C"

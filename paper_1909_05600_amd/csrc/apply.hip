@@ -223,6 +223,236 @@ k_pw_backward(const double *__restrict__ xs, const double *__restrict__ ys, cons
     }
 }
 
+
+// ------------------------------------------------------------------ Gegenbauer levels, ring-pair form
+// The quadrature's directions (sin t_m cos f_n, sin t_m sin f_n, cos t_m) of ring m and its antipodal
+// ring L - m (cos t_{L-m} = -cos t_m) with f_n and f_n + pi give four directions whose phases against
+// a box-centred point y are +-P +- C, P = (k/2pi) sin t_m (y_1 cos f_n + y_2 sin f_n) and
+// C = (k/2pi) cos t_m y_3.  One sin/cos of P and the per-(point, ring) factors e^{-+iC} serve all four:
+//   u~(m, n)        = sum e^{-iP} u',    u~(m, n+L)     = sum e^{+iP} u',    u' = u e^{-iC}
+//   u~(L-m, n)      = sum e^{-iP} u'',   u~(L-m, n+L)   = sum e^{+iP} u'',   u'' = u e^{+iC}
+// Storage keeps the direction-pair layout: pair (m, n) = (u~(m,n), u~(L-m,n+L)), pair (m, n+L) =
+// (u~(m,n+L), u~(L-m,n)); the equator ring (m = L/2, L even) holds pair (m, n) = (u~(m,n), u~(m,n+L)).
+// C is reduced in FP64 once per (point, ring); P is evaluated in FP32 or FP64 (P64).
+constexpr int kRingChunk = 64;
+constexpr int kMaxRings = 16;
+
+template <int G, bool P64>
+__global__ void __launch_bounds__(kThreads)
+k_pw_forward_rings(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+                   const float2 *__restrict__ u, const int32_t *__restrict__ start, const double *__restrict__ ctr,
+                   const int32_t *__restrict__ boxes, const double2 *__restrict__ rings,
+                   const double2 *__restrict__ phis, int L, int nrp, int Tr, int R, int nchunk, int nsplit,
+                   int64_t npair, float4 *__restrict__ out, int64_t split_stride) {
+    typedef typename std::conditional<P64, double, float>::type real;
+    const int work = blockIdx.x / nsplit, seg = blockIdx.x % nsplit;
+    const int bi = work / nchunk;
+    const int b = boxes[bi];
+    const int m0 = (work % nchunk) * R;
+    const int tid = threadIdx.x;
+    const int rl = tid / Tr, nloc = tid % Tr;
+    const int m = m0 + rl;
+    const int nr = min(R, nrp - m0);
+    const bool active = rl < nr;
+    real cf[G], sf[G];
+    float acc[G][8];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const int n = min(nloc + j * Tr, L - 1);
+        cf[j] = (real)phis[n].x;
+        sf[j] = (real)phis[n].y;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[j][q] = 0.f;
+    }
+    const double cx = ctr[3 * b], cy = ctr[3 * b + 1], cz = ctr[3 * b + 2];
+    __shared__ real sA[kMaxRings][kRingChunk], sB[kMaxRings][kRingChunk];
+    __shared__ float4 sU[kMaxRings][kRingChunk];
+    // this block's segment of the box's points
+    const int b0 = start[b], b1 = start[b + 1];
+    const int per = (b1 - b0 + nsplit - 1) / nsplit;
+    const int i0 = b0 + seg * per, i1 = min(b1, i0 + per);
+    for (int s0 = i0; s0 < i1; s0 += kRingChunk) {
+        const int cnt = min(kRingChunk, i1 - s0);
+        __syncthreads();
+        for (int it = tid; it < nr * cnt; it += kThreads) {
+            const int r = it / cnt, j = it % cnt, i = s0 + j;
+            const double2 rg = rings[m0 + r];
+            const double xr = xs[i] - cx, yr = ys[i] - cy, zr = zs[i] - cz;
+            sA[r][j] = (real)(rg.x * xr);
+            sB[r][j] = (real)(rg.x * yr);
+            const double C = rg.y * zr;
+            float sn, cs;
+            sincos_rev((float)(C - floor(C)), sn, cs);
+            const float2 uu = u[i];
+            sU[r][j] = make_float4(uu.x * cs + uu.y * sn, uu.y * cs - uu.x * sn, uu.x * cs - uu.y * sn,
+                                   uu.y * cs + uu.x * sn);
+        }
+        __syncthreads();
+        if (active) {
+            for (int jj = 0; jj < cnt; ++jj) {
+                const real A = sA[rl][jj], B = sB[rl][jj];
+                const float4 w = sU[rl][jj];
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    float f;
+                    if (P64) {
+                        const double P = fma((double)A, (double)cf[j], (double)B * (double)sf[j]);
+                        f = (float)__builtin_amdgcn_fract(P);
+                    } else {
+                        const float P = fmaf((float)A, (float)cf[j], (float)B * (float)sf[j]);
+                        f = __builtin_amdgcn_fractf(P);
+                    }
+                    float sn, cs;
+                    sincos_rev(f, sn, cs);
+                    acc[j][0] = fmaf(cs, w.x, acc[j][0]);
+                    acc[j][1] = fmaf(cs, w.y, acc[j][1]);
+                    acc[j][2] = fmaf(sn, w.x, acc[j][2]);
+                    acc[j][3] = fmaf(sn, w.y, acc[j][3]);
+                    acc[j][4] = fmaf(cs, w.z, acc[j][4]);
+                    acc[j][5] = fmaf(cs, w.w, acc[j][5]);
+                    acc[j][6] = fmaf(sn, w.z, acc[j][6]);
+                    acc[j][7] = fmaf(sn, w.w, acc[j][7]);
+                }
+            }
+        }
+    }
+    if (!active) return;
+    const bool equator = 2 * m == L;
+    float4 *o = out + (int64_t)seg * split_stride + (int64_t)b * npair + (int64_t)m * 2 * L;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const int n = nloc + j * Tr;
+        if (n >= L) continue;
+        // S' = (0,1), T' = (2,3), S'' = (4,5), T'' = (6,7); S -+ iT
+        const float2 k0 = make_float2(acc[j][0] + acc[j][3], acc[j][1] - acc[j][2]);
+        const float2 k1 = make_float2(acc[j][0] - acc[j][3], acc[j][1] + acc[j][2]);
+        const float2 k2 = make_float2(acc[j][4] + acc[j][7], acc[j][5] - acc[j][6]);
+        const float2 k3 = make_float2(acc[j][4] - acc[j][7], acc[j][5] + acc[j][6]);
+        if (equator) {
+            o[n] = make_float4(k0.x, k0.y, k1.x, k1.y);
+        } else {
+            o[n] = make_float4(k0.x, k0.y, k3.x, k3.y);
+            o[n + L] = make_float4(k1.x, k1.y, k2.x, k2.y);
+        }
+    }
+}
+
+// Sum the point-segment partials of the forward transform in segment order.
+__global__ void __launch_bounds__(kThreads)
+k_sum_segments(const float4 *__restrict__ part, const int32_t *__restrict__ boxes, int64_t npair, int nsplit,
+               int64_t split_stride, float4 *__restrict__ out) {
+    const int b = boxes[blockIdx.y];
+    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < npair; p += (int64_t)gridDim.x * kThreads) {
+        const int64_t o = (int64_t)b * npair + p;
+        float4 a = part[o];
+        for (int s = 1; s < nsplit; ++s) {
+            const float4 w = part[(int64_t)s * split_stride + o];
+            a.x += w.x; a.y += w.y; a.z += w.z; a.w += w.w;
+        }
+        out[o] = a;
+    }
+}
+
+// Backward transform in ring-pair form: per target point and ring pair m,
+//   v += e^{iC} sum_n [e^{iP} v~(m,n) + e^{-iP} v~(m,n+L)] + e^{-iC} sum_n [e^{iP} v~(L-m,n) + e^{-iP} v~(L-m,n+L)]
+// Two target points per thread.
+template <bool P64>
+__global__ void __launch_bounds__(kThreads)
+k_pw_backward_rings(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+                    const int32_t *__restrict__ start, const double *__restrict__ ctr, const int2 *__restrict__ work,
+                    const double2 *__restrict__ rings, const double2 *__restrict__ phis, int L, int nrp,
+                    const float4 *__restrict__ vt, int64_t npair, float2 *__restrict__ v) {
+    typedef typename std::conditional<P64, double, float>::type real;
+    constexpr int PT = 2;
+    const int2 wk = work[blockIdx.x];
+    const int t = wk.x;
+    const int tid = threadIdx.x;
+    const int iend = start[t + 1];
+    double xr[PT], yr[PT], zr[PT];
+    bool valid[PT];
+    float vr[PT], vi[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        const int i = wk.y + tid + q * kThreads;
+        valid[q] = i < iend;
+        xr[q] = valid[q] ? xs[i] - ctr[3 * t] : 0.0;
+        yr[q] = valid[q] ? ys[i] - ctr[3 * t + 1] : 0.0;
+        zr[q] = valid[q] ? zs[i] - ctr[3 * t + 2] : 0.0;
+        vr[q] = vi[q] = 0.f;
+    }
+    __shared__ float4 s01[kThreads], s23[kThreads];
+    __shared__ real scf[kThreads], ssf[kThreads];
+    const float4 *vb = vt + (int64_t)t * npair;
+    for (int m = 0; m < nrp; ++m) {
+        const double2 rg = rings[m];
+        const bool eq = 2 * m == L;
+        real A[PT], B[PT];
+        float ecs[PT], esn[PT], xre[PT], xim[PT], yre[PT], yim[PT];
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            A[q] = (real)(rg.x * xr[q]);
+            B[q] = (real)(rg.x * yr[q]);
+            const double C = rg.y * zr[q];
+            sincos_rev((float)(C - floor(C)), esn[q], ecs[q]);
+            xre[q] = xim[q] = yre[q] = yim[q] = 0.f;
+        }
+        for (int n0 = 0; n0 < L; n0 += kThreads) {
+            const int cnt = min(kThreads, L - n0);
+            __syncthreads();
+            if (tid < cnt) {
+                const int n = n0 + tid;
+                const float4 p1 = vb[(int64_t)m * 2 * L + n];
+                if (eq) {
+                    s01[tid] = make_float4(p1.x + p1.z, p1.y + p1.w, p1.x - p1.z, p1.y - p1.w);
+                    s23[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                } else {
+                    const float4 p2 = vb[(int64_t)m * 2 * L + n + L];
+                    s01[tid] = make_float4(p1.x + p2.x, p1.y + p2.y, p1.x - p2.x, p1.y - p2.y);
+                    s23[tid] = make_float4(p2.z + p1.z, p2.w + p1.w, p2.z - p1.z, p2.w - p1.w);
+                }
+                scf[tid] = (real)phis[n].x;
+                ssf[tid] = (real)phis[n].y;
+            }
+            __syncthreads();
+            for (int jj = 0; jj < cnt; ++jj) {
+                const real cfn = scf[jj], sfn = ssf[jj];
+                const float4 a = s01[jj], c = s23[jj];
+#pragma unroll
+                for (int q = 0; q < PT; ++q) {
+                    float f;
+                    if (P64) {
+                        const double P = fma((double)A[q], (double)cfn, (double)B[q] * (double)sfn);
+                        f = (float)__builtin_amdgcn_fract(P);
+                    } else {
+                        const float P = fmaf((float)A[q], (float)cfn, (float)B[q] * (float)sfn);
+                        f = __builtin_amdgcn_fractf(P);
+                    }
+                    float sn, cs;
+                    sincos_rev(f, sn, cs);
+                    xre[q] = fmaf(cs, a.x, fmaf(-sn, a.w, xre[q]));
+                    xim[q] = fmaf(cs, a.y, fmaf(sn, a.z, xim[q]));
+                    yre[q] = fmaf(cs, c.x, fmaf(-sn, c.w, yre[q]));
+                    yim[q] = fmaf(cs, c.y, fmaf(sn, c.z, yim[q]));
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            vr[q] += ecs[q] * (xre[q] + yre[q]) - esn[q] * (xim[q] - yim[q]);
+            vi[q] += ecs[q] * (xim[q] + yim[q]) + esn[q] * (xre[q] - yre[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        if (!valid[q]) continue;
+        const int i = wk.y + tid + q * kThreads;
+        float2 o = v[i];
+        o.x += vr[q];
+        o.y += vi[q];
+        v[i] = o;
+    }
+}
+
 // ------------------------------------------------------------------ Lagrange levels
 constexpr int kMaxR1 = 8;
 constexpr int kAnterpChunk = 64;
@@ -501,6 +731,30 @@ void launch_forward(const Plan &P, const Level &LV, const Tree &TY, int l, hipSt
                ntile, P.wsrc.p);
 }
 
+
+template <int G, bool P64>
+void launch_forward_rings(const Plan &P, const Level &LV, const Tree &TY, int l, hipStream_t st) {
+    const int L = LV.L;
+    const int Tr = (L + G - 1) / G;
+    const int R = std::max(1, std::min({kMaxRings, kThreads / Tr, LV.nrp}));
+    const int nchunk = (LV.nrp + R - 1) / R;
+    const int nsplit = LV.qSplit;
+    const int64_t nb = (int64_t)LV.fwd_boxes.n * nchunk * nsplit;
+    FFM_CHECK(Tr <= kThreads && nb < (int64_t)1 << 31, FFM_EINTERNAL, "ring forward grid");
+    float4 *dst = nsplit > 1 ? P.wpart.p : P.wsrc.p;
+    const int64_t stride = (int64_t)TY.lev[l].nbox * LV.npair;
+    FFM_CHECK(nsplit == 1 || (size_t)(stride * nsplit) <= P.wpart.n, FFM_EINTERNAL, "ring forward partials");
+    FFM_LAUNCH((k_pw_forward_rings<G, P64>), (int)nb, kThreads, 0, st, TY.xs.p, TY.ys.p, TY.zs.p, P.u_sorted.p,
+               TY.lev[l].start.p, TY.lev[l].ctr.p, LV.fwd_boxes.p, LV.rings.p, LV.phis.p, L, LV.nrp, Tr, R, nchunk,
+               nsplit, LV.npair, dst, stride);
+    if (nsplit > 1) {
+        dim3 grid((unsigned)std::min<int64_t>((LV.npair + kThreads - 1) / kThreads, 64), (unsigned)LV.fwd_boxes.n);
+        hipLaunchKernelGGL(k_sum_segments, grid, dim3(kThreads), 0, st, P.wpart.p, LV.fwd_boxes.p, LV.npair, nsplit,
+                           stride, P.wsrc.p);
+        FFM_HIP(hipGetLastError());
+    }
+}
+
 template <int PPT>
 void launch_transfer(const Plan &P, const Level &LV, hipStream_t st) {
     const int ntile = (int)((LV.npair + kThreads * PPT - 1) / (kThreads * PPT));
@@ -537,7 +791,13 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
         const Level &LV = P.lev[l];
         if (LV.method == kGegenbauer) {
             // source transform, diagonal transfer, target transform (Sec. 2.2.3)
-            if (LV.npair >= 4 * kThreads) {
+            if (LV.qG == 4) {
+                if (LV.phase64) launch_forward_rings<4, true>(P, LV, TY, l, st);
+                else launch_forward_rings<4, false>(P, LV, TY, l, st);
+            } else if (LV.qG == 2) {
+                if (LV.phase64) launch_forward_rings<2, true>(P, LV, TY, l, st);
+                else launch_forward_rings<2, false>(P, LV, TY, l, st);
+            } else if (LV.npair >= 4 * kThreads) {
                 if (LV.phase64) launch_forward<4, true>(P, LV, TY, l, st);
                 else launch_forward<4, false>(P, LV, TY, l, st);
             } else if (LV.npair >= 2 * kThreads) {
@@ -551,14 +811,24 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
             if (LV.npair >= 2 * kThreads) launch_transfer<2>(P, LV, st);
             else launch_transfer<1>(P, LV, st);
             P.mark(2 + 3 * (l - 1), st);
-            if (LV.phase64)
+            if (LV.qG) {
+                if (LV.phase64)
+                    FFM_LAUNCH(k_pw_backward_rings<true>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p,
+                               TX.zs.p, TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, LV.rings.p, LV.phis.p, LV.L,
+                               LV.nrp, P.wtgt.p, LV.npair, P.v_sorted.p);
+                else
+                    FFM_LAUNCH(k_pw_backward_rings<false>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p,
+                               TX.zs.p, TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, LV.rings.p, LV.phis.p, LV.L,
+                               LV.nrp, P.wtgt.p, LV.npair, P.v_sorted.p);
+            } else if (LV.phase64) {
                 FFM_LAUNCH(k_pw_backward<true>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p, TX.zs.p,
                            TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, (const float4 *)LV.dirs.p, LV.dirs64.p,
                            P.wtgt.p, LV.npair, P.v_sorted.p);
-            else
+            } else {
                 FFM_LAUNCH(k_pw_backward<false>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p, TX.zs.p,
                            TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, (const float4 *)LV.dirs.p, LV.dirs64.p,
                            P.wtgt.p, LV.npair, P.v_sorted.p);
+            }
             P.mark(3 + 3 * (l - 1), st);
         } else if (LV.method == kLagrange) {
             // interpolation, MFMA transfer, interpolation back (Sec. 2.2.2)

@@ -127,6 +127,13 @@ struct Level {
     DevBuf<double> dirs64;               // [npair][3] direction * k / (2 pi), FP64
     DevBuf<float4> D;                    // [ncls][npair] (D(s_p), D(-s_p)) as two complex
     bool phase64 = false;                // FP64 phase reduction at this level
+    // ring-pair form of the transforms: ring m and its antipodal ring share one in-plane phase
+    int nrp = 0;                         // ring pairs: (L+1)/2 rounded up (the equator ring when L is even)
+    DevBuf<double2> rings;               // [nrp] (sin theta_m, cos theta_m) * k / (2 pi)
+    DevBuf<double2> phis;                // [L] (cos phi_n, sin phi_n), phi_n = pi n / L
+    int qG = 0;                          // groups of 4 directions per thread (0: direction-pair kernels)
+    int qSplit = 1;                      // point segments of the forward transform (partials summed in order)
+    int bwd_tile = 256;                  // target points per backward block
     // Lagrange node tables (FP32): Chebyshev nodes and 1 / prod_{b != a}(t_a - t_b)
     DevBuf<float> lnodes, lden;
     // work lists, largest boxes first
@@ -155,7 +162,8 @@ struct Plan {
     DevBuf<float2> u_sorted, v_sorted;   // [ny], [nx]
     DevBuf<float4> wsrc, wtgt;           // Gegenbauer u~ / v~, or Lagrange (as float2) scratch
     DevBuf<float2> wz;                   // Lagrange per-pair products
-    size_t ws_src = 0, ws_tgt = 0, ws_z = 0;
+    DevBuf<float4> wpart;                // forward-transform partial sums of point segments
+    size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0;
     // stats
     ffm_stats_t stats{};
     hipEvent_t done = nullptr;           // recorded after every apply

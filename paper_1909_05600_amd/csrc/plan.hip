@@ -559,7 +559,7 @@ void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &
     std::vector<int2> work;
     for (int32_t t : tgt) {
         LV.max_tgt_pts = std::max(LV.max_tgt_pts, sx[t + 1] - sx[t]);
-        for (int32_t i = sx[t]; i < sx[t + 1]; i += 256) work.push_back(make_int2(t, i));
+        for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) work.push_back(make_int2(t, i));
     }
     upload(LV.bwd_work, work, st);
     std::vector<int32_t> fwd;
@@ -739,7 +739,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     }
 
     // --- compression form and tables per level (Sec. 2.2.2, 2.2.3)
-    size_t ws_src = 0, ws_tgt = 0, ws_z = 0;
+    size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0;
     for (int l = 1; l <= P.leaf; ++l) {
         Level &LV = P.lev[l];
         if (LV.nfar == 0) continue;
@@ -749,12 +749,17 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             for (int d = 0; d < 3; ++d)
                 r0[3 * c + d] = (corner[0][d] - corner[1][d]) + (double)LV.cls_off[3 * c + d] * dl;
         const int32_t nby = TY.lev[l].nbox, nbx = TX.lev[l].nbox;
-        build_work_lists(P, LV, TX.lev[l], TY.lev[l], false, st);
         const bool geg = P.kernel == FFM_HELMHOLTZ && P.k * dl >= P.opt.kd_switch;
         if (geg) {
             LV.method = kGegenbauer;
             LV.L = gegenbauer_L(P.k, dl, P.eps);
             FFM_CHECK(LV.L <= 1000, FFM_EINVAL, "ffm_plan: k * d_0 too large (Gegenbauer rank above 1000)");
+            // ring-pair kernels where rings are long enough to fill the threads
+            LV.qG = LV.L >= 64 ? 4 : (LV.L >= 32 ? 2 : 0);
+            LV.bwd_tile = LV.qG ? 512 : 256;
+        }
+        build_work_lists(P, LV, TX.lev[l], TY.lev[l], false, st);
+        if (geg) {
             const int L = LV.L, nth = L + 1, nph = 2 * L;
             LV.nq = 2 * (int64_t)L * (L + 1);
             LV.npair = LV.nq / 2;
@@ -784,8 +789,32 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             }
             upload(LV.dirs, dirs32, st);
             upload(LV.dirs64, dirs64, st);
-            // FP64 phase reduction where a box spans more than 8 wavelengths of phase
-            LV.phase64 = P.k * dl * std::sqrt(3.0) * 0.5 / (2.0 * M_PI) > 8.0;
+            // ring-pair tables: (sin, cos) of every ring pair's polar angle, scaled by k / 2pi, and the
+            // azimuths of one half turn
+            LV.nrp = nth / 2 + (nth & 1);
+            std::vector<double2> rings(LV.nrp), phis(L);
+            for (int m = 0; m < LV.nrp; ++m)
+                rings[m] = make_double2(std::sqrt(1.0 - xm[m] * xm[m]) * kr, xm[m] * kr);
+            for (int n = 0; n < L; ++n) phis[n] = make_double2(std::cos(M_PI * n / L), std::sin(M_PI * n / L));
+            upload(LV.rings, rings, st);
+            upload(LV.phis, phis, st);
+            // FP64 phase reduction where the FP32 rounding of the largest phase (a few ulp of
+            // k sqrt(3) d_l / 2 radians) would reach eps / 20; the per-(point, ring) factor e^{iC} of
+            // the ring-pair form is always reduced in FP64
+            const double max_rad = P.k * dl * std::sqrt(3.0) * 0.5;
+            LV.phase64 = max_rad * std::ldexp(1.0, -22) > P.eps / 20.0;
+            if (LV.qG) {
+                // split the points of each box into segments when boxes are too few to fill the chip
+                const int Tr = (L + LV.qG - 1) / LV.qG;
+                const int R = std::max(1, std::min({16, 256 / Tr, LV.nrp}));
+                const int64_t blocks = (int64_t)LV.fwd_boxes.n * ((LV.nrp + R - 1) / R);
+                const double avg = LV.pts_src / std::max<double>(1.0, (double)LV.fwd_boxes.n);
+                int split = 1;
+                while (split < 8 && blocks * split < 4096 && avg / (2 * split) >= 512 && LV.fwd_boxes.n < 65536)
+                    split *= 2;
+                LV.qSplit = split;
+                if (split > 1) ws_part = std::max(ws_part, (size_t)split * nby * LV.npair);
+            }
             // per-class series coefficients (host FP64), unit directions r0/|r0|
             std::vector<double> rhat(3 * (size_t)LV.ncls);
             std::vector<double2> coef((size_t)LV.ncls * (L + 1));
@@ -873,6 +902,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.ws_src = ws_src;
     P.ws_tgt = ws_tgt;
     P.ws_z = ws_z;
+    P.ws_part = ws_part;
+    P.wpart.alloc(ws_part);
     P.u_sorted.alloc(ny);
     P.v_sorted.alloc(nx);
     P.wsrc.alloc(ws_src);
@@ -903,6 +934,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.nclass[l] = LV.ncls;
         s.nq[l] = LV.nq;
         s.fwd_points[l] = LV.pts_src;
+        s.tform[l] = LV.method == kGegenbauer ? (LV.qG ? 2 : 1) : 0;
         s.bwd_points[l] = LV.pts_tgt;
         if (LV.method == kGegenbauer) {
             s.transform_terms += (LV.pts_src + LV.pts_tgt) * (double)LV.nq;
@@ -930,9 +962,9 @@ size_t plan_device_bytes(const Plan &P) {
         b += L.far_ptr.bytes() + L.near_ptr.bytes() + L.far_src.bytes() + L.far_cls.bytes() + L.near_src.bytes() +
              L.T.bytes() + L.grp_pair.bytes() + L.grp_cls.bytes() + L.dirs.bytes() + L.dirs64.bytes() + L.D.bytes() +
              L.lnodes.bytes() + L.lden.bytes() + L.fwd_boxes.bytes() + L.tgt_boxes.bytes() + L.bwd_work.bytes() +
-             L.near_boxes.bytes();
+             L.near_boxes.bytes() + L.rings.bytes() + L.phis.bytes();
     }
-    b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes();
+    b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes();
     return b;
 }
 

@@ -168,3 +168,26 @@ def test_ragged_and_unequal_sizes(orc):
         op = orc.Plan(X, Y, kernel, k, 1e-3, n_leaf=40)
         compare_trees(gp, op)
         assert rel(gpu_apply(gp, wu), op.apply(wu)) < RTOL_FFM[kernel]
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-4])
+def test_ring_pair_transforms(orc, eps):
+    """Coarse Gegenbauer levels with long rings use the ring-pair transform kernels (4 directions per
+    sin/cos); at eps = 1e-4 the in-plane phase is reduced in FP64, at 1e-3 in FP32."""
+    rng = np.random.default_rng(21)
+    X = W.sphere_points(50000, rng)
+    wu = ((rng.standard_normal(50000) + 1j * rng.standard_normal(50000)) / 50000).astype(np.complex64)
+    k = 100.0
+    gp = gpu_plan(X, X, 1, k, eps)
+    op = orc.Plan(X, X, 1, k, eps)
+    st = gp.stats()
+    assert max(st["order"]) >= 64
+    compare_trees(gp, op)
+    v = gpu_apply(gp, wu)
+    vo = op.apply(wu)
+    rows = np.arange(0, 50000, 97)
+    d = orc.dense_rows(X, X, wu, 1, k, rows)
+    print("ring-pair eps=%g: vs oracle %.3e  vs dense %.3e (oracle %.3e)"
+          % (eps, rel(v, vo), rel(v[rows], d), rel(vo[rows], d)))
+    assert rel(v, vo) < RTOL_FFM[1]
+    assert rel(v[rows], d) <= eps
