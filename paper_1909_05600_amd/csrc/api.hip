@@ -116,6 +116,39 @@ void dev_free(void *p) {
     g_cached += sz;
 }
 
+namespace {
+std::mutex g_pmx;
+std::unordered_map<void *, size_t> g_plive;
+std::multimap<size_t, void *> g_pfree;
+}  // namespace
+
+void *pinned_alloc(size_t bytes) {
+    const size_t sz = round_size(bytes);
+    std::lock_guard<std::mutex> lk(g_pmx);
+    auto it = g_pfree.find(sz);
+    void *p = nullptr;
+    if (it != g_pfree.end()) {
+        p = it->second;
+        g_pfree.erase(it);
+    } else {
+        hipError_t e = hipHostMalloc(&p, sz, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(FFM_ENOMEM, std::string("hipHostMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        }
+    }
+    g_plive[p] = sz;
+    return p;
+}
+
+void pinned_free(void *p) {
+    std::lock_guard<std::mutex> lk(g_pmx);
+    auto it = g_plive.find(p);
+    if (it == g_plive.end()) return;
+    g_pfree.emplace(it->second, p);
+    g_plive.erase(it);
+}
+
 size_t dev_bytes_live() { return (size_t)std::max<long long>(0, g_live_bytes.load()); }
 
 }  // namespace ffm

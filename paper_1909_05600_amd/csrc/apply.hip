@@ -591,6 +591,91 @@ k_lag_mfma(const float *__restrict__ T, int helm, const float2 *__restrict__ ut,
     }
 }
 
+
+// Mixed precision: the same class-group products on FP16 MFMA (v_mfma_f32_32x32x8f16) with FP32
+// accumulation.  A[i][k] comes from lane i + 32 (k / 4) (element k % 4 of a half4), B[k][j] from lane
+// j + 32 (k / 4); D as for the FP32 instruction.  T16 = T * sT (plan time); the sources are scaled by a
+// power of two s_u derived on the device from max |u| so that |u~ s_u| < 6e4; Z = C / (sT s_u).
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float u_scale(float amax, int maxpts) {
+    // |u~| <= (Lebesgue constant of the tensor grid, <= 8) * points * max|u|
+    const float bound = 8.f * (float)maxpts * fmaxf(amax, 1e-30f);
+    return exp2f(floorf(log2f(6.0e4f / bound)));
+}
+
+__global__ void __launch_bounds__(64)
+k_lag_mfma16(const _Float16 *__restrict__ T16, int helm, float sT, const float *__restrict__ amax, int maxpts,
+             const float2 *__restrict__ ut, const int32_t *__restrict__ far_src, const int32_t *__restrict__ grp_pair,
+             const int32_t *__restrict__ grp_cls, int rp, float2 *__restrict__ Z) {
+    extern __shared__ _Float16 U16[];   // [32][rp]: column-major tile, k contiguous
+    const int g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c = grp_cls[g];
+    const float su = u_scale(*amax, maxpts);
+    __shared__ int pe[16], ps[16];
+    if (lane < 16) {
+        const int e = grp_pair[(int64_t)g * 16 + lane];
+        pe[lane] = e;
+        ps[lane] = e >= 0 ? far_src[e] : -1;
+    }
+    __syncthreads();
+    for (int idx = lane; idx < rp * 32; idx += 64) {
+        const int col = idx / rp, k = idx % rp, m = col >> 1;
+        float val = 0.f;
+        if (ps[m] >= 0) {
+            const float2 w = ut[(int64_t)ps[m] * rp + k];
+            val = ((col & 1) ? w.y : w.x) * su;
+        }
+        U16[idx] = (_Float16)val;
+    }
+    __syncthreads();
+    const int64_t per = (int64_t)rp * rp;
+    const _Float16 *Tre = T16 + (int64_t)c * (helm ? 2 : 1) * per;
+    const _Float16 *Tim = Tre + per;
+    const int col = lane & 31, kh = lane >> 5;
+    const int e = pe[col >> 1];
+    const float inv = 1.f / (sT * su);
+    for (int mt = 0; mt < rp / 32; ++mt) {
+        floatx16 acc1, acc2;
+        for (int v = 0; v < 16; ++v) {
+            acc1[v] = 0.f;
+            acc2[v] = 0.f;
+        }
+        const int i = mt * 32 + col;
+        for (int k0 = 0; k0 < rp; k0 += 8) {
+            const int k = k0 + 4 * kh;
+            const half4_t b = *reinterpret_cast<const half4_t *>(U16 + col * rp + k);
+            const half4_t a1 = *reinterpret_cast<const half4_t *>(Tre + (int64_t)i * rp + k);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(a1, b, acc1, 0, 0, 0);
+            if (helm) {
+                const half4_t a2 = *reinterpret_cast<const half4_t *>(Tim + (int64_t)i * rp + k);
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x8f16(a2, b, acc2, 0, 0, 0);
+            }
+        }
+        for (int v = 0; v < 16; ++v) {
+            const int row = mt * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+            float val = acc1[v];
+            if (helm) {
+                const float sw = __shfl_xor(acc2[v], 1, 64);
+                val = (col & 1) ? val + sw : val - sw;
+            }
+            if (e >= 0) reinterpret_cast<float *>(Z + (int64_t)e * rp + row)[col & 1] = val * inv;
+        }
+    }
+}
+
+// max over |Re u|, |Im u| (non-negative floats compare as their bit patterns)
+__global__ void __launch_bounds__(kThreads) k_amax(const float2 *__restrict__ u, int64_t n, float *out) {
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        m = fmaxf(m, fmaxf(fabsf(u[i].x), fabsf(u[i].y)));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int *>(out), __float_as_uint(m));
+}
+
+__global__ void k_zero1(float *a) { *a = 0.f; }
+
 // v_i += L_X^T v~_t with v~_t = sum_{e in far(t)} Z_e (fixed order), t = 2 (x - c_t) / d_l.
 __global__ void __launch_bounds__(kThreads)
 k_lag_interp(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
@@ -648,8 +733,9 @@ k_lag_interp(const double *__restrict__ xs, const double *__restrict__ ys, const
 }
 
 // ------------------------------------------------------------------ near field (leaf)
-// v_i += sum_{s in near(t)} sum_{j in s, r_ij > 0} G(r_ij) u_j.  One 64-lane block per target box;
-// source points are staged through LDS relative to the target centre, in FP32.
+// v_i += sum_{s in near(t)} sum_{j in s, r_ij > 0} G(r_ij) u_j.  One 64-lane block per target box; source
+// points are staged through LDS in FP64 relative to the target centre, and every pair's difference is
+// formed in FP64 and rounded once to FP32, so close pairs keep the full FP32 relative accuracy of r.
 template <bool HELM>
 __global__ void __launch_bounds__(64)
 k_near(const double *__restrict__ txs, const double *__restrict__ tys, const double *__restrict__ tzs,
@@ -660,18 +746,18 @@ k_near(const double *__restrict__ txs, const double *__restrict__ tys, const dou
     const int t = tboxes[blockIdx.x];
     const int lane = threadIdx.x;
     const double cx = tctr[3 * t], cy = tctr[3 * t + 1], cz = tctr[3 * t + 2];
-    __shared__ float4 sp[64];   // x, y, z relative to c_t; unused
-    __shared__ float2 su[64];   // u / (4 pi)
+    __shared__ double spx[64], spy[64], spz[64];   // sources relative to c_t
+    __shared__ float2 su[64];                      // u / (4 pi)
     const float inv4pi = (float)(1.0 / (4.0 * M_PI));
     const int64_t e0 = near_ptr[t], e1 = near_ptr[t + 1];
     for (int i0 = tstart[t]; i0 < tstart[t + 1]; i0 += 64) {
         const int i = i0 + lane;
         const bool valid = i < tstart[t + 1];
-        float x = 0.f, y = 0.f, z = 0.f;
+        double x = 0.0, y = 0.0, z = 0.0;
         if (valid) {
-            x = (float)(txs[i] - cx);
-            y = (float)(tys[i] - cy);
-            z = (float)(tzs[i] - cz);
+            x = txs[i] - cx;
+            y = tys[i] - cy;
+            z = tzs[i] - cz;
         }
         float are = 0.f, aim = 0.f;
         for (int64_t e = e0; e < e1; ++e) {
@@ -682,15 +768,16 @@ k_near(const double *__restrict__ txs, const double *__restrict__ tys, const dou
                 __syncthreads();
                 if (lane < cnt) {
                     const int j = c0 + lane;
-                    sp[lane] = make_float4((float)(sxs[j] - cx), (float)(sys[j] - cy), (float)(szs[j] - cz), 0.f);
+                    spx[lane] = sxs[j] - cx;
+                    spy[lane] = sys[j] - cy;
+                    spz[lane] = szs[j] - cz;
                     const float2 uu = u[j];
                     su[lane] = make_float2(uu.x * inv4pi, uu.y * inv4pi);
                 }
                 __syncthreads();
                 for (int jj = 0; jj < cnt; ++jj) {
-                    const float4 p = sp[jj];
+                    const float dx = (float)(x - spx[jj]), dy = (float)(y - spy[jj]), dz = (float)(z - spz[jj]);
                     const float2 uu = su[jj];
-                    const float dx = x - p.x, dy = y - p.y, dz = z - p.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
                     if (HELM) {
@@ -785,6 +872,11 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
     Tree &TX = *P.tx, &TY = *P.ty;
     FFM_LAUNCH(k_perm_in, nblocks(P.ny), kThreads, 0, st, wu, dtype, TY.perm.p, P.ny, P.u_sorted.p);
     FFM_LAUNCH(k_zero2, nblocks(P.nx), kThreads, 0, st, P.v_sorted.p, P.nx);
+    if (P.any_fp16) {
+        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, P.amax.p);
+        FFM_LAUNCH(k_amax, (int)std::min<int64_t>(nblocks(P.ny), 1024), kThreads, 0, st, P.u_sorted.p, P.ny,
+                   P.amax.p);
+    }
     P.mark(0, st);
     const bool helm = P.kernel == FFM_HELMHOLTZ;
     for (int l = 1; l <= P.leaf; ++l) {
@@ -837,8 +929,13 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
             FFM_LAUNCH(k_lag_anterp, (int)LV.fwd_boxes.n, kThreads, 0, st, TY.xs.p, TY.ys.p, TY.zs.p, P.u_sorted.p,
                        TY.lev[l].start.p, TY.lev[l].ctr.p, LV.fwd_boxes.p, LV.r1, LV.rp, LV.lnodes.p, LV.lden.p,
                        2.0 / dl, ut);
-            FFM_LAUNCH(k_lag_mfma, LV.ngrp, 64, sizeof(float) * LV.rp * 32, st, LV.T.p, helm ? 1 : 0, ut,
-                       LV.far_src.p, LV.grp_pair.p, LV.grp_cls.p, LV.rp, P.wz.p);
+            if (LV.fp16)
+                FFM_LAUNCH(k_lag_mfma16, LV.ngrp, 64, sizeof(_Float16) * LV.rp * 32, st, LV.T16.p, helm ? 1 : 0,
+                           LV.sT, P.amax.p, LV.max_src_pts, ut, LV.far_src.p, LV.grp_pair.p, LV.grp_cls.p, LV.rp,
+                           P.wz.p);
+            else
+                FFM_LAUNCH(k_lag_mfma, LV.ngrp, 64, sizeof(float) * LV.rp * 32, st, LV.T.p, helm ? 1 : 0, ut,
+                           LV.far_src.p, LV.grp_pair.p, LV.grp_cls.p, LV.rp, P.wz.p);
             P.mark(1 + 3 * (l - 1), st);   // interpolation and transfer share the first two slots
             P.mark(2 + 3 * (l - 1), st);
             FFM_LAUNCH(k_lag_interp, (int)LV.tgt_boxes.n, kThreads, sizeof(float2) * LV.r, st, TX.xs.p, TX.ys.p,

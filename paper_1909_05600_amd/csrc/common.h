@@ -46,6 +46,9 @@ struct Error : std::runtime_error {
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
 size_t dev_bytes_live();
+// Pinned host staging memory (cached like device memory) for asynchronous uploads.
+void *pinned_alloc(size_t bytes);
+void pinned_free(void *p);
 
 // ---------------------------------------------------------------- device buffer
 template <class T>
@@ -73,6 +76,34 @@ struct DevBuf {
         n = 0;
     }
     size_t bytes() const { return n * sizeof(T); }
+};
+
+// Temporaries that must outlive the stream work using them: device buffers and pinned host
+// staging, released together when the scratch list goes out of scope, after its stream drains.
+struct Scratch {
+    hipStream_t stream = nullptr;
+    std::vector<DevBuf<char>> bufs;
+    std::vector<void *> pinned;
+    explicit Scratch(hipStream_t st) : stream(st) {}
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    ~Scratch() {
+        (void)hipStreamSynchronize(stream);
+        for (void *p : pinned) pinned_free(p);
+    }
+    template <class T>
+    T *get(size_t count) {
+        bufs.emplace_back(count * sizeof(T));
+        return reinterpret_cast<T *>(bufs.back().p);
+    }
+    // copy host data into pinned staging memory that stays valid until the scratch list is released
+    template <class T>
+    const T *stage(const std::vector<T> &h) {
+        void *p = pinned_alloc(std::max<size_t>(h.size() * sizeof(T), 1));
+        pinned.push_back(p);
+        if (!h.empty()) std::memcpy(p, h.data(), h.size() * sizeof(T));
+        return static_cast<const T *>(p);
+    }
 };
 
 // ---------------------------------------------------------------- plan data
@@ -120,6 +151,9 @@ struct Level {
     DevBuf<int32_t> grp_pair;            // [ngrp][16] far pair index (-1 = empty), grouped by class
     DevBuf<int32_t> grp_cls;             // [ngrp]
     int32_t ngrp = 0;
+    bool fp16 = false;                   // transfer on FP16 MFMA (mixed precision)
+    DevBuf<_Float16> T16;                // [ncls][rp][rp] (x2 re/im), row-major by target index, times sT
+    float sT = 1.f;                      // power-of-two scale of T16
     // Gegenbauer
     int L = 0;
     int64_t nq = 0, npair = 0;           // n_Q = 2L(L+1) directions, npair = n_Q / 2 antipodal pairs
@@ -163,6 +197,8 @@ struct Plan {
     DevBuf<float4> wsrc, wtgt;           // Gegenbauer u~ / v~, or Lagrange (as float2) scratch
     DevBuf<float2> wz;                   // Lagrange per-pair products
     DevBuf<float4> wpart;                // forward-transform partial sums of point segments
+    DevBuf<float> amax;                  // max |Re u|, |Im u| of the current apply (FP16 scaling)
+    bool any_fp16 = false;
     size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0;
     // stats
     ffm_stats_t stats{};
@@ -181,8 +217,9 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st);
 size_t plan_device_bytes(const Plan &P);
 
 // device primitives (scan_sort.hip)
-void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st);  // out[n] = total
-void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st);  // out[n] = total
-void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st);      // stable
+// (temporaries come from the scratch list; nothing here synchronises the stream)
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st, Scratch &S);  // out[n] = total
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st, Scratch &S);  // out[n] = total
+void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st, Scratch &S);      // stable
 
 }  // namespace ffm

@@ -12,8 +12,10 @@
 #include "common.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
 
 namespace ffm {
@@ -267,12 +269,37 @@ __global__ void __launch_bounds__(kThreads) k_mark_sources(const int32_t *far_sr
     if (i < n) active[far_src[i]] = 1;
 }
 
+// number of point pairs of the near lists (exact: integer sum)
+__global__ void __launch_bounds__(kThreads)
+k_near_pairs(const int64_t *ptr, const int32_t *src, int32_t nbx, const int32_t *sx, const int32_t *sy,
+             unsigned long long *out) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long acc = 0;
+    if (t < nbx)
+        for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e)
+            acc += (unsigned long long)(sx[t + 1] - sx[t]) * (unsigned long long)(sy[src[e] + 1] - sy[src[e]]);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
 __global__ void __launch_bounds__(kThreads) k_remap(int32_t *cls, int64_t n, const int32_t *map) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) cls[i] = map[cls[i]];
 }
 
 // ------------------------------------------------------------------ Lagrange tables
+// FP16 copy of the FP32 transfer tables, row-major by target index (k contiguous for the MFMA A
+// operand), times a power-of-two scale.
+__global__ void __launch_bounds__(kThreads)
+k_to_half(const float *T, int64_t nplanes, int rp, float scale, _Float16 *T16) {
+    const int64_t per = (int64_t)rp * rp;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= per * nplanes) return;
+    const int64_t pl = g / per, e = g % per;
+    const int i = (int)(e / rp), j = (int)(e % rp);   // element (i, j); T is stored as [j][i]
+    T16[g] = (_Float16)(T[pl * per + (int64_t)j * rp + i] * scale);
+}
+
 // T_c[i][j] = G(|r0_c + (d_l / 2)(xi_i - xi_j)|), xi on the tensor Chebyshev grid; stored transposed
 // (column j contiguous over i) for the MFMA A operand; zero padding beyond r.
 __global__ void __launch_bounds__(kThreads)
@@ -434,27 +461,28 @@ int gegenbauer_L(double k, double dl, double eps) {
 }
 
 template <class T>
-void upload(DevBuf<T> &b, const std::vector<T> &h, hipStream_t st) {
+void upload(DevBuf<T> &b, const std::vector<T> &h, hipStream_t st, Scratch &SC) {
     b.alloc(h.size());
-    if (!h.empty()) FFM_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    if (!h.empty()) FFM_HIP(hipMemcpyAsync(b.p, SC.stage(h), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
+// upload into a scratch-owned buffer (released with the scratch list, after the final sync)
 template <class T>
-T fetch(const T *dev, hipStream_t st) {
-    T v;
-    FFM_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, st));
-    FFM_HIP(hipStreamSynchronize(st));
-    return v;
+T *keep(Scratch &SC, const std::vector<T> &h, hipStream_t st) {
+    T *p = SC.get<T>(std::max<size_t>(h.size(), 1));
+    if (!h.empty()) FFM_HIP(hipMemcpyAsync(p, SC.stage(h), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return p;
 }
 
 // ------------------------------------------------------------------ tree construction
-void build_tree(Tree &T, const double *P, int64_t n, const double corner[3], double S, hipStream_t st) {
+void build_tree(Tree &T, const double *P, int64_t n, const double corner[3], double S, hipStream_t st,
+                Scratch &SC) {
     T.n = n;
     std::memcpy(T.corner, corner, sizeof(double) * 3);
     T.key.alloc(n);
     T.perm.alloc(n);
     FFM_LAUNCH(k_morton, nblocks(n), kThreads, 0, st, P, n, corner[0], corner[1], corner[2], S, T.key.p, T.perm.p);
-    radix_sort_u64_u32(T.key.p, T.perm.p, n, st);
+    radix_sort_u64_u32(T.key.p, T.perm.p, n, st, SC);
     T.xs.alloc(n);
     T.ys.alloc(n);
     T.zs.alloc(n);
@@ -465,6 +493,7 @@ struct LevelScratch {
     DevBuf<int8_t> f;
     DevBuf<int32_t> flag, pos, boxid_prev;
     std::vector<int64_t> cum;   // boxes per level (cumulative start counts)
+    Scratch *sc = nullptr;
 };
 
 void first_levels(Tree &T, LevelScratch &S, hipStream_t st) {
@@ -493,7 +522,7 @@ void build_level(Tree &T, LevelScratch &S, int l, double d0, hipStream_t st) {
     TreeLevel &L = T.lev[l];
     L.nbox = (int32_t)S.cum[l];
     FFM_LAUNCH(k_flags, nblocks(n), kThreads, 0, st, S.f.p, n, l, S.flag.p);
-    exclusive_scan_i32(S.flag.p, S.pos.p, n, st);
+    exclusive_scan_i32(S.flag.p, S.pos.p, n, st, *S.sc);
     L.start.alloc(L.nbox + 1);
     L.ijk.alloc((size_t)3 * L.nbox);
     L.ctr.alloc((size_t)3 * L.nbox);
@@ -514,18 +543,22 @@ void build_level(Tree &T, LevelScratch &S, int l, double d0, hipStream_t st) {
 
 // Work lists of a level, built on the host from the box sizes and list pointers: largest boxes
 // first so that the longest blocks start early.
-void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &LY, bool near, hipStream_t st) {
+void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &LY, bool near, hipStream_t st,
+                      Scratch &SC) {
     std::vector<int32_t> sx(LX.nbox + 1), sy(LY.nbox + 1);
     FFM_HIP(hipMemcpyAsync(sx.data(), LX.start.p, sizeof(int32_t) * sx.size(), hipMemcpyDeviceToHost, st));
     FFM_HIP(hipMemcpyAsync(sy.data(), LY.start.p, sizeof(int32_t) * sy.size(), hipMemcpyDeviceToHost, st));
     std::vector<int64_t> ptr(LX.nbox + 1);
     const DevBuf<int64_t> &dptr = near ? LV.near_ptr : LV.far_ptr;
     FFM_HIP(hipMemcpyAsync(ptr.data(), dptr.p, sizeof(int64_t) * ptr.size(), hipMemcpyDeviceToHost, st));
-    std::vector<int32_t> src;
     std::vector<uint8_t> act;
+    unsigned long long near_pairs = 0;
     if (near && LV.nnear) {
-        src.resize(LV.nnear);
-        FFM_HIP(hipMemcpyAsync(src.data(), LV.near_src.p, sizeof(int32_t) * LV.nnear, hipMemcpyDeviceToHost, st));
+        unsigned long long *dn = SC.get<unsigned long long>(1);
+        FFM_HIP(hipMemsetAsync(dn, 0, sizeof(unsigned long long), st));
+        FFM_LAUNCH(k_near_pairs, nblocks(LX.nbox), kThreads, 0, st, LV.near_ptr.p, LV.near_src.p, LX.nbox, LX.start.p,
+                   LY.start.p, dn);
+        FFM_HIP(hipMemcpyAsync(&near_pairs, dn, sizeof(near_pairs), hipMemcpyDeviceToHost, st));
     }
     if (!near) {
         DevBuf<uint8_t> dact(LY.nbox);
@@ -533,7 +566,6 @@ void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &
         FFM_LAUNCH(k_mark_sources, nblocks(LV.nfar), kThreads, 0, st, LV.far_src.p, LV.nfar, dact.p);
         act.resize(LY.nbox);
         FFM_HIP(hipMemcpyAsync(act.data(), dact.p, LY.nbox, hipMemcpyDeviceToHost, st));
-        FFM_HIP(hipStreamSynchronize(st));
     }
     FFM_HIP(hipStreamSynchronize(st));
     auto by_size = [](const std::vector<int32_t> &start, std::vector<int32_t> &boxes) {
@@ -546,22 +578,17 @@ void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &
         if (ptr[t + 1] > ptr[t]) tgt.push_back(t);
     by_size(sx, tgt);
     if (near) {
-        upload(LV.near_boxes, tgt, st);
-        double pairs = 0;
-        for (int32_t t : tgt)
-            for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e)
-                pairs += (double)(sx[t + 1] - sx[t]) * (double)(sy[src[e] + 1] - sy[src[e]]);
-        P.stats.near_pairs = pairs;
-        FFM_HIP(hipStreamSynchronize(st));
+        upload(LV.near_boxes, tgt, st, SC);
+        P.stats.near_pairs = (double)near_pairs;
         return;
     }
-    upload(LV.tgt_boxes, tgt, st);
+    upload(LV.tgt_boxes, tgt, st, SC);
     std::vector<int2> work;
     for (int32_t t : tgt) {
         LV.max_tgt_pts = std::max(LV.max_tgt_pts, sx[t + 1] - sx[t]);
         for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) work.push_back(make_int2(t, i));
     }
-    upload(LV.bwd_work, work, st);
+    upload(LV.bwd_work, work, st, SC);
     std::vector<int32_t> fwd;
     for (int32_t s = 0; s < LY.nbox; ++s)
         if (act[s]) {
@@ -569,19 +596,37 @@ void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &
             LV.max_src_pts = std::max(LV.max_src_pts, sy[s + 1] - sy[s]);
         }
     by_size(sy, fwd);
-    upload(LV.fwd_boxes, fwd, st);
+    upload(LV.fwd_boxes, fwd, st, SC);
     double npts_src = 0, npts_tgt = 0;
     for (int32_t s : fwd) npts_src += sy[s + 1] - sy[s];
     for (int32_t t : tgt) npts_tgt += sx[t + 1] - sx[t];
     LV.pts_src = npts_src;
     LV.pts_tgt = npts_tgt;
-    FFM_HIP(hipStreamSynchronize(st));
 }
+
+// FFM_LOG=1: host wall time of the plan phases on stderr (quiet by default)
+struct PhaseLog {
+    bool on = std::getenv("FFM_LOG") && std::getenv("FFM_LOG")[0] == '1';
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    std::string line;
+    void mark(const char *what) {
+        if (!on) return;
+        auto now = std::chrono::steady_clock::now();
+        char buf[64];
+        std::snprintf(buf, sizeof(buf), " %s=%.3f", what, std::chrono::duration<double, std::milli>(now - t).count());
+        line += buf;
+        t = now;
+    }
+    ~PhaseLog() {
+        if (on) std::fprintf(stderr, "ffm_plan ms:%s\n", line.c_str());
+    }
+};
 
 }  // namespace
 
 // =========================================================================== plan
 void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
+    PhaseLog plog;
     const int64_t nx = P.nx, ny = P.ny;
     if (P.empty) return;
 
@@ -626,41 +671,49 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.S = (double)(1 << kBits) / d0;
     P.aligned = std::memcmp(corner[0], corner[1], sizeof(double) * 3) == 0;
 
+    plog.mark("bbox");
     // --- Morton-sorted trees (Sec. 2.1)
+    Scratch SC(st);
     P.tx.reset(new Tree());
-    build_tree(*P.tx, X, nx, corner[0], P.S, st);
+    build_tree(*P.tx, X, nx, corner[0], P.S, st, SC);
     if (P.same) {
         P.ty = P.tx.get();
     } else {
         P.ty_own.reset(new Tree());
-        build_tree(*P.ty_own, Y, ny, corner[1], P.S, st);
+        build_tree(*P.ty_own, Y, ny, corner[1], P.S, st, SC);
         P.ty = P.ty_own.get();
     }
     Tree &TX = *P.tx, &TY = *P.ty;
     LevelScratch SX, SY;
+    SX.sc = SY.sc = &SC;
     first_levels(TX, SX, st);
     if (!P.same) first_levels(TY, SY, st);
+    plog.mark("trees");
     const int maxlev = P.opt.max_level;
     build_level(TX, SX, 0, d0, st);
     if (!P.same) build_level(TY, SY, 0, d0, st);
 
-    // --- descent lists (Sec. 2.2.2, 2.2.4; Prop. 1)
-    DevBuf<int64_t> pnear_ptr(2), cnt_f, cnt_n;
-    DevBuf<int32_t> pnear_src(1);
+    // --- descent lists (Sec. 2.2.2, 2.2.4; Prop. 1): near_0 = {(root, root)}; the near lists of
+    // level l - 1 (CSR by target) generate the candidates of level l.
     {
+        Level &L0 = P.lev[0];
         const int64_t h_ptr[2] = {0, 1};
         const int32_t h_src[1] = {0};
-        FFM_HIP(hipMemcpyAsync(pnear_ptr.p, h_ptr, sizeof(h_ptr), hipMemcpyHostToDevice, st));
-        FFM_HIP(hipMemcpyAsync(pnear_src.p, h_src, sizeof(h_src), hipMemcpyHostToDevice, st));
+        L0.near_ptr.alloc(2);
+        L0.near_src.alloc(1);
+        L0.nnear = 1;
+        FFM_HIP(hipMemcpyAsync(L0.near_ptr.p, h_ptr, sizeof(h_ptr), hipMemcpyHostToDevice, st));
+        FFM_HIP(hipMemcpyAsync(L0.near_src.p, h_src, sizeof(h_src), hipMemcpyHostToDevice, st));
     }
-    DevBuf<int> bad(1);
-    DevBuf<int32_t> win_used(kWin3);
+    int *bad = SC.get<int>(1);
+    int32_t *win_used = SC.get<int32_t>(kWin3);
     P.leaf = maxlev;
     for (int l = 1; l <= maxlev; ++l) {
         build_level(TX, SX, l, d0, st);
         if (!P.same) build_level(TY, SY, l, d0, st);
         const int32_t nbx = TX.lev[l].nbox;
         Level &LV = P.lev[l];
+        const Level &LP = P.lev[l - 1];
         const double dl = std::ldexp(d0, -l);
         FarTest ft;
         ft.ijk_t = TX.lev[l].ijk.p;
@@ -675,28 +728,31 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             ft.base[d] = (l == 1) ? -1 : (int32_t)std::floor(-(corner[0][d] - corner[1][d]) / dl) - 5;
             LV.win_base[d] = ft.base[d];
         }
-        cnt_f.alloc(nbx + 1);
-        cnt_n.alloc(nbx + 1);
-        FFM_LAUNCH(k_list_count, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, pnear_ptr.p, pnear_src.p,
-                   TY.lev[l - 1].child.p, ft, cnt_f.p, cnt_n.p);
+        int64_t *cnt_f = SC.get<int64_t>(nbx + 1), *cnt_n = SC.get<int64_t>(nbx + 1);
+        FFM_LAUNCH(k_list_count, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, LP.near_ptr.p,
+                   LP.near_src.p, TY.lev[l - 1].child.p, ft, cnt_f, cnt_n);
         LV.far_ptr.alloc(nbx + 1);
         LV.near_ptr.alloc(nbx + 1);
-        exclusive_scan_i64(cnt_f.p, LV.far_ptr.p, nbx, st);
-        exclusive_scan_i64(cnt_n.p, LV.near_ptr.p, nbx, st);
-        LV.nfar = fetch(LV.far_ptr.p + nbx, st);
-        LV.nnear = fetch(LV.near_ptr.p + nbx, st);
+        exclusive_scan_i64(cnt_f, LV.far_ptr.p, nbx, st, SC);
+        exclusive_scan_i64(cnt_n, LV.near_ptr.p, nbx, st, SC);
+        int64_t tot[2];
+        FFM_HIP(hipMemcpyAsync(&tot[0], LV.far_ptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipMemcpyAsync(&tot[1], LV.near_ptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipStreamSynchronize(st));
+        LV.nfar = tot[0];
+        LV.nnear = tot[1];
         LV.far_src.alloc(LV.nfar);
         LV.far_cls.alloc(LV.nfar);
-        LV.near_src.alloc(LV.nnear);
-        FFM_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
-        FFM_HIP(hipMemsetAsync(win_used.p, 0, sizeof(int32_t) * kWin3, st));
-        FFM_LAUNCH(k_list_fill, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, pnear_ptr.p, pnear_src.p,
+        LV.near_src.alloc(std::max<int64_t>(LV.nnear, 1));
+        FFM_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+        FFM_HIP(hipMemsetAsync(win_used, 0, sizeof(int32_t) * kWin3, st));
+        FFM_LAUNCH(k_list_fill, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, LP.near_ptr.p, LP.near_src.p,
                    TY.lev[l - 1].child.p, ft, LV.far_ptr.p, LV.near_ptr.p, LV.far_src.p, LV.far_cls.p,
-                   LV.near_src.p, win_used.p, bad.p);
+                   LV.near_src.p, win_used, bad);
         std::vector<int32_t> used(kWin3);
         int hbad = 0;
-        FFM_HIP(hipMemcpyAsync(used.data(), win_used.p, sizeof(int32_t) * kWin3, hipMemcpyDeviceToHost, st));
-        FFM_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipMemcpyAsync(used.data(), win_used, sizeof(int32_t) * kWin3, hipMemcpyDeviceToHost, st));
+        FFM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
         FFM_HIP(hipStreamSynchronize(st));
         FFM_CHECK(!hbad, FFM_EINTERNAL, "ffm_plan: translation outside its window");
         // compact translation classes
@@ -711,33 +767,19 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 LV.cls_off.push_back(w % kWin + LV.win_base[2]);
             }
         if (LV.nfar) {
-            DevBuf<int32_t> dmap;
-            upload(dmap, map, st);
-            FFM_LAUNCH(k_remap, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, dmap.p);
-            FFM_HIP(hipStreamSynchronize(st));
+            int32_t *dmap = SC.get<int32_t>(kWin3);
+            FFM_HIP(hipMemcpyAsync(dmap, SC.stage(map), sizeof(int32_t) * kWin3, hipMemcpyHostToDevice, st));
+            FFM_LAUNCH(k_remap, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, dmap);
         }
-        // next level's parent lists are this level's near lists
-        pnear_ptr = std::move(LV.near_ptr);
-        pnear_src = std::move(LV.near_src);
-        LV.near_ptr = DevBuf<int64_t>();
-        LV.near_src = DevBuf<int32_t>();
         // stopping rule (Sec. 2.2.4)
         const int64_t nb = (int64_t)TX.lev[l].nbox + TY.lev[l].nbox;
-        const bool stop = LV.nnear == 0 || nx + ny <= (int64_t)P.opt.n_leaf * nb || l == maxlev;
-        if (stop) {
+        if (LV.nnear == 0 || nx + ny <= (int64_t)P.opt.n_leaf * nb || l == maxlev) {
             P.leaf = l;
-            LV.near_ptr = std::move(pnear_ptr);
-            LV.near_src = std::move(pnear_src);
             break;
         }
-        // keep the near lists of inner levels only for export
-        LV.near_ptr.alloc(nbx + 1);
-        LV.near_src.alloc(std::max<int64_t>(LV.nnear, 1));
-        FFM_HIP(hipMemcpyAsync(LV.near_ptr.p, pnear_ptr.p, sizeof(int64_t) * (nbx + 1), hipMemcpyDeviceToDevice, st));
-        if (LV.nnear)
-            FFM_HIP(hipMemcpyAsync(LV.near_src.p, pnear_src.p, sizeof(int32_t) * LV.nnear, hipMemcpyDeviceToDevice, st));
     }
 
+    plog.mark("lists");
     // --- compression form and tables per level (Sec. 2.2.2, 2.2.3)
     size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0;
     for (int l = 1; l <= P.leaf; ++l) {
@@ -749,6 +791,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             for (int d = 0; d < 3; ++d)
                 r0[3 * c + d] = (corner[0][d] - corner[1][d]) + (double)LV.cls_off[3 * c + d] * dl;
         const int32_t nby = TY.lev[l].nbox, nbx = TX.lev[l].nbox;
+        plog.mark("tab.start");
         const bool geg = P.kernel == FFM_HELMHOLTZ && P.k * dl >= P.opt.kd_switch;
         if (geg) {
             LV.method = kGegenbauer;
@@ -758,20 +801,25 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             LV.qG = LV.L >= 64 ? 4 : (LV.L >= 32 ? 2 : 0);
             LV.bwd_tile = LV.qG ? 512 : 256;
         }
-        build_work_lists(P, LV, TX.lev[l], TY.lev[l], false, st);
+        build_work_lists(P, LV, TX.lev[l], TY.lev[l], false, st, SC);
+        plog.mark("tab.work");
         if (geg) {
             const int L = LV.L, nth = L + 1, nph = 2 * L;
             LV.nq = 2 * (int64_t)L * (L + 1);
             LV.npair = LV.nq / 2;
             std::vector<double> xm, wm;
             gauss_legendre_host(nth, xm, wm);
-            std::vector<double> dirs, wts;
+            std::vector<double> dirs, wts, cph(2 * L), sph(2 * L);
             dirs.reserve(3 * LV.npair);
             wts.reserve(LV.npair);
+            for (int n = 0; n < 2 * L; ++n) {
+                cph[n] = std::cos(M_PI * n / L);
+                sph[n] = std::sin(M_PI * n / L);
+            }
             auto add = [&](int m, int n) {
-                const double ct = xm[m], stt = std::sqrt(1.0 - ct * ct), ph = M_PI * n / L;
-                dirs.push_back(stt * std::cos(ph));
-                dirs.push_back(stt * std::sin(ph));
+                const double ct = xm[m], stt = std::sqrt(1.0 - ct * ct);
+                dirs.push_back(stt * cph[n]);
+                dirs.push_back(stt * sph[n]);
                 dirs.push_back(ct);
                 wts.push_back(wm[m] * M_PI / L);
             };
@@ -787,17 +835,17 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 for (int d = 0; d < 3; ++d) dirs64[3 * q + d] = dirs[3 * q + d] * kr;
                 dirs32[q] = make_float4((float)dirs64[3 * q], (float)dirs64[3 * q + 1], (float)dirs64[3 * q + 2], 0.f);
             }
-            upload(LV.dirs, dirs32, st);
-            upload(LV.dirs64, dirs64, st);
+            upload(LV.dirs, dirs32, st, SC);
+            upload(LV.dirs64, dirs64, st, SC);
             // ring-pair tables: (sin, cos) of every ring pair's polar angle, scaled by k / 2pi, and the
             // azimuths of one half turn
             LV.nrp = nth / 2 + (nth & 1);
             std::vector<double2> rings(LV.nrp), phis(L);
             for (int m = 0; m < LV.nrp; ++m)
                 rings[m] = make_double2(std::sqrt(1.0 - xm[m] * xm[m]) * kr, xm[m] * kr);
-            for (int n = 0; n < L; ++n) phis[n] = make_double2(std::cos(M_PI * n / L), std::sin(M_PI * n / L));
-            upload(LV.rings, rings, st);
-            upload(LV.phis, phis, st);
+            for (int n = 0; n < L; ++n) phis[n] = make_double2(cph[n], sph[n]);
+            upload(LV.rings, rings, st, SC);
+            upload(LV.phis, phis, st, SC);
             // FP64 phase reduction where the FP32 rounding of the largest phase (a few ulp of
             // k sqrt(3) d_l / 2 radians) would reach eps / 20; the per-(point, ring) factor e^{iC} of
             // the ring-pair form is always reduced in FP64
@@ -818,10 +866,21 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             // per-class series coefficients (host FP64), unit directions r0/|r0|
             std::vector<double> rhat(3 * (size_t)LV.ncls);
             std::vector<double2> coef((size_t)LV.ncls * (L + 1));
+            // the series coefficients depend on |r0| only: one Hankel recurrence per distinct norm
             std::vector<std::complex<double>> h;
+            std::vector<std::pair<double, int>> seen;   // (|r0|, first class with that norm)
             for (int c = 0; c < LV.ncls; ++c) {
                 const double rn = std::sqrt(r0[3 * c] * r0[3 * c] + r0[3 * c + 1] * r0[3 * c + 1] + r0[3 * c + 2] * r0[3 * c + 2]);
                 for (int d = 0; d < 3; ++d) rhat[3 * c + d] = r0[3 * c + d] / rn;
+                int same = -1;
+                for (const auto &sn : seen)
+                    if (sn.first == rn) same = sn.second;
+                if (same >= 0) {
+                    std::copy(coef.begin() + (size_t)same * (L + 1), coef.begin() + (size_t)(same + 1) * (L + 1),
+                              coef.begin() + (size_t)c * (L + 1));
+                    continue;
+                }
+                seen.emplace_back(rn, c);
                 hankel_host(L, P.k * rn, h);
                 std::complex<double> ip(1, 0);
                 for (int p = 0; p <= L; ++p) {
@@ -830,18 +889,15 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     ip *= std::complex<double>(0, 1);
                 }
             }
-            DevBuf<double> ddirs, dwts, drhat;
-            DevBuf<double2> dcoef;
-            upload(ddirs, dirs, st);
-            upload(dwts, wts, st);
-            upload(drhat, rhat, st);
-            upload(dcoef, coef, st);
+            plog.mark("tab.host");
+            const double *ddirs = keep(SC, dirs, st), *dwts = keep(SC, wts, st), *drhat = keep(SC, rhat, st);
+            const double2 *dcoef = keep(SC, coef, st);
             LV.D.alloc((size_t)LV.ncls * LV.npair);
             dim3 grid((unsigned)nblocks(LV.npair), (unsigned)LV.ncls);
-            hipLaunchKernelGGL(k_gegen_D, grid, dim3(kThreads), 2 * sizeof(double2) * (L + 1), st, LV.npair, L, ddirs.p,
-                               dwts.p, drhat.p, dcoef.p, P.k, LV.D.p);
+            hipLaunchKernelGGL(k_gegen_D, grid, dim3(kThreads), 2 * sizeof(double2) * (L + 1), st, LV.npair, L, ddirs,
+                               dwts, drhat, dcoef, P.k, LV.D.p);
             FFM_HIP(hipGetLastError());
-            FFM_HIP(hipStreamSynchronize(st));
+            plog.mark("tab.D");
             ws_src = std::max(ws_src, (size_t)nby * LV.npair);
             ws_tgt = std::max(ws_tgt, (size_t)nbx * LV.npair);
         } else {
@@ -860,16 +916,28 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 nf[a] = (float)nodes[a];
                 df[a] = (float)(1.0 / den);
             }
-            upload(LV.lnodes, nf, st);
-            upload(LV.lden, df, st);
+            upload(LV.lnodes, nf, st, SC);
+            upload(LV.lden, df, st, SC);
             DevBuf<double> dnodes, dr0;
-            upload(dnodes, nodes, st);
-            upload(dr0, r0, st);
+            upload(dnodes, nodes, st, SC);
+            upload(dr0, r0, st, SC);
             const int helm = P.kernel == FFM_HELMHOLTZ ? 1 : 0;
             const int64_t per = (int64_t)LV.rp * LV.rp;
             LV.T.alloc((size_t)per * LV.ncls * (helm ? 2 : 1));
             FFM_LAUNCH(k_lagrange_T, nblocks(per * LV.ncls), kThreads, 0, st, LV.ncls, dr0.p, LV.r1, LV.rp, dnodes.p,
                        0.5 * dl, helm, P.k, LV.T.p);
+            // mixed precision: FP16 transfers where the FP16 rounding (2^-11 relative, twice that for the
+            // oscillatory complex kernel) stays within eps; |T| <= 1 / (4 pi d_l) is scaled to <= 1
+            const double cond = helm ? 2.0 : 1.0;
+            LV.fp16 = P.opt.precision == FFM_PREC_MIXED && std::ldexp(1.0, -11) * cond <= P.eps;
+            if (LV.fp16) {
+                LV.sT = (float)std::ldexp(1.0, (int)std::floor(std::log2(4.0 * M_PI * dl)));
+                const int64_t planes = (int64_t)LV.ncls * (helm ? 2 : 1);
+                LV.T16.alloc((size_t)per * planes);
+                FFM_LAUNCH(k_to_half, nblocks(per * planes), kThreads, 0, st, LV.T.p, planes, LV.rp, LV.sT,
+                           LV.T16.p);
+                P.any_fp16 = true;
+            }
             // class groups of 16 pairs for the MFMA transfer
             DevBuf<int32_t> cnt(LV.ncls), cursor(LV.ncls);
             FFM_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * LV.ncls, st));
@@ -886,8 +954,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             }
             LV.ngrp = g;
             DevBuf<int32_t> dgs;
-            upload(dgs, gstart, st);
-            upload(LV.grp_cls, gcls, st);
+            upload(dgs, gstart, st, SC);
+            upload(LV.grp_cls, gcls, st, SC);
             LV.grp_pair.alloc((size_t)16 * std::max(g, 1));
             FFM_HIP(hipMemsetAsync(LV.grp_pair.p, 0xff, sizeof(int32_t) * 16 * std::max(g, 1), st));
             FFM_HIP(hipMemsetAsync(cursor.p, 0, sizeof(int32_t) * LV.ncls, st));
@@ -898,7 +966,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             ws_z = std::max(ws_z, (size_t)LV.nfar * LV.rp);
         }
     }
-    build_work_lists(P, P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st);
+    plog.mark("tables");
+    build_work_lists(P, P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC);
     P.ws_src = ws_src;
     P.ws_tgt = ws_tgt;
     P.ws_z = ws_z;
@@ -909,7 +978,9 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.wsrc.alloc(ws_src);
     P.wtgt.alloc(ws_tgt);
     P.wz.alloc(ws_z);
+    if (P.any_fp16) P.amax.alloc(1);
     FFM_HIP(hipStreamSynchronize(st));
+    plog.mark("workspace");
 
     // --- statistics
     ffm_stats_t &s = P.stats;
@@ -935,6 +1006,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.nq[l] = LV.nq;
         s.fwd_points[l] = LV.pts_src;
         s.tform[l] = LV.method == kGegenbauer ? (LV.qG ? 2 : 1) : 0;
+        s.prec[l] = LV.fp16 ? 1 : 0;
         s.bwd_points[l] = LV.pts_tgt;
         if (LV.method == kGegenbauer) {
             s.transform_terms += (LV.pts_src + LV.pts_tgt) * (double)LV.nq;
@@ -962,7 +1034,7 @@ size_t plan_device_bytes(const Plan &P) {
         b += L.far_ptr.bytes() + L.near_ptr.bytes() + L.far_src.bytes() + L.far_cls.bytes() + L.near_src.bytes() +
              L.T.bytes() + L.grp_pair.bytes() + L.grp_cls.bytes() + L.dirs.bytes() + L.dirs64.bytes() + L.D.bytes() +
              L.lnodes.bytes() + L.lden.bytes() + L.fwd_boxes.bytes() + L.tgt_boxes.bytes() + L.bwd_work.bytes() +
-             L.near_boxes.bytes() + L.rings.bytes() + L.phis.bytes();
+             L.near_boxes.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes();
     return b;

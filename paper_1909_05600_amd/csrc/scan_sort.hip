@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const T *in, T *out
 }
 
 template <class T>
-void exclusive_scan(const T *in, T *out, int64_t n, hipStream_t st) {
+void exclusive_scan(const T *in, T *out, int64_t n, hipStream_t st, Scratch &S) {
     if (n <= 0) {
         FFM_HIP(hipMemsetAsync(out, 0, sizeof(T), st));
         return;
@@ -83,12 +83,10 @@ void exclusive_scan(const T *in, T *out, int64_t n, hipStream_t st) {
         FFM_LAUNCH(k_scan_apply<T>, 1, kScanThreads, 0, st, in, out, n, (const T *)nullptr);
         return;
     }
-    DevBuf<T> bsum(nb + 1), boff(nb + 1);
-    FFM_LAUNCH(k_scan_reduce<T>, nb, kScanThreads, 0, st, in, n, bsum.p);
-    exclusive_scan<T>(bsum.p, boff.p, nb, st);
-    FFM_LAUNCH(k_scan_apply<T>, nb, kScanThreads, 0, st, in, out, n, (const T *)boff.p);
-    // the temporaries are released only after the stream has consumed them
-    FFM_HIP(hipStreamSynchronize(st));
+    T *bsum = S.get<T>(nb + 1), *boff = S.get<T>(nb + 1);
+    FFM_LAUNCH(k_scan_reduce<T>, nb, kScanThreads, 0, st, in, n, bsum);
+    exclusive_scan<T>(bsum, boff, nb, st, S);
+    FFM_LAUNCH(k_scan_apply<T>, nb, kScanThreads, 0, st, in, out, n, (const T *)boff);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -161,32 +159,31 @@ k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *v
 
 }  // namespace
 
-void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
-    exclusive_scan<int64_t>(in, out, n, st);
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st, Scratch &S) {
+    exclusive_scan<int64_t>(in, out, n, st, S);
 }
-void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) {
-    exclusive_scan<int32_t>(in, out, n, st);
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st, Scratch &S) {
+    exclusive_scan<int32_t>(in, out, n, st, S);
 }
 
-void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st) {
+void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st, Scratch &S) {
     if (n <= 1) return;
     FFM_CHECK(n < (int64_t(1) << 31), FFM_EINVAL, "radix sort: too many keys");
     const int nblk = (int)((n + kRsTile - 1) / kRsTile);
-    DevBuf<uint64_t> k2(n);
-    DevBuf<int32_t> v2(n);
-    DevBuf<int32_t> counts((size_t)256 * nblk + 1), offs((size_t)256 * nblk + 1);
-    uint64_t *ka = keys, *kb = k2.p;
-    int32_t *va = vals, *vb = v2.p;
+    uint64_t *k2 = S.get<uint64_t>(n);
+    int32_t *v2 = S.get<int32_t>(n);
+    int32_t *counts = S.get<int32_t>((size_t)256 * nblk + 1), *offs = S.get<int32_t>((size_t)256 * nblk + 1);
+    uint64_t *ka = keys, *kb = k2;
+    int32_t *va = vals, *vb = v2;
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
-        FFM_LAUNCH(k_rs_hist, nblk, kRsThreads, 0, st, ka, n, shift, counts.p, nblk);
-        exclusive_scan<int32_t>(counts.p, offs.p, (int64_t)256 * nblk, st);
-        FFM_LAUNCH(k_rs_scatter, nblk, kRsThreads, 0, st, ka, va, kb, vb, n, shift, offs.p, nblk);
+        FFM_LAUNCH(k_rs_hist, nblk, kRsThreads, 0, st, ka, n, shift, counts, nblk);
+        exclusive_scan<int32_t>(counts, offs, (int64_t)256 * nblk, st, S);
+        FFM_LAUNCH(k_rs_scatter, nblk, kRsThreads, 0, st, ka, va, kb, vb, n, shift, offs, nblk);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
     // eight passes: the result is back in (keys, vals)
-    FFM_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace ffm

@@ -1,7 +1,12 @@
 """Helpers shared by the GPU tests: device upload, the HIP plan, comparisons with the oracle."""
 import numpy as np
 
-RTOL_FFM = {0: 2e-5, 1: 1e-4}   # |v_gpu - v_oracle| / |v_oracle| (FP32 path vs FP64 oracle, same parameters)
+# |v_gpu - v_oracle| / |v_oracle| for the FP32 path against the FP64 oracle with identical parameters.
+# Derivation: every stage rounds to FP32 (2^-24 = 6e-8 relative) and sums O(10^2..10^4) terms, giving
+# ~sqrt(n) 6e-8 ~ 1e-6..6e-6 relative per stage; FP32 in-plane phases of up to ~12 revolutions add
+# ~12 * 2^-24 * 2 pi ~ 5e-6 rad on the Helmholtz levels; the Gegenbauer diagonal amplifies FP32 rounding
+# by its cancellation factor (~10 at the leaf level).  Laplace: 2e-5; Helmholtz: 1e-4.
+RTOL_FFM = {0: 2e-5, 1: 1e-4}
 
 
 def rel(a, b):
