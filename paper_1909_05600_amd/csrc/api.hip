@@ -236,6 +236,7 @@ ffm_status_t ffm_destroy(ffm_plan_t plan) {
     }
     return (ffm_status_t)Guard::run([&] {
         if (plan->P.done) (void)hipEventDestroy(plan->P.done);
+        if (plan->P.hio) pinned_free(plan->P.hio);
         for (auto e : plan->P.tev)
             if (e) (void)hipEventDestroy(e);
         delete plan;

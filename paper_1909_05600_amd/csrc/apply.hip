@@ -4,8 +4,10 @@
 // Gegenbauer levels, eqs. gegenbauerQuadrature and the three products that follow it), Sec. 2.2.4 (dense
 // remainder), remark closing Sec. 2.2.3 (transforms evaluated on the fly at every level, no upward pass).
 //
+// Every kernel reads its parameters from the level descriptor named by its work item (int4, .x =
+// descriptor), so one launch serves one level of one plan or the same step of many plans (a batch).
 // Every output element is owned by exactly one thread of each kernel and accumulated in a fixed order,
-// so results are bitwise reproducible run to run.
+// so results are bitwise reproducible and independent of how work items are grouped into launches.
 #include "common.h"
 
 #include <algorithm>
@@ -16,9 +18,9 @@ namespace ffm {
 namespace {
 
 constexpr int kThreads = 256;
-inline int nblocks(int64_t n, int per = kThreads) { return (int)((n + per - 1) / per); }
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 
 // sin(2 pi x), cos(2 pi x) for x in revolutions, x already reduced to [0, 1)
 __device__ __forceinline__ void sincos_rev(float x, float &s, float &c) {
@@ -26,45 +28,79 @@ __device__ __forceinline__ void sincos_rev(float x, float &s, float &c) {
     c = __builtin_amdgcn_cosf(x);
 }
 
-// ------------------------------------------------------------------ permutations
+// ------------------------------------------------------------------ permutations and scaling
+// item (desc, first index): u[i] = wu[perm_y[i]] for i < ny, v[i] = 0 for i < nx (256 per block)
 __global__ void __launch_bounds__(kThreads)
-k_perm_in(const void *wu, int dtype, const int32_t *perm, int64_t n, float2 *out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t j = perm[i];
-    float2 r;
-    switch (dtype) {
-        case FFM_C64: r = static_cast<const float2 *>(wu)[j]; break;
-        case FFM_F32: r = make_float2(static_cast<const float *>(wu)[j], 0.f); break;
-        case FFM_F64: r = make_float2((float)static_cast<const double *>(wu)[j], 0.f); break;
-        default: {
-            const double2 d = static_cast<const double2 *>(wu)[j];
-            r = make_float2((float)d.x, (float)d.y);
+k_perm_in(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const IoEntry e = io[d.inst];
+    const int64_t i = (int64_t)wk.y + threadIdx.x;
+    if (i < d.ny) {
+        const int64_t j = d.perm_y[i];
+        float2 r;
+        switch (e.dtype) {
+            case FFM_C64: r = static_cast<const float2 *>(e.wu)[j]; break;
+            case FFM_F32: r = make_float2(static_cast<const float *>(e.wu)[j], 0.f); break;
+            case FFM_F64: r = make_float2((float)static_cast<const double *>(e.wu)[j], 0.f); break;
+            default: {
+                const double2 w = static_cast<const double2 *>(e.wu)[j];
+                r = make_float2((float)w.x, (float)w.y);
+            }
         }
+        d.u[i] = r;
     }
-    out[i] = r;
+    if (i < d.nx) d.v[i] = make_float2(0.f, 0.f);
 }
 
+// max over |Re u|, |Im u| (non-negative floats compare as their bit patterns); item (desc, first index),
+// 4096 entries per block.  The maximum is zeroed by the stage before (k_zero_amax).
 __global__ void __launch_bounds__(kThreads)
-k_perm_out(const float2 *vs, const int32_t *perm, int64_t n, float2 *v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[perm[i]] = vs[i];
+k_amax(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    float m = 0.f;
+    const int64_t end = min<int64_t>(d.ny, (int64_t)wk.y + 16 * kThreads);
+    for (int64_t i = (int64_t)wk.y + threadIdx.x; i < end; i += kThreads)
+        m = fmaxf(m, fmaxf(fabsf(d.u[i].x), fabsf(d.u[i].y)));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(reinterpret_cast<unsigned int *>(d.amax), __float_as_uint(m));
 }
 
-// ------------------------------------------------------------------ Gegenbauer levels
-// Forward transform u~_s(q) = sum_{j in s} e^{-ik s_q.(y_j - c_s)} u_j for an antipodal pair
-// (q, -q): with S = sum cos(th) u, T = sum sin(th) u, u~(q) = S - iT and u~(-q) = S + iT.
-// Block: one source box and 256*PPT direction pairs; the box's points stream through LDS.
+// item (desc, 0): zero the instance's max |u| (a kernel, not a memset, so the apply can be captured)
+__global__ void k_zero_amax(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    if (threadIdx.x == 0) *descs[wk.x].amax = 0.f;
+}
+
+// v[i] = 0 (empty plans: no sources or no targets)
+__global__ void __launch_bounds__(kThreads) k_zero_out(float2 *v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) v[i] = make_float2(0.f, 0.f);
+}
+
+// item (desc, first index): vout[perm_x[i]] = v[i]
+__global__ void __launch_bounds__(kThreads)
+k_perm_out(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int64_t i = (int64_t)wk.y + threadIdx.x;
+    if (i < d.nx) io[d.inst].vout[d.perm_x[i]] = d.v[i];
+}
+
+// ------------------------------------------------------------------ Gegenbauer levels, direction pairs
+// Forward transform u~_s(q) = sum_{j in s} e^{-ik s_q.(y_j - c_s)} u_j for an antipodal pair (q, -q): with
+// S = sum cos(th) u, T = sum sin(th) u, u~(q) = S - iT and u~(-q) = S + iT.
+// Item (desc, source box, tile of 256 PPT pairs); the box's points stream through LDS.
 template <int PPT, bool P64>
 __global__ void __launch_bounds__(kThreads)
-k_pw_forward(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
-             const float2 *__restrict__ u, const int32_t *__restrict__ start, const double *__restrict__ ctr,
-             const int32_t *__restrict__ boxes, const float4 *__restrict__ dirs, const double *__restrict__ dirs64,
-             int64_t npair, int ntile, float4 *__restrict__ out) {
-    const int b = boxes[blockIdx.x / ntile];
-    const int tile = blockIdx.x % ntile;
+k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int b = wk.y;
     const int tid = threadIdx.x;
-    const int64_t p0 = (int64_t)tile * kThreads * PPT + tid;
+    const int64_t npair = d.npair;
+    const int64_t p0 = (int64_t)wk.z * kThreads * PPT + tid;
     typedef typename std::conditional<P64, double, float>::type real;
     real sx[PPT], sy[PPT], sz[PPT];
     float Sre[PPT], Sim[PPT], Tre[PPT], Tim[PPT];
@@ -73,26 +109,26 @@ k_pw_forward(const double *__restrict__ xs, const double *__restrict__ ys, const
         const int64_t p = p0 + (int64_t)j * kThreads;
         const int64_t pc = p < npair ? p : npair - 1;
         if (P64) {
-            sx[j] = dirs64[3 * pc]; sy[j] = dirs64[3 * pc + 1]; sz[j] = dirs64[3 * pc + 2];
+            sx[j] = d.dirs64[3 * pc]; sy[j] = d.dirs64[3 * pc + 1]; sz[j] = d.dirs64[3 * pc + 2];
         } else {
-            const float4 d = dirs[pc];
-            sx[j] = d.x; sy[j] = d.y; sz[j] = d.z;
+            const float4 q = d.dirs[pc];
+            sx[j] = q.x; sy[j] = q.y; sz[j] = q.z;
         }
         Sre[j] = Sim[j] = Tre[j] = Tim[j] = 0.f;
     }
-    const double cx = ctr[3 * b], cy = ctr[3 * b + 1], cz = ctr[3 * b + 2];
+    const double cx = d.sctr[3 * b], cy = d.sctr[3 * b + 1], cz = d.sctr[3 * b + 2];
     __shared__ real px[kThreads], py[kThreads], pz[kThreads];
     __shared__ float2 us[kThreads];
-    const int i0 = start[b], i1 = start[b + 1];
+    const int i0 = d.sstart[b], i1 = d.sstart[b + 1];
     for (int s0 = i0; s0 < i1; s0 += kThreads) {
         const int cnt = min(kThreads, i1 - s0);
         __syncthreads();
         if (tid < cnt) {
             const int i = s0 + tid;
-            px[tid] = (real)(xs[i] - cx);
-            py[tid] = (real)(ys[i] - cy);
-            pz[tid] = (real)(zs[i] - cz);
-            us[tid] = u[i];
+            px[tid] = (real)(d.sxs[i] - cx);
+            py[tid] = (real)(d.sys[i] - cy);
+            pz[tid] = (real)(d.szs[i] - cz);
+            us[tid] = d.u[i];
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; ++jj) {
@@ -102,10 +138,10 @@ k_pw_forward(const double *__restrict__ xs, const double *__restrict__ ys, const
             for (int j = 0; j < PPT; ++j) {
                 float f;
                 if (P64) {
-                    const double ph = fma(sx[j], x, fma(sy[j], y, (double)sz[j] * z));
+                    const double ph = fma((double)sx[j], (double)x, fma((double)sy[j], (double)y, (double)sz[j] * z));
                     f = (float)__builtin_amdgcn_fract(ph);
                 } else {
-                    const float ph = fmaf(sx[j], x, fmaf(sy[j], y, (float)sz[j] * z));
+                    const float ph = fmaf((float)sx[j], (float)x, fmaf((float)sy[j], (float)y, (float)sz[j] * (float)z));
                     f = __builtin_amdgcn_fractf(ph);
                 }
                 float sn, cs;
@@ -121,79 +157,81 @@ k_pw_forward(const double *__restrict__ xs, const double *__restrict__ ys, const
     for (int j = 0; j < PPT; ++j) {
         const int64_t p = p0 + (int64_t)j * kThreads;
         if (p < npair)
-            out[(int64_t)b * npair + p] = make_float4(Sre[j] + Tim[j], Sim[j] - Tre[j], Sre[j] - Tim[j], Sim[j] + Tre[j]);
+            d.ut[(int64_t)b * npair + p] = make_float4(Sre[j] + Tim[j], Sim[j] - Tre[j], Sre[j] - Tim[j], Sim[j] + Tre[j]);
     }
 }
 
 // Diagonal transfer v~_t(q) = sum_{s in far(t)} D_{c(t,s)}(q) u~_s(q) (both directions of a pair).
+// Item (desc, target box, tile of 256 PPT pairs).
 template <int PPT>
 __global__ void __launch_bounds__(kThreads)
-k_pw_transfer(const int32_t *__restrict__ tboxes, const int64_t *__restrict__ far_ptr,
-              const int32_t *__restrict__ far_src, const int32_t *__restrict__ far_cls, const float4 *__restrict__ D,
-              const float4 *__restrict__ ut, int64_t npair, int ntile, float4 *__restrict__ vt) {
-    const int t = tboxes[blockIdx.x / ntile];
-    const int tile = blockIdx.x % ntile;
-    const int64_t p0 = (int64_t)tile * kThreads * PPT + threadIdx.x;
+k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
+    const int64_t npair = d.npair;
+    const int64_t p0 = (int64_t)wk.z * kThreads * PPT + threadIdx.x;
     float4 acc[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int64_t e0 = far_ptr[t], e1 = far_ptr[t + 1];
+    const int64_t e0 = d.far_ptr[t], e1 = d.far_ptr[t + 1];
+    const float4 *__restrict__ D = d.D;
+    const float4 *__restrict__ ut = d.ut;
     for (int64_t e = e0; e < e1; ++e) {
-        const int64_t s = far_src[e], c = far_cls[e];
+        const int64_t s = d.far_src[e], c = d.far_cls[e];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int64_t p = p0 + (int64_t)j * kThreads;
             if (p < npair) {
-                const float4 d = D[c * npair + p];
+                const float4 q = D[c * npair + p];
                 const float4 w = ut[s * npair + p];
-                acc[j].x = fmaf(d.x, w.x, fmaf(-d.y, w.y, acc[j].x));
-                acc[j].y = fmaf(d.x, w.y, fmaf(d.y, w.x, acc[j].y));
-                acc[j].z = fmaf(d.z, w.z, fmaf(-d.w, w.w, acc[j].z));
-                acc[j].w = fmaf(d.z, w.w, fmaf(d.w, w.z, acc[j].w));
+                acc[j].x = fmaf(q.x, w.x, fmaf(-q.y, w.y, acc[j].x));
+                acc[j].y = fmaf(q.x, w.y, fmaf(q.y, w.x, acc[j].y));
+                acc[j].z = fmaf(q.z, w.z, fmaf(-q.w, w.w, acc[j].z));
+                acc[j].w = fmaf(q.z, w.w, fmaf(q.w, w.z, acc[j].w));
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int64_t p = p0 + (int64_t)j * kThreads;
-        if (p < npair) vt[(int64_t)t * npair + p] = acc[j];
+        if (p < npair) d.vt[(int64_t)t * npair + p] = acc[j];
     }
 }
 
-// Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q)
-// and B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Thread per target point.
+// Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q) and
+// B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Item (desc, target box, first point).
 template <bool P64>
 __global__ void __launch_bounds__(kThreads)
-k_pw_backward(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
-              const int32_t *__restrict__ start, const double *__restrict__ ctr, const int2 *__restrict__ work,
-              const float4 *__restrict__ dirs, const double *__restrict__ dirs64, const float4 *__restrict__ vt,
-              int64_t npair, float2 *__restrict__ v) {
-    const int2 wk = work[blockIdx.x];
-    const int t = wk.x;
+k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
     const int tid = threadIdx.x;
-    const int i = wk.y + tid;
-    const bool valid = i < start[t + 1];
+    const int i = wk.z + tid;
+    const bool valid = i < d.tstart[t + 1];
+    const int64_t npair = d.npair;
     typedef typename std::conditional<P64, double, float>::type real;
     real x = 0, y = 0, z = 0;
     if (valid) {
-        x = (real)(xs[i] - ctr[3 * t]);
-        y = (real)(ys[i] - ctr[3 * t + 1]);
-        z = (real)(zs[i] - ctr[3 * t + 2]);
+        x = (real)(d.txs[i] - d.tctr[3 * t]);
+        y = (real)(d.tys[i] - d.tctr[3 * t + 1]);
+        z = (real)(d.tzs[i] - d.tctr[3 * t + 2]);
     }
     float are = 0.f, aim = 0.f;
     __shared__ real sdx[kThreads], sdy[kThreads], sdz[kThreads];
     __shared__ float4 ab[kThreads];
-    const float4 *vb = vt + (int64_t)t * npair;
+    const float4 *vb = d.vt + (int64_t)t * npair;
     for (int64_t q0 = 0; q0 < npair; q0 += kThreads) {
         const int cnt = (int)min<int64_t>(kThreads, npair - q0);
         __syncthreads();
         if (tid < cnt) {
             const int64_t q = q0 + tid;
             if (P64) {
-                sdx[tid] = dirs64[3 * q]; sdy[tid] = dirs64[3 * q + 1]; sdz[tid] = dirs64[3 * q + 2];
+                sdx[tid] = d.dirs64[3 * q]; sdy[tid] = d.dirs64[3 * q + 1]; sdz[tid] = d.dirs64[3 * q + 2];
             } else {
-                const float4 d = dirs[q];
-                sdx[tid] = d.x; sdy[tid] = d.y; sdz[tid] = d.z;
+                const float4 w = d.dirs[q];
+                sdx[tid] = w.x; sdy[tid] = w.y; sdz[tid] = w.z;
             }
             const float4 w = vb[q];
             ab[tid] = make_float4(w.x + w.z, w.y + w.w, w.x - w.z, w.y - w.w);
@@ -202,10 +240,10 @@ k_pw_backward(const double *__restrict__ xs, const double *__restrict__ ys, cons
         for (int jj = 0; jj < cnt; ++jj) {
             float f;
             if (P64) {
-                const double ph = fma((double)sdx[jj], x, fma((double)sdy[jj], y, (double)sdz[jj] * z));
+                const double ph = fma((double)sdx[jj], (double)x, fma((double)sdy[jj], (double)y, (double)sdz[jj] * z));
                 f = (float)__builtin_amdgcn_fract(ph);
             } else {
-                const float ph = fmaf((float)sdx[jj], x, fmaf((float)sdy[jj], y, (float)sdz[jj] * z));
+                const float ph = fmaf((float)sdx[jj], (float)x, fmaf((float)sdy[jj], (float)y, (float)sdz[jj] * (float)z));
                 f = __builtin_amdgcn_fractf(ph);
             }
             float sn, cs;
@@ -216,13 +254,12 @@ k_pw_backward(const double *__restrict__ xs, const double *__restrict__ ys, cons
         }
     }
     if (valid) {
-        float2 o = v[i];
+        float2 o = d.v[i];
         o.x += are;
         o.y += aim;
-        v[i] = o;
+        d.v[i] = o;
     }
 }
-
 
 // ------------------------------------------------------------------ Gegenbauer levels, ring-pair form
 // The quadrature's directions (sin t_m cos f_n, sin t_m sin f_n, cos t_m) of ring m and its antipodal
@@ -237,18 +274,17 @@ k_pw_backward(const double *__restrict__ xs, const double *__restrict__ ys, cons
 constexpr int kRingChunk = 64;
 constexpr int kMaxRings = 16;
 
+// Item (desc, source box, ring chunk, point segment); Tr threads per ring, R rings per block.
 template <int G, bool P64>
 __global__ void __launch_bounds__(kThreads)
-k_pw_forward_rings(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
-                   const float2 *__restrict__ u, const int32_t *__restrict__ start, const double *__restrict__ ctr,
-                   const int32_t *__restrict__ boxes, const double2 *__restrict__ rings,
-                   const double2 *__restrict__ phis, int L, int nrp, int Tr, int R, int nchunk, int nsplit,
-                   int64_t npair, float4 *__restrict__ out, int64_t split_stride) {
+k_pw_forward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     typedef typename std::conditional<P64, double, float>::type real;
-    const int work = blockIdx.x / nsplit, seg = blockIdx.x % nsplit;
-    const int bi = work / nchunk;
-    const int b = boxes[bi];
-    const int m0 = (work % nchunk) * R;
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int b = wk.y;
+    const int L = d.L, nrp = d.nrp, Tr = d.Tr, R = d.R, nsplit = d.nsplit, seg = wk.w;
+    const int64_t npair = d.npair;
+    const int m0 = wk.z * R;
     const int tid = threadIdx.x;
     const int rl = tid / Tr, nloc = tid % Tr;
     const int m = m0 + rl;
@@ -259,16 +295,16 @@ k_pw_forward_rings(const double *__restrict__ xs, const double *__restrict__ ys,
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         const int n = min(nloc + j * Tr, L - 1);
-        cf[j] = (real)phis[n].x;
-        sf[j] = (real)phis[n].y;
+        cf[j] = (real)d.phis[n].x;
+        sf[j] = (real)d.phis[n].y;
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[j][q] = 0.f;
     }
-    const double cx = ctr[3 * b], cy = ctr[3 * b + 1], cz = ctr[3 * b + 2];
+    const double cx = d.sctr[3 * b], cy = d.sctr[3 * b + 1], cz = d.sctr[3 * b + 2];
     __shared__ real sA[kMaxRings][kRingChunk], sB[kMaxRings][kRingChunk];
     __shared__ float4 sU[kMaxRings][kRingChunk];
     // this block's segment of the box's points
-    const int b0 = start[b], b1 = start[b + 1];
+    const int b0 = d.sstart[b], b1 = d.sstart[b + 1];
     const int per = (b1 - b0 + nsplit - 1) / nsplit;
     const int i0 = b0 + seg * per, i1 = min(b1, i0 + per);
     for (int s0 = i0; s0 < i1; s0 += kRingChunk) {
@@ -276,14 +312,14 @@ k_pw_forward_rings(const double *__restrict__ xs, const double *__restrict__ ys,
         __syncthreads();
         for (int it = tid; it < nr * cnt; it += kThreads) {
             const int r = it / cnt, j = it % cnt, i = s0 + j;
-            const double2 rg = rings[m0 + r];
-            const double xr = xs[i] - cx, yr = ys[i] - cy, zr = zs[i] - cz;
+            const double2 rg = d.rings[m0 + r];
+            const double xr = d.sxs[i] - cx, yr = d.sys[i] - cy, zr = d.szs[i] - cz;
             sA[r][j] = (real)(rg.x * xr);
             sB[r][j] = (real)(rg.x * yr);
             const double C = rg.y * zr;
             float sn, cs;
             sincos_rev((float)(C - floor(C)), sn, cs);
-            const float2 uu = u[i];
+            const float2 uu = d.u[i];
             sU[r][j] = make_float4(uu.x * cs + uu.y * sn, uu.y * cs - uu.x * sn, uu.x * cs - uu.y * sn,
                                    uu.y * cs + uu.x * sn);
         }
@@ -318,7 +354,7 @@ k_pw_forward_rings(const double *__restrict__ xs, const double *__restrict__ ys,
     }
     if (!active) return;
     const bool equator = 2 * m == L;
-    float4 *o = out + (int64_t)seg * split_stride + (int64_t)b * npair + (int64_t)m * 2 * L;
+    float4 *o = (nsplit > 1 ? d.part + (int64_t)seg * d.part_stride : d.ut) + (int64_t)b * npair + (int64_t)m * 2 * L;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         const int n = nloc + j * Tr;
@@ -337,54 +373,54 @@ k_pw_forward_rings(const double *__restrict__ xs, const double *__restrict__ ys,
     }
 }
 
-// Sum the point-segment partials of the forward transform in segment order.
+// Sum the point-segment partials of the forward transform in segment order.  Item (desc, source box).
 __global__ void __launch_bounds__(kThreads)
-k_sum_segments(const float4 *__restrict__ part, const int32_t *__restrict__ boxes, int64_t npair, int nsplit,
-               int64_t split_stride, float4 *__restrict__ out) {
-    const int b = boxes[blockIdx.y];
-    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < npair; p += (int64_t)gridDim.x * kThreads) {
-        const int64_t o = (int64_t)b * npair + p;
-        float4 a = part[o];
-        for (int s = 1; s < nsplit; ++s) {
-            const float4 w = part[(int64_t)s * split_stride + o];
+k_sum_segments(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int64_t npair = d.npair;
+    for (int64_t p = threadIdx.x; p < npair; p += kThreads) {
+        const int64_t o = (int64_t)wk.y * npair + p;
+        float4 a = d.part[o];
+        for (int s = 1; s < d.nsplit; ++s) {
+            const float4 w = d.part[(int64_t)s * d.part_stride + o];
             a.x += w.x; a.y += w.y; a.z += w.z; a.w += w.w;
         }
-        out[o] = a;
+        d.ut[o] = a;
     }
 }
 
 // Backward transform in ring-pair form: per target point and ring pair m,
 //   v += e^{iC} sum_n [e^{iP} v~(m,n) + e^{-iP} v~(m,n+L)] + e^{-iC} sum_n [e^{iP} v~(L-m,n) + e^{-iP} v~(L-m,n+L)]
-// Two target points per thread.
-template <bool P64>
+// PT target points per thread; item (desc, target box, first point).
+template <int PT, bool P64>
 __global__ void __launch_bounds__(kThreads)
-k_pw_backward_rings(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
-                    const int32_t *__restrict__ start, const double *__restrict__ ctr, const int2 *__restrict__ work,
-                    const double2 *__restrict__ rings, const double2 *__restrict__ phis, int L, int nrp,
-                    const float4 *__restrict__ vt, int64_t npair, float2 *__restrict__ v) {
+k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     typedef typename std::conditional<P64, double, float>::type real;
-    constexpr int PT = 2;
-    const int2 wk = work[blockIdx.x];
-    const int t = wk.x;
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
     const int tid = threadIdx.x;
-    const int iend = start[t + 1];
+    const int L = d.L, nrp = d.nrp;
+    const int64_t npair = d.npair;
+    const int iend = d.tstart[t + 1];
     double xr[PT], yr[PT], zr[PT];
     bool valid[PT];
     float vr[PT], vi[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        const int i = wk.y + tid + q * kThreads;
+        const int i = wk.z + tid + q * kThreads;
         valid[q] = i < iend;
-        xr[q] = valid[q] ? xs[i] - ctr[3 * t] : 0.0;
-        yr[q] = valid[q] ? ys[i] - ctr[3 * t + 1] : 0.0;
-        zr[q] = valid[q] ? zs[i] - ctr[3 * t + 2] : 0.0;
+        xr[q] = valid[q] ? d.txs[i] - d.tctr[3 * t] : 0.0;
+        yr[q] = valid[q] ? d.tys[i] - d.tctr[3 * t + 1] : 0.0;
+        zr[q] = valid[q] ? d.tzs[i] - d.tctr[3 * t + 2] : 0.0;
         vr[q] = vi[q] = 0.f;
     }
     __shared__ float4 s01[kThreads], s23[kThreads];
     __shared__ real scf[kThreads], ssf[kThreads];
-    const float4 *vb = vt + (int64_t)t * npair;
+    const float4 *vb = d.vt + (int64_t)t * npair;
     for (int m = 0; m < nrp; ++m) {
-        const double2 rg = rings[m];
+        const double2 rg = d.rings[m];
         const bool eq = 2 * m == L;
         real A[PT], B[PT];
         float ecs[PT], esn[PT], xre[PT], xim[PT], yre[PT], yim[PT];
@@ -410,8 +446,8 @@ k_pw_backward_rings(const double *__restrict__ xs, const double *__restrict__ ys
                     s01[tid] = make_float4(p1.x + p2.x, p1.y + p2.y, p1.x - p2.x, p1.y - p2.y);
                     s23[tid] = make_float4(p2.z + p1.z, p2.w + p1.w, p2.z - p1.z, p2.w - p1.w);
                 }
-                scf[tid] = (real)phis[n].x;
-                ssf[tid] = (real)phis[n].y;
+                scf[tid] = (real)d.phis[n].x;
+                ssf[tid] = (real)d.phis[n].y;
             }
             __syncthreads();
             for (int jj = 0; jj < cnt; ++jj) {
@@ -445,11 +481,11 @@ k_pw_backward_rings(const double *__restrict__ xs, const double *__restrict__ ys
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
         if (!valid[q]) continue;
-        const int i = wk.y + tid + q * kThreads;
-        float2 o = v[i];
+        const int i = wk.z + tid + q * kThreads;
+        float2 o = d.v[i];
         o.x += vr[q];
         o.y += vi[q];
-        v[i] = o;
+        d.v[i] = o;
     }
 }
 
@@ -468,20 +504,21 @@ __device__ __forceinline__ void lagrange_1d(float t, int r1, const float *nodes,
 }
 
 // u~_s = L_Y u_s: u~_s[(a r1 + b) r1 + c] = sum_j l_a(t_x) l_b(t_y) l_c(t_z) u_j, t = 2 (y - c_s) / d_l.
+// Item (desc, source box).
 __global__ void __launch_bounds__(kThreads)
-k_lag_anterp(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
-             const float2 *__restrict__ u, const int32_t *__restrict__ start, const double *__restrict__ ctr,
-             const int32_t *__restrict__ boxes, int r1, int rp, const float *__restrict__ nodes_g,
-             const float *__restrict__ den_g, double two_over_dl, float2 *__restrict__ ut) {
-    const int b = boxes[blockIdx.x];
+k_lag_anterp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int b = wk.y;
     const int tid = threadIdx.x;
-    const int r = r1 * r1 * r1;
+    const int r1 = d.r1, rp = d.rp, r = r1 * r1 * r1;
+    const double two_over_dl = d.two_over_dl;
     __shared__ float ell[kAnterpChunk][3 * kMaxR1];
     __shared__ float2 us[kAnterpChunk];
     __shared__ float nodes[kMaxR1], den[kMaxR1];
     if (tid < r1) {
-        nodes[tid] = nodes_g[tid];
-        den[tid] = den_g[tid];
+        nodes[tid] = d.lnodes[tid];
+        den[tid] = d.lden[tid];
     }
     constexpr int kOut = (kMaxR1 * kMaxR1 * kMaxR1 + kThreads - 1) / kThreads;
     float2 acc[kOut];
@@ -496,17 +533,17 @@ k_lag_anterp(const double *__restrict__ xs, const double *__restrict__ ys, const
         ic[o] = ii % r1;
     }
     const int nout = (r + kThreads - 1) / kThreads;
-    const double cx = ctr[3 * b], cy = ctr[3 * b + 1], cz = ctr[3 * b + 2];
-    const int i0 = start[b], i1 = start[b + 1];
+    const double cx = d.sctr[3 * b], cy = d.sctr[3 * b + 1], cz = d.sctr[3 * b + 2];
+    const int i0 = d.sstart[b], i1 = d.sstart[b + 1];
     for (int s0 = i0; s0 < i1; s0 += kAnterpChunk) {
         const int cnt = min(kAnterpChunk, i1 - s0);
         __syncthreads();
         if (tid < cnt) {
             const int j = s0 + tid;
-            lagrange_1d((float)((xs[j] - cx) * two_over_dl), r1, nodes, den, &ell[tid][0]);
-            lagrange_1d((float)((ys[j] - cy) * two_over_dl), r1, nodes, den, &ell[tid][r1]);
-            lagrange_1d((float)((zs[j] - cz) * two_over_dl), r1, nodes, den, &ell[tid][2 * r1]);
-            us[tid] = u[j];
+            lagrange_1d((float)((d.sxs[j] - cx) * two_over_dl), r1, nodes, den, &ell[tid][0]);
+            lagrange_1d((float)((d.sys[j] - cy) * two_over_dl), r1, nodes, den, &ell[tid][r1]);
+            lagrange_1d((float)((d.szs[j] - cz) * two_over_dl), r1, nodes, den, &ell[tid][2 * r1]);
+            us[tid] = d.u[j];
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; ++jj) {
@@ -521,48 +558,50 @@ k_lag_anterp(const double *__restrict__ xs, const double *__restrict__ ys, const
             }
         }
     }
+    float2 *ut = d.ut2 + (int64_t)b * rp;
 #pragma unroll
     for (int o = 0; o < kOut; ++o) {
         const int i = tid + o * kThreads;
-        if (o < nout && i < rp) ut[(int64_t)b * rp + i] = (i < r) ? acc[o] : make_float2(0.f, 0.f);
+        if (o < nout && i < rp) ut[i] = (i < r) ? acc[o] : make_float2(0.f, 0.f);
     }
-    for (int i = r + tid; i < rp; i += kThreads) ut[(int64_t)b * rp + i] = make_float2(0.f, 0.f);
+    for (int i = r + tid; i < rp; i += kThreads) ut[i] = make_float2(0.f, 0.f);
 }
 
 // Transfer products of one class group on MFMA: Z_e = T_c u~_{s(e)} for up to 16 pairs e.
 // C (rp x 32) = T_c (rp x rp) x U (rp x 32), U[k][2m + part] = part of u~_{s(e_m)}[k].
 // v_mfma_f32_32x32x2f32 operands: A[i][k] from lane i + 32 k, B[k][j] from lane j + 32 k,
-// D[i][j] in lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8).
+// D[i][j] in lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8).  Item (desc, group).
 __global__ void __launch_bounds__(64)
-k_lag_mfma(const float *__restrict__ T, int helm, const float2 *__restrict__ ut, const int32_t *__restrict__ far_src,
-           const int32_t *__restrict__ grp_pair, const int32_t *__restrict__ grp_cls, int rp, float2 *__restrict__ Z) {
+k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     extern __shared__ float U[];   // [rp][32]
-    const int g = blockIdx.x;
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int g = wk.y;
     const int lane = threadIdx.x;
-    const int c = grp_cls[g];
+    const int rp = d.rp, helm = d.helm;
+    const int c = d.grp_cls[g];
     __shared__ int pe[16], ps[16];
     if (lane < 16) {
-        const int e = grp_pair[(int64_t)g * 16 + lane];
+        const int e = d.grp_pair[(int64_t)g * 16 + lane];
         pe[lane] = e;
-        ps[lane] = e >= 0 ? far_src[e] : -1;
+        ps[lane] = e >= 0 ? d.far_src[e] : -1;
     }
     __syncthreads();
     for (int idx = lane; idx < rp * 32; idx += 64) {
         const int k = idx >> 5, col = idx & 31, m = col >> 1;
         float val = 0.f;
         if (ps[m] >= 0) {
-            const float2 w = ut[(int64_t)ps[m] * rp + k];
+            const float2 w = d.ut2[(int64_t)ps[m] * rp + k];
             val = (col & 1) ? w.y : w.x;
         }
         U[idx] = val;
     }
     __syncthreads();
     const int64_t per = (int64_t)rp * rp;
-    const float *Tre = T + (int64_t)c * (helm ? 2 : 1) * per;
+    const float *Tre = d.T + (int64_t)c * (helm ? 2 : 1) * per;
     const float *Tim = Tre + per;
     const int col = lane & 31, kh = lane >> 5;
-    const int m = col >> 1;
-    const int e = pe[m];
+    const int e = pe[col >> 1];
     for (int mt = 0; mt < rp / 32; ++mt) {
         floatx16 acc1, acc2;
         for (int v = 0; v < 16; ++v) {
@@ -586,18 +625,15 @@ k_lag_mfma(const float *__restrict__ T, int helm, const float2 *__restrict__ ut,
                 const float sw = __shfl_xor(acc2[v], 1, 64);
                 val = (col & 1) ? val + sw : val - sw;
             }
-            if (e >= 0) reinterpret_cast<float *>(Z + (int64_t)e * rp + i)[col & 1] = val;
+            if (e >= 0) reinterpret_cast<float *>(d.Z + (int64_t)e * rp + i)[col & 1] = val;
         }
     }
 }
-
 
 // Mixed precision: the same class-group products on FP16 MFMA (v_mfma_f32_32x32x8f16) with FP32
 // accumulation.  A[i][k] comes from lane i + 32 (k / 4) (element k % 4 of a half4), B[k][j] from lane
 // j + 32 (k / 4); D as for the FP32 instruction.  T16 = T * sT (plan time); the sources are scaled by a
 // power of two s_u derived on the device from max |u| so that |u~ s_u| < 6e4; Z = C / (sT s_u).
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-
 __device__ __forceinline__ float u_scale(float amax, int maxpts) {
     // |u~| <= (Lebesgue constant of the tensor grid, <= 8) * points * max|u|
     const float bound = 8.f * (float)maxpts * fmaxf(amax, 1e-30f);
@@ -605,37 +641,38 @@ __device__ __forceinline__ float u_scale(float amax, int maxpts) {
 }
 
 __global__ void __launch_bounds__(64)
-k_lag_mfma16(const _Float16 *__restrict__ T16, int helm, float sT, const float *__restrict__ amax, int maxpts,
-             const float2 *__restrict__ ut, const int32_t *__restrict__ far_src, const int32_t *__restrict__ grp_pair,
-             const int32_t *__restrict__ grp_cls, int rp, float2 *__restrict__ Z) {
+k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     extern __shared__ _Float16 U16[];   // [32][rp]: column-major tile, k contiguous
-    const int g = blockIdx.x;
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int g = wk.y;
     const int lane = threadIdx.x;
-    const int c = grp_cls[g];
-    const float su = u_scale(*amax, maxpts);
+    const int rp = d.rp, helm = d.helm;
+    const int c = d.grp_cls[g];
+    const float su = u_scale(*d.amax, d.maxpts);
     __shared__ int pe[16], ps[16];
     if (lane < 16) {
-        const int e = grp_pair[(int64_t)g * 16 + lane];
+        const int e = d.grp_pair[(int64_t)g * 16 + lane];
         pe[lane] = e;
-        ps[lane] = e >= 0 ? far_src[e] : -1;
+        ps[lane] = e >= 0 ? d.far_src[e] : -1;
     }
     __syncthreads();
     for (int idx = lane; idx < rp * 32; idx += 64) {
         const int col = idx / rp, k = idx % rp, m = col >> 1;
         float val = 0.f;
         if (ps[m] >= 0) {
-            const float2 w = ut[(int64_t)ps[m] * rp + k];
+            const float2 w = d.ut2[(int64_t)ps[m] * rp + k];
             val = ((col & 1) ? w.y : w.x) * su;
         }
         U16[idx] = (_Float16)val;
     }
     __syncthreads();
     const int64_t per = (int64_t)rp * rp;
-    const _Float16 *Tre = T16 + (int64_t)c * (helm ? 2 : 1) * per;
+    const _Float16 *Tre = d.T16 + (int64_t)c * (helm ? 2 : 1) * per;
     const _Float16 *Tim = Tre + per;
     const int col = lane & 31, kh = lane >> 5;
     const int e = pe[col >> 1];
-    const float inv = 1.f / (sT * su);
+    const float inv = 1.f / (d.sT * su);
     for (int mt = 0; mt < rp / 32; ++mt) {
         floatx16 acc1, acc2;
         for (int v = 0; v < 16; ++v) {
@@ -660,55 +697,44 @@ k_lag_mfma16(const _Float16 *__restrict__ T16, int helm, float sT, const float *
                 const float sw = __shfl_xor(acc2[v], 1, 64);
                 val = (col & 1) ? val + sw : val - sw;
             }
-            if (e >= 0) reinterpret_cast<float *>(Z + (int64_t)e * rp + row)[col & 1] = val * inv;
+            if (e >= 0) reinterpret_cast<float *>(d.Z + (int64_t)e * rp + row)[col & 1] = val * inv;
         }
     }
 }
 
-// max over |Re u|, |Im u| (non-negative floats compare as their bit patterns)
-__global__ void __launch_bounds__(kThreads) k_amax(const float2 *__restrict__ u, int64_t n, float *out) {
-    float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-        m = fmaxf(m, fmaxf(fabsf(u[i].x), fabsf(u[i].y)));
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int *>(out), __float_as_uint(m));
-}
-
-__global__ void k_zero1(float *a) { *a = 0.f; }
-
 // v_i += L_X^T v~_t with v~_t = sum_{e in far(t)} Z_e (fixed order), t = 2 (x - c_t) / d_l.
+// Item (desc, target box).
 __global__ void __launch_bounds__(kThreads)
-k_lag_interp(const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
-             const int32_t *__restrict__ start, const double *__restrict__ ctr, const int32_t *__restrict__ tboxes,
-             const int64_t *__restrict__ far_ptr, const float2 *__restrict__ Z, int r1, int rp,
-             const float *__restrict__ nodes_g, const float *__restrict__ den_g, double two_over_dl,
-             float2 *__restrict__ v) {
+k_lag_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     extern __shared__ float2 vt[];   // [r]
     __shared__ float nodes[kMaxR1], den[kMaxR1];
-    const int t = tboxes[blockIdx.x];
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
     const int tid = threadIdx.x;
-    const int r = r1 * r1 * r1;
+    const int r1 = d.r1, rp = d.rp, r = r1 * r1 * r1;
+    const double two_over_dl = d.two_over_dl;
     if (tid < r1) {
-        nodes[tid] = nodes_g[tid];
-        den[tid] = den_g[tid];
+        nodes[tid] = d.lnodes[tid];
+        den[tid] = d.lden[tid];
     }
-    const int64_t e0 = far_ptr[t], e1 = far_ptr[t + 1];
+    const int64_t e0 = d.far_ptr[t], e1 = d.far_ptr[t + 1];
     for (int i = tid; i < r; i += kThreads) {
         float2 a = make_float2(0.f, 0.f);
         for (int64_t e = e0; e < e1; ++e) {
-            const float2 z = Z[e * rp + i];
+            const float2 z = d.Z[e * rp + i];
             a.x += z.x;
             a.y += z.y;
         }
         vt[i] = a;
     }
     __syncthreads();
-    const double cx = ctr[3 * t], cy = ctr[3 * t + 1], cz = ctr[3 * t + 2];
-    for (int i = start[t] + tid; i < start[t + 1]; i += kThreads) {
+    const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
+    for (int i = d.tstart[t] + tid; i < d.tstart[t + 1]; i += kThreads) {
         float lx[kMaxR1], ly[kMaxR1], lz[kMaxR1];
-        lagrange_1d((float)((xs[i] - cx) * two_over_dl), r1, nodes, den, lx);
-        lagrange_1d((float)((ys[i] - cy) * two_over_dl), r1, nodes, den, ly);
-        lagrange_1d((float)((zs[i] - cz) * two_over_dl), r1, nodes, den, lz);
+        lagrange_1d((float)((d.txs[i] - cx) * two_over_dl), r1, nodes, den, lx);
+        lagrange_1d((float)((d.tys[i] - cy) * two_over_dl), r1, nodes, den, ly);
+        lagrange_1d((float)((d.tzs[i] - cz) * two_over_dl), r1, nodes, den, lz);
         float sre = 0.f, sim = 0.f;
         for (int a = 0; a < r1; ++a) {
             float bre = 0.f, bim = 0.f;
@@ -725,10 +751,10 @@ k_lag_interp(const double *__restrict__ xs, const double *__restrict__ ys, const
             sre = fmaf(lx[a], bre, sre);
             sim = fmaf(lx[a], bim, sim);
         }
-        float2 o = v[i];
+        float2 o = d.v[i];
         o.x += sre;
         o.y += sim;
-        v[i] = o;
+        d.v[i] = o;
     }
 }
 
@@ -736,42 +762,42 @@ k_lag_interp(const double *__restrict__ xs, const double *__restrict__ ys, const
 // v_i += sum_{s in near(t)} sum_{j in s, r_ij > 0} G(r_ij) u_j.  One 64-lane block per target box; source
 // points are staged through LDS in FP64 relative to the target centre, and every pair's difference is
 // formed in FP64 and rounded once to FP32, so close pairs keep the full FP32 relative accuracy of r.
+// Item (desc, target box).
 template <bool HELM>
 __global__ void __launch_bounds__(64)
-k_near(const double *__restrict__ txs, const double *__restrict__ tys, const double *__restrict__ tzs,
-       const int32_t *__restrict__ tstart, const double *__restrict__ tctr, const double *__restrict__ sxs,
-       const double *__restrict__ sys, const double *__restrict__ szs, const int32_t *__restrict__ sstart,
-       const float2 *__restrict__ u, const int32_t *__restrict__ tboxes, const int64_t *__restrict__ near_ptr,
-       const int32_t *__restrict__ near_src, float k_rev, float2 *__restrict__ v) {
-    const int t = tboxes[blockIdx.x];
+k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
     const int lane = threadIdx.x;
-    const double cx = tctr[3 * t], cy = tctr[3 * t + 1], cz = tctr[3 * t + 2];
+    const float k_rev = d.k_rev;
+    const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
     __shared__ double spx[64], spy[64], spz[64];   // sources relative to c_t
     __shared__ float2 su[64];                      // u / (4 pi)
     const float inv4pi = (float)(1.0 / (4.0 * M_PI));
-    const int64_t e0 = near_ptr[t], e1 = near_ptr[t + 1];
-    for (int i0 = tstart[t]; i0 < tstart[t + 1]; i0 += 64) {
+    const int64_t e0 = d.near_ptr[t], e1 = d.near_ptr[t + 1];
+    for (int i0 = d.tstart[t]; i0 < d.tstart[t + 1]; i0 += 64) {
         const int i = i0 + lane;
-        const bool valid = i < tstart[t + 1];
+        const bool valid = i < d.tstart[t + 1];
         double x = 0.0, y = 0.0, z = 0.0;
         if (valid) {
-            x = txs[i] - cx;
-            y = tys[i] - cy;
-            z = tzs[i] - cz;
+            x = d.txs[i] - cx;
+            y = d.tys[i] - cy;
+            z = d.tzs[i] - cz;
         }
         float are = 0.f, aim = 0.f;
         for (int64_t e = e0; e < e1; ++e) {
-            const int s = near_src[e];
-            const int j0 = sstart[s], j1 = sstart[s + 1];
+            const int s = d.near_src[e];
+            const int j0 = d.sstart[s], j1 = d.sstart[s + 1];
             for (int c0 = j0; c0 < j1; c0 += 64) {
                 const int cnt = min(64, j1 - c0);
                 __syncthreads();
                 if (lane < cnt) {
                     const int j = c0 + lane;
-                    spx[lane] = sxs[j] - cx;
-                    spy[lane] = sys[j] - cy;
-                    spz[lane] = szs[j] - cz;
-                    const float2 uu = u[j];
+                    spx[lane] = d.sxs[j] - cx;
+                    spy[lane] = d.sys[j] - cy;
+                    spz[lane] = d.szs[j] - cz;
+                    const float2 uu = d.u[j];
                     su[lane] = make_float2(uu.x * inv4pi, uu.y * inv4pi);
                 }
                 __syncthreads();
@@ -795,63 +821,54 @@ k_near(const double *__restrict__ txs, const double *__restrict__ tys, const dou
             }
         }
         if (valid) {
-            float2 o = v[i];
+            float2 o = d.v[i];
             o.x += are;
             o.y += aim;
-            v[i] = o;
+            d.v[i] = o;
         }
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_zero2(float2 *a, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = make_float2(0.f, 0.f);
-}
+typedef void (*KernelFn)(const LDesc *, const IoEntry *, const int4 *);
 
-template <int PPT, bool P64>
-void launch_forward(const Plan &P, const Level &LV, const Tree &TY, int l, hipStream_t st) {
-    const int ntile = (int)((LV.npair + kThreads * PPT - 1) / (kThreads * PPT));
-    const int64_t nb = (int64_t)LV.fwd_boxes.n * ntile;
-    FFM_CHECK(nb < (int64_t)1 << 31, FFM_EINTERNAL, "forward grid too large");
-    FFM_LAUNCH((k_pw_forward<PPT, P64>), (int)nb, kThreads, 0, st, TY.xs.p, TY.ys.p, TY.zs.p, P.u_sorted.p,
-               TY.lev[l].start.p, TY.lev[l].ctr.p, LV.fwd_boxes.p, (const float4 *)LV.dirs.p, LV.dirs64.p, LV.npair,
-               ntile, P.wsrc.p);
-}
-
-
-template <int G, bool P64>
-void launch_forward_rings(const Plan &P, const Level &LV, const Tree &TY, int l, hipStream_t st) {
-    const int L = LV.L;
-    const int Tr = (L + G - 1) / G;
-    const int R = std::max(1, std::min({kMaxRings, kThreads / Tr, LV.nrp}));
-    const int nchunk = (LV.nrp + R - 1) / R;
-    const int nsplit = LV.qSplit;
-    const int64_t nb = (int64_t)LV.fwd_boxes.n * nchunk * nsplit;
-    FFM_CHECK(Tr <= kThreads && nb < (int64_t)1 << 31, FFM_EINTERNAL, "ring forward grid");
-    float4 *dst = nsplit > 1 ? P.wpart.p : P.wsrc.p;
-    const int64_t stride = (int64_t)TY.lev[l].nbox * LV.npair;
-    FFM_CHECK(nsplit == 1 || (size_t)(stride * nsplit) <= P.wpart.n, FFM_EINTERNAL, "ring forward partials");
-    FFM_LAUNCH((k_pw_forward_rings<G, P64>), (int)nb, kThreads, 0, st, TY.xs.p, TY.ys.p, TY.zs.p, P.u_sorted.p,
-               TY.lev[l].start.p, TY.lev[l].ctr.p, LV.fwd_boxes.p, LV.rings.p, LV.phis.p, L, LV.nrp, Tr, R, nchunk,
-               nsplit, LV.npair, dst, stride);
-    if (nsplit > 1) {
-        dim3 grid((unsigned)std::min<int64_t>((LV.npair + kThreads - 1) / kThreads, 64), (unsigned)LV.fwd_boxes.n);
-        hipLaunchKernelGGL(k_sum_segments, grid, dim3(kThreads), 0, st, P.wpart.p, LV.fwd_boxes.p, LV.npair, nsplit,
-                           stride, P.wsrc.p);
-        FFM_HIP(hipGetLastError());
+KernelFn kernel_of(const Stage &S, int &threads) {
+    threads = kThreads;
+    switch (S.kern) {
+        case K_PERM_IN: return k_perm_in;
+        case K_AMAX: return S.a ? k_zero_amax : k_amax;
+        case K_PERM_OUT: return k_perm_out;
+        case K_FWD_PAIR:
+            if (S.a == 4) return S.b ? k_pw_forward<4, true> : k_pw_forward<4, false>;
+            if (S.a == 2) return S.b ? k_pw_forward<2, true> : k_pw_forward<2, false>;
+            return S.b ? k_pw_forward<1, true> : k_pw_forward<1, false>;
+        case K_FWD_RING:
+            if (S.a == 4) return S.b ? k_pw_forward_rings<4, true> : k_pw_forward_rings<4, false>;
+            return S.b ? k_pw_forward_rings<2, true> : k_pw_forward_rings<2, false>;
+        case K_SUM: return k_sum_segments;
+        case K_TRANSFER: return S.a == 2 ? k_pw_transfer<2> : k_pw_transfer<1>;
+        case K_BWD_PAIR: return S.b ? k_pw_backward<true> : k_pw_backward<false>;
+        case K_BWD_RING:
+            if (S.a == 2) return S.b ? k_pw_backward_rings<2, true> : k_pw_backward_rings<2, false>;
+            return S.b ? k_pw_backward_rings<1, true> : k_pw_backward_rings<1, false>;
+        case K_ANTERP: return k_lag_anterp;
+        case K_MFMA32: threads = 64; return k_lag_mfma;
+        case K_MFMA16: threads = 64; return k_lag_mfma16;
+        case K_INTERP: return k_lag_interp;
+        case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
+        default: throw Error(FFM_EINTERNAL, "unknown kernel variant");
     }
 }
 
-template <int PPT>
-void launch_transfer(const Plan &P, const Level &LV, hipStream_t st) {
-    const int ntile = (int)((LV.npair + kThreads * PPT - 1) / (kThreads * PPT));
-    const int64_t nb = (int64_t)LV.tgt_boxes.n * ntile;
-    FFM_CHECK(nb < (int64_t)1 << 31, FFM_EINTERNAL, "transfer grid too large");
-    FFM_LAUNCH((k_pw_transfer<PPT>), (int)nb, kThreads, 0, st, LV.tgt_boxes.p, LV.far_ptr.p, LV.far_src.p,
-               LV.far_cls.p, LV.D.p, P.wsrc.p, LV.npair, ntile, P.wtgt.p);
-}
-
 }  // namespace
+
+void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream_t st) {
+    if (S.ditems.n == 0) return;
+    FFM_CHECK(S.ditems.n < ((size_t)1 << 31), FFM_EINTERNAL, "stage grid too large");
+    int threads = kThreads;
+    KernelFn fn = kernel_of(S, threads);
+    hipLaunchKernelGGL(fn, dim3((unsigned)S.ditems.n), dim3(threads), S.shmem, st, ddesc, dio, S.ditems.p);
+    FFM_HIP(hipGetLastError());
+}
 
 // Record the end of a phase (timing plans only): the first call opens the apply.
 void Plan::mark(int phase, hipStream_t st) {
@@ -864,100 +881,30 @@ void Plan::mark(int phase, hipStream_t st) {
 
 void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
     P.tused = 0;
-    P.mark(-1, st);
     if (P.empty) {
-        FFM_LAUNCH(k_zero2, nblocks(P.nx), kThreads, 0, st, v, P.nx);
+        P.mark(-1, st);
+        if (P.nx > 0) FFM_LAUNCH(k_zero_out, (int)((P.nx + kThreads - 1) / kThreads), kThreads, 0, st, v, P.nx);
         return;
     }
-    Tree &TX = *P.tx, &TY = *P.ty;
-    FFM_LAUNCH(k_perm_in, nblocks(P.ny), kThreads, 0, st, wu, dtype, TY.perm.p, P.ny, P.u_sorted.p);
-    FFM_LAUNCH(k_zero2, nblocks(P.nx), kThreads, 0, st, P.v_sorted.p, P.nx);
-    if (P.any_fp16) {
-        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, P.amax.p);
-        FFM_LAUNCH(k_amax, (int)std::min<int64_t>(nblocks(P.ny), 1024), kThreads, 0, st, P.u_sorted.p, P.ny,
-                   P.amax.p);
-    }
+    // this apply's input and output go to the plan's I/O entry (pinned, copied in stream order); the
+    // previous apply's copy has completed once its completion event has
+    if (P.applied) FFM_HIP(hipEventSynchronize(P.done));
+    P.hio->wu = wu;
+    P.hio->vout = v;
+    P.hio->dtype = dtype;
+    FFM_HIP(hipMemcpyAsync(P.dio.p, P.hio, sizeof(IoEntry), hipMemcpyHostToDevice, st));
+    P.mark(-1, st);
+    for (const Stage &S : P.pre) run_stage(S, P.ddesc.p, P.dio.p, st);
     P.mark(0, st);
-    const bool helm = P.kernel == FFM_HELMHOLTZ;
-    for (int l = 1; l <= P.leaf; ++l) {
-        const Level &LV = P.lev[l];
-        if (LV.method == kGegenbauer) {
-            // source transform, diagonal transfer, target transform (Sec. 2.2.3)
-            if (LV.qG == 4) {
-                if (LV.phase64) launch_forward_rings<4, true>(P, LV, TY, l, st);
-                else launch_forward_rings<4, false>(P, LV, TY, l, st);
-            } else if (LV.qG == 2) {
-                if (LV.phase64) launch_forward_rings<2, true>(P, LV, TY, l, st);
-                else launch_forward_rings<2, false>(P, LV, TY, l, st);
-            } else if (LV.npair >= 4 * kThreads) {
-                if (LV.phase64) launch_forward<4, true>(P, LV, TY, l, st);
-                else launch_forward<4, false>(P, LV, TY, l, st);
-            } else if (LV.npair >= 2 * kThreads) {
-                if (LV.phase64) launch_forward<2, true>(P, LV, TY, l, st);
-                else launch_forward<2, false>(P, LV, TY, l, st);
-            } else {
-                if (LV.phase64) launch_forward<1, true>(P, LV, TY, l, st);
-                else launch_forward<1, false>(P, LV, TY, l, st);
-            }
-            P.mark(1 + 3 * (l - 1), st);
-            if (LV.npair >= 2 * kThreads) launch_transfer<2>(P, LV, st);
-            else launch_transfer<1>(P, LV, st);
-            P.mark(2 + 3 * (l - 1), st);
-            if (LV.qG) {
-                if (LV.phase64)
-                    FFM_LAUNCH(k_pw_backward_rings<true>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p,
-                               TX.zs.p, TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, LV.rings.p, LV.phis.p, LV.L,
-                               LV.nrp, P.wtgt.p, LV.npair, P.v_sorted.p);
-                else
-                    FFM_LAUNCH(k_pw_backward_rings<false>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p,
-                               TX.zs.p, TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, LV.rings.p, LV.phis.p, LV.L,
-                               LV.nrp, P.wtgt.p, LV.npair, P.v_sorted.p);
-            } else if (LV.phase64) {
-                FFM_LAUNCH(k_pw_backward<true>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p, TX.zs.p,
-                           TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, (const float4 *)LV.dirs.p, LV.dirs64.p,
-                           P.wtgt.p, LV.npair, P.v_sorted.p);
-            } else {
-                FFM_LAUNCH(k_pw_backward<false>, (int)LV.bwd_work.n, kThreads, 0, st, TX.xs.p, TX.ys.p, TX.zs.p,
-                           TX.lev[l].start.p, TX.lev[l].ctr.p, LV.bwd_work.p, (const float4 *)LV.dirs.p, LV.dirs64.p,
-                           P.wtgt.p, LV.npair, P.v_sorted.p);
-            }
-            P.mark(3 + 3 * (l - 1), st);
-        } else if (LV.method == kLagrange) {
-            // interpolation, MFMA transfer, interpolation back (Sec. 2.2.2)
-            const double dl = std::ldexp(P.d0, -l);
-            float2 *ut = reinterpret_cast<float2 *>(P.wsrc.p);
-            FFM_LAUNCH(k_lag_anterp, (int)LV.fwd_boxes.n, kThreads, 0, st, TY.xs.p, TY.ys.p, TY.zs.p, P.u_sorted.p,
-                       TY.lev[l].start.p, TY.lev[l].ctr.p, LV.fwd_boxes.p, LV.r1, LV.rp, LV.lnodes.p, LV.lden.p,
-                       2.0 / dl, ut);
-            if (LV.fp16)
-                FFM_LAUNCH(k_lag_mfma16, LV.ngrp, 64, sizeof(_Float16) * LV.rp * 32, st, LV.T16.p, helm ? 1 : 0,
-                           LV.sT, P.amax.p, LV.max_src_pts, ut, LV.far_src.p, LV.grp_pair.p, LV.grp_cls.p, LV.rp,
-                           P.wz.p);
-            else
-                FFM_LAUNCH(k_lag_mfma, LV.ngrp, 64, sizeof(float) * LV.rp * 32, st, LV.T.p, helm ? 1 : 0, ut,
-                           LV.far_src.p, LV.grp_pair.p, LV.grp_cls.p, LV.rp, P.wz.p);
-            P.mark(1 + 3 * (l - 1), st);   // interpolation and transfer share the first two slots
-            P.mark(2 + 3 * (l - 1), st);
-            FFM_LAUNCH(k_lag_interp, (int)LV.tgt_boxes.n, kThreads, sizeof(float2) * LV.r, st, TX.xs.p, TX.ys.p,
-                       TX.zs.p, TX.lev[l].start.p, TX.lev[l].ctr.p, LV.tgt_boxes.p, LV.far_ptr.p, P.wz.p, LV.r1,
-                       LV.rp, LV.lnodes.p, LV.lden.p, 2.0 / dl, P.v_sorted.p);
-            P.mark(3 + 3 * (l - 1), st);
+    for (int l = 1; l <= P.leaf; ++l)
+        for (const Stage &S : P.lev[l].stages) {
+            run_stage(S, P.ddesc.p, P.dio.p, st);
+            if (S.slot >= 0) P.mark(S.slot, st);
         }
+    for (const Stage &S : P.post) {
+        run_stage(S, P.ddesc.p, P.dio.p, st);
+        if (S.slot >= 0) P.mark(S.slot, st);
     }
-    // dense remainder at the leaf (Sec. 2.2.4)
-    const Level &LL = P.lev[P.leaf];
-    const float k_rev = (float)(P.k / (2.0 * M_PI));
-    if (helm)
-        FFM_LAUNCH(k_near<true>, (int)LL.near_boxes.n, 64, 0, st, TX.xs.p, TX.ys.p, TX.zs.p, TX.lev[P.leaf].start.p,
-                   TX.lev[P.leaf].ctr.p, TY.xs.p, TY.ys.p, TY.zs.p, TY.lev[P.leaf].start.p, P.u_sorted.p,
-                   LL.near_boxes.p, LL.near_ptr.p, LL.near_src.p, k_rev, P.v_sorted.p);
-    else
-        FFM_LAUNCH(k_near<false>, (int)LL.near_boxes.n, 64, 0, st, TX.xs.p, TX.ys.p, TX.zs.p, TX.lev[P.leaf].start.p,
-                   TX.lev[P.leaf].ctr.p, TY.xs.p, TY.ys.p, TY.zs.p, TY.lev[P.leaf].start.p, P.u_sorted.p,
-                   LL.near_boxes.p, LL.near_ptr.p, LL.near_src.p, k_rev, P.v_sorted.p);
-    P.mark(61, st);
-    FFM_LAUNCH(k_perm_out, nblocks(P.nx), kThreads, 0, st, P.v_sorted.p, TX.perm.p, P.nx, v);
-    P.mark(62, st);
 }
 
 }  // namespace ffm

@@ -134,6 +134,72 @@ struct Tree {
 
 enum Method { kNone = 0, kLagrange = 1, kGegenbauer = 2 };
 
+// ---------------------------------------------------------------- execution descriptors
+// Every apply kernel takes an array of level descriptors and a list of work items (int4, .x = descriptor
+// index); a block reads everything it needs from its item's descriptor.  One plan's levels, or many
+// plans' levels (a batch), run through the same kernels: a launch covers any mix of instances.
+struct IoEntry {           // per-instance input and output of the current apply
+    const void *wu;
+    float2 *vout;
+    int dtype;
+    int pad;
+};
+
+struct LDesc {
+    // instance
+    int inst;                         // index into the I/O table
+    int helm;                         // Helmholtz kernel
+    const int32_t *perm_x, *perm_y;   // sorted position -> caller index
+    int64_t nx, ny;
+    float2 *u, *v;                    // sorted input, sorted output accumulator
+    float *amax;                      // max |u| of the apply (FP16 scaling), or null
+    float k_rev;                      // k / (2 pi)
+    // level
+    const double *txs, *tys, *tzs, *tctr;
+    const int32_t *tstart;
+    const double *sxs, *sys, *szs, *sctr;
+    const int32_t *sstart;
+    const int64_t *far_ptr, *near_ptr;
+    const int32_t *far_src, *far_cls, *near_src;
+    // Gegenbauer level
+    const float4 *dirs;
+    const double *dirs64;
+    const double2 *rings, *phis;
+    const float4 *D;
+    float4 *ut, *vt, *part;           // u~ / v~ / point-segment partials of this level
+    int64_t npair, part_stride;
+    int L, nrp, Tr, R, nchunk, nsplit;
+    // Lagrange level
+    const float *T, *lnodes, *lden;
+    const _Float16 *T16;
+    const int32_t *grp_pair, *grp_cls;
+    float2 *ut2, *Z;
+    double two_over_dl;
+    int r1, rp, maxpts;
+    float sT;
+};
+
+// Kernel variants (the template parameters travel with the stage).
+enum Kern {
+    K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
+    K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT
+};
+
+struct Stage {
+    int kern = 0, a = 0, b = 0;       // kernel and its template parameters
+    int slot = -1;                    // timing slot (FFM_TIMING layout)
+    int level = 0;                    // level (ordering of target-side stages in batches)
+    size_t shmem = 0;                 // dynamic LDS bytes
+    std::vector<int4> items;          // work items (host copy, kept for batching)
+    DevBuf<int4> ditems;
+};
+
+// Tile choices of the plane-wave kernels (the autotuner picks among them).
+struct Tune {
+    int ring_g = 4;                   // groups of 4 directions per thread in ring-pair forward kernels
+    int bwd_pt = 2;                   // target points per thread in ring-pair backward kernels
+};
+
 struct Level {
     // descent lists, CSR by target box of this level; sources ascending
     int64_t nfar = 0, nnear = 0;
@@ -168,14 +234,16 @@ struct Level {
     int qG = 0;                          // groups of 4 directions per thread (0: direction-pair kernels)
     int qSplit = 1;                      // point segments of the forward transform (partials summed in order)
     int bwd_tile = 256;                  // target points per backward block
+    int Tr = 0, R = 0, nchunk = 0;       // ring-pair forward: threads per ring, rings per block, ring chunks
     // Lagrange node tables (FP32): Chebyshev nodes and 1 / prod_{b != a}(t_a - t_b)
     DevBuf<float> lnodes, lden;
-    // work lists, largest boxes first
-    DevBuf<int32_t> fwd_boxes;           // source boxes in at least one far pair
-    DevBuf<int32_t> tgt_boxes;           // target boxes with a non-empty far list
-    DevBuf<int2> bwd_work;               // (target box, first point) tiles of 256 points
-    DevBuf<int32_t> near_boxes;          // leaf: target boxes with a non-empty near list
+    // box lists on the host, largest boxes first, and the box point ranges
+    std::vector<int32_t> h_fwd;          // source boxes in at least one far pair
+    std::vector<int32_t> h_tgt;          // target boxes with a non-empty far list
+    std::vector<int32_t> h_near;         // leaf: target boxes with a non-empty near list
+    std::vector<int32_t> h_sx, h_sy;     // box start arrays of the two trees
     int32_t max_src_pts = 0, max_tgt_pts = 0;
+    std::vector<Stage> stages;           // launches of this level, in order
     double pts_src = 0, pts_tgt = 0;     // points in the forward / backward work lists
 };
 
@@ -204,6 +272,13 @@ struct Plan {
     ffm_stats_t stats{};
     hipEvent_t done = nullptr;           // recorded after every apply
     bool applied = false;
+    // execution: descriptors (index = level), I/O table, stages before and after the levels
+    std::vector<LDesc> hdesc;
+    DevBuf<LDesc> ddesc;
+    DevBuf<IoEntry> dio;
+    IoEntry *hio = nullptr;              // pinned host copy of the I/O entry
+    std::vector<Stage> pre, post;
+    Tune tune;
     // optional phase timing (FFM_FLAG_TIMING): events recorded at phase ends
     std::vector<hipEvent_t> tev;
     std::vector<int> tphase;             // phase slot of each recorded event (after the first)
@@ -215,6 +290,15 @@ struct Plan {
 void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st);
 void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st);
 size_t plan_device_bytes(const Plan &P);
+// stages of a plan for a tile choice; descriptors of a plan over given workspaces
+void plan_stages(Plan &P, const Tune &t, hipStream_t st);
+struct LevelWork {                     // workspace of one level (a batch keeps one per level)
+    float4 *ut = nullptr, *vt = nullptr, *part = nullptr;
+    float2 *ut2 = nullptr, *Z = nullptr;
+};
+LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w);
+// one launch per stage
+void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream_t st);
 
 // device primitives (scan_sort.hip)
 // (temporaries come from the scratch list; nothing here synchronises the stream)

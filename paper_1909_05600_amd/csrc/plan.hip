@@ -577,18 +577,13 @@ void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &
     for (int32_t t = 0; t < LX.nbox; ++t)
         if (ptr[t + 1] > ptr[t]) tgt.push_back(t);
     by_size(sx, tgt);
+    LV.h_sx = sx;
+    LV.h_sy = sy;
     if (near) {
-        upload(LV.near_boxes, tgt, st, SC);
+        LV.h_near = std::move(tgt);
         P.stats.near_pairs = (double)near_pairs;
         return;
     }
-    upload(LV.tgt_boxes, tgt, st, SC);
-    std::vector<int2> work;
-    for (int32_t t : tgt) {
-        LV.max_tgt_pts = std::max(LV.max_tgt_pts, sx[t + 1] - sx[t]);
-        for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) work.push_back(make_int2(t, i));
-    }
-    upload(LV.bwd_work, work, st, SC);
     std::vector<int32_t> fwd;
     for (int32_t s = 0; s < LY.nbox; ++s)
         if (act[s]) {
@@ -596,12 +591,16 @@ void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &
             LV.max_src_pts = std::max(LV.max_src_pts, sy[s + 1] - sy[s]);
         }
     by_size(sy, fwd);
-    upload(LV.fwd_boxes, fwd, st, SC);
     double npts_src = 0, npts_tgt = 0;
     for (int32_t s : fwd) npts_src += sy[s + 1] - sy[s];
-    for (int32_t t : tgt) npts_tgt += sx[t + 1] - sx[t];
+    for (int32_t t : tgt) {
+        npts_tgt += sx[t + 1] - sx[t];
+        LV.max_tgt_pts = std::max(LV.max_tgt_pts, sx[t + 1] - sx[t]);
+    }
     LV.pts_src = npts_src;
     LV.pts_tgt = npts_tgt;
+    LV.h_fwd = std::move(fwd);
+    LV.h_tgt = std::move(tgt);
 }
 
 // FFM_LOG=1: host wall time of the plan phases on stderr (quiet by default)
@@ -797,9 +796,6 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             LV.method = kGegenbauer;
             LV.L = gegenbauer_L(P.k, dl, P.eps);
             FFM_CHECK(LV.L <= 1000, FFM_EINVAL, "ffm_plan: k * d_0 too large (Gegenbauer rank above 1000)");
-            // ring-pair kernels where rings are long enough to fill the threads
-            LV.qG = LV.L >= 64 ? 4 : (LV.L >= 32 ? 2 : 0);
-            LV.bwd_tile = LV.qG ? 512 : 256;
         }
         build_work_lists(P, LV, TX.lev[l], TY.lev[l], false, st, SC);
         plog.mark("tab.work");
@@ -851,18 +847,6 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             // the ring-pair form is always reduced in FP64
             const double max_rad = P.k * dl * std::sqrt(3.0) * 0.5;
             LV.phase64 = max_rad * std::ldexp(1.0, -22) > P.eps / 20.0;
-            if (LV.qG) {
-                // split the points of each box into segments when boxes are too few to fill the chip
-                const int Tr = (L + LV.qG - 1) / LV.qG;
-                const int R = std::max(1, std::min({16, 256 / Tr, LV.nrp}));
-                const int64_t blocks = (int64_t)LV.fwd_boxes.n * ((LV.nrp + R - 1) / R);
-                const double avg = LV.pts_src / std::max<double>(1.0, (double)LV.fwd_boxes.n);
-                int split = 1;
-                while (split < 8 && blocks * split < 4096 && avg / (2 * split) >= 512 && LV.fwd_boxes.n < 65536)
-                    split *= 2;
-                LV.qSplit = split;
-                if (split > 1) ws_part = std::max(ws_part, (size_t)split * nby * LV.npair);
-            }
             // per-class series coefficients (host FP64), unit directions r0/|r0|
             std::vector<double> rhat(3 * (size_t)LV.ncls);
             std::vector<double2> coef((size_t)LV.ncls * (L + 1));
@@ -968,17 +952,33 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     }
     plog.mark("tables");
     build_work_lists(P, P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC);
+    (void)ws_part;
     P.ws_src = ws_src;
     P.ws_tgt = ws_tgt;
     P.ws_z = ws_z;
-    P.ws_part = ws_part;
-    P.wpart.alloc(ws_part);
     P.u_sorted.alloc(ny);
     P.v_sorted.alloc(nx);
     P.wsrc.alloc(ws_src);
     P.wtgt.alloc(ws_tgt);
     P.wz.alloc(ws_z);
     if (P.any_fp16) P.amax.alloc(1);
+    // launches and descriptors
+    plan_stages(P, P.tune, st);
+    P.dio.alloc(1);
+    P.hio = static_cast<IoEntry *>(pinned_alloc(sizeof(IoEntry)));
+    std::memset(P.hio, 0, sizeof(IoEntry));
+    {
+        LevelWork w;
+        w.ut = P.wsrc.p;
+        w.vt = P.wtgt.p;
+        w.part = P.wpart.p;
+        w.ut2 = reinterpret_cast<float2 *>(P.wsrc.p);
+        w.Z = P.wz.p;
+        P.hdesc.clear();
+        for (int l = 0; l <= P.leaf; ++l)
+            P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
+        upload(P.ddesc, P.hdesc, st, SC);
+    }
     FFM_HIP(hipStreamSynchronize(st));
     plog.mark("workspace");
 
@@ -1018,6 +1018,179 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     (void)ws_tgt;
 }
 
+// ---------------------------------------------------------------------------- launches
+namespace {
+Stage make_stage(int kern, int a, int b, int slot, int level, size_t shmem, std::vector<int4> &&items, hipStream_t st,
+                 Scratch &SC) {
+    Stage S;
+    S.kern = kern;
+    S.a = a;
+    S.b = b;
+    S.slot = slot;
+    S.level = level;
+    S.shmem = shmem;
+    S.items = std::move(items);
+    upload(S.ditems, S.items, st, SC);
+    return S;
+}
+}  // namespace
+
+// Choose the kernel form of every level for a tile choice and build its launches (work items).
+void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
+    Scratch SC(st);
+    P.pre.clear();
+    P.post.clear();
+    if (P.empty) return;
+    const int64_t nmax = std::max(P.nx, P.ny);
+    {
+        std::vector<int4> it;
+        for (int64_t i = 0; i < nmax; i += kThreads) it.push_back(make_int4(0, (int)i, 0, 0));
+        P.pre.push_back(make_stage(K_PERM_IN, 0, 0, -1, 0, 0, std::move(it), st, SC));
+        if (P.any_fp16) {
+            std::vector<int4> z(1, make_int4(0, 0, 0, 0)), am;
+            for (int64_t i = 0; i < P.ny; i += 16 * kThreads) am.push_back(make_int4(0, (int)i, 0, 0));
+            P.pre.push_back(make_stage(K_AMAX, 1, 0, -1, 0, 0, std::move(z), st, SC));
+            P.pre.push_back(make_stage(K_AMAX, 0, 0, -1, 0, 0, std::move(am), st, SC));
+        }
+    }
+    size_t ws_part = 0;
+    for (int l = 1; l <= P.leaf; ++l) {
+        Level &LV = P.lev[l];
+        LV.stages.clear();
+        if (LV.method == kNone) continue;
+        const int s1 = 1 + 3 * (l - 1), s2 = s1 + 1, s3 = s1 + 2;
+        const std::vector<int32_t> &sx = LV.h_sx;
+        if (LV.method == kGegenbauer) {
+            const int L = LV.L;
+            LV.qG = L >= 64 ? tu.ring_g : (L >= 32 ? 2 : 0);
+            if (LV.qG && (L + LV.qG - 1) / LV.qG > kThreads) LV.qG = 4;   // one ring must fit one block
+            LV.bwd_tile = LV.qG ? kThreads * tu.bwd_pt : kThreads;
+            std::vector<int4> fw;
+            if (LV.qG) {
+                // ring-pair form; split each box's points into segments when boxes are too few to fill the chip
+                LV.Tr = (L + LV.qG - 1) / LV.qG;
+                LV.R = std::max(1, std::min({16, kThreads / LV.Tr, LV.nrp}));
+                LV.nchunk = (LV.nrp + LV.R - 1) / LV.R;
+                const int64_t blocks = (int64_t)LV.h_fwd.size() * LV.nchunk;
+                const double avg = LV.pts_src / std::max<double>(1.0, (double)LV.h_fwd.size());
+                int split = 1;
+                while (split < 8 && blocks * split < 4096 && avg / (2 * split) >= 512) split *= 2;
+                LV.qSplit = split;
+                if (split > 1) ws_part = std::max(ws_part, (size_t)split * P.ty->lev[l].nbox * LV.npair);
+                for (int32_t b : LV.h_fwd)
+                    for (int c = 0; c < LV.nchunk; ++c)
+                        for (int g = 0; g < split; ++g) fw.push_back(make_int4(l, b, c, g));
+                LV.stages.push_back(make_stage(K_FWD_RING, LV.qG, LV.phase64, split > 1 ? -1 : s1, l, 0, std::move(fw), st, SC));
+                if (split > 1) {
+                    std::vector<int4> sm;
+                    for (int32_t b : LV.h_fwd) sm.push_back(make_int4(l, b, 0, 0));
+                    LV.stages.push_back(make_stage(K_SUM, 0, 0, s1, l, 0, std::move(sm), st, SC));
+                }
+            } else {
+                LV.qSplit = 1;
+                const int ppt = LV.npair >= 4 * kThreads ? 4 : (LV.npair >= 2 * kThreads ? 2 : 1);
+                const int64_t nt = (LV.npair + kThreads * ppt - 1) / (kThreads * ppt);
+                for (int32_t b : LV.h_fwd)
+                    for (int64_t t = 0; t < nt; ++t) fw.push_back(make_int4(l, b, (int)t, 0));
+                LV.stages.push_back(make_stage(K_FWD_PAIR, ppt, LV.phase64, s1, l, 0, std::move(fw), st, SC));
+            }
+            const int ppt = LV.npair >= 2 * kThreads ? 2 : 1;
+            const int64_t nt = (LV.npair + kThreads * ppt - 1) / (kThreads * ppt);
+            std::vector<int4> tr, bw;
+            for (int32_t t : LV.h_tgt)
+                for (int64_t q = 0; q < nt; ++q) tr.push_back(make_int4(l, t, (int)q, 0));
+            LV.stages.push_back(make_stage(K_TRANSFER, ppt, 0, s2, l, 0, std::move(tr), st, SC));
+            for (int32_t t : LV.h_tgt)
+                for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) bw.push_back(make_int4(l, t, i, 0));
+            if (LV.qG)
+                LV.stages.push_back(make_stage(K_BWD_RING, tu.bwd_pt, LV.phase64, s3, l, 0, std::move(bw), st, SC));
+            else
+                LV.stages.push_back(make_stage(K_BWD_PAIR, 0, LV.phase64, s3, l, 0, std::move(bw), st, SC));
+        } else {
+            std::vector<int4> an, mf, ip;
+            for (int32_t b : LV.h_fwd) an.push_back(make_int4(l, b, 0, 0));
+            for (int32_t g = 0; g < LV.ngrp; ++g) mf.push_back(make_int4(l, g, 0, 0));
+            for (int32_t t : LV.h_tgt) ip.push_back(make_int4(l, t, 0, 0));
+            LV.stages.push_back(make_stage(K_ANTERP, 0, 0, s1, l, 0, std::move(an), st, SC));
+            LV.stages.push_back(make_stage(LV.fp16 ? K_MFMA16 : K_MFMA32, 0, 0, s2, l,
+                                           (size_t)LV.rp * 32 * (LV.fp16 ? 2 : 4), std::move(mf), st, SC));
+            LV.stages.push_back(make_stage(K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r, std::move(ip), st, SC));
+        }
+    }
+    if (ws_part > P.wpart.n) P.wpart.alloc(ws_part);
+    {
+        const Level &LL = P.lev[P.leaf];
+        std::vector<int4> nr, po;
+        for (int32_t t : LL.h_near) nr.push_back(make_int4(P.leaf, t, 0, 0));
+        for (int64_t i = 0; i < P.nx; i += kThreads) po.push_back(make_int4(0, (int)i, 0, 0));
+        P.post.push_back(make_stage(K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, 61, P.leaf, 0, std::move(nr), st, SC));
+        P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
+    }
+}
+
+// The descriptor of level l of a plan, over the given instance buffers and level workspace.
+LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w) {
+    LDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.inst = inst;
+    d.helm = P.kernel == FFM_HELMHOLTZ ? 1 : 0;
+    d.perm_x = P.tx->perm.p;
+    d.perm_y = P.ty->perm.p;
+    d.nx = P.nx;
+    d.ny = P.ny;
+    d.u = u;
+    d.v = v;
+    d.amax = amax;
+    d.k_rev = (float)(P.k / (2.0 * M_PI));
+    const TreeLevel &LX = P.tx->lev[l], &LY = P.ty->lev[l];
+    d.txs = P.tx->xs.p;
+    d.tys = P.tx->ys.p;
+    d.tzs = P.tx->zs.p;
+    d.tctr = LX.ctr.p;
+    d.tstart = LX.start.p;
+    d.sxs = P.ty->xs.p;
+    d.sys = P.ty->ys.p;
+    d.szs = P.ty->zs.p;
+    d.sctr = LY.ctr.p;
+    d.sstart = LY.start.p;
+    const Level &LV = P.lev[l];
+    d.far_ptr = LV.far_ptr.p;
+    d.far_src = LV.far_src.p;
+    d.far_cls = LV.far_cls.p;
+    d.near_ptr = LV.near_ptr.p;
+    d.near_src = LV.near_src.p;
+    d.dirs = LV.dirs.p;
+    d.dirs64 = LV.dirs64.p;
+    d.rings = LV.rings.p;
+    d.phis = LV.phis.p;
+    d.D = LV.D.p;
+    d.ut = w.ut;
+    d.vt = w.vt;
+    d.part = w.part;
+    d.npair = LV.npair;
+    d.part_stride = (int64_t)LY.nbox * LV.npair;
+    d.L = LV.L;
+    d.nrp = LV.nrp;
+    d.Tr = LV.Tr;
+    d.R = LV.R;
+    d.nchunk = LV.nchunk;
+    d.nsplit = LV.qSplit;
+    d.T = LV.T.p;
+    d.lnodes = LV.lnodes.p;
+    d.lden = LV.lden.p;
+    d.T16 = LV.T16.p;
+    d.grp_pair = LV.grp_pair.p;
+    d.grp_cls = LV.grp_cls.p;
+    d.ut2 = w.ut2;
+    d.Z = w.Z;
+    d.two_over_dl = l > 0 ? 2.0 / std::ldexp(P.d0, -l) : 0.0;
+    d.r1 = LV.r1;
+    d.rp = LV.rp;
+    d.maxpts = LV.max_src_pts;
+    d.sT = LV.sT;
+    return d;
+}
+
 size_t plan_device_bytes(const Plan &P) {
     size_t b = 0;
     auto tree = [&](const Tree &T) {
@@ -1033,10 +1206,13 @@ size_t plan_device_bytes(const Plan &P) {
         const Level &L = P.lev[l];
         b += L.far_ptr.bytes() + L.near_ptr.bytes() + L.far_src.bytes() + L.far_cls.bytes() + L.near_src.bytes() +
              L.T.bytes() + L.grp_pair.bytes() + L.grp_cls.bytes() + L.dirs.bytes() + L.dirs64.bytes() + L.D.bytes() +
-             L.lnodes.bytes() + L.lden.bytes() + L.fwd_boxes.bytes() + L.tgt_boxes.bytes() + L.bwd_work.bytes() +
-             L.near_boxes.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes();
+             L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes();
+        for (const Stage &S : L.stages) b += S.ditems.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes();
+    b += P.ddesc.bytes() + P.dio.bytes();
+    for (const Stage &S : P.pre) b += S.ditems.bytes();
+    for (const Stage &S : P.post) b += S.ditems.bytes();
     return b;
 }
 
