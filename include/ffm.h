@@ -184,6 +184,81 @@ ffm_status_t ffm_plan_timing(ffm_plan_t plan, float *ms, int32_t n);
 size_t ffm_plan_bytes(ffm_plan_t plan);
 size_t ffm_workspace_bytes(ffm_plan_t plan);
 
+/* ------------------------------------------------------------------ tiles and batches
+ * Not in the paper: the paper evaluates one product at a time.  These entry
+ * points apply many independent plans together (one launch per step kind for
+ * all of them, optionally captured in a HIP graph) and choose the tile shapes
+ * of the plane-wave transform kernels (Sec. 2.2.3) by timing them.
+ */
+
+/* Tile choice of the ring-pair plane-wave kernels: ring_g groups of four
+ * quadrature directions per thread in the source transform (2 or 4), bwd_pt
+ * target points per thread in the target transform (1 or 2).  Default {4, 2}.
+ * Results do not depend on bwd_pt; ring_g can change how a box's points are
+ * split into partial sums, so results with different ring_g agree to
+ * rounding, not bitwise. */
+typedef struct {
+    int32_t ring_g;
+    int32_t bwd_pt;
+} ffm_tiles_t;
+
+/* Rebuild a plan's launches for a tile choice.  Waits for the plan's last
+ * apply.  FFM_EINVAL for other values; FFM_EBUSY while the plan belongs to a
+ * batch. */
+ffm_status_t ffm_plan_set_tiles(ffm_plan_t plan, const ffm_tiles_t *tiles, void *hip_stream);
+ffm_status_t ffm_plan_get_tiles(ffm_plan_t plan, ffm_tiles_t *tiles);
+
+typedef struct ffm_batch_s *ffm_batch_t;
+
+#define FFM_BATCH_GRAPH    1u   /* capture the merged launches once in a HIP graph; apply replays it */
+#define FFM_BATCH_AUTOTUNE 2u   /* time the tile candidates on this batch and keep the fastest */
+
+/*
+ * ffm_batch_create -- group n >= 1 distinct plans for joint application.
+ *   plans       host array of n plan handles.  The batch borrows them: while it
+ *               exists ffm_destroy and ffm_plan_set_tiles on them return
+ *               FFM_EBUSY, a plan belongs to at most one batch, and a plan must
+ *               not be applied on its own while a batch apply is in flight
+ *               (both use the plan's workspace).
+ *   flags       FFM_BATCH_GRAPH | FFM_BATCH_AUTOTUNE.
+ *   tile_cache  NULL, or the path of a JSON file {"<signature>": {"ring_g": G,
+ *               "bwd_pt": PT, "ms": T}, ...}: with FFM_BATCH_AUTOTUNE a
+ *               recorded choice for this batch's shapes is used without timing,
+ *               and a new one is added.  The signature hashes each instance's
+ *               kernel, sizes, depth and per-level method, order and box count.
+ *   hip_stream  stream for the set-up work (autotuning runs the batch on it).
+ * Autotuning sets the chosen tiles on every plan of the batch.  Host-
+ * synchronous.  Errors: FFM_EINVAL (NULL, n <= 0, repeated plan, unknown
+ * flags, unwritable cache), FFM_EBUSY (a plan already in a batch).
+ */
+ffm_status_t ffm_batch_create(const ffm_plan_t *plans, int32_t n, uint32_t flags, const char *tile_cache,
+                              void *hip_stream, ffm_batch_t *out);
+
+/*
+ * ffm_batch_apply -- v[i] = FFM_i(wu[i]) for every instance i of the batch, as
+ * ffm_apply would give it with the same tiles (bitwise).  wu, in_dtype and v
+ * are host arrays of n entries; wu[i] and v[i] are device pointers with the
+ * layouts of ffm_apply.  Asynchronous on hip_stream; the pointer table is
+ * copied in stream order, so the caller may reuse the host arrays on return.
+ */
+ffm_status_t ffm_batch_apply(ffm_batch_t batch, const void *const *wu, const ffm_dtype_t *in_dtype, void *const *v,
+                             void *hip_stream);
+
+typedef struct {
+    int32_t n;             /* instances                                          */
+    int32_t launches;      /* kernel launches per apply                          */
+    int32_t graph;         /* 1 if applies replay a HIP graph                    */
+    int32_t tuned;         /* 0 plans' own tiles, 1 timed at creation, 2 from the cache */
+    ffm_tiles_t tiles;     /* tiles in use                                       */
+    float tuned_ms[4];     /* timings of {4,2}, {4,1}, {2,2}, {2,1} (tuned == 1) */
+    int64_t work_items;    /* thread blocks per apply                            */
+} ffm_batch_info_t;
+
+ffm_status_t ffm_batch_info(ffm_batch_t batch, ffm_batch_info_t *out);
+
+/* Free a batch (not its plans).  FFM_EBUSY if an apply is in flight. */
+ffm_status_t ffm_batch_destroy(ffm_batch_t batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,8 +25,12 @@ STATUS = {0: "FFM_OK", -1: "FFM_EINVAL", -2: "FFM_ENOMEM", -3: "FFM_EDEVICE", -4
 
 # every symbol the C ABI exports (include/ffm.h)
 EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_version", "ffm_plan_stats",
-            "ffm_plan_export", "ffm_plan_timing", "ffm_plan_bytes", "ffm_workspace_bytes"]
+            "ffm_plan_export", "ffm_plan_timing", "ffm_plan_bytes", "ffm_workspace_bytes",
+            "ffm_plan_set_tiles", "ffm_plan_get_tiles", "ffm_batch_create", "ffm_batch_apply", "ffm_batch_info",
+            "ffm_batch_destroy"]
 FFM_FLAG_TIMING = 1
+FFM_BATCH_GRAPH = 1
+FFM_BATCH_AUTOTUNE = 2
 TIMING_SLOTS = 64
 
 
@@ -63,6 +67,15 @@ class Stats(C.Structure):
         return out
 
 
+class Tiles(C.Structure):
+    _fields_ = [("ring_g", C.c_int32), ("bwd_pt", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("n", C.c_int32), ("launches", C.c_int32), ("graph", C.c_int32), ("tuned", C.c_int32),
+                ("tiles", Tiles), ("tuned_ms", C.c_float * 4), ("work_items", C.c_int64)]
+
+
 _lib = None
 
 
@@ -86,6 +99,12 @@ def lib():
             "ffm_plan_timing": (C.c_int, [P, P, i32]),
             "ffm_plan_bytes": (C.c_size_t, [P]),
             "ffm_workspace_bytes": (C.c_size_t, [P]),
+            "ffm_plan_set_tiles": (C.c_int, [P, P, P]),
+            "ffm_plan_get_tiles": (C.c_int, [P, P]),
+            "ffm_batch_create": (C.c_int, [P, i32, C.c_uint32, C.c_char_p, P, P]),
+            "ffm_batch_apply": (C.c_int, [P, P, P, P, P]),
+            "ffm_batch_info": (C.c_int, [P, P]),
+            "ffm_batch_destroy": (C.c_int, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -216,6 +235,15 @@ class Plan:
         _check(lib().ffm_plan_timing(self._h, buf, TIMING_SLOTS))
         return list(buf)
 
+    def set_tiles(self, ring_g: int, bwd_pt: int, stream=None):
+        """Rebuild the plane-wave kernels' launches for a tile choice (ring_g in {2, 4}, bwd_pt in {1, 2})."""
+        _check(lib().ffm_plan_set_tiles(self._h, C.byref(Tiles(int(ring_g), int(bwd_pt))), _stream(stream)))
+
+    def tiles(self) -> tuple:
+        t = Tiles()
+        _check(lib().ffm_plan_get_tiles(self._h, C.byref(t)))
+        return (t.ring_g, t.bwd_pt)
+
     def plan_bytes(self) -> int:
         return int(lib().ffm_plan_bytes(self._h))
 
@@ -231,6 +259,69 @@ class Plan:
         try:
             if getattr(self, "_h", None):
                 lib().ffm_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many plans applied together: one launch per step kind for all instances (ffm_batch_*).
+
+    ``Batch(plans, graph=True, autotune=False, cache=None)``; ``apply(wus, outs=None)`` returns the list of
+    outputs (complex64, each instance's caller order).  The plans stay owned by the caller and must outlive
+    the batch (the batch keeps references to them).
+    """
+
+    def __init__(self, plans, graph: bool = True, autotune: bool = False, cache: str | None = None, stream=None):
+        import torch
+        self.plans = list(plans)
+        n = len(self.plans)
+        arr = (C.c_void_p * n)(*[p._h for p in self.plans])
+        flags = (FFM_BATCH_GRAPH if graph else 0) | (FFM_BATCH_AUTOTUNE if autotune else 0)
+        h = C.c_void_p()
+        self._h = None
+        with torch.cuda.device(self.plans[0].device):
+            _check(lib().ffm_batch_create(arr, n, flags, cache.encode() if cache else None, _stream(stream),
+                                          C.byref(h)))
+        self._h = h.value
+
+    def apply(self, wus, outs=None, stream=None):
+        import torch
+        n = len(self.plans)
+        if len(wus) != n:
+            raise ValueError("one input per plan")
+        wus = [w.contiguous() for w in wus]
+        for p, w in zip(self.plans, wus):
+            if w.shape[0] != p.n_y or not w.is_cuda:
+                raise ValueError("wu[i] must be a CUDA tensor of length n_y of plan i")
+        if outs is None:
+            outs = [torch.empty(p.n_x, dtype=torch.complex64, device=p.device) for p in self.plans]
+        for p, o in zip(self.plans, outs):
+            if o.dtype != torch.complex64 or o.shape[0] != p.n_x or not o.is_contiguous():
+                raise ValueError("outs[i] must be a contiguous complex64 tensor of length n_x of plan i")
+        wp = (C.c_void_p * n)(*[w.data_ptr() for w in wus])
+        dt = (C.c_int32 * n)(*[_dtype_code(w) for w in wus])
+        vp = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        self._keep = (wus, outs)
+        _check(lib().ffm_batch_apply(self._h, wp, dt, vp, _stream(stream)))
+        return outs
+
+    def info(self) -> dict:
+        b = BatchInfo()
+        _check(lib().ffm_batch_info(self._h, C.byref(b)))
+        return {"n": b.n, "launches": b.launches, "graph": b.graph, "tuned": b.tuned,
+                "tiles": (b.tiles.ring_g, b.tiles.bwd_pt), "tuned_ms": list(b.tuned_ms),
+                "work_items": b.work_items}
+
+    def destroy(self):
+        if self._h:
+            _check(lib().ffm_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().ffm_batch_destroy(self._h)
                 self._h = None
         except Exception:
             pass

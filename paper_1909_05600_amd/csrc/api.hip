@@ -24,29 +24,13 @@ long long fail_after() {
     return v;
 }
 
+}  // namespace
+
 int set_err(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
-
-struct Guard {
-    // maps exceptions to status codes; every ABI entry runs inside one
-    template <class F>
-    static int run(F &&f) {
-        try {
-            g_err.clear();
-            f();
-            return FFM_OK;
-        } catch (const Error &e) {
-            return set_err(e.code, e.what());
-        } catch (const std::bad_alloc &) {
-            return set_err(FFM_ENOMEM, "host allocation failed");
-        } catch (const std::exception &e) {
-            return set_err(FFM_EINTERNAL, e.what());
-        }
-    }
-};
-}  // namespace
+void clear_err() { g_err.clear(); }
 
 // Device memory comes from a process-wide cache: a freed block goes back to a free list keyed by its
 // rounded size and the next request of that size takes it without a hipMalloc.  Plans are rebuilt
@@ -155,10 +139,6 @@ size_t dev_bytes_live() { return (size_t)std::max<long long>(0, g_live_bytes.loa
 
 using namespace ffm;
 
-struct ffm_plan_s {
-    Plan P;
-};
-
 extern "C" {
 
 const char *ffm_last_error(void) { return g_err.c_str(); }
@@ -230,6 +210,7 @@ ffm_status_t ffm_apply(ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, vo
 
 ffm_status_t ffm_destroy(ffm_plan_t plan) {
     if (!plan) return FFM_OK;
+    if (plan->P.batch_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: the plan belongs to a batch");
     if (plan->P.done && plan->P.applied) {
         hipError_t q = hipEventQuery(plan->P.done);
         if (q == hipErrorNotReady) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: an apply is still in flight");

@@ -79,6 +79,15 @@ __global__ void __launch_bounds__(kThreads) k_zero_out(float2 *v, int64_t n) {
     if (i < n) v[i] = make_float2(0.f, 0.f);
 }
 
+// item (desc, first index): vout[i] = 0 for i < nx (an instance without sources inside a batch)
+__global__ void __launch_bounds__(kThreads)
+k_zero_io(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int64_t i = (int64_t)wk.y + threadIdx.x;
+    if (i < d.nx) io[d.inst].vout[i] = make_float2(0.f, 0.f);
+}
+
 // item (desc, first index): vout[perm_x[i]] = v[i]
 __global__ void __launch_bounds__(kThreads)
 k_perm_out(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const int4 *__restrict__ work) {
@@ -320,8 +329,9 @@ k_pw_forward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__,
             float sn, cs;
             sincos_rev((float)(C - floor(C)), sn, cs);
             const float2 uu = d.u[i];
-            sU[r][j] = make_float4(uu.x * cs + uu.y * sn, uu.y * cs - uu.x * sn, uu.x * cs - uu.y * sn,
-                                   uu.y * cs + uu.x * sn);
+            // explicit fused forms: the rounding must not depend on how the compiler contracts
+            sU[r][j] = make_float4(fmaf(uu.x, cs, uu.y * sn), fmaf(uu.y, cs, -(uu.x * sn)),
+                                   fmaf(uu.x, cs, -(uu.y * sn)), fmaf(uu.y, cs, uu.x * sn));
         }
         __syncthreads();
         if (active) {
@@ -474,8 +484,9 @@ k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__
         }
 #pragma unroll
         for (int q = 0; q < PT; ++q) {
-            vr[q] += ecs[q] * (xre[q] + yre[q]) - esn[q] * (xim[q] - yim[q]);
-            vi[q] += ecs[q] * (xim[q] + yim[q]) + esn[q] * (xre[q] - yre[q]);
+            // explicit fused forms, so every points-per-thread variant rounds identically
+            vr[q] = fmaf(ecs[q], xre[q] + yre[q], fmaf(-esn[q], xim[q] - yim[q], vr[q]));
+            vi[q] = fmaf(ecs[q], xim[q] + yim[q], fmaf(esn[q], xre[q] - yre[q], vi[q]));
         }
     }
 #pragma unroll
@@ -855,6 +866,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_MFMA16: threads = 64; return k_lag_mfma16;
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
+        case K_ZERO_OUT: return k_zero_io;
         default: throw Error(FFM_EINTERNAL, "unknown kernel variant");
     }
 }

@@ -33,6 +33,27 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::ffm::Error((code), (msg));                                             \
     } while (0)
 
+// Error state of the C ABI: a thread-local message for ffm_last_error.  Every entry point runs its
+// body inside Guard::run, which maps exceptions to status codes.
+int set_err(int code, const std::string &msg);
+void clear_err();
+struct Guard {
+    template <class F>
+    static int run(F &&f) {
+        try {
+            clear_err();
+            f();
+            return FFM_OK;
+        } catch (const Error &e) {
+            return set_err(e.code, e.what());
+        } catch (const std::bad_alloc &) {
+            return set_err(FFM_ENOMEM, "host allocation failed");
+        } catch (const std::exception &e) {
+            return set_err(FFM_EINTERNAL, e.what());
+        }
+    }
+};
+
 // Kernel launches go through this so a bad configuration becomes an error, not a fault.
 #define FFM_LAUNCH(kern, grid, block, shmem, stream, ...)                                           \
     do {                                                                                            \
@@ -182,7 +203,7 @@ struct LDesc {
 // Kernel variants (the template parameters travel with the stage).
 enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
-    K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT
+    K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT
 };
 
 struct Stage {
@@ -272,6 +293,7 @@ struct Plan {
     ffm_stats_t stats{};
     hipEvent_t done = nullptr;           // recorded after every apply
     bool applied = false;
+    int batch_refs = 0;                  // batches that launch this plan's stages
     // execution: descriptors (index = level), I/O table, stages before and after the levels
     std::vector<LDesc> hdesc;
     DevBuf<LDesc> ddesc;
@@ -297,6 +319,8 @@ struct LevelWork {                     // workspace of one level (a batch keeps 
     float2 *ut2 = nullptr, *Z = nullptr;
 };
 LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w);
+// rebuild the stages and descriptors of a built plan for a tile choice (the plan must be idle)
+void plan_set_tune(Plan &P, const Tune &t, hipStream_t st);
 // one launch per stage
 void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream_t st);
 
@@ -307,3 +331,8 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t 
 void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st, Scratch &S);      // stable
 
 }  // namespace ffm
+
+// the opaque handle of the C ABI
+struct ffm_plan_s {
+    ffm::Plan P;
+};

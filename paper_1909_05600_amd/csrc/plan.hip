@@ -963,22 +963,10 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.wz.alloc(ws_z);
     if (P.any_fp16) P.amax.alloc(1);
     // launches and descriptors
-    plan_stages(P, P.tune, st);
     P.dio.alloc(1);
     P.hio = static_cast<IoEntry *>(pinned_alloc(sizeof(IoEntry)));
     std::memset(P.hio, 0, sizeof(IoEntry));
-    {
-        LevelWork w;
-        w.ut = P.wsrc.p;
-        w.vt = P.wtgt.p;
-        w.part = P.wpart.p;
-        w.ut2 = reinterpret_cast<float2 *>(P.wsrc.p);
-        w.Z = P.wz.p;
-        P.hdesc.clear();
-        for (int l = 0; l <= P.leaf; ++l)
-            P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
-        upload(P.ddesc, P.hdesc, st, SC);
-    }
+    plan_set_tune(P, P.tune, st);
     FFM_HIP(hipStreamSynchronize(st));
     plog.mark("workspace");
 
@@ -1189,6 +1177,22 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.maxpts = LV.max_src_pts;
     d.sT = LV.sT;
     return d;
+}
+
+void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st) {
+    plan_stages(P, tu, st);
+    P.tune = tu;
+    if (P.empty) return;
+    LevelWork w;
+    w.ut = P.wsrc.p;
+    w.vt = P.wtgt.p;
+    w.part = P.wpart.p;
+    w.ut2 = reinterpret_cast<float2 *>(P.wsrc.p);
+    w.Z = P.wz.p;
+    P.hdesc.clear();
+    for (int l = 0; l <= P.leaf; ++l) P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
+    Scratch SC(st);
+    upload(P.ddesc, P.hdesc, st, SC);
 }
 
 size_t plan_device_bytes(const Plan &P) {

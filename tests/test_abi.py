@@ -71,6 +71,25 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
     assert L.ffm_plan_export(None, 0, 0, 0, None, C.byref(cnt)) == -1
 
 
+def test_batch_arguments_are_rejected_before_any_device_work(L):
+    import paper_1909_05600_amd as ffm
+    h = C.c_void_p()
+    arr = (C.c_void_p * 2)(None, None)
+    assert L.ffm_batch_create(arr, 2, 0, None, None, None) == -1          # out == NULL
+    assert L.ffm_batch_create(None, 2, 0, None, None, C.byref(h)) == -1   # no plans
+    assert L.ffm_batch_create(arr, 0, 0, None, None, C.byref(h)) == -1    # n <= 0
+    assert L.ffm_batch_create(arr, 2, 0, None, None, C.byref(h)) == -1    # NULL plan
+    assert L.ffm_batch_create(arr, 2, 8, None, None, C.byref(h)) == -1    # unknown flag
+    assert h.value is None
+    assert L.ffm_batch_apply(None, None, None, None, None) == -1
+    assert L.ffm_batch_info(None, None) == -1
+    assert L.ffm_batch_destroy(None) == 0
+    t = ffm.Tiles(4, 2)
+    assert L.ffm_plan_set_tiles(None, C.byref(t), None) == -1
+    assert L.ffm_plan_get_tiles(None, C.byref(t)) == -1
+    assert "batch" in L.ffm_last_error().decode() or "tiles" in L.ffm_last_error().decode()
+
+
 def test_oracle_is_not_linked_into_the_product():
     """The GPU library and its binding never reference the oracle."""
     pkg = os.path.join(ROOT, "paper_1909_05600_amd")
