@@ -259,6 +259,63 @@ ffm_status_t ffm_batch_info(ffm_batch_t batch, ffm_batch_info_t *out);
 /* Free a batch (not its plans).  FFM_EBUSY if an apply is in flight. */
 ffm_status_t ffm_batch_destroy(ffm_batch_t batch);
 
+/* ------------------------------------------------------------------ serving
+ * Not in the paper (its applications call the product repeatedly inside an
+ * iterative solver, Sec. 5).  A server keeps plans resident and runs apply
+ * requests submitted from any host thread: a scheduler thread admits queued
+ * requests in submission order as soon as one of `slots` HIP streams is free
+ * and the request's apply workspace (ffm_stats_t.workspace_bytes of its plan)
+ * fits in the part of `budget_bytes` not held by running requests.  Each
+ * running request owns its workspace, so requests of different plans, or of
+ * the same plan, run concurrently; each computes bitwise what ffm_apply
+ * computes for its plan.
+ */
+typedef struct ffm_server_s *ffm_server_t;
+
+typedef struct {
+    int32_t slots;          /* concurrent requests (streams), 1..16; 0 = 4        */
+    int32_t reserved;       /* must be 0                                          */
+    double  budget_bytes;   /* device memory for request workspaces; 0 = 80% of the free memory at creation */
+} ffm_server_options_t;
+
+/* Start a server on the current device.  opts may be NULL (defaults). */
+ffm_status_t ffm_server_create(const ffm_server_options_t *opts, ffm_server_t *out);
+
+/*
+ * ffm_server_submit -- queue v = FFM(wu) for a plan; returns at once with a
+ * ticket.  wu and v are device pointers with the layouts of ffm_apply; wu must
+ * already hold its values (the request runs on the server's own streams, with
+ * no ordering against the caller's streams) and both must stay valid until
+ * the request completes.  The plan may not be destroyed or retiled while it
+ * has pending requests (FFM_EBUSY).  FFM_ENOMEM if the workspace exceeds the
+ * whole budget.  Thread-safe.
+ */
+ffm_status_t ffm_server_submit(ffm_server_t server, ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, void *v,
+                               int64_t *ticket);
+
+/* Block until the request completes; *latency_ms (nullable) receives the
+ * time from submission to observed completion.  Each ticket is waited for
+ * once; returns the request's own error status if it failed. */
+ffm_status_t ffm_server_wait(ffm_server_t server, int64_t ticket, double *latency_ms);
+
+/* *done = 1 if the request has completed (the ticket stays valid until waited for). */
+ffm_status_t ffm_server_poll(ffm_server_t server, int64_t ticket, int32_t *done);
+
+typedef struct {
+    int32_t slots;
+    int32_t running, peak_running;
+    int32_t reserved;
+    int64_t completed, failed, queued;
+    double  budget_bytes, in_use_bytes, peak_in_use_bytes;
+    double  points;         /* sum of target counts of completed requests */
+    double  p50_ms, p99_ms, max_ms;   /* latency quantiles of completed requests */
+} ffm_server_stats_t;
+
+ffm_status_t ffm_server_stats(ffm_server_t server, ffm_server_stats_t *out);
+
+/* Finish every queued and running request, then stop the server. */
+ffm_status_t ffm_server_destroy(ffm_server_t server);
+
 #ifdef __cplusplus
 }
 #endif

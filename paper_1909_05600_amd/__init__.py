@@ -27,7 +27,8 @@ STATUS = {0: "FFM_OK", -1: "FFM_EINVAL", -2: "FFM_ENOMEM", -3: "FFM_EDEVICE", -4
 EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_version", "ffm_plan_stats",
             "ffm_plan_export", "ffm_plan_timing", "ffm_plan_bytes", "ffm_workspace_bytes",
             "ffm_plan_set_tiles", "ffm_plan_get_tiles", "ffm_batch_create", "ffm_batch_apply", "ffm_batch_info",
-            "ffm_batch_destroy"]
+            "ffm_batch_destroy", "ffm_server_create", "ffm_server_submit", "ffm_server_wait", "ffm_server_poll",
+            "ffm_server_stats", "ffm_server_destroy"]
 FFM_FLAG_TIMING = 1
 FFM_BATCH_GRAPH = 1
 FFM_BATCH_AUTOTUNE = 2
@@ -76,6 +77,17 @@ class BatchInfo(C.Structure):
                 ("tiles", Tiles), ("tuned_ms", C.c_float * 4), ("work_items", C.c_int64)]
 
 
+class ServerOptions(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("reserved", C.c_int32), ("budget_bytes", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("running", C.c_int32), ("peak_running", C.c_int32),
+                ("reserved", C.c_int32), ("completed", C.c_int64), ("failed", C.c_int64), ("queued", C.c_int64),
+                ("budget_bytes", C.c_double), ("in_use_bytes", C.c_double), ("peak_in_use_bytes", C.c_double),
+                ("points", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -105,6 +117,12 @@ def lib():
             "ffm_batch_apply": (C.c_int, [P, P, P, P, P]),
             "ffm_batch_info": (C.c_int, [P, P]),
             "ffm_batch_destroy": (C.c_int, [P]),
+            "ffm_server_create": (C.c_int, [P, P]),
+            "ffm_server_submit": (C.c_int, [P, P, P, C.c_int, P, P]),
+            "ffm_server_wait": (C.c_int, [P, i64, P]),
+            "ffm_server_poll": (C.c_int, [P, i64, P]),
+            "ffm_server_stats": (C.c_int, [P, P]),
+            "ffm_server_destroy": (C.c_int, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -322,6 +340,65 @@ class Batch:
         try:
             if getattr(self, "_h", None):
                 lib().ffm_batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Server:
+    """Resident-plan request loop (ffm_server_*): ``submit(plan, wu, out=None)`` queues one apply and returns
+    (ticket, out); ``wait(ticket)`` blocks until it completes and returns its latency in ms."""
+
+    def __init__(self, slots: int = 4, budget_bytes: float = 0.0):
+        opts = ServerOptions(int(slots), 0, float(budget_bytes))
+        h = C.c_void_p()
+        self._h = None
+        _check(lib().ffm_server_create(C.byref(opts), C.byref(h)))
+        self._h = h.value
+        self._live = {}
+
+    def submit(self, plan: Plan, wu, out=None):
+        import torch
+        if wu.shape[0] != plan.n_y or not wu.is_cuda or not wu.is_contiguous():
+            raise ValueError("wu must be a contiguous CUDA tensor of length n_y")
+        if out is None:
+            out = torch.empty(plan.n_x, dtype=torch.complex64, device=plan.device)
+        elif out.dtype != torch.complex64 or out.shape[0] != plan.n_x or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 tensor of length n_x")
+        t = C.c_int64()
+        _check(lib().ffm_server_submit(self._h, plan._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(),
+                                       C.byref(t)))
+        self._live[t.value] = (plan, wu, out)     # keep the buffers alive until the request is waited for
+        return t.value, out
+
+    def wait(self, ticket: int) -> float:
+        lat = C.c_double()
+        try:
+            _check(lib().ffm_server_wait(self._h, int(ticket), C.byref(lat)))
+        finally:
+            self._live.pop(int(ticket), None)
+        return lat.value
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        _check(lib().ffm_server_poll(self._h, int(ticket), C.byref(d)))
+        return bool(d.value)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().ffm_server_stats(self._h, C.byref(s)))
+        return {name: getattr(s, name) for name, _ in s._fields_ if name != "reserved"}
+
+    def destroy(self):
+        if self._h:
+            _check(lib().ffm_server_destroy(self._h))
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().ffm_server_destroy(self._h)
                 self._h = None
         except Exception:
             pass

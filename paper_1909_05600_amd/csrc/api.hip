@@ -211,6 +211,7 @@ ffm_status_t ffm_apply(ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, vo
 ffm_status_t ffm_destroy(ffm_plan_t plan) {
     if (!plan) return FFM_OK;
     if (plan->P.batch_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: the plan belongs to a batch");
+    if (plan->P.server_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: server requests of the plan are pending");
     if (plan->P.done && plan->P.applied) {
         hipError_t q = hipEventQuery(plan->P.done);
         if (q == hipErrorNotReady) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: an apply is still in flight");

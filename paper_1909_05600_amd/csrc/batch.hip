@@ -334,6 +334,7 @@ ffm_status_t ffm_plan_set_tiles(ffm_plan_t plan, const ffm_tiles_t *tiles, void 
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_set_tiles: ring_g must be 2 or 4, bwd_pt 1 or 2");
     Plan &P = plan->P;
     if (P.batch_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: the plan belongs to a batch");
+    if (P.server_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: server requests of the plan are pending");
     return (ffm_status_t)Guard::run([&] {
         if (P.applied) FFM_HIP(hipEventSynchronize(P.done));
         Tune t;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -294,6 +295,7 @@ struct Plan {
     hipEvent_t done = nullptr;           // recorded after every apply
     bool applied = false;
     int batch_refs = 0;                  // batches that launch this plan's stages
+    std::atomic<int> server_refs{0};     // server requests of this plan queued or running
     // execution: descriptors (index = level), I/O table, stages before and after the levels
     std::vector<LDesc> hdesc;
     DevBuf<LDesc> ddesc;

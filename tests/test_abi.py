@@ -90,6 +90,23 @@ def test_batch_arguments_are_rejected_before_any_device_work(L):
     assert "batch" in L.ffm_last_error().decode() or "tiles" in L.ffm_last_error().decode()
 
 
+def test_server_arguments_are_rejected_before_any_device_work(L):
+    import paper_1909_05600_amd as ffm
+    h = C.c_void_p()
+    assert L.ffm_server_create(None, None) == -1                                    # out == NULL
+    for bad in (ffm.ServerOptions(-1, 0, 0.0), ffm.ServerOptions(17, 0, 0.0), ffm.ServerOptions(2, 1, 0.0),
+                ffm.ServerOptions(2, 0, -5.0), ffm.ServerOptions(2, 0, float("nan"))):
+        assert L.ffm_server_create(C.byref(bad), C.byref(h)) == -1
+    assert h.value is None
+    t = C.c_int64()
+    assert L.ffm_server_submit(None, None, None, 0, None, C.byref(t)) == -1
+    assert L.ffm_server_wait(None, 1, None) == -1
+    d = C.c_int32()
+    assert L.ffm_server_poll(None, 1, C.byref(d)) == -1
+    assert L.ffm_server_stats(None, None) == -1
+    assert L.ffm_server_destroy(None) == 0
+
+
 def test_oracle_is_not_linked_into_the_product():
     """The GPU library and its binding never reference the oracle."""
     pkg = os.path.join(ROOT, "paper_1909_05600_amd")
