@@ -33,6 +33,21 @@ PEAK_ALU_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12          # 78.6
 #   ring-pair form:      per (point, group of 4 dirs)   2 phase + 1 fract + 8 accumulate = 11 slots / 4 directions
 SLOTS_PER_DIRECTION = {1: 8 / 2, 2: 11 / 4}
 
+# HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
+# workload (profiles/traffic_pw_rings_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
+# kernel of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel source they were taken on.
+TRAFFIC_SOURCE_HASH = "a4c5347dc3f27bf8"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
+TRAFFIC = {
+    "k_pw_backward_rings<2, false>": (96725.0 * 2.0 + 8248.0) * 1024.0,
+    "k_pw_forward_rings<4, false>": (25328.5 * 2.0 + 156852.5) * 1024.0,
+}
+
+
+def _source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1909_05600_amd", "csrc", "apply.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -43,6 +58,13 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-strides", type=str, default="64,128")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serving-matvecs", type=int, default=10,
+                    help="dependent matvecs per session in the serving workload (50 in the full study)")
+    ap.add_argument("--serving-loads", type=str, default="0.8",
+                    help="offered loads as fractions of the one-at-a-time capacity, e.g. 0.5,0.8,0.95")
+    ap.add_argument("--serving-slots", type=int, default=4)
     return ap.parse_args()
 
 
@@ -73,6 +95,156 @@ def cpu_baseline(w, strides):
     }
 
 
+def _sync_time(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def batched(reps=5):
+    """256 independent instances (N log-uniform in [2e3, 2e5], half Laplace / half Helmholtz, sphere /
+    ellipsoid / cube; resident plans): apply points/s of (a) one ffm_apply per instance in FP32, (b) the
+    FP32 batch replayed from a HIP graph with autotuned tiles, (c) the same with mixed-precision plans
+    (FP16 MFMA transfers on Lagrange levels); accuracy of (b) and (c) against FP64 dense rows (16 sampled
+    targets per instance)."""
+    import torch
+    import ffm_workloads as W
+    import oracle
+    import paper_1909_05600_amd as ffm
+    ws = W.batched_instances(256, seed=4)
+    n_tot = sum(w.n for w in ws)
+    Xs = [torch.from_numpy(w.X).cuda() for w in ws]
+    wus = [torch.from_numpy(w.wu).cuda() for w in ws]
+    outs = [torch.empty(w.n, dtype=torch.complex64, device="cuda") for w in ws]
+    res = {"instances": len(ws), "points": n_tot}
+    t0 = time.perf_counter()
+    p32 = [ffm.Plan(X, X, w.kernel, w.k, w.eps) for X, w in zip(Xs, ws)]
+    torch.cuda.synchronize()
+    res["plan_s_fp32"] = time.perf_counter() - t0
+    pmx = [ffm.Plan(X, X, w.kernel, w.k, w.eps, precision=ffm.FFM_PREC_MIXED) for X, w in zip(Xs, ws)]
+
+    def single():
+        for p, u, o in zip(p32, wus, outs):
+            p.apply(u, out=o)
+
+    single()
+    t = _sync_time(single, reps)
+    res["fp32_per_instance_points_per_s"] = n_tot / t
+    res["fp32_per_instance_ms"] = t * 1e3
+    for name, plans in (("fp32_batched_graph", p32), ("mixed_batched_graph", pmx)):
+        b = ffm.Batch(plans, graph=True, autotune=True)
+        o2 = [torch.empty_like(o) for o in outs]
+        b.apply(wus, outs=o2)
+        t = _sync_time(lambda: b.apply(wus, outs=o2), reps)
+        info = b.info()
+        errs = []
+        for w, o in zip(ws, o2):
+            rows = w.rows[:16]
+            d = oracle.dense_rows(w.X, w.X, w.wu, w.kernel, w.k, rows)
+            v = o.cpu().numpy()[rows].astype(np.complex128)
+            errs.append(float(np.linalg.norm(v - d) / np.linalg.norm(d)))
+        res[name + "_points_per_s"] = n_tot / t
+        res[name + "_ms"] = t * 1e3
+        res[name + "_launches"] = info["launches"]
+        res[name + "_tiles"] = list(info["tiles"])
+        res[name + "_err_max"] = max(errs)
+        res[name + "_err_median"] = float(np.median(errs))
+        b.destroy()
+    for p in p32 + pmx:
+        p.destroy()
+    res["eps"] = ws[0].eps
+    return res
+
+
+def serving(matvecs, loads, slots):
+    """64 resident plans (N log-uniform in [1e4, 5e6], Laplace / Helmholtz alternating, 10 points per
+    wavelength, sphere / ellipsoid / cube); a session is `matvecs` dependent applies u_{m+1} = v_m/|v_m|;
+    sessions start at Poisson times at a given fraction of the one-at-a-time capacity.  The same arrival
+    trace runs through the server with `slots` concurrent slots and through a one-slot server (requests
+    one at a time, in arrival order).  Reports points/s over the makespan and p50/p99 request latency
+    (submission to completion)."""
+    import torch
+    import ffm_workloads as W
+    import paper_1909_05600_amd as ffm
+    ws = W.serving_plans(64, seed=5)
+    plans, u0 = [], []
+    for w in ws:
+        X = torch.from_numpy(w.X).cuda()
+        plans.append(ffm.Plan(X, X, w.kernel, w.k, w.eps))
+        u0.append(torch.from_numpy(w.wu).cuda())
+        del X
+    torch.cuda.synchronize()
+    # one-at-a-time service time of a session -> capacity in sessions/s
+    t_apply = []
+    for p, u in zip(plans, u0):
+        p.apply(u)
+        t_apply.append(_sync_time(lambda: p.apply(u), 1))
+    t_session = matvecs * float(np.mean(t_apply))
+    out = {"plans": len(plans), "points_per_request_mean": float(np.mean([w.n for w in ws])),
+           "matvecs_per_session": matvecs, "session_s_one_at_a_time": t_session, "loads": []}
+    norm_stream = torch.cuda.Stream()
+
+    def run(rate, nslots):
+        arr = W.poisson_arrivals(len(plans), rate, seed=5)
+        srv = ffm.Server(slots=nslots)
+        state = [None] * len(plans)       # (ticket, out, step)
+        lat = []
+        started = done = 0
+        total_pts = 0.0
+        t0 = time.perf_counter()
+        while done < len(plans):
+            now = time.perf_counter() - t0
+            progressed = False
+            while started < len(plans) and arr[started] <= now:
+                t, o = srv.submit(plans[started], u0[started])
+                state[started] = (t, o, 0)
+                started += 1
+                progressed = True
+            for i in range(started):
+                st = state[i]
+                if st is None or not srv.poll(st[0]):
+                    continue
+                lat.append(srv.wait(st[0]))
+                total_pts += plans[i].n_x
+                step = st[2] + 1
+                progressed = True
+                if step == matvecs:
+                    state[i] = None
+                    done += 1
+                    continue
+                with torch.cuda.stream(norm_stream):
+                    v = st[1]
+                    u = (v / torch.linalg.vector_norm(v)).contiguous()
+                norm_stream.synchronize()
+                t, o = srv.submit(plans[i], u)
+                state[i] = (t, o, step)
+            if not progressed:
+                time.sleep(50e-6)
+        makespan = time.perf_counter() - t0
+        srv.destroy()
+        return {"points_per_s": total_pts / makespan, "makespan_s": makespan,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "requests": len(lat)}
+
+    for rho in loads:
+        rate = rho / t_session
+        served = run(rate, slots)
+        fifo = run(rate, 1)
+        out["loads"].append({"load": rho, "sessions_per_s": rate, "server": served, "one_at_a_time": fifo,
+                             "slots": slots})
+        print("serving load %.2f: %d-slot %.3g pts/s p50 %.1f ms p99 %.1f ms | one-at-a-time %.3g pts/s "
+              "p50 %.1f ms p99 %.1f ms" % (rho, slots, served["points_per_s"], served["p50_ms"],
+                                          served["p99_ms"], fifo["points_per_s"], fifo["p50_ms"],
+                                          fifo["p99_ms"]), file=sys.stderr, flush=True)
+    for p in plans:
+        p.destroy()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -93,9 +265,12 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
+    tiles = [4, 2]
+
     def step(record):
         t0 = time.perf_counter()
         plan = ffm.Plan(X, X, ffm.FFM_HELMHOLTZ, w.k, w.eps, timing=True)
+        tiles[:] = plan.tiles()
         t1 = time.perf_counter()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -127,21 +302,28 @@ def main():
     st = rec["stats"]
     ph = np.array(rec["phases"])          # [steps][64]
     leaf = st["leaf"]
-    # plane-wave transform kernels: forward (slot 1 + 3(l-1)) and backward (slot 3 + 3(l-1))
-    fwd_ms = bwd_ms = fwd_slots = bwd_slots = 0.0
-    nlaunch = 0
-    for l in range(1, leaf + 1):
-        if st["method"][l] != 2:
-            continue
-        per_dir = SLOTS_PER_DIRECTION[st["tform"][l]]
-        fwd_ms += ph[:, 1 + 3 * (l - 1)].sum()
-        bwd_ms += ph[:, 3 + 3 * (l - 1)].sum()
-        fwd_slots += args.steps * st["fwd_points"][l] * st["nq"][l] * per_dir
-        bwd_slots += args.steps * st["bwd_points"][l] * st["nq"][l] * per_dir
-        nlaunch += args.steps
-    dom = "plane-wave forward transform" if fwd_ms >= bwd_ms else "plane-wave backward transform"
-    d_ms, d_slots = (fwd_ms, fwd_slots) if fwd_ms >= bwd_ms else (bwd_ms, bwd_slots)
+    # Dominant kernel: the ring-pair plane-wave transform (forward, slot 1 + 3(l-1), or backward, slot
+    # 3 + 3(l-1)) with the larger total time; its launches are the ring-pair levels of the apply.
+    ring = [l for l in range(1, leaf + 1) if st["method"][l] == 2 and st["tform"][l] == 2]
+    fwd_ms = {l: ph[:, 1 + 3 * (l - 1)].sum() for l in ring}
+    bwd_ms = {l: ph[:, 3 + 3 * (l - 1)].sum() for l in ring}
+    per_dir = SLOTS_PER_DIRECTION[2]
+    if sum(bwd_ms.values()) >= sum(fwd_ms.values()):
+        t_ms, pts, name = bwd_ms, "bwd_points", "k_pw_backward_rings<%d, %s>"
+        tile = tiles[1]
+    else:
+        t_ms, pts, name = fwd_ms, "fwd_points", "k_pw_forward_rings<%d, %s>"
+        tile = tiles[0]
+    # one kernel symbol: the levels sharing the phase precision of the most expensive level
+    lmax = max(ring, key=lambda l: t_ms[l])
+    p64 = st["phase64"][lmax]
+    lv = [l for l in ring if st["phase64"][l] == p64]
+    dom = name % (tile, "true" if p64 else "false")
+    d_ms = sum(t_ms[l] for l in lv)
+    d_slots = sum(args.steps * st[pts][l] * st["nq"][l] * per_dir for l in lv)
+    nlaunch = args.steps * len(lv)
     achieved = 2 * d_slots / (d_ms * 1e-3) / 1e12 if d_ms > 0 else 0.0
+    traffic = TRAFFIC.get(dom) if _source_hash() == TRAFFIC_SOURCE_HASH else None
     phase_mean = ph.mean(axis=0)
     names = {0: "perm_in", 61: "near_field", 62: "perm_out"}
     for l in range(1, leaf + 1):
@@ -173,18 +355,29 @@ def main():
         "phases_ms": phases,
         "roofline": {
             "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
             "launches": nlaunch, "avg_launch_ms": d_ms / max(nlaunch, 1),
-            "work": "non-transcendental VALU issue slots x 2 (FMA-equivalent flops) of the implemented form: "
-                    "11 per (point, 4 directions) in ring-pair levels, 8 per (point, 2 directions) otherwise; "
+            "work": "non-transcendental VALU issue slots x 2 (FMA-equivalent flops) of the ring-pair form: "
+                    "11 per (point, 4 quadrature directions), over the ring-pair levels; "
                     "peak = 256 CU x 64 lanes x 2.4 GHz x 2",
+            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy)",
         },
         "levels": {"leaf": leaf, "nq": [int(x) for x in st["nq"][:leaf + 1]],
                    "transform_form": [int(x) for x in st["tform"][:leaf + 1]],
                    "nfar": [int(x) for x in st["nfar"][:leaf + 1]], "near_pairs": st["near_pairs"],
                    "transform_terms": st["transform_terms"]},
     }
+    del X, wu, out
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("bench: batched workload", file=sys.stderr, flush=True)
+        res["batched"] = batched()
+    if not args.no_serving:
+        print("bench: serving workload", file=sys.stderr, flush=True)
+        res["serving"] = serving(args.serving_matvecs, [float(x) for x in args.serving_loads.split(",")],
+                                 args.serving_slots)
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         strides = tuple(int(s) for s in args.cpu_strides.split(","))
         res["cpu_baseline"] = cpu_baseline(w, strides)
     print(json.dumps(res), flush=True)

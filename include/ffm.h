@@ -135,6 +135,7 @@ typedef struct {
     int32_t order[FFM_MAX_LEVELS];         /* r1 (Lagrange) or L (Gegenbauer)              */
     int32_t tform[FFM_MAX_LEVELS];         /* Gegenbauer transform kernels: 1 direction pairs, 2 ring pairs */
     int32_t prec[FFM_MAX_LEVELS];          /* transfer arithmetic: 0 FP32, 1 FP16 MFMA with FP32 accumulation */
+    int32_t phase64[FFM_MAX_LEVELS];       /* Gegenbauer in-plane phases in FP64 (1) or FP32 (0) */
     int32_t nclass[FFM_MAX_LEVELS];        /* distinct translations at level l             */
     int64_t nq[FFM_MAX_LEVELS];            /* quadrature directions (Gegenbauer levels)    */
     double  fwd_points[FFM_MAX_LEVELS];    /* points of the source boxes transformed at level l */

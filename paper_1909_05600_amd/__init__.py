@@ -54,7 +54,7 @@ class Stats(C.Structure):
                 ("corner_x", C.c_double * 3), ("corner_y", C.c_double * 3),
                 ("nbox_x", C.c_int64 * _L), ("nbox_y", C.c_int64 * _L), ("nfar", C.c_int64 * _L),
                 ("nnear", C.c_int64 * _L), ("method", C.c_int32 * _L), ("order", C.c_int32 * _L),
-                ("tform", C.c_int32 * _L), ("prec", C.c_int32 * _L),
+                ("tform", C.c_int32 * _L), ("prec", C.c_int32 * _L), ("phase64", C.c_int32 * _L),
                 ("nclass", C.c_int32 * _L), ("nq", C.c_int64 * _L), ("fwd_points", C.c_double * _L),
                 ("bwd_points", C.c_double * _L), ("transform_terms", C.c_double),
                 ("transfer_macs", C.c_double), ("near_pairs", C.c_double), ("plan_bytes", C.c_double),

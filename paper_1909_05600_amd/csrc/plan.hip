@@ -995,6 +995,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.fwd_points[l] = LV.pts_src;
         s.tform[l] = LV.method == kGegenbauer ? (LV.qG ? 2 : 1) : 0;
         s.prec[l] = LV.fp16 ? 1 : 0;
+        s.phase64[l] = LV.method == kGegenbauer && LV.phase64 ? 1 : 0;
         s.bwd_points[l] = LV.pts_tgt;
         if (LV.method == kGegenbauer) {
             s.transform_terms += (LV.pts_src + LV.pts_tgt) * (double)LV.nq;
