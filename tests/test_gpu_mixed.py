@@ -31,6 +31,9 @@ def test_mixed_laplace(orc, eps):
     print("mixed laplace eps=%g fp16=%s: vs oracle %.3e vs dense %.3e" % (eps, expect_fp16, e_o, e_d))
     assert e_d <= eps
     assert e_o <= (2.0 ** -11 if expect_fp16 else 2e-5)
+    if not expect_fp16:
+        # no FP16 level: the mixed plan runs exactly the FP32 kernels
+        assert np.array_equal(v, gpu_apply(gpu_plan(w.X, w.X, 0, 0.0, eps), w.wu))
 
 
 def test_mixed_helmholtz_low_frequency(orc):

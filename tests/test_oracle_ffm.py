@@ -6,6 +6,8 @@ eps = 1e-3 (plausibility only: the norm and the random points are not given).
 """
 import math
 
+import os
+
 import numpy as np
 import pytest
 
@@ -161,11 +163,16 @@ def test_ffm_uniform_shell_closed_form(orc, kernel, k, rho):
 
 
 def test_paper_error_range_plausibility(orc):
-    """At eps = 1e-3 the paper reports 8.0e-5 .. 3.5e-4; the oracle must at least be below eps."""
+    """At eps = 1e-3 the paper's Tables 1-2 report errors of 8.0e-5 .. 3.5e-4 (tests/golden): the oracle's
+    error on the 4096-point Laplace sphere lies between a tenth of the smallest printed value and eps.
+    (Plausibility only: the paper's own point sets and norms are not reproducible.)"""
+    import json
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.json")))
+    printed = gold["laplace_table_errors_eps_1e-3"]["value"] + gold["helmholtz_table_errors_eps_1e-3"]["value"]
     w = W.laplace_sphere(4096, seed=1)
     d = orc.dense_rows(w.X, w.X, w.wu, 0, 0.0, np.arange(w.n))
     e = _rel(orc.Plan(w.X, w.X, 0, 0.0, 1e-3).apply(w.wu), d)
-    assert 1e-6 < e < 1e-3
+    assert min(printed) / 10 < e < 1e-3, e
 
 
 def test_empty_sets(orc):

@@ -4,6 +4,8 @@ Paper: Sec. 2.1 (two octrees with equal cubic boxes), Sec. 2.2.1 (root cubes, d_
 Sec. 2.2.2 (admissibility), Sec. 2.2.4 (stopping rule), Sec. 3.2 proof of Prop. 1 (27 interactions
 of an interior box and 7^2 - 3^2 = 40 translations in 2-D).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -163,9 +165,15 @@ def _grid_points(m, dim, seed):
     return P
 
 
+def _paper(key):
+    import json
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.json")
+    return json.load(open(path))[key]["value"]
+
+
 def test_quadtree_counts_of_the_paper(orc):
     """Points on a plane make the octree a quadtree: an interior box has 27 far interactions and a
-    level has 7^2 - 3^2 = 40 distinct translations (proof of Prop. 1)."""
+    level has 7^2 - 3^2 = 40 distinct translations (Sec. 3.2, proof of Prop. 1; tests/golden)."""
     P = _grid_points(16, 2, 3)
     p = orc.Plan(P, P, 0, 0.0, 1e-3, n_leaf=1, max_level=5)
     assert p.leaf >= 4
@@ -175,9 +183,10 @@ def test_quadtree_counts_of_the_paper(orc):
     assert np.all(off[:, 2] == 0)
     counts = np.bincount(t, minlength=p.nbox(0, l))
     interior = np.all((ijk[:, :2] // 2 >= 1) & (ijk[:, :2] // 2 <= 6), axis=1)
-    assert np.all(counts[interior] == 27)
-    assert counts.max() == 27
-    assert len({tuple(o) for o in off}) == 40
+    n_far, n_tr = _paper("quadtree_interior_far_interactions"), _paper("quadtree_distinct_translations")
+    assert np.all(counts[interior] == n_far)
+    assert counts.max() == n_far
+    assert len({tuple(o) for o in off}) == n_tr
 
 
 def test_octree_counts(orc):
