@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--serving-loads", type=str, default="0.8",
                     help="offered loads as fractions of the one-at-a-time capacity, e.g. 0.5,0.8,0.95")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--mixed-study", action="store_true",
+                    help="only run the 10M-point sphere + cube study (FP32 and mixed precision at eps 1e-3, 1e-4)")
+    ap.add_argument("--mixed-n", type=int, default=10_000_000)
+    ap.add_argument("--mixed-rows", type=int, default=1024)
     return ap.parse_args()
 
 
@@ -245,6 +249,54 @@ def serving(matvecs, loads, slots):
     return out
 
 
+def mixed_study(n, n_rows, reps=3):
+    """Helmholtz on 80% sphere + 20% cube cluster points (non-uniform octree), k by ten points per wavelength
+    on the sphere: plan and apply time per precision mode and eps, and the error against FP64 dense rows on
+    sampled targets, overall and per target class (sphere / cube)."""
+    import torch
+    import ffm_workloads as W
+    import oracle
+    import paper_1909_05600_amd as ffm
+    out = {"n": n, "rows": n_rows, "runs": []}
+    w = W.sphere_plus_cube(n, seed=3, n_rows=n_rows)     # the points, u and rows do not depend on eps
+    out["k"] = w.k
+    X = torch.from_numpy(w.X).cuda()
+    wu = torch.from_numpy(w.wu).cuda()
+    t0 = time.perf_counter()
+    d = oracle.dense_rows(w.X, w.X, w.wu, 1, w.k, w.rows)
+    t_dense = time.perf_counter() - t0
+    sph = w.rows < w.meta["n_sphere"]
+    for eps in (1e-3, 1e-4):
+        for prec in (0, 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = ffm.Plan(X, X, 1, w.k, eps, precision=prec)
+            torch.cuda.synchronize()
+            t_plan = time.perf_counter() - t0
+            v = p.apply(wu)
+            t_apply = _sync_time(lambda: p.apply(wu, out=v), reps)
+            vv = v.cpu().numpy()[w.rows].astype(np.complex128)
+            st = p.stats()
+
+            def rl(a, b):
+                return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            r = {"eps": eps, "precision": "mixed" if prec else "fp32", "plan_s": t_plan, "apply_s": t_apply,
+                 "points_per_s": n / (t_plan + t_apply), "apply_points_per_s": n / t_apply,
+                 "err": rl(vv, d), "err_sphere": rl(vv[sph], d[sph]), "err_cube": rl(vv[~sph], d[~sph]),
+                 "leaf": st["leaf"], "methods": st["method"][:st["leaf"] + 1],
+                 "fp16_levels": [l for l in range(st["leaf"] + 1) if st["prec"][l]],
+                 "phase64_levels": [l for l in range(st["leaf"] + 1) if st["phase64"][l]],
+                 "plan_mb": st["plan_bytes"] / 1e6, "workspace_mb": st["workspace_bytes"] / 1e6,
+                 "dense_rows_s": t_dense}
+            out["runs"].append(r)
+            print("mixed study eps=%g %s: plan %.2fs apply %.3fs err %.2e (sphere %.2e cube %.2e)"
+                  % (eps, r["precision"], t_plan, t_apply, r["err"], r["err_sphere"], r["err_cube"]),
+                  file=sys.stderr, flush=True)
+            p.destroy()
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -256,6 +308,12 @@ def main():
     import torch
     import ffm_workloads as W
     import paper_1909_05600_amd as ffm
+
+    if args.mixed_study:
+        res = {"metric": "10M sphere + cube Helmholtz: points/s and error per precision mode",
+               "mixed_study": mixed_study(args.mixed_n, args.mixed_rows)}
+        print(json.dumps(res), flush=True)
+        return
 
     w = W.helmholtz_sphere(args.n, seed=2, eps=args.eps)
     dev = torch.device("cuda:0")

@@ -187,7 +187,7 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         }
         P.stats.plan_bytes = (double)plan_device_bytes(P);
         P.stats.workspace_bytes = (double)(P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() +
-                                           P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes());
+                                           P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() + P.wbpart.bytes());
         h = p.release();
     });
     if (rc == FFM_OK) *out = h;

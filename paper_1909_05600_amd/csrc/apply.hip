@@ -403,7 +403,7 @@ k_sum_segments(const LDesc *__restrict__ descs, const IoEntry *__restrict__, con
 // Backward transform in ring-pair form: per target point and ring pair m,
 //   v += e^{iC} sum_n [e^{iP} v~(m,n) + e^{-iP} v~(m,n+L)] + e^{-iC} sum_n [e^{iP} v~(L-m,n) + e^{-iP} v~(L-m,n+L)]
 // PT target points per thread; item (desc, target box, first point).
-template <int PT, bool P64>
+template <int PT, int U, bool P64>
 __global__ void __launch_bounds__(kThreads)
 k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     typedef typename std::conditional<P64, double, float>::type real;
@@ -429,7 +429,10 @@ k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__
     __shared__ float4 s01[kThreads], s23[kThreads];
     __shared__ real scf[kThreads], ssf[kThreads];
     const float4 *vb = d.vt + (int64_t)t * npair;
-    for (int m = 0; m < nrp; ++m) {
+    // this block's ring pairs (part wk.w of bsplit)
+    const int mper = (nrp + d.bsplit - 1) / d.bsplit;
+    const int mb = wk.w * mper, me = min(nrp, mb + mper);
+    for (int m = mb; m < me; ++m) {
         const double2 rg = d.rings[m];
         const bool eq = 2 * m == L;
         real A[PT], B[PT];
@@ -444,41 +447,55 @@ k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__
         }
         for (int n0 = 0; n0 < L; n0 += kThreads) {
             const int cnt = min(kThreads, L - n0);
+            // staged entries padded with zeros to a multiple of U (a zero term leaves every sum unchanged),
+            // so the inner loop runs in unrolled steps of U with immediate LDS offsets
+            const int cnt4 = (cnt + U - 1) / U * U;
             __syncthreads();
-            if (tid < cnt) {
+            if (tid < cnt4) {
                 const int n = n0 + tid;
-                const float4 p1 = vb[(int64_t)m * 2 * L + n];
-                if (eq) {
-                    s01[tid] = make_float4(p1.x + p1.z, p1.y + p1.w, p1.x - p1.z, p1.y - p1.w);
+                if (tid >= cnt) {
+                    s01[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                     s23[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    scf[tid] = (real)0;
+                    ssf[tid] = (real)0;
                 } else {
-                    const float4 p2 = vb[(int64_t)m * 2 * L + n + L];
-                    s01[tid] = make_float4(p1.x + p2.x, p1.y + p2.y, p1.x - p2.x, p1.y - p2.y);
-                    s23[tid] = make_float4(p2.z + p1.z, p2.w + p1.w, p2.z - p1.z, p2.w - p1.w);
+                    const float4 p1 = vb[(int64_t)m * 2 * L + n];
+                    if (eq) {
+                        s01[tid] = make_float4(p1.x + p1.z, p1.y + p1.w, p1.x - p1.z, p1.y - p1.w);
+                        s23[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    } else {
+                        const float4 p2 = vb[(int64_t)m * 2 * L + n + L];
+                        s01[tid] = make_float4(p1.x + p2.x, p1.y + p2.y, p1.x - p2.x, p1.y - p2.y);
+                        s23[tid] = make_float4(p2.z + p1.z, p2.w + p1.w, p2.z - p1.z, p2.w - p1.w);
+                    }
+                    scf[tid] = (real)d.phis[n].x;
+                    ssf[tid] = (real)d.phis[n].y;
                 }
-                scf[tid] = (real)d.phis[n].x;
-                ssf[tid] = (real)d.phis[n].y;
             }
             __syncthreads();
-            for (int jj = 0; jj < cnt; ++jj) {
-                const real cfn = scf[jj], sfn = ssf[jj];
-                const float4 a = s01[jj], c = s23[jj];
+            for (int j0 = 0; j0 < cnt4; j0 += U) {
 #pragma unroll
-                for (int q = 0; q < PT; ++q) {
-                    float f;
-                    if (P64) {
-                        const double P = fma((double)A[q], (double)cfn, (double)B[q] * (double)sfn);
-                        f = (float)__builtin_amdgcn_fract(P);
-                    } else {
-                        const float P = fmaf((float)A[q], (float)cfn, (float)B[q] * (float)sfn);
-                        f = __builtin_amdgcn_fractf(P);
+                for (int ju = 0; ju < U; ++ju) {
+                    const int jj = j0 + ju;
+                    const real cfn = scf[jj], sfn = ssf[jj];
+                    const float4 a = s01[jj], c = s23[jj];
+#pragma unroll
+                    for (int q = 0; q < PT; ++q) {
+                        float f;
+                        if (P64) {
+                            const double P = fma((double)A[q], (double)cfn, (double)B[q] * (double)sfn);
+                            f = (float)__builtin_amdgcn_fract(P);
+                        } else {
+                            const float P = fmaf((float)A[q], (float)cfn, (float)B[q] * (float)sfn);
+                            f = __builtin_amdgcn_fractf(P);
+                        }
+                        float sn, cs;
+                        sincos_rev(f, sn, cs);
+                        xre[q] = fmaf(cs, a.x, fmaf(-sn, a.w, xre[q]));
+                        xim[q] = fmaf(cs, a.y, fmaf(sn, a.z, xim[q]));
+                        yre[q] = fmaf(cs, c.x, fmaf(-sn, c.w, yre[q]));
+                        yim[q] = fmaf(cs, c.y, fmaf(sn, c.z, yim[q]));
                     }
-                    float sn, cs;
-                    sincos_rev(f, sn, cs);
-                    xre[q] = fmaf(cs, a.x, fmaf(-sn, a.w, xre[q]));
-                    xim[q] = fmaf(cs, a.y, fmaf(sn, a.z, xim[q]));
-                    yre[q] = fmaf(cs, c.x, fmaf(-sn, c.w, yre[q]));
-                    yim[q] = fmaf(cs, c.y, fmaf(sn, c.z, yim[q]));
                 }
             }
         }
@@ -493,11 +510,35 @@ k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__
     for (int q = 0; q < PT; ++q) {
         if (!valid[q]) continue;
         const int i = wk.z + tid + q * kThreads;
-        float2 o = d.v[i];
-        o.x += vr[q];
-        o.y += vi[q];
-        d.v[i] = o;
+        if (d.bsplit > 1) {
+            d.bpart[(int64_t)wk.w * d.nx + i] = make_float2(vr[q], vi[q]);
+        } else {
+            float2 o = d.v[i];
+            o.x += vr[q];
+            o.y += vi[q];
+            d.v[i] = o;
+        }
     }
+}
+
+// v_i += sum over ring parts of the target-transform partials, in part order.  Item (desc, target box,
+// first point), 256 points per block.
+__global__ void __launch_bounds__(kThreads)
+k_sum_parts(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int i = wk.z + threadIdx.x;
+    if (i >= d.tstart[wk.y + 1]) return;
+    float2 a = d.bpart[i];
+    for (int s = 1; s < d.bsplit; ++s) {
+        const float2 w = d.bpart[(int64_t)s * d.nx + i];
+        a.x += w.x;
+        a.y += w.y;
+    }
+    float2 o = d.v[i];
+    o.x += a.x;
+    o.y += a.y;
+    d.v[i] = o;
 }
 
 // ------------------------------------------------------------------ Lagrange levels
@@ -859,8 +900,10 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_TRANSFER: return S.a == 2 ? k_pw_transfer<2> : k_pw_transfer<1>;
         case K_BWD_PAIR: return S.b ? k_pw_backward<true> : k_pw_backward<false>;
         case K_BWD_RING:
-            if (S.a == 2) return S.b ? k_pw_backward_rings<2, true> : k_pw_backward_rings<2, false>;
-            return S.b ? k_pw_backward_rings<1, true> : k_pw_backward_rings<1, false>;
+            // inner loop unrolled by 4 (one point per thread) or 2 (two points per thread)
+            if (S.a == 2) return S.b ? k_pw_backward_rings<2, 2, true> : k_pw_backward_rings<2, 2, false>;
+            return S.b ? k_pw_backward_rings<1, 4, true> : k_pw_backward_rings<1, 4, false>;
+        case K_BSUM: return k_sum_parts;
         case K_ANTERP: return k_lag_anterp;
         case K_MFMA32: threads = 64; return k_lag_mfma;
         case K_MFMA16: threads = 64; return k_lag_mfma16;
@@ -872,6 +915,25 @@ KernelFn kernel_of(const Stage &S, int &threads) {
 }
 
 }  // namespace
+
+int stage_blocks_per_cu(int kern, int a, int b) {
+    Stage S;
+    S.kern = kern;
+    S.a = a;
+    S.b = b;
+    int threads = kThreads;
+    KernelFn fn = kernel_of(S, threads);
+    int nb = 0;
+    FFM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0));
+    return std::max(nb, 1);
+}
+
+int device_cus() {
+    int dev = 0, n = 0;
+    FFM_HIP(hipGetDevice(&dev));
+    FFM_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(n, 1);
+}
 
 void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream_t st) {
     if (S.ditems.n == 0) return;

@@ -42,6 +42,7 @@ int stage_role(const Stage &S) {
         case K_SUM: return 1;
         case K_TRANSFER: case K_MFMA32: case K_MFMA16: return 2;
         case K_BWD_PAIR: case K_BWD_RING: case K_INTERP: return 3;
+        case K_BSUM: return 4;
         case K_NEAR: case K_ZERO_OUT: return 0;
         case K_PERM_OUT: return 1;
         default: throw Error(FFM_EINTERNAL, "stage without a batch order");

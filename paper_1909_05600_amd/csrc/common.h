@@ -191,6 +191,8 @@ struct LDesc {
     float4 *ut, *vt, *part;           // u~ / v~ / point-segment partials of this level
     int64_t npair, part_stride;
     int L, nrp, Tr, R, nchunk, nsplit;
+    int bsplit;                            // ring parts of the target transform (partials summed in order)
+    float2 *bpart;                         // [bsplit][nx] target-transform partials
     // Lagrange level
     const float *T, *lnodes, *lden;
     const _Float16 *T16;
@@ -204,7 +206,7 @@ struct LDesc {
 // Kernel variants (the template parameters travel with the stage).
 enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
-    K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT
+    K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM
 };
 
 struct Stage {
@@ -257,6 +259,7 @@ struct Level {
     int qSplit = 1;                      // point segments of the forward transform (partials summed in order)
     int bwd_tile = 256;                  // target points per backward block
     int Tr = 0, R = 0, nchunk = 0;       // ring-pair forward: threads per ring, rings per block, ring chunks
+    int bSplit = 1;                      // ring parts of the target transform
     // Lagrange node tables (FP32): Chebyshev nodes and 1 / prod_{b != a}(t_a - t_b)
     DevBuf<float> lnodes, lden;
     // box lists on the host, largest boxes first, and the box point ranges
@@ -287,6 +290,7 @@ struct Plan {
     DevBuf<float4> wsrc, wtgt;           // Gegenbauer u~ / v~, or Lagrange (as float2) scratch
     DevBuf<float2> wz;                   // Lagrange per-pair products
     DevBuf<float4> wpart;                // forward-transform partial sums of point segments
+    DevBuf<float2> wbpart;               // target-transform partial sums of ring parts
     DevBuf<float> amax;                  // max |Re u|, |Im u| of the current apply (FP16 scaling)
     bool any_fp16 = false;
     size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0;
@@ -316,10 +320,13 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st);
 size_t plan_device_bytes(const Plan &P);
 // stages of a plan for a tile choice; descriptors of a plan over given workspaces
 void plan_stages(Plan &P, const Tune &t, hipStream_t st);
-struct LevelWork {                     // workspace of one level (a batch keeps one per level)
+struct LevelWork {                     // apply workspace a descriptor points into
     float4 *ut = nullptr, *vt = nullptr, *part = nullptr;
-    float2 *ut2 = nullptr, *Z = nullptr;
+    float2 *ut2 = nullptr, *Z = nullptr, *bpart = nullptr;
 };
+// concurrent blocks per CU of a kernel variant (occupancy) and the device's CU count
+int stage_blocks_per_cu(int kern, int a, int b);
+int device_cus();
 LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w);
 // rebuild the stages and descriptors of a built plan for a tile choice (the plan must be idle)
 void plan_set_tune(Plan &P, const Tune &t, hipStream_t st);

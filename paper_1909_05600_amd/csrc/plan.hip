@@ -568,10 +568,22 @@ void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &
         FFM_HIP(hipMemcpyAsync(act.data(), dact.p, LY.nbox, hipMemcpyDeviceToHost, st));
     }
     FFM_HIP(hipStreamSynchronize(st));
+    // boxes by decreasing point count, ties in index order (counting sort over the counts)
     auto by_size = [](const std::vector<int32_t> &start, std::vector<int32_t> &boxes) {
-        std::stable_sort(boxes.begin(), boxes.end(), [&](int32_t a, int32_t b) {
-            return start[a + 1] - start[a] > start[b + 1] - start[b];
-        });
+        if (boxes.size() < 2) return;
+        int32_t mx = 0;
+        for (int32_t b : boxes) mx = std::max(mx, start[b + 1] - start[b]);
+        if ((size_t)mx > 8 * boxes.size() + 4096) {
+            std::stable_sort(boxes.begin(), boxes.end(), [&](int32_t a, int32_t b) {
+                return start[a + 1] - start[a] > start[b + 1] - start[b];
+            });
+            return;
+        }
+        std::vector<int32_t> cnt((size_t)mx + 2, 0), out(boxes.size());
+        for (int32_t b : boxes) ++cnt[(size_t)(mx - (start[b + 1] - start[b])) + 1];
+        for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+        for (int32_t b : boxes) out[cnt[(size_t)(mx - (start[b + 1] - start[b]))]++] = b;
+        boxes.swap(out);
     };
     std::vector<int32_t> tgt;
     for (int32_t t = 0; t < LX.nbox; ++t)
@@ -962,13 +974,14 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.wtgt.alloc(ws_tgt);
     P.wz.alloc(ws_z);
     if (P.any_fp16) P.amax.alloc(1);
+    plog.mark("alloc");
     // launches and descriptors
     P.dio.alloc(1);
     P.hio = static_cast<IoEntry *>(pinned_alloc(sizeof(IoEntry)));
     std::memset(P.hio, 0, sizeof(IoEntry));
     plan_set_tune(P, P.tune, st);
     FFM_HIP(hipStreamSynchronize(st));
-    plog.mark("workspace");
+    plog.mark("stages");
 
     // --- statistics
     ffm_stats_t &s = P.stats;
@@ -1024,6 +1037,20 @@ Stage make_stage(int kern, int a, int b, int slot, int level, size_t shmem, std:
 }
 }  // namespace
 
+// Parts s to split `blocks` equal blocks into, given `conc` blocks that run at once: the launch then runs
+// in about blocks * s / conc rounds, and blocks of the last, partly filled round run with the chip partly
+// idle.  Take the smallest s (up to smax, at most `cap`) that gives at least 8 rounds or a last round at
+// least 90% full.
+static int choose_split(int64_t blocks, int conc, int smax, int cap) {
+    smax = std::max(1, std::min(smax, cap));
+    for (int s = 1; s <= smax; ++s) {
+        const double r = (double)blocks * s / conc;
+        const double frac = r - std::floor(r);
+        if (r >= 8.0 || frac == 0.0 || frac >= 0.9) return s;
+    }
+    return smax;
+}
+
 // Choose the kernel form of every level for a tile choice and build its launches (work items).
 void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
     Scratch SC(st);
@@ -1042,7 +1069,15 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             P.pre.push_back(make_stage(K_AMAX, 0, 0, -1, 0, 0, std::move(am), st, SC));
         }
     }
-    size_t ws_part = 0;
+    size_t ws_part = 0, ws_bpart = 0;
+    // concurrent blocks of the ring-pair kernels on this device: [G == 4 / PT == 2][FP64 phase]
+    const int cus = device_cus();
+    int conc_fwd[2][2], conc_bwd[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            conc_fwd[i][j] = cus * stage_blocks_per_cu(K_FWD_RING, i ? 4 : 2, j);
+            conc_bwd[i][j] = cus * stage_blocks_per_cu(K_BWD_RING, i ? 2 : 1, j);
+        }
     for (int l = 1; l <= P.leaf; ++l) {
         Level &LV = P.lev[l];
         LV.stages.clear();
@@ -1062,8 +1097,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 LV.nchunk = (LV.nrp + LV.R - 1) / LV.R;
                 const int64_t blocks = (int64_t)LV.h_fwd.size() * LV.nchunk;
                 const double avg = LV.pts_src / std::max<double>(1.0, (double)LV.h_fwd.size());
-                int split = 1;
-                while (split < 8 && blocks * split < 4096 && avg / (2 * split) >= 512) split *= 2;
+                const int split = choose_split(blocks, conc_fwd[LV.qG == 4][LV.phase64], 16,
+                                               (int)std::max(1.0, avg / 256.0));
                 LV.qSplit = split;
                 if (split > 1) ws_part = std::max(ws_part, (size_t)split * P.ty->lev[l].nbox * LV.npair);
                 for (int32_t b : LV.h_fwd)
@@ -1086,15 +1121,29 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             const int ppt = LV.npair >= 2 * kThreads ? 2 : 1;
             const int64_t nt = (LV.npair + kThreads * ppt - 1) / (kThreads * ppt);
             std::vector<int4> tr, bw;
-            for (int32_t t : LV.h_tgt)
-                for (int64_t q = 0; q < nt; ++q) tr.push_back(make_int4(l, t, (int)q, 0));
+            // tile-major: the blocks running together share the tile of the class tables D
+            for (int64_t q = 0; q < nt; ++q)
+                for (int32_t t : LV.h_tgt) tr.push_back(make_int4(l, t, (int)q, 0));
             LV.stages.push_back(make_stage(K_TRANSFER, ppt, 0, s2, l, 0, std::move(tr), st, SC));
-            for (int32_t t : LV.h_tgt)
-                for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) bw.push_back(make_int4(l, t, i, 0));
+            int64_t tiles = 0;
+            for (int32_t t : LV.h_tgt) tiles += (sx[t + 1] - sx[t] + LV.bwd_tile - 1) / LV.bwd_tile;
+            // ring parts of the target transform: enough blocks for several rounds of the chip
+            LV.bSplit = LV.qG ? choose_split(tiles, conc_bwd[tu.bwd_pt == 2][LV.phase64], 8, LV.nrp) : 1;
+            if (LV.bSplit > 1) ws_bpart = std::max(ws_bpart, (size_t)LV.bSplit * P.nx);
+            for (int g = 0; g < LV.bSplit; ++g)
+                for (int32_t t : LV.h_tgt)
+                    for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) bw.push_back(make_int4(l, t, i, g));
             if (LV.qG)
-                LV.stages.push_back(make_stage(K_BWD_RING, tu.bwd_pt, LV.phase64, s3, l, 0, std::move(bw), st, SC));
+                LV.stages.push_back(make_stage(K_BWD_RING, tu.bwd_pt, LV.phase64, LV.bSplit > 1 ? -1 : s3, l, 0,
+                                               std::move(bw), st, SC));
             else
                 LV.stages.push_back(make_stage(K_BWD_PAIR, 0, LV.phase64, s3, l, 0, std::move(bw), st, SC));
+            if (LV.bSplit > 1) {
+                std::vector<int4> bs;
+                for (int32_t t : LV.h_tgt)
+                    for (int32_t i = sx[t]; i < sx[t + 1]; i += kThreads) bs.push_back(make_int4(l, t, i, 0));
+                LV.stages.push_back(make_stage(K_BSUM, 0, 0, s3, l, 0, std::move(bs), st, SC));
+            }
         } else {
             std::vector<int4> an, mf, ip;
             for (int32_t b : LV.h_fwd) an.push_back(make_int4(l, b, 0, 0));
@@ -1107,6 +1156,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
         }
     }
     if (ws_part > P.wpart.n) P.wpart.alloc(ws_part);
+    if (ws_bpart > P.wbpart.n) P.wbpart.alloc(ws_bpart);
     {
         const Level &LL = P.lev[P.leaf];
         std::vector<int4> nr, po;
@@ -1164,6 +1214,8 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.R = LV.R;
     d.nchunk = LV.nchunk;
     d.nsplit = LV.qSplit;
+    d.bsplit = LV.bSplit;
+    d.bpart = w.bpart;
     d.T = LV.T.p;
     d.lnodes = LV.lnodes.p;
     d.lden = LV.lden.p;
@@ -1190,6 +1242,7 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st) {
     w.part = P.wpart.p;
     w.ut2 = reinterpret_cast<float2 *>(P.wsrc.p);
     w.Z = P.wz.p;
+    w.bpart = P.wbpart.p;
     P.hdesc.clear();
     for (int l = 0; l <= P.leaf; ++l) P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
@@ -1214,7 +1267,8 @@ size_t plan_device_bytes(const Plan &P) {
              L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes();
         for (const Stage &S : L.stages) b += S.ditems.bytes();
     }
-    b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes();
+    b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
+         P.wbpart.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
     for (const Stage &S : P.pre) b += S.ditems.bytes();
     for (const Stage &S : P.post) b += S.ditems.bytes();

@@ -105,7 +105,8 @@ def test_batch_matches_oracle(orc):
 
 
 def test_tiles_change_only_rounding():
-    """bwd_pt does not change results; ring_g only regroups forward partial sums (rounding level)."""
+    """Tiles only regroup partial sums (forward point segments, target-transform ring parts): results agree
+    to rounding, and an apply is bitwise reproducible for fixed tiles."""
     import torch
     w = W.helmholtz_sphere(40000, seed=7, k=100.0)
     p = gpu_plan(w.X, w.X, 1, w.k, w.eps)
@@ -117,7 +118,8 @@ def test_tiles_change_only_rounding():
     p.set_tiles(2, 2)
     v22 = gpu_apply(p, w.wu)
     assert p.tiles() == (2, 2)
-    assert np.array_equal(v42, v41)
+    assert np.array_equal(v22, gpu_apply(p, w.wu))
+    assert rel(v41, v42) < 1e-5
     assert rel(v22, v42) < 1e-5
 
 
