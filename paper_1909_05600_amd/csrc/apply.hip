@@ -101,21 +101,21 @@ k_perm_out(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, cons
 // Forward transform u~_s(q) = sum_{j in s} e^{-ik s_q.(y_j - c_s)} u_j for an antipodal pair (q, -q): with
 // S = sum cos(th) u, T = sum sin(th) u, u~(q) = S - iT and u~(-q) = S + iT.
 // Item (desc, source box, tile of 256 PPT pairs); the box's points stream through LDS.
-template <int PPT, bool P64>
-__global__ void __launch_bounds__(kThreads)
+template <int PPT, int BS, bool P64>
+__global__ void __launch_bounds__(BS)
 k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int b = wk.y;
     const int tid = threadIdx.x;
     const int64_t npair = d.npair;
-    const int64_t p0 = (int64_t)wk.z * kThreads * PPT + tid;
+    const int64_t p0 = (int64_t)wk.z * BS * PPT + tid;
     typedef typename std::conditional<P64, double, float>::type real;
     real sx[PPT], sy[PPT], sz[PPT];
     float Sre[PPT], Sim[PPT], Tre[PPT], Tim[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int64_t p = p0 + (int64_t)j * kThreads;
+        const int64_t p = p0 + (int64_t)j * BS;
         const int64_t pc = p < npair ? p : npair - 1;
         if (P64) {
             sx[j] = d.dirs64[3 * pc]; sy[j] = d.dirs64[3 * pc + 1]; sz[j] = d.dirs64[3 * pc + 2];
@@ -126,11 +126,11 @@ k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
         Sre[j] = Sim[j] = Tre[j] = Tim[j] = 0.f;
     }
     const double cx = d.sctr[3 * b], cy = d.sctr[3 * b + 1], cz = d.sctr[3 * b + 2];
-    __shared__ real px[kThreads], py[kThreads], pz[kThreads];
-    __shared__ float2 us[kThreads];
+    __shared__ real px[BS], py[BS], pz[BS];
+    __shared__ float2 us[BS];
     const int i0 = d.sstart[b], i1 = d.sstart[b + 1];
-    for (int s0 = i0; s0 < i1; s0 += kThreads) {
-        const int cnt = min(kThreads, i1 - s0);
+    for (int s0 = i0; s0 < i1; s0 += BS) {
+        const int cnt = min(BS, i1 - s0);
         __syncthreads();
         if (tid < cnt) {
             const int i = s0 + tid;
@@ -164,7 +164,7 @@ k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int64_t p = p0 + (int64_t)j * kThreads;
+        const int64_t p = p0 + (int64_t)j * BS;
         if (p < npair)
             d.ut[(int64_t)b * npair + p] = make_float4(Sre[j] + Tim[j], Sim[j] - Tre[j], Sre[j] - Tim[j], Sim[j] + Tre[j]);
     }
@@ -172,14 +172,14 @@ k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 
 // Diagonal transfer v~_t(q) = sum_{s in far(t)} D_{c(t,s)}(q) u~_s(q) (both directions of a pair).
 // Item (desc, target box, tile of 256 PPT pairs).
-template <int PPT>
-__global__ void __launch_bounds__(kThreads)
+template <int PPT, int BS>
+__global__ void __launch_bounds__(BS)
 k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int t = wk.y;
     const int64_t npair = d.npair;
-    const int64_t p0 = (int64_t)wk.z * kThreads * PPT + threadIdx.x;
+    const int64_t p0 = (int64_t)wk.z * BS * PPT + threadIdx.x;
     float4 acc[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -190,7 +190,7 @@ k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
         const int64_t s = d.far_src[e], c = d.far_cls[e];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            const int64_t p = p0 + (int64_t)j * kThreads;
+            const int64_t p = p0 + (int64_t)j * BS;
             if (p < npair) {
                 const float4 q = D[c * npair + p];
                 const float4 w = ut[s * npair + p];
@@ -203,15 +203,16 @@ k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int64_t p = p0 + (int64_t)j * kThreads;
+        const int64_t p = p0 + (int64_t)j * BS;
         if (p < npair) d.vt[(int64_t)t * npair + p] = acc[j];
     }
 }
 
 // Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q) and
-// B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Item (desc, target box, first point).
-template <bool P64>
-__global__ void __launch_bounds__(kThreads)
+// B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Item (desc, target box, first point);
+// BS points per block (64 for levels of small boxes).
+template <int BS, bool P64>
+__global__ void __launch_bounds__(BS)
 k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
@@ -228,11 +229,11 @@ k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
         z = (real)(d.tzs[i] - d.tctr[3 * t + 2]);
     }
     float are = 0.f, aim = 0.f;
-    __shared__ real sdx[kThreads], sdy[kThreads], sdz[kThreads];
-    __shared__ float4 ab[kThreads];
+    __shared__ real sdx[BS], sdy[BS], sdz[BS];
+    __shared__ float4 ab[BS];
     const float4 *vb = d.vt + (int64_t)t * npair;
-    for (int64_t q0 = 0; q0 < npair; q0 += kThreads) {
-        const int cnt = (int)min<int64_t>(kThreads, npair - q0);
+    for (int64_t q0 = 0; q0 < npair; q0 += BS) {
+        const int cnt = (int)min<int64_t>(BS, npair - q0);
         __syncthreads();
         if (tid < cnt) {
             const int64_t q = q0 + tid;
@@ -890,15 +891,31 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_AMAX: return S.a ? k_zero_amax : k_amax;
         case K_PERM_OUT: return k_perm_out;
         case K_FWD_PAIR:
-            if (S.a == 4) return S.b ? k_pw_forward<4, true> : k_pw_forward<4, false>;
-            if (S.a == 2) return S.b ? k_pw_forward<2, true> : k_pw_forward<2, false>;
-            return S.b ? k_pw_forward<1, true> : k_pw_forward<1, false>;
+            // a = PPT (+100: 64-thread blocks)
+            if (S.a == 101) {
+                threads = 64;
+                return S.b ? k_pw_forward<1, 64, true> : k_pw_forward<1, 64, false>;
+            }
+            if (S.a == 4) return S.b ? k_pw_forward<4, kThreads, true> : k_pw_forward<4, kThreads, false>;
+            if (S.a == 2) return S.b ? k_pw_forward<2, kThreads, true> : k_pw_forward<2, kThreads, false>;
+            return S.b ? k_pw_forward<1, kThreads, true> : k_pw_forward<1, kThreads, false>;
         case K_FWD_RING:
             if (S.a == 4) return S.b ? k_pw_forward_rings<4, true> : k_pw_forward_rings<4, false>;
             return S.b ? k_pw_forward_rings<2, true> : k_pw_forward_rings<2, false>;
         case K_SUM: return k_sum_segments;
-        case K_TRANSFER: return S.a == 2 ? k_pw_transfer<2> : k_pw_transfer<1>;
-        case K_BWD_PAIR: return S.b ? k_pw_backward<true> : k_pw_backward<false>;
+        case K_TRANSFER:
+            if (S.a == 101) {
+                threads = 64;
+                return k_pw_transfer<1, 64>;
+            }
+            return S.a == 2 ? k_pw_transfer<2, kThreads> : k_pw_transfer<1, kThreads>;
+        case K_BWD_PAIR:
+            // a = 100: 64-thread blocks
+            if (S.a == 100) {
+                threads = 64;
+                return S.b ? k_pw_backward<64, true> : k_pw_backward<64, false>;
+            }
+            return S.b ? k_pw_backward<kThreads, true> : k_pw_backward<kThreads, false>;
         case K_BWD_RING:
             // inner loop unrolled by 4 (one point per thread) or 2 (two points per thread)
             if (S.a == 2) return S.b ? k_pw_backward_rings<2, 2, true> : k_pw_backward_rings<2, 2, false>;

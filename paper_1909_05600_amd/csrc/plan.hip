@@ -1051,6 +1051,26 @@ static int choose_split(int64_t blocks, int conc, int smax, int cap) {
     return smax;
 }
 
+// Block size and pairs per thread of a direction-pair kernel over npair pairs: the variant among
+// (64 threads, 1), (256, 1), (256, 2), (256, 4) (PPT at most ppt_max) whose tiles waste the fewest idle
+// threads, the larger tile among near-equal ones.
+static void pick_pair_tile(int64_t npair, int ppt_max, int &bs, int &ppt) {
+    const int cand[4][2] = {{64, 1}, {256, 1}, {256, 2}, {256, 4}};
+    double best = 1e30;
+    bs = 256;
+    ppt = 1;
+    for (const auto &c : cand) {
+        if (c[1] > ppt_max) continue;
+        const int64_t T = (int64_t)c[0] * c[1];
+        const double waste = (double)((npair + T - 1) / T * T) / (double)std::max<int64_t>(npair, 1);
+        if (waste <= best * 1.05) {
+            if (waste < best) best = waste;
+            bs = c[0];
+            ppt = c[1];
+        }
+    }
+}
+
 // Choose the kernel form of every level for a tile choice and build its launches (work items).
 void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
     Scratch SC(st);
@@ -1112,19 +1132,25 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 }
             } else {
                 LV.qSplit = 1;
-                const int ppt = LV.npair >= 4 * kThreads ? 4 : (LV.npair >= 2 * kThreads ? 2 : 1);
-                const int64_t nt = (LV.npair + kThreads * ppt - 1) / (kThreads * ppt);
+                int bs, ppt;
+                pick_pair_tile(LV.npair, 4, bs, ppt);
+                const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
                 for (int32_t b : LV.h_fwd)
                     for (int64_t t = 0; t < nt; ++t) fw.push_back(make_int4(l, b, (int)t, 0));
-                LV.stages.push_back(make_stage(K_FWD_PAIR, ppt, LV.phase64, s1, l, 0, std::move(fw), st, SC));
+                LV.stages.push_back(make_stage(K_FWD_PAIR, ppt + (bs == 64 ? 100 : 0), LV.phase64, s1, l, 0,
+                                               std::move(fw), st, SC));
             }
-            const int ppt = LV.npair >= 2 * kThreads ? 2 : 1;
-            const int64_t nt = (LV.npair + kThreads * ppt - 1) / (kThreads * ppt);
+            int bs, ppt;
+            pick_pair_tile(LV.npair, 2, bs, ppt);
+            const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
             std::vector<int4> tr, bw;
             // tile-major: the blocks running together share the tile of the class tables D
             for (int64_t q = 0; q < nt; ++q)
                 for (int32_t t : LV.h_tgt) tr.push_back(make_int4(l, t, (int)q, 0));
-            LV.stages.push_back(make_stage(K_TRANSFER, ppt, 0, s2, l, 0, std::move(tr), st, SC));
+            LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
+            // direction-pair target transform: 64-point blocks where target boxes are small
+            const bool small = !LV.qG && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
+            if (small) LV.bwd_tile = 64;
             int64_t tiles = 0;
             for (int32_t t : LV.h_tgt) tiles += (sx[t + 1] - sx[t] + LV.bwd_tile - 1) / LV.bwd_tile;
             // ring parts of the target transform: enough blocks for several rounds of the chip
@@ -1137,7 +1163,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 LV.stages.push_back(make_stage(K_BWD_RING, tu.bwd_pt, LV.phase64, LV.bSplit > 1 ? -1 : s3, l, 0,
                                                std::move(bw), st, SC));
             else
-                LV.stages.push_back(make_stage(K_BWD_PAIR, 0, LV.phase64, s3, l, 0, std::move(bw), st, SC));
+                LV.stages.push_back(make_stage(K_BWD_PAIR, small ? 100 : 0, LV.phase64, s3, l, 0, std::move(bw), st, SC));
             if (LV.bSplit > 1) {
                 std::vector<int4> bs;
                 for (int32_t t : LV.h_tgt)
