@@ -27,11 +27,11 @@ sys.path.insert(0, ROOT)
 # the form this library is built for); reported as FMA-equivalent TFLOP/s = 2 x slots/s.
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 PEAK_ALU_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12          # 78.6
-# Minimal non-transcendental VALU slots of the plane-wave transforms (sin/cos co-issue on the
-# transcendental unit at half rate and are not the bound; see profiles/peaks_mi355x.txt):
-#   direction-pair form: per (point, antipodal pair)   3 phase + 1 fract + 4 accumulate = 8 slots / 2 directions
-#   ring-pair form:      per (point, group of 4 dirs)   2 phase + 1 fract + 8 accumulate = 11 slots / 4 directions
-SLOTS_PER_DIRECTION = {1: 8 / 2, 2: 11 / 4}
+# Minimal non-transcendental VALU slots of the plane-wave transforms as implemented (sin/cos run on the
+# transcendental unit at half rate, co-issued, and take FP32 phases unreduced; see profiles/peaks_mi355x.txt):
+#   direction-pair form: per (point, antipodal pair)   3 phase + 4 accumulate = 7 slots / 2 directions
+#   ring-pair form:      per (point, group of 4 dirs)   2 phase + 8 accumulate = 10 slots / 4 directions
+SLOTS_PER_DIRECTION = {1: 7 / 2, 2: 10 / 4}
 
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
 # workload (profiles/traffic_pw_rings_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
@@ -416,7 +416,7 @@ def main():
             "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
             "launches": nlaunch, "avg_launch_ms": d_ms / max(nlaunch, 1),
             "work": "non-transcendental VALU issue slots x 2 (FMA-equivalent flops) of the ring-pair form: "
-                    "11 per (point, 4 quadrature directions), over the ring-pair levels; "
+                    "10 per (point, 4 quadrature directions), over the ring-pair levels; "
                     "peak = 256 CU x 64 lanes x 2.4 GHz x 2",
             "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy)",
         },

@@ -858,7 +858,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             // k sqrt(3) d_l / 2 radians) would reach eps / 20; the per-(point, ring) factor e^{iC} of
             // the ring-pair form is always reduced in FP64
             const double max_rad = P.k * dl * std::sqrt(3.0) * 0.5;
-            LV.phase64 = max_rad * std::ldexp(1.0, -22) > P.eps / 20.0;
+            // FP32 phases go to the hardware sine unreduced, which needs |phase| <= 128 revolutions
+            LV.phase64 = max_rad * std::ldexp(1.0, -22) > P.eps / 20.0 || max_rad / (2.0 * M_PI) > 128.0;
             // per-class series coefficients (host FP64), unit directions r0/|r0|
             std::vector<double> rhat(3 * (size_t)LV.ncls);
             std::vector<double2> coef((size_t)LV.ncls * (L + 1));
