@@ -36,10 +36,10 @@ SLOTS_PER_DIRECTION = {1: 7 / 2, 2: 10 / 4}
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
 # workload (profiles/traffic_pw_rings_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
 # kernel of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel source they were taken on.
-TRAFFIC_SOURCE_HASH = "a4c5347dc3f27bf8"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
+TRAFFIC_SOURCE_HASH = "d75c13247fdb8a34"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
 TRAFFIC = {
-    "k_pw_backward_rings<2, false>": (96725.0 * 2.0 + 8248.0) * 1024.0,
-    "k_pw_forward_rings<4, false>": (25328.5 * 2.0 + 156852.5) * 1024.0,
+    "k_pw_forward_rings<4, false>": ((16954.0 + 67948.0) / 2 * 2.0 + (189422.0 + 217487.0) / 2) * 1024.0,
+    "k_pw_backward_rings<2, 2, false>": ((195245.0 + 199058.0 + 85082.0) / 3 * 2.0 + (65938.0 + 65954.0 + 24773.0) / 3) * 1024.0,
 }
 
 
@@ -219,6 +219,9 @@ def serving(matvecs, loads, slots):
                 if step == matvecs:
                     state[i] = None
                     done += 1
+                    if done % 8 == 0:
+                        print("serving: %d-slot run, %d of %d sessions done" % (nslots, done, len(plans)),
+                              file=sys.stderr, flush=True)
                     continue
                 with torch.cuda.stream(norm_stream):
                     v = st[1]
@@ -367,11 +370,11 @@ def main():
     bwd_ms = {l: ph[:, 3 + 3 * (l - 1)].sum() for l in ring}
     per_dir = SLOTS_PER_DIRECTION[2]
     if sum(bwd_ms.values()) >= sum(fwd_ms.values()):
-        t_ms, pts, name = bwd_ms, "bwd_points", "k_pw_backward_rings<%d, %s>"
-        tile = tiles[1]
+        t_ms, pts, name = bwd_ms, "bwd_points", "k_pw_backward_rings<%s, %s>"
+        tile = "%d, %d" % (tiles[1], 4 if tiles[1] == 1 else 2)
     else:
-        t_ms, pts, name = fwd_ms, "fwd_points", "k_pw_forward_rings<%d, %s>"
-        tile = tiles[0]
+        t_ms, pts, name = fwd_ms, "fwd_points", "k_pw_forward_rings<%s, %s>"
+        tile = "%d" % tiles[0]
     # one kernel symbol: the levels sharing the phase precision of the most expensive level
     lmax = max(ring, key=lambda l: t_ms[l])
     p64 = st["phase64"][lmax]
