@@ -75,6 +75,13 @@ typedef struct {
 
 /* options.flags: record HIP events between the phases of every apply (see ffm_plan_timing). */
 #define FFM_FLAG_TIMING 1u
+/* options.flags: form of the plane-wave transforms of the Gegenbauer levels (Sec. 2.2.3).  By
+ * default the planner picks, per level, the cheaper of the direct sums (every point against every
+ * quadrature direction) and the grid form (points spread onto a uniform grid with a smooth kernel,
+ * separable sums from the grid to the directions, the kernel's Fourier transform divided out: the
+ * fast evaluation the remark closing Sec. 2.2.3 calls for).  These bits force one form. */
+#define FFM_FLAG_DIRECT_TRANSFORMS 2u
+#define FFM_FLAG_GRID_TRANSFORMS   4u
 
 /*
  * ffm_plan -- build the two octrees, the descent lists and the transfer
@@ -133,7 +140,7 @@ typedef struct {
     int64_t nnear[FFM_MAX_LEVELS];         /* near pairs of level l                        */
     int32_t method[FFM_MAX_LEVELS];        /* 0 none, 1 Lagrange, 2 Gegenbauer             */
     int32_t order[FFM_MAX_LEVELS];         /* r1 (Lagrange) or L (Gegenbauer)              */
-    int32_t tform[FFM_MAX_LEVELS];         /* Gegenbauer transform kernels: 1 direction pairs, 2 ring pairs */
+    int32_t tform[FFM_MAX_LEVELS];         /* Gegenbauer transforms: 1 direction pairs, 2 ring pairs, 3 grid form */
     int32_t prec[FFM_MAX_LEVELS];          /* transfer arithmetic: 0 FP32, 1 FP16 MFMA with FP32 accumulation */
     int32_t phase64[FFM_MAX_LEVELS];       /* Gegenbauer in-plane phases in FP64 (1) or FP32 (0) */
     int32_t nclass[FFM_MAX_LEVELS];        /* distinct translations at level l             */

@@ -30,6 +30,8 @@ EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_versi
             "ffm_batch_destroy", "ffm_server_create", "ffm_server_submit", "ffm_server_wait", "ffm_server_poll",
             "ffm_server_stats", "ffm_server_destroy"]
 FFM_FLAG_TIMING = 1
+FFM_FLAG_DIRECT_TRANSFORMS = 2
+FFM_FLAG_GRID_TRANSFORMS = 4
 FFM_BATCH_GRAPH = 1
 FFM_BATCH_AUTOTUNE = 2
 TIMING_SLOTS = 64
@@ -190,7 +192,7 @@ class Plan:
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 0, precision: int = 0,
                  kd_switch: float = 0.0, r1_override: int = 0, max_level: int = 0, timing: bool = False,
-                 stream=None):
+                 transforms: str = "auto", stream=None):
         import torch
         same = Y is X
         X = X.detach().contiguous()
@@ -205,8 +207,9 @@ class Plan:
         self.n_x, self.n_y = int(X.shape[0]), int(Y.shape[0])
         self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
         self.device = X.device
-        opts = Options(int(n_leaf), int(precision), float(kd_switch), int(r1_override), int(max_level),
-                       FFM_FLAG_TIMING if timing else 0)
+        flags = (FFM_FLAG_TIMING if timing else 0) | {"auto": 0, "direct": FFM_FLAG_DIRECT_TRANSFORMS,
+                                                      "grid": FFM_FLAG_GRID_TRANSFORMS}[transforms]
+        opts = Options(int(n_leaf), int(precision), float(kd_switch), int(r1_override), int(max_level), flags)
         self._h = None
         with torch.cuda.device(self.device):
             self._h = ffm_plan(X.data_ptr(), self.n_x, Y.data_ptr(), self.n_y, self.kernel, self.k, self.eps,

@@ -157,7 +157,10 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     if (!(k >= 0.0) || !std::isfinite(k)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: k must be finite and >= 0");
     ffm_options_t o{};
     if (opts) o = *opts;
-    if (o.flags & ~FFM_FLAG_TIMING) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: unknown options.flags bits");
+    if (o.flags & ~(FFM_FLAG_TIMING | FFM_FLAG_DIRECT_TRANSFORMS | FFM_FLAG_GRID_TRANSFORMS))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: unknown options.flags bits");
+    if ((o.flags & FFM_FLAG_DIRECT_TRANSFORMS) && (o.flags & FFM_FLAG_GRID_TRANSFORMS))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: direct and grid transforms both forced");
     if (o.n_leaf < 0 || o.max_level < 0 || o.max_level > kMaxLev || o.r1_override < 0 || o.r1_override > 8 ||
         !(o.kd_switch >= 0.0) || (o.precision != FFM_PREC_FP32 && o.precision != FFM_PREC_MIXED))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: invalid options");
@@ -187,7 +190,8 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         }
         P.stats.plan_bytes = (double)plan_device_bytes(P);
         P.stats.workspace_bytes = (double)(P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() +
-                                           P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() + P.wbpart.bytes());
+                                           P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() + P.wbpart.bytes() +
+                                           P.wG.bytes() + P.wH.bytes());
         h = p.release();
     });
     if (rc == FFM_OK) *out = h;

@@ -546,6 +546,464 @@ k_sum_parts(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
     d.v[i] = o;
 }
 
+// ------------------------------------------------------------------ Gegenbauer levels, grid form
+// The transforms as sums over a uniform grid: with a smooth kernel phi of width w (grid units) and its
+// Fourier transform phi^, e^{-ik s.y} ~ (1/Phi(s)) sum_g phi((x_g - y)/h) e^{-ik s.x_g} (per axis, aliasing
+// negligible for kh <= pi / 1.9), Phi(s) = prod_d phi^(k s_d h).  Forward: spread u onto the grid, sum
+// over z for every ring (cos t_m), then over the plane for every direction; backward: the mirror sums
+// and an interpolation at the targets.  Phi is divided out (twice) in the transfer diagonal.  Grid nodes
+// x_a = (a - (p-1)/2) h about the box centre; G [box][c][a][b] (c: z), H [ring][box][a][b].
+// Rings m and L - m (cos t opposite) share Ex, Ey; azimuths n and n + L give the conjugate tables.
+
+// phi(x) = exp(beta (sqrt(1 - (2x/w)^2) - 1)) for |x| < w/2, 0 outside (exponential of semicircle)
+__device__ __forceinline__ float es_phi(float x, float w, float beta) {
+    const float t = 2.f * x / w;
+    const float s = 1.f - t * t;
+    return s > 0.f ? expf(beta * (sqrtf(s) - 1.f)) : 0.f;
+}
+
+constexpr int kGT = 64;      // spreading tile edge (grid nodes)
+constexpr int kGW = 9;       // most grid nodes a point touches per axis (w <= 8)
+
+// Spread the source points of a box onto one z-plane of its grid (one 64 x 64 tile of it).  Every
+// contribution is rounded once to 64-bit fixed point and summed with integer LDS atomics: the sums are
+// exact, so the result does not depend on the order of the points.  Item (desc, box, plane, tile).
+__global__ void __launch_bounds__(kThreads)
+k_grid_spread(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int sb = wk.y, c = wk.z;
+    const int p = d.gp, w = d.gw;
+    const int nta = (p + kGT - 1) / kGT;
+    const int a0 = (wk.w / nta) * kGT, b0 = (wk.w % nta) * kGT;
+    const int na = min(kGT, p - a0), nb = min(kGT, p - b0);
+    __shared__ unsigned long long acc[2][kGT * kGT];
+    for (int i = threadIdx.x; i < kGT * kGT; i += kThreads) {
+        acc[0][i] = 0ull;
+        acc[1][i] = 0ull;
+    }
+    __syncthreads();
+    // fixed point: |sum| <= (points of the box) x max |Re u|, |Im u| (phi <= 1)
+    const double bound = (double)(d.sstart[sb + 1] - d.sstart[sb]) * (double)(*d.amax);
+    int e = 0;
+    if (bound > 0.0) frexp(bound, &e);
+    e = max(e, -900);
+    const double scale = ldexp(1.0, 61 - e), inv_scale = ldexp(1.0, e - 61);
+    const float half = 0.5f * (float)(p - 1), hw = 0.5f * (float)w, fw = (float)w, beta = d.gbeta;
+    const double ih = (double)d.ginv_h;
+    const double cx = d.sctr[3 * sb], cy = d.sctr[3 * sb + 1], cz = d.sctr[3 * sb + 2];
+    const int clo = max(0, c - w / 2 - 1), chi = min(p - 1, c + w / 2 + 1);
+    const int64_t zoff = (int64_t)sb * p;
+    const int j0 = d.gzs[zoff + clo], j1 = d.gzs[zoff + chi + 1];
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += kThreads) {
+        const int i = d.gperm[j];
+        const float zg = (float)((d.szs[i] - cz) * ih) + half;
+        const float wz = es_phi((float)c - zg, fw, beta);
+        if (wz == 0.f) continue;
+        const float xg = (float)((d.sxs[i] - cx) * ih) + half;
+        const float yg = (float)((d.sys[i] - cy) * ih) + half;
+        const int alo = max(a0, (int)ceilf(xg - hw)), ahi = min(a0 + na - 1, (int)floorf(xg + hw));
+        const int blo = max(b0, (int)ceilf(yg - hw)), bhi = min(b0 + nb - 1, (int)floorf(yg + hw));
+        const float2 uu = d.u[i];
+        const float ur = uu.x * wz, ui = uu.y * wz;
+        float wy[kGW];
+#pragma unroll
+        for (int q = 0; q < kGW; ++q) wy[q] = (blo + q <= bhi) ? es_phi((float)(blo + q) - yg, fw, beta) : 0.f;
+        for (int a = alo; a <= ahi; ++a) {
+            const float wx = es_phi((float)a - xg, fw, beta);
+            const int row = (a - a0) * kGT - b0;
+#pragma unroll
+            for (int q = 0; q < kGW; ++q) {
+                if (blo + q <= bhi) {
+                    const float wxy = wx * wy[q];
+                    const int kk = row + blo + q;
+                    atomicAdd(&acc[0][kk], (unsigned long long)__double2ll_rn((double)(ur * wxy) * scale));
+                    atomicAdd(&acc[1][kk], (unsigned long long)__double2ll_rn((double)(ui * wxy) * scale));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    float2 *G = d.G + ((int64_t)sb * p + c) * p * p;
+    for (int kk = threadIdx.x; kk < kGT * kGT; kk += kThreads) {
+        const int al = kk / kGT, bl = kk % kGT;
+        if (al < na && bl < nb)
+            G[(int64_t)(a0 + al) * p + b0 + bl] = make_float2((float)((double)(long long)acc[0][kk] * inv_scale),
+                                                              (float)((double)(long long)acc[1][kk] * inv_scale));
+    }
+}
+
+// Sums over z: H[m][a][b] = sum_c Ez[m][c] G[c][a][b] and H[L-m] with conj(Ez[m]) (four real products
+// serve both), as a tiled product: 32 ring pairs x 128 grid columns per block, 4 x 4 per thread, the
+// planes c staged through LDS 32 at a time.  Item (desc, box, column tile, ring-pair tile).
+__global__ void __launch_bounds__(kThreads)
+k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int sb = wk.y, p = d.gp, L = d.L, nrp = d.nrp;
+    const int p2 = p * p;
+    const int ab0 = wk.z * 128, m0 = wk.w * 32;
+    const int tid = threadIdx.x, tm = tid / 32, tab = tid % 32;   // 8 x 32 threads
+    __shared__ float4 Es[32][16];    // [c][ring pairs m0 .. m0+31] (two complex per float4)
+    __shared__ float4 Gs[32][64];    // [c][columns ab0 .. ab0+127]
+    float q1[4][4], q2[4][4], q3[4][4], q4[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q1[i][j] = q2[i][j] = q3[i][j] = q4[i][j] = 0.f;
+    const float2 *G = d.G + (int64_t)sb * p * p2;
+    for (int c0 = 0; c0 < p; c0 += 32) {
+        const int cc = min(32, p - c0);
+        __syncthreads();
+        for (int k = tid; k < 32 * 32; k += kThreads) {
+            const int c = k / 32, m = k % 32;
+            reinterpret_cast<float2 *>(&Es[c][0])[m] =
+                (c < cc && m0 + m < nrp) ? d.Ez[(int64_t)(m0 + m) * p + c0 + c] : make_float2(0.f, 0.f);
+        }
+        for (int k = tid; k < 32 * 128; k += kThreads) {
+            const int c = k / 128, j = k % 128;
+            reinterpret_cast<float2 *>(&Gs[c][0])[j] =
+                (c < cc && ab0 + j < p2) ? G[(int64_t)(c0 + c) * p2 + ab0 + j] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        for (int c = 0; c < cc; ++c) {
+            const float4 e01 = Es[c][2 * tm], e23 = Es[c][2 * tm + 1];
+            const float4 g01 = Gs[c][2 * tab], g23 = Gs[c][2 * tab + 1];
+            const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
+            const float gr[4] = {g01.x, g01.z, g23.x, g23.z}, gi[4] = {g01.y, g01.w, g23.y, g23.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    q1[i][j] = fmaf(er[i], gr[j], q1[i][j]);
+                    q2[i][j] = fmaf(ei[i], gi[j], q2[i][j]);
+                    q3[i][j] = fmaf(er[i], gi[j], q3[i][j]);
+                    q4[i][j] = fmaf(ei[i], gr[j], q4[i][j]);
+                }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + tm * 4 + i;
+        if (m >= nrp) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ab = ab0 + tab * 4 + j;
+            if (ab >= p2) continue;
+            d.H[((int64_t)m * d.gnbox + sb) * p2 + ab] = make_float2(q1[i][j] - q2[i][j], q3[i][j] + q4[i][j]);
+            if (L - m != m)
+                d.H[((int64_t)(L - m) * d.gnbox + sb) * p2 + ab] = make_float2(q1[i][j] + q2[i][j], q3[i][j] - q4[i][j]);
+        }
+    }
+}
+
+// Sums over the plane to the directions: u~(m, n) = sum_a Ex[a][n] X[a][n], X = H_m Ey (sum over b), and
+// u~(m, n+L) with the conjugate tables (the same four real products).  A tiled product: 64 rows a x 64
+// azimuths n per block, 4 x 4 per thread, b staged through LDS 32 at a time; then each thread's sums over
+// its 4 rows are added over the 16 row groups in order.  Item (desc, box, ring, azimuth tile).
+__global__ void __launch_bounds__(kThreads)
+k_grid_phi(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int sb = wk.y, m = wk.z;
+    const int p = d.gp, L = d.L, mt = min(m, L - m);
+    const int n0 = wk.w * 64;
+    const int tid = threadIdx.x, ta = tid / 16, tn = tid % 16;
+    __shared__ float4 Hs[32][32];    // [b][rows a]  (two complex per float4)
+    __shared__ float4 Es[32][32];    // [b][azimuths n]
+    __shared__ float4 red[16][64];   // [row group][n]: (u~(m,n), u~(m,n+L)) partial sums
+    const float2 *H = d.H + ((int64_t)m * d.gnbox + sb) * p * p;
+    const float2 *Ey = d.Ey + (int64_t)mt * p * L;
+    const float2 *Ex = d.Ex + (int64_t)mt * p * L;
+    float tr[4], ti[4], ur[4], ui[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tr[j] = ti[j] = ur[j] = ui[j] = 0.f;
+    for (int a0 = 0; a0 < p; a0 += 64) {
+        float P1[4][4], P2[4][4], P3[4][4], P4[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) P1[i][j] = P2[i][j] = P3[i][j] = P4[i][j] = 0.f;
+        for (int b0 = 0; b0 < p; b0 += 32) {
+            const int nbb = min(32, p - b0);
+            __syncthreads();
+            for (int k = tid; k < 32 * 64; k += kThreads) {
+                const int b = k / 64, r = k % 64;
+                reinterpret_cast<float2 *>(&Hs[b][0])[r] =
+                    (b < nbb && a0 + r < p) ? H[(int64_t)(a0 + r) * p + b0 + b] : make_float2(0.f, 0.f);
+                reinterpret_cast<float2 *>(&Es[b][0])[r] =
+                    (b < nbb && n0 + r < L) ? Ey[(int64_t)(b0 + b) * L + n0 + r] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            for (int b = 0; b < nbb; ++b) {
+                const float4 h01 = Hs[b][2 * ta], h23 = Hs[b][2 * ta + 1];
+                const float4 e01 = Es[b][2 * tn], e23 = Es[b][2 * tn + 1];
+                const float hr[4] = {h01.x, h01.z, h23.x, h23.z}, hi[4] = {h01.y, h01.w, h23.y, h23.w};
+                const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        P1[i][j] = fmaf(er[j], hr[i], P1[i][j]);
+                        P2[i][j] = fmaf(ei[j], hi[i], P2[i][j]);
+                        P3[i][j] = fmaf(er[j], hi[i], P3[i][j]);
+                        P4[i][j] = fmaf(ei[j], hr[i], P4[i][j]);
+                    }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int a = a0 + ta * 4 + i;
+            if (a >= p) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = n0 + tn * 4 + j;
+                if (n >= L) continue;
+                const float2 ex = Ex[(int64_t)a * L + n];
+                const float xr = P1[i][j] - P2[i][j], xi = P3[i][j] + P4[i][j];     // sum_b Ey H
+                const float yr = P1[i][j] + P2[i][j], yi = P3[i][j] - P4[i][j];     // sum_b conj(Ey) H
+                tr[j] = fmaf(ex.x, xr, fmaf(-ex.y, xi, tr[j]));
+                ti[j] = fmaf(ex.x, xi, fmaf(ex.y, xr, ti[j]));
+                ur[j] = fmaf(ex.x, yr, fmaf(ex.y, yi, ur[j]));
+                ui[j] = fmaf(ex.x, yi, fmaf(-ex.y, yr, ui[j]));
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[ta][tn * 4 + j] = make_float4(tr[j], ti[j], ur[j], ui[j]);
+    __syncthreads();
+    if (tid >= 64) return;
+    const int n = n0 + tid;
+    if (n >= L) return;
+    float4 a = red[0][tid];
+    for (int q = 1; q < 16; ++q) {
+        const float4 b = red[q][tid];
+        a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+    }
+    // a.xy = u~(m, n), a.zw = u~(m, n + L), into the antipodal-pair layout
+    float2 *ut = reinterpret_cast<float2 *>(d.ut) + (int64_t)sb * d.npair * 2;
+    const int64_t twoL = 2 * (int64_t)L;
+    if (2 * m < L) {
+        ut[(m * twoL + n) * 2] = make_float2(a.x, a.y);
+        ut[(m * twoL + n + L) * 2] = make_float2(a.z, a.w);
+    } else if (2 * m > L) {
+        const int64_t m2 = L - m;
+        ut[(m2 * twoL + n) * 2 + 1] = make_float2(a.z, a.w);
+        ut[(m2 * twoL + n + L) * 2 + 1] = make_float2(a.x, a.y);
+    } else {
+        ut[(m * twoL + n) * 2] = make_float2(a.x, a.y);
+        ut[(m * twoL + n) * 2 + 1] = make_float2(a.z, a.w);
+    }
+}
+
+// v~ of ring m back to the plane: H'[a][b] = sum_{n < L} conj(Ex) conj(Ey) v~(m, n) + Ex Ey v~(m, n + L),
+// one 64 x 64 tile of (a, b) per block, 4 x 4 per thread.  Item (desc, box, ring, tile).
+__global__ void __launch_bounds__(kThreads)
+k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int tb_ = wk.y, m = wk.z;
+    const int p = d.gp, L = d.L, mt = min(m, L - m);
+    const int nta = (p + 63) / 64;
+    const int a0 = (wk.w / nta) * 64, b0 = (wk.w % nta) * 64;
+    const int tid = threadIdx.x, ta = tid / 16, tb = tid % 16;
+    __shared__ float4 sS[32][32], sD[32][32], sE[32][32];   // [n][pairs of a (or b)]: 64 complex per row
+    float2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
+    const float2 *vt = reinterpret_cast<const float2 *>(d.vt) + (int64_t)tb_ * d.npair * 2;
+    const float2 *Ey = d.Ey + (int64_t)mt * p * L;
+    const float2 *Ex = d.Ex + (int64_t)mt * p * L;
+    const int64_t twoL = 2 * (int64_t)L;
+    for (int n0 = 0; n0 < L; n0 += 32) {
+        const int cnt = min(32, L - n0);
+        __syncthreads();
+        for (int k = tid; k < 32 * 64; k += kThreads) {
+            const int nn = k / 64, r = k % 64, n = n0 + nn;
+            float2 S = make_float2(0.f, 0.f), Dd = S, E = S;
+            if (nn < cnt) {
+                float2 v1, v2;   // v~(m, n), v~(m, n + L)
+                if (2 * m < L) {
+                    v1 = vt[(m * twoL + n) * 2];
+                    v2 = vt[(m * twoL + n + L) * 2];
+                } else if (2 * m > L) {
+                    const int64_t m2 = L - m;
+                    v1 = vt[(m2 * twoL + n + L) * 2 + 1];
+                    v2 = vt[(m2 * twoL + n) * 2 + 1];
+                } else {
+                    v1 = vt[(m * twoL + n) * 2];
+                    v2 = vt[(m * twoL + n) * 2 + 1];
+                }
+                const int a = a0 + r;
+                if (a < p) {
+                    const float2 ex = Ex[(int64_t)a * L + n];
+                    const float y1r = fmaf(ex.x, v1.x, ex.y * v1.y), y1i = fmaf(ex.x, v1.y, -(ex.y * v1.x));   // conj(ex) v1
+                    const float y2r = fmaf(ex.x, v2.x, -(ex.y * v2.y)), y2i = fmaf(ex.x, v2.y, ex.y * v2.x);   // ex v2
+                    S = make_float2(y1r + y2r, y1i + y2i);
+                    Dd = make_float2(y2r - y1r, y2i - y1i);
+                }
+                const int b = b0 + r;
+                if (b < p) E = Ey[(int64_t)b * L + n];
+            }
+            reinterpret_cast<float2 *>(&sS[nn][0])[r] = S;
+            reinterpret_cast<float2 *>(&sD[nn][0])[r] = Dd;
+            reinterpret_cast<float2 *>(&sE[nn][0])[r] = E;
+        }
+        __syncthreads();
+        for (int nn = 0; nn < cnt; ++nn) {
+            const float4 s01 = sS[nn][2 * ta], s23 = sS[nn][2 * ta + 1];
+            const float4 d01 = sD[nn][2 * ta], d23 = sD[nn][2 * ta + 1];
+            const float4 e01 = sE[nn][2 * tb], e23 = sE[nn][2 * tb + 1];
+            const float2 sv[4] = {make_float2(s01.x, s01.y), make_float2(s01.z, s01.w), make_float2(s23.x, s23.y),
+                                  make_float2(s23.z, s23.w)};
+            const float2 dv[4] = {make_float2(d01.x, d01.y), make_float2(d01.z, d01.w), make_float2(d23.x, d23.y),
+                                  make_float2(d23.z, d23.w)};
+            const float2 ev[4] = {make_float2(e01.x, e01.y), make_float2(e01.z, e01.w), make_float2(e23.x, e23.y),
+                                  make_float2(e23.z, e23.w)};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j].x = fmaf(sv[i].x, ev[j].x, fmaf(-dv[i].y, ev[j].y, acc[i][j].x));
+                    acc[i][j].y = fmaf(sv[i].y, ev[j].x, fmaf(dv[i].x, ev[j].y, acc[i][j].y));
+                }
+        }
+    }
+    float2 *Hb = d.H + ((int64_t)m * d.gnbox + tb_) * p * p;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int a = a0 + ta * 4 + i;
+        if (a >= p) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int b = b0 + tb * 4 + j;
+            if (b < p) Hb[(int64_t)a * p + b] = acc[i][j];
+        }
+    }
+}
+
+// Back over z: G'[c][a][b] = sum over ring pairs of conj(Ez[m][c]) H'[m][a][b] + Ez[m][c] H'[L-m][a][b]
+// = Re(Ez) (H'[m] + H'[L-m]) + i Im(Ez) (H'[L-m] - H'[m]), as a tiled product: 32 planes x 128 columns per
+// block, 4 x 4 per thread, ring pairs staged through LDS 16 at a time.  Item (desc, box, column tile,
+// plane tile).
+__global__ void __launch_bounds__(kThreads)
+k_grid_zt(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int tb_ = wk.y, p = d.gp, L = d.L, nrp = d.nrp;
+    const int p2 = p * p;
+    const int ab0 = wk.z * 128, c0 = wk.w * 32;
+    const int tid = threadIdx.x, tc = tid / 32, tab = tid % 32;
+    __shared__ float4 Es[16][16];    // [ring pair][planes c0 .. c0+31]
+    __shared__ float4 Ss[16][64];    // [ring pair][columns]: H'[m] + H'[L-m]
+    __shared__ float4 Ds[16][64];    //                       H'[L-m] - H'[m]
+    float2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
+    for (int mp0 = 0; mp0 < nrp; mp0 += 16) {
+        const int mc = min(16, nrp - mp0);
+        __syncthreads();
+        for (int k = tid; k < 16 * 32; k += kThreads) {
+            const int mm = k / 32, c = k % 32;
+            reinterpret_cast<float2 *>(&Es[mm][0])[c] =
+                (mm < mc && c0 + c < p) ? d.Ez[(int64_t)(mp0 + mm) * p + c0 + c] : make_float2(0.f, 0.f);
+        }
+        for (int k = tid; k < 16 * 128; k += kThreads) {
+            const int mm = k / 128, j = k % 128, mp = mp0 + mm, ab = ab0 + j;
+            float2 S = make_float2(0.f, 0.f), Dd = S;
+            if (mm < mc && ab < p2) {
+                const int m2 = L - mp;
+                const float2 h1 = d.H[((int64_t)mp * d.gnbox + tb_) * p2 + ab];
+                const float2 h2 = (m2 != mp) ? d.H[((int64_t)m2 * d.gnbox + tb_) * p2 + ab] : make_float2(0.f, 0.f);
+                S = make_float2(h1.x + h2.x, h1.y + h2.y);
+                Dd = make_float2(h2.x - h1.x, h2.y - h1.y);
+            }
+            reinterpret_cast<float2 *>(&Ss[mm][0])[j] = S;
+            reinterpret_cast<float2 *>(&Ds[mm][0])[j] = Dd;
+        }
+        __syncthreads();
+        for (int mm = 0; mm < mc; ++mm) {
+            const float4 e01 = Es[mm][2 * tc], e23 = Es[mm][2 * tc + 1];
+            const float4 s01 = Ss[mm][2 * tab], s23 = Ss[mm][2 * tab + 1];
+            const float4 d01 = Ds[mm][2 * tab], d23 = Ds[mm][2 * tab + 1];
+            const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
+            const float sr[4] = {s01.x, s01.z, s23.x, s23.z}, si[4] = {s01.y, s01.w, s23.y, s23.w};
+            const float dr[4] = {d01.x, d01.z, d23.x, d23.z}, di[4] = {d01.y, d01.w, d23.y, d23.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j].x = fmaf(er[i], sr[j], fmaf(-ei[i], di[j], acc[i][j].x));
+                    acc[i][j].y = fmaf(er[i], si[j], fmaf(ei[i], dr[j], acc[i][j].y));
+                }
+        }
+    }
+    float2 *G = d.G + (int64_t)tb_ * p * p2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = c0 + tc * 4 + i;
+        if (c >= p) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ab = ab0 + tab * 4 + j;
+            if (ab < p2) G[(int64_t)c * p2 + ab] = acc[i][j];
+        }
+    }
+}
+
+// v_i += sum over the grid nodes around x_i of phi phi phi G'.  Item (desc, target box, first point).
+__global__ void __launch_bounds__(kThreads)
+k_grid_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
+    const int i = wk.z + threadIdx.x;
+    if (i >= d.tstart[t + 1]) return;
+    const int p = d.gp;
+    const float half = 0.5f * (float)(p - 1), hw = 0.5f * (float)d.gw, fw = (float)d.gw, beta = d.gbeta;
+    const double ih = (double)d.ginv_h;
+    const float xg = (float)((d.txs[i] - d.tctr[3 * t]) * ih) + half;
+    const float yg = (float)((d.tys[i] - d.tctr[3 * t + 1]) * ih) + half;
+    const float zg = (float)((d.tzs[i] - d.tctr[3 * t + 2]) * ih) + half;
+    const int alo = max(0, (int)ceilf(xg - hw)), ahi = min(p - 1, (int)floorf(xg + hw));
+    const int blo = max(0, (int)ceilf(yg - hw)), bhi = min(p - 1, (int)floorf(yg + hw));
+    const int clo = max(0, (int)ceilf(zg - hw)), chi = min(p - 1, (int)floorf(zg + hw));
+    float wy[kGW];
+#pragma unroll
+    for (int q = 0; q < kGW; ++q) wy[q] = (blo + q <= bhi) ? es_phi((float)(blo + q) - yg, fw, beta) : 0.f;
+    const float2 *G = d.G + (int64_t)t * p * p * p;
+    float sr = 0.f, si = 0.f;
+    for (int c = clo; c <= chi; ++c) {
+        const float wz = es_phi((float)c - zg, fw, beta);
+        float pr = 0.f, pi = 0.f;
+        for (int a = alo; a <= ahi; ++a) {
+            const float wx = es_phi((float)a - xg, fw, beta);
+            const float2 *row = G + ((int64_t)c * p + a) * p;
+            float rr = 0.f, ri = 0.f;
+#pragma unroll
+            for (int q = 0; q < kGW; ++q) {
+                if (blo + q <= bhi) {
+                    const float2 g = row[blo + q];
+                    rr = fmaf(wy[q], g.x, rr);
+                    ri = fmaf(wy[q], g.y, ri);
+                }
+            }
+            pr = fmaf(wx, rr, pr);
+            pi = fmaf(wx, ri, pi);
+        }
+        sr = fmaf(wz, pr, sr);
+        si = fmaf(wz, pi, si);
+    }
+    float2 o = d.v[i];
+    o.x += sr;
+    o.y += si;
+    d.v[i] = o;
+}
+
 // ------------------------------------------------------------------ Lagrange levels
 constexpr int kMaxR1 = 8;
 constexpr int kAnterpChunk = 64;
@@ -931,6 +1389,12 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
         case K_ZERO_OUT: return k_zero_io;
+        case K_GSPREAD: return k_grid_spread;
+        case K_GZ: return k_grid_z;
+        case K_GPHI: return k_grid_phi;
+        case K_GPHIT: return k_grid_phit;
+        case K_GZT: return k_grid_zt;
+        case K_GINTERP: return k_grid_interp;
         default: throw Error(FFM_EINTERNAL, "unknown kernel variant");
     }
 }

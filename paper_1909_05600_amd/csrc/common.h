@@ -201,12 +201,21 @@ struct LDesc {
     double two_over_dl;
     int r1, rp, maxpts;
     float sT;
+    // grid form of the plane-wave transforms (spread onto a uniform grid, separable sums to the
+    // quadrature directions): p nodes per axis at spacing h, kernel width w, shape beta
+    int gp, gw;
+    float gbeta, ginv_h;                   // kernel shape, 1 / h
+    int64_t gnbox;                         // boxes in the grid arrays of this level
+    float2 *G, *H;                         // G [box][c][a][b] grid values, H [m][box][a][b] ring sums
+    const float2 *Ez, *Ex, *Ey;            // [nrp][p], [nrp][p][L], [nrp][p][L]
+    const int32_t *gperm, *gzs;            // source points by z-plane: permutation, [box][p + 1] offsets
 };
 
 // Kernel variants (the template parameters travel with the stage).
 enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
-    K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM
+    K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
+    K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP
 };
 
 struct Stage {
@@ -260,6 +269,12 @@ struct Level {
     int bwd_tile = 256;                  // target points per backward block
     int Tr = 0, R = 0, nchunk = 0;       // ring-pair forward: threads per ring, rings per block, ring chunks
     int bSplit = 1;                      // ring parts of the target transform
+    // grid form (tform 3): p nodes per axis, spacing h, kernel width w and shape beta
+    bool grid = false;
+    int gp = 0, gw = 0;
+    double gh = 0, gbeta = 0;
+    DevBuf<float2> Ez, Ex, Ey;           // [nrp][p], [nrp][p][L], [nrp][p][L]
+    DevBuf<int32_t> gperm, gzs;          // source points ordered by box and z-plane; [nbox_y][p + 1]
     // Lagrange node tables (FP32): Chebyshev nodes and 1 / prod_{b != a}(t_a - t_b)
     DevBuf<float> lnodes, lden;
     // box lists on the host, largest boxes first, and the box point ranges
@@ -291,6 +306,8 @@ struct Plan {
     DevBuf<float2> wz;                   // Lagrange per-pair products
     DevBuf<float4> wpart;                // forward-transform partial sums of point segments
     DevBuf<float2> wbpart;               // target-transform partial sums of ring parts
+    DevBuf<float2> wG, wH;               // grid-form workspaces (grid values, ring sums)
+    bool any_grid = false;
     DevBuf<float> amax;                  // max |Re u|, |Im u| of the current apply (FP16 scaling)
     bool any_fp16 = false;
     size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0;
@@ -323,6 +340,7 @@ void plan_stages(Plan &P, const Tune &t, hipStream_t st);
 struct LevelWork {                     // apply workspace a descriptor points into
     float4 *ut = nullptr, *vt = nullptr, *part = nullptr;
     float2 *ut2 = nullptr, *Z = nullptr, *bpart = nullptr;
+    float2 *G = nullptr, *H = nullptr;
 };
 // concurrent blocks per CU of a kernel variant (occupancy) and the device's CU count
 int stage_blocks_per_cu(int kern, int a, int b);

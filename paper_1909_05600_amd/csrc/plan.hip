@@ -13,6 +13,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -362,7 +365,8 @@ k_fill_groups(const int32_t *cls, int64_t n, const int32_t *gstart, int32_t *cur
 // coef_p = (2p + 1) i^p h_p(k |r0|) / (4 pi).  P_p(-t) = (-1)^p P_p(t) gives the antipode.
 __global__ void __launch_bounds__(kThreads)
 k_gegen_D(int64_t npair, int L, const double *dirs /*[npair][3] unit*/, const double *wts, const double *rhat,
-          const double2 *coef /*[ncls][L+1]*/, double k, float4 *D) {
+          const double2 *coef /*[ncls][L+1]*/, double k, float4 *D, const double *phat, int nphat, double dphat,
+          double kh) {
     extern __shared__ double2 sm[];
     double2 *sc = sm;               // series coefficients of this class
     double2 *rc = sm + (L + 1);     // Bonnet recurrence: P_{p+1} = a_p t P_p - b_p P_{p-1}
@@ -395,12 +399,122 @@ k_gegen_D(int64_t npair, int L, const double *dirs /*[npair][3] unit*/, const do
         }
     }
     // T(t) = even + odd, T(-t) = even - odd;  (ik/4pi) w (a + ib) = (w k / 4pi) (-b + ia)
-    const double f = wts[q] * k / (4.0 * M_PI);
+    double f = wts[q] * k / (4.0 * M_PI);
+    if (phat) {
+        // grid form: both transforms carry the kernel's Fourier transform Phi(q) = prod_d phi^(k s_d h);
+        // divide it out twice here (Phi(-q) = Phi(q))
+        double Phi = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            const double x = fabs(k * dirs[3 * q + d] * kh) / dphat;
+            const int i = min((int)x, nphat - 2);
+            const double t = x - i;
+            Phi *= phat[i] * (1.0 - t) + phat[i + 1] * t;
+        }
+        f /= Phi * Phi;
+    }
     D[(int64_t)c * npair + q] = make_float4((float)(-f * (ei + oi)), (float)(f * (er + orr)),
                                             (float)(-f * (ei - oi)), (float)(f * (er - orr)));
 }
 
+// ------------------------------------------------------------------ grid form tables
+// Ez[m][c] = e^{-ik cos(t_m) z_c}, Ex[m][a][n] = e^{-ik sin(t_m) cos(f_n) x_a}, Ey[m][b][n] =
+// e^{-ik sin(t_m) sin(f_n) y_b} for ring pairs m < nrp, n < L, grid nodes x_a = (a - (p-1)/2) h.
+// Phases in revolutions from the ring tables (k / 2pi folded in), reduced and evaluated in FP64.
+__global__ void __launch_bounds__(kThreads)
+k_grid_tables(int nrp, int L, int p, double h, const double2 *rings, const double2 *phis, float2 *Ez, float2 *Ex,
+              float2 *Ey) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t nxy = (int64_t)nrp * p * L;
+    auto cis = [](double rev) {
+        const double f = rev - floor(rev);
+        double sn, cs;
+        sincospi(2.0 * f, &sn, &cs);
+        return make_float2((float)cs, (float)(-sn));
+    };
+    if (i < nxy) {
+        const int n = (int)(i % L);
+        const int64_t ma = i / L;
+        const int a = (int)(ma % p), m = (int)(ma / p);
+        const double x = (a - 0.5 * (p - 1)) * h;
+        Ex[i] = cis(rings[m].x * phis[n].x * x);
+        Ey[i] = cis(rings[m].x * phis[n].y * x);
+    }
+    if (i < (int64_t)nrp * p) {
+        const int c = (int)(i % p), m = (int)(i / p);
+        Ez[i] = cis(rings[m].y * (c - 0.5 * (p - 1)) * h);
+    }
+}
+
+// z-plane of every source point of a level's box (for the spreading launches): count per (box, plane)
+__device__ __forceinline__ int grid_cell(double z, double cz, double inv_h, int p) {
+    const int c = (int)floor((z - cz) * inv_h + 0.5 * (p - 1));
+    return min(max(c, 0), p - 1);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *zs, const double *ctr, double inv_h, int p,
+              int32_t *cnt, int32_t *cell_of) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = nbox;   // box b with start[b] <= i < start[b + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const int c = grid_cell(zs[i], ctr[3 * lo + 2], inv_h, p);
+    const int64_t slot = (int64_t)lo * p + c;
+    cell_of[i] = (int32_t)slot;
+    atomicAdd(&cnt[slot], 1);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_grid_zscatter(int64_t n, const int32_t *cell_of, int32_t *cursor, int32_t *perm) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    perm[atomicAdd(&cursor[cell_of[i]], 1)] = (int32_t)i;
+}
+
+__global__ void k_copy_i32(const int32_t *a, int32_t *b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
 // ------------------------------------------------------------------ host helpers
+void gauss_legendre_host(int n, std::vector<double> &x, std::vector<double> &w);
+
+// Fourier transform of the spreading kernel phi(x) = exp(beta (sqrt(1 - (2x/w)^2) - 1)), |x| < w/2
+// (exponential of semicircle), on a uniform grid of frequencies [0, 2.1] (grid units; the transforms
+// need |k s_d h| <= pi / 1.9): Gauss-Legendre quadrature on the support, kept per (w, beta) for the
+// life of the process.
+const std::vector<double> &phi_hat_table(int w, double beta, double &step) {
+    static std::mutex mx;
+    static std::map<std::tuple<int, double>, std::vector<double>> cache;
+    constexpr int kTab = 4096;
+    constexpr double wmax = 2.1;
+    step = wmax / (kTab - 1);
+    std::lock_guard<std::mutex> lk(mx);
+    auto key = std::make_tuple(w, beta);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    std::vector<double> x, wt;
+    gauss_legendre_host(256, x, wt);
+    std::vector<double> f(x.size());
+    for (size_t j = 0; j < x.size(); ++j) {
+        const double t = x[j];   // 2 x / w
+        f[j] = std::exp(beta * (std::sqrt(std::max(0.0, 1.0 - t * t)) - 1.0)) * wt[j] * 0.5 * w;
+    }
+    std::vector<double> tab(kTab);
+    for (int i = 0; i < kTab; ++i) {
+        const double om = i * step;
+        double a = 0.0;
+        for (size_t j = 0; j < x.size(); ++j) a += f[j] * std::cos(om * 0.5 * w * x[j]);
+        tab[i] = a;
+    }
+    return cache.emplace(key, std::move(tab)).first->second;
+}
+
+
 void gauss_legendre_host(int n, std::vector<double> &x, std::vector<double> &w) {
     // Newton iteration on P_n from the Chebyshev-like initial guesses; nodes x_m in descending
     // order with exact mirror symmetry x_{n-1-m} = -x_m.
@@ -792,7 +906,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
 
     plog.mark("lists");
     // --- compression form and tables per level (Sec. 2.2.2, 2.2.3)
-    size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0;
+    size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0, ws_gG = 0, ws_gH = 0;
     for (int l = 1; l <= P.leaf; ++l) {
         Level &LV = P.lev[l];
         if (LV.nfar == 0) continue;
@@ -860,6 +974,65 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             const double max_rad = P.k * dl * std::sqrt(3.0) * 0.5;
             // FP32 phases go to the hardware sine unreduced, which needs |phase| <= 128 revolutions
             LV.phase64 = max_rad * std::ldexp(1.0, -22) > P.eps / 20.0 || max_rad / (2.0 * M_PI) > 128.0;
+            // form of the transforms: the direct sums, or the grid form where it is cheaper (points spread
+            // onto a uniform grid of spacing h <= pi / (1.9 k) with a kernel of width w, separable sums from
+            // the grid to the directions, the kernel's Fourier transform divided out in the transfer)
+            const double *dphat = nullptr;
+            int nphat = 0;
+            double dphat_step = 1.0;
+            {
+                const int w = P.eps >= 3e-4 ? 6 : 8;
+                const double hmax = M_PI / (1.9 * P.k);
+                int p = (int)std::ceil(dl / hmax) + w + 1;
+                p = (p + 7) / 8 * 8;
+                const double h = dl / (double)(p - 1 - w);
+                // cost model in seconds, from measured MI355X rates: direct sums 9e-14 s per (point,
+                // direction); grid form: spreading 0.8 ns and interpolation 0.26 ns per point (w = 6), the
+                // tiled sums 3.4e-14 s per FMA divided by the fraction of their tiles the shapes fill
+                const double nbf = (double)LV.h_fwd.size(), nbt = (double)LV.h_tgt.size(), ws = (double)w / 6.0;
+                const double p2 = (double)p * p, p3 = p2 * p;
+                auto fill = [](double n, double t) { return n / (std::ceil(n / t) * t); };
+                const double z_eff = fill(LV.nrp, 32) * fill(p, 32), phi_eff = fill(p, 64) * fill(L, 64);
+                const double direct = (LV.pts_src + LV.pts_tgt) * (double)LV.nq * 9e-14;
+                const double gridc = ws * ws * ws * (0.8e-9 * LV.pts_src + 0.26e-9 * LV.pts_tgt) +
+                                     (nbf + nbt) * (LV.nrp * p3 * 4.0 * 3.4e-14 / z_eff +
+                                                    (L + 1.0) * L * p2 * 4.0 * 3.4e-14 / phi_eff);
+                const size_t gnb = (size_t)std::max(nbx, nby);
+                const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
+                const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
+                const bool force_direct = (P.opt.flags & FFM_FLAG_DIRECT_TRANSFORMS) != 0;
+                LV.grid = !force_direct && L >= 8 && gbytes <= ((size_t)24 << 30) && (force_grid || gridc < direct);
+                if (LV.grid) {
+                    P.any_grid = true;
+                    LV.gw = w;
+                    LV.gp = p;
+                    LV.gh = h;
+                    LV.gbeta = 2.3 * w;
+                    const int64_t nxy = (int64_t)LV.nrp * p * L;
+                    LV.Ez.alloc((size_t)LV.nrp * p);
+                    LV.Ex.alloc((size_t)nxy);
+                    LV.Ey.alloc((size_t)nxy);
+                    FFM_LAUNCH(k_grid_tables, nblocks(std::max<int64_t>(nxy, (int64_t)LV.nrp * p)), kThreads, 0, st,
+                               LV.nrp, L, p, h, LV.rings.p, LV.phis.p, LV.Ez.p, LV.Ex.p, LV.Ey.p);
+                    // source points ordered by box and z-plane
+                    const int64_t ncell = (int64_t)nby * p;
+                    int32_t *cnt = SC.get<int32_t>(ncell + 1), *cell_of = SC.get<int32_t>(std::max<int64_t>(TY.n, 1));
+                    FFM_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (ncell + 1), st));
+                    FFM_LAUNCH(k_grid_zcount, nblocks(TY.n), kThreads, 0, st, TY.n, TY.lev[l].start.p, nby, TY.zs.p,
+                               TY.lev[l].ctr.p, 1.0 / h, p, cnt, cell_of);
+                    LV.gzs.alloc((size_t)ncell + 1);
+                    exclusive_scan_i32(cnt, LV.gzs.p, ncell, st, SC);
+                    int32_t *cursor = SC.get<int32_t>(ncell + 1);
+                    FFM_LAUNCH(k_copy_i32, nblocks(ncell + 1), kThreads, 0, st, LV.gzs.p, cursor, ncell + 1);
+                    LV.gperm.alloc((size_t)std::max<int64_t>(TY.n, 1));
+                    FFM_LAUNCH(k_grid_zscatter, nblocks(TY.n), kThreads, 0, st, TY.n, cell_of, cursor, LV.gperm.p);
+                    const std::vector<double> &tab = phi_hat_table(w, LV.gbeta, dphat_step);
+                    dphat = keep(SC, tab, st);
+                    nphat = (int)tab.size();
+                    ws_gG = std::max(ws_gG, gnb * p * p * p);
+                    ws_gH = std::max(ws_gH, gnb * (size_t)(L + 1) * p * p);
+                }
+            }
             // per-class series coefficients (host FP64), unit directions r0/|r0|
             std::vector<double> rhat(3 * (size_t)LV.ncls);
             std::vector<double2> coef((size_t)LV.ncls * (L + 1));
@@ -892,7 +1065,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             LV.D.alloc((size_t)LV.ncls * LV.npair);
             dim3 grid((unsigned)nblocks(LV.npair), (unsigned)LV.ncls);
             hipLaunchKernelGGL(k_gegen_D, grid, dim3(kThreads), 2 * sizeof(double2) * (L + 1), st, LV.npair, L, ddirs,
-                               dwts, drhat, dcoef, P.k, LV.D.p);
+                               dwts, drhat, dcoef, P.k, LV.D.p, dphat, nphat, dphat_step, LV.gh);
             FFM_HIP(hipGetLastError());
             plog.mark("tab.D");
             ws_src = std::max(ws_src, (size_t)nby * LV.npair);
@@ -974,7 +1147,9 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.wsrc.alloc(ws_src);
     P.wtgt.alloc(ws_tgt);
     P.wz.alloc(ws_z);
-    if (P.any_fp16) P.amax.alloc(1);
+    P.wG.alloc(ws_gG);
+    P.wH.alloc(ws_gH);
+    if (P.any_fp16 || P.any_grid) P.amax.alloc(1);
     plog.mark("alloc");
     // launches and descriptors
     P.dio.alloc(1);
@@ -1007,7 +1182,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.nclass[l] = LV.ncls;
         s.nq[l] = LV.nq;
         s.fwd_points[l] = LV.pts_src;
-        s.tform[l] = LV.method == kGegenbauer ? (LV.qG ? 2 : 1) : 0;
+        s.tform[l] = LV.method == kGegenbauer ? (LV.grid ? 3 : (LV.qG ? 2 : 1)) : 0;
         s.prec[l] = LV.fp16 ? 1 : 0;
         s.phase64[l] = LV.method == kGegenbauer && LV.phase64 ? 1 : 0;
         s.bwd_points[l] = LV.pts_tgt;
@@ -1083,7 +1258,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
         std::vector<int4> it;
         for (int64_t i = 0; i < nmax; i += kThreads) it.push_back(make_int4(0, (int)i, 0, 0));
         P.pre.push_back(make_stage(K_PERM_IN, 0, 0, -1, 0, 0, std::move(it), st, SC));
-        if (P.any_fp16) {
+        if (P.any_fp16 || P.any_grid) {
             std::vector<int4> z(1, make_int4(0, 0, 0, 0)), am;
             for (int64_t i = 0; i < P.ny; i += 16 * kThreads) am.push_back(make_int4(0, (int)i, 0, 0));
             P.pre.push_back(make_stage(K_AMAX, 1, 0, -1, 0, 0, std::move(z), st, SC));
@@ -1105,7 +1280,43 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
         if (LV.method == kNone) continue;
         const int s1 = 1 + 3 * (l - 1), s2 = s1 + 1, s3 = s1 + 2;
         const std::vector<int32_t> &sx = LV.h_sx;
-        if (LV.method == kGegenbauer) {
+        if (LV.method == kGegenbauer && LV.grid) {
+            // grid form: spread (per z-plane and 64 x 64 tile), sums over z (8 ring pairs per block), sums
+            // over the plane to the directions (64 directions per block); the transfer; the mirror stages
+            const int L = LV.L, p = LV.gp, nta = (p + 63) / 64;
+            LV.qG = 0;
+            LV.qSplit = 1;
+            LV.bSplit = 1;
+            const int ncol = (p * p + 127) / 128;
+            std::vector<int4> a1, a2, a3, tr, b1, b2, b3;
+            for (int32_t b : LV.h_fwd) {
+                for (int c = 0; c < p; ++c)
+                    for (int t = 0; t < nta * nta; ++t) a1.push_back(make_int4(l, b, c, t));
+                for (int t = 0; t < ncol; ++t)
+                    for (int mc = 0; mc < (LV.nrp + 31) / 32; ++mc) a2.push_back(make_int4(l, b, t, mc));
+                for (int m = 0; m <= L; ++m)
+                    for (int nt = 0; nt < (L + 63) / 64; ++nt) a3.push_back(make_int4(l, b, m, nt));
+            }
+            LV.stages.push_back(make_stage(K_GSPREAD, 0, 0, -1, l, 0, std::move(a1), st, SC));
+            LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
+            LV.stages.push_back(make_stage(K_GPHI, 0, 0, s1, l, 0, std::move(a3), st, SC));
+            int bs, ppt;
+            pick_pair_tile(LV.npair, 2, bs, ppt);
+            const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
+            for (int64_t q = 0; q < nt; ++q)
+                for (int32_t t : LV.h_tgt) tr.push_back(make_int4(l, t, (int)q, 0));
+            LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
+            for (int32_t t : LV.h_tgt) {
+                for (int m = 0; m <= L; ++m)
+                    for (int q = 0; q < nta * nta; ++q) b1.push_back(make_int4(l, t, m, q));
+                for (int q = 0; q < ncol; ++q)
+                    for (int cc = 0; cc < (p + 31) / 32; ++cc) b2.push_back(make_int4(l, t, q, cc));
+                for (int32_t i = sx[t]; i < sx[t + 1]; i += kThreads) b3.push_back(make_int4(l, t, i, 0));
+            }
+            LV.stages.push_back(make_stage(K_GPHIT, 0, 0, -1, l, 0, std::move(b1), st, SC));
+            LV.stages.push_back(make_stage(K_GZT, 0, 0, -1, l, 0, std::move(b2), st, SC));
+            LV.stages.push_back(make_stage(K_GINTERP, 0, 0, s3, l, 0, std::move(b3), st, SC));
+        } else if (LV.method == kGegenbauer) {
             const int L = LV.L;
             LV.qG = L >= 64 ? tu.ring_g : (L >= 32 ? 2 : 0);
             if (LV.qG && (L + LV.qG - 1) / LV.qG > kThreads) LV.qG = 4;   // one ring must fit one block
@@ -1256,6 +1467,18 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.rp = LV.rp;
     d.maxpts = LV.max_src_pts;
     d.sT = LV.sT;
+    d.gp = LV.gp;
+    d.gw = LV.gw;
+    d.gbeta = (float)LV.gbeta;
+    d.ginv_h = LV.grid ? (float)(1.0 / LV.gh) : 0.f;
+    d.gnbox = std::max(LX.nbox, LY.nbox);
+    d.G = w.G;
+    d.H = w.H;
+    d.Ez = LV.Ez.p;
+    d.Ex = LV.Ex.p;
+    d.Ey = LV.Ey.p;
+    d.gperm = LV.gperm.p;
+    d.gzs = LV.gzs.p;
     return d;
 }
 
@@ -1270,6 +1493,8 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st) {
     w.ut2 = reinterpret_cast<float2 *>(P.wsrc.p);
     w.Z = P.wz.p;
     w.bpart = P.wbpart.p;
+    w.G = P.wG.p;
+    w.H = P.wH.p;
     P.hdesc.clear();
     for (int l = 0; l <= P.leaf; ++l) P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
@@ -1295,7 +1520,7 @@ size_t plan_device_bytes(const Plan &P) {
         for (const Stage &S : L.stages) b += S.ditems.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
-         P.wbpart.bytes();
+         P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
     for (const Stage &S : P.pre) b += S.ditems.bytes();
     for (const Stage &S : P.post) b += S.ditems.bytes();

@@ -32,7 +32,7 @@ struct ReqWork {
     DevBuf<char> block;
     float2 *u = nullptr, *v = nullptr, *Z = nullptr;
     float4 *ut = nullptr, *vt = nullptr, *part = nullptr;
-    float2 *bpart = nullptr;
+    float2 *bpart = nullptr, *G = nullptr, *H = nullptr;
     float *amax = nullptr;
 };
 
@@ -40,7 +40,8 @@ size_t work_bytes(const Plan &P) {
     if (P.empty) return 0;
     return align256(sizeof(float2) * P.ny) + align256(sizeof(float2) * P.nx) + align256(sizeof(float4) * P.ws_src) +
            align256(sizeof(float4) * P.ws_tgt) + align256(sizeof(float2) * P.ws_z) +
-           align256(sizeof(float4) * P.wpart.n) + align256(sizeof(float2) * P.wbpart.n) + (P.any_fp16 ? 256 : 0);
+           align256(sizeof(float4) * P.wpart.n) + align256(sizeof(float2) * P.wbpart.n) +
+           align256(sizeof(float2) * P.wG.n) + align256(sizeof(float2) * P.wH.n) + (P.any_fp16 || P.any_grid ? 256 : 0);
 }
 
 void carve(const Plan &P, ReqWork &w) {
@@ -59,7 +60,9 @@ void carve(const Plan &P, ReqWork &w) {
     w.Z = reinterpret_cast<float2 *>(take(sizeof(float2) * P.ws_z));
     w.part = reinterpret_cast<float4 *>(take(sizeof(float4) * P.wpart.n));
     w.bpart = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wbpart.n));
-    w.amax = P.any_fp16 ? reinterpret_cast<float *>(take(sizeof(float))) : nullptr;
+    w.G = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wG.n));
+    w.H = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wH.n));
+    w.amax = P.any_fp16 || P.any_grid ? reinterpret_cast<float *>(take(sizeof(float))) : nullptr;
 }
 
 }  // namespace
@@ -126,6 +129,8 @@ void Server::start_one(Request *r, int slot) {
     w.ut2 = reinterpret_cast<float2 *>(r->work.ut);
     w.Z = r->work.Z;
     w.bpart = r->work.bpart;
+    w.G = r->work.G;
+    w.H = r->work.H;
     const int nd = P.leaf + 1;
     const size_t db = sizeof(LDesc) * nd;
     r->pinned = pinned_alloc(db + sizeof(IoEntry));
