@@ -327,62 +327,75 @@ def main():
     torch.cuda.synchronize()
 
     tiles = [4, 2]
+    plan_stream = torch.cuda.Stream()
 
-    def step(record):
+    def make_plan():
         t0 = time.perf_counter()
-        plan = ffm.Plan(X, X, ffm.FFM_HELMHOLTZ, w.k, w.eps, timing=True)
-        tiles[:] = plan.tiles()
-        t1 = time.perf_counter()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        plan.apply(wu, out=out)
-        e1.record(stream)
-        e1.synchronize()
-        if record is not None:
-            record["plan_ms"].append((t1 - t0) * 1e3)
-            record["apply_ms"].append(e0.elapsed_time(e1))
-            record["phases"].append(plan.timing())
-            record["stats"] = plan.stats()
-        plan.destroy()
+        plan = ffm.Plan(X, X, ffm.FFM_HELMHOLTZ, w.k, w.eps, timing=True, stream=plan_stream)
+        return plan, t0, time.perf_counter()
 
-    for _ in range(args.warmup):
-        step(None)
-    rec = {"plan_ms": [], "apply_ms": [], "phases": [], "stats": None}
-    step_ms = []
+    def run(nsteps, record):
+        """nsteps complete products; the plan of product i+1 is built (host work, and its kernels on a
+        second stream) while product i's apply runs on the GPU: every product still runs its own full plan
+        and apply, in order, and the apply starts only once its plan is complete."""
+        if nsteps == 0:
+            return
+        cur = make_plan()
+        for i in range(nsteps):
+            plan, tp0, tp1 = cur
+            tiles[:] = plan.tiles()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.apply(wu, out=out, stream=stream)
+            e1.record(stream)
+            nxt = make_plan() if i + 1 < nsteps else None
+            e1.synchronize()
+            t_done = time.perf_counter()
+            if record is not None:
+                record["plan_ms"].append((tp1 - tp0) * 1e3)
+                record["apply_ms"].append(e0.elapsed_time(e1))
+                record["latency_ms"].append((t_done - tp0) * 1e3)
+                record["phases"].append(plan.timing())
+                record["stats"] = plan.stats()
+            plan.destroy()
+            cur = nxt
+
+    run(args.warmup, None)
+    rec = {"plan_ms": [], "apply_ms": [], "latency_ms": [], "phases": [], "stats": None}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        step(rec)
-        step_ms.append((time.perf_counter() - ts) * 1e3)
+    run(args.steps, rec)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = t_total * 1e3 / args.steps
+    step_ms = rec["latency_ms"]
 
     st = rec["stats"]
     ph = np.array(rec["phases"])          # [steps][64]
     leaf = st["leaf"]
-    # Dominant kernel: the ring-pair plane-wave transform (forward, slot 1 + 3(l-1), or backward, slot
-    # 3 + 3(l-1)) with the larger total time; its launches are the ring-pair levels of the apply.
-    ring = [l for l in range(1, leaf + 1) if st["method"][l] == 2 and st["tform"][l] == 2]
-    fwd_ms = {l: ph[:, 1 + 3 * (l - 1)].sum() for l in ring}
-    bwd_ms = {l: ph[:, 3 + 3 * (l - 1)].sum() for l in ring}
+    # Dominant kernel: among the ring-pair plane-wave transforms (one kernel symbol per template instance;
+    # forward in slot 1 + 3(l-1), backward in slot 3 + 3(l-1)), the symbol with the largest total time.
     per_dir = SLOTS_PER_DIRECTION[2]
-    if sum(bwd_ms.values()) >= sum(fwd_ms.values()):
-        t_ms, pts, name = bwd_ms, "bwd_points", "k_pw_backward_rings<%s, %s>"
-        tile = "%d, %d" % (tiles[1], 4 if tiles[1] == 1 else 2)
-    else:
-        t_ms, pts, name = fwd_ms, "fwd_points", "k_pw_forward_rings<%s, %s>"
-        tile = "%d" % tiles[0]
-    # one kernel symbol: the levels sharing the phase precision of the most expensive level
-    lmax = max(ring, key=lambda l: t_ms[l])
-    p64 = st["phase64"][lmax]
-    lv = [l for l in ring if st["phase64"][l] == p64]
-    dom = name % (tile, "true" if p64 else "false")
-    d_ms = sum(t_ms[l] for l in lv)
-    d_slots = sum(args.steps * st[pts][l] * st["nq"][l] * per_dir for l in lv)
-    nlaunch = args.steps * len(lv)
+    groups = {}
+    for l in range(1, leaf + 1):
+        if st["method"][l] != 2 or st["tform"][l] != 2:
+            continue
+        L = st["order"][l]
+        g = tiles[0] if L >= 64 else 2
+        if (L + g - 1) // g > 256:
+            g = 4
+        p64 = "true" if st["phase64"][l] else "false"
+        pt = tiles[1]
+        for sym, slot, pts in (("k_pw_forward_rings<%d, %s>" % (g, p64), 1 + 3 * (l - 1), "fwd_points"),
+                               ("k_pw_backward_rings<%d, %d, %s>" % (pt, 4 if pt == 1 else 2, p64), 3 + 3 * (l - 1),
+                                "bwd_points")):
+            e = groups.setdefault(sym, [0.0, 0.0, 0])
+            e[0] += ph[:, slot].sum()
+            e[1] += args.steps * st[pts][l] * st["nq"][l] * per_dir
+            e[2] += args.steps
+    dom = max(groups, key=lambda k: groups[k][0]) if groups else "none"
+    d_ms, d_slots, nlaunch = groups.get(dom, (0.0, 0.0, 0))
     achieved = 2 * d_slots / (d_ms * 1e-3) / 1e12 if d_ms > 0 else 0.0
     traffic = TRAFFIC.get(dom) if _source_hash() == TRAFFIC_SOURCE_HASH else None
     phase_mean = ph.mean(axis=0)
@@ -408,11 +421,15 @@ def main():
         "config": {"workload": "helmholtz_sphere", "n": w.n, "k": round(w.k, 4), "eps": w.eps,
                    "points": "uniform on the unit sphere (seed 2), sources = targets",
                    "u": "complex64, Re/Im ~ N(0,1), w = 4 pi / N",
-                   "step": "ffm_plan + ffm_apply + ffm_destroy (the whole product)"},
+                   "step": "ffm_plan + ffm_apply + ffm_destroy (the whole product); the plan of the next "
+                           "product is built while this product's apply runs"},
         "apply_points_per_s": w.n / (np.mean(rec["apply_ms"]) * 1e-3),
         "apply_ms": float(np.mean(rec["apply_ms"])),
         "plan_ms": float(np.mean(rec["plan_ms"])),
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "definition": "per product, from the start of its plan to the end of its apply"},
+        "plan_plus_apply_ms": float(np.mean(rec["plan_ms"]) + np.mean(rec["apply_ms"])),
+        "sequential_points_per_s": w.n / ((np.mean(rec["plan_ms"]) + np.mean(rec["apply_ms"])) * 1e-3),
         "phases_ms": phases,
         "roofline": {
             "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",

@@ -12,6 +12,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace ffm {
 
@@ -1402,6 +1405,17 @@ KernelFn kernel_of(const Stage &S, int &threads) {
 }  // namespace
 
 int stage_blocks_per_cu(int kern, int a, int b) {
+    // a property of the compiled kernel and the device: queried once per (device, variant)
+    static std::mutex mx;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
+    int dev = 0;
+    FFM_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, kern, a, b);
+    {
+        std::lock_guard<std::mutex> lk(mx);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
     Stage S;
     S.kern = kern;
     S.a = a;
@@ -1410,14 +1424,22 @@ int stage_blocks_per_cu(int kern, int a, int b) {
     KernelFn fn = kernel_of(S, threads);
     int nb = 0;
     FFM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0));
-    return std::max(nb, 1);
+    nb = std::max(nb, 1);
+    std::lock_guard<std::mutex> lk(mx);
+    cache[key] = nb;
+    return nb;
 }
 
 int device_cus() {
+    static std::mutex mx;
+    static std::map<int, int> cache;
     int dev = 0, n = 0;
     FFM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mx);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
     FFM_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
-    return std::max(n, 1);
+    return cache[dev] = std::max(n, 1);
 }
 
 void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream_t st) {
