@@ -701,20 +701,24 @@ k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int
 }
 
 // Sums over the plane to the directions: u~(m, n) = sum_a Ex[a][n] X[a][n], X = H_m Ey (sum over b), and
-// u~(m, n+L) with the conjugate tables (the same four real products).  A tiled product: 64 rows a x 64
-// azimuths n per block, 4 x 4 per thread, b staged through LDS 32 at a time; then each thread's sums over
-// its 4 rows are added over the 16 row groups in order.  Item (desc, box, ring, azimuth tile).
+// u~(m, n+L) with the conjugate tables (the same four real products).  A tiled product: 4 rows x 4 azimuths
+// per thread; the rows of a 64-row pass are split over TA = ceil(rows / 4) thread rows and the azimuths over
+// TN = min(32, 256 / TA) thread columns (grid_phi_tile); b is staged through LDS 32 at a time.  Each thread's
+// sums over its rows are then added over the thread rows in order.  Item (desc, box, ring, azimuth tile).
 __global__ void __launch_bounds__(kThreads)
 k_grid_phi(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int sb = wk.y, m = wk.z;
     const int p = d.gp, L = d.L, mt = min(m, L - m);
-    const int n0 = wk.w * 64;
-    const int tid = threadIdx.x, ta = tid / 16, tn = tid % 16;
-    __shared__ float4 Hs[32][32];    // [b][rows a]  (two complex per float4)
-    __shared__ float4 Es[32][32];    // [b][azimuths n]
-    __shared__ float4 red[16][64];   // [row group][n]: (u~(m,n), u~(m,n+L)) partial sums
+    int TA, TN;
+    grid_phi_tile(p, TA, TN);
+    const int NT = 4 * TN, n0 = wk.w * NT;
+    const int tid = threadIdx.x, ta = tid / TN, tn = tid % TN;
+    const bool act = tid < TA * TN;
+    __shared__ float4 smem[3072];            // 48 KB
+    float4 *Hs = smem;                       // [32 b][32]: 64 complex rows a
+    float4 *Es = smem + 32 * 32;             // [32 b][64]: 128 complex azimuths n
     const float2 *H = d.H + ((int64_t)m * d.gnbox + sb) * p * p;
     const float2 *Ey = d.Ey + (int64_t)mt * p * L;
     const float2 *Ex = d.Ex + (int64_t)mt * p * L;
@@ -732,55 +736,66 @@ k_grid_phi(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
             __syncthreads();
             for (int k = tid; k < 32 * 64; k += kThreads) {
                 const int b = k / 64, r = k % 64;
-                reinterpret_cast<float2 *>(&Hs[b][0])[r] =
+                reinterpret_cast<float2 *>(Hs + b * 32)[r] =
                     (b < nbb && a0 + r < p) ? H[(int64_t)(a0 + r) * p + b0 + b] : make_float2(0.f, 0.f);
-                reinterpret_cast<float2 *>(&Es[b][0])[r] =
+            }
+            for (int k = tid; k < 32 * NT; k += kThreads) {
+                const int b = k / NT, r = k % NT;
+                reinterpret_cast<float2 *>(Es + b * 64)[r] =
                     (b < nbb && n0 + r < L) ? Ey[(int64_t)(b0 + b) * L + n0 + r] : make_float2(0.f, 0.f);
             }
             __syncthreads();
-            for (int b = 0; b < nbb; ++b) {
-                const float4 h01 = Hs[b][2 * ta], h23 = Hs[b][2 * ta + 1];
-                const float4 e01 = Es[b][2 * tn], e23 = Es[b][2 * tn + 1];
-                const float hr[4] = {h01.x, h01.z, h23.x, h23.z}, hi[4] = {h01.y, h01.w, h23.y, h23.w};
-                const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
+            if (act) {
+                for (int b = 0; b < nbb; ++b) {
+                    const float4 h01 = Hs[b * 32 + 2 * ta], h23 = Hs[b * 32 + 2 * ta + 1];
+                    const float4 e01 = Es[b * 64 + 2 * tn], e23 = Es[b * 64 + 2 * tn + 1];
+                    const float hr[4] = {h01.x, h01.z, h23.x, h23.z}, hi[4] = {h01.y, h01.w, h23.y, h23.w};
+                    const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                    for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        P1[i][j] = fmaf(er[j], hr[i], P1[i][j]);
-                        P2[i][j] = fmaf(ei[j], hi[i], P2[i][j]);
-                        P3[i][j] = fmaf(er[j], hi[i], P3[i][j]);
-                        P4[i][j] = fmaf(ei[j], hr[i], P4[i][j]);
-                    }
+                        for (int j = 0; j < 4; ++j) {
+                            P1[i][j] = fmaf(er[j], hr[i], P1[i][j]);
+                            P2[i][j] = fmaf(ei[j], hi[i], P2[i][j]);
+                            P3[i][j] = fmaf(er[j], hi[i], P3[i][j]);
+                            P4[i][j] = fmaf(ei[j], hr[i], P4[i][j]);
+                        }
+                }
             }
         }
+        if (act) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int a = a0 + ta * 4 + i;
-            if (a >= p) continue;
+            for (int i = 0; i < 4; ++i) {
+                const int a = a0 + ta * 4 + i;
+                if (a >= p) continue;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int n = n0 + tn * 4 + j;
-                if (n >= L) continue;
-                const float2 ex = Ex[(int64_t)a * L + n];
-                const float xr = P1[i][j] - P2[i][j], xi = P3[i][j] + P4[i][j];     // sum_b Ey H
-                const float yr = P1[i][j] + P2[i][j], yi = P3[i][j] - P4[i][j];     // sum_b conj(Ey) H
-                tr[j] = fmaf(ex.x, xr, fmaf(-ex.y, xi, tr[j]));
-                ti[j] = fmaf(ex.x, xi, fmaf(ex.y, xr, ti[j]));
-                ur[j] = fmaf(ex.x, yr, fmaf(ex.y, yi, ur[j]));
-                ui[j] = fmaf(ex.x, yi, fmaf(-ex.y, yr, ui[j]));
+                for (int j = 0; j < 4; ++j) {
+                    const int n = n0 + tn * 4 + j;
+                    if (n >= L) continue;
+                    const float2 ex = Ex[(int64_t)a * L + n];
+                    const float xr = P1[i][j] - P2[i][j], xi = P3[i][j] + P4[i][j];     // sum_b Ey H
+                    const float yr = P1[i][j] + P2[i][j], yi = P3[i][j] - P4[i][j];     // sum_b conj(Ey) H
+                    tr[j] = fmaf(ex.x, xr, fmaf(-ex.y, xi, tr[j]));
+                    ti[j] = fmaf(ex.x, xi, fmaf(ex.y, xr, ti[j]));
+                    ur[j] = fmaf(ex.x, yr, fmaf(ex.y, yi, ur[j]));
+                    ui[j] = fmaf(ex.x, yi, fmaf(-ex.y, yr, ui[j]));
+                }
             }
         }
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) red[ta][tn * 4 + j] = make_float4(tr[j], ti[j], ur[j], ui[j]);
     __syncthreads();
-    if (tid >= 64) return;
+    float4 *red = smem;                      // [16 thread rows][128 azimuths]
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[ta * 128 + tn * 4 + j] = make_float4(tr[j], ti[j], ur[j], ui[j]);
+    }
+    __syncthreads();
+    if (tid >= NT) return;
     const int n = n0 + tid;
     if (n >= L) return;
-    float4 a = red[0][tid];
-    for (int q = 1; q < 16; ++q) {
-        const float4 b = red[q][tid];
+    float4 a = red[tid];
+    for (int q = 1; q < TA; ++q) {
+        const float4 b = red[q * 128 + tid];
         a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
     }
     // a.xy = u~(m, n), a.zw = u~(m, n + L), into the antipodal-pair layout
@@ -799,81 +814,94 @@ k_grid_phi(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
     }
 }
 
-// v~ of ring m back to the plane: H'[a][b] = sum_{n < L} conj(Ex) conj(Ey) v~(m, n) + Ex Ey v~(m, n + L),
-// one 64 x 64 tile of (a, b) per block, 4 x 4 per thread.  Item (desc, box, ring, tile).
+// v~ of ring m back to the plane: H'[a][b] = sum_{n < L} conj(Ex) conj(Ey) v~(m, n) + Ex Ey v~(m, n + L)
+// = sum_n S Re(Ey) + i D Im(Ey) with S = conj(Ex) v~(n) + Ex v~(n+L), D = Ex v~(n+L) - conj(Ex) v~(n).
+// 4 x 4 (a, b) per thread over a 64 x 64 tile; when the grid is smaller, R = grid_phit_rings rings share a
+// block (each its own tables and v~), n staged through LDS 32 / R at a time.  Item (desc, box, first ring,
+// tile).
 __global__ void __launch_bounds__(kThreads)
 k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
-    const int tb_ = wk.y, m = wk.z;
-    const int p = d.gp, L = d.L, mt = min(m, L - m);
+    const int tb_ = wk.y;
+    const int p = d.gp, L = d.L;
+    const int R = grid_phit_rings(p), NC = 32 / R;
+    const int TC = p > 64 ? 16 : (p + 3) / 4, TAB = TC * TC;     // thread tiles per ring
     const int nta = (p + 63) / 64;
     const int a0 = (wk.w / nta) * 64, b0 = (wk.w % nta) * 64;
-    const int tid = threadIdx.x, ta = tid / 16, tb = tid % 16;
-    __shared__ float4 sS[32][32], sD[32][32], sE[32][32];   // [n][pairs of a (or b)]: 64 complex per row
+    const int tid = threadIdx.x, rr = tid / TAB, tt = tid % TAB, ta = tt / TC, tb = tt % TC;
+    const int m = wk.z + rr;
+    const bool act = rr < R && m <= L;
+    const int mt = act ? min(m, L - m) : 0;
+    __shared__ float4 sS[32][32], sD[32][32], sE[32][32];   // [ring r x NC + n][64 complex]
     float2 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
     const float2 *vt = reinterpret_cast<const float2 *>(d.vt) + (int64_t)tb_ * d.npair * 2;
-    const float2 *Ey = d.Ey + (int64_t)mt * p * L;
-    const float2 *Ex = d.Ex + (int64_t)mt * p * L;
     const int64_t twoL = 2 * (int64_t)L;
-    for (int n0 = 0; n0 < L; n0 += 32) {
-        const int cnt = min(32, L - n0);
+    for (int n0 = 0; n0 < L; n0 += NC) {
+        const int cnt = min(NC, L - n0);
         __syncthreads();
-        for (int k = tid; k < 32 * 64; k += kThreads) {
-            const int nn = k / 64, r = k % 64, n = n0 + nn;
+        for (int k = tid; k < R * NC * 64; k += kThreads) {
+            const int r = k / (NC * 64), nn = (k / 64) % NC, idx = k % 64, n = n0 + nn;
+            const int mr = wk.z + r;
             float2 S = make_float2(0.f, 0.f), Dd = S, E = S;
-            if (nn < cnt) {
-                float2 v1, v2;   // v~(m, n), v~(m, n + L)
-                if (2 * m < L) {
-                    v1 = vt[(m * twoL + n) * 2];
-                    v2 = vt[(m * twoL + n + L) * 2];
-                } else if (2 * m > L) {
-                    const int64_t m2 = L - m;
+            if (nn < cnt && mr <= L) {
+                const int mtr = min(mr, L - mr);
+                float2 v1, v2;   // v~(mr, n), v~(mr, n + L)
+                if (2 * mr < L) {
+                    v1 = vt[(mr * twoL + n) * 2];
+                    v2 = vt[(mr * twoL + n + L) * 2];
+                } else if (2 * mr > L) {
+                    const int64_t m2 = L - mr;
                     v1 = vt[(m2 * twoL + n + L) * 2 + 1];
                     v2 = vt[(m2 * twoL + n) * 2 + 1];
                 } else {
-                    v1 = vt[(m * twoL + n) * 2];
-                    v2 = vt[(m * twoL + n) * 2 + 1];
+                    v1 = vt[(mr * twoL + n) * 2];
+                    v2 = vt[(mr * twoL + n) * 2 + 1];
                 }
-                const int a = a0 + r;
+                const int a = a0 + idx;
                 if (a < p) {
-                    const float2 ex = Ex[(int64_t)a * L + n];
+                    const float2 ex = d.Ex[((int64_t)mtr * p + a) * L + n];
                     const float y1r = fmaf(ex.x, v1.x, ex.y * v1.y), y1i = fmaf(ex.x, v1.y, -(ex.y * v1.x));   // conj(ex) v1
                     const float y2r = fmaf(ex.x, v2.x, -(ex.y * v2.y)), y2i = fmaf(ex.x, v2.y, ex.y * v2.x);   // ex v2
                     S = make_float2(y1r + y2r, y1i + y2i);
                     Dd = make_float2(y2r - y1r, y2i - y1i);
                 }
-                const int b = b0 + r;
-                if (b < p) E = Ey[(int64_t)b * L + n];
+                const int b = b0 + idx;
+                if (b < p) E = d.Ey[((int64_t)mtr * p + b) * L + n];
             }
-            reinterpret_cast<float2 *>(&sS[nn][0])[r] = S;
-            reinterpret_cast<float2 *>(&sD[nn][0])[r] = Dd;
-            reinterpret_cast<float2 *>(&sE[nn][0])[r] = E;
+            reinterpret_cast<float2 *>(&sS[r * NC + nn][0])[idx] = S;
+            reinterpret_cast<float2 *>(&sD[r * NC + nn][0])[idx] = Dd;
+            reinterpret_cast<float2 *>(&sE[r * NC + nn][0])[idx] = E;
         }
         __syncthreads();
-        for (int nn = 0; nn < cnt; ++nn) {
-            const float4 s01 = sS[nn][2 * ta], s23 = sS[nn][2 * ta + 1];
-            const float4 d01 = sD[nn][2 * ta], d23 = sD[nn][2 * ta + 1];
-            const float4 e01 = sE[nn][2 * tb], e23 = sE[nn][2 * tb + 1];
-            const float2 sv[4] = {make_float2(s01.x, s01.y), make_float2(s01.z, s01.w), make_float2(s23.x, s23.y),
-                                  make_float2(s23.z, s23.w)};
-            const float2 dv[4] = {make_float2(d01.x, d01.y), make_float2(d01.z, d01.w), make_float2(d23.x, d23.y),
-                                  make_float2(d23.z, d23.w)};
-            const float2 ev[4] = {make_float2(e01.x, e01.y), make_float2(e01.z, e01.w), make_float2(e23.x, e23.y),
-                                  make_float2(e23.z, e23.w)};
+        if (act) {
+            for (int nn = 0; nn < cnt; ++nn) {
+                const int row = rr * NC + nn;
+                const float4 s01 = sS[row][2 * ta], s23 = sS[row][2 * ta + 1];
+                const float4 d01 = sD[row][2 * ta], d23 = sD[row][2 * ta + 1];
+                const float4 e01 = sE[row][2 * tb], e23 = sE[row][2 * tb + 1];
+                const float2 sv[4] = {make_float2(s01.x, s01.y), make_float2(s01.z, s01.w), make_float2(s23.x, s23.y),
+                                      make_float2(s23.z, s23.w)};
+                const float2 dv[4] = {make_float2(d01.x, d01.y), make_float2(d01.z, d01.w), make_float2(d23.x, d23.y),
+                                      make_float2(d23.z, d23.w)};
+                const float2 ev[4] = {make_float2(e01.x, e01.y), make_float2(e01.z, e01.w), make_float2(e23.x, e23.y),
+                                      make_float2(e23.z, e23.w)};
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j].x = fmaf(sv[i].x, ev[j].x, fmaf(-dv[i].y, ev[j].y, acc[i][j].x));
-                    acc[i][j].y = fmaf(sv[i].y, ev[j].x, fmaf(dv[i].x, ev[j].y, acc[i][j].y));
-                }
+                    for (int j = 0; j < 4; ++j) {
+                        acc[i][j].x = fmaf(sv[i].x, ev[j].x, fmaf(-dv[i].y, ev[j].y, acc[i][j].x));
+                        acc[i][j].y = fmaf(sv[i].y, ev[j].x, fmaf(dv[i].x, ev[j].y, acc[i][j].y));
+                    }
+            }
         }
     }
+    if (!act) return;
+    (void)mt;
     float2 *Hb = d.H + ((int64_t)m * d.gnbox + tb_) * p * p;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

@@ -227,6 +227,22 @@ struct Stage {
     DevBuf<int4> ditems;
 };
 
+// Thread layout of the grid-form sums over the plane (k_grid_phi): TA thread rows of 4 grid rows each
+// (a pass covers at most 64 rows), TN thread columns of 4 azimuths each.
+__host__ __device__ inline void grid_phi_tile(int p, int &TA, int &TN) {
+    const int pp = p < 64 ? p : 64;
+    TA = (pp + 3) / 4;
+    TN = 256 / TA < 32 ? 256 / TA : 32;
+}
+// Rings per block of the mirror sums (k_grid_phit): 4 x 4 (a, b) per thread over the grid's (at most
+// 64 x 64) tile, as many rings as fill 256 threads.
+__host__ __device__ inline int grid_phit_rings(int p) {
+    if (p > 64) return 1;
+    const int t = (p + 3) / 4;
+    const int r = 256 / (t * t);
+    return r < 1 ? 1 : (r > 4 ? 4 : r);
+}
+
 // Tile choices of the plane-wave kernels (the autotuner picks among them).
 struct Tune {
     int ring_g = 4;                   // groups of 4 directions per thread in ring-pair forward kernels

@@ -992,11 +992,22 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 const double nbf = (double)LV.h_fwd.size(), nbt = (double)LV.h_tgt.size(), ws = (double)w / 6.0;
                 const double p2 = (double)p * p, p3 = p2 * p;
                 auto fill = [](double n, double t) { return n / (std::ceil(n / t) * t); };
-                const double z_eff = fill(LV.nrp, 32) * fill(p, 32), phi_eff = fill(p, 64) * fill(L, 64);
+                int TA, TN;
+                grid_phi_tile(p, TA, TN);
+                const int RR = grid_phit_rings(p), TC = p > 64 ? 16 : (p + 3) / 4;
+                const double z_eff = fill(LV.nrp, 32) * fill(p, 32);
+                // narrower tiles (p < 64) reuse each staged value fewer times: measured rates fall as
+                // (p / 64)^0.5 for the sums to the directions and (p / 64)^0.75 for the sums back
+                const double narrow = std::min(1.0, p / 64.0);
+                const double phi_eff =
+                    (p > 64 ? fill(p, 64) : 1.0) * (TA * TN / 256.0) * fill(L, 4.0 * TN) * std::sqrt(narrow);
+                const double phit_eff = (p > 64 ? fill(p, 64) * fill(p, 64) : RR * TC * TC / 256.0) *
+                                        fill(L + 1.0, RR) * std::pow(narrow, 0.75);
                 const double direct = (LV.pts_src + LV.pts_tgt) * (double)LV.nq * 9e-14;
                 const double gridc = ws * ws * ws * (0.8e-9 * LV.pts_src + 0.26e-9 * LV.pts_tgt) +
-                                     (nbf + nbt) * (LV.nrp * p3 * 4.0 * 3.4e-14 / z_eff +
-                                                    (L + 1.0) * L * p2 * 4.0 * 3.4e-14 / phi_eff);
+                                     (nbf + nbt) * LV.nrp * p3 * 4.0 * 3.4e-14 / z_eff +
+                                     nbf * (L + 1.0) * L * p2 * 4.0 * 3.4e-14 / phi_eff +
+                                     nbt * (L + 1.0) * L * p2 * 4.0 * 3.4e-14 / phit_eff;
                 const size_t gnb = (size_t)std::max(nbx, nby);
                 const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
                 const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
@@ -1288,6 +1299,9 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             LV.qSplit = 1;
             LV.bSplit = 1;
             const int ncol = (p * p + 127) / 128;
+            int TA, TN;
+            grid_phi_tile(p, TA, TN);
+            const int NT = 4 * TN, RR = grid_phit_rings(p);
             std::vector<int4> a1, a2, a3, tr, b1, b2, b3;
             for (int32_t b : LV.h_fwd) {
                 for (int c = 0; c < p; ++c)
@@ -1295,7 +1309,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 for (int t = 0; t < ncol; ++t)
                     for (int mc = 0; mc < (LV.nrp + 31) / 32; ++mc) a2.push_back(make_int4(l, b, t, mc));
                 for (int m = 0; m <= L; ++m)
-                    for (int nt = 0; nt < (L + 63) / 64; ++nt) a3.push_back(make_int4(l, b, m, nt));
+                    for (int nt = 0; nt < (L + NT - 1) / NT; ++nt) a3.push_back(make_int4(l, b, m, nt));
             }
             LV.stages.push_back(make_stage(K_GSPREAD, 0, 0, -1, l, 0, std::move(a1), st, SC));
             LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
@@ -1307,7 +1321,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 for (int32_t t : LV.h_tgt) tr.push_back(make_int4(l, t, (int)q, 0));
             LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
             for (int32_t t : LV.h_tgt) {
-                for (int m = 0; m <= L; ++m)
+                for (int m = 0; m <= L; m += RR)
                     for (int q = 0; q < nta * nta; ++q) b1.push_back(make_int4(l, t, m, q));
                 for (int q = 0; q < ncol; ++q)
                     for (int cc = 0; cc < (p + 31) / 32; ++cc) b2.push_back(make_int4(l, t, q, cc));
