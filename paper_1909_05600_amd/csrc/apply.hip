@@ -23,6 +23,7 @@ namespace {
 constexpr int kThreads = 256;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 
 // sin(2 pi x), cos(2 pi x) for x in revolutions.  The hardware reduces its argument itself over
@@ -558,435 +559,723 @@ k_sum_parts(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
 // x_a = (a - (p-1)/2) h about the box centre; G [box][c][a][b] (c: z), H [ring][box][a][b].
 // Rings m and L - m (cos t opposite) share Ex, Ey; azimuths n and n + L give the conjugate tables.
 
-// phi(x) = exp(beta (sqrt(1 - (2x/w)^2) - 1)) for |x| < w/2, 0 outside (exponential of semicircle)
-__device__ __forceinline__ float es_phi(float x, float w, float beta) {
-    const float t = 2.f * x / w;
-    const float s = 1.f - t * t;
-    return s > 0.f ? expf(beta * (sqrtf(s) - 1.f)) : 0.f;
+// phi(x) = exp(beta (sqrt(1 - (2x/w)^2) - 1)) for |x| < w/2, 0 outside (exponential of semicircle), with
+// k1 = 2 / w and k2 = beta log2(e): the hardware square root and base-2 exponential (exponents in
+// [-27, 0]), about 1e-7 relative.
+__device__ __forceinline__ float es_phi(float x, float k1, float k2) {
+    const float t = x * k1;
+    const float s = fmaf(-t, t, 1.f);
+    return s > 0.f ? __builtin_amdgcn_exp2f(k2 * (__builtin_amdgcn_sqrtf(s) - 1.f)) : 0.f;
 }
 
 constexpr int kGT = 64;      // spreading tile edge (grid nodes)
-constexpr int kGW = 9;       // most grid nodes a point touches per axis (w <= 8)
 
-// Spread the source points of a box onto one z-plane of its grid (one 64 x 64 tile of it).  Every
-// contribution is rounded once to 64-bit fixed point and summed with integer LDS atomics: the sums are
-// exact, so the result does not depend on the order of the points.  Item (desc, box, plane, tile).
+// A contribution t (|t| < 2^62) as 64-bit fixed point: hi = floor(t 2^-32) and lo = t - hi 2^32 in [0, 2^32),
+// th = t 2^-32 given.  lo is rounded to FP32 and truncated (at most 2^32 - 256), so the value is within a few
+// hundred units of t, far below the FP32 rounding of the sums; each contribution is converted once, which keeps the integer sums order-independent.
+__device__ __forceinline__ unsigned long long fixed64(float t, float th) {
+    const float hi = floorf(th);
+    const float lo = fmaf(-hi, 4294967296.f, t);
+    return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)fminf(lo, 4294967040.f);
+}
+
+// Spread the source points of a box onto one z-plane of its grid (one tile of at most 64 x 64 nodes), kernel
+// width W.  The points come ordered by z-plane floor(z_g) with their grid coordinates: the W planes below and
+// at c + W/2 - 1 hold exactly the points whose support reaches plane c.  Every contribution is rounded once
+// to 64-bit fixed point (u scaled by 2^(61-e), 2^e >= (points of the box) x max |Re u|, |Im u| >= any partial
+// sum) and summed with integer LDS atomics: the sums are exact, so the result does not depend on the order of
+// the points.  Lane l of a wave takes every R-th point from l R on, so that the lanes of one atomic
+// instruction fall on distinct, distant nodes (points are in Morton order within a plane).  Item (desc, box,
+// plane, tile).
+template <int W>
 __global__ void __launch_bounds__(kThreads)
 k_grid_spread(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int sb = wk.y, c = wk.z;
-    const int p = d.gp, w = d.gw;
+    const int p = d.gp;
     const int nta = (p + kGT - 1) / kGT;
     const int a0 = (wk.w / nta) * kGT, b0 = (wk.w % nta) * kGT;
-    const int na = min(kGT, p - a0), nb = min(kGT, p - b0);
-    __shared__ unsigned long long acc[2][kGT * kGT];
-    for (int i = threadIdx.x; i < kGT * kGT; i += kThreads) {
-        acc[0][i] = 0ull;
-        acc[1][i] = 0ull;
+    const int na = min(kGT, p - a0), nb = min(kGT, p - b0), ncell = na * nb;
+    extern __shared__ unsigned long long accs[];           // [part][(a - a0) nb + b - b0], dynamic: 2 ncell
+    unsigned long long *acc0 = accs, *acc1 = accs + ncell;
+    for (int i = threadIdx.x; i < ncell; i += kThreads) {
+        acc0[i] = 0ull;
+        acc1[i] = 0ull;
     }
     __syncthreads();
-    // fixed point: |sum| <= (points of the box) x max |Re u|, |Im u| (phi <= 1)
     const double bound = (double)(d.sstart[sb + 1] - d.sstart[sb]) * (double)(*d.amax);
     int e = 0;
     if (bound > 0.0) frexp(bound, &e);
-    e = max(e, -900);
-    const double scale = ldexp(1.0, 61 - e), inv_scale = ldexp(1.0, e - 61);
-    const float half = 0.5f * (float)(p - 1), hw = 0.5f * (float)w, fw = (float)w, beta = d.gbeta;
-    const double ih = (double)d.ginv_h;
-    const double cx = d.sctr[3 * sb], cy = d.sctr[3 * sb + 1], cz = d.sctr[3 * sb + 2];
-    const int clo = max(0, c - w / 2 - 1), chi = min(p - 1, c + w / 2 + 1);
+    constexpr float hw = 0.5f * W, k1 = 2.f / W;
+    const float k2 = d.gbeta * 1.44269504f;
     const int64_t zoff = (int64_t)sb * p;
-    const int j0 = d.gzs[zoff + clo], j1 = d.gzs[zoff + chi + 1];
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += kThreads) {
-        const int i = d.gperm[j];
-        const float zg = (float)((d.szs[i] - cz) * ih) + half;
-        const float wz = es_phi((float)c - zg, fw, beta);
-        if (wz == 0.f) continue;
-        const float xg = (float)((d.sxs[i] - cx) * ih) + half;
-        const float yg = (float)((d.sys[i] - cy) * ih) + half;
-        const int alo = max(a0, (int)ceilf(xg - hw)), ahi = min(a0 + na - 1, (int)floorf(xg + hw));
-        const int blo = max(b0, (int)ceilf(yg - hw)), bhi = min(b0 + nb - 1, (int)floorf(yg + hw));
-        const float2 uu = d.u[i];
-        const float ur = uu.x * wz, ui = uu.y * wz;
-        float wy[kGW];
+    const int j0 = d.gzs[zoff + max(0, c - W / 2)], j1 = d.gzs[zoff + min(p - 1, c + W / 2 - 1) + 1];
+    const int R = (j1 - j0 + 63) / 64, lane = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < R; r += kThreads / 64) {
+        const int j = j0 + lane * R + r;
+        if (j >= j1) continue;
+        const float4 g = d.gxyz[j];
+        const int alo = min(max((int)floorf(g.x - hw) + 1, 0), p - W);
+        const int blo = min(max((int)floorf(g.y - hw) + 1, 0), p - W);
+        if (alo + W <= a0 || alo >= a0 + na || blo + W <= b0 || blo >= b0 + nb) continue;
+        const float wz = es_phi((float)c - g.z, k1, k2);
+        const float2 uu = d.u[d.gperm[j]];
+        const float ur = ldexpf(uu.x * wz, 61 - e), ui = ldexpf(uu.y * wz, 61 - e);
+        float wx[W], ry[W], iy[W], rh[W], ih[W];
+        int col[W];
 #pragma unroll
-        for (int q = 0; q < kGW; ++q) wy[q] = (blo + q <= bhi) ? es_phi((float)(blo + q) - yg, fw, beta) : 0.f;
-        for (int a = alo; a <= ahi; ++a) {
-            const float wx = es_phi((float)a - xg, fw, beta);
-            const int row = (a - a0) * kGT - b0;
+        for (int k = 0; k < W; ++k) {
+            const int a = alo + k, b = blo + k;
+            wx[k] = (a >= a0 && a < a0 + na) ? es_phi((float)a - g.x, k1, k2) : 0.f;
+            const float wy = (b >= b0 && b < b0 + nb) ? es_phi((float)b - g.y, k1, k2) : 0.f;
+            ry[k] = ur * wy;
+            iy[k] = ui * wy;
+            rh[k] = ry[k] * 2.3283064e-10f;    // 2^-32
+            ih[k] = iy[k] * 2.3283064e-10f;
+            col[k] = min(max(b - b0, 0), nb - 1);
+        }
 #pragma unroll
-            for (int q = 0; q < kGW; ++q) {
-                if (blo + q <= bhi) {
-                    const float wxy = wx * wy[q];
-                    const int kk = row + blo + q;
-                    atomicAdd(&acc[0][kk], (unsigned long long)__double2ll_rn((double)(ur * wxy) * scale));
-                    atomicAdd(&acc[1][kk], (unsigned long long)__double2ll_rn((double)(ui * wxy) * scale));
-                }
+        for (int ka = 0; ka < W; ++ka) {
+            const int row = min(max(alo + ka - a0, 0), na - 1) * nb;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                atomicAdd(&acc0[row + col[q]], fixed64(ry[q] * wx[ka], rh[q] * wx[ka]));
+                atomicAdd(&acc1[row + col[q]], fixed64(iy[q] * wx[ka], ih[q] * wx[ka]));
             }
         }
     }
     __syncthreads();
+    const double inv_scale = ldexp(1.0, e - 61);
     float2 *G = d.G + ((int64_t)sb * p + c) * p * p;
-    for (int kk = threadIdx.x; kk < kGT * kGT; kk += kThreads) {
-        const int al = kk / kGT, bl = kk % kGT;
-        if (al < na && bl < nb)
-            G[(int64_t)(a0 + al) * p + b0 + bl] = make_float2((float)((double)(long long)acc[0][kk] * inv_scale),
-                                                              (float)((double)(long long)acc[1][kk] * inv_scale));
+    for (int kk = threadIdx.x; kk < ncell; kk += kThreads) {
+        const int al = kk / nb, bl = kk % nb;
+        G[(int64_t)(a0 + al) * p + b0 + bl] = make_float2((float)((double)(long long)acc0[kk] * inv_scale),
+                                                          (float)((double)(long long)acc1[kk] * inv_scale));
     }
 }
 
-// Sums over z: H[m][a][b] = sum_c Ez[m][c] G[c][a][b] and H[L-m] with conj(Ez[m]) (four real products
-// serve both), as a tiled product: 32 ring pairs x 128 grid columns per block, 4 x 4 per thread, the
-// planes c staged through LDS 32 at a time.  Item (desc, box, column tile, ring-pair tile).
+// v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, D[4 (lane / 16) + r][lane % 16]
+// in register r.  The four grid sums below are real products with the real and imaginary parts of each
+// operand as separate rows or columns; LDS operand rows are padded (80 floats for 64 columns, 144 for 128) so
+// that the four 16-lane groups of a wave, which read four consecutive rows, hit distinct banks.  Steps run in
+// groups of four without per-step conditions, so that the LDS reads of a group are issued together.
+__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+constexpr int kRow64 = 80;
+constexpr int kRow128 = 144;
+
+// Global-memory views of device pointers: accesses through them compile to global instructions, which the
+// LDS wait counter does not track (flat accesses are counted by both the memory and the LDS counters).
+// Complex values are accessed as two-float vectors.
+typedef float v2f __attribute__((ext_vector_type(2)));
+using gc2 = const __attribute__((address_space(1))) v2f *;
+using gm2 = __attribute__((address_space(1))) v2f *;
+__device__ __forceinline__ gc2 gl(const float2 *p) { return (gc2)p; }
+__device__ __forceinline__ gm2 gw(float2 *p) { return (gm2)p; }
+
+// Sums over z: C[(m, pe)][(ab, pg)] = sum_c Ez_pe[m][c] G_pg[c][ab]; H[m] = C_rr - C_ii + i (C_ri + C_ir) and
+// H[L-m] = C_rr + C_ii + i (C_ri - C_ir) (rings m and L - m have conjugate z tables).  Block: 64 grid columns
+// (16 per wave, held in registers) and a group of up to four 16-ring-pair blocks (grid_z_groups, their z
+// tables staged through LDS); planes 64 at a time, MFMA step s and lane group g taking plane c0 + S g + s.
+// Item (desc, box, column chunk, group).
 __global__ void __launch_bounds__(kThreads)
 k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
-    const int sb = wk.y, p = d.gp, L = d.L, nrp = d.nrp;
-    const int p2 = p * p;
-    const int ab0 = wk.z * 128, m0 = wk.w * 32;
-    const int tid = threadIdx.x, tm = tid / 32, tab = tid % 32;   // 8 x 32 threads
-    __shared__ float4 Es[32][16];    // [c][ring pairs m0 .. m0+31] (two complex per float4)
-    __shared__ float4 Gs[32][64];    // [c][columns ab0 .. ab0+127]
-    float q1[4][4], q2[4][4], q3[4][4], q4[4][4];
+    const int sb = wk.y, p = d.gp, L = d.L, nrp = d.nrp, p2 = p * p;
+    const int ab0 = wk.z * 64;
+    int ngr, gsz;
+    grid_z_groups(nrp, ngr, gsz);
+    const int nmb = (nrp + 15) / 16, mb0 = wk.w * gsz, nmbg = min(gsz, nmb - mb0);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    __shared__ float As[64 * kRow128];       // [step s, group g][ring block, part, ring]
+    floatx4 acc[4][2][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) q1[i][j] = q2[i][j] = q3[i][j] = q4[i][j] = 0.f;
-    const float2 *G = d.G + (int64_t)sb * p * p2;
-    for (int c0 = 0; c0 < p; c0 += 32) {
-        const int cc = min(32, p - c0);
-        __syncthreads();
-        for (int k = tid; k < 32 * 32; k += kThreads) {
-            const int c = k / 32, m = k % 32;
-            reinterpret_cast<float2 *>(&Es[c][0])[m] =
-                (c < cc && m0 + m < nrp) ? d.Ez[(int64_t)(m0 + m) * p + c0 + c] : make_float2(0.f, 0.f);
-        }
-        for (int k = tid; k < 32 * 128; k += kThreads) {
-            const int c = k / 128, j = k % 128;
-            reinterpret_cast<float2 *>(&Gs[c][0])[j] =
-                (c < cc && ab0 + j < p2) ? G[(int64_t)(c0 + c) * p2 + ab0 + j] : make_float2(0.f, 0.f);
-        }
-        __syncthreads();
-        for (int c = 0; c < cc; ++c) {
-            const float4 e01 = Es[c][2 * tm], e23 = Es[c][2 * tm + 1];
-            const float4 g01 = Gs[c][2 * tab], g23 = Gs[c][2 * tab + 1];
-            const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
-            const float gr[4] = {g01.x, g01.z, g23.x, g23.z}, gi[4] = {g01.y, g01.w, g23.y, g23.w};
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int k = 0; k < 2; ++k) acc[i][j][k] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int ab = ab0 + wv * 16 + li;
+    const gc2 G = gl(d.G) + (int64_t)sb * p * p2 + min(ab, p2 - 1);
+    const gc2 Ez = gl(d.Ez);
+    const float gkeep = ab < p2 ? 1.f : 0.f;
+    for (int c0 = 0; c0 < p; c0 += 64) {
+        const int nc = min(64, p - c0), S = nc / 4;
+        float gr[16], gi[16];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    q1[i][j] = fmaf(er[i], gr[j], q1[i][j]);
-                    q2[i][j] = fmaf(ei[i], gi[j], q2[i][j]);
-                    q3[i][j] = fmaf(er[i], gi[j], q3[i][j]);
-                    q4[i][j] = fmaf(ei[i], gr[j], q4[i][j]);
+        for (int s4 = 0; s4 < 4; ++s4)
+            if (4 * s4 < S) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const v2f g = G[(int64_t)(c0 + S * lg + 4 * s4 + u) * p2];
+                    gr[4 * s4 + u] = g.x * gkeep;
+                    gi[4 * s4 + u] = g.y * gkeep;
                 }
+            }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nc * 16 * nmbg; k += kThreads) {
+            const int cl = k % nc, mr = k / nc, m = mb0 * 16 + mr;
+            v2f e = {0.f, 0.f};
+            if (m < nrp) e = Ez[(int64_t)m * p + c0 + cl];
+            float *r = As + (4 * (cl % S) + cl / S) * kRow128 + (mr >> 4) * 32 + (mr & 15);
+            r[0] = e.x;
+            r[16] = e.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) {
+            if (mi < nmbg) {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    if (4 * s4 < S) {
+                        float er[4], ei[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float *ar = As + (4 * (4 * s4 + u) + lg) * kRow128 + mi * 32 + li;
+                            er[u] = ar[0];
+                            ei[u] = ar[16];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int s = 4 * s4 + u;
+                            acc[mi][0][0] = mfma16(er[u], gr[s], acc[mi][0][0]);
+                            acc[mi][0][1] = mfma16(er[u], gi[s], acc[mi][0][1]);
+                            acc[mi][1][0] = mfma16(ei[u], gr[s], acc[mi][1][0]);
+                            acc[mi][1][1] = mfma16(ei[u], gi[s], acc[mi][1][1]);
+                        }
+                    }
+            }
         }
     }
+    if (ab >= p2) return;
+    const gm2 H = gw(d.H);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + tm * 4 + i;
-        if (m >= nrp) continue;
+    for (int mi = 0; mi < 4; ++mi) {
+        if (mi >= nmbg) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int ab = ab0 + tab * 4 + j;
-            if (ab >= p2) continue;
-            d.H[((int64_t)m * d.gnbox + sb) * p2 + ab] = make_float2(q1[i][j] - q2[i][j], q3[i][j] + q4[i][j]);
-            if (L - m != m)
-                d.H[((int64_t)(L - m) * d.gnbox + sb) * p2 + ab] = make_float2(q1[i][j] + q2[i][j], q3[i][j] - q4[i][j]);
+        for (int r = 0; r < 4; ++r) {
+            const int m = (mb0 + mi) * 16 + 4 * lg + r;
+            if (m >= nrp) continue;
+            const float q1 = acc[mi][0][0][r], q3 = acc[mi][0][1][r], q4 = acc[mi][1][0][r], q2 = acc[mi][1][1][r];
+            H[((int64_t)m * d.gnbox + sb) * p2 + ab] = v2f{q1 - q2, q3 + q4};
+            if (L - m != m) H[((int64_t)(L - m) * d.gnbox + sb) * p2 + ab] = v2f{q1 + q2, q3 - q4};
         }
     }
 }
 
-// Sums over the plane to the directions: u~(m, n) = sum_a Ex[a][n] X[a][n], X = H_m Ey (sum over b), and
-// u~(m, n+L) with the conjugate tables (the same four real products).  A tiled product: 4 rows x 4 azimuths
-// per thread; the rows of a 64-row pass are split over TA = ceil(rows / 4) thread rows and the azimuths over
-// TN = min(32, 256 / TA) thread columns (grid_phi_tile); b is staged through LDS 32 at a time.  Each thread's
-// sums over its rows are then added over the thread rows in order.  Item (desc, box, ring, azimuth tile).
+// The MFMA steps of k_grid_phi: 4 S4 steps over the staged rows, NT column tiles, in groups of four steps
+// whose LDS operands are read together before their products.
+template <int S4, int NT>
+__device__ __forceinline__ void phi_steps(const float *bl, const float (&hr)[16], const float (&hi)[16],
+                                          floatx4 (&acc)[2][4]) {
+#pragma unroll
+    for (int g = 0; g < S4; ++g) {
+        float bv[4][NT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bv[u][t] = bl[4 * (4 * g + u) * kRow64 + t * 16];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                acc[0][t] = mfma16(hr[4 * g + u], bv[u][t], acc[0][t]);
+                acc[1][t] = mfma16(hi[4 * g + u], bv[u][t], acc[1][t]);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int S4>
+__device__ __forceinline__ void phi_steps_nt(int ntile, const float *bl, const float (&hr)[16], const float (&hi)[16],
+                                             floatx4 (&acc)[2][4]) {
+    switch (ntile) {
+        case 1: phi_steps<S4, 1>(bl, hr, hi, acc); break;
+        case 2: phi_steps<S4, 2>(bl, hr, hi, acc); break;
+        case 3: phi_steps<S4, 3>(bl, hr, hi, acc); break;
+        default: phi_steps<S4, 4>(bl, hr, hi, acc); break;
+    }
+}
+
+// Sums over the plane to the directions of ring m: C[(a, pa)][(n, pe)] = sum_b H_pa[a][b] Ey_pe[b][n], whose
+// four real products give z0 = C_rr + i C_ir and z1 = C_ri + i C_ii per (a, n); then u~(m, n) = sum_a Ex[a][n]
+// (z0 + i z1) and u~(m, n + L) = sum_a conj(Ex[a][n]) (z0 - i z1) (azimuths n and n + L have conjugate
+// in-plane tables).  Block: one ring of one box; waves take 16-row blocks of a (held in registers when the
+// grid has at most 64 rows); azimuths in chunks of 32 (four column tiles of 8 azimuths, real parts in columns
+// 0-7 and imaginary parts in 8-15), b staged through LDS 64 at a time (step s, lane group g: b = b0 + S g + s)
+// with Ex beside it.  Each lane sums its four rows, the two parts are added across lanes, and the partial
+// sums of the 16 row groups are added in order.  Item (desc, box, ring, 0).
 __global__ void __launch_bounds__(kThreads)
 k_grid_phi(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int sb = wk.y, m = wk.z;
     const int p = d.gp, L = d.L, mt = min(m, L - m);
-    int TA, TN;
-    grid_phi_tile(p, TA, TN);
-    const int NT = 4 * TN, n0 = wk.w * NT;
-    const int tid = threadIdx.x, ta = tid / TN, tn = tid % TN;
-    const bool act = tid < TA * TN;
-    __shared__ float4 smem[3072];            // 48 KB
-    float4 *Hs = smem;                       // [32 b][32]: 64 complex rows a
-    float4 *Es = smem + 32 * 32;             // [32 b][64]: 128 complex azimuths n
-    const float2 *H = d.H + ((int64_t)m * d.gnbox + sb) * p * p;
-    const float2 *Ey = d.Ey + (int64_t)mt * p * L;
-    const float2 *Ex = d.Ex + (int64_t)mt * p * L;
-    float tr[4], ti[4], ur[4], ui[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) tr[j] = ti[j] = ur[j] = ui[j] = 0.f;
-    for (int a0 = 0; a0 < p; a0 += 64) {
-        float P1[4][4], P2[4][4], P3[4][4], P4[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) P1[i][j] = P2[i][j] = P3[i][j] = P4[i][j] = 0.f;
-        for (int b0 = 0; b0 < p; b0 += 32) {
-            const int nbb = min(32, p - b0);
-            __syncthreads();
-            for (int k = tid; k < 32 * 64; k += kThreads) {
-                const int b = k / 64, r = k % 64;
-                reinterpret_cast<float2 *>(Hs + b * 32)[r] =
-                    (b < nbb && a0 + r < p) ? H[(int64_t)(a0 + r) * p + b0 + b] : make_float2(0.f, 0.f);
-            }
-            for (int k = tid; k < 32 * NT; k += kThreads) {
-                const int b = k / NT, r = k % NT;
-                reinterpret_cast<float2 *>(Es + b * 64)[r] =
-                    (b < nbb && n0 + r < L) ? Ey[(int64_t)(b0 + b) * L + n0 + r] : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            if (act) {
-                for (int b = 0; b < nbb; ++b) {
-                    const float4 h01 = Hs[b * 32 + 2 * ta], h23 = Hs[b * 32 + 2 * ta + 1];
-                    const float4 e01 = Es[b * 64 + 2 * tn], e23 = Es[b * 64 + 2 * tn + 1];
-                    const float hr[4] = {h01.x, h01.z, h23.x, h23.z}, hi[4] = {h01.y, h01.w, h23.y, h23.w};
-                    const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            P1[i][j] = fmaf(er[j], hr[i], P1[i][j]);
-                            P2[i][j] = fmaf(ei[j], hi[i], P2[i][j]);
-                            P3[i][j] = fmaf(er[j], hi[i], P3[i][j]);
-                            P4[i][j] = fmaf(ei[j], hr[i], P4[i][j]);
-                        }
-                }
-            }
-        }
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int a = a0 + ta * 4 + i;
-                if (a >= p) continue;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int n = n0 + tn * 4 + j;
-                    if (n >= L) continue;
-                    const float2 ex = Ex[(int64_t)a * L + n];
-                    const float xr = P1[i][j] - P2[i][j], xi = P3[i][j] + P4[i][j];     // sum_b Ey H
-                    const float yr = P1[i][j] + P2[i][j], yi = P3[i][j] - P4[i][j];     // sum_b conj(Ey) H
-                    tr[j] = fmaf(ex.x, xr, fmaf(-ex.y, xi, tr[j]));
-                    ti[j] = fmaf(ex.x, xi, fmaf(ex.y, xr, ti[j]));
-                    ur[j] = fmaf(ex.x, yr, fmaf(ex.y, yi, ur[j]));
-                    ui[j] = fmaf(ex.x, yi, fmaf(-ex.y, yr, ui[j]));
-                }
-            }
-        }
-    }
-    __syncthreads();
-    float4 *red = smem;                      // [16 thread rows][128 azimuths]
-    if (act) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) red[ta * 128 + tn * 4 + j] = make_float4(tr[j], ti[j], ur[j], ui[j]);
-    }
-    __syncthreads();
-    if (tid >= NT) return;
-    const int n = n0 + tid;
-    if (n >= L) return;
-    float4 a = red[tid];
-    for (int q = 1; q < TA; ++q) {
-        const float4 b = red[q * 128 + tid];
-        a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
-    }
-    // a.xy = u~(m, n), a.zw = u~(m, n + L), into the antipodal-pair layout
-    float2 *ut = reinterpret_cast<float2 *>(d.ut) + (int64_t)sb * d.npair * 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    constexpr int kExRow = 68;               // 32 complex azimuths + pad, in floats
+    __shared__ float Bs[64 * kRow64];
+    __shared__ float Exs[64 * kExRow];
+    __shared__ float4 red[4][4][32];         // [wave][lane group][azimuth]
+    const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + sb) * p * p;
+    const gc2 Ey = gl(d.Ey) + (int64_t)mt * p * L;
+    const gc2 Ex = gl(d.Ex) + (int64_t)mt * p * L;
+    const int nab = p / 16, rounds = (nab + 3) / 4;
+    const bool one = p <= 64;                // one round of row blocks and one chunk of b
+    const gm2 ut = gw(reinterpret_cast<float2 *>(d.ut)) + (int64_t)sb * d.npair * 2;
     const int64_t twoL = 2 * (int64_t)L;
-    if (2 * m < L) {
-        ut[(m * twoL + n) * 2] = make_float2(a.x, a.y);
-        ut[(m * twoL + n + L) * 2] = make_float2(a.z, a.w);
-    } else if (2 * m > L) {
-        const int64_t m2 = L - m;
-        ut[(m2 * twoL + n) * 2 + 1] = make_float2(a.z, a.w);
-        ut[(m2 * twoL + n + L) * 2 + 1] = make_float2(a.x, a.y);
-    } else {
-        ut[(m * twoL + n) * 2] = make_float2(a.x, a.y);
-        ut[(m * twoL + n) * 2 + 1] = make_float2(a.z, a.w);
+    float hr[16], hi[16];
+    auto load_rows = [&](int blk, int b0, int S) {
+        const gc2 hrow = H + (int64_t)(blk * 16 + li) * p + b0 + S * lg;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+            if (4 * s4 < S) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const v2f h = hrow[4 * s4 + u];
+                    hr[4 * s4 + u] = h.x;
+                    hi[4 * s4 + u] = h.y;
+                }
+            }
+    };
+    if (one && wv < nab) load_rows(wv, 0, p / 4);
+    const float *bl = Bs + lg * kRow64 + li;
+    for (int n0 = 0; n0 < L; n0 += 32) {
+        const int ntile = min(4, (L - n0 + 7) / 8);
+        float4 tot[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) tot[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int blk = rd * 4 + wv;
+            const bool act = blk < nab;
+            floatx4 acc[2][4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[i][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int b0 = 0; b0 < p; b0 += 64) {
+                const int nb = min(64, p - b0), S = nb / 4;
+                __syncthreads();
+                {
+                    // all loads of the chunk in flight at once: 8 per thread for Ey, 8 for Ex
+                    const int nl = threadIdx.x % 32, n = n0 + nl, q0 = threadIdx.x / 32;
+                    const int na = b0 == 0 ? min(64, p - rd * 64) : 0;
+                    v2f ey[8], ex[8];
+#pragma unroll
+                    for (int it = 0; it < 8; ++it) {
+                        const int q = q0 + 8 * it;
+                        ey[it] = v2f{0.f, 0.f};
+                        ex[it] = v2f{0.f, 0.f};
+                        if (q < nb && n < L) ey[it] = Ey[(int64_t)(b0 + q) * L + n];
+                        if (q < na && n < L) ex[it] = Ex[(int64_t)(rd * 64 + q) * L + n];
+                    }
+#pragma unroll
+                    for (int it = 0; it < 8; ++it) {
+                        const int q = q0 + 8 * it;
+                        if (q < nb) {
+                            float *r = Bs + (4 * (q % S) + q / S) * kRow64 + (nl >> 3) * 16 + (nl & 7);
+                            r[0] = ey[it].x;
+                            r[8] = ey[it].y;
+                        }
+                        if (q < na) reinterpret_cast<float2 *>(Exs + q * kExRow)[nl] = make_float2(ex[it].x, ex[it].y);
+                    }
+                }
+                __syncthreads();
+                if (act) {
+                    if (!one) load_rows(blk, b0, S);
+                    switch (S / 4) {
+                        case 1: phi_steps_nt<1>(ntile, bl, hr, hi, acc); break;
+                        case 2: phi_steps_nt<2>(ntile, bl, hr, hi, acc); break;
+                        case 3: phi_steps_nt<3>(ntile, bl, hr, hi, acc); break;
+                        default: phi_steps_nt<4>(ntile, bl, hr, hi, acc); break;
+                    }
+                }
+            }
+            if (act) {
+                const bool im = li >= 8;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (t >= ntile) continue;
+                    const int nl = 8 * t + (li & 7);
+                    float fr = 0.f, fi = 0.f, gr = 0.f, gi = 0.f;   // sum Ex z, sum conj(Ex) z over this lane's rows
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float2 ex = reinterpret_cast<const float2 *>(Exs + (wv * 16 + 4 * lg + r) * kExRow)[nl];
+                        const float x = acc[0][t][r], y = acc[1][t][r];
+                        fr = fmaf(ex.x, x, fmaf(-ex.y, y, fr));
+                        fi = fmaf(ex.x, y, fmaf(ex.y, x, fi));
+                        gr = fmaf(ex.x, x, fmaf(ex.y, y, gr));
+                        gi = fmaf(ex.x, y, fmaf(-ex.y, x, gi));
+                    }
+                    // the imaginary-part columns hold z1: contribute i F and -i G
+                    float t0 = im ? -fi : fr, t1 = im ? fr : fi, t2 = im ? gi : gr, t3 = im ? -gr : gi;
+                    t0 += __shfl_xor(t0, 8, 64);
+                    t1 += __shfl_xor(t1, 8, 64);
+                    t2 += __shfl_xor(t2, 8, 64);
+                    t3 += __shfl_xor(t3, 8, 64);
+                    tot[t].x += t0;
+                    tot[t].y += t1;
+                    tot[t].z += t2;
+                    tot[t].w += t3;
+                }
+            }
+        }
+        if (li < 8) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) red[wv][lg][8 * t + li] = tot[t];
+        }
+        __syncthreads();
+        const int nl = threadIdx.x, n = n0 + nl;
+        if (nl < 32 && n < L) {
+            float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int w = 0; w < min(4, nab); ++w)
+                for (int g = 0; g < 4; ++g) {
+                    const float4 b = red[w][g][nl];
+                    a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+                }
+            // a.xy = u~(m, n), a.zw = u~(m, n + L), into the antipodal-pair layout
+            if (2 * m < L) {
+                ut[(m * twoL + n) * 2] = v2f{a.x, a.y};
+                ut[(m * twoL + n + L) * 2] = v2f{a.z, a.w};
+            } else if (2 * m > L) {
+                const int64_t m2 = L - m;
+                ut[(m2 * twoL + n) * 2 + 1] = v2f{a.z, a.w};
+                ut[(m2 * twoL + n + L) * 2 + 1] = v2f{a.x, a.y};
+            } else {
+                ut[(m * twoL + n) * 2] = v2f{a.x, a.y};
+                ut[(m * twoL + n) * 2 + 1] = v2f{a.z, a.w};
+            }
+        }
     }
 }
 
-// v~ of ring m back to the plane: H'[a][b] = sum_{n < L} conj(Ex) conj(Ey) v~(m, n) + Ex Ey v~(m, n + L)
-// = sum_n S Re(Ey) + i D Im(Ey) with S = conj(Ex) v~(n) + Ex v~(n+L), D = Ex v~(n+L) - conj(Ex) v~(n).
-// 4 x 4 (a, b) per thread over a 64 x 64 tile; when the grid is smaller, R = grid_phit_rings rings share a
-// block (each its own tables and v~), n staged through LDS 32 / R at a time.  Item (desc, box, first ring,
-// tile).
+// Sums over the plane to the directions for grids of P = 16 P16 <= 64 nodes per axis: the products of
+// k_grid_phi with H staged once in LDS as the A operand ([b][a block, part, a % 16], b = 4 s + g for step s and
+// lane group g); each wave then runs on its own over its 8-azimuth column tiles (tiles w, w + 4, ...): the Ey
+// values a lane needs come from memory straight into registers one tile ahead, Ex goes through a
+// wave-private LDS slice, and the sums over a are completed inside the wave (its 4 rows per lane, then across
+// the two parts and the four lane groups).  Item (desc, box, ring, 0).
+template <int P16>
+__global__ void __launch_bounds__(kThreads)
+k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    constexpr int P = 16 * P16, S = 4 * P16, NX = P / 8;   // nodes, MFMA steps, Ex values per lane and tile
+    constexpr int kExR = 20;                                // floats per Ex row: 8 complex azimuths + pad
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int sb = wk.y, m = wk.z, L = d.L, mt = min(m, L - m);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    __shared__ float As[P * kRow128];
+    __shared__ float Exw[4][P * kExR];
+    {
+        const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + sb) * P * P;
+        v2f hv[P16 * P16];
+#pragma unroll
+        for (int it = 0; it < P16 * P16; ++it) hv[it] = H[threadIdx.x + it * kThreads];
+#pragma unroll
+        for (int it = 0; it < P16 * P16; ++it) {
+            const int idx = threadIdx.x + it * kThreads, a = idx / P, b = idx % P;
+            float *r = As + b * kRow128 + (a >> 4) * 32 + (a & 15);
+            r[0] = hv[it].x;
+            r[16] = hv[it].y;
+        }
+    }
+    __syncthreads();
+    using gcf = const __attribute__((address_space(1))) float *;
+    const gcf Eyf = (gcf)(d.Ey + (int64_t)mt * P * L);
+    const gc2 Ex = gl(d.Ex) + (int64_t)mt * P * L;
+    const int pe = li >> 3, ntiles = (L + 7) / 8;
+    float *exw = Exw[wv];
+    const gm2 ut = gw(reinterpret_cast<float2 *>(d.ut)) + (int64_t)sb * d.npair * 2;
+    const int64_t twoL = 2 * (int64_t)L;
+    float bnx[S];
+    v2f xnx[NX];
+    auto prefetch = [&](int t) {
+        const int n = 8 * t + (li & 7);
+        const bool ok = n < L;
+        const int nc = ok ? n : 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) bnx[s] = ok ? Eyf[2 * ((int64_t)(4 * s + lg) * L + nc) + pe] : 0.f;
+        const int nx = 8 * t + (lane & 7);
+        const bool okx = nx < L;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) xnx[j] = okx ? Ex[(int64_t)(lane / 8 + 8 * j) * L + nx] : v2f{0.f, 0.f};
+    };
+    if (wv < ntiles) prefetch(wv);
+    for (int t = wv; t < ntiles; t += 4) {
+        float bv[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) bv[s] = bnx[s];
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            reinterpret_cast<float2 *>(exw + (lane / 8 + 8 * j) * kExR)[lane & 7] = make_float2(xnx[j].x, xnx[j].y);
+        if (t + 4 < ntiles) prefetch(t + 4);
+        floatx4 acc[P16][2];
+#pragma unroll
+        for (int q = 0; q < P16; ++q) acc[q][0] = acc[q][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float *al = As + lg * kRow128 + li;
+#pragma unroll
+        for (int g = 0; g < P16; ++g) {
+            float av[4][P16][2];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < P16; ++q) {
+                    av[u][q][0] = al[4 * (4 * g + u) * kRow128 + q * 32];
+                    av[u][q][1] = al[4 * (4 * g + u) * kRow128 + q * 32 + 16];
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < P16; ++q) {
+                    acc[q][0] = mfma16(av[u][q][0], bv[4 * g + u], acc[q][0]);
+                    acc[q][1] = mfma16(av[u][q][1], bv[4 * g + u], acc[q][1]);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // sums over this lane's rows: F = sum Ex z, G = sum conj(Ex) z, z = (row of H_r, row of H_i) products
+        float fr = 0.f, fi = 0.f, gr = 0.f, gi = 0.f;
+#pragma unroll
+        for (int q = 0; q < P16; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 ex = reinterpret_cast<const float2 *>(exw + (q * 16 + 4 * lg + r) * kExR)[li & 7];
+                const float x = acc[q][0][r], y = acc[q][1][r];
+                fr = fmaf(ex.x, x, fmaf(-ex.y, y, fr));
+                fi = fmaf(ex.x, y, fmaf(ex.y, x, fi));
+                gr = fmaf(ex.x, x, fmaf(ex.y, y, gr));
+                gi = fmaf(ex.x, y, fmaf(-ex.y, x, gi));
+            }
+        // the imaginary-part columns hold z1: contribute i F and -i G
+        float t0 = pe ? -fi : fr, t1 = pe ? fr : fi, t2 = pe ? gi : gr, t3 = pe ? -gr : gi;
+#pragma unroll
+        for (int o = 8; o < 64; o <<= 1) {
+            t0 += __shfl_xor(t0, o, 64);
+            t1 += __shfl_xor(t1, o, 64);
+            t2 += __shfl_xor(t2, o, 64);
+            t3 += __shfl_xor(t3, o, 64);
+        }
+        const int n = 8 * t + li;
+        if (lane < 8 && n < L) {
+            // (t0, t1) = u~(m, n), (t2, t3) = u~(m, n + L), into the antipodal-pair layout
+            if (2 * m < L) {
+                ut[(m * twoL + n) * 2] = v2f{t0, t1};
+                ut[(m * twoL + n + L) * 2] = v2f{t2, t3};
+            } else if (2 * m > L) {
+                const int64_t m2 = L - m;
+                ut[(m2 * twoL + n) * 2 + 1] = v2f{t2, t3};
+                ut[(m2 * twoL + n + L) * 2 + 1] = v2f{t0, t1};
+            } else {
+                ut[(m * twoL + n) * 2] = v2f{t0, t1};
+                ut[(m * twoL + n) * 2 + 1] = v2f{t2, t3};
+            }
+        }
+    }
+}
+
+// v~ of ring m back to its plane: H'_pa[a][b] = sum over (n, pe) of A[(a, pa)][(n, pe)] E_pe[b][n] with
+// A = (S_r, -D_i | S_i, D_r), S = conj(Ex) v~(n) + Ex v~(n + L), D = Ex v~(n + L) - conj(Ex) v~(n).  Block: one
+// ring and a 64 x 64 tile of the plane; waves take 16-row blocks of a and all four 16-column blocks of b;
+// azimuths staged through LDS 16 at a time from the transposed tables ([n][node]), step s and lane group g
+// taking azimuth 2 s + g / 2 and part g % 2.  Item (desc, box, ring, tile).
 __global__ void __launch_bounds__(kThreads)
 k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
-    const int tb_ = wk.y;
-    const int p = d.gp, L = d.L;
-    const int R = grid_phit_rings(p), NC = 32 / R;
-    const int TC = p > 64 ? 16 : (p + 3) / 4, TAB = TC * TC;     // thread tiles per ring
+    const int tb = wk.y, m = wk.z;
+    const int p = d.gp, L = d.L, mt = min(m, L - m);
     const int nta = (p + 63) / 64;
     const int a0 = (wk.w / nta) * 64, b0 = (wk.w % nta) * 64;
-    const int tid = threadIdx.x, rr = tid / TAB, tt = tid % TAB, ta = tt / TC, tb = tt % TC;
-    const int m = wk.z + rr;
-    const bool act = rr < R && m <= L;
-    const int mt = act ? min(m, L - m) : 0;
-    __shared__ float4 sS[32][32], sD[32][32], sE[32][32];   // [ring r x NC + n][64 complex]
-    float2 acc[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    __shared__ float Ar[32 * kRow64], Ai[32 * kRow64], Bs[32 * kRow64];
+    __shared__ float2 vs[2][16];
+    floatx4 acc[2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
-    const float2 *vt = reinterpret_cast<const float2 *>(d.vt) + (int64_t)tb_ * d.npair * 2;
+        for (int q = 0; q < 4; ++q) acc[i][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool act = a0 + wv * 16 < p;
+    const float2 *vt = reinterpret_cast<const float2 *>(d.vt) + (int64_t)tb * d.npair * 2;
     const int64_t twoL = 2 * (int64_t)L;
-    for (int n0 = 0; n0 < L; n0 += NC) {
-        const int cnt = min(NC, L - n0);
+    const float2 *ExT = d.ExT + (int64_t)mt * L * p, *EyT = d.EyT + (int64_t)mt * L * p;
+    for (int n0 = 0; n0 < L; n0 += 16) {
+        const int cnt = min(16, L - n0);
         __syncthreads();
-        for (int k = tid; k < R * NC * 64; k += kThreads) {
-            const int r = k / (NC * 64), nn = (k / 64) % NC, idx = k % 64, n = n0 + nn;
-            const int mr = wk.z + r;
-            float2 S = make_float2(0.f, 0.f), Dd = S, E = S;
-            if (nn < cnt && mr <= L) {
-                const int mtr = min(mr, L - mr);
-                float2 v1, v2;   // v~(mr, n), v~(mr, n + L)
-                if (2 * mr < L) {
-                    v1 = vt[(mr * twoL + n) * 2];
-                    v2 = vt[(mr * twoL + n + L) * 2];
-                } else if (2 * mr > L) {
-                    const int64_t m2 = L - mr;
+        if (threadIdx.x < 16) {
+            const int n = n0 + threadIdx.x;
+            float2 v1 = make_float2(0.f, 0.f), v2 = v1;   // v~(m, n), v~(m, n + L)
+            if ((int)threadIdx.x < cnt) {
+                if (2 * m < L) {
+                    v1 = vt[(m * twoL + n) * 2];
+                    v2 = vt[(m * twoL + n + L) * 2];
+                } else if (2 * m > L) {
+                    const int64_t m2 = L - m;
                     v1 = vt[(m2 * twoL + n + L) * 2 + 1];
                     v2 = vt[(m2 * twoL + n) * 2 + 1];
                 } else {
-                    v1 = vt[(mr * twoL + n) * 2];
-                    v2 = vt[(mr * twoL + n) * 2 + 1];
+                    v1 = vt[(m * twoL + n) * 2];
+                    v2 = vt[(m * twoL + n) * 2 + 1];
                 }
-                const int a = a0 + idx;
-                if (a < p) {
-                    const float2 ex = d.Ex[((int64_t)mtr * p + a) * L + n];
+            }
+            vs[0][threadIdx.x] = v1;
+            vs[1][threadIdx.x] = v2;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < 16 * 64; k += kThreads) {
+            const int nl = k / 64, x = k % 64, n = n0 + nl;
+            float sr = 0.f, si = 0.f, dr = 0.f, di = 0.f, er = 0.f, ei = 0.f;
+            if (nl < cnt) {
+                if (a0 + x < p) {
+                    const float2 ex = ExT[(int64_t)n * p + a0 + x], v1 = vs[0][nl], v2 = vs[1][nl];
                     const float y1r = fmaf(ex.x, v1.x, ex.y * v1.y), y1i = fmaf(ex.x, v1.y, -(ex.y * v1.x));   // conj(ex) v1
                     const float y2r = fmaf(ex.x, v2.x, -(ex.y * v2.y)), y2i = fmaf(ex.x, v2.y, ex.y * v2.x);   // ex v2
-                    S = make_float2(y1r + y2r, y1i + y2i);
-                    Dd = make_float2(y2r - y1r, y2i - y1i);
+                    sr = y1r + y2r;
+                    si = y1i + y2i;
+                    dr = y2r - y1r;
+                    di = y2i - y1i;
                 }
-                const int b = b0 + idx;
-                if (b < p) E = d.Ey[((int64_t)mtr * p + b) * L + n];
+                if (b0 + x < p) {
+                    const float2 e = EyT[(int64_t)n * p + b0 + x];
+                    er = e.x;
+                    ei = e.y;
+                }
             }
-            reinterpret_cast<float2 *>(&sS[r * NC + nn][0])[idx] = S;
-            reinterpret_cast<float2 *>(&sD[r * NC + nn][0])[idx] = Dd;
-            reinterpret_cast<float2 *>(&sE[r * NC + nn][0])[idx] = E;
+            Ar[(2 * nl) * kRow64 + x] = sr;
+            Ar[(2 * nl + 1) * kRow64 + x] = -di;
+            Ai[(2 * nl) * kRow64 + x] = si;
+            Ai[(2 * nl + 1) * kRow64 + x] = dr;
+            Bs[(2 * nl) * kRow64 + x] = er;
+            Bs[(2 * nl + 1) * kRow64 + x] = ei;
         }
         __syncthreads();
         if (act) {
-            for (int nn = 0; nn < cnt; ++nn) {
-                const int row = rr * NC + nn;
-                const float4 s01 = sS[row][2 * ta], s23 = sS[row][2 * ta + 1];
-                const float4 d01 = sD[row][2 * ta], d23 = sD[row][2 * ta + 1];
-                const float4 e01 = sE[row][2 * tb], e23 = sE[row][2 * tb + 1];
-                const float2 sv[4] = {make_float2(s01.x, s01.y), make_float2(s01.z, s01.w), make_float2(s23.x, s23.y),
-                                      make_float2(s23.z, s23.w)};
-                const float2 dv[4] = {make_float2(d01.x, d01.y), make_float2(d01.z, d01.w), make_float2(d23.x, d23.y),
-                                      make_float2(d23.z, d23.w)};
-                const float2 ev[4] = {make_float2(e01.x, e01.y), make_float2(e01.z, e01.w), make_float2(e23.x, e23.y),
-                                      make_float2(e23.z, e23.w)};
+            const int steps = (2 * cnt + 3) / 4;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+            for (int s = 0; s < 8; ++s)
+                if (s < steps) {
+                    const int row = (4 * s + lg) * kRow64;
+                    const float ar = Ar[row + wv * 16 + li], ai = Ai[row + wv * 16 + li];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        acc[i][j].x = fmaf(sv[i].x, ev[j].x, fmaf(-dv[i].y, ev[j].y, acc[i][j].x));
-                        acc[i][j].y = fmaf(sv[i].y, ev[j].x, fmaf(dv[i].x, ev[j].y, acc[i][j].y));
-                    }
-            }
+                    for (int q = 0; q < 4; ++q)
+                        if (b0 + q * 16 < p) {
+                            const float bv = Bs[row + q * 16 + li];
+                            acc[0][q] = mfma16(ar, bv, acc[0][q]);
+                            acc[1][q] = mfma16(ai, bv, acc[1][q]);
+                        }
+                }
         }
     }
     if (!act) return;
-    (void)mt;
-    float2 *Hb = d.H + ((int64_t)m * d.gnbox + tb_) * p * p;
+    float2 *Hb = d.H + ((int64_t)m * d.gnbox + tb) * p * p;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int a = a0 + ta * 4 + i;
-        if (a >= p) continue;
+    for (int q = 0; q < 4; ++q) {
+        const int b = b0 + q * 16 + li;
+        if (b >= p) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = b0 + tb * 4 + j;
-            if (b < p) Hb[(int64_t)a * p + b] = acc[i][j];
+        for (int r = 0; r < 4; ++r) {
+            const int a = a0 + wv * 16 + 4 * lg + r;
+            if (a < p) Hb[(int64_t)a * p + b] = make_float2(acc[0][q][r], acc[1][q][r]);
         }
     }
 }
 
-// Back over z: G'[c][a][b] = sum over ring pairs of conj(Ez[m][c]) H'[m][a][b] + Ez[m][c] H'[L-m][a][b]
-// = Re(Ez) (H'[m] + H'[L-m]) + i Im(Ez) (H'[L-m] - H'[m]), as a tiled product: 32 planes x 128 columns per
-// block, 4 x 4 per thread, ring pairs staged through LDS 16 at a time.  Item (desc, box, column tile,
-// plane tile).
+// Back over z: G'_pg[c][ab] = sum over (ring pair m, part pe) of A[c][(m, pe)] B[(m, pe)][(ab, pg)] with
+// A = (Re Ez, Im Ez) and B = (S_r, S_i | -D_i, D_r), S = H'[m] + H'[L-m], D = H'[L-m] - H'[m].  Block: 64 grid
+// columns and 64 planes (16 per wave); ring pairs staged through LDS 16 at a time, step s and lane group g
+// taking ring pair 2 s + g / 2 and part g % 2.  Item (desc, box, column chunk, plane chunk).
 __global__ void __launch_bounds__(kThreads)
 k_grid_zt(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
-    const int tb_ = wk.y, p = d.gp, L = d.L, nrp = d.nrp;
-    const int p2 = p * p;
-    const int ab0 = wk.z * 128, c0 = wk.w * 32;
-    const int tid = threadIdx.x, tc = tid / 32, tab = tid % 32;
-    __shared__ float4 Es[16][16];    // [ring pair][planes c0 .. c0+31]
-    __shared__ float4 Ss[16][64];    // [ring pair][columns]: H'[m] + H'[L-m]
-    __shared__ float4 Ds[16][64];    //                       H'[L-m] - H'[m]
-    float2 acc[4][4];
+    const int tb = wk.y, p = d.gp, L = d.L, nrp = d.nrp, p2 = p * p;
+    const int ab0 = wk.z * 64, c0 = wk.w * 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    __shared__ float As[32 * kRow64];
+    __shared__ float Bs[32 * kRow128];
+    floatx4 acc[4][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
+    for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool act = c0 + wv * 16 < p;
+    const gc2 H = gl(d.H), Ez = gl(d.Ez);
     for (int mp0 = 0; mp0 < nrp; mp0 += 16) {
         const int mc = min(16, nrp - mp0);
         __syncthreads();
-        for (int k = tid; k < 16 * 32; k += kThreads) {
-            const int mm = k / 32, c = k % 32;
-            reinterpret_cast<float2 *>(&Es[mm][0])[c] =
-                (mm < mc && c0 + c < p) ? d.Ez[(int64_t)(mp0 + mm) * p + c0 + c] : make_float2(0.f, 0.f);
-        }
-        for (int k = tid; k < 16 * 128; k += kThreads) {
-            const int mm = k / 128, j = k % 128, mp = mp0 + mm, ab = ab0 + j;
-            float2 S = make_float2(0.f, 0.f), Dd = S;
-            if (mm < mc && ab < p2) {
-                const int m2 = L - mp;
-                const float2 h1 = d.H[((int64_t)mp * d.gnbox + tb_) * p2 + ab];
-                const float2 h2 = (m2 != mp) ? d.H[((int64_t)m2 * d.gnbox + tb_) * p2 + ab] : make_float2(0.f, 0.f);
-                S = make_float2(h1.x + h2.x, h1.y + h2.y);
-                Dd = make_float2(h2.x - h1.x, h2.y - h1.y);
+        {
+            const int x = threadIdx.x % 64, mq = threadIdx.x / 64, ab = ab0 + x;
+            v2f ev[4], h1v[4], h2v[4];
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {     // all loads of the chunk in flight at once
+                const int ml = mq + 4 * it, mp = mp0 + ml, m2 = L - mp;
+                ev[it] = h1v[it] = h2v[it] = v2f{0.f, 0.f};
+                if (ml < mc) {
+                    if (c0 + x < p) ev[it] = Ez[(int64_t)mp * p + c0 + x];
+                    if (ab < p2) {
+                        h1v[it] = H[((int64_t)mp * d.gnbox + tb) * p2 + ab];
+                        if (m2 != mp) h2v[it] = H[((int64_t)m2 * d.gnbox + tb) * p2 + ab];
+                    }
+                }
             }
-            reinterpret_cast<float2 *>(&Ss[mm][0])[j] = S;
-            reinterpret_cast<float2 *>(&Ds[mm][0])[j] = Dd;
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {
+                const int ml = mq + 4 * it;
+                const v2f h1 = h1v[it], h2 = h2v[it];
+                const float Sx = h1.x + h2.x, Sy = h1.y + h2.y, Dx = h2.x - h1.x, Dy = h2.y - h1.y;
+                As[(2 * ml) * kRow64 + x] = ev[it].x;
+                As[(2 * ml + 1) * kRow64 + x] = ev[it].y;
+                float *r0 = Bs + (2 * ml) * kRow128 + (x >> 4) * 32 + (x & 15);
+                float *r1 = r0 + kRow128;
+                r0[0] = Sx;
+                r0[16] = Sy;
+                r1[0] = -Dy;
+                r1[16] = Dx;
+            }
         }
         __syncthreads();
-        for (int mm = 0; mm < mc; ++mm) {
-            const float4 e01 = Es[mm][2 * tc], e23 = Es[mm][2 * tc + 1];
-            const float4 s01 = Ss[mm][2 * tab], s23 = Ss[mm][2 * tab + 1];
-            const float4 d01 = Ds[mm][2 * tab], d23 = Ds[mm][2 * tab + 1];
-            const float er[4] = {e01.x, e01.z, e23.x, e23.z}, ei[4] = {e01.y, e01.w, e23.y, e23.w};
-            const float sr[4] = {s01.x, s01.z, s23.x, s23.z}, si[4] = {s01.y, s01.w, s23.y, s23.w};
-            const float dr[4] = {d01.x, d01.z, d23.x, d23.z}, di[4] = {d01.y, d01.w, d23.y, d23.w};
+        if (act) {
+            const int steps = (2 * mc + 3) / 4;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int g = 0; g < 2; ++g) {
+                if (4 * g >= steps) break;
+                float av[4], bv[4][8];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j].x = fmaf(er[i], sr[j], fmaf(-ei[i], di[j], acc[i][j].x));
-                    acc[i][j].y = fmaf(er[i], si[j], fmaf(ei[i], dr[j], acc[i][j].y));
+                for (int u = 0; u < 4; ++u) {
+                    const int s = 4 * g + u;
+                    av[u] = As[(4 * s + lg) * kRow64 + wv * 16 + li];
+                    const float *br = Bs + (4 * s + lg) * kRow128 + li;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) bv[u][q] = br[q * 16];
                 }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc[q][0] = mfma16(av[u], bv[u][2 * q], acc[q][0]);
+                        acc[q][1] = mfma16(av[u], bv[u][2 * q + 1], acc[q][1]);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
-    float2 *G = d.G + (int64_t)tb_ * p * p2;
+    if (!act) return;
+    const gm2 G = gw(d.G) + (int64_t)tb * p * p2;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int c = c0 + tc * 4 + i;
-        if (c >= p) continue;
+    for (int q = 0; q < 4; ++q) {
+        const int ab = ab0 + q * 16 + li;
+        if (ab >= p2) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int ab = ab0 + tab * 4 + j;
-            if (ab < p2) G[(int64_t)c * p2 + ab] = acc[i][j];
+        for (int r = 0; r < 4; ++r) {
+            const int c = c0 + wv * 16 + 4 * lg + r;
+            if (c < p) G[(int64_t)c * p2 + ab] = v2f{acc[q][0][r], acc[q][1][r]};
         }
     }
 }
 
-// v_i += sum over the grid nodes around x_i of phi phi phi G'.  Item (desc, target box, first point).
+// v_i += sum over the W^3 grid nodes around x_i of phi phi phi G'.  Item (desc, target box, first point).
+template <int W>
 __global__ void __launch_bounds__(kThreads)
 k_grid_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
@@ -995,39 +1284,42 @@ k_grid_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     const int i = wk.z + threadIdx.x;
     if (i >= d.tstart[t + 1]) return;
     const int p = d.gp;
-    const float half = 0.5f * (float)(p - 1), hw = 0.5f * (float)d.gw, fw = (float)d.gw, beta = d.gbeta;
-    const double ih = (double)d.ginv_h;
+    constexpr float hw = 0.5f * W, k1 = 2.f / W;
+    const float half = 0.5f * (float)(p - 1), k2 = d.gbeta * 1.44269504f;
+    const double ih = d.ginv_h;
     const float xg = (float)((d.txs[i] - d.tctr[3 * t]) * ih) + half;
     const float yg = (float)((d.tys[i] - d.tctr[3 * t + 1]) * ih) + half;
     const float zg = (float)((d.tzs[i] - d.tctr[3 * t + 2]) * ih) + half;
-    const int alo = max(0, (int)ceilf(xg - hw)), ahi = min(p - 1, (int)floorf(xg + hw));
-    const int blo = max(0, (int)ceilf(yg - hw)), bhi = min(p - 1, (int)floorf(yg + hw));
-    const int clo = max(0, (int)ceilf(zg - hw)), chi = min(p - 1, (int)floorf(zg + hw));
-    float wy[kGW];
+    const int alo = min(max((int)floorf(xg - hw) + 1, 0), p - W);
+    const int blo = min(max((int)floorf(yg - hw) + 1, 0), p - W);
+    const int clo = min(max((int)floorf(zg - hw) + 1, 0), p - W);
+    float wx[W], wy[W], wz[W];
 #pragma unroll
-    for (int q = 0; q < kGW; ++q) wy[q] = (blo + q <= bhi) ? es_phi((float)(blo + q) - yg, fw, beta) : 0.f;
-    const float2 *G = d.G + (int64_t)t * p * p * p;
+    for (int k = 0; k < W; ++k) {
+        wx[k] = es_phi((float)(alo + k) - xg, k1, k2);
+        wy[k] = es_phi((float)(blo + k) - yg, k1, k2);
+        wz[k] = es_phi((float)(clo + k) - zg, k1, k2);
+    }
+    const gc2 G = gl(d.G) + (int64_t)t * p * p * p + ((int64_t)clo * p + alo) * p + blo;
     float sr = 0.f, si = 0.f;
-    for (int c = clo; c <= chi; ++c) {
-        const float wz = es_phi((float)c - zg, fw, beta);
+#pragma unroll
+    for (int kc = 0; kc < W; ++kc) {
         float pr = 0.f, pi = 0.f;
-        for (int a = alo; a <= ahi; ++a) {
-            const float wx = es_phi((float)a - xg, fw, beta);
-            const float2 *row = G + ((int64_t)c * p + a) * p;
+#pragma unroll
+        for (int ka = 0; ka < W; ++ka) {
+            const gc2 row = G + ((int64_t)kc * p + ka) * p;
             float rr = 0.f, ri = 0.f;
 #pragma unroll
-            for (int q = 0; q < kGW; ++q) {
-                if (blo + q <= bhi) {
-                    const float2 g = row[blo + q];
-                    rr = fmaf(wy[q], g.x, rr);
-                    ri = fmaf(wy[q], g.y, ri);
-                }
+            for (int q = 0; q < W; ++q) {
+                const v2f g = row[q];
+                rr = fmaf(wy[q], g.x, rr);
+                ri = fmaf(wy[q], g.y, ri);
             }
-            pr = fmaf(wx, rr, pr);
-            pi = fmaf(wx, ri, pi);
+            pr = fmaf(wx[ka], rr, pr);
+            pi = fmaf(wx[ka], ri, pi);
         }
-        sr = fmaf(wz, pr, sr);
-        si = fmaf(wz, pi, si);
+        sr = fmaf(wz[kc], pr, sr);
+        si = fmaf(wz[kc], pi, si);
     }
     float2 o = d.v[i];
     o.x += sr;
@@ -1420,12 +1712,20 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
         case K_ZERO_OUT: return k_zero_io;
-        case K_GSPREAD: return k_grid_spread;
+        case K_GSPREAD: return S.a == 8 ? k_grid_spread<8> : k_grid_spread<6>;
         case K_GZ: return k_grid_z;
-        case K_GPHI: return k_grid_phi;
+        case K_GPHI:
+            // a = p / 16 for grids of at most 64 nodes per axis, 0 otherwise
+            switch (S.a) {
+                case 1: return k_grid_phi_s<1>;
+                case 2: return k_grid_phi_s<2>;
+                case 3: return k_grid_phi_s<3>;
+                case 4: return k_grid_phi_s<4>;
+                default: return k_grid_phi;
+            }
         case K_GPHIT: return k_grid_phit;
         case K_GZT: return k_grid_zt;
-        case K_GINTERP: return k_grid_interp;
+        case K_GINTERP: return S.a == 8 ? k_grid_interp<8> : k_grid_interp<6>;
         default: throw Error(FFM_EINTERNAL, "unknown kernel variant");
     }
 }

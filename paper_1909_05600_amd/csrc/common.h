@@ -204,11 +204,14 @@ struct LDesc {
     // grid form of the plane-wave transforms (spread onto a uniform grid, separable sums to the
     // quadrature directions): p nodes per axis at spacing h, kernel width w, shape beta
     int gp, gw;
-    float gbeta, ginv_h;                   // kernel shape, 1 / h
+    float gbeta;                           // kernel shape
+    double ginv_h;                         // 1 / h
     int64_t gnbox;                         // boxes in the grid arrays of this level
     float2 *G, *H;                         // G [box][c][a][b] grid values, H [m][box][a][b] ring sums
     const float2 *Ez, *Ex, *Ey;            // [nrp][p], [nrp][p][L], [nrp][p][L]
+    const float2 *ExT, *EyT;               // [nrp][L][p] (Ex, Ey transposed)
     const int32_t *gperm, *gzs;            // source points by z-plane: permutation, [box][p + 1] offsets
+    const float4 *gxyz;                    // their grid coordinates (node units), in the same order
 };
 
 // Kernel variants (the template parameters travel with the stage).
@@ -227,20 +230,13 @@ struct Stage {
     DevBuf<int4> ditems;
 };
 
-// Thread layout of the grid-form sums over the plane (k_grid_phi): TA thread rows of 4 grid rows each
-// (a pass covers at most 64 rows), TN thread columns of 4 azimuths each.
-__host__ __device__ inline void grid_phi_tile(int p, int &TA, int &TN) {
-    const int pp = p < 64 ? p : 64;
-    TA = (pp + 3) / 4;
-    TN = 256 / TA < 32 ? 256 / TA : 32;
-}
-// Rings per block of the mirror sums (k_grid_phit): 4 x 4 (a, b) per thread over the grid's (at most
-// 64 x 64) tile, as many rings as fill 256 threads.
-__host__ __device__ inline int grid_phit_rings(int p) {
-    if (p > 64) return 1;
-    const int t = (p + 3) / 4;
-    const int r = 256 / (t * t);
-    return r < 1 ? 1 : (r > 4 ? 4 : r);
+
+// Ring-pair blocks (16 ring pairs each) per work item of the grid form's sums over z: at most four per item,
+// balanced over the items.
+__host__ __device__ inline void grid_z_groups(int nrp, int &ngroups, int &per) {
+    const int nmb = (nrp + 15) / 16;
+    ngroups = (nmb + 3) / 4;
+    per = (nmb + ngroups - 1) / ngroups;
 }
 
 // Tile choices of the plane-wave kernels (the autotuner picks among them).
@@ -290,7 +286,9 @@ struct Level {
     int gp = 0, gw = 0;
     double gh = 0, gbeta = 0;
     DevBuf<float2> Ez, Ex, Ey;           // [nrp][p], [nrp][p][L], [nrp][p][L]
+    DevBuf<float2> ExT, EyT;             // [nrp][L][p]
     DevBuf<int32_t> gperm, gzs;          // source points ordered by box and z-plane; [nbox_y][p + 1]
+    DevBuf<float4> gxyz;                 // grid coordinates of the source points, gperm order
     // Lagrange node tables (FP32): Chebyshev nodes and 1 / prod_{b != a}(t_a - t_b)
     DevBuf<float> lnodes, lden;
     // box lists on the host, largest boxes first, and the box point ranges

@@ -418,11 +418,12 @@ k_gegen_D(int64_t npair, int L, const double *dirs /*[npair][3] unit*/, const do
 
 // ------------------------------------------------------------------ grid form tables
 // Ez[m][c] = e^{-ik cos(t_m) z_c}, Ex[m][a][n] = e^{-ik sin(t_m) cos(f_n) x_a}, Ey[m][b][n] =
-// e^{-ik sin(t_m) sin(f_n) y_b} for ring pairs m < nrp, n < L, grid nodes x_a = (a - (p-1)/2) h.
+// e^{-ik sin(t_m) sin(f_n) y_b} for ring pairs m < nrp, n < L, grid nodes x_a = (a - (p-1)/2) h; ExT and EyT
+// hold Ex and Ey as [m][n][node].
 // Phases in revolutions from the ring tables (k / 2pi folded in), reduced and evaluated in FP64.
 __global__ void __launch_bounds__(kThreads)
 k_grid_tables(int nrp, int L, int p, double h, const double2 *rings, const double2 *phis, float2 *Ez, float2 *Ex,
-              float2 *Ey) {
+              float2 *Ey, float2 *ExT, float2 *EyT) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t nxy = (int64_t)nrp * p * L;
     auto cis = [](double rev) {
@@ -436,8 +437,12 @@ k_grid_tables(int nrp, int L, int p, double h, const double2 *rings, const doubl
         const int64_t ma = i / L;
         const int a = (int)(ma % p), m = (int)(ma / p);
         const double x = (a - 0.5 * (p - 1)) * h;
-        Ex[i] = cis(rings[m].x * phis[n].x * x);
-        Ey[i] = cis(rings[m].x * phis[n].y * x);
+        const float2 ex = cis(rings[m].x * phis[n].x * x), ey = cis(rings[m].x * phis[n].y * x);
+        Ex[i] = ex;
+        Ey[i] = ey;
+        const int64_t it = ((int64_t)m * L + n) * p + a;
+        ExT[it] = ex;
+        EyT[it] = ey;
     }
     if (i < (int64_t)nrp * p) {
         const int c = (int)(i % p), m = (int)(i / p);
@@ -445,15 +450,12 @@ k_grid_tables(int nrp, int L, int p, double h, const double2 *rings, const doubl
     }
 }
 
-// z-plane of every source point of a level's box (for the spreading launches): count per (box, plane)
-__device__ __forceinline__ int grid_cell(double z, double cz, double inv_h, int p) {
-    const int c = (int)floor((z - cz) * inv_h + 0.5 * (p - 1));
-    return min(max(c, 0), p - 1);
-}
-
+// Grid coordinates of every source point of a level, in node units (x_a = a for the node at
+// (a - (p-1)/2) h from the box centre), FP32 as the spreading kernels use them, and the z-plane floor(z_g)
+// that orders the points for the spreading launches: count per (box, plane).
 __global__ void __launch_bounds__(kThreads)
-k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *zs, const double *ctr, double inv_h, int p,
-              int32_t *cnt, int32_t *cell_of) {
+k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *xs, const double *ys, const double *zs,
+              const double *ctr, double inv_h, int p, int32_t *cnt, int32_t *cell_of, float4 *gtmp) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
     int lo = 0, hi = nbox;   // box b with start[b] <= i < start[b + 1]
@@ -462,17 +464,24 @@ k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *zs, const
         if (start[mid] <= i) lo = mid;
         else hi = mid;
     }
-    const int c = grid_cell(zs[i], ctr[3 * lo + 2], inv_h, p);
+    const float half = 0.5f * (float)(p - 1);
+    const float xg = (float)((xs[i] - ctr[3 * lo]) * inv_h) + half;
+    const float yg = (float)((ys[i] - ctr[3 * lo + 1]) * inv_h) + half;
+    const float zg = (float)((zs[i] - ctr[3 * lo + 2]) * inv_h) + half;
+    const int c = min(max((int)floorf(zg), 0), p - 1);
     const int64_t slot = (int64_t)lo * p + c;
     cell_of[i] = (int32_t)slot;
+    gtmp[i] = make_float4(xg, yg, zg, 0.f);
     atomicAdd(&cnt[slot], 1);
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_grid_zscatter(int64_t n, const int32_t *cell_of, int32_t *cursor, int32_t *perm) {
+k_grid_zscatter(int64_t n, const int32_t *cell_of, int32_t *cursor, int32_t *perm, const float4 *gtmp, float4 *gxyz) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    perm[atomicAdd(&cursor[cell_of[i]], 1)] = (int32_t)i;
+    const int pos = atomicAdd(&cursor[cell_of[i]], 1);
+    perm[pos] = (int32_t)i;
+    gxyz[pos] = gtmp[i];
 }
 
 __global__ void k_copy_i32(const int32_t *a, int32_t *b, int64_t n) {
@@ -984,30 +993,23 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 const int w = P.eps >= 3e-4 ? 6 : 8;
                 const double hmax = M_PI / (1.9 * P.k);
                 int p = (int)std::ceil(dl / hmax) + w + 1;
-                p = (p + 7) / 8 * 8;
+                p = (p + 15) / 16 * 16;   // whole 16-row blocks of the MFMA sums
                 const double h = dl / (double)(p - 1 - w);
                 // cost model in seconds, from measured MI355X rates: direct sums 9e-14 s per (point,
-                // direction); grid form: spreading 0.8 ns and interpolation 0.26 ns per point (w = 6), the
-                // tiled sums 3.4e-14 s per FMA divided by the fraction of their tiles the shapes fill
+                // direction); grid form: spreading 0.29 ns per point plus 2.5 ns per (box, plane) launch item
+                // and interpolation 0.12 ns per point (w = 6; w^3 nodes per point), and the four sums on FP32
+                // MFMA (real multiply-adds as issued) at a fraction of the 78.6e12 per second peak that falls
+                // with narrower grids (measured 0.5 at 64 nodes, 0.44 at 48, 0.37 at 32; 0.35 above 64)
                 const double nbf = (double)LV.h_fwd.size(), nbt = (double)LV.h_tgt.size(), ws = (double)w / 6.0;
                 const double p2 = (double)p * p, p3 = p2 * p;
-                auto fill = [](double n, double t) { return n / (std::ceil(n / t) * t); };
-                int TA, TN;
-                grid_phi_tile(p, TA, TN);
-                const int RR = grid_phit_rings(p), TC = p > 64 ? 16 : (p + 3) / 4;
-                const double z_eff = fill(LV.nrp, 32) * fill(p, 32);
-                // narrower tiles (p < 64) reuse each staged value fewer times: measured rates fall as
-                // (p / 64)^0.5 for the sums to the directions and (p / 64)^0.75 for the sums back
-                const double narrow = std::min(1.0, p / 64.0);
-                const double phi_eff =
-                    (p > 64 ? fill(p, 64) : 1.0) * (TA * TN / 256.0) * fill(L, 4.0 * TN) * std::sqrt(narrow);
-                const double phit_eff = (p > 64 ? fill(p, 64) * fill(p, 64) : RR * TC * TC / 256.0) *
-                                        fill(L + 1.0, RR) * std::pow(narrow, 0.75);
+                const double rings16 = 16.0 * ((LV.nrp + 15) / 16), tiles64 = 64.0 * ((p + 63) / 64);
+                const double macs = (nbf + nbt) * 4.0 * rings16 * p3 +                    // over z, both ways
+                                    nbf * 4.0 * p2 * (L + 1.0) * 8.0 * ((L + 7) / 8) +    // plane to directions
+                                    nbt * 4.0 * p * tiles64 * (L + 1.0) * 2.0 * ((L + 1) / 2);   // and back
+                const double eff = p > 64 ? 0.35 : 0.5 * std::pow(p / 64.0, 0.45);
                 const double direct = (LV.pts_src + LV.pts_tgt) * (double)LV.nq * 9e-14;
-                const double gridc = ws * ws * ws * (0.8e-9 * LV.pts_src + 0.26e-9 * LV.pts_tgt) +
-                                     (nbf + nbt) * LV.nrp * p3 * 4.0 * 3.4e-14 / z_eff +
-                                     nbf * (L + 1.0) * L * p2 * 4.0 * 3.4e-14 / phi_eff +
-                                     nbt * (L + 1.0) * L * p2 * 4.0 * 3.4e-14 / phit_eff;
+                const double gridc = ws * ws * ws * (0.29e-9 * LV.pts_src + 0.12e-9 * LV.pts_tgt) + 2.5e-9 * nbf * p +
+                                     macs / (eff * 78.6e12);
                 const size_t gnb = (size_t)std::max(nbx, nby);
                 const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
                 const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
@@ -1023,20 +1025,25 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     LV.Ez.alloc((size_t)LV.nrp * p);
                     LV.Ex.alloc((size_t)nxy);
                     LV.Ey.alloc((size_t)nxy);
+                    LV.ExT.alloc((size_t)nxy);
+                    LV.EyT.alloc((size_t)nxy);
                     FFM_LAUNCH(k_grid_tables, nblocks(std::max<int64_t>(nxy, (int64_t)LV.nrp * p)), kThreads, 0, st,
-                               LV.nrp, L, p, h, LV.rings.p, LV.phis.p, LV.Ez.p, LV.Ex.p, LV.Ey.p);
+                               LV.nrp, L, p, h, LV.rings.p, LV.phis.p, LV.Ez.p, LV.Ex.p, LV.Ey.p, LV.ExT.p, LV.EyT.p);
                     // source points ordered by box and z-plane
                     const int64_t ncell = (int64_t)nby * p;
                     int32_t *cnt = SC.get<int32_t>(ncell + 1), *cell_of = SC.get<int32_t>(std::max<int64_t>(TY.n, 1));
+                    float4 *gtmp = SC.get<float4>(std::max<int64_t>(TY.n, 1));
                     FFM_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (ncell + 1), st));
-                    FFM_LAUNCH(k_grid_zcount, nblocks(TY.n), kThreads, 0, st, TY.n, TY.lev[l].start.p, nby, TY.zs.p,
-                               TY.lev[l].ctr.p, 1.0 / h, p, cnt, cell_of);
+                    FFM_LAUNCH(k_grid_zcount, nblocks(TY.n), kThreads, 0, st, TY.n, TY.lev[l].start.p, nby, TY.xs.p,
+                               TY.ys.p, TY.zs.p, TY.lev[l].ctr.p, 1.0 / h, p, cnt, cell_of, gtmp);
                     LV.gzs.alloc((size_t)ncell + 1);
                     exclusive_scan_i32(cnt, LV.gzs.p, ncell, st, SC);
                     int32_t *cursor = SC.get<int32_t>(ncell + 1);
                     FFM_LAUNCH(k_copy_i32, nblocks(ncell + 1), kThreads, 0, st, LV.gzs.p, cursor, ncell + 1);
                     LV.gperm.alloc((size_t)std::max<int64_t>(TY.n, 1));
-                    FFM_LAUNCH(k_grid_zscatter, nblocks(TY.n), kThreads, 0, st, TY.n, cell_of, cursor, LV.gperm.p);
+                    LV.gxyz.alloc((size_t)std::max<int64_t>(TY.n, 1));
+                    FFM_LAUNCH(k_grid_zscatter, nblocks(TY.n), kThreads, 0, st, TY.n, cell_of, cursor, LV.gperm.p, gtmp,
+                               LV.gxyz.p);
                     const std::vector<double> &tab = phi_hat_table(w, LV.gbeta, dphat_step);
                     dphat = keep(SC, tab, st);
                     nphat = (int)tab.size();
@@ -1292,28 +1299,29 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
         const int s1 = 1 + 3 * (l - 1), s2 = s1 + 1, s3 = s1 + 2;
         const std::vector<int32_t> &sx = LV.h_sx;
         if (LV.method == kGegenbauer && LV.grid) {
-            // grid form: spread (per z-plane and 64 x 64 tile), sums over z (8 ring pairs per block), sums
-            // over the plane to the directions (64 directions per block); the transfer; the mirror stages
+            // grid form: spread (per z-plane and 64 x 64 tile), sums over z (64 grid columns and up to 64
+            // ring pairs per block), sums over the plane to the directions (one ring per block); the transfer;
+            // the mirror stages (one ring and 64 x 64 tile, then 64 columns x 64 planes per block)
             const int L = LV.L, p = LV.gp, nta = (p + 63) / 64;
             LV.qG = 0;
             LV.qSplit = 1;
             LV.bSplit = 1;
-            const int ncol = (p * p + 127) / 128;
-            int TA, TN;
-            grid_phi_tile(p, TA, TN);
-            const int NT = 4 * TN, RR = grid_phit_rings(p);
+            const int ncol = (p * p + 63) / 64;
+            int zng, zper;
+            grid_z_groups(LV.nrp, zng, zper);
+            zng = ((LV.nrp + 15) / 16 + zper - 1) / zper;
             std::vector<int4> a1, a2, a3, tr, b1, b2, b3;
             for (int32_t b : LV.h_fwd) {
                 for (int c = 0; c < p; ++c)
                     for (int t = 0; t < nta * nta; ++t) a1.push_back(make_int4(l, b, c, t));
                 for (int t = 0; t < ncol; ++t)
-                    for (int mc = 0; mc < (LV.nrp + 31) / 32; ++mc) a2.push_back(make_int4(l, b, t, mc));
-                for (int m = 0; m <= L; ++m)
-                    for (int nt = 0; nt < (L + NT - 1) / NT; ++nt) a3.push_back(make_int4(l, b, m, nt));
+                    for (int g = 0; g < zng; ++g) a2.push_back(make_int4(l, b, t, g));
+                for (int m = 0; m <= L; ++m) a3.push_back(make_int4(l, b, m, 0));
             }
-            LV.stages.push_back(make_stage(K_GSPREAD, 0, 0, -1, l, 0, std::move(a1), st, SC));
+            LV.stages.push_back(make_stage(K_GSPREAD, LV.gw, 0, -1, l, 2 * sizeof(uint64_t) * std::min(p, 64) * std::min(p, 64),
+                                           std::move(a1), st, SC));
             LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
-            LV.stages.push_back(make_stage(K_GPHI, 0, 0, s1, l, 0, std::move(a3), st, SC));
+            LV.stages.push_back(make_stage(K_GPHI, p <= 64 ? p / 16 : 0, 0, s1, l, 0, std::move(a3), st, SC));
             int bs, ppt;
             pick_pair_tile(LV.npair, 2, bs, ppt);
             const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
@@ -1321,15 +1329,15 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 for (int32_t t : LV.h_tgt) tr.push_back(make_int4(l, t, (int)q, 0));
             LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
             for (int32_t t : LV.h_tgt) {
-                for (int m = 0; m <= L; m += RR)
+                for (int m = 0; m <= L; ++m)
                     for (int q = 0; q < nta * nta; ++q) b1.push_back(make_int4(l, t, m, q));
                 for (int q = 0; q < ncol; ++q)
-                    for (int cc = 0; cc < (p + 31) / 32; ++cc) b2.push_back(make_int4(l, t, q, cc));
+                    for (int cc = 0; cc < nta; ++cc) b2.push_back(make_int4(l, t, q, cc));
                 for (int32_t i = sx[t]; i < sx[t + 1]; i += kThreads) b3.push_back(make_int4(l, t, i, 0));
             }
             LV.stages.push_back(make_stage(K_GPHIT, 0, 0, -1, l, 0, std::move(b1), st, SC));
             LV.stages.push_back(make_stage(K_GZT, 0, 0, -1, l, 0, std::move(b2), st, SC));
-            LV.stages.push_back(make_stage(K_GINTERP, 0, 0, s3, l, 0, std::move(b3), st, SC));
+            LV.stages.push_back(make_stage(K_GINTERP, LV.gw, 0, s3, l, 0, std::move(b3), st, SC));
         } else if (LV.method == kGegenbauer) {
             const int L = LV.L;
             LV.qG = L >= 64 ? tu.ring_g : (L >= 32 ? 2 : 0);
@@ -1484,15 +1492,18 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.gp = LV.gp;
     d.gw = LV.gw;
     d.gbeta = (float)LV.gbeta;
-    d.ginv_h = LV.grid ? (float)(1.0 / LV.gh) : 0.f;
+    d.ginv_h = LV.grid ? 1.0 / LV.gh : 0.0;
     d.gnbox = std::max(LX.nbox, LY.nbox);
     d.G = w.G;
     d.H = w.H;
     d.Ez = LV.Ez.p;
     d.Ex = LV.Ex.p;
     d.Ey = LV.Ey.p;
+    d.ExT = LV.ExT.p;
+    d.EyT = LV.EyT.p;
     d.gperm = LV.gperm.p;
     d.gzs = LV.gzs.p;
+    d.gxyz = LV.gxyz.p;
     return d;
 }
 
@@ -1530,7 +1541,8 @@ size_t plan_device_bytes(const Plan &P) {
         const Level &L = P.lev[l];
         b += L.far_ptr.bytes() + L.near_ptr.bytes() + L.far_src.bytes() + L.far_cls.bytes() + L.near_src.bytes() +
              L.T.bytes() + L.grp_pair.bytes() + L.grp_cls.bytes() + L.dirs.bytes() + L.dirs64.bytes() + L.D.bytes() +
-             L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes();
+             L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes() + L.Ez.bytes() +
+             L.Ex.bytes() + L.Ey.bytes() + L.ExT.bytes() + L.EyT.bytes() + L.gperm.bytes() + L.gzs.bytes() + L.gxyz.bytes();
         for (const Stage &S : L.stages) b += S.ditems.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
