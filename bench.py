@@ -32,6 +32,12 @@ PEAK_ALU_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12          # 78.6
 #   direction-pair form: per (point, antipodal pair)   3 phase + 4 accumulate = 7 slots / 2 directions
 #   ring-pair form:      per (point, group of 4 dirs)   2 phase + 8 accumulate = 10 slots / 4 directions
 SLOTS_PER_DIRECTION = {1: 7 / 2, 2: 10 / 4}
+# Near field, per (target, source) pair: Laplace ~10 non-transcendental slots, Helmholtz ~18 (plus sin, cos and
+# reciprocal square root on the transcendental unit).
+NEAR_SLOTS = {"k_near<false>": 10.0, "k_near<true>": 18.0}
+# Published MI355X peaks per bound: dense FP32 MFMA 157.3 TFLOP/s, FP32 VALU (non-packed, FMA = 2) 78.6,
+# HBM3E 8 TB/s.
+PEAKS = {"mfma": (157.3, "TFLOP/s"), "alu": (PEAK_ALU_TFLOPS, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
 
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
 # workload (profiles/traffic_pw_rings_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
@@ -300,6 +306,74 @@ def mixed_study(n, n_rows, reps=3):
     return out
 
 
+def kernel_totals(launches, steps):
+    """Milliseconds per step of every kernel symbol over the timed steps (HIP events around each launch)."""
+    tot = {}
+    for step in launches:
+        for r in step:
+            tot[r["kernel"]] = tot.get(r["kernel"], 0.0) + r["ms"] / steps
+    return dict(sorted(tot.items(), key=lambda kv: -kv[1]))
+
+
+def launch_work(name, level, st):
+    """Algorithmic work of one launch of a kernel at a level: (amount, unit kind, definition), or None for
+    kernels without a model here.  mfma / alu amounts are flops (FMA = 2), hbm amounts bytes."""
+    L, nq = st["order"][level], st["nq"][level]
+    p, nbf, nbt = st["grid_nodes"][level], st["fwd_boxes"][level], st["bwd_boxes"][level]
+    if name.startswith("k_grid_phi"):
+        nb = nbt if name == "k_grid_phit" else nbf
+        return (8.0 * nb * (L + 1) * p * p * L, "mfma",
+                "8 flops per (box, ring, node a, node b, azimuth): the four real products of the separable "
+                "plane sums, FP32 MFMA")
+    if name in ("k_grid_z", "k_grid_zt"):
+        nb = nbf if name == "k_grid_z" else nbt
+        return (8.0 * nb * ((L + 2) // 2) * p ** 3, "mfma",
+                "8 flops per (box, ring pair, plane, column): the four real products of the z sums, FP32 MFMA")
+    if name.startswith("k_pw_forward_rings") or name.startswith("k_pw_backward_rings"):
+        pts = st["fwd_points"][level] if "forward" in name else st["bwd_points"][level]
+        return (2.0 * SLOTS_PER_DIRECTION[2] * pts * nq, "alu",
+                "non-transcendental VALU issue slots x 2 of the ring-pair form: 10 per (point, 4 directions)")
+    if name.startswith("k_pw_forward") or name.startswith("k_pw_backward"):
+        pts = st["fwd_points"][level] if "forward" in name else st["bwd_points"][level]
+        return (2.0 * SLOTS_PER_DIRECTION[1] * pts * nq, "alu",
+                "non-transcendental VALU issue slots x 2 of the direction-pair form: 7 per (point, 2 directions)")
+    if name.startswith("k_near"):
+        return (2.0 * NEAR_SLOTS[name] * st["near_pairs"], "alu",
+                "non-transcendental VALU issue slots x 2 per (target, source) pair of the near field")
+    if name.startswith("k_pw_transfer"):
+        return (16.0 * st["nfar"][level] * nq + 8.0 * nbt * nq, "hbm",
+                "bytes: u~(q) and D(q) (8 + 8) per (far pair, direction), v~(q) (8) per (target box, direction)")
+    return None
+
+
+def roofline(launches, st, steps):
+    """Roofline of the dominant kernel: the kernel symbol with the most time per step among those with a
+    work model; achieved = its algorithmic work over all its launches / their HIP-event time."""
+    tot = kernel_totals(launches, steps)
+    for name in tot:
+        work, kind, definition, ms, n = 0.0, None, None, 0.0, 0
+        for step in launches:
+            for r in step:
+                if r["kernel"] != name:
+                    continue
+                m = launch_work(name, r["level"], st)
+                if m is None:
+                    break
+                work += m[0]
+                kind, definition = m[1], m[2]
+                ms += r["ms"]
+                n += 1
+        if kind is None or ms <= 0:
+            continue
+        peak, unit = PEAKS[kind]
+        rate = work / (ms * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
+        return name, {"bound": kind, "kernel": name, "achieved": rate, "peak": peak, "unit": unit,
+                      "frac": rate / peak, "launches": n // steps, "avg_launch_ms": ms / n,
+                      "work_per_step": work / steps, "work": definition}
+    return "none", {"bound": "alu", "kernel": "none", "achieved": 0.0, "peak": PEAK_ALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": 0.0}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -357,12 +431,13 @@ def main():
                 record["apply_ms"].append(e0.elapsed_time(e1))
                 record["latency_ms"].append((t_done - tp0) * 1e3)
                 record["phases"].append(plan.timing())
+                record["launches"].append(plan.launch_timing())
                 record["stats"] = plan.stats()
             plan.destroy()
             cur = nxt
 
     run(args.warmup, None)
-    rec = {"plan_ms": [], "apply_ms": [], "latency_ms": [], "phases": [], "stats": None}
+    rec = {"plan_ms": [], "apply_ms": [], "latency_ms": [], "phases": [], "launches": [], "stats": None}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     run(args.steps, rec)
@@ -374,29 +449,7 @@ def main():
     st = rec["stats"]
     ph = np.array(rec["phases"])          # [steps][64]
     leaf = st["leaf"]
-    # Dominant kernel: among the ring-pair plane-wave transforms (one kernel symbol per template instance;
-    # forward in slot 1 + 3(l-1), backward in slot 3 + 3(l-1)), the symbol with the largest total time.
-    per_dir = SLOTS_PER_DIRECTION[2]
-    groups = {}
-    for l in range(1, leaf + 1):
-        if st["method"][l] != 2 or st["tform"][l] != 2:
-            continue
-        L = st["order"][l]
-        g = tiles[0] if L >= 64 else 2
-        if (L + g - 1) // g > 256:
-            g = 4
-        p64 = "true" if st["phase64"][l] else "false"
-        pt = tiles[1]
-        for sym, slot, pts in (("k_pw_forward_rings<%d, %s>" % (g, p64), 1 + 3 * (l - 1), "fwd_points"),
-                               ("k_pw_backward_rings<%d, %d, %s>" % (pt, 4 if pt == 1 else 2, p64), 3 + 3 * (l - 1),
-                                "bwd_points")):
-            e = groups.setdefault(sym, [0.0, 0.0, 0])
-            e[0] += ph[:, slot].sum()
-            e[1] += args.steps * st[pts][l] * st["nq"][l] * per_dir
-            e[2] += args.steps
-    dom = max(groups, key=lambda k: groups[k][0]) if groups else "none"
-    d_ms, d_slots, nlaunch = groups.get(dom, (0.0, 0.0, 0))
-    achieved = 2 * d_slots / (d_ms * 1e-3) / 1e12 if d_ms > 0 else 0.0
+    dom, roof = roofline(rec["launches"], st, args.steps)
     traffic = TRAFFIC.get(dom) if _source_hash() == TRAFFIC_SOURCE_HASH else None
     phase_mean = ph.mean(axis=0)
     names = {0: "perm_in", 61: "near_field", 62: "perm_out"}
@@ -431,15 +484,10 @@ def main():
         "plan_plus_apply_ms": float(np.mean(rec["plan_ms"]) + np.mean(rec["apply_ms"])),
         "sequential_points_per_s": w.n / ((np.mean(rec["plan_ms"]) + np.mean(rec["apply_ms"])) * 1e-3),
         "phases_ms": phases,
-        "roofline": {
-            "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
-            "launches": nlaunch, "avg_launch_ms": d_ms / max(nlaunch, 1),
-            "work": "non-transcendental VALU issue slots x 2 (FMA-equivalent flops) of the ring-pair form: "
-                    "10 per (point, 4 quadrature directions), over the ring-pair levels; "
-                    "peak = 256 CU x 64 lanes x 2.4 GHz x 2",
-            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy)",
-        },
+        "roofline": dict(roof, traffic=traffic,
+                         traffic_unit="bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a "
+                                      "1 GiB copy)"),
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in kernel_totals(rec["launches"], args.steps).items()},
         "levels": {"leaf": leaf, "nq": [int(x) for x in st["nq"][:leaf + 1]],
                    "transform_form": [int(x) for x in st["tform"][:leaf + 1]],
                    "nfar": [int(x) for x in st["nfar"][:leaf + 1]], "near_pairs": st["near_pairs"],

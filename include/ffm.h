@@ -152,6 +152,9 @@ typedef struct {
     double  near_pairs;                    /* point pairs of the leaf near field          */
     double  plan_bytes;                    /* device memory held by the plan              */
     double  workspace_bytes;               /* device memory of the apply workspace        */
+    int32_t grid_nodes[FFM_MAX_LEVELS];    /* grid form: nodes p per axis of each box's grid, else 0 */
+    int64_t fwd_boxes[FFM_MAX_LEVELS];     /* source boxes transformed at level l         */
+    int64_t bwd_boxes[FFM_MAX_LEVELS];     /* target boxes transformed at level l         */
 } ffm_stats_t;
 
 ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out);
@@ -187,6 +190,32 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
  */
 #define FFM_TIMING_SLOTS 64
 ffm_status_t ffm_plan_timing(ffm_plan_t plan, float *ms, int32_t n);
+
+/*
+ * ffm_plan_launch_timing -- the kernel launches of the most recent apply of a
+ * plan made with FFM_FLAG_TIMING, in launch order, each timed by its own pair
+ * of HIP events on the apply's stream; waits for that apply to finish.  The
+ * first min(n, launches) records are written to out (host memory); *count
+ * receives the number of launches.  kernel, variant_a and variant_b name the
+ * kernel (ffm_kernel_name); level is the level the launch works on (0 for the
+ * permutations and the near field); blocks its thread blocks.  FFM_EINVAL
+ * without FFM_FLAG_TIMING or with NULL out (n > 0) or count.
+ */
+typedef struct {
+    int32_t kernel, variant_a, variant_b, level;
+    int64_t blocks;
+    float   ms;
+    int32_t reserved;
+} ffm_launch_t;
+ffm_status_t ffm_plan_launch_timing(ffm_plan_t plan, ffm_launch_t *out, int32_t n, int32_t *count);
+
+/*
+ * ffm_kernel_name -- the symbol of a launch's kernel as profilers print it
+ * (template arguments included, namespaces and parameters left out), e.g.
+ * "k_grid_phi_s<4>", written NUL-terminated into buf (host, n bytes, cut to
+ * fit).  Returns the full length, or -1 for an unknown kernel.
+ */
+int32_t ffm_kernel_name(int32_t kernel, int32_t variant_a, int32_t variant_b, char *buf, int32_t n);
 
 /* Device bytes held by the plan, and by its apply workspace. */
 size_t ffm_plan_bytes(ffm_plan_t plan);

@@ -28,7 +28,7 @@ EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_versi
             "ffm_plan_export", "ffm_plan_timing", "ffm_plan_bytes", "ffm_workspace_bytes",
             "ffm_plan_set_tiles", "ffm_plan_get_tiles", "ffm_batch_create", "ffm_batch_apply", "ffm_batch_info",
             "ffm_batch_destroy", "ffm_server_create", "ffm_server_submit", "ffm_server_wait", "ffm_server_poll",
-            "ffm_server_stats", "ffm_server_destroy"]
+            "ffm_server_stats", "ffm_server_destroy", "ffm_plan_launch_timing", "ffm_kernel_name"]
 FFM_FLAG_TIMING = 1
 FFM_FLAG_DIRECT_TRANSFORMS = 2
 FFM_FLAG_GRID_TRANSFORMS = 4
@@ -60,7 +60,8 @@ class Stats(C.Structure):
                 ("nclass", C.c_int32 * _L), ("nq", C.c_int64 * _L), ("fwd_points", C.c_double * _L),
                 ("bwd_points", C.c_double * _L), ("transform_terms", C.c_double),
                 ("transfer_macs", C.c_double), ("near_pairs", C.c_double), ("plan_bytes", C.c_double),
-                ("workspace_bytes", C.c_double)]
+                ("workspace_bytes", C.c_double), ("grid_nodes", C.c_int32 * _L), ("fwd_boxes", C.c_int64 * _L),
+                ("bwd_boxes", C.c_int64 * _L)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -81,6 +82,11 @@ class BatchInfo(C.Structure):
 
 class ServerOptions(C.Structure):
     _fields_ = [("slots", C.c_int32), ("reserved", C.c_int32), ("budget_bytes", C.c_double)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("variant_a", C.c_int32), ("variant_b", C.c_int32), ("level", C.c_int32),
+                ("blocks", C.c_int64), ("ms", C.c_float), ("reserved", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -125,6 +131,8 @@ def lib():
             "ffm_server_poll": (C.c_int, [P, i64, P]),
             "ffm_server_stats": (C.c_int, [P, P]),
             "ffm_server_destroy": (C.c_int, [P]),
+            "ffm_plan_launch_timing": (C.c_int, [P, P, i32, P]),
+            "ffm_kernel_name": (i32, [i32, i32, i32, C.c_char_p, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -180,6 +188,15 @@ def _dtype_code(t) -> int:
     if t.dtype not in _DTYPES:
         raise TypeError("wu must be complex64, complex128, float32 or float64")
     return _DTYPES[t.dtype]
+
+
+def kernel_name(kernel: int, variant_a: int = 0, variant_b: int = 0) -> str:
+    """Symbol of a launch's kernel as profilers print it (ffm_kernel_name)."""
+    buf = C.create_string_buffer(96)
+    n = lib().ffm_kernel_name(kernel, variant_a, variant_b, buf, 96)
+    if n < 0:
+        raise FFMError(-1, "unknown kernel %d" % kernel)
+    return buf.value.decode()
 
 
 class Plan:
@@ -255,6 +272,16 @@ class Plan:
         buf = (C.c_float * TIMING_SLOTS)()
         _check(lib().ffm_plan_timing(self._h, buf, TIMING_SLOTS))
         return list(buf)
+
+    def launch_timing(self) -> list:
+        """The kernel launches of the last apply (plans made with timing=True), in order: dicts with the kernel's
+        symbol, its level, thread blocks and HIP-event milliseconds."""
+        n = C.c_int32(0)
+        _check(lib().ffm_plan_launch_timing(self._h, None, 0, C.byref(n)))
+        buf = (Launch * max(n.value, 1))()
+        _check(lib().ffm_plan_launch_timing(self._h, buf, n.value, C.byref(n)))
+        return [{"kernel": kernel_name(r.kernel, r.variant_a, r.variant_b), "level": r.level, "blocks": r.blocks,
+                 "ms": r.ms} for r in buf[:n.value]]
 
     def set_tiles(self, ring_g: int, bwd_pt: int, stream=None):
         """Rebuild the plane-wave kernels' launches for a tile choice (ring_g in {2, 4}, bwd_pt in {1, 2})."""

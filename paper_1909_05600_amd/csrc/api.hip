@@ -1,4 +1,5 @@
 // The C ABI of include/ffm.h: argument checks, error mapping, ownership.
+#include <cstring>
 #include "common.h"
 
 #include <atomic>
@@ -184,8 +185,10 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         plan_build(P, X, Y, st);
         FFM_HIP(hipEventCreateWithFlags(&P.done, hipEventDisableTiming));
         if (o.flags & FFM_FLAG_TIMING) {
-            P.tev.resize(3 * kMaxLev + 8, nullptr);
+            P.tev.resize(12 * kMaxLev + 16, nullptr);   // one event per launch, every form of every level
             P.tphase.assign(P.tev.size(), -1);
+            P.tkern.assign(P.tev.size(), make_int4(-1, 0, 0, 0));
+            P.tblocks.assign(P.tev.size(), 0);
             for (auto &e : P.tev) FFM_HIP(hipEventCreate(&e));
         }
         P.stats.plan_bytes = (double)plan_device_bytes(P);
@@ -243,6 +246,48 @@ ffm_status_t ffm_plan_timing(ffm_plan_t plan, float *ms, int32_t n) {
             if (P.tphase[i] >= 0 && P.tphase[i] < n) ms[P.tphase[i]] += t;
         }
     });
+}
+
+ffm_status_t ffm_plan_launch_timing(ffm_plan_t plan, ffm_launch_t *out, int32_t n, int32_t *count) {
+    if (!plan || !count || n < 0 || (n > 0 && !out))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_launch_timing: bad argument");
+    Plan &P = plan->P;
+    if (P.tev.empty())
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_launch_timing: plan made without FFM_FLAG_TIMING");
+    return (ffm_status_t)Guard::run([&] {
+        *count = 0;
+        if (P.tused < 2) return;
+        FFM_HIP(hipEventSynchronize(P.tev[P.tused - 1]));
+        int32_t k = 0;
+        for (int i = 1; i < P.tused; ++i) {
+            if (P.tkern[i].x < 0) continue;
+            if (k < n) {
+                float t = 0.f;
+                FFM_HIP(hipEventElapsedTime(&t, P.tev[i - 1], P.tev[i]));
+                ffm_launch_t &r = out[k];
+                r.kernel = P.tkern[i].x;
+                r.variant_a = P.tkern[i].y;
+                r.variant_b = P.tkern[i].z;
+                r.level = P.tkern[i].w;
+                r.blocks = P.tblocks[i];
+                r.ms = t;
+                r.reserved = 0;
+            }
+            ++k;
+        }
+        *count = k;
+    });
+}
+
+int32_t ffm_kernel_name(int32_t kernel, int32_t variant_a, int32_t variant_b, char *buf, int32_t n) {
+    const std::string s = kernel_name(kernel, variant_a, variant_b);
+    if (s.empty()) return -1;
+    if (buf && n > 0) {
+        const size_t m = std::min((size_t)n - 1, s.size());
+        std::memcpy(buf, s.data(), m);
+        buf[m] = 0;
+    }
+    return (int32_t)s.size();
 }
 
 ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out) {

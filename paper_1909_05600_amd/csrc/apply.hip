@@ -1780,11 +1780,13 @@ void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream
 }
 
 // Record the end of a phase (timing plans only): the first call opens the apply.
-void Plan::mark(int phase, hipStream_t st) {
+void Plan::mark(int phase, hipStream_t st, const Stage *S) {
     if (tev.empty()) return;
     FFM_CHECK(tused < (int)tev.size(), FFM_EINTERNAL, "timing events exhausted");
     FFM_HIP(hipEventRecord(tev[tused], st));
     tphase[tused] = phase;
+    tkern[tused] = S ? make_int4(S->kern, S->a, S->b, S->level) : make_int4(-1, 0, 0, 0);
+    tblocks[tused] = S ? (int64_t)S->ditems.n : 0;
     ++tused;
 }
 
@@ -1803,16 +1805,53 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
     P.hio->dtype = dtype;
     FFM_HIP(hipMemcpyAsync(P.dio.p, P.hio, sizeof(IoEntry), hipMemcpyHostToDevice, st));
     P.mark(-1, st);
-    for (const Stage &S : P.pre) run_stage(S, P.ddesc.p, P.dio.p, st);
-    P.mark(0, st);
+    for (const Stage &S : P.pre) {
+        run_stage(S, P.ddesc.p, P.dio.p, st);
+        P.mark(0, st, &S);
+    }
     for (int l = 1; l <= P.leaf; ++l)
         for (const Stage &S : P.lev[l].stages) {
             run_stage(S, P.ddesc.p, P.dio.p, st);
-            if (S.slot >= 0) P.mark(S.slot, st);
+            P.mark(S.tslot, st, &S);
         }
     for (const Stage &S : P.post) {
         run_stage(S, P.ddesc.p, P.dio.p, st);
-        if (S.slot >= 0) P.mark(S.slot, st);
+        P.mark(S.tslot, st, &S);
+    }
+}
+
+// The symbol of a stage's kernel as profilers print it (see kernel_of for the variants).
+std::string kernel_name(int kern, int a, int b) {
+    auto tf = [](int v) { return std::string(v ? "true" : "false"); };
+    switch (kern) {
+        case K_PERM_IN: return "k_perm_in";
+        case K_AMAX: return a ? "k_zero_amax" : "k_amax";
+        case K_PERM_OUT: return "k_perm_out";
+        case K_FWD_PAIR:
+            if (a == 101) return "k_pw_forward<1, 64, " + tf(b) + ">";
+            return "k_pw_forward<" + std::to_string(a == 4 || a == 2 ? a : 1) + ", 256, " + tf(b) + ">";
+        case K_FWD_RING: return "k_pw_forward_rings<" + std::to_string(a == 4 ? 4 : 2) + ", " + tf(b) + ">";
+        case K_SUM: return "k_sum_segments";
+        case K_TRANSFER:
+            if (a == 101) return "k_pw_transfer<1, 64>";
+            return "k_pw_transfer<" + std::to_string(a == 2 ? 2 : 1) + ", 256>";
+        case K_BWD_PAIR: return "k_pw_backward<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
+        case K_BWD_RING:
+            return a == 2 ? "k_pw_backward_rings<2, 2, " + tf(b) + ">" : "k_pw_backward_rings<1, 4, " + tf(b) + ">";
+        case K_BSUM: return "k_sum_parts";
+        case K_ANTERP: return "k_lag_anterp";
+        case K_MFMA32: return "k_lag_mfma";
+        case K_MFMA16: return "k_lag_mfma16";
+        case K_INTERP: return "k_lag_interp";
+        case K_NEAR: return "k_near<" + tf(b) + ">";
+        case K_ZERO_OUT: return "k_zero_io";
+        case K_GSPREAD: return a == 8 ? "k_grid_spread<8>" : "k_grid_spread<6>";
+        case K_GZ: return "k_grid_z";
+        case K_GPHI: return a >= 1 && a <= 4 ? "k_grid_phi_s<" + std::to_string(a) + ">" : "k_grid_phi";
+        case K_GPHIT: return "k_grid_phit";
+        case K_GZT: return "k_grid_zt";
+        case K_GINTERP: return a == 8 ? "k_grid_interp<8>" : "k_grid_interp<6>";
+        default: return "";
     }
 }
 

@@ -223,7 +223,8 @@ enum Kern {
 
 struct Stage {
     int kern = 0, a = 0, b = 0;       // kernel and its template parameters
-    int slot = -1;                    // timing slot (FFM_TIMING layout)
+    int slot = -1;                    // timing slot (FFM_TIMING layout) closed by this stage, or -1
+    int tslot = -1;                   // timing slot the stage's time belongs to
     int level = 0;                    // level (ordering of target-side stages in batches)
     size_t shmem = 0;                 // dynamic LDS bytes
     std::vector<int4> items;          // work items (host copy, kept for batching)
@@ -341,8 +342,10 @@ struct Plan {
     // optional phase timing (FFM_FLAG_TIMING): events recorded at phase ends
     std::vector<hipEvent_t> tev;
     std::vector<int> tphase;             // phase slot of each recorded event (after the first)
+    std::vector<int4> tkern;             // (kernel, a, b, level) of the launch each event closes
+    std::vector<int64_t> tblocks;        // its thread blocks
     int tused = 0;
-    void mark(int phase, hipStream_t st);
+    void mark(int phase, hipStream_t st, const Stage *S = nullptr);
 };
 
 // ---------------------------------------------------------------- entry points
@@ -358,6 +361,7 @@ struct LevelWork {                     // apply workspace a descriptor points in
 };
 // concurrent blocks per CU of a kernel variant (occupancy) and the device's CU count
 int stage_blocks_per_cu(int kern, int a, int b);
+std::string kernel_name(int kern, int a, int b);
 int device_cus();
 LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w);
 // rebuild the stages and descriptors of a built plan for a tile choice (the plan must be idle)

@@ -452,36 +452,72 @@ k_grid_tables(int nrp, int L, int p, double h, const double2 *rings, const doubl
 
 // Grid coordinates of every source point of a level, in node units (x_a = a for the node at
 // (a - (p-1)/2) h from the box centre), FP32 as the spreading kernels use them, and the z-plane floor(z_g)
-// that orders the points for the spreading launches: count per (box, plane).
-__global__ void __launch_bounds__(kThreads)
-k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *xs, const double *ys, const double *zs,
-              const double *ctr, double inv_h, int p, int32_t *cnt, int32_t *cell_of, float4 *gtmp) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
+// that orders the points for the spreading launches: count per (box, plane).  A block's 256 consecutive points
+// lie in few boxes: their counts are gathered in LDS (bins from the block's first box on, 2 p of them) and
+// added to the global counts once per bin; points beyond those bins count globally.
+constexpr int kZBins = 512;
+
+__device__ __forceinline__ int box_of(int64_t i, const int32_t *start, int nbox) {
     int lo = 0, hi = nbox;   // box b with start[b] <= i < start[b + 1]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (start[mid] <= i) lo = mid;
         else hi = mid;
     }
-    const float half = 0.5f * (float)(p - 1);
-    const float xg = (float)((xs[i] - ctr[3 * lo]) * inv_h) + half;
-    const float yg = (float)((ys[i] - ctr[3 * lo + 1]) * inv_h) + half;
-    const float zg = (float)((zs[i] - ctr[3 * lo + 2]) * inv_h) + half;
-    const int c = min(max((int)floorf(zg), 0), p - 1);
-    const int64_t slot = (int64_t)lo * p + c;
-    cell_of[i] = (int32_t)slot;
-    gtmp[i] = make_float4(xg, yg, zg, 0.f);
-    atomicAdd(&cnt[slot], 1);
+    return lo;
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_grid_zscatter(int64_t n, const int32_t *cell_of, int32_t *cursor, int32_t *perm, const float4 *gtmp, float4 *gxyz) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    const int pos = atomicAdd(&cursor[cell_of[i]], 1);
-    perm[pos] = (int32_t)i;
-    gxyz[pos] = gtmp[i];
+k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *xs, const double *ys, const double *zs,
+              const double *ctr, double inv_h, int p, int32_t *cnt, int32_t *cell_of, float4 *gtmp) {
+    __shared__ int32_t hist[kZBins];
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads, i = i0 + threadIdx.x;
+    for (int k = threadIdx.x; k < kZBins; k += kThreads) hist[k] = 0;
+    const int64_t base = (int64_t)box_of(i0, start, nbox) * p;
+    __syncthreads();
+    if (i < n) {
+        const int b = box_of(i, start, nbox);
+        const float half = 0.5f * (float)(p - 1);
+        const float xg = (float)((xs[i] - ctr[3 * b]) * inv_h) + half;
+        const float yg = (float)((ys[i] - ctr[3 * b + 1]) * inv_h) + half;
+        const float zg = (float)((zs[i] - ctr[3 * b + 2]) * inv_h) + half;
+        const int c = min(max((int)floorf(zg), 0), p - 1);
+        const int64_t slot = (int64_t)b * p + c;
+        cell_of[i] = (int32_t)slot;
+        gtmp[i] = make_float4(xg, yg, zg, 0.f);
+        if (slot - base < kZBins) atomicAdd(&hist[slot - base], 1);
+        else atomicAdd(&cnt[slot], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kZBins; k += kThreads)
+        if (hist[k]) atomicAdd(&cnt[base + k], hist[k]);
+}
+
+// Each point's position in the (box, plane) order: one global cursor addition per bin of the block, then the
+// point's rank within its bin in the block.
+__global__ void __launch_bounds__(kThreads)
+k_grid_zscatter(int64_t n, int p, const int32_t *cell_of, int32_t *cursor, int32_t *perm, const float4 *gtmp,
+                float4 *gxyz) {
+    __shared__ int32_t hist[kZBins], bin0[kZBins];
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads, i = i0 + threadIdx.x;
+    for (int k = threadIdx.x; k < kZBins; k += kThreads) hist[k] = 0;
+    const int64_t base = (int64_t)(cell_of[i0] / p) * p;    // bins from plane 0 of the block's first box
+    __syncthreads();
+    int64_t slot = -1;
+    int rank = 0;
+    if (i < n) {
+        slot = cell_of[i];
+        if (slot >= base && slot - base < kZBins) rank = atomicAdd(&hist[slot - base], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kZBins; k += kThreads)
+        if (hist[k]) bin0[k] = atomicAdd(&cursor[base + k], hist[k]);
+    __syncthreads();
+    if (i < n) {
+        const int pos = (slot >= base && slot - base < kZBins) ? bin0[slot - base] + rank : atomicAdd(&cursor[slot], 1);
+        perm[pos] = (int32_t)i;
+        gxyz[pos] = gtmp[i];
+    }
 }
 
 __global__ void k_copy_i32(const int32_t *a, int32_t *b, int64_t n) {
@@ -1042,7 +1078,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     FFM_LAUNCH(k_copy_i32, nblocks(ncell + 1), kThreads, 0, st, LV.gzs.p, cursor, ncell + 1);
                     LV.gperm.alloc((size_t)std::max<int64_t>(TY.n, 1));
                     LV.gxyz.alloc((size_t)std::max<int64_t>(TY.n, 1));
-                    FFM_LAUNCH(k_grid_zscatter, nblocks(TY.n), kThreads, 0, st, TY.n, cell_of, cursor, LV.gperm.p, gtmp,
+                    FFM_LAUNCH(k_grid_zscatter, nblocks(TY.n), kThreads, 0, st, TY.n, p, cell_of, cursor, LV.gperm.p, gtmp,
                                LV.gxyz.p);
                     const std::vector<double> &tab = phi_hat_table(w, LV.gbeta, dphat_step);
                     dphat = keep(SC, tab, st);
@@ -1204,6 +1240,9 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.prec[l] = LV.fp16 ? 1 : 0;
         s.phase64[l] = LV.method == kGegenbauer && LV.phase64 ? 1 : 0;
         s.bwd_points[l] = LV.pts_tgt;
+        s.grid_nodes[l] = LV.method == kGegenbauer && LV.grid ? LV.gp : 0;
+        s.fwd_boxes[l] = (int64_t)LV.h_fwd.size();
+        s.bwd_boxes[l] = (int64_t)LV.h_tgt.size();
         if (LV.method == kGegenbauer) {
             s.transform_terms += (LV.pts_src + LV.pts_tgt) * (double)LV.nq;
             s.transfer_macs += (double)LV.nfar * (double)LV.nq;
@@ -1425,6 +1464,16 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
         P.post.push_back(make_stage(K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, 61, P.leaf, 0, std::move(nr), st, SC));
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
     }
+    // timing slot of every stage: a stage that closes no phase belongs to the next one that does
+    auto fill = [](std::vector<Stage> &v) {
+        int next = -1;
+        for (int i = (int)v.size() - 1; i >= 0; --i) {
+            if (v[i].slot >= 0) next = v[i].slot;
+            v[i].tslot = next;
+        }
+    };
+    fill(P.post);
+    for (int l = 1; l <= P.leaf; ++l) fill(P.lev[l].stages);
 }
 
 // The descriptor of level l of a plan, over the given instance buffers and level workspace.

@@ -117,3 +117,22 @@ def test_oracle_is_not_linked_into_the_product():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), os.path.join(dirpath, f)
+
+
+def test_kernel_names_and_launch_timing_validation(L):
+    """Launch records name their kernels as profilers print them; bad timing calls are rejected."""
+    import paper_1909_05600_amd as ffm
+    # (kernel id, variants) -> symbol, ids in the library's launch order of kinds
+    assert ffm.kernel_name(0) == "k_perm_in"
+    assert ffm.kernel_name(3, 4, 0) == "k_pw_forward_rings<4, false>"
+    assert ffm.kernel_name(7, 2, 1) == "k_pw_backward_rings<2, 2, true>"
+    assert ffm.kernel_name(12, 0, 1) == "k_near<true>"
+    assert ffm.kernel_name(18, 4, 0) == "k_grid_phi_s<4>"
+    assert ffm.kernel_name(18, 0, 0) == "k_grid_phi"
+    assert ffm.kernel_name(16, 8, 0) == "k_grid_spread<8>"
+    buf = C.create_string_buffer(6)
+    assert L.ffm_kernel_name(18, 4, 0, buf, 6) == len("k_grid_phi_s<4>")
+    assert buf.value == b"k_gri"                       # cut to fit, NUL-terminated
+    assert L.ffm_kernel_name(999, 0, 0, None, 0) == -1
+    n = C.c_int32(0)
+    assert L.ffm_plan_launch_timing(None, None, 0, C.byref(n)) == -1
