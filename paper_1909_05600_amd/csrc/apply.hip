@@ -1080,7 +1080,8 @@ k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 // A = (S_r, -D_i | S_i, D_r), S = conj(Ex) v~(n) + Ex v~(n + L), D = Ex v~(n + L) - conj(Ex) v~(n).  Block: one
 // ring and a 64 x 64 tile of the plane; waves take 16-row blocks of a and all four 16-column blocks of b;
 // azimuths staged through LDS 16 at a time from the transposed tables ([n][node]), step s and lane group g
-// taking azimuth 2 s + g / 2 and part g % 2.  Item (desc, box, ring, tile).
+// taking azimuth 2 s + g / 2 and part g % 2.  The next chunk's table values and v~ are loaded into registers
+// while the current chunk's products run.  Item (desc, box, ring, tile).
 __global__ void __launch_bounds__(kThreads)
 k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
@@ -1091,65 +1092,63 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
     const int a0 = (wk.w / nta) * 64, b0 = (wk.w % nta) * 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
     __shared__ float Ar[32 * kRow64], Ai[32 * kRow64], Bs[32 * kRow64];
-    __shared__ float2 vs[2][16];
     floatx4 acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[i][q] = floatx4{0.f, 0.f, 0.f, 0.f};
     const bool act = a0 + wv * 16 < p;
-    const float2 *vt = reinterpret_cast<const float2 *>(d.vt) + (int64_t)tb * d.npair * 2;
+    const gc2 vt = gl(reinterpret_cast<const float2 *>(d.vt)) + (int64_t)tb * d.npair * 2;
     const int64_t twoL = 2 * (int64_t)L;
-    const float2 *ExT = d.ExT + (int64_t)mt * L * p, *EyT = d.EyT + (int64_t)mt * L * p;
+    const gc2 ExT = gl(d.ExT) + (int64_t)mt * L * p, EyT = gl(d.EyT) + (int64_t)mt * L * p;
+    // v~(m, n) and v~(m, n + L) in the antipodal-pair layout
+    int64_t o1, o2, dn;   // v1 at vt[o1 + dn n], v2 at vt[o2 + dn n]
+    if (2 * m < L) {
+        o1 = (int64_t)m * twoL * 2;
+        o2 = ((int64_t)m * twoL + L) * 2;
+    } else if (2 * m > L) {
+        o1 = ((int64_t)(L - m) * twoL + L) * 2 + 1;
+        o2 = (int64_t)(L - m) * twoL * 2 + 1;
+    } else {
+        o1 = (int64_t)m * twoL * 2;
+        o2 = (int64_t)m * twoL * 2 + 1;
+    }
+    dn = 2;
+    const int x = threadIdx.x % 64, nq = threadIdx.x / 64;
+    v2f exv[4], eyv[4], v1v[4], v2v[4];
+    auto fetch = [&](int n0) {
+        const int cnt = min(16, L - n0);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int nl = nq + 4 * it, n = n0 + nl;
+            const bool ok = nl < cnt;
+            exv[it] = eyv[it] = v1v[it] = v2v[it] = v2f{0.f, 0.f};
+            if (ok && a0 + x < p) {
+                exv[it] = ExT[(int64_t)n * p + a0 + x];
+                v1v[it] = vt[o1 + dn * n];
+                v2v[it] = vt[o2 + dn * n];
+            }
+            if (ok && b0 + x < p) eyv[it] = EyT[(int64_t)n * p + b0 + x];
+        }
+    };
+    fetch(0);
     for (int n0 = 0; n0 < L; n0 += 16) {
         const int cnt = min(16, L - n0);
         __syncthreads();
-        if (threadIdx.x < 16) {
-            const int n = n0 + threadIdx.x;
-            float2 v1 = make_float2(0.f, 0.f), v2 = v1;   // v~(m, n), v~(m, n + L)
-            if ((int)threadIdx.x < cnt) {
-                if (2 * m < L) {
-                    v1 = vt[(m * twoL + n) * 2];
-                    v2 = vt[(m * twoL + n + L) * 2];
-                } else if (2 * m > L) {
-                    const int64_t m2 = L - m;
-                    v1 = vt[(m2 * twoL + n + L) * 2 + 1];
-                    v2 = vt[(m2 * twoL + n) * 2 + 1];
-                } else {
-                    v1 = vt[(m * twoL + n) * 2];
-                    v2 = vt[(m * twoL + n) * 2 + 1];
-                }
-            }
-            vs[0][threadIdx.x] = v1;
-            vs[1][threadIdx.x] = v2;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int nl = nq + 4 * it;
+            const v2f ex = exv[it], v1 = v1v[it], v2 = v2v[it];
+            const float y1r = fmaf(ex.x, v1.x, ex.y * v1.y), y1i = fmaf(ex.x, v1.y, -(ex.y * v1.x));   // conj(ex) v1
+            const float y2r = fmaf(ex.x, v2.x, -(ex.y * v2.y)), y2i = fmaf(ex.x, v2.y, ex.y * v2.x);   // ex v2
+            Ar[(2 * nl) * kRow64 + x] = y1r + y2r;          // S_r
+            Ar[(2 * nl + 1) * kRow64 + x] = y1i - y2i;      // -D_i
+            Ai[(2 * nl) * kRow64 + x] = y1i + y2i;          // S_i
+            Ai[(2 * nl + 1) * kRow64 + x] = y2r - y1r;      // D_r
+            Bs[(2 * nl) * kRow64 + x] = eyv[it].x;
+            Bs[(2 * nl + 1) * kRow64 + x] = eyv[it].y;
         }
-        __syncthreads();
-        for (int k = threadIdx.x; k < 16 * 64; k += kThreads) {
-            const int nl = k / 64, x = k % 64, n = n0 + nl;
-            float sr = 0.f, si = 0.f, dr = 0.f, di = 0.f, er = 0.f, ei = 0.f;
-            if (nl < cnt) {
-                if (a0 + x < p) {
-                    const float2 ex = ExT[(int64_t)n * p + a0 + x], v1 = vs[0][nl], v2 = vs[1][nl];
-                    const float y1r = fmaf(ex.x, v1.x, ex.y * v1.y), y1i = fmaf(ex.x, v1.y, -(ex.y * v1.x));   // conj(ex) v1
-                    const float y2r = fmaf(ex.x, v2.x, -(ex.y * v2.y)), y2i = fmaf(ex.x, v2.y, ex.y * v2.x);   // ex v2
-                    sr = y1r + y2r;
-                    si = y1i + y2i;
-                    dr = y2r - y1r;
-                    di = y2i - y1i;
-                }
-                if (b0 + x < p) {
-                    const float2 e = EyT[(int64_t)n * p + b0 + x];
-                    er = e.x;
-                    ei = e.y;
-                }
-            }
-            Ar[(2 * nl) * kRow64 + x] = sr;
-            Ar[(2 * nl + 1) * kRow64 + x] = -di;
-            Ai[(2 * nl) * kRow64 + x] = si;
-            Ai[(2 * nl + 1) * kRow64 + x] = dr;
-            Bs[(2 * nl) * kRow64 + x] = er;
-            Bs[(2 * nl + 1) * kRow64 + x] = ei;
-        }
+        if (n0 + 16 < L) fetch(n0 + 16);
         __syncthreads();
         if (act) {
             const int steps = (2 * cnt + 3) / 4;
@@ -1169,7 +1168,7 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
         }
     }
     if (!act) return;
-    float2 *Hb = d.H + ((int64_t)m * d.gnbox + tb) * p * p;
+    const gm2 Hb = gw(d.H) + ((int64_t)m * d.gnbox + tb) * p * p;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int b = b0 + q * 16 + li;
@@ -1177,7 +1176,7 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int a = a0 + wv * 16 + 4 * lg + r;
-            if (a < p) Hb[(int64_t)a * p + b] = make_float2(acc[0][q][r], acc[1][q][r]);
+            Hb[(int64_t)a * p + b] = v2f{acc[0][q][r], acc[1][q][r]};
         }
     }
 }
