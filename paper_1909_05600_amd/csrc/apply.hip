@@ -1599,7 +1599,9 @@ k_lag_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 // v_i += sum_{s in near(t)} sum_{j in s, r_ij > 0} G(r_ij) u_j.  One 64-lane block per target box; source
 // points are staged through LDS in FP64 relative to the target centre, and every pair's difference is
 // formed in FP64 and rounded once to FP32, so close pairs keep the full FP32 relative accuracy of r.
-// Item (desc, target box).
+// Targets go through the lanes in passes of at most 64; a pass of nt targets gives each target R = 64 / nt
+// lanes, lane r of a target taking the staged sources r, r + R, ... (the chunk is padded with zero sources to
+// a multiple of R), and the R partial sums of a target are added in order of r.  Item (desc, target box).
 template <bool HELM>
 __global__ void __launch_bounds__(64)
 k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
@@ -1609,13 +1611,21 @@ k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 
     const int lane = threadIdx.x;
     const float k_rev = d.k_rev;
     const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
-    __shared__ double spx[64], spy[64], spz[64];   // sources relative to c_t
-    __shared__ float2 su[64];                      // u / (4 pi)
+    __shared__ double spx[128], spy[128], spz[128];   // sources relative to c_t, zero-padded past the chunk
+    __shared__ float2 su[128];                         // u / (4 pi), zero past the chunk
+    __shared__ float2 part[64];
     const float inv4pi = (float)(1.0 / (4.0 * M_PI));
     const int64_t e0 = d.near_ptr[t], e1 = d.near_ptr[t + 1];
-    for (int i0 = d.tstart[t]; i0 < d.tstart[t + 1]; i0 += 64) {
-        const int i = i0 + lane;
-        const bool valid = i < d.tstart[t + 1];
+    const int ta = d.tstart[t], tz = d.tstart[t + 1];
+    for (int k = lane; k < 128; k += 64) {
+        spx[k] = spy[k] = spz[k] = 0.0;
+        su[k] = make_float2(0.f, 0.f);
+    }
+    for (int i0 = ta; i0 < tz; i0 += 64) {
+        const int nt = min(64, tz - i0), R = 64 / nt;
+        const int r = lane / nt, ti = lane - r * nt;
+        const bool valid = r < R;
+        const int i = i0 + ti;
         double x = 0.0, y = 0.0, z = 0.0;
         if (valid) {
             x = d.txs[i] - cx;
@@ -1623,44 +1633,65 @@ k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 
             z = d.tzs[i] - cz;
         }
         float are = 0.f, aim = 0.f;
+        auto pair = [&](int jj) {
+            const float dx = (float)(x - spx[jj]), dy = (float)(y - spy[jj]), dz = (float)(z - spz[jj]);
+            const float2 uu = su[jj];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+            if (HELM) {
+                const float ph = r2 * inv * k_rev;
+                float sn, cs;
+                sincos_rev(__builtin_amdgcn_fractf(ph), sn, cs);
+                const float gr = cs * inv, gi = sn * inv;
+                are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
+                aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
+            } else {
+                are = fmaf(inv, uu.x, are);
+                aim = fmaf(inv, uu.y, aim);
+            }
+        };
         for (int64_t e = e0; e < e1; ++e) {
-            const int s = d.near_src[e];
-            const int j0 = d.sstart[s], j1 = d.sstart[s + 1];
+            const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
+            const int j0 = __builtin_amdgcn_readfirstlane(d.sstart[s]), j1 = __builtin_amdgcn_readfirstlane(d.sstart[s + 1]);
             for (int c0 = j0; c0 < j1; c0 += 64) {
-                const int cnt = min(64, j1 - c0);
+                const int cnt = min(64, j1 - c0), steps = (cnt + R - 1) / R;
                 __syncthreads();
-                if (lane < cnt) {
+                {
                     const int j = c0 + lane;
-                    spx[lane] = d.sxs[j] - cx;
-                    spy[lane] = d.sys[j] - cy;
-                    spz[lane] = d.szs[j] - cz;
-                    const float2 uu = d.u[j];
-                    su[lane] = make_float2(uu.x * inv4pi, uu.y * inv4pi);
-                }
-                __syncthreads();
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const float dx = (float)(x - spx[jj]), dy = (float)(y - spy[jj]), dz = (float)(z - spz[jj]);
-                    const float2 uu = su[jj];
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                    if (HELM) {
-                        const float ph = r2 * inv * k_rev;
-                        float sn, cs;
-                        sincos_rev(__builtin_amdgcn_fractf(ph), sn, cs);
-                        const float gr = cs * inv, gi = sn * inv;
-                        are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
-                        aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
+                    if (lane < cnt) {
+                        spx[lane] = d.sxs[j] - cx;
+                        spy[lane] = d.sys[j] - cy;
+                        spz[lane] = d.szs[j] - cz;
+                        const float2 uu = d.u[j];
+                        su[lane] = make_float2(uu.x * inv4pi, uu.y * inv4pi);
                     } else {
-                        are = fmaf(inv, uu.x, are);
-                        aim = fmaf(inv, uu.y, aim);
+                        su[lane] = make_float2(0.f, 0.f);    // padding: zero sources
                     }
                 }
+                __syncthreads();
+                // lane r of a target: sources r + R q, q < steps (entries past cnt are zero sources)
+                int q = 0;
+                for (; q + 4 <= steps; q += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) pair(r + R * (q + u));
+                }
+                for (; q < steps; ++q) pair(r + R * q);
             }
         }
-        if (valid) {
+        // the R partial sums of each target, added in order of r
+        __syncthreads();
+        part[lane] = make_float2(are, aim);
+        __syncthreads();
+        if (lane < nt) {
+            float2 a = part[lane];
+            for (int rr = 1; rr < R; ++rr) {
+                const float2 b = part[lane + rr * nt];
+                a.x += b.x;
+                a.y += b.y;
+            }
             float2 o = d.v[i];
-            o.x += are;
-            o.y += aim;
+            o.x += a.x;
+            o.y += a.y;
             d.v[i] = o;
         }
     }
