@@ -118,6 +118,13 @@ struct Scratch {
         bufs.emplace_back(count * sizeof(T));
         return reinterpret_cast<T *>(bufs.back().p);
     }
+    // pinned host memory for device-to-host copies, valid until the scratch list is released
+    template <class T>
+    T *pin(size_t count) {
+        void *p = pinned_alloc(std::max<size_t>(count * sizeof(T), 1));
+        pinned.push_back(p);
+        return static_cast<T *>(p);
+    }
     // copy host data into pinned staging memory that stays valid until the scratch list is released
     template <class T>
     const T *stage(const std::vector<T> &h) {

@@ -365,12 +365,12 @@ k_fill_groups(const int32_t *cls, int64_t n, const int32_t *gstart, int32_t *cur
 // coef_p = (2p + 1) i^p h_p(k |r0|) / (4 pi).  P_p(-t) = (-1)^p P_p(t) gives the antipode.
 __global__ void __launch_bounds__(kThreads)
 k_gegen_D(int64_t npair, int L, const double *dirs /*[npair][3] unit*/, const double *wts, const double *rhat,
-          const double2 *coef /*[ncls][L+1]*/, double k, float4 *D, const double *phat, int nphat, double dphat,
-          double kh) {
+          const double2 *coef /*[ncls][L+1]*/, const int32_t *reps /*[2 nrep]: class, mirror class or -1*/,
+          double k, float4 *D, const double *phat, int nphat, double dphat, double kh) {
     extern __shared__ double2 sm[];
     double2 *sc = sm;               // series coefficients of this class
     double2 *rc = sm + (L + 1);     // Bonnet recurrence: P_{p+1} = a_p t P_p - b_p P_{p-1}
-    const int c = blockIdx.y;
+    const int c = reps[2 * blockIdx.y], cm = reps[2 * blockIdx.y + 1];
     for (int p = threadIdx.x; p <= L; p += blockDim.x) {
         sc[p] = coef[(int64_t)c * (L + 1) + p];
         rc[p] = make_double2((2.0 * p + 1.0) / (p + 1.0), p / (p + 1.0));
@@ -412,8 +412,34 @@ k_gegen_D(int64_t npair, int L, const double *dirs /*[npair][3] unit*/, const do
         }
         f /= Phi * Phi;
     }
-    D[(int64_t)c * npair + q] = make_float4((float)(-f * (ei + oi)), (float)(f * (er + orr)),
-                                            (float)(-f * (ei - oi)), (float)(f * (er - orr)));
+    const float4 dq = make_float4((float)(-f * (ei + oi)), (float)(f * (er + orr)), (float)(-f * (ei - oi)),
+                                  (float)(f * (er - orr)));
+    D[(int64_t)c * npair + q] = dq;
+    // the mirror translation -r0 (same norm, so the same series) sees every direction pair reversed
+    if (cm >= 0) D[(int64_t)cm * npair + q] = make_float4(dq.z, dq.w, dq.x, dq.y);
+}
+
+// Quadrature directions of a Gegenbauer level in antipodal-pair order (ring pairs m < (L+1)/2 with all 2L
+// azimuths, then the equator ring with L azimuths when L + 1 is odd) and their weights w_m pi / L: unit
+// vectors in FP64, and scaled by k / 2pi in FP64 and FP32 for the transform kernels.
+__global__ void __launch_bounds__(kThreads)
+k_quad_dirs(int64_t npair, int L, const double *xm, const double *wm, double kr, double *unit, double *wts,
+            double *dirs64, float4 *dirs32) {
+    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= npair) return;
+    const int64_t full = (int64_t)((L + 1) / 2) * 2 * L;
+    const int m = q < full ? (int)(q / (2 * L)) : (L + 1) / 2;
+    const int n = q < full ? (int)(q % (2 * L)) : (int)(q - full);
+    const double ct = xm[m], stt = sqrt(1.0 - ct * ct);
+    double sp, cp;
+    sincospi((double)n / (double)L, &sp, &cp);
+    const double u[3] = {stt * cp, stt * sp, ct};
+    for (int d = 0; d < 3; ++d) {
+        unit[3 * q + d] = u[d];
+        dirs64[3 * q + d] = u[d] * kr;
+    }
+    wts[q] = wm[m] * M_PI / L;
+    dirs32[q] = make_float4((float)(u[0] * kr), (float)(u[1] * kr), (float)(u[2] * kr), 0.f);
 }
 
 // ------------------------------------------------------------------ grid form tables
@@ -702,31 +728,57 @@ void build_level(Tree &T, LevelScratch &S, int l, double d0, hipStream_t st) {
 
 // Work lists of a level, built on the host from the box sizes and list pointers: largest boxes
 // first so that the longest blocks start early.
-void build_work_lists(Plan &P, Level &LV, const TreeLevel &LX, const TreeLevel &LY, bool near, hipStream_t st,
-                      Scratch &SC) {
-    std::vector<int32_t> sx(LX.nbox + 1), sy(LY.nbox + 1);
-    FFM_HIP(hipMemcpyAsync(sx.data(), LX.start.p, sizeof(int32_t) * sx.size(), hipMemcpyDeviceToHost, st));
-    FFM_HIP(hipMemcpyAsync(sy.data(), LY.start.p, sizeof(int32_t) * sy.size(), hipMemcpyDeviceToHost, st));
-    std::vector<int64_t> ptr(LX.nbox + 1);
+// What the work lists of a level need on the host (box ranges, the far or near pointer array, the marks of
+// the source boxes with far work, the near pair count), copied into pinned memory in stream order, so that the
+// lists of every level are read after one synchronisation.
+struct WorkFetch {
+    int32_t *sx = nullptr, *sy = nullptr;
+    int64_t *ptr = nullptr;
+    uint8_t *act = nullptr;
+    unsigned long long *near_pairs = nullptr;
+    int nbx = 0, nby = 0;
+};
+
+void fetch_work_lists(Level &LV, const TreeLevel &LX, const TreeLevel &LY, bool near, hipStream_t st, Scratch &SC,
+                      WorkFetch &F) {
+    F.nbx = LX.nbox;
+    F.nby = LY.nbox;
+    F.sx = SC.pin<int32_t>(LX.nbox + 1);
+    F.sy = SC.pin<int32_t>(LY.nbox + 1);
+    F.ptr = SC.pin<int64_t>(LX.nbox + 1);
+    FFM_HIP(hipMemcpyAsync(F.sx, LX.start.p, sizeof(int32_t) * (LX.nbox + 1), hipMemcpyDeviceToHost, st));
+    FFM_HIP(hipMemcpyAsync(F.sy, LY.start.p, sizeof(int32_t) * (LY.nbox + 1), hipMemcpyDeviceToHost, st));
     const DevBuf<int64_t> &dptr = near ? LV.near_ptr : LV.far_ptr;
-    FFM_HIP(hipMemcpyAsync(ptr.data(), dptr.p, sizeof(int64_t) * ptr.size(), hipMemcpyDeviceToHost, st));
-    std::vector<uint8_t> act;
-    unsigned long long near_pairs = 0;
-    if (near && LV.nnear) {
-        unsigned long long *dn = SC.get<unsigned long long>(1);
-        FFM_HIP(hipMemsetAsync(dn, 0, sizeof(unsigned long long), st));
-        FFM_LAUNCH(k_near_pairs, nblocks(LX.nbox), kThreads, 0, st, LV.near_ptr.p, LV.near_src.p, LX.nbox, LX.start.p,
-                   LY.start.p, dn);
-        FFM_HIP(hipMemcpyAsync(&near_pairs, dn, sizeof(near_pairs), hipMemcpyDeviceToHost, st));
+    FFM_HIP(hipMemcpyAsync(F.ptr, dptr.p, sizeof(int64_t) * (LX.nbox + 1), hipMemcpyDeviceToHost, st));
+    if (near) {
+        F.near_pairs = SC.pin<unsigned long long>(1);
+        *F.near_pairs = 0;
+        if (LV.nnear) {
+            unsigned long long *dn = SC.get<unsigned long long>(1);
+            FFM_HIP(hipMemsetAsync(dn, 0, sizeof(unsigned long long), st));
+            FFM_LAUNCH(k_near_pairs, nblocks(LX.nbox), kThreads, 0, st, LV.near_ptr.p, LV.near_src.p, LX.nbox,
+                       LX.start.p, LY.start.p, dn);
+            FFM_HIP(hipMemcpyAsync(F.near_pairs, dn, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        }
+    } else {
+        uint8_t *dact = SC.get<uint8_t>(std::max(LY.nbox, 1));
+        FFM_HIP(hipMemsetAsync(dact, 0, LY.nbox, st));
+        FFM_LAUNCH(k_mark_sources, nblocks(LV.nfar), kThreads, 0, st, LV.far_src.p, LV.nfar, dact);
+        F.act = SC.pin<uint8_t>(LY.nbox);
+        FFM_HIP(hipMemcpyAsync(F.act, dact, LY.nbox, hipMemcpyDeviceToHost, st));
     }
-    if (!near) {
-        DevBuf<uint8_t> dact(LY.nbox);
-        FFM_HIP(hipMemsetAsync(dact.p, 0, LY.nbox, st));
-        FFM_LAUNCH(k_mark_sources, nblocks(LV.nfar), kThreads, 0, st, LV.far_src.p, LV.nfar, dact.p);
-        act.resize(LY.nbox);
-        FFM_HIP(hipMemcpyAsync(act.data(), dact.p, LY.nbox, hipMemcpyDeviceToHost, st));
-    }
-    FFM_HIP(hipStreamSynchronize(st));
+}
+
+// The work lists of a level from its fetched data (after the stream has passed the fetch): boxes with work,
+// largest first, and their point counts.
+void build_work_lists(Plan &P, Level &LV, bool near, const WorkFetch &F) {
+    std::vector<int32_t> sx(F.sx, F.sx + F.nbx + 1), sy(F.sy, F.sy + F.nby + 1);
+    const int64_t *ptr = F.ptr;
+    const uint8_t *act = F.act;
+    const unsigned long long near_pairs = F.near_pairs ? *F.near_pairs : 0ull;
+    struct {
+        int32_t nbox;
+    } LX{F.nbx}, LY{F.nby};
     // boxes by decreasing point count, ties in index order (counting sort over the counts)
     auto by_size = [](const std::vector<int32_t> &start, std::vector<int32_t> &boxes) {
         if (boxes.size() < 2) return;
@@ -950,6 +1002,13 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     }
 
     plog.mark("lists");
+    // the host side of every level's work lists, after one synchronisation
+    std::vector<WorkFetch> wf(P.leaf + 1);
+    WorkFetch wf_near;
+    for (int l = 1; l <= P.leaf; ++l)
+        if (P.lev[l].nfar) fetch_work_lists(P.lev[l], TX.lev[l], TY.lev[l], false, st, SC, wf[l]);
+    fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near);
+    FFM_HIP(hipStreamSynchronize(st));
     // --- compression form and tables per level (Sec. 2.2.2, 2.2.3)
     size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0, ws_gG = 0, ws_gH = 0;
     for (int l = 1; l <= P.leaf; ++l) {
@@ -968,42 +1027,26 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             LV.L = gegenbauer_L(P.k, dl, P.eps);
             FFM_CHECK(LV.L <= 1000, FFM_EINVAL, "ffm_plan: k * d_0 too large (Gegenbauer rank above 1000)");
         }
-        build_work_lists(P, LV, TX.lev[l], TY.lev[l], false, st, SC);
+        build_work_lists(P, LV, false, wf[l]);
         plog.mark("tab.work");
         if (geg) {
-            const int L = LV.L, nth = L + 1, nph = 2 * L;
+            const int L = LV.L, nth = L + 1;
             LV.nq = 2 * (int64_t)L * (L + 1);
             LV.npair = LV.nq / 2;
             std::vector<double> xm, wm;
             gauss_legendre_host(nth, xm, wm);
-            std::vector<double> dirs, wts, cph(2 * L), sph(2 * L);
-            dirs.reserve(3 * LV.npair);
-            wts.reserve(LV.npair);
-            for (int n = 0; n < 2 * L; ++n) {
+            std::vector<double> cph(L), sph(L);
+            for (int n = 0; n < L; ++n) {
                 cph[n] = std::cos(M_PI * n / L);
                 sph[n] = std::sin(M_PI * n / L);
             }
-            auto add = [&](int m, int n) {
-                const double ct = xm[m], stt = std::sqrt(1.0 - ct * ct);
-                dirs.push_back(stt * cph[n]);
-                dirs.push_back(stt * sph[n]);
-                dirs.push_back(ct);
-                wts.push_back(wm[m] * M_PI / L);
-            };
-            for (int m = 0; m < nth / 2; ++m)
-                for (int n = 0; n < nph; ++n) add(m, n);
-            if (nth & 1)
-                for (int n = 0; n < L; ++n) add(nth / 2, n);
-            FFM_CHECK((int64_t)wts.size() == LV.npair, FFM_EINTERNAL, "quadrature pair count");
             const double kr = P.k / (2.0 * M_PI);
-            std::vector<float4> dirs32(LV.npair);
-            std::vector<double> dirs64(3 * LV.npair);
-            for (int64_t q = 0; q < LV.npair; ++q) {
-                for (int d = 0; d < 3; ++d) dirs64[3 * q + d] = dirs[3 * q + d] * kr;
-                dirs32[q] = make_float4((float)dirs64[3 * q], (float)dirs64[3 * q + 1], (float)dirs64[3 * q + 2], 0.f);
-            }
-            upload(LV.dirs, dirs32, st, SC);
-            upload(LV.dirs64, dirs64, st, SC);
+            const double *dxm = keep(SC, xm, st), *dwm = keep(SC, wm, st);
+            double *ddirs = SC.get<double>(3 * LV.npair), *dwts = SC.get<double>(LV.npair);
+            LV.dirs.alloc((size_t)LV.npair);
+            LV.dirs64.alloc((size_t)3 * LV.npair);
+            FFM_LAUNCH(k_quad_dirs, nblocks(LV.npair), kThreads, 0, st, LV.npair, L, dxm, dwm, kr, ddirs, dwts,
+                       LV.dirs64.p, LV.dirs.p);
             // ring-pair tables: (sin, cos) of every ring pair's polar angle, scaled by k / 2pi, and the
             // azimuths of one half turn
             LV.nrp = nth / 2 + (nth & 1);
@@ -1013,6 +1056,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             for (int n = 0; n < L; ++n) phis[n] = make_double2(cph[n], sph[n]);
             upload(LV.rings, rings, st, SC);
             upload(LV.phis, phis, st, SC);
+            plog.mark("tab.quad");
             // FP64 phase reduction where the FP32 rounding of the largest phase (a few ulp of
             // k sqrt(3) d_l / 2 radians) would reach eps / 20; the per-(point, ring) factor e^{iC} of
             // the ring-pair form is always reduced in FP64
@@ -1087,6 +1131,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     ws_gH = std::max(ws_gH, gnb * (size_t)(L + 1) * p * p);
                 }
             }
+            plog.mark("tab.grid");
             // per-class series coefficients (host FP64), unit directions r0/|r0|
             std::vector<double> rhat(3 * (size_t)LV.ncls);
             std::vector<double2> coef((size_t)LV.ncls * (L + 1));
@@ -1114,12 +1159,35 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 }
             }
             plog.mark("tab.host");
-            const double *ddirs = keep(SC, dirs, st), *dwts = keep(SC, wts, st), *drhat = keep(SC, rhat, st);
+            // classes evaluated: one of each pair of opposite translations (the other is written alongside)
+            std::vector<int32_t> reps;
+            {
+                std::map<std::tuple<int, int, int>, int> by_off;
+                for (int c = 0; c < LV.ncls; ++c)
+                    by_off[std::make_tuple(LV.cls_off[3 * c], LV.cls_off[3 * c + 1], LV.cls_off[3 * c + 2])] = c;
+                std::vector<char> done(LV.ncls, 0);
+                for (int c = 0; c < LV.ncls; ++c) {
+                    if (done[c]) continue;
+                    int cm = -1;
+                    bool opposite = true;   // r0(cm) = -r0(c) exactly
+                    auto it = by_off.find(std::make_tuple(-LV.cls_off[3 * c], -LV.cls_off[3 * c + 1], -LV.cls_off[3 * c + 2]));
+                    if (it != by_off.end() && it->second != c) {
+                        for (int d = 0; d < 3; ++d) opposite = opposite && r0[3 * it->second + d] == -r0[3 * c + d];
+                        if (opposite) cm = it->second;
+                    }
+                    reps.push_back(c);
+                    reps.push_back(cm);
+                    done[c] = 1;
+                    if (cm >= 0) done[cm] = 1;
+                }
+            }
+            const double *drhat = keep(SC, rhat, st);
             const double2 *dcoef = keep(SC, coef, st);
+            const int32_t *dreps = keep(SC, reps, st);
             LV.D.alloc((size_t)LV.ncls * LV.npair);
-            dim3 grid((unsigned)nblocks(LV.npair), (unsigned)LV.ncls);
+            dim3 grid((unsigned)nblocks(LV.npair), (unsigned)(reps.size() / 2));
             hipLaunchKernelGGL(k_gegen_D, grid, dim3(kThreads), 2 * sizeof(double2) * (L + 1), st, LV.npair, L, ddirs,
-                               dwts, drhat, dcoef, P.k, LV.D.p, dphat, nphat, dphat_step, LV.gh);
+                               dwts, drhat, dcoef, dreps, P.k, LV.D.p, dphat, nphat, dphat_step, LV.gh);
             FFM_HIP(hipGetLastError());
             plog.mark("tab.D");
             ws_src = std::max(ws_src, (size_t)nby * LV.npair);
@@ -1191,7 +1259,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         }
     }
     plog.mark("tables");
-    build_work_lists(P, P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC);
+    build_work_lists(P, P.lev[P.leaf], true, wf_near);
     (void)ws_part;
     P.ws_src = ws_src;
     P.ws_tgt = ws_tgt;
