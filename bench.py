@@ -341,8 +341,9 @@ def launch_work(name, level, st):
         return (2.0 * NEAR_SLOTS[name] * st["near_pairs"], "alu",
                 "non-transcendental VALU issue slots x 2 per (target, source) pair of the near field")
     if name.startswith("k_pw_transfer"):
-        return (16.0 * st["nfar"][level] * nq + 8.0 * nbt * nq, "hbm",
-                "bytes: u~(q) and D(q) (8 + 8) per (far pair, direction), v~(q) (8) per (target box, direction)")
+        return (8.0 * nq * (nbf + st["nclass"][level] + nbt), "hbm",
+                "unique bytes: u~ of every source box, the class tables D and v~ of every target box, 8 per "
+                "direction each (the far-pair gathers re-read them from the caches)")
     return None
 
 

@@ -191,11 +191,42 @@ k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     float4 acc[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int64_t e0 = d.far_ptr[t], e1 = d.far_ptr[t + 1];
+    const int e0 = __builtin_amdgcn_readfirstlane((int)d.far_ptr[t]);
+    const int e1 = __builtin_amdgcn_readfirstlane((int)d.far_ptr[t + 1]);
     const float4 *__restrict__ D = d.D;
     const float4 *__restrict__ ut = d.ut;
-    for (int64_t e = e0; e < e1; ++e) {
-        const int64_t s = d.far_src[e], c = d.far_cls[e];
+    // four far pairs per step, their loads issued together
+    constexpr int U = 4;
+    int e = e0;
+    for (; e + U <= e1; e += U) {
+        int64_t sv[U], cv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            sv[k] = __builtin_amdgcn_readfirstlane(d.far_src[e + k]);
+            cv[k] = __builtin_amdgcn_readfirstlane(d.far_cls[e + k]);
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int64_t p = p0 + (int64_t)j * BS;
+            if (p < npair) {
+                float4 q[U], w[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    q[k] = D[cv[k] * npair + p];
+                    w[k] = ut[sv[k] * npair + p];
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    acc[j].x = fmaf(q[k].x, w[k].x, fmaf(-q[k].y, w[k].y, acc[j].x));
+                    acc[j].y = fmaf(q[k].x, w[k].y, fmaf(q[k].y, w[k].x, acc[j].y));
+                    acc[j].z = fmaf(q[k].z, w[k].z, fmaf(-q[k].w, w[k].w, acc[j].z));
+                    acc[j].w = fmaf(q[k].z, w[k].w, fmaf(q[k].w, w[k].z, acc[j].w));
+                }
+            }
+        }
+    }
+    for (; e < e1; ++e) {
+        const int64_t s = __builtin_amdgcn_readfirstlane(d.far_src[e]), c = __builtin_amdgcn_readfirstlane(d.far_cls[e]);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int64_t p = p0 + (int64_t)j * BS;

@@ -1338,6 +1338,27 @@ Stage make_stage(int kern, int a, int b, int slot, int level, size_t shmem, std:
 }
 }  // namespace
 
+// Transfer work items, tile-major (the blocks running together share a tile of the class tables D).  Within a
+// tile the target boxes go in Morton order, cut into 8 contiguous ranges interleaved so that block b takes
+// range b mod 8: workgroups are dealt to the 8 XCDs of the chip in turn, so each XCD works through one
+// contiguous region, and neighbouring targets, which share most of their far sources, find u~ in that XCD's L2.
+static std::vector<int4> transfer_items(int l, const std::vector<int32_t> &tgt_by_size, int64_t ntiles) {
+    std::vector<int32_t> tg(tgt_by_size);
+    std::sort(tg.begin(), tg.end());
+    const int64_t n = (int64_t)tg.size();
+    constexpr int kXcd = 8;
+    const int64_t per = (n + kXcd - 1) / kXcd;
+    std::vector<int4> it;
+    it.reserve((size_t)(n * ntiles));
+    for (int64_t q = 0; q < ntiles; ++q)
+        for (int64_t k = 0; k < per; ++k)
+            for (int x = 0; x < kXcd; ++x) {
+                const int64_t i = x * per + k;
+                if (i < n) it.push_back(make_int4(l, tg[(size_t)i], (int)q, 0));
+            }
+    return it;
+}
+
 // Parts s to split `blocks` equal blocks into, given `conc` blocks that run at once: the launch then runs
 // in about blocks * s / conc rounds, and blocks of the last, partly filled round run with the chip partly
 // idle.  Take the smallest s (up to smax, at most `cap`) that gives at least 8 rounds or a last round at
@@ -1432,8 +1453,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             int bs, ppt;
             pick_pair_tile(LV.npair, 2, bs, ppt);
             const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
-            for (int64_t q = 0; q < nt; ++q)
-                for (int32_t t : LV.h_tgt) tr.push_back(make_int4(l, t, (int)q, 0));
+            tr = transfer_items(l, LV.h_tgt, nt);
             LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
             for (int32_t t : LV.h_tgt) {
                 for (int m = 0; m <= L; ++m)
@@ -1485,9 +1505,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             pick_pair_tile(LV.npair, 2, bs, ppt);
             const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
             std::vector<int4> tr, bw;
-            // tile-major: the blocks running together share the tile of the class tables D
-            for (int64_t q = 0; q < nt; ++q)
-                for (int32_t t : LV.h_tgt) tr.push_back(make_int4(l, t, (int)q, 0));
+            tr = transfer_items(l, LV.h_tgt, nt);
             LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
             // direction-pair target transform: 64-point blocks where target boxes are small
             const bool small = !LV.qG && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
