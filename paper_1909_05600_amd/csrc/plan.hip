@@ -1439,13 +1439,21 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             grid_z_groups(LV.nrp, zng, zper);
             zng = ((LV.nrp + 15) / 16 + zper - 1) / zper;
             std::vector<int4> a1, a2, a3, tr, b1, b2, b3;
+            // the plane sums go ring by ring, rings m and L - m (which share their tables) together, so that
+            // the blocks running at once read the same few tables
+            std::vector<int> ring_order;
+            for (int mt = 0; mt < LV.nrp; ++mt) {
+                ring_order.push_back(mt);
+                if (L - mt != mt) ring_order.push_back(L - mt);
+            }
             for (int32_t b : LV.h_fwd) {
                 for (int c = 0; c < p; ++c)
                     for (int t = 0; t < nta * nta; ++t) a1.push_back(make_int4(l, b, c, t));
                 for (int t = 0; t < ncol; ++t)
                     for (int g = 0; g < zng; ++g) a2.push_back(make_int4(l, b, t, g));
-                for (int m = 0; m <= L; ++m) a3.push_back(make_int4(l, b, m, 0));
             }
+            for (int m : ring_order)
+                for (int32_t b : LV.h_fwd) a3.push_back(make_int4(l, b, m, 0));
             LV.stages.push_back(make_stage(K_GSPREAD, LV.gw, 0, -1, l, 2 * sizeof(uint64_t) * std::min(p, 64) * std::min(p, 64),
                                            std::move(a1), st, SC));
             LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
@@ -1455,9 +1463,10 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
             tr = transfer_items(l, LV.h_tgt, nt);
             LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
-            for (int32_t t : LV.h_tgt) {
-                for (int m = 0; m <= L; ++m)
+            for (int m : ring_order)
+                for (int32_t t : LV.h_tgt)
                     for (int q = 0; q < nta * nta; ++q) b1.push_back(make_int4(l, t, m, q));
+            for (int32_t t : LV.h_tgt) {
                 for (int q = 0; q < ncol; ++q)
                     for (int cc = 0; cc < nta; ++cc) b2.push_back(make_int4(l, t, q, cc));
                 for (int32_t i = sx[t]; i < sx[t + 1]; i += kThreads) b3.push_back(make_int4(l, t, i, 0));
