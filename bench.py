@@ -40,12 +40,12 @@ NEAR_SLOTS = {"k_near<false>": 10.0, "k_near<true>": 18.0}
 PEAKS = {"mfma": (157.3, "TFLOP/s"), "alu": (PEAK_ALU_TFLOPS, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
 
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
-# workload (profiles/traffic_pw_rings_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
-# kernel of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel source they were taken on.
-TRAFFIC_SOURCE_HASH = "d75c13247fdb8a34"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
+# workload (profiles/traffic_grid_phit_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
+# kernel of known size (FETCH x 2.0, WRITE x 1.0), mean over the kernel's launches in one product.  Valid only
+# for the kernel source it was taken on.
+TRAFFIC_SOURCE_HASH = "f44c740cd0384124"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
 TRAFFIC = {
-    "k_pw_forward_rings<4, false>": ((16954.0 + 67948.0) / 2 * 2.0 + (189422.0 + 217487.0) / 2) * 1024.0,
-    "k_pw_backward_rings<2, 2, false>": ((195245.0 + 199058.0 + 85082.0) / 3 * 2.0 + (65938.0 + 65954.0 + 24773.0) / 3) * 1024.0,
+    "k_grid_phit": ((67390.8125 * 2.0 + 295680.0) + (28041.8125 * 2.0 + 421056.0)) / 2 * 1024.0,
 }
 
 
