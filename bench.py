@@ -499,6 +499,7 @@ def main():
     if not args.no_batched:
         print("bench: batched workload", file=sys.stderr, flush=True)
         res["batched"] = batched()
+        torch.cuda.empty_cache()
     if not args.no_serving:
         print("bench: serving workload", file=sys.stderr, flush=True)
         res["serving"] = serving(args.serving_matvecs, [float(x) for x in args.serving_loads.split(",")],

@@ -136,6 +136,11 @@ void pinned_free(void *p) {
 
 size_t dev_bytes_live() { return (size_t)std::max<long long>(0, g_live_bytes.load()); }
 
+size_t dev_bytes_cached() {
+    std::lock_guard<std::mutex> lk(g_mx);
+    return g_cached;
+}
+
 }  // namespace ffm
 
 using namespace ffm;

@@ -68,6 +68,7 @@ struct Guard {
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
 size_t dev_bytes_live();
+size_t dev_bytes_cached();   // freed device blocks the library keeps for reuse
 // Pinned host staging memory (cached like device memory) for asynchronous uploads.
 void *pinned_alloc(size_t bytes);
 void pinned_free(void *p);

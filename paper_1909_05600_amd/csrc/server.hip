@@ -267,7 +267,9 @@ ffm_status_t ffm_server_create(const ffm_server_options_t *opts, ffm_server_t *o
         } else {
             size_t fr = 0, tot = 0;
             FFM_HIP(hipMemGetInfo(&fr, &tot));
-            S.budget = fr / 10 * 8;      // 80% of the free device memory
+            // 80% of the free device memory, counting the blocks the library has cached for reuse (the
+            // workspaces are carved from them first, and the cache is released when the device runs out)
+            S.budget = (fr + dev_bytes_cached()) / 10 * 8;
         }
         S.slot_req.assign(S.nslots, nullptr);
         for (int i = 0; i < S.nslots; ++i) {
