@@ -19,13 +19,16 @@ pytestmark = pytest.mark.gpu
 
 def _mixed_instances():
     """A small mix of every kind of level and kernel variant: cfg4-like instances (sphere, ellipsoid, cube;
-    Laplace and Helmholtz), a Helmholtz sphere with ring-pair levels (L >= 64), a mixed-precision Laplace
+    Laplace and Helmholtz), a Helmholtz sphere with ring-pair levels (L >= 64), one with grid-form levels
+    (spreading, MFMA plane sums, interpolation), a mixed-precision Laplace
     plan (FP16 MFMA transfers), distinct source and target sets, and plans without sources or targets."""
     import torch
     ws = W.batched_instances(9, seed=4, n_min=2000, n_max=30000)
     specs = [(w.X, w.X, w.kernel, w.k, w.eps, {}, w.wu) for w in ws]
     h = W.helmholtz_sphere(40000, seed=7, k=100.0)
     specs.append((h.X, h.X, 1, h.k, h.eps, {}, h.wu))
+    g = W.helmholtz_sphere(30000, seed=10, k=60.0)
+    specs.append((g.X, g.X, 1, g.k, g.eps, {"transforms": "grid"}, g.wu))   # grid-form levels
     l = W.laplace_sphere(20000, seed=8)
     specs.append((l.X, l.X, 0, 0.0, l.eps, {"precision": 1}, l.wu.astype(np.complex64)))
     rng = np.random.default_rng(9)
@@ -90,7 +93,7 @@ def test_batch_matches_oracle(orc):
     b = ffm.Batch(plans, graph=True)
     outs = b.apply(wus)
     torch.cuda.synchronize()
-    for i in (0, 1, 2, 9):
+    for i in (0, 1, 2, 9, 10):          # 10: grid-form levels
         X, Y, kern, k, eps, kw, w = specs[i]
         op = orc.Plan(X, X if Y is X else Y, kern, k, eps)
         vo = op.apply(w)

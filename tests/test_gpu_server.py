@@ -23,6 +23,8 @@ def _plans():
         specs.append((w.X, w.kernel, w.k, w.eps, {}, w.wu))
     l = W.laplace_sphere(20000, seed=8)
     specs.append((l.X, 0, 0.0, 1e-4, {"precision": 1}, l.wu.astype(np.complex64)))
+    g = W.helmholtz_sphere(30000, seed=10, k=60.0)
+    specs.append((g.X, 1, g.k, g.eps, {"transforms": "grid"}, g.wu))     # grid-form levels
     plans, wus = [], []
     for X, kern, k, eps, kw, wu in specs:
         plans.append(gpu_plan(X, X, kern, k, eps, **kw))
