@@ -247,6 +247,57 @@ k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     }
 }
 
+// The same transfer for levels with many direction pairs per box.  Block: a
+// tile of QT direction pairs for 256 / QT target boxes (consecutive in Morton order); the tile of every class's
+// D is staged in LDS once per block, so each far pair reads D from LDS and only u~ from memory.  Four far pairs
+// per step, their loads issued together.  Item (desc, group of target slots, tile).
+template <int QT>
+__global__ void __launch_bounds__(kThreads)
+k_pw_transfer_lds(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    extern __shared__ float4 Ds[];            // [ncls][QT]
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int64_t npair = d.npair, q0 = (int64_t)wk.z * QT;
+    const int ncls = d.ncls;
+    for (int k = threadIdx.x; k < ncls * QT; k += kThreads) {
+        const int c = k / QT, ql = k % QT;
+        Ds[k] = q0 + ql < npair ? d.D[(int64_t)c * npair + q0 + ql] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    const int slot = threadIdx.x / QT, ql = threadIdx.x % QT;
+    const int ti = wk.y * (kThreads / QT) + slot;
+    const int64_t q = q0 + ql;
+    if (ti >= d.ntr || q >= npair) return;
+    const int t = d.tr_tgt[ti];
+    const float4 *__restrict__ ut = d.ut;
+    const float4 *Dq = Ds + ql;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto step = [&](const float4 &dq, const float4 &w) {
+        acc.x = fmaf(dq.x, w.x, fmaf(-dq.y, w.y, acc.x));
+        acc.y = fmaf(dq.x, w.y, fmaf(dq.y, w.x, acc.y));
+        acc.z = fmaf(dq.z, w.z, fmaf(-dq.w, w.w, acc.z));
+        acc.w = fmaf(dq.z, w.w, fmaf(dq.w, w.z, acc.w));
+    };
+    const int64_t e0 = d.far_ptr[t], e1 = d.far_ptr[t + 1];
+    int64_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        int64_t sv[4];
+        int cv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sv[k] = d.far_src[e + k];
+            cv[k] = d.far_cls[e + k];
+        }
+        float4 w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = ut[sv[k] * npair + q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) step(Dq[cv[k] * QT], w[k]);
+    }
+    for (; e < e1; ++e) step(Dq[d.far_cls[e] * QT], ut[(int64_t)d.far_src[e] * npair + q]);
+    d.vt[(int64_t)t * npair + q] = acc;
+}
+
 // Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q) and
 // B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Item (desc, target box, first point);
 // BS points per block (64 for levels of small boxes).
@@ -1750,11 +1801,16 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             return S.b ? k_pw_forward_rings<2, true> : k_pw_forward_rings<2, false>;
         case K_SUM: return k_sum_segments;
         case K_TRANSFER:
-            if (S.a == 101) {
-                threads = 64;
-                return k_pw_transfer<1, 64>;
+            // a = 1000 + direction pairs per tile (transfer_qt): class tables staged in LDS; else
+            // a = PPT (+100: 64-thread blocks)
+            switch (S.a) {
+                case 1004: return k_pw_transfer_lds<4>;
+                case 1002: return k_pw_transfer_lds<2>;
+                case 1001: return k_pw_transfer_lds<1>;
+                case 101: threads = 64; return k_pw_transfer<1, 64>;
+                case 2: return k_pw_transfer<2, kThreads>;
+                default: return k_pw_transfer<1, kThreads>;
             }
-            return S.a == 2 ? k_pw_transfer<2, kThreads> : k_pw_transfer<1, kThreads>;
         case K_BWD_PAIR:
             // a = 100: 64-thread blocks
             if (S.a == 100) {
@@ -1894,6 +1950,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_FWD_RING: return "k_pw_forward_rings<" + std::to_string(a == 4 ? 4 : 2) + ", " + tf(b) + ">";
         case K_SUM: return "k_sum_segments";
         case K_TRANSFER:
+            if (a > 1000) return "k_pw_transfer_lds<" + std::to_string(a - 1000) + ">";
             if (a == 101) return "k_pw_transfer<1, 64>";
             return "k_pw_transfer<" + std::to_string(a == 2 ? 2 : 1) + ", 256>";
         case K_BWD_PAIR: return "k_pw_backward<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";

@@ -191,6 +191,8 @@ struct LDesc {
     const int32_t *sstart;
     const int64_t *far_ptr, *near_ptr;
     const int32_t *far_src, *far_cls, *near_src;
+    const int32_t *tr_tgt;                 // target boxes of the transfers, in Morton order
+    int ntr, ncls;                         // their number; translation classes
     // Gegenbauer level
     const float4 *dirs;
     const double *dirs64;
@@ -242,6 +244,11 @@ struct Stage {
 
 // Ring-pair blocks (16 ring pairs each) per work item of the grid form's sums over z: at most four per item,
 // balanced over the items.
+// Direction pairs per transfer tile: the tile of every class's D is staged in LDS (at most 48 KB).
+__host__ __device__ inline int transfer_qt(int ncls) {
+    return ncls * 4 * 16 <= 49152 ? 4 : (ncls * 2 * 16 <= 49152 ? 2 : 1);
+}
+
 __host__ __device__ inline void grid_z_groups(int nrp, int &ngroups, int &per) {
     const int nmb = (nrp + 15) / 16;
     ngroups = (nmb + 3) / 4;
@@ -280,6 +287,7 @@ struct Level {
     DevBuf<float4> dirs;                 // [npair] direction * k / (2 pi), FP32 (w unused)
     DevBuf<double> dirs64;               // [npair][3] direction * k / (2 pi), FP64
     DevBuf<float4> D;                    // [ncls][npair] (D(s_p), D(-s_p)) as two complex
+    DevBuf<int32_t> tr_tgt;              // target boxes with far work in Morton order (transfer slots)
     bool phase64 = false;                // FP64 phase reduction at this level
     // ring-pair form of the transforms: ring m and its antipodal ring share one in-plane phase
     int nrp = 0;                         // ring pairs: (L+1)/2 rounded up (the equator ring when L is even)

@@ -1338,14 +1338,19 @@ Stage make_stage(int kern, int a, int b, int slot, int level, size_t shmem, std:
 }
 }  // namespace
 
-// Transfer work items, tile-major (the blocks running together share a tile of the class tables D).  Within a
-// tile the target boxes go in Morton order, cut into 8 contiguous ranges interleaved so that block b takes
-// range b mod 8: workgroups are dealt to the 8 XCDs of the chip in turn, so each XCD works through one
-// contiguous region, and neighbouring targets, which share most of their far sources, find u~ in that XCD's L2.
-static std::vector<int4> transfer_items(int l, const std::vector<int32_t> &tgt_by_size, int64_t ntiles) {
+// Transfer work items, tile-major (the blocks running together share a tile of the class tables D): with the
+// class tables staged in LDS (levels with many direction pairs), groups of 256 / qt consecutive target slots
+// (targets with far work in Morton order) and tiles of qt pairs; otherwise one target box and a tile of
+// bs ppt pairs per block.  Within a tile the groups (or targets, in Morton order) are cut into 8 contiguous
+// ranges interleaved so that block b takes range b mod 8: workgroups are dealt to the 8 XCDs of the chip in
+// turn, so each XCD works through one contiguous region, and neighbouring targets, which share most of their
+// far sources, find u~ in that XCD's L2.
+static std::vector<int4> transfer_items(int l, const std::vector<int32_t> &tgt_by_size, int64_t npair, bool lds,
+                                        int qt, int tile) {
     std::vector<int32_t> tg(tgt_by_size);
     std::sort(tg.begin(), tg.end());
-    const int64_t n = (int64_t)tg.size();
+    const int64_t n = lds ? ((int64_t)tg.size() + kThreads / qt - 1) / (kThreads / qt) : (int64_t)tg.size();
+    const int64_t ntiles = (npair + tile - 1) / tile;
     constexpr int kXcd = 8;
     const int64_t per = (n + kXcd - 1) / kXcd;
     std::vector<int4> it;
@@ -1353,8 +1358,8 @@ static std::vector<int4> transfer_items(int l, const std::vector<int32_t> &tgt_b
     for (int64_t q = 0; q < ntiles; ++q)
         for (int64_t k = 0; k < per; ++k)
             for (int x = 0; x < kXcd; ++x) {
-                const int64_t i = x * per + k;
-                if (i < n) it.push_back(make_int4(l, tg[(size_t)i], (int)q, 0));
+                const int64_t g = x * per + k;
+                if (g < n) it.push_back(make_int4(l, lds ? (int)g : tg[(size_t)g], (int)q, 0));
             }
     return it;
 }
@@ -1393,6 +1398,21 @@ static void pick_pair_tile(int64_t npair, int ppt_max, int &bs, int &ppt) {
     }
 }
 
+// The transfer stage of a Gegenbauer level: class tables in LDS where boxes have many direction pairs
+// (measured faster from n_pair ~ 4096 on), one target per block otherwise.
+static Stage transfer_stage(int l, const Level &LV, int slot, hipStream_t st, Scratch &SC) {
+    if (LV.npair >= 4096) {
+        const int qt = transfer_qt(LV.ncls);
+        return make_stage(K_TRANSFER, 1000 + qt, 0, slot, l, sizeof(float4) * LV.ncls * qt,
+                          transfer_items(l, LV.h_tgt, LV.npair, true, qt, qt), st, SC);
+    }
+    int bs, ppt;
+    pick_pair_tile(LV.npair, 2, bs, ppt);
+    return make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, slot, l, 0,
+                      transfer_items(l, LV.h_tgt, LV.npair, false, 1, bs * ppt), st, SC);
+}
+
+
 // Choose the kernel form of every level for a tile choice and build its launches (work items).
 void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
     Scratch SC(st);
@@ -1426,6 +1446,12 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
         if (LV.method == kNone) continue;
         const int s1 = 1 + 3 * (l - 1), s2 = s1 + 1, s3 = s1 + 2;
         const std::vector<int32_t> &sx = LV.h_sx;
+        if (LV.method == kGegenbauer) {
+            // transfer slots: the targets with far work in Morton order
+            std::vector<int32_t> tg(LV.h_tgt);
+            std::sort(tg.begin(), tg.end());
+            upload(LV.tr_tgt, tg, st, SC);
+        }
         if (LV.method == kGegenbauer && LV.grid) {
             // grid form: spread (per z-plane and 64 x 64 tile), sums over z (64 grid columns and up to 64
             // ring pairs per block), sums over the plane to the directions (one ring per block); the transfer;
@@ -1438,7 +1464,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             int zng, zper;
             grid_z_groups(LV.nrp, zng, zper);
             zng = ((LV.nrp + 15) / 16 + zper - 1) / zper;
-            std::vector<int4> a1, a2, a3, tr, b1, b2, b3;
+            std::vector<int4> a1, a2, a3, b1, b2, b3;
             // the plane sums go ring by ring, rings m and L - m (which share their tables) together, so that
             // the blocks running at once read the same few tables
             std::vector<int> ring_order;
@@ -1458,11 +1484,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                                            std::move(a1), st, SC));
             LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
             LV.stages.push_back(make_stage(K_GPHI, p <= 64 ? p / 16 : 0, 0, s1, l, 0, std::move(a3), st, SC));
-            int bs, ppt;
-            pick_pair_tile(LV.npair, 2, bs, ppt);
-            const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
-            tr = transfer_items(l, LV.h_tgt, nt);
-            LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
+            LV.stages.push_back(transfer_stage(l, LV, s2, st, SC));
             for (int m : ring_order)
                 for (int32_t t : LV.h_tgt)
                     for (int q = 0; q < nta * nta; ++q) b1.push_back(make_int4(l, t, m, q));
@@ -1510,12 +1532,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 LV.stages.push_back(make_stage(K_FWD_PAIR, ppt + (bs == 64 ? 100 : 0), LV.phase64, s1, l, 0,
                                                std::move(fw), st, SC));
             }
-            int bs, ppt;
-            pick_pair_tile(LV.npair, 2, bs, ppt);
-            const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
-            std::vector<int4> tr, bw;
-            tr = transfer_items(l, LV.h_tgt, nt);
-            LV.stages.push_back(make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, s2, l, 0, std::move(tr), st, SC));
+            std::vector<int4> bw;
+            LV.stages.push_back(transfer_stage(l, LV, s2, st, SC));
             // direction-pair target transform: 64-point blocks where target boxes are small
             const bool small = !LV.qG && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
             if (small) LV.bwd_tile = 64;
@@ -1600,6 +1618,9 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.far_ptr = LV.far_ptr.p;
     d.far_src = LV.far_src.p;
     d.far_cls = LV.far_cls.p;
+    d.tr_tgt = LV.tr_tgt.p;
+    d.ntr = (int)LV.h_tgt.size();
+    d.ncls = LV.ncls;
     d.near_ptr = LV.near_ptr.p;
     d.near_src = LV.near_src.p;
     d.dirs = LV.dirs.p;
@@ -1686,7 +1707,8 @@ size_t plan_device_bytes(const Plan &P) {
         b += L.far_ptr.bytes() + L.near_ptr.bytes() + L.far_src.bytes() + L.far_cls.bytes() + L.near_src.bytes() +
              L.T.bytes() + L.grp_pair.bytes() + L.grp_cls.bytes() + L.dirs.bytes() + L.dirs64.bytes() + L.D.bytes() +
              L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes() + L.Ez.bytes() +
-             L.Ex.bytes() + L.Ey.bytes() + L.ExT.bytes() + L.EyT.bytes() + L.gperm.bytes() + L.gzs.bytes() + L.gxyz.bytes();
+             L.Ex.bytes() + L.Ey.bytes() + L.ExT.bytes() + L.EyT.bytes() + L.gperm.bytes() + L.gzs.bytes() + L.gxyz.bytes() +
+             L.tr_tgt.bytes();
         for (const Stage &S : L.stages) b += S.ditems.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
