@@ -74,6 +74,11 @@ def parse():
     ap.add_argument("--mixed-study", action="store_true",
                     help="only run the 10M-point sphere + cube study (FP32 and mixed precision at eps 1e-3, 1e-4)")
     ap.add_argument("--mixed-n", type=int, default=10_000_000)
+    ap.add_argument("--bie-study", action="store_true",
+                    help="only run the single-layer sphere solve (GMRES with FFM products) at --bie-n nodes")
+    ap.add_argument("--bie-n", type=int, default=1 << 20)
+    ap.add_argument("--bie-eps", type=float, default=1e-3)
+    ap.add_argument("--bie-tol", type=float, default=1e-3)
     ap.add_argument("--mixed-rows", type=int, default=1024)
     return ap.parse_args()
 
@@ -105,6 +110,22 @@ def cpu_baseline(w, strides):
     }
 
 
+def dense_rows_device(X, wu, kernel, k, rows, chunk=1 << 15):
+    """FP64 direct sums v_i = sum_{j: r_ij > 0} G(x_i, x_j) wu_j on sampled target rows, in plain torch on the
+    device (the reference for the error figures; sources = targets = X, G = e^{ikr}/(4 pi r) or 1/(4 pi r))."""
+    import torch
+    R = X[torch.as_tensor(np.asarray(rows, dtype=np.int64), device=X.device)]
+    u = wu.to(torch.complex128)
+    acc = torch.zeros(R.shape[0], dtype=torch.complex128, device=X.device)
+    for s in range(0, X.shape[0], chunk):
+        d = R[:, None, :] - X[None, s:s + chunk, :]
+        r = torch.sqrt((d * d).sum(-1))
+        inv = torch.where(r > 0, 1.0 / (4.0 * math.pi * r), torch.zeros_like(r))
+        g = torch.polar(inv, k * r) if kernel == 1 else inv.to(torch.complex128)
+        acc += g @ u[s:s + chunk]
+    return acc.cpu().numpy()
+
+
 def _sync_time(fn, reps):
     import torch
     torch.cuda.synchronize()
@@ -123,7 +144,6 @@ def batched(reps=5):
     targets per instance)."""
     import torch
     import ffm_workloads as W
-    import oracle
     import paper_1909_05600_amd as ffm
     ws = W.batched_instances(256, seed=4)
     n_tot = sum(w.n for w in ws)
@@ -152,9 +172,9 @@ def batched(reps=5):
         t = _sync_time(lambda: b.apply(wus, outs=o2), reps)
         info = b.info()
         errs = []
-        for w, o in zip(ws, o2):
+        for w, X, u, o in zip(ws, Xs, wus, o2):
             rows = w.rows[:16]
-            d = oracle.dense_rows(w.X, w.X, w.wu, w.kernel, w.k, rows)
+            d = dense_rows_device(X, u, w.kernel, w.k, rows)
             v = o.cpu().numpy()[rows].astype(np.complex128)
             errs.append(float(np.linalg.norm(v - d) / np.linalg.norm(d)))
         res[name + "_points_per_s"] = n_tot / t
@@ -264,7 +284,6 @@ def mixed_study(n, n_rows, reps=3):
     sampled targets, overall and per target class (sphere / cube)."""
     import torch
     import ffm_workloads as W
-    import oracle
     import paper_1909_05600_amd as ffm
     out = {"n": n, "rows": n_rows, "runs": []}
     w = W.sphere_plus_cube(n, seed=3, n_rows=n_rows)     # the points, u and rows do not depend on eps
@@ -272,7 +291,7 @@ def mixed_study(n, n_rows, reps=3):
     X = torch.from_numpy(w.X).cuda()
     wu = torch.from_numpy(w.wu).cuda()
     t0 = time.perf_counter()
-    d = oracle.dense_rows(w.X, w.X, w.wu, 1, w.k, w.rows)
+    d = dense_rows_device(X, wu, 1, w.k, w.rows)
     t_dense = time.perf_counter() - t0
     sph = w.rows < w.meta["n_sphere"]
     for eps in (1e-3, 1e-4):
@@ -303,6 +322,57 @@ def mixed_study(n, n_rows, reps=3):
                   file=sys.stderr, flush=True)
             p.destroy()
             torch.cuda.empty_cache()
+    return out
+
+
+def bie_study(n, eps, tol, kernels=(0, 1)):
+    """The single-layer equation on the unit sphere (reduced Gauss grid with about n nodes): GMRES with one FFM
+    product per iteration, for Laplace (data: the potential of a point charge inside the sphere) and for
+    Helmholtz at ten nodes per wavelength (data: a plane wave on a sound-soft sphere).
+    Reports set-up (plan + the correction's product), iterations, solve time, products per second and the
+    error of the density against the closed form (harmonics divided by their eigenvalues)."""
+    import torch
+    import ffm_workloads as W
+    from paper_1909_05600_amd import bie
+    out = {"n_target": n, "eps": eps, "tol": tol, "runs": []}
+    for kernel in kernels:
+        p = W.bie_sphere(W.n_theta_for(n), kernel, None, eps, data="source" if kernel == 0 else "plane_wave")
+        X = torch.from_numpy(p.X).cuda()
+        w = torch.from_numpy(p.w).cuda()
+        f = torch.from_numpy(p.f).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = bie.SingleLayer(X, w, kernel, p.k, eps)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sigma, info = bie.solve(A, f, tol=tol, restart=300, maxiter=1500)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        if kernel == 0:
+            exact = bie.zonal_density(p.X, p.x0, bie.point_source_coefficients(np.linalg.norm(p.x0), p.radius))
+        else:
+            exact = bie.plane_wave_density(p.X, p.direction, p.k, p.radius)
+        s = sigma.cpu().numpy().astype(np.complex128)
+        sw = np.sqrt(p.w)
+        err = float(np.linalg.norm((s - exact) * sw) / np.linalg.norm(exact * sw))
+        res = float(torch.linalg.vector_norm(A.matvec(sigma) - f.to(torch.complex64))
+                    / torch.linalg.vector_norm(f))
+        st = A.plan.stats()
+        t_mv = _sync_time(lambda: A.matvec(sigma), 5)
+        r = {"kernel": "laplace" if kernel == 0 else "helmholtz", "data": p.data, "n": p.n, "k": p.k, "setup_s": t_setup,
+             "solve_s": t_solve, "iterations": info["iterations"], "converged": info["converged"],
+             "products": A.products - 1, "ms_per_iteration": t_solve * 1e3 / max(1, info["iterations"]),
+             "matvec_ms": t_mv * 1e3, "final_residual": res, "err_vs_closed_form": err, "leaf": st["leaf"],
+             "transform_form": [int(x) for x in st["tform"][:st["leaf"] + 1]]}
+        out["runs"].append(r)
+        print("bie study %s N=%d k=%.2f: setup %.3fs, %d iterations in %.3fs (%.2f ms each, matvec %.2f ms), "
+              "residual %.2e, error vs closed form %.2e" % (r["kernel"], p.n, p.k, t_setup, r["iterations"],
+                                                            t_solve, r["ms_per_iteration"], t_mv * 1e3, res, err),
+              file=sys.stderr, flush=True)
+        A.destroy()
+        del X, w, f, sigma
+        torch.cuda.empty_cache()
     return out
 
 
@@ -390,6 +460,12 @@ def main():
     if args.mixed_study:
         res = {"metric": "10M sphere + cube Helmholtz: points/s and error per precision mode",
                "mixed_study": mixed_study(args.mixed_n, args.mixed_rows)}
+        print(json.dumps(res), flush=True)
+        return
+
+    if args.bie_study:
+        res = {"metric": "single-layer sphere solve: GMRES iterations, time and error vs the closed form",
+               "bie_study": bie_study(args.bie_n, args.bie_eps, args.bie_tol)}
         print(json.dumps(res), flush=True)
         return
 

@@ -163,3 +163,76 @@ def shell_grid(n_theta: int, n_phi: int, radius: float = 1.0):
                   np.repeat(ct, n_phi)], axis=1) * radius
     w = np.repeat(wt, n_phi) * (2.0 * math.pi / n_phi) * radius * radius
     return P, w
+
+
+def reduced_sphere_grid(n_theta: int, radius: float = 1.0):
+    """Quasi-uniform quadrature nodes on a sphere: n_theta Gauss-Legendre rings in cos(theta); ring m holds
+    max(6, ceil(2 n_theta sin(theta_m))) equispaced azimuths, every other ring turned by half a step.  A node's
+    weight is its ring's Gauss weight times 2 pi over the ring's azimuth count, times radius^2.  About
+    4 n_theta^2 / pi nodes, spaced evenly over the surface like the vertices of a uniform surface mesh."""
+    ct, wt = np.polynomial.legendre.leggauss(n_theta)
+    st = np.sqrt(1.0 - ct * ct)
+    n_phi = np.maximum(6, np.ceil(2.0 * n_theta * st).astype(np.int64))
+    ring = np.repeat(np.arange(n_theta), n_phi)
+    start = np.concatenate([[0], np.cumsum(n_phi)[:-1]])
+    j = np.arange(int(n_phi.sum())) - np.repeat(start, n_phi)
+    ph = 2.0 * math.pi * (j + 0.5 * (ring % 2)) / n_phi[ring]
+    P = np.stack([st[ring] * np.cos(ph), st[ring] * np.sin(ph), ct[ring]], axis=1) * radius
+    w = wt[ring] * (2.0 * math.pi / n_phi[ring]) * radius * radius
+    return P, w
+
+
+def n_theta_for(n: int) -> int:
+    """The ring count whose reduced sphere grid holds about n nodes."""
+    return max(4, int(round(math.sqrt(math.pi * n / 4.0))))
+
+
+@dataclass
+class SurfaceProblem:
+    """A Dirichlet problem on a sphere for the single-layer equation: nodes, weights and boundary data f.
+    ``data`` names the data: "harmonics" (a sum of spherical harmonics, each term's degree and nodal values
+    in ``harmonics``), "source" (the potential 1/(4 pi |x - x0|) of a unit point charge at ``x0`` inside the
+    sphere) or "plane_wave" (f = -exp(i k d.x), a sound-soft sphere hit by a plane wave along ``direction``)."""
+    name: str
+    X: np.ndarray                 # nodes, FP64 (n, 3)
+    w: np.ndarray                 # quadrature weights, FP64 (n,)
+    kernel: int
+    k: float
+    eps: float
+    radius: float
+    data: str
+    f: np.ndarray                 # boundary data at the nodes (complex128)
+    harmonics: list = field(default_factory=list)   # [(degree, values at the nodes, FP64)]
+    x0: np.ndarray | None = None
+    direction: np.ndarray | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.X.shape[0])
+
+
+def bie_sphere(n_theta: int, kernel: int = HELMHOLTZ, k: float | None = None, eps: float = 1e-3,
+               radius: float = 1.0, data: str = "harmonics") -> SurfaceProblem:
+    """A single-layer problem on the reduced sphere grid of radius a.  Helmholtz k defaults to ten nodes per
+    wavelength.  Data: "harmonics" is f = 1 + x/a + xyz/a^3 (degrees 0, 1, 3: x and xyz are harmonic
+    polynomials); "source" puts the charge at x0 = (0.15, -0.25, 0.35) a; "plane_wave" travels along
+    d = (1, 2, 3)/sqrt(14)."""
+    X, w = reduced_sphere_grid(n_theta, radius)
+    x, y, z = (X / radius).T
+    kk = 0.0 if kernel == LAPLACE else (wavenumber_10ppw(X.shape[0]) / radius if k is None else float(k))
+    name = "bie_sphere_%s_%d" % (data, X.shape[0])
+    if data == "harmonics":
+        h = [(0, np.ones_like(x)), (1, x.copy()), (3, x * y * z)]
+        return SurfaceProblem(name, X, w, kernel, kk, eps, radius, data, sum(v for _, v in h).astype(complex),
+                              harmonics=h)
+    if data == "source":
+        x0 = np.array([0.15, -0.25, 0.35]) * radius
+        f = (1.0 / (4.0 * math.pi * np.linalg.norm(X - x0, axis=1))).astype(np.complex128)
+        return SurfaceProblem(name, X, w, kernel, kk, eps, radius, data, f, x0=x0)
+    if data == "plane_wave":
+        if kernel != HELMHOLTZ:
+            raise ValueError("plane-wave data needs the Helmholtz kernel")
+        d = np.array([1.0, 2.0, 3.0]) / math.sqrt(14.0)
+        f = -np.exp(1j * kk * (X @ d))
+        return SurfaceProblem(name, X, w, kernel, kk, eps, radius, data, f, direction=d)
+    raise ValueError("unknown data %r" % data)
