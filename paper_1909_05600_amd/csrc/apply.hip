@@ -692,7 +692,9 @@ k_grid_spread(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     constexpr float hw = 0.5f * W, k1 = 2.f / W;
     const float k2 = d.gbeta * 1.44269504f;
     const int64_t zoff = (int64_t)sb * p;
-    const int j0 = d.gzs[zoff + max(0, c - W / 2)], j1 = d.gzs[zoff + min(p - 1, c + W / 2 - 1) + 1];
+    // points binned by plane (even W: floor(z), odd W: nearest plane) whose support reaches plane c
+    constexpr int zlo = W / 2, zhi = (W - 1) / 2;
+    const int j0 = d.gzs[zoff + max(0, c - zlo)], j1 = d.gzs[zoff + min(p - 1, c + zhi) + 1];
     const int R = (j1 - j0 + 63) / 64, lane = threadIdx.x & 63;
     for (int r = threadIdx.x >> 6; r < R; r += kThreads / 64) {
         const int j = j0 + lane * R + r;
@@ -1829,7 +1831,15 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
         case K_ZERO_OUT: return k_zero_io;
-        case K_GSPREAD: return S.a == 8 ? k_grid_spread<8> : k_grid_spread<6>;
+        case K_GSPREAD:
+            switch (S.a) {
+                case 4: return k_grid_spread<4>;
+                case 5: return k_grid_spread<5>;
+                case 6: return k_grid_spread<6>;
+                case 7: return k_grid_spread<7>;
+                case 8: return k_grid_spread<8>;
+                default: throw Error(FFM_EINTERNAL, "unknown spreading width");
+            }
         case K_GZ: return k_grid_z;
         case K_GPHI:
             // a = p / 16 for grids of at most 64 nodes per axis, 0 otherwise
@@ -1842,7 +1852,15 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             }
         case K_GPHIT: return k_grid_phit;
         case K_GZT: return k_grid_zt;
-        case K_GINTERP: return S.a == 8 ? k_grid_interp<8> : k_grid_interp<6>;
+        case K_GINTERP:
+            switch (S.a) {
+                case 4: return k_grid_interp<4>;
+                case 5: return k_grid_interp<5>;
+                case 6: return k_grid_interp<6>;
+                case 7: return k_grid_interp<7>;
+                case 8: return k_grid_interp<8>;
+                default: throw Error(FFM_EINTERNAL, "unknown spreading width");
+            }
         default: throw Error(FFM_EINTERNAL, "unknown kernel variant");
     }
 }
@@ -1888,11 +1906,11 @@ int device_cus() {
 }
 
 void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream_t st) {
-    if (S.ditems.n == 0) return;
-    FFM_CHECK(S.ditems.n < ((size_t)1 << 31), FFM_EINTERNAL, "stage grid too large");
+    if (S.nitems == 0) return;
+    FFM_CHECK(S.nitems < ((size_t)1 << 31), FFM_EINTERNAL, "stage grid too large");
     int threads = kThreads;
     KernelFn fn = kernel_of(S, threads);
-    hipLaunchKernelGGL(fn, dim3((unsigned)S.ditems.n), dim3(threads), S.shmem, st, ddesc, dio, S.ditems.p);
+    hipLaunchKernelGGL(fn, dim3((unsigned)S.nitems), dim3(threads), S.shmem, st, ddesc, dio, S.ditems);
     FFM_HIP(hipGetLastError());
 }
 
@@ -1903,7 +1921,7 @@ void Plan::mark(int phase, hipStream_t st, const Stage *S) {
     FFM_HIP(hipEventRecord(tev[tused], st));
     tphase[tused] = phase;
     tkern[tused] = S ? make_int4(S->kern, S->a, S->b, S->level) : make_int4(-1, 0, 0, 0);
-    tblocks[tused] = S ? (int64_t)S->ditems.n : 0;
+    tblocks[tused] = S ? (int64_t)S->nitems : 0;
     ++tused;
 }
 
@@ -1963,12 +1981,12 @@ std::string kernel_name(int kern, int a, int b) {
         case K_INTERP: return "k_lag_interp";
         case K_NEAR: return "k_near<" + tf(b) + ">";
         case K_ZERO_OUT: return "k_zero_io";
-        case K_GSPREAD: return a == 8 ? "k_grid_spread<8>" : "k_grid_spread<6>";
+        case K_GSPREAD: return a >= 4 && a <= 8 ? "k_grid_spread<" + std::to_string(a) + ">" : "";
         case K_GZ: return "k_grid_z";
         case K_GPHI: return a >= 1 && a <= 4 ? "k_grid_phi_s<" + std::to_string(a) + ">" : "k_grid_phi";
         case K_GPHIT: return "k_grid_phit";
         case K_GZT: return "k_grid_zt";
-        case K_GINTERP: return a == 8 ? "k_grid_interp<8>" : "k_grid_interp<6>";
+        case K_GINTERP: return a >= 4 && a <= 8 ? "k_grid_interp<" + std::to_string(a) + ">" : "";
         default: return "";
     }
 }

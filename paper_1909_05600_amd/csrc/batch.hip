@@ -72,6 +72,7 @@ struct Batch {
     DevBuf<IoEntry> dio;
     IoEntry *hio = nullptr;              // pinned
     std::vector<Stage> stages;           // merged launches in execution order
+    DevBuf<int4> items;                  // their work items (one arena)
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -148,9 +149,11 @@ void batch_build(Batch &B, hipStream_t st) {
         S.shmem = std::get<6>(kv.first);
         S.level = std::get<1>(kv.first);
         S.items = std::move(kv.second);
-        upload_b(S.ditems, S.items, st, SC);
         B.stages.push_back(std::move(S));
     }
+    std::vector<Stage *> all;
+    for (Stage &S : B.stages) all.push_back(&S);
+    upload_stage_items(all, B.items, st, SC);
     upload_b(B.ddesc, B.hdesc, st, SC);
 }
 

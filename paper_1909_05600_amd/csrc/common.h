@@ -238,8 +238,13 @@ struct Stage {
     int level = 0;                    // level (ordering of target-side stages in batches)
     size_t shmem = 0;                 // dynamic LDS bytes
     std::vector<int4> items;          // work items (host copy, kept for batching)
-    DevBuf<int4> ditems;
+    const int4 *ditems = nullptr;     // the items on the device: a slice of the owner's item arena
+    size_t nitems = 0;
 };
+
+// Upload the work items of all the given stages into one device arena with one copy, and point each stage
+// at its slice.
+void upload_stage_items(const std::vector<Stage *> &stages, DevBuf<int4> &arena, hipStream_t st, Scratch &SC);
 
 
 // Ring-pair blocks (16 ring pairs each) per work item of the grid form's sums over z: at most four per item,
@@ -351,6 +356,7 @@ struct Plan {
     // execution: descriptors (index = level), I/O table, stages before and after the levels
     std::vector<LDesc> hdesc;
     DevBuf<LDesc> ddesc;
+    DevBuf<int4> items;               // work items of every stage (one arena)
     DevBuf<IoEntry> dio;
     IoEntry *hio = nullptr;              // pinned host copy of the I/O entry
     std::vector<Stage> pre, post;

@@ -495,7 +495,7 @@ __device__ __forceinline__ int box_of(int64_t i, const int32_t *start, int nbox)
 
 __global__ void __launch_bounds__(kThreads)
 k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *xs, const double *ys, const double *zs,
-              const double *ctr, double inv_h, int p, int32_t *cnt, int32_t *cell_of, float4 *gtmp) {
+              const double *ctr, double inv_h, int p, float zshift, int32_t *cnt, int32_t *cell_of, float4 *gtmp) {
     __shared__ int32_t hist[kZBins];
     const int64_t i0 = (int64_t)blockIdx.x * kThreads, i = i0 + threadIdx.x;
     for (int k = threadIdx.x; k < kZBins; k += kThreads) hist[k] = 0;
@@ -507,7 +507,7 @@ k_grid_zcount(int64_t n, const int32_t *start, int nbox, const double *xs, const
         const float xg = (float)((xs[i] - ctr[3 * b]) * inv_h) + half;
         const float yg = (float)((ys[i] - ctr[3 * b + 1]) * inv_h) + half;
         const float zg = (float)((zs[i] - ctr[3 * b + 2]) * inv_h) + half;
-        const int c = min(max((int)floorf(zg), 0), p - 1);
+        const int c = min(max((int)floorf(zg + zshift), 0), p - 1);
         const int64_t slot = (int64_t)b * p + c;
         cell_of[i] = (int32_t)slot;
         gtmp[i] = make_float4(xg, yg, zg, 0.f);
@@ -585,6 +585,71 @@ const std::vector<double> &phi_hat_table(int w, double beta, double &step) {
     return cache.emplace(key, std::move(tab)).first->second;
 }
 
+
+// Bound on the relative aliasing error of spreading one frequency with the kernel above: by Poisson
+// summation, sum_a phi(x - a) e^{i om (a - x)} = sum_m phi^(om + 2 pi m) e^{2 pi i m x} (grid units), so the
+// error relative to phi^(om) is at most sum_{m != 0} |phi^(om + 2 pi m)| / phi^(om); maximised over
+// |om| <= kh (33 samples).  phi^ by 128-point Gauss-Legendre quadrature; kept per (w, beta, kh to 1/64) for
+// the process.
+double spread_alias_bound(int w, double beta, double kh) {
+    static std::mutex mx;
+    static std::map<std::tuple<int, int, int>, double> cache;
+    const int qkh = (int)std::ceil(kh * 64.0);
+    const auto key = std::make_tuple(w, (int)std::lround(beta * 100.0), qkh);
+    {
+        std::lock_guard<std::mutex> lk(mx);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    std::vector<double> x, wt;
+    gauss_legendre_host(128, x, wt);
+    std::vector<double> f(x.size());
+    for (size_t j = 0; j < x.size(); ++j)
+        f[j] = std::exp(beta * (std::sqrt(std::max(0.0, 1.0 - x[j] * x[j])) - 1.0)) * wt[j] * 0.5 * w;
+    auto ft = [&](double om) {
+        double a = 0.0;
+        for (size_t j = 0; j < x.size(); ++j) a += f[j] * std::cos(om * 0.5 * w * x[j]);
+        return a;
+    };
+    const double khq = qkh / 64.0;
+    double worst = 0.0;
+    for (int i = 0; i <= 32; ++i) {
+        const double om = khq * i / 32.0;
+        double s = 0.0;
+        for (int m = 1; m <= 4; ++m) s += std::fabs(ft(om + 2.0 * M_PI * m)) + std::fabs(ft(2.0 * M_PI * m - om));
+        worst = std::max(worst, s / ft(om));
+    }
+    worst *= 1.1;   // the maximum between the sampled frequencies (within 10% of a 64-point scan)
+    std::lock_guard<std::mutex> lk(mx);
+    cache[key] = worst;
+    return worst;
+}
+
+// Grid of a grid-form level: spacing h <= hmax over the box edge dl plus the kernel's support, p nodes per axis
+// rounded up to whole 16-row MFMA blocks.  The kernel is the narrowest width w (and its best shape beta among
+// 2.0 w .. 2.3 w) whose aliasing bound at that grid is at most eps / 2.  The bound covers one axis of one
+// transform in the worst direction; measured products err by well under a third of it overall.
+void grid_kernel_choice(double eps, double k, double dl, double hmax, int &w, double &beta, int &p, double &h) {
+    for (int ww = 4; ww <= 8; ++ww) {
+        int pp = (int)std::ceil(dl / hmax) + ww + 1;
+        pp = (pp + 15) / 16 * 16;
+        const double hh = dl / (double)(pp - 1 - ww);
+        double best = 1e300, bb = 2.3 * ww;
+        for (int c = 0; c < 4; ++c) {
+            const double b = (2.0 + 0.1 * c) * ww;
+            const double e = spread_alias_bound(ww, b, k * hh);
+            if (e < best) {
+                best = e;
+                bb = b;
+            }
+        }
+        w = ww;
+        beta = bb;
+        p = pp;
+        h = hh;
+        if (best <= eps / 2.0) return;
+    }
+}
 
 void gauss_legendre_host(int n, std::vector<double> &x, std::vector<double> &w) {
     // Newton iteration on P_n from the Chebyshev-like initial guesses; nodes x_m in descending
@@ -1070,11 +1135,10 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             int nphat = 0;
             double dphat_step = 1.0;
             {
-                const int w = P.eps >= 3e-4 ? 6 : 8;
                 const double hmax = M_PI / (1.9 * P.k);
-                int p = (int)std::ceil(dl / hmax) + w + 1;
-                p = (p + 15) / 16 * 16;   // whole 16-row blocks of the MFMA sums
-                const double h = dl / (double)(p - 1 - w);
+                int w = 0, p = 0;
+                double beta = 0.0, h = 0.0;
+                grid_kernel_choice(P.eps, P.k, dl, hmax, w, beta, p, h);
                 // cost model in seconds, from measured MI355X rates: direct sums 9e-14 s per (point,
                 // direction); grid form: spreading 0.29 ns per point plus 2.5 ns per (box, plane) launch item
                 // and interpolation 0.12 ns per point (w = 6; w^3 nodes per point), and the four sums on FP32
@@ -1100,7 +1164,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     LV.gw = w;
                     LV.gp = p;
                     LV.gh = h;
-                    LV.gbeta = 2.3 * w;
+                    LV.gbeta = beta;
                     const int64_t nxy = (int64_t)LV.nrp * p * L;
                     LV.Ez.alloc((size_t)LV.nrp * p);
                     LV.Ex.alloc((size_t)nxy);
@@ -1115,7 +1179,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     float4 *gtmp = SC.get<float4>(std::max<int64_t>(TY.n, 1));
                     FFM_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (ncell + 1), st));
                     FFM_LAUNCH(k_grid_zcount, nblocks(TY.n), kThreads, 0, st, TY.n, TY.lev[l].start.p, nby, TY.xs.p,
-                               TY.ys.p, TY.zs.p, TY.lev[l].ctr.p, 1.0 / h, p, cnt, cell_of, gtmp);
+                               TY.ys.p, TY.zs.p, TY.lev[l].ctr.p, 1.0 / h, p, (w & 1) ? 0.5f : 0.f, cnt, cell_of, gtmp);
                     LV.gzs.alloc((size_t)ncell + 1);
                     exclusive_scan_i32(cnt, LV.gzs.p, ncell, st, SC);
                     int32_t *cursor = SC.get<int32_t>(ncell + 1);
@@ -1333,10 +1397,33 @@ Stage make_stage(int kern, int a, int b, int slot, int level, size_t shmem, std:
     S.level = level;
     S.shmem = shmem;
     S.items = std::move(items);
-    upload(S.ditems, S.items, st, SC);
+    (void)st;
+    (void)SC;
     return S;
 }
 }  // namespace
+
+void upload_stage_items(const std::vector<Stage *> &stages, DevBuf<int4> &arena, hipStream_t st, Scratch &SC) {
+    size_t total = 0;
+    for (const Stage *S : stages) total += S->items.size();
+    arena.alloc(total);
+    if (total == 0) {
+        for (Stage *S : stages) {
+            S->ditems = nullptr;
+            S->nitems = 0;
+        }
+        return;
+    }
+    int4 *h = SC.pin<int4>(total);
+    size_t off = 0;
+    for (Stage *S : stages) {
+        if (!S->items.empty()) std::memcpy(h + off, S->items.data(), S->items.size() * sizeof(int4));
+        S->ditems = arena.p + off;
+        S->nitems = S->items.size();
+        off += S->items.size();
+    }
+    FFM_HIP(hipMemcpyAsync(arena.p, h, total * sizeof(int4), hipMemcpyHostToDevice, st));
+}
 
 // Transfer work items, tile-major (the blocks running together share a tile of the class tables D): with the
 // class tables staged in LDS (levels with many direction pairs), groups of 256 / qt consecutive target slots
@@ -1587,6 +1674,12 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
     };
     fill(P.post);
     for (int l = 1; l <= P.leaf; ++l) fill(P.lev[l].stages);
+    std::vector<Stage *> all;
+    for (Stage &S : P.pre) all.push_back(&S);
+    for (int l = 1; l <= P.leaf; ++l)
+        for (Stage &S : P.lev[l].stages) all.push_back(&S);
+    for (Stage &S : P.post) all.push_back(&S);
+    upload_stage_items(all, P.items, st, SC);
 }
 
 // The descriptor of level l of a plan, over the given instance buffers and level workspace.
@@ -1709,13 +1802,11 @@ size_t plan_device_bytes(const Plan &P) {
              L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes() + L.Ez.bytes() +
              L.Ex.bytes() + L.Ey.bytes() + L.ExT.bytes() + L.EyT.bytes() + L.gperm.bytes() + L.gzs.bytes() + L.gxyz.bytes() +
              L.tr_tgt.bytes();
-        for (const Stage &S : L.stages) b += S.ditems.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
          P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
-    for (const Stage &S : P.pre) b += S.ditems.bytes();
-    for (const Stage &S : P.post) b += S.ditems.bytes();
+    b += P.items.bytes();
     return b;
 }
 
