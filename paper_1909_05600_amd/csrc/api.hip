@@ -188,6 +188,8 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         P.empty = (n_x == 0 || n_y == 0);
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         plan_build(P, X, Y, st);
+        FFM_HIP(hipEventCreateWithFlags(&P.ready, hipEventDisableTiming));
+        FFM_HIP(hipEventRecord(P.ready, st));
         FFM_HIP(hipEventCreateWithFlags(&P.done, hipEventDisableTiming));
         if (o.flags & FFM_FLAG_TIMING) {
             P.tev.resize(12 * kMaxLev + 16, nullptr);   // one event per launch, every form of every level
@@ -229,6 +231,8 @@ ffm_status_t ffm_destroy(ffm_plan_t plan) {
         if (q == hipErrorNotReady) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: an apply is still in flight");
     }
     return (ffm_status_t)Guard::run([&] {
+        plan_sync_ready(plan->P);
+        if (plan->P.ready) (void)hipEventDestroy(plan->P.ready);
         if (plan->P.done) (void)hipEventDestroy(plan->P.done);
         if (plan->P.hio) pinned_free(plan->P.hio);
         for (auto e : plan->P.tev)
@@ -303,7 +307,7 @@ ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out) {
 
 ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t level, void *dst, int64_t *count) {
     if (!plan || !count) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_export: NULL argument");
-    const Plan &P = plan->P;
+    Plan &P = plan->P;
     if (set < 0 || set > 1) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_export: set must be 0 or 1");
     if (P.empty) {
         *count = 0;
@@ -311,6 +315,7 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
     }
     if (level < 0 || level > P.leaf) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_export: level out of range");
     return (ffm_status_t)Guard::run([&] {
+        plan_sync_ready(P);
         const Tree &T = set == 0 ? *P.tx : *P.ty;
         const TreeLevel &TL = T.lev[level];
         const Level &LV = P.lev[level];

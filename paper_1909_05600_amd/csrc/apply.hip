@@ -1935,6 +1935,15 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
     // this apply's input and output go to the plan's I/O entry (pinned, copied in stream order); the
     // previous apply's copy has completed once its completion event has
     if (P.applied) FFM_HIP(hipEventSynchronize(P.done));
+    if (P.pending) {
+        // the plan's last GPU work runs on its planning stream: order this apply after it, and free its
+        // temporaries once it is complete
+        FFM_HIP(hipStreamWaitEvent(st, P.ready, 0));
+        if (hipEventQuery(P.ready) == hipSuccess) {
+            P.pending->release();
+            P.pending.reset();
+        }
+    }
     P.hio->wu = wu;
     P.hio->vout = v;
     P.hio->dtype = dtype;

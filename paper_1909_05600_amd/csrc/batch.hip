@@ -342,6 +342,7 @@ ffm_status_t ffm_plan_set_tiles(ffm_plan_t plan, const ffm_tiles_t *tiles, void 
     if (P.batch_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: the plan belongs to a batch");
     if (P.server_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: server requests of the plan are pending");
     return (ffm_status_t)Guard::run([&] {
+        plan_sync_ready(P);
         if (P.applied) FFM_HIP(hipEventSynchronize(P.done));
         Tune t;
         t.ring_g = tiles->ring_g;
@@ -378,6 +379,7 @@ ffm_status_t ffm_batch_create(const ffm_plan_t *plans, int32_t n, uint32_t flags
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         for (int32_t i = 0; i < n; ++i) {
             Plan &P = plans[i]->P;
+            plan_sync_ready(P);
             if (P.applied) FFM_HIP(hipEventSynchronize(P.done));
             B.plans.push_back(&P);
             ++P.batch_refs;

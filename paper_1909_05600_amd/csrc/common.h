@@ -111,8 +111,22 @@ struct Scratch {
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
     ~Scratch() {
+        if (bufs.empty() && pinned.empty()) return;
         (void)hipStreamSynchronize(stream);
+        release();
+    }
+    // take over another list's temporaries (the other list is left empty and will not synchronise)
+    void adopt(Scratch &o) {
+        for (auto &b : o.bufs) bufs.push_back(std::move(b));
+        pinned.insert(pinned.end(), o.pinned.begin(), o.pinned.end());
+        o.bufs.clear();
+        o.pinned.clear();
+    }
+    // free everything now; only once the work using it is known to be complete
+    void release() {
+        bufs.clear();
         for (void *p : pinned) pinned_free(p);
+        pinned.clear();
     }
     template <class T>
     T *get(size_t count) {
@@ -357,6 +371,10 @@ struct Plan {
     std::vector<LDesc> hdesc;
     DevBuf<LDesc> ddesc;
     DevBuf<int4> items;               // work items of every stage (one arena)
+    // the plan's last GPU work (tables, launch lists) may still run on the planning stream when ffm_plan
+    // returns: `ready` is recorded after it, and `pending` holds its temporaries until it is complete
+    hipEvent_t ready = nullptr;
+    std::unique_ptr<Scratch> pending;
     DevBuf<IoEntry> dio;
     IoEntry *hio = nullptr;              // pinned host copy of the I/O entry
     std::vector<Stage> pre, post;
@@ -375,7 +393,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st);
 void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st);
 size_t plan_device_bytes(const Plan &P);
 // stages of a plan for a tile choice; descriptors of a plan over given workspaces
-void plan_stages(Plan &P, const Tune &t, hipStream_t st);
+void plan_stages(Plan &P, const Tune &t, hipStream_t st, Scratch *keep = nullptr);
 struct LevelWork {                     // apply workspace a descriptor points into
     float4 *ut = nullptr, *vt = nullptr, *part = nullptr;
     float2 *ut2 = nullptr, *Z = nullptr, *bpart = nullptr;
@@ -387,7 +405,10 @@ std::string kernel_name(int kern, int a, int b);
 int device_cus();
 LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w);
 // rebuild the stages and descriptors of a built plan for a tile choice (the plan must be idle)
-void plan_set_tune(Plan &P, const Tune &t, hipStream_t st);
+void plan_set_tune(Plan &P, const Tune &t, hipStream_t st, Scratch *keep = nullptr);
+// Wait on the host until the plan's own GPU work is complete (plans return with their last tables and launch
+// lists still being written on the planning stream) and free its temporaries.
+void plan_sync_ready(Plan &P);
 // one launch per stage
 void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream_t st);
 

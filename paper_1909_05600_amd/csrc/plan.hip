@@ -285,6 +285,23 @@ k_near_pairs(const int64_t *ptr, const int32_t *src, int32_t nbx, const int32_t 
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
+// Translation classes in use, numbered in window order: map[w] = number of used windows before w (one
+// block, an exclusive scan of the flags).
+__global__ void __launch_bounds__(kThreads) k_class_map(const int32_t *used, int nw, int32_t *map) {
+    __shared__ int32_t part[kThreads];
+    const int per = (nw + kThreads - 1) / kThreads, w0 = threadIdx.x * per;
+    int32_t c = 0;
+    for (int w = w0; w < min(nw, w0 + per); ++w) c += used[w] != 0;
+    part[threadIdx.x] = c;
+    __syncthreads();
+    int32_t off = 0;
+    for (int t = 0; t < (int)threadIdx.x; ++t) off += part[t];
+    for (int w = w0; w < min(nw, w0 + per); ++w) {
+        map[w] = off;
+        off += used[w] != 0;
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_remap(int32_t *cls, int64_t n, const int32_t *map) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) cls[i] = map[cls[i]];
@@ -895,7 +912,10 @@ void build_work_lists(Plan &P, Level &LV, bool near, const WorkFetch &F) {
 struct PhaseLog {
     bool on = std::getenv("FFM_LOG") && std::getenv("FFM_LOG")[0] == '1';
     std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    std::string title = "ffm_plan ms:";
     std::string line;
+    PhaseLog() = default;
+    explicit PhaseLog(const char *what) : title(what) {}
     void mark(const char *what) {
         if (!on) return;
         auto now = std::chrono::steady_clock::now();
@@ -905,7 +925,7 @@ struct PhaseLog {
         t = now;
     }
     ~PhaseLog() {
-        if (on) std::fprintf(stderr, "ffm_plan ms:%s\n", line.c_str());
+        if (on) std::fprintf(stderr, "%s%s\n", title.c_str(), line.c_str());
     }
 };
 
@@ -993,7 +1013,9 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         FFM_HIP(hipMemcpyAsync(L0.near_src.p, h_src, sizeof(h_src), hipMemcpyHostToDevice, st));
     }
     int *bad = SC.get<int>(1);
-    int32_t *win_used = SC.get<int32_t>(kWin3);
+    FFM_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    // translation windows in use per level: read back with the work lists, after the descent
+    std::vector<int32_t *> win_used(maxlev + 1, nullptr);
     P.leaf = maxlev;
     for (int l = 1; l <= maxlev; ++l) {
         build_level(TX, SX, l, d0, st);
@@ -1031,31 +1053,15 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         LV.far_src.alloc(LV.nfar);
         LV.far_cls.alloc(LV.nfar);
         LV.near_src.alloc(std::max<int64_t>(LV.nnear, 1));
-        FFM_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
-        FFM_HIP(hipMemsetAsync(win_used, 0, sizeof(int32_t) * kWin3, st));
+        win_used[l] = SC.get<int32_t>(kWin3);
+        FFM_HIP(hipMemsetAsync(win_used[l], 0, sizeof(int32_t) * kWin3, st));
         FFM_LAUNCH(k_list_fill, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, LP.near_ptr.p, LP.near_src.p,
                    TY.lev[l - 1].child.p, ft, LV.far_ptr.p, LV.near_ptr.p, LV.far_src.p, LV.far_cls.p,
-                   LV.near_src.p, win_used, bad);
-        std::vector<int32_t> used(kWin3);
-        int hbad = 0;
-        FFM_HIP(hipMemcpyAsync(used.data(), win_used, sizeof(int32_t) * kWin3, hipMemcpyDeviceToHost, st));
-        FFM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-        FFM_HIP(hipStreamSynchronize(st));
-        FFM_CHECK(!hbad, FFM_EINTERNAL, "ffm_plan: translation outside its window");
-        // compact translation classes
-        std::vector<int32_t> map(kWin3, 0);
-        LV.cls_off.clear();
-        LV.ncls = 0;
-        for (int w = 0; w < kWin3; ++w)
-            if (used[w]) {
-                map[w] = LV.ncls++;
-                LV.cls_off.push_back(w / (kWin * kWin) + LV.win_base[0]);
-                LV.cls_off.push_back((w / kWin) % kWin + LV.win_base[1]);
-                LV.cls_off.push_back(w % kWin + LV.win_base[2]);
-            }
+                   LV.near_src.p, win_used[l], bad);
+        // compact translation classes (numbered in window order) on the device
         if (LV.nfar) {
             int32_t *dmap = SC.get<int32_t>(kWin3);
-            FFM_HIP(hipMemcpyAsync(dmap, SC.stage(map), sizeof(int32_t) * kWin3, hipMemcpyHostToDevice, st));
+            FFM_LAUNCH(k_class_map, 1, kThreads, 0, st, win_used[l], kWin3, dmap);
             FFM_LAUNCH(k_remap, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, dmap);
         }
         // stopping rule (Sec. 2.2.4)
@@ -1073,7 +1079,27 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     for (int l = 1; l <= P.leaf; ++l)
         if (P.lev[l].nfar) fetch_work_lists(P.lev[l], TX.lev[l], TY.lev[l], false, st, SC, wf[l]);
     fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near);
+    int32_t *used_h = SC.pin<int32_t>((size_t)kWin3 * (P.leaf + 1) + 1);
+    for (int l = 1; l <= P.leaf; ++l)
+        FFM_HIP(hipMemcpyAsync(used_h + (size_t)kWin3 * l, win_used[l], sizeof(int32_t) * kWin3,
+                               hipMemcpyDeviceToHost, st));
+    FFM_HIP(hipMemcpyAsync(used_h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     FFM_HIP(hipStreamSynchronize(st));
+    FFM_CHECK(!used_h[0], FFM_EINTERNAL, "ffm_plan: translation outside its window");
+    // translation classes of every level on the host: the same window-order numbering as k_class_map
+    for (int l = 1; l <= P.leaf; ++l) {
+        Level &LV = P.lev[l];
+        const int32_t *used = used_h + (size_t)kWin3 * l;
+        LV.cls_off.clear();
+        LV.ncls = 0;
+        for (int w = 0; w < kWin3; ++w)
+            if (used[w]) {
+                ++LV.ncls;
+                LV.cls_off.push_back(w / (kWin * kWin) + LV.win_base[0]);
+                LV.cls_off.push_back((w / kWin) % kWin + LV.win_base[1]);
+                LV.cls_off.push_back(w % kWin + LV.win_base[2]);
+            }
+    }
     // --- compression form and tables per level (Sec. 2.2.2, 2.2.3)
     size_t ws_src = 0, ws_tgt = 0, ws_z = 0, ws_part = 0, ws_gG = 0, ws_gH = 0;
     for (int l = 1; l <= P.leaf; ++l) {
@@ -1341,8 +1367,10 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.dio.alloc(1);
     P.hio = static_cast<IoEntry *>(pinned_alloc(sizeof(IoEntry)));
     std::memset(P.hio, 0, sizeof(IoEntry));
-    plan_set_tune(P, P.tune, st);
-    FFM_HIP(hipStreamSynchronize(st));
+    // the last tables and the launch lists are left to run on the planning stream: their temporaries go to
+    // P.pending, and applies wait for P.ready (recorded by the caller after this returns)
+    P.pending = std::make_unique<Scratch>(st);
+    plan_set_tune(P, P.tune, st, P.pending.get());
     plog.mark("stages");
 
     // --- statistics
@@ -1383,6 +1411,15 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         }
     }
     (void)ws_tgt;
+    P.pending->adopt(SC);
+}
+
+void plan_sync_ready(Plan &P) {
+    if (!P.pending) return;
+    if (P.ready) FFM_HIP(hipEventSynchronize(P.ready));
+    else FFM_HIP(hipStreamSynchronize(P.pending->stream));
+    P.pending->release();
+    P.pending.reset();
 }
 
 // ---------------------------------------------------------------------------- launches
@@ -1434,8 +1471,17 @@ void upload_stage_items(const std::vector<Stage *> &stages, DevBuf<int4> &arena,
 // far sources, find u~ in that XCD's L2.
 static std::vector<int4> transfer_items(int l, const std::vector<int32_t> &tgt_by_size, int64_t npair, bool lds,
                                         int qt, int tile) {
-    std::vector<int32_t> tg(tgt_by_size);
-    std::sort(tg.begin(), tg.end());
+    // targets in Morton (box id) order: flags over the id range instead of a comparison sort
+    std::vector<int32_t> tg;
+    {
+        int32_t hi = 0;
+        for (int32_t t : tgt_by_size) hi = std::max(hi, t + 1);
+        std::vector<char> on((size_t)hi, 0);
+        for (int32_t t : tgt_by_size) on[(size_t)t] = 1;
+        tg.reserve(tgt_by_size.size());
+        for (int32_t t = 0; t < hi; ++t)
+            if (on[(size_t)t]) tg.push_back(t);
+    }
     const int64_t n = lds ? ((int64_t)tg.size() + kThreads / qt - 1) / (kThreads / qt) : (int64_t)tg.size();
     const int64_t ntiles = (npair + tile - 1) / tile;
     constexpr int kXcd = 8;
@@ -1501,7 +1547,8 @@ static Stage transfer_stage(int l, const Level &LV, int slot, hipStream_t st, Sc
 
 
 // Choose the kernel form of every level for a tile choice and build its launches (work items).
-void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
+void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
+    PhaseLog plog("ffm_plan stages ms:");
     Scratch SC(st);
     P.pre.clear();
     P.post.clear();
@@ -1528,6 +1575,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             conc_bwd[i][j] = cus * stage_blocks_per_cu(K_BWD_RING, i ? 2 : 1, j);
         }
     for (int l = 1; l <= P.leaf; ++l) {
+        plog.mark("l");
         Level &LV = P.lev[l];
         LV.stages.clear();
         if (LV.method == kNone) continue;
@@ -1600,6 +1648,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                                                (int)std::max(1.0, avg / 256.0));
                 LV.qSplit = split;
                 if (split > 1) ws_part = std::max(ws_part, (size_t)split * P.ty->lev[l].nbox * LV.npair);
+                fw.reserve((size_t)(LV.h_fwd.size() * LV.nchunk * split));
                 for (int32_t b : LV.h_fwd)
                     for (int c = 0; c < LV.nchunk; ++c)
                         for (int g = 0; g < split; ++g) fw.push_back(make_int4(l, b, c, g));
@@ -1614,6 +1663,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
                 int bs, ppt;
                 pick_pair_tile(LV.npair, 4, bs, ppt);
                 const int64_t nt = (LV.npair + bs * ppt - 1) / (bs * ppt);
+                fw.reserve((size_t)(LV.h_fwd.size() * nt));
                 for (int32_t b : LV.h_fwd)
                     for (int64_t t = 0; t < nt; ++t) fw.push_back(make_int4(l, b, (int)t, 0));
                 LV.stages.push_back(make_stage(K_FWD_PAIR, ppt + (bs == 64 ? 100 : 0), LV.phase64, s1, l, 0,
@@ -1629,6 +1679,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             // ring parts of the target transform: enough blocks for several rounds of the chip
             LV.bSplit = LV.qG ? choose_split(tiles, conc_bwd[tu.bwd_pt == 2][LV.phase64], 8, LV.nrp) : 1;
             if (LV.bSplit > 1) ws_bpart = std::max(ws_bpart, (size_t)LV.bSplit * P.nx);
+            bw.reserve((size_t)(tiles * LV.bSplit));
             for (int g = 0; g < LV.bSplit; ++g)
                 for (int32_t t : LV.h_tgt)
                     for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) bw.push_back(make_int4(l, t, i, g));
@@ -1654,6 +1705,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
             LV.stages.push_back(make_stage(K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r, std::move(ip), st, SC));
         }
     }
+    plog.mark("lev");
     if (ws_part > P.wpart.n) P.wpart.alloc(ws_part);
     if (ws_bpart > P.wbpart.n) P.wbpart.alloc(ws_bpart);
     {
@@ -1674,12 +1726,15 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st) {
     };
     fill(P.post);
     for (int l = 1; l <= P.leaf; ++l) fill(P.lev[l].stages);
+    plog.mark("levels");
     std::vector<Stage *> all;
     for (Stage &S : P.pre) all.push_back(&S);
     for (int l = 1; l <= P.leaf; ++l)
         for (Stage &S : P.lev[l].stages) all.push_back(&S);
     for (Stage &S : P.post) all.push_back(&S);
     upload_stage_items(all, P.items, st, SC);
+    plog.mark("upload");
+    if (keep) keep->adopt(SC);
 }
 
 // The descriptor of level l of a plan, over the given instance buffers and level workspace.
@@ -1765,8 +1820,8 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     return d;
 }
 
-void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st) {
-    plan_stages(P, tu, st);
+void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
+    plan_stages(P, tu, st, keep);
     P.tune = tu;
     if (P.empty) return;
     LevelWork w;
@@ -1782,6 +1837,7 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st) {
     for (int l = 0; l <= P.leaf; ++l) P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
     upload(P.ddesc, P.hdesc, st, SC);
+    if (keep) keep->adopt(SC);
 }
 
 size_t plan_device_bytes(const Plan &P) {

@@ -72,6 +72,38 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const T *in, T *out
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (boff ? boff[blockIdx.x] : T(0)) + tot;
 }
 
+// The same with the block offset summed from the per-block totals by the block itself (a short block
+// reduction over bsum[0 .. block - 1]), so that a two-level scan takes two launches.
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply_sum(const T *in, T *out, int64_t n, const T *bsum) {
+    __shared__ T lw[kScanThreads / 64];
+    __shared__ T red[kScanThreads / 64];
+    T pre = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += kScanThreads) pre += bsum[j];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    T boff = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) boff += red[w];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T loc[kScanItems];
+    T s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        loc[j] = (i < n) ? in[i] : T(0);
+        s += loc[j];
+    }
+    T tot;
+    T incl = block_inclusive_sum(s, lw, tot);
+    T run = boff + incl - s;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += loc[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = boff + tot;
+}
+
 template <class T>
 void exclusive_scan(const T *in, T *out, int64_t n, hipStream_t st, Scratch &S) {
     if (n <= 0) {
@@ -83,8 +115,13 @@ void exclusive_scan(const T *in, T *out, int64_t n, hipStream_t st, Scratch &S) 
         FFM_LAUNCH(k_scan_apply<T>, 1, kScanThreads, 0, st, in, out, n, (const T *)nullptr);
         return;
     }
-    T *bsum = S.get<T>(nb + 1), *boff = S.get<T>(nb + 1);
+    T *bsum = S.get<T>(nb + 1);
     FFM_LAUNCH(k_scan_reduce<T>, nb, kScanThreads, 0, st, in, n, bsum);
+    if (nb <= 4096) {
+        FFM_LAUNCH(k_scan_apply_sum<T>, nb, kScanThreads, 0, st, in, out, n, (const T *)bsum);
+        return;
+    }
+    T *boff = S.get<T>(nb + 1);
     exclusive_scan<T>(bsum, boff, nb, st, S);
     FFM_LAUNCH(k_scan_apply<T>, nb, kScanThreads, 0, st, in, out, n, (const T *)boff);
 }

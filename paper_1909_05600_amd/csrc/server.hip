@@ -296,6 +296,7 @@ ffm_status_t ffm_server_submit(ffm_server_t server, ffm_plan_t plan, const void 
     if (bytes > S.budget)
         return (ffm_status_t)set_err(FFM_ENOMEM, "ffm_server_submit: the request's workspace exceeds the whole budget");
     return (ffm_status_t)Guard::run([&] {
+        plan_sync_ready(P);      // the server's streams then need no ordering after the planning stream
         std::unique_ptr<Request> r(new Request());
         r->plan = &P;
         r->io.wu = wu;
