@@ -96,9 +96,13 @@ typedef struct {
  *   opts   host pointer or NULL.
  *   hip_stream  stream for the planning kernels.
  *   out    host pointer receiving the plan handle.
- * Host-synchronous: when it returns, X and Y may be freed.  The plan owns its
- * device memory until ffm_destroy.  n_x == 0 or n_y == 0 gives a plan whose
- * apply writes zeros.  Limits: n_x, n_y < 2^31.
+ * When it returns, X and Y may be freed (every read of them is complete).  The
+ * plan's last tables and launch lists may still be in flight on hip_stream:
+ * ffm_apply on any stream is ordered after them on the device (a stream wait,
+ * no host synchronisation), and the other calls that use the plan's device
+ * data (export, set_tiles, batch_create, server_submit, destroy) wait for them
+ * on the host.  The plan owns its device memory until ffm_destroy.  n_x == 0
+ * or n_y == 0 gives a plan whose apply writes zeros.  Limits: n_x, n_y < 2^31.
  */
 ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y,
                       ffm_kernel_t kernel, double k, double eps, const ffm_options_t *opts,
