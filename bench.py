@@ -58,8 +58,8 @@ def _source_hash():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -572,7 +572,9 @@ def main():
         "apply_ms": float(np.mean(rec["apply_ms"])),
         "plan_ms": float(np.mean(rec["plan_ms"])),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
-                       "definition": "per product, from the start of its plan to the end of its apply"},
+                       "definition": "per product, from the start of its plan to the end of its apply",
+                       "per_product": [round(float(x), 3) for x in step_ms]},
+        "plan_ms_per_product": [round(float(x), 3) for x in rec["plan_ms"]],
         "plan_plus_apply_ms": float(np.mean(rec["plan_ms"]) + np.mean(rec["apply_ms"])),
         "sequential_points_per_s": w.n / ((np.mean(rec["plan_ms"]) + np.mean(rec["apply_ms"])) * 1e-3),
         "phases_ms": phases,
