@@ -25,6 +25,7 @@ constexpr int kThreads = 256;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+using gch4 = const __attribute__((address_space(1))) half4_t *;
 
 // sin(2 pi x), cos(2 pi x) for x in revolutions.  The hardware reduces its argument itself over
 // |x| <= 256 revolutions; against an exact reduction to [0, 1) first it differs by at most 2.4e-7
@@ -758,13 +759,18 @@ using gc2 = const __attribute__((address_space(1))) v2f *;
 using gm2 = __attribute__((address_space(1))) v2f *;
 __device__ __forceinline__ gc2 gl(const float2 *p) { return (gc2)p; }
 __device__ __forceinline__ gm2 gw(float2 *p) { return (gm2)p; }
+using gcf = const __attribute__((address_space(1))) float *;
+__device__ __forceinline__ gcf gfl(const float *p) { return (gcf)p; }
+// Read-only views in the constant address space: wave-uniform loads through them are scalar loads.
+using kc2 = const __attribute__((address_space(4))) v2f *;
+__device__ __forceinline__ kc2 kcv(const float2 *p) { return (kc2)p; }
 
 // Sums over z: C[(m, pe)][(ab, pg)] = sum_c Ez_pe[m][c] G_pg[c][ab]; H[m] = C_rr - C_ii + i (C_ri + C_ir) and
 // H[L-m] = C_rr + C_ii + i (C_ri - C_ir) (rings m and L - m have conjugate z tables).  Block: 64 grid columns
 // (16 per wave, held in registers) and a group of up to four 16-ring-pair blocks (grid_z_groups, their z
 // tables staged through LDS); planes 64 at a time, MFMA step s and lane group g taking plane c0 + S g + s.
 // Item (desc, box, column chunk, group).
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
@@ -822,6 +828,7 @@ k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int
                             er[u] = ar[0];
                             ei[u] = ar[16];
                         }
+                        __builtin_amdgcn_sched_barrier(0);   // the group's LDS reads are issued together
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const int s = 4 * s4 + u;
@@ -1160,13 +1167,56 @@ k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     }
 }
 
+// The products of one staged chunk of k_grid_phit: QN column tiles of 16, all eight steps when the chunk is
+// full (its rows past the staged azimuths are zero otherwise), with no conditions inside a step.
+template <int QN>
+__device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const float *Bs, int wv, int li, int lg,
+                                         int steps, floatx4 (&acc)[2][4]) {
+    if (steps == 8) {
+        // two groups of four steps: a group's LDS reads are all issued before its products
+#pragma unroll 1
+        for (int s0 = 0; s0 < 8; s0 += 4) {
+            float ar[4], ai[4], bv[4][QN];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int row = (4 * (s0 + u) + lg) * kRow64;
+                ar[u] = Ar[row + wv * 16 + li];
+                ai[u] = Ai[row + wv * 16 + li];
+#pragma unroll
+                for (int q = 0; q < QN; ++q) bv[u][q] = Bs[row + q * 16 + li];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < QN; ++q) {
+                    acc[0][q] = mfma16(ar[u], bv[u][q], acc[0][q]);
+                    acc[1][q] = mfma16(ai[u], bv[u][q], acc[1][q]);
+                }
+        }
+    } else {
+        for (int s = 0; s < steps; ++s) {
+            const int row = (4 * s + lg) * kRow64;
+            const float ar = Ar[row + wv * 16 + li], ai = Ai[row + wv * 16 + li];
+            float bv[QN];
+#pragma unroll
+            for (int q = 0; q < QN; ++q) bv[q] = Bs[row + q * 16 + li];
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                acc[0][q] = mfma16(ar, bv[q], acc[0][q]);
+                acc[1][q] = mfma16(ai, bv[q], acc[1][q]);
+            }
+        }
+    }
+}
+
 // v~ of ring m back to its plane: H'_pa[a][b] = sum over (n, pe) of A[(a, pa)][(n, pe)] E_pe[b][n] with
 // A = (S_r, -D_i | S_i, D_r), S = conj(Ex) v~(n) + Ex v~(n + L), D = Ex v~(n + L) - conj(Ex) v~(n).  Block: one
 // ring and a 64 x 64 tile of the plane; waves take 16-row blocks of a and all four 16-column blocks of b;
 // azimuths staged through LDS 16 at a time from the transposed tables ([n][node]), step s and lane group g
 // taking azimuth 2 s + g / 2 and part g % 2.  The next chunk's table values and v~ are loaded into registers
 // while the current chunk's products run.  Item (desc, box, ring, tile).
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
@@ -1174,6 +1224,7 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
     const int p = d.gp, L = d.L, mt = min(m, L - m);
     const int nta = (p + 63) / 64;
     const int a0 = (wk.w / nta) * 64, b0 = (wk.w % nta) * 64;
+    const int qn = min(4, (p - b0 + 15) / 16);   // column tiles of 16 inside the grid
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
     __shared__ float Ar[32 * kRow64], Ai[32 * kRow64], Bs[32 * kRow64];
     floatx4 acc[2][4];
@@ -1182,7 +1233,6 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[i][q] = floatx4{0.f, 0.f, 0.f, 0.f};
     const bool act = a0 + wv * 16 < p;
-    const gc2 vt = gl(reinterpret_cast<const float2 *>(d.vt)) + (int64_t)tb * d.npair * 2;
     const int64_t twoL = 2 * (int64_t)L;
     const gc2 ExT = gl(d.ExT) + (int64_t)mt * L * p, EyT = gl(d.EyT) + (int64_t)mt * L * p;
     // v~(m, n) and v~(m, n + L) in the antipodal-pair layout
@@ -1198,7 +1248,9 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
         o2 = (int64_t)m * twoL * 2 + 1;
     }
     dn = 2;
-    const int x = threadIdx.x % 64, nq = threadIdx.x / 64;
+    const int x = threadIdx.x % 64, nq = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    // v~ depends on the azimuth only, one per wave and step: scalar loads into scalar registers
+    const kc2 vts = kcv(reinterpret_cast<const float2 *>(d.vt)) + (int64_t)tb * d.npair * 2;
     v2f exv[4], eyv[4], v1v[4], v2v[4];
     auto fetch = [&](int n0) {
         const int cnt = min(16, L - n0);
@@ -1207,11 +1259,11 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
             const int nl = nq + 4 * it, n = n0 + nl;
             const bool ok = nl < cnt;
             exv[it] = eyv[it] = v1v[it] = v2v[it] = v2f{0.f, 0.f};
-            if (ok && a0 + x < p) {
-                exv[it] = ExT[(int64_t)n * p + a0 + x];
-                v1v[it] = vt[o1 + dn * n];
-                v2v[it] = vt[o2 + dn * n];
+            if (ok) {
+                v1v[it] = vts[o1 + dn * n];
+                v2v[it] = vts[o2 + dn * n];
             }
+            if (ok && a0 + x < p) exv[it] = ExT[(int64_t)n * p + a0 + x];
             if (ok && b0 + x < p) eyv[it] = EyT[(int64_t)n * p + b0 + x];
         }
     };
@@ -1235,20 +1287,15 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
         if (n0 + 16 < L) fetch(n0 + 16);
         __syncthreads();
         if (act) {
+            // branch-free bodies for the common shapes, so that the LDS reads of later steps are issued
+            // ahead of the products (rows past the chunk hold zeros in the partial last chunk)
             const int steps = (2 * cnt + 3) / 4;
-#pragma unroll
-            for (int s = 0; s < 8; ++s)
-                if (s < steps) {
-                    const int row = (4 * s + lg) * kRow64;
-                    const float ar = Ar[row + wv * 16 + li], ai = Ai[row + wv * 16 + li];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (b0 + q * 16 < p) {
-                            const float bv = Bs[row + q * 16 + li];
-                            acc[0][q] = mfma16(ar, bv, acc[0][q]);
-                            acc[1][q] = mfma16(ai, bv, acc[1][q]);
-                        }
-                }
+            switch (qn) {
+                case 4: phit_mma<4>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
+                case 3: phit_mma<3>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
+                case 2: phit_mma<2>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
+                default: phit_mma<1>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
+            }
         }
     }
     if (!act) return;
@@ -1529,14 +1576,24 @@ k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
             acc1[v] = 0.f;
             acc2[v] = 0.f;
         }
-        for (int kk = 0; kk < rp / 2; ++kk) {
-            const int k = 2 * kk + kh;
-            const float bval = U[k * 32 + col];
-            const float a1 = Tre[(int64_t)k * rp + mt * 32 + col];
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bval, acc1, 0, 0, 0);
-            if (helm) {
-                const float a2 = Tim[(int64_t)k * rp + mt * 32 + col];
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bval, acc2, 0, 0, 0);
+        // groups of four steps (rp / 2 is a multiple of 16): the group's operands are loaded before its
+        // products, through global-address-space views of T
+        const gcf TreG = gfl(Tre) + mt * 32 + col, TimG = gfl(Tim) + mt * 32 + col;
+        for (int kk0 = 0; kk0 < rp / 2; kk0 += 4) {
+            float bv[4], a1[4], a2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 2 * (kk0 + u) + kh;
+                bv[u] = U[k * 32 + col];
+                a1[u] = TreG[(int64_t)k * rp];
+                a2[u] = 0.f;
+                if (helm) a2[u] = TimG[(int64_t)k * rp];   // Laplace tables have no imaginary part
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[u], bv[u], acc1, 0, 0, 0);
+                if (helm) acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[u], bv[u], acc2, 0, 0, 0);
             }
         }
         for (int v = 0; v < 16; ++v) {
@@ -1601,14 +1658,24 @@ k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
             acc2[v] = 0.f;
         }
         const int i = mt * 32 + col;
-        for (int k0 = 0; k0 < rp; k0 += 8) {
-            const int k = k0 + 4 * kh;
-            const half4_t b = *reinterpret_cast<const half4_t *>(U16 + col * rp + k);
-            const half4_t a1 = *reinterpret_cast<const half4_t *>(Tre + (int64_t)i * rp + k);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(a1, b, acc1, 0, 0, 0);
-            if (helm) {
-                const half4_t a2 = *reinterpret_cast<const half4_t *>(Tim + (int64_t)i * rp + k);
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x8f16(a2, b, acc2, 0, 0, 0);
+        // groups of four steps (rp is a multiple of 32), operands loaded before the group's products
+        const gch4 TreG = (gch4) reinterpret_cast<const half4_t *>(Tre + (int64_t)i * rp + 4 * kh);
+        const gch4 TimG = (gch4) reinterpret_cast<const half4_t *>(Tim + (int64_t)i * rp + 4 * kh);
+        for (int k00 = 0; k00 < rp; k00 += 32) {
+            half4_t bv[4], a1[4], a2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k0 = k00 + 8 * u;
+                bv[u] = *reinterpret_cast<const half4_t *>(U16 + col * rp + k0 + 4 * kh);
+                a1[u] = TreG[k0 / 4];
+                a2[u] = a1[u];
+                if (helm) a2[u] = TimG[k0 / 4];   // Laplace tables have no imaginary part
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(a1[u], bv[u], acc1, 0, 0, 0);
+                if (helm) acc2 = __builtin_amdgcn_mfma_f32_32x32x8f16(a2[u], bv[u], acc2, 0, 0, 0);
             }
         }
         for (int v = 0; v < 16; ++v) {
