@@ -196,48 +196,58 @@ k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     const int e1 = __builtin_amdgcn_readfirstlane((int)d.far_ptr[t + 1]);
     const float4 *__restrict__ D = d.D;
     const float4 *__restrict__ ut = d.ut;
-    // four far pairs per step, their loads issued together
+    // the far list in chunks of 64 entries, one per lane (a single load and wait per chunk), then four far
+    // pairs per step taken from the lanes' registers, their data loads issued together
     constexpr int U = 4;
-    int e = e0;
-    for (; e + U <= e1; e += U) {
-        int64_t sv[U], cv[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            sv[k] = __builtin_amdgcn_readfirstlane(d.far_src[e + k]);
-            cv[k] = __builtin_amdgcn_readfirstlane(d.far_cls[e + k]);
+    const int lane = threadIdx.x & 63;
+    for (int c0 = e0; c0 < e1; c0 += 64) {
+        const int nch = min(64, e1 - c0);
+        int src_l = 0, cls_l = 0;
+        if (lane < nch) {
+            src_l = d.far_src[c0 + lane];
+            cls_l = d.far_cls[c0 + lane];
         }
+        int k0 = 0;
+        for (; k0 + U <= nch; k0 += U) {
+            int64_t sv[U], cv[U];
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const int64_t p = p0 + (int64_t)j * BS;
-            if (p < npair) {
-                float4 q[U], w[U];
+            for (int k = 0; k < U; ++k) {
+                sv[k] = __builtin_amdgcn_readlane(src_l, k0 + k);
+                cv[k] = __builtin_amdgcn_readlane(cls_l, k0 + k);
+            }
 #pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    q[k] = D[cv[k] * npair + p];
-                    w[k] = ut[sv[k] * npair + p];
-                }
+            for (int j = 0; j < PPT; ++j) {
+                const int64_t p = p0 + (int64_t)j * BS;
+                if (p < npair) {
+                    float4 q[U], w[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    acc[j].x = fmaf(q[k].x, w[k].x, fmaf(-q[k].y, w[k].y, acc[j].x));
-                    acc[j].y = fmaf(q[k].x, w[k].y, fmaf(q[k].y, w[k].x, acc[j].y));
-                    acc[j].z = fmaf(q[k].z, w[k].z, fmaf(-q[k].w, w[k].w, acc[j].z));
-                    acc[j].w = fmaf(q[k].z, w[k].w, fmaf(q[k].w, w[k].z, acc[j].w));
+                    for (int k = 0; k < U; ++k) {
+                        q[k] = D[cv[k] * npair + p];
+                        w[k] = ut[sv[k] * npair + p];
+                    }
+#pragma unroll
+                    for (int k = 0; k < U; ++k) {
+                        acc[j].x = fmaf(q[k].x, w[k].x, fmaf(-q[k].y, w[k].y, acc[j].x));
+                        acc[j].y = fmaf(q[k].x, w[k].y, fmaf(q[k].y, w[k].x, acc[j].y));
+                        acc[j].z = fmaf(q[k].z, w[k].z, fmaf(-q[k].w, w[k].w, acc[j].z));
+                        acc[j].w = fmaf(q[k].z, w[k].w, fmaf(q[k].w, w[k].z, acc[j].w));
+                    }
                 }
             }
         }
-    }
-    for (; e < e1; ++e) {
-        const int64_t s = __builtin_amdgcn_readfirstlane(d.far_src[e]), c = __builtin_amdgcn_readfirstlane(d.far_cls[e]);
+        for (; k0 < nch; ++k0) {
+            const int64_t s = __builtin_amdgcn_readlane(src_l, k0), c = __builtin_amdgcn_readlane(cls_l, k0);
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const int64_t p = p0 + (int64_t)j * BS;
-            if (p < npair) {
-                const float4 q = D[c * npair + p];
-                const float4 w = ut[s * npair + p];
-                acc[j].x = fmaf(q.x, w.x, fmaf(-q.y, w.y, acc[j].x));
-                acc[j].y = fmaf(q.x, w.y, fmaf(q.y, w.x, acc[j].y));
-                acc[j].z = fmaf(q.z, w.z, fmaf(-q.w, w.w, acc[j].z));
-                acc[j].w = fmaf(q.z, w.w, fmaf(q.w, w.z, acc[j].w));
+            for (int j = 0; j < PPT; ++j) {
+                const int64_t p = p0 + (int64_t)j * BS;
+                if (p < npair) {
+                    const float4 q = D[c * npair + p];
+                    const float4 w = ut[s * npair + p];
+                    acc[j].x = fmaf(q.x, w.x, fmaf(-q.y, w.y, acc[j].x));
+                    acc[j].y = fmaf(q.x, w.y, fmaf(q.y, w.x, acc[j].y));
+                    acc[j].z = fmaf(q.z, w.z, fmaf(-q.w, w.w, acc[j].z));
+                    acc[j].w = fmaf(q.z, w.w, fmaf(q.w, w.z, acc[j].w));
+                }
             }
         }
     }
@@ -281,17 +291,34 @@ k_pw_transfer_lds(const LDesc *__restrict__ descs, const IoEntry *__restrict__, 
     };
     const int64_t e0 = d.far_ptr[t], e1 = d.far_ptr[t + 1];
     int64_t e = e0;
+    // groups of four far pairs; the list entries of the next group are loaded while this group's u~ loads
+    // are in flight
+    int sn[4], cn[4];
+    if (e + 4 <= e1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sn[k] = d.far_src[e + k];
+            cn[k] = d.far_cls[e + k];
+        }
+    }
     for (; e + 4 <= e1; e += 4) {
         int64_t sv[4];
         int cv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            sv[k] = d.far_src[e + k];
-            cv[k] = d.far_cls[e + k];
+            sv[k] = sn[k];
+            cv[k] = cn[k];
         }
         float4 w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) w[k] = ut[sv[k] * npair + q];
+        if (e + 8 <= e1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sn[k] = d.far_src[e + 4 + k];
+                cn[k] = d.far_cls[e + 4 + k];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) step(Dq[cv[k] * QT], w[k]);
     }
