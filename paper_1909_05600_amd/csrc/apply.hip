@@ -1566,23 +1566,23 @@ k_lag_anterp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 // C (rp x 32) = T_c (rp x rp) x U (rp x 32), U[k][2m + part] = part of u~_{s(e_m)}[k].
 // v_mfma_f32_32x32x2f32 operands: A[i][k] from lane i + 32 k, B[k][j] from lane j + 32 k,
 // D[i][j] in lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8).  Item (desc, group).
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     extern __shared__ float U[];   // [rp][32]
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int g = wk.y;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
     const int rp = d.rp, helm = d.helm;
     const int c = d.grp_cls[g];
     __shared__ int pe[16], ps[16];
-    if (lane < 16) {
-        const int e = d.grp_pair[(int64_t)g * 16 + lane];
-        pe[lane] = e;
-        ps[lane] = e >= 0 ? d.far_src[e] : -1;
+    if (tid < 16) {
+        const int e = d.grp_pair[(int64_t)g * 16 + tid];
+        pe[tid] = e;
+        ps[tid] = e >= 0 ? d.far_src[e] : -1;
     }
     __syncthreads();
-    for (int idx = lane; idx < rp * 32; idx += 64) {
+    for (int idx = tid; idx < rp * 32; idx += blockDim.x) {
         const int k = idx >> 5, col = idx & 31, m = col >> 1;
         float val = 0.f;
         if (ps[m] >= 0) {
@@ -1597,7 +1597,7 @@ k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
     const float *Tim = Tre + per;
     const int col = lane & 31, kh = lane >> 5;
     const int e = pe[col >> 1];
-    for (int mt = 0; mt < rp / 32; ++mt) {
+    for (int mt = wv; mt < rp / 32; mt += nwv) {   // the waves share the staged sources, one row tile each
         floatx16 acc1, acc2;
         for (int v = 0; v < 16; ++v) {
             acc1[v] = 0.f;
@@ -1606,16 +1606,28 @@ k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
         // groups of four steps (rp / 2 is a multiple of 16): the group's operands are loaded before its
         // products, through global-address-space views of T
         const gcf TreG = gfl(Tre) + mt * 32 + col, TimG = gfl(Tim) + mt * 32 + col;
+        // groups of four steps, double-buffered: the next group's T loads are issued before this group's
+        // products (rp / 2 is a multiple of 16)
+        float a1n[4], a2n[4];
+        auto load = [&](int kk0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 2 * (kk0 + u) + kh;
+                a1n[u] = TreG[(int64_t)k * rp];
+                a2n[u] = 0.f;
+                if (helm) a2n[u] = TimG[(int64_t)k * rp];   // Laplace tables have no imaginary part
+            }
+        };
+        load(0);
         for (int kk0 = 0; kk0 < rp / 2; kk0 += 4) {
             float bv[4], a1[4], a2[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = 2 * (kk0 + u) + kh;
-                bv[u] = U[k * 32 + col];
-                a1[u] = TreG[(int64_t)k * rp];
-                a2[u] = 0.f;
-                if (helm) a2[u] = TimG[(int64_t)k * rp];   // Laplace tables have no imaginary part
+                bv[u] = U[(2 * (kk0 + u) + kh) * 32 + col];
+                a1[u] = a1n[u];
+                a2[u] = a2n[u];
             }
+            if (kk0 + 4 < rp / 2) load(kk0 + 4);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1645,24 +1657,24 @@ __device__ __forceinline__ float u_scale(float amax, int maxpts) {
     return exp2f(floorf(log2f(6.0e4f / bound)));
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     extern __shared__ _Float16 U16[];   // [32][rp]: column-major tile, k contiguous
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int g = wk.y;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
     const int rp = d.rp, helm = d.helm;
     const int c = d.grp_cls[g];
     const float su = u_scale(*d.amax, d.maxpts);
     __shared__ int pe[16], ps[16];
-    if (lane < 16) {
-        const int e = d.grp_pair[(int64_t)g * 16 + lane];
-        pe[lane] = e;
-        ps[lane] = e >= 0 ? d.far_src[e] : -1;
+    if (tid < 16) {
+        const int e = d.grp_pair[(int64_t)g * 16 + tid];
+        pe[tid] = e;
+        ps[tid] = e >= 0 ? d.far_src[e] : -1;
     }
     __syncthreads();
-    for (int idx = lane; idx < rp * 32; idx += 64) {
+    for (int idx = tid; idx < rp * 32; idx += blockDim.x) {
         const int col = idx / rp, k = idx % rp, m = col >> 1;
         float val = 0.f;
         if (ps[m] >= 0) {
@@ -1678,7 +1690,7 @@ k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     const int col = lane & 31, kh = lane >> 5;
     const int e = pe[col >> 1];
     const float inv = 1.f / (d.sT * su);
-    for (int mt = 0; mt < rp / 32; ++mt) {
+    for (int mt = wv; mt < rp / 32; mt += nwv) {   // the waves share the staged sources, one row tile each
         floatx16 acc1, acc2;
         for (int v = 0; v < 16; ++v) {
             acc1[v] = 0.f;
@@ -1688,16 +1700,27 @@ k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
         // groups of four steps (rp is a multiple of 32), operands loaded before the group's products
         const gch4 TreG = (gch4) reinterpret_cast<const half4_t *>(Tre + (int64_t)i * rp + 4 * kh);
         const gch4 TimG = (gch4) reinterpret_cast<const half4_t *>(Tim + (int64_t)i * rp + 4 * kh);
+        // double-buffered as in the FP32 kernel
+        half4_t a1n[4], a2n[4];
+        auto load = [&](int k00) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k0 = k00 + 8 * u;
+                a1n[u] = TreG[k0 / 4];
+                a2n[u] = a1n[u];
+                if (helm) a2n[u] = TimG[k0 / 4];   // Laplace tables have no imaginary part
+            }
+        };
+        load(0);
         for (int k00 = 0; k00 < rp; k00 += 32) {
             half4_t bv[4], a1[4], a2[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k0 = k00 + 8 * u;
-                bv[u] = *reinterpret_cast<const half4_t *>(U16 + col * rp + k0 + 4 * kh);
-                a1[u] = TreG[k0 / 4];
-                a2[u] = a1[u];
-                if (helm) a2[u] = TimG[k0 / 4];   // Laplace tables have no imaginary part
+                bv[u] = *reinterpret_cast<const half4_t *>(U16 + col * rp + k00 + 8 * u + 4 * kh);
+                a1[u] = a1n[u];
+                a2[u] = a2n[u];
             }
+            if (k00 + 32 < rp) load(k00 + 32);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1920,8 +1943,9 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             return S.b ? k_pw_backward_rings<1, 4, true> : k_pw_backward_rings<1, 4, false>;
         case K_BSUM: return k_sum_parts;
         case K_ANTERP: return k_lag_anterp;
-        case K_MFMA32: threads = 64; return k_lag_mfma;
-        case K_MFMA16: threads = 64; return k_lag_mfma16;
+        // a = waves per block (each takes its own 32-row tiles of T over the block's staged sources)
+        case K_MFMA32: threads = 64 * std::max(1, S.a); return k_lag_mfma;
+        case K_MFMA16: threads = 64 * std::max(1, S.a); return k_lag_mfma16;
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
         case K_ZERO_OUT: return k_zero_io;

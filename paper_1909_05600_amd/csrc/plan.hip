@@ -1697,10 +1697,21 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         } else {
             std::vector<int4> an, mf, ip;
             for (int32_t b : LV.h_fwd) an.push_back(make_int4(l, b, 0, 0));
-            for (int32_t g = 0; g < LV.ngrp; ++g) mf.push_back(make_int4(l, g, 0, 0));
+            // class groups are numbered class by class; blocks are dealt to the 8 XCDs in turn, so block b takes
+            // group (b mod 8) per + b / 8 and each XCD works through a contiguous range of classes, reading
+            // each class's T into its own L2 once
+            {
+                constexpr int kXcd = 8;
+                const int32_t per = (LV.ngrp + kXcd - 1) / kXcd;
+                for (int32_t k = 0; k < per; ++k)
+                    for (int x = 0; x < kXcd; ++x) {
+                        const int32_t g = x * per + k;
+                        if (g < LV.ngrp) mf.push_back(make_int4(l, g, 0, 0));
+                    }
+            }
             for (int32_t t : LV.h_tgt) ip.push_back(make_int4(l, t, 0, 0));
             LV.stages.push_back(make_stage(K_ANTERP, 0, 0, s1, l, 0, std::move(an), st, SC));
-            LV.stages.push_back(make_stage(LV.fp16 ? K_MFMA16 : K_MFMA32, 0, 0, s2, l,
+            LV.stages.push_back(make_stage(LV.fp16 ? K_MFMA16 : K_MFMA32, LV.fp16 ? 1 : std::min(4, LV.rp / 32), 0, s2, l,
                                            (size_t)LV.rp * 32 * (LV.fp16 ? 2 : 4), std::move(mf), st, SC));
             LV.stages.push_back(make_stage(K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r, std::move(ip), st, SC));
         }
