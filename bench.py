@@ -78,7 +78,7 @@ def parse():
                     help="only run the single-layer sphere solve (GMRES with FFM products) at --bie-n nodes")
     ap.add_argument("--bie-n", type=int, default=1 << 20)
     ap.add_argument("--bie-eps", type=float, default=1e-3)
-    ap.add_argument("--bie-tol", type=float, default=1e-3)
+    ap.add_argument("--bie-tol", type=float, default=1e-4)
     ap.add_argument("--mixed-rows", type=int, default=1024)
     return ap.parse_args()
 
@@ -346,7 +346,11 @@ def bie_study(n, eps, tol, kernels=(0, 1)):
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
-        sigma, info = bie.solve(A, f, tol=tol, restart=300, maxiter=1500)
+        bie.solve(A, f, tol=0.5, restart=100, maxiter=1)   # warms up the library kernels and the basis memory
+        A.products = 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sigma, info = bie.solve(A, f, tol=tol, restart=100, maxiter=2000)
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t0
         if kernel == 0:

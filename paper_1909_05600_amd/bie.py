@@ -172,9 +172,10 @@ def gmres(matvec, b, tol: float = 1e-5, restart: int = 50, maxiter: int = 500):
         for j in range(m):
             wv = matvec(V[j])
             Vj = V[:j + 1]
-            h = torch.mv(Vj.conj(), wv)
+            # V^H w as conj(V conj(w)): no conjugated copy of the basis
+            h = torch.mv(Vj, wv.conj()).conj()
             wv = wv - h @ Vj
-            h2 = torch.mv(Vj.conj(), wv)
+            h2 = torch.mv(Vj, wv.conj()).conj()
             wv = wv - h2 @ Vj
             hcol = (h + h2).to(torch.complex128).cpu().numpy()
             hn = float(torch.linalg.vector_norm(wv))
