@@ -191,3 +191,35 @@ def test_ring_pair_transforms(orc, eps):
           % (eps, rel(v, vo), rel(v[rows], d), rel(vo[rows], d)))
     assert rel(v, vo) < RTOL_FFM[1]
     assert rel(v[rows], d) <= eps
+
+
+def test_plan_tail_runs_ahead_of_the_caller():
+    """ffm_plan returns with its last tables and launch lists still running on the planning stream.  An apply
+    on another stream issued at once (ordered by the plan's readiness event on the device), an export, a
+    second plan and a destroy right after planning all see a complete plan: results equal those of a plan
+    whose stream was synchronised first, bitwise."""
+    import torch
+    import paper_1909_05600_amd as ffm
+    w = W.helmholtz_sphere(200000, seed=12, k=80.0)
+    X = torch.from_numpy(w.X).cuda()
+    wu = torch.from_numpy(w.wu).cuda()
+    s_plan, s_apply = torch.cuda.Stream(), torch.cuda.Stream()
+    ref_plan = ffm.Plan(X, X, 1, w.k, w.eps, stream=s_plan)
+    torch.cuda.synchronize()
+    ref = ref_plan.apply(wu)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    keys_ref = ref_plan.export(ffm.FFM_EXPORT_FAR, 0, ref_plan.stats()["leaf"])
+    for rep in range(3):
+        p = ffm.Plan(X, X, 1, w.k, w.eps, stream=s_plan)
+        with torch.cuda.stream(s_apply):
+            out = torch.empty(w.n, dtype=torch.complex64, device="cuda")
+        v = p.apply(wu, out=out, stream=s_apply)          # no host synchronisation in between
+        s_apply.synchronize()
+        assert np.array_equal(v.cpu().numpy(), ref), rep
+        q = ffm.Plan(X, X, 1, w.k, w.eps, stream=s_plan)   # export before any apply
+        assert np.array_equal(q.export(ffm.FFM_EXPORT_FAR, 0, q.stats()["leaf"]), keys_ref)
+        q.destroy()
+        ffm.Plan(X, X, 1, w.k, w.eps, stream=s_plan).destroy()   # destroy with the tail still running
+        p.destroy()
+    ref_plan.destroy()
