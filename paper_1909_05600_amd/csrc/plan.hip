@@ -642,30 +642,46 @@ double spread_alias_bound(int w, double beta, double kh) {
     return worst;
 }
 
-// Grid of a grid-form level: spacing h <= hmax over the box edge dl plus the kernel's support, p nodes per axis
-// rounded up to whole 16-row MFMA blocks.  The kernel is the narrowest width w (and its best shape beta among
-// 2.0 w .. 2.3 w) whose aliasing bound at that grid is at most eps / 2.  The bound covers one axis of one
-// transform in the worst direction; measured products err by well under a third of it overall.
-void grid_kernel_choice(double eps, double k, double dl, double hmax, int &w, double &beta, int &p, double &h) {
-    for (int ww = 4; ww <= 8; ++ww) {
-        int pp = (int)std::ceil(dl / hmax) + ww + 1;
-        pp = (pp + 15) / 16 * 16;
-        const double hh = dl / (double)(pp - 1 - ww);
-        double best = 1e300, bb = 2.3 * ww;
-        for (int c = 0; c < 4; ++c) {
-            const double b = (2.0 + 0.1 * c) * ww;
-            const double e = spread_alias_bound(ww, b, k * hh);
-            if (e < best) {
-                best = e;
-                bb = b;
+// Grid of a grid-form level: p nodes per axis (whole 16-row MFMA blocks) of spacing h = dl / (p - 1 - w), so that
+// every point's support lies inside the grid, with |k s_d h| = kh <= kh_max.  For each p from the smallest
+// such multiple of 16 up to two steps larger, the narrowest width w in 4 ... 8 (with the best shape beta among
+// 2.0 w .. 2.3 w) whose aliasing bound at that kh is at most eps / 2 (the bound covers one axis of one transform
+// in the worst direction; measured products err by well under a third of it), and of these (p, w) the one the
+// cost function rates cheapest.  Returns false if none qualifies.
+template <class Cost>
+bool grid_choice(double eps, double k, double dl, double kh_max, const Cost &cost, int &w, double &beta, int &p,
+                 double &h) {
+    double best_cost = 1e300;
+    bool found = false;
+    const int p0 = ((int)std::ceil(dl * k / kh_max) + 4 + 1 + 15) / 16 * 16;
+    for (int pp = p0; pp <= p0 + 32; pp += 16) {
+        for (int ww = 4; ww <= 8; ++ww) {
+            if (pp - 1 - ww <= 0) continue;
+            const double hh = dl / (double)(pp - 1 - ww);
+            if (k * hh > kh_max) continue;
+            double bnd = 1e300, bb = 2.3 * ww;
+            for (int c = 0; c < 4; ++c) {
+                const double b = (2.0 + 0.1 * c) * ww;
+                const double e = spread_alias_bound(ww, b, k * hh);
+                if (e < bnd) {
+                    bnd = e;
+                    bb = b;
+                }
             }
+            if (bnd > eps / 2.0) continue;
+            const double c = cost(pp, ww);
+            if (c < best_cost) {
+                best_cost = c;
+                found = true;
+                w = ww;
+                beta = bb;
+                p = pp;
+                h = hh;
+            }
+            break;   // wider kernels on the same grid only cost more
         }
-        w = ww;
-        beta = bb;
-        p = pp;
-        h = hh;
-        if (best <= eps / 2.0) return;
     }
+    return found;
 }
 
 void gauss_legendre_host(int n, std::vector<double> &x, std::vector<double> &w) {
@@ -1161,30 +1177,34 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             int nphat = 0;
             double dphat_step = 1.0;
             {
-                const double hmax = M_PI / (1.9 * P.k);
-                int w = 0, p = 0;
-                double beta = 0.0, h = 0.0;
-                grid_kernel_choice(P.eps, P.k, dl, hmax, w, beta, p, h);
                 // cost model in seconds, from measured MI355X rates: direct sums 9e-14 s per (point,
                 // direction); grid form: spreading 0.29 ns per point plus 2.5 ns per (box, plane) launch item
                 // and interpolation 0.12 ns per point (w = 6; w^3 nodes per point), and the four sums on FP32
                 // MFMA (real multiply-adds as issued) at a fraction of the 78.6e12 per second peak that falls
                 // with narrower grids (measured 0.5 at 64 nodes, 0.44 at 48, 0.37 at 32; 0.35 above 64)
-                const double nbf = (double)LV.h_fwd.size(), nbt = (double)LV.h_tgt.size(), ws = (double)w / 6.0;
-                const double p2 = (double)p * p, p3 = p2 * p;
-                const double rings16 = 16.0 * ((LV.nrp + 15) / 16), tiles64 = 64.0 * ((p + 63) / 64);
-                const double macs = (nbf + nbt) * 4.0 * rings16 * p3 +                    // over z, both ways
-                                    nbf * 4.0 * p2 * (L + 1.0) * 8.0 * ((L + 7) / 8) +    // plane to directions
-                                    nbt * 4.0 * p * tiles64 * (L + 1.0) * 2.0 * ((L + 1) / 2);   // and back
-                const double eff = p > 64 ? 0.35 : 0.5 * std::pow(p / 64.0, 0.45);
+                const double nbf = (double)LV.h_fwd.size(), nbt = (double)LV.h_tgt.size();
+                auto grid_cost = [&](int pp, int ww) {
+                    const double ws = (double)ww / 6.0, p2 = (double)pp * pp, p3 = p2 * pp;
+                    const double rings16 = 16.0 * ((LV.nrp + 15) / 16), tiles64 = 64.0 * ((pp + 63) / 64);
+                    const double macs = (nbf + nbt) * 4.0 * rings16 * p3 +                    // over z, both ways
+                                        nbf * 4.0 * p2 * (L + 1.0) * 8.0 * ((L + 7) / 8) +    // plane to directions
+                                        nbt * 4.0 * pp * tiles64 * (L + 1.0) * 2.0 * ((L + 1) / 2);   // and back
+                    const double eff = pp > 64 ? 0.35 : 0.5 * std::pow(pp / 64.0, 0.45);
+                    return ws * ws * ws * (0.29e-9 * LV.pts_src + 0.12e-9 * LV.pts_tgt) + 2.5e-9 * nbf * pp +
+                           macs / (eff * 78.6e12);
+                };
+                // grids down to 1.5 nodes per half wavelength: k s_d h <= pi / 1.5, where the kernel's Fourier
+                // transform divided out stays above 0.3 per axis
+                int w = 0, p = 0;
+                double beta = 0.0, h = 0.0;
+                const bool have = grid_choice(P.eps, P.k, dl, M_PI / 1.5, grid_cost, w, beta, p, h);
                 const double direct = (LV.pts_src + LV.pts_tgt) * (double)LV.nq * 9e-14;
-                const double gridc = ws * ws * ws * (0.29e-9 * LV.pts_src + 0.12e-9 * LV.pts_tgt) + 2.5e-9 * nbf * p +
-                                     macs / (eff * 78.6e12);
+                const double gridc = have ? grid_cost(p, w) : 1e300;
                 const size_t gnb = (size_t)std::max(nbx, nby);
                 const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
                 const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
                 const bool force_direct = (P.opt.flags & FFM_FLAG_DIRECT_TRANSFORMS) != 0;
-                LV.grid = !force_direct && L >= 8 && gbytes <= ((size_t)24 << 30) && (force_grid || gridc < direct);
+                LV.grid = have && !force_direct && L >= 8 && gbytes <= ((size_t)24 << 30) && (force_grid || gridc < direct);
                 if (LV.grid) {
                     P.any_grid = true;
                     LV.gw = w;

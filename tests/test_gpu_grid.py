@@ -29,7 +29,9 @@ def test_grid_matches_oracle_and_dense(orc, n, k, seed, eps):
           % (grid_levels, rel(v, vo), rel(v[w.rows], d), rel(v, vd)))
     assert rel(v, vo) < RTOL_FFM[1]
     assert rel(v[w.rows], d) <= w.eps
-    assert rel(v, vd) < 1e-4
+    # both forms are within eps of the product; the grid form keeps its aliasing bound (one axis, worst
+    # direction) at eps / 2, and products measure well under a third of that: the two agree to eps / 4
+    assert rel(v, vd) < w.eps / 4
     assert np.array_equal(v, gpu_apply(gp, w.wu))
 
 
@@ -73,4 +75,4 @@ def test_planner_choice_full_size(orc):
     d = orc.dense_rows(w.X, w.X, w.wu, 1, w.k, w.rows)
     print("auto vs dense %.3e, vs direct %.3e" % (rel(va[w.rows], d), rel(va, vd)))
     assert rel(va[w.rows], d) <= w.eps
-    assert rel(va, vd) < 1e-4
+    assert rel(va, vd) < w.eps / 4      # as in test_grid_matches_oracle_and_dense
