@@ -219,8 +219,10 @@ __device__ __forceinline__ bool is_far(const FarTest &ft, int32_t t, int32_t s) 
 // For every target box t of level l: the children of the near sources of its parent.
 __global__ void __launch_bounds__(kThreads)
 k_list_count(int32_t nbx, const int32_t *parent_x, const int64_t *pnear_ptr, const int32_t *pnear_src,
-             const int32_t *child_y, FarTest ft, int64_t *nfar, int64_t *nnear) {
+             const int32_t *child_y, FarTest ft, int64_t *nfar, int64_t *nnear, int32_t *win_used) {
     int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    // the translation windows the fill marks start cleared
+    for (int32_t i = t; i < kWin3; i += gridDim.x * blockDim.x) win_used[i] = 0;
     if (t >= nbx) return;
     const int32_t T = parent_x[t];
     int64_t cf = 0, cn = 0;
@@ -285,25 +287,24 @@ k_near_pairs(const int64_t *ptr, const int32_t *src, int32_t nbx, const int32_t 
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
-// Translation classes in use, numbered in window order: map[w] = number of used windows before w (one
-// block, an exclusive scan of the flags).
-__global__ void __launch_bounds__(kThreads) k_class_map(const int32_t *used, int nw, int32_t *map) {
+// Far-list windows to class numbers: every block numbers the used windows itself (in window order, a block
+// scan of the flags into LDS), then maps its entries.
+__global__ void __launch_bounds__(kThreads) k_remap(int32_t *cls, int64_t n, const int32_t *used) {
+    __shared__ int32_t map[kWin3];
     __shared__ int32_t part[kThreads];
-    const int per = (nw + kThreads - 1) / kThreads, w0 = threadIdx.x * per;
+    const int per = (kWin3 + kThreads - 1) / kThreads, w0 = threadIdx.x * per;
     int32_t c = 0;
-    for (int w = w0; w < min(nw, w0 + per); ++w) c += used[w] != 0;
+    for (int w = w0; w < min(kWin3, w0 + per); ++w) c += used[w] != 0;
     part[threadIdx.x] = c;
     __syncthreads();
     int32_t off = 0;
-    for (int t = 0; t < (int)threadIdx.x; ++t) off += part[t];
-    for (int w = w0; w < min(nw, w0 + per); ++w) {
+    for (int q = 0; q < (int)threadIdx.x; ++q) off += part[q];
+    for (int w = w0; w < min(kWin3, w0 + per); ++w) {
         map[w] = off;
         off += used[w] != 0;
     }
-}
-
-__global__ void __launch_bounds__(kThreads) k_remap(int32_t *cls, int64_t n, const int32_t *map) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) cls[i] = map[cls[i]];
 }
 
@@ -1032,6 +1033,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     FFM_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
     // translation windows in use per level: read back with the work lists, after the descent
     std::vector<int32_t *> win_used(maxlev + 1, nullptr);
+    int64_t *tot_h = SC.pin<int64_t>(2);      // list totals, written by the scan kernel
     P.leaf = maxlev;
     for (int l = 1; l <= maxlev; ++l) {
         build_level(TX, SX, l, d0, st);
@@ -1054,32 +1056,24 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             LV.win_base[d] = ft.base[d];
         }
         int64_t *cnt_f = SC.get<int64_t>(nbx + 1), *cnt_n = SC.get<int64_t>(nbx + 1);
-        FFM_LAUNCH(k_list_count, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, LP.near_ptr.p,
-                   LP.near_src.p, TY.lev[l - 1].child.p, ft, cnt_f, cnt_n);
+        win_used[l] = SC.get<int32_t>(kWin3);
+        FFM_LAUNCH(k_list_count, nblocks(std::max<int64_t>(nbx, kWin3)), kThreads, 0, st, nbx, TX.lev[l].parent.p,
+                   LP.near_ptr.p, LP.near_src.p, TY.lev[l - 1].child.p, ft, cnt_f, cnt_n, win_used[l]);
         LV.far_ptr.alloc(nbx + 1);
         LV.near_ptr.alloc(nbx + 1);
-        exclusive_scan_i64(cnt_f, LV.far_ptr.p, nbx, st, SC);
-        exclusive_scan_i64(cnt_n, LV.near_ptr.p, nbx, st, SC);
-        int64_t tot[2];
-        FFM_HIP(hipMemcpyAsync(&tot[0], LV.far_ptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        FFM_HIP(hipMemcpyAsync(&tot[1], LV.near_ptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        // both list offsets in one scan; the two totals arrive in host-visible memory
+        exclusive_scan2_i64(cnt_f, LV.far_ptr.p, cnt_n, LV.near_ptr.p, nbx, tot_h, st, SC);
         FFM_HIP(hipStreamSynchronize(st));
-        LV.nfar = tot[0];
-        LV.nnear = tot[1];
+        LV.nfar = tot_h[0];
+        LV.nnear = tot_h[1];
         LV.far_src.alloc(LV.nfar);
         LV.far_cls.alloc(LV.nfar);
         LV.near_src.alloc(std::max<int64_t>(LV.nnear, 1));
-        win_used[l] = SC.get<int32_t>(kWin3);
-        FFM_HIP(hipMemsetAsync(win_used[l], 0, sizeof(int32_t) * kWin3, st));
         FFM_LAUNCH(k_list_fill, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, LP.near_ptr.p, LP.near_src.p,
                    TY.lev[l - 1].child.p, ft, LV.far_ptr.p, LV.near_ptr.p, LV.far_src.p, LV.far_cls.p,
                    LV.near_src.p, win_used[l], bad);
         // compact translation classes (numbered in window order) on the device
-        if (LV.nfar) {
-            int32_t *dmap = SC.get<int32_t>(kWin3);
-            FFM_LAUNCH(k_class_map, 1, kThreads, 0, st, win_used[l], kWin3, dmap);
-            FFM_LAUNCH(k_remap, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, dmap);
-        }
+        if (LV.nfar) FFM_LAUNCH(k_remap, nblocks(LV.nfar), kThreads, 0, st, LV.far_cls.p, LV.nfar, win_used[l]);
         // stopping rule (Sec. 2.2.4)
         const int64_t nb = (int64_t)TX.lev[l].nbox + TY.lev[l].nbox;
         if (LV.nnear == 0 || nx + ny <= (int64_t)P.opt.n_leaf * nb || l == maxlev) {
@@ -1102,7 +1096,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     FFM_HIP(hipMemcpyAsync(used_h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     FFM_HIP(hipStreamSynchronize(st));
     FFM_CHECK(!used_h[0], FFM_EINTERNAL, "ffm_plan: translation outside its window");
-    // translation classes of every level on the host: the same window-order numbering as k_class_map
+    // translation classes of every level on the host: the same window-order numbering as k_remap
     for (int l = 1; l <= P.leaf; ++l) {
         Level &LV = P.lev[l];
         const int32_t *used = used_h + (size_t)kWin3 * l;

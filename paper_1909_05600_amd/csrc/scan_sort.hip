@@ -194,6 +194,81 @@ k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *v
     }
 }
 
+// Two arrays of the same length in one pass: per-block totals of both, then both scans with the block
+// offsets summed in the block; the last block also stores both totals to host-visible memory.
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce2(const T *a, const T *b, int64_t n, T *bsum, int nb) {
+    __shared__ T lw[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T sa = 0, sb = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + (int64_t)j * kScanThreads + threadIdx.x;
+        if (i < n) {
+            sa += a[i];
+            sb += b[i];
+        }
+    }
+    T ta, tb;
+    block_inclusive_sum(sa, lw, ta);
+    block_inclusive_sum(sb, lw, tb);
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = ta;
+        bsum[nb + blockIdx.x] = tb;
+    }
+}
+
+template <class T>
+__device__ T block_prefix_of(const T *bsum, T *red) {
+    T pre = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += kScanThreads) pre += bsum[j];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    T r = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) r += red[w];
+    return r;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_apply2(const T *a, T *oa, const T *b, T *ob, int64_t n, const T *bsum, int nb, T *host_tot) {
+    __shared__ T lw[kScanThreads / 64];
+    __shared__ T red[kScanThreads / 64];
+    const T offa = block_prefix_of(bsum, red);
+    const T offb = block_prefix_of(bsum + nb, red);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T la[kScanItems], lb[kScanItems];
+    T sa = 0, sb = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        la[j] = i < n ? a[i] : T(0);
+        lb[j] = i < n ? b[i] : T(0);
+        sa += la[j];
+        sb += lb[j];
+    }
+    T ta, tb;
+    const T ia = block_inclusive_sum(sa, lw, ta);
+    const T ib = block_inclusive_sum(sb, lw, tb);
+    T ra = offa + ia - sa, rb = offb + ib - sb;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        if (i < n) {
+            oa[i] = ra;
+            ob[i] = rb;
+        }
+        ra += la[j];
+        rb += lb[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        oa[n] = offa + ta;
+        ob[n] = offb + tb;
+        host_tot[0] = offa + ta;
+        host_tot[1] = offb + tb;
+        __threadfence_system();
+    }
+}
+
 }  // namespace
 
 void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st, Scratch &S) {
@@ -201,6 +276,17 @@ void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t 
 }
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st, Scratch &S) {
     exclusive_scan<int32_t>(in, out, n, st, S);
+}
+
+void exclusive_scan2_i64(const int64_t *a, int64_t *oa, const int64_t *b, int64_t *ob, int64_t n, int64_t *host_tot,
+                         hipStream_t st, Scratch &S) {
+    FFM_CHECK(n > 0, FFM_EINTERNAL, "two-array scan of an empty range");
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    FFM_CHECK(nb <= 4096, FFM_EINTERNAL, "two-array scan: too many tiles");
+    int64_t *bsum = S.get<int64_t>(2 * nb);
+    FFM_LAUNCH(k_scan_reduce2<int64_t>, nb, kScanThreads, 0, st, a, b, n, bsum, (int)nb);
+    FFM_LAUNCH(k_scan_apply2<int64_t>, nb, kScanThreads, 0, st, a, oa, b, ob, n, (const int64_t *)bsum, (int)nb,
+               host_tot);
 }
 
 void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st, Scratch &S) {
