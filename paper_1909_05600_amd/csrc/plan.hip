@@ -155,33 +155,85 @@ k_first_level(const uint64_t *key, int64_t n, int8_t *f, int32_t *hist) {
     if (threadIdx.x < 23 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(kThreads) k_flags(const int8_t *f, int64_t n, int l, int32_t *flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flag[i] = (f[i] <= l) ? 1 : 0;
+// A level's boxes in two launches: k_lvl_count counts, per tile of kLvlTile points, the box starts
+// (f[i] <= l); k_lvl_boxes numbers the starts (its tile's offset summed from the counts of the tiles before it,
+// then a block scan) and writes every box's start, integer coordinates and centre and every point's box.
+// Centres c = corner + (2i + 1) * (d_0 2^-(l+1)).
+constexpr int kLvlItems = 8;
+constexpr int kLvlTile = kThreads * kLvlItems;
+
+__global__ void __launch_bounds__(kThreads) k_lvl_count(const int8_t *f, int64_t n, int l, int32_t *tcount) {
+    __shared__ int32_t red[kThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kLvlTile;
+    int32_t c = 0;
+    for (int j = 0; j < kLvlItems; ++j) {
+        const int64_t i = base + (int64_t)j * kThreads + threadIdx.x;
+        if (i < n && f[i] <= l) ++c;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+        tcount[blockIdx.x] = t;
+    }
 }
 
-// Boxes of level l from the scanned start flags; centres c = corner + (2i + 1) * (d_0 2^-(l+1)).
 __global__ void __launch_bounds__(kThreads)
-k_level_boxes(const uint64_t *key, const int8_t *f, const int32_t *pos, int64_t n, int l, double cx, double cy,
-              double cz, double h, int32_t *start, int32_t *ijk, double *ctr, int32_t *boxid, int32_t nbox) {
+k_lvl_boxes(const uint64_t *key, const int8_t *f, int64_t n, int l, const int32_t *tcount, double cx, double cy,
+            double cz, double h, int32_t *start, int32_t *ijk, double *ctr, int32_t *boxid, int32_t nbox) {
 #pragma clang fp contract(off)
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const bool st = f[i] <= l;
-    const int32_t b = pos[i] + (st ? 0 : -1);
-    boxid[i] = b;
-    if (!st) return;
-    start[b] = (int32_t)i;
-    const uint64_t pre = key[i] >> (3 * (kBits - l));
-    const int32_t a0 = compact3(pre >> 2), a1 = compact3(pre >> 1), a2 = compact3(pre);
-    ijk[3 * b] = a0;
-    ijk[3 * b + 1] = a1;
-    ijk[3 * b + 2] = a2;
-    // product and sum rounded separately (no FMA)
-    ctr[3 * b] = cx + (double)(2 * a0 + 1) * h;
-    ctr[3 * b + 1] = cy + (double)(2 * a1 + 1) * h;
-    ctr[3 * b + 2] = cz + (double)(2 * a2 + 1) * h;
-    if (i == 0) start[nbox] = (int32_t)n;
+    __shared__ int32_t red[kThreads / 64];
+    __shared__ int32_t wsum[kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // boxes started in the tiles before this one
+    int32_t pre = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += kThreads) pre += tcount[j];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if (lane == 0) red[wv] = pre;
+    // this thread's kLvlItems consecutive points
+    const int64_t base = (int64_t)blockIdx.x * kLvlTile + (int64_t)threadIdx.x * kLvlItems;
+    bool stt[kLvlItems];
+    int32_t c = 0;
+    for (int j = 0; j < kLvlItems; ++j) {
+        const int64_t i = base + j;
+        stt[j] = i < n && f[i] <= l;
+        c += stt[j];
+    }
+    // block exclusive scan of the per-thread counts
+    int32_t v = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    if (lane == 63) wsum[wv] = v;
+    __syncthreads();
+    int32_t off = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+        off += red[w];
+        if (w < wv) off += wsum[w];
+    }
+    int32_t run = off + v - c;   // boxes started before this thread's first point
+    for (int j = 0; j < kLvlItems; ++j) {
+        const int64_t i = base + j;
+        if (i >= n) break;
+        if (stt[j]) ++run;
+        const int32_t b = run - 1;
+        boxid[i] = b;
+        if (!stt[j]) continue;
+        start[b] = (int32_t)i;
+        const uint64_t pfx = key[i] >> (3 * (kBits - l));
+        const int32_t a0 = compact3(pfx >> 2), a1 = compact3(pfx >> 1), a2 = compact3(pfx);
+        ijk[3 * b] = a0;
+        ijk[3 * b + 1] = a1;
+        ijk[3 * b + 2] = a2;
+        // product and sum rounded separately (no FMA)
+        ctr[3 * b] = cx + (double)(2 * a0 + 1) * h;
+        ctr[3 * b + 1] = cy + (double)(2 * a1 + 1) * h;
+        ctr[3 * b + 2] = cz + (double)(2 * a2 + 1) * h;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[nbox] = (int32_t)n;
 }
 
 // parent of box b (level l) and children of box B (level l-1)
@@ -775,7 +827,7 @@ void build_tree(Tree &T, const double *P, int64_t n, const double corner[3], dou
 
 struct LevelScratch {
     DevBuf<int8_t> f;
-    DevBuf<int32_t> flag, pos, boxid_prev;
+    DevBuf<int32_t> boxid_prev;
     std::vector<int64_t> cum;   // boxes per level (cumulative start counts)
     Scratch *sc = nullptr;
 };
@@ -795,8 +847,6 @@ void first_levels(Tree &T, LevelScratch &S, hipStream_t st) {
         acc += h[l];
         S.cum[l] = acc;
     }
-    S.flag.alloc(n + 1);
-    S.pos.alloc(n + 1);
     T.boxid.alloc(n);
     S.boxid_prev.alloc(n);
 }
@@ -805,15 +855,16 @@ void build_level(Tree &T, LevelScratch &S, int l, double d0, hipStream_t st) {
     const int64_t n = T.n;
     TreeLevel &L = T.lev[l];
     L.nbox = (int32_t)S.cum[l];
-    FFM_LAUNCH(k_flags, nblocks(n), kThreads, 0, st, S.f.p, n, l, S.flag.p);
-    exclusive_scan_i32(S.flag.p, S.pos.p, n, st, *S.sc);
+    const int64_t ntile = (n + kLvlTile - 1) / kLvlTile;
+    int32_t *tcount = S.sc->get<int32_t>(std::max<int64_t>(ntile, 1));
+    FFM_LAUNCH(k_lvl_count, ntile, kThreads, 0, st, S.f.p, n, l, tcount);
     L.start.alloc(L.nbox + 1);
     L.ijk.alloc((size_t)3 * L.nbox);
     L.ctr.alloc((size_t)3 * L.nbox);
     if (l > 0) std::swap(S.boxid_prev, T.boxid);
     const double h = std::ldexp(d0, -(l + 1));
-    FFM_LAUNCH(k_level_boxes, nblocks(n), kThreads, 0, st, T.key.p, S.f.p, S.pos.p, n, l, T.corner[0], T.corner[1],
-               T.corner[2], h, L.start.p, L.ijk.p, L.ctr.p, T.boxid.p, L.nbox);
+    FFM_LAUNCH(k_lvl_boxes, ntile, kThreads, 0, st, T.key.p, S.f.p, n, l, (const int32_t *)tcount, T.corner[0],
+               T.corner[1], T.corner[2], h, L.start.p, L.ijk.p, L.ctr.p, T.boxid.p, L.nbox);
     if (l > 0) {
         TreeLevel &Pl = T.lev[l - 1];
         L.parent.alloc(L.nbox);
