@@ -588,6 +588,8 @@ def main():
         "kernels_ms_per_step": {k: round(v, 4) for k, v in kernel_totals(rec["launches"], args.steps).items()},
         "levels": {"leaf": leaf, "nq": [int(x) for x in st["nq"][:leaf + 1]],
                    "transform_form": [int(x) for x in st["tform"][:leaf + 1]],
+                   "grid_nodes": [int(x) for x in st["grid_nodes"][:leaf + 1]],
+                   "grid_width": [int(x) for x in st["grid_width"][:leaf + 1]],
                    "nfar": [int(x) for x in st["nfar"][:leaf + 1]], "near_pairs": st["near_pairs"],
                    "transform_terms": st["transform_terms"]},
     }

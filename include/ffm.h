@@ -159,6 +159,7 @@ typedef struct {
     int32_t grid_nodes[FFM_MAX_LEVELS];    /* grid form: nodes p per axis of each box's grid, else 0 */
     int64_t fwd_boxes[FFM_MAX_LEVELS];     /* source boxes transformed at level l         */
     int64_t bwd_boxes[FFM_MAX_LEVELS];     /* target boxes transformed at level l         */
+    int32_t grid_width[FFM_MAX_LEVELS];    /* grid form: spreading kernel width w in nodes, else 0 */
 } ffm_stats_t;
 
 ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out);

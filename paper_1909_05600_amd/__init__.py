@@ -61,7 +61,7 @@ class Stats(C.Structure):
                 ("bwd_points", C.c_double * _L), ("transform_terms", C.c_double),
                 ("transfer_macs", C.c_double), ("near_pairs", C.c_double), ("plan_bytes", C.c_double),
                 ("workspace_bytes", C.c_double), ("grid_nodes", C.c_int32 * _L), ("fwd_boxes", C.c_int64 * _L),
-                ("bwd_boxes", C.c_int64 * _L)]
+                ("bwd_boxes", C.c_int64 * _L), ("grid_width", C.c_int32 * _L)]
 
     def as_dict(self) -> dict:
         out = {}

@@ -2,6 +2,7 @@
 //
 //   fma32  FP32 FMA (non-packed)            -> TFLOP/s (2 flops per FMA)
 //   fma64  FP64 FMA                         -> TFLOP/s
+//   mfma32 FP32 matrix core, 16x16x4 blocks -> TFLOP/s (2 flops per multiply-add)
 //   sin    v_sin_f32 (revolutions)          -> G evaluations/s
 //   pw32   plane-wave transform inner step  -> G (point, direction-pair) updates/s, FP32 phase
 //   pw64   the same with an FP64 phase      -> G updates/s
@@ -45,6 +46,20 @@ __global__ void __launch_bounds__(kThreads) k_fma64(double *out, double b, doubl
         for (int i = 0; i < 8; ++i) a[i] = fma(a[i], b, c);
     double s = 0.0;
     for (int i = 0; i < 8; ++i) s += a[i];
+    out[blockIdx.x * kThreads + threadIdx.x] = s;
+}
+
+// Eight independent accumulator tiles per wave, so that the matrix pipe never waits on a result.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(kThreads) k_mfma32(float *out, float b) {
+    floatx4 acc[8];
+    for (int i = 0; i < 8; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float a = threadIdx.x * 1e-3f;
+    for (int it = 0; it < kIter; ++it)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
+    float s = 0.f;
+    for (int i = 0; i < 8; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
     out[blockIdx.x * kThreads + threadIdx.x] = s;
 }
 
@@ -133,6 +148,9 @@ int main() {
     std::printf("fma32  %8.2f TFLOP/s\n", threads * kIter * 8 * 2 / t / 1e12);
     t = timeit([&] { hipLaunchKernelGGL(k_fma64, dim3(grid), dim3(kThreads), 0, 0, od, 0.999, 1e-3); });
     std::printf("fma64  %8.2f TFLOP/s\n", threads * kIter * 8 * 2 / t / 1e12);
+    t = timeit([&] { hipLaunchKernelGGL(k_mfma32, dim3(grid / 4), dim3(kThreads), 0, 0, of, 0.999f); });
+    // per wave and iteration: 8 products of 16 x 16 x 4 multiply-adds
+    std::printf("mfma32 %8.2f TFLOP/s\n", (double)grid / 4 * (kThreads / 64) * kIter * 8 * 16 * 16 * 4 * 2 / t / 1e12);
     t = timeit([&] { hipLaunchKernelGGL(k_sin, dim3(grid), dim3(kThreads), 0, 0, of); });
     const double sin_rate = threads * kIter * 8 / t;
     std::printf("sin    %8.2f G/s  (%.2f lanes/clk/CU)\n", sin_rate / 1e9, sin_rate / (ncu * prop.clockRate * 1e3));

@@ -1466,6 +1466,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.phase64[l] = LV.method == kGegenbauer && LV.phase64 ? 1 : 0;
         s.bwd_points[l] = LV.pts_tgt;
         s.grid_nodes[l] = LV.method == kGegenbauer && LV.grid ? LV.gp : 0;
+        s.grid_width[l] = LV.method == kGegenbauer && LV.grid ? LV.gw : 0;
         s.fwd_boxes[l] = (int64_t)LV.h_fwd.size();
         s.bwd_boxes[l] = (int64_t)LV.h_tgt.size();
         if (LV.method == kGegenbauer) {
