@@ -179,16 +179,11 @@ k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     }
 }
 
-// Diagonal transfer v~_t(q) = sum_{s in far(t)} D_{c(t,s)}(q) u~_s(q) (both directions of a pair).
-// Item (desc, target box, tile of 256 PPT pairs).
+// Diagonal transfer v~_t(q) = sum_{s in far(t)} D_{c(t,s)}(q) u~_s(q) (both directions of a pair), for
+// target t and the pairs p0 + j BS, j < PPT (t the same across the wave).
 template <int PPT, int BS>
-__global__ void __launch_bounds__(BS)
-k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
-    const int4 wk = work[blockIdx.x];
-    const LDesc &d = descs[wk.x];
-    const int t = wk.y;
+__device__ __forceinline__ void transfer_target(const LDesc &d, int t, int64_t p0) {
     const int64_t npair = d.npair;
-    const int64_t p0 = (int64_t)wk.z * BS * PPT + threadIdx.x;
     float4 acc[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -256,6 +251,26 @@ k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
         const int64_t p = p0 + (int64_t)j * BS;
         if (p < npair) d.vt[(int64_t)t * npair + p] = acc[j];
     }
+}
+
+// Item (desc, target box, tile of BS PPT pairs).
+template <int PPT, int BS>
+__global__ void __launch_bounds__(BS)
+k_pw_transfer(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    transfer_target<PPT, BS>(descs[wk.x], wk.y, (int64_t)wk.z * BS * PPT + threadIdx.x);
+}
+
+// Four consecutive target slots (Morton order) per block, one per wave, on the same tile of 64 pairs: a
+// quarter of the blocks and work items of one target per block, for the same work per wave.  Item (desc,
+// group of four slots, tile).
+__global__ void __launch_bounds__(kThreads)
+k_pw_transfer_grp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int ti = __builtin_amdgcn_readfirstlane(wk.y * 4 + (int)(threadIdx.x >> 6));
+    if (ti >= d.ntr) return;
+    transfer_target<1, 64>(d, __builtin_amdgcn_readfirstlane(d.tr_tgt[ti]), (int64_t)wk.z * 64 + (threadIdx.x & 63));
 }
 
 // The same transfer for levels with many direction pairs per box.  Block: a
@@ -1927,6 +1942,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
                 case 1002: return k_pw_transfer_lds<2>;
                 case 1001: return k_pw_transfer_lds<1>;
                 case 101: threads = 64; return k_pw_transfer<1, 64>;
+                case 201: return k_pw_transfer_grp;
                 case 2: return k_pw_transfer<2, kThreads>;
                 default: return k_pw_transfer<1, kThreads>;
             }
@@ -2097,6 +2113,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_TRANSFER:
             if (a > 1000) return "k_pw_transfer_lds<" + std::to_string(a - 1000) + ">";
             if (a == 101) return "k_pw_transfer<1, 64>";
+            if (a == 201) return "k_pw_transfer_grp";
             return "k_pw_transfer<" + std::to_string(a == 2 ? 2 : 1) + ", 256>";
         case K_BWD_PAIR: return "k_pw_backward<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
         case K_BWD_RING:

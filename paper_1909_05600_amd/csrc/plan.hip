@@ -1607,8 +1607,12 @@ static Stage transfer_stage(int l, const Level &LV, int slot, hipStream_t st, Sc
     }
     int bs, ppt;
     pick_pair_tile(LV.npair, 2, bs, ppt);
-    return make_stage(K_TRANSFER, ppt + (bs == 64 ? 100 : 0), 0, slot, l, 0,
-                      transfer_items(l, LV.h_tgt, LV.npair, false, 1, bs * ppt), st, SC);
+    // 64-pair tiles: four consecutive targets per block (measured faster over a whole product than one target
+    // per block, mostly through the plan's four times fewer work items)
+    if (bs == 64)
+        return make_stage(K_TRANSFER, 201, 0, slot, l, 0, transfer_items(l, LV.h_tgt, LV.npair, true, 64, 64), st, SC);
+    return make_stage(K_TRANSFER, ppt, 0, slot, l, 0, transfer_items(l, LV.h_tgt, LV.npair, false, 1, bs * ppt), st,
+                      SC);
 }
 
 
