@@ -1535,19 +1535,22 @@ void upload_stage_items(const std::vector<Stage *> &stages, DevBuf<int4> &arena,
 // ranges interleaved so that block b takes range b mod 8: workgroups are dealt to the 8 XCDs of the chip in
 // turn, so each XCD works through one contiguous region, and neighbouring targets, which share most of their
 // far sources, find u~ in that XCD's L2.
-static std::vector<int4> transfer_items(int l, const std::vector<int32_t> &tgt_by_size, int64_t npair, bool lds,
-                                        int qt, int tile) {
-    // targets in Morton (box id) order: flags over the id range instead of a comparison sort
-    std::vector<int32_t> tg;
-    {
-        int32_t hi = 0;
-        for (int32_t t : tgt_by_size) hi = std::max(hi, t + 1);
-        std::vector<char> on((size_t)hi, 0);
-        for (int32_t t : tgt_by_size) on[(size_t)t] = 1;
-        tg.reserve(tgt_by_size.size());
-        for (int32_t t = 0; t < hi; ++t)
-            if (on[(size_t)t]) tg.push_back(t);
-    }
+// Distinct box ids in increasing (Morton) order: flags over the id range instead of a comparison sort.
+static std::vector<int32_t> morton_order(const std::vector<int32_t> &boxes) {
+    int32_t hi = 0;
+    for (int32_t t : boxes) hi = std::max(hi, t + 1);
+    std::vector<char> on((size_t)hi, 0);
+    for (int32_t t : boxes) on[(size_t)t] = 1;
+    std::vector<int32_t> out;
+    out.reserve(boxes.size());
+    for (int32_t t = 0; t < hi; ++t)
+        if (on[(size_t)t]) out.push_back(t);
+    return out;
+}
+
+// tg: the targets with far work in Morton order
+static std::vector<int4> transfer_items(int l, const std::vector<int32_t> &tg, int64_t npair, bool lds, int qt,
+                                        int tile) {
     const int64_t n = lds ? ((int64_t)tg.size() + kThreads / qt - 1) / (kThreads / qt) : (int64_t)tg.size();
     const int64_t ntiles = (npair + tile - 1) / tile;
     constexpr int kXcd = 8;
@@ -1599,20 +1602,20 @@ static void pick_pair_tile(int64_t npair, int ppt_max, int &bs, int &ppt) {
 
 // The transfer stage of a Gegenbauer level: class tables in LDS where boxes have many direction pairs
 // (measured faster from n_pair ~ 4096 on), one target per block otherwise.
-static Stage transfer_stage(int l, const Level &LV, int slot, hipStream_t st, Scratch &SC) {
+static Stage transfer_stage(int l, const Level &LV, const std::vector<int32_t> &tg, int slot, hipStream_t st,
+                            Scratch &SC) {
     if (LV.npair >= 4096) {
         const int qt = transfer_qt(LV.ncls);
         return make_stage(K_TRANSFER, 1000 + qt, 0, slot, l, sizeof(float4) * LV.ncls * qt,
-                          transfer_items(l, LV.h_tgt, LV.npair, true, qt, qt), st, SC);
+                          transfer_items(l, tg, LV.npair, true, qt, qt), st, SC);
     }
     int bs, ppt;
     pick_pair_tile(LV.npair, 2, bs, ppt);
     // 64-pair tiles: four consecutive targets per block (measured faster over a whole product than one target
     // per block, mostly through the plan's four times fewer work items)
     if (bs == 64)
-        return make_stage(K_TRANSFER, 201, 0, slot, l, 0, transfer_items(l, LV.h_tgt, LV.npair, true, 64, 64), st, SC);
-    return make_stage(K_TRANSFER, ppt, 0, slot, l, 0, transfer_items(l, LV.h_tgt, LV.npair, false, 1, bs * ppt), st,
-                      SC);
+        return make_stage(K_TRANSFER, 201, 0, slot, l, 0, transfer_items(l, tg, LV.npair, true, 64, 64), st, SC);
+    return make_stage(K_TRANSFER, ppt, 0, slot, l, 0, transfer_items(l, tg, LV.npair, false, 1, bs * ppt), st, SC);
 }
 
 
@@ -1651,10 +1654,10 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         if (LV.method == kNone) continue;
         const int s1 = 1 + 3 * (l - 1), s2 = s1 + 1, s3 = s1 + 2;
         const std::vector<int32_t> &sx = LV.h_sx;
+        // transfer slots: the targets with far work in Morton order
+        std::vector<int32_t> tg;
         if (LV.method == kGegenbauer) {
-            // transfer slots: the targets with far work in Morton order
-            std::vector<int32_t> tg(LV.h_tgt);
-            std::sort(tg.begin(), tg.end());
+            tg = morton_order(LV.h_tgt);
             upload(LV.tr_tgt, tg, st, SC);
         }
         if (LV.method == kGegenbauer && LV.grid) {
@@ -1689,7 +1692,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
                                            std::move(a1), st, SC));
             LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
             LV.stages.push_back(make_stage(K_GPHI, p <= 64 ? p / 16 : 0, 0, s1, l, 0, std::move(a3), st, SC));
-            LV.stages.push_back(transfer_stage(l, LV, s2, st, SC));
+            LV.stages.push_back(transfer_stage(l, LV, tg, s2, st, SC));
             for (int m : ring_order)
                 for (int32_t t : LV.h_tgt)
                     for (int q = 0; q < nta * nta; ++q) b1.push_back(make_int4(l, t, m, q));
@@ -1740,7 +1743,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
                                                std::move(fw), st, SC));
             }
             std::vector<int4> bw;
-            LV.stages.push_back(transfer_stage(l, LV, s2, st, SC));
+            LV.stages.push_back(transfer_stage(l, LV, tg, s2, st, SC));
             // direction-pair target transform: 64-point blocks where target boxes are small
             const bool small = !LV.qG && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
             if (small) LV.bwd_tile = 64;
