@@ -1209,37 +1209,37 @@ k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     }
 }
 
-// The products of one staged chunk of k_grid_phit: QN column tiles of 16, all eight steps when the chunk is
-// full (its rows past the staged azimuths are zero otherwise), with no conditions inside a step.
+// The products of steps s_lo .. s_hi - 1 of one staged chunk of k_grid_phit for the 16-row block ab of a: QN
+// column tiles of 16, in groups of four steps where the range allows (a group's LDS reads are all issued before
+// its products; rows past the staged azimuths of a partial chunk are zero), with no conditions inside a step.
 template <int QN>
-__device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const float *Bs, int wv, int li, int lg,
-                                         int steps, floatx4 (&acc)[2][4]) {
-    if (steps == 8) {
-        // two groups of four steps: a group's LDS reads are all issued before its products
+__device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const float *Bs, int ab, int li, int lg,
+                                         int s_lo, int s_hi, floatx4 (&acc)[2][4]) {
+    int s0 = s_lo;
 #pragma unroll 1
-        for (int s0 = 0; s0 < 8; s0 += 4) {
-            float ar[4], ai[4], bv[4][QN];
+    for (; s0 + 4 <= s_hi; s0 += 4) {
+        float ar[4], ai[4], bv[4][QN];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int row = (4 * (s0 + u) + lg) * kRow64;
-                ar[u] = Ar[row + wv * 16 + li];
-                ai[u] = Ai[row + wv * 16 + li];
+        for (int u = 0; u < 4; ++u) {
+            const int row = (4 * (s0 + u) + lg) * kRow64;
+            ar[u] = Ar[row + ab * 16 + li];
+            ai[u] = Ai[row + ab * 16 + li];
 #pragma unroll
-                for (int q = 0; q < QN; ++q) bv[u][q] = Bs[row + q * 16 + li];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int q = 0; q < QN; ++q) {
-                    acc[0][q] = mfma16(ar[u], bv[u][q], acc[0][q]);
-                    acc[1][q] = mfma16(ai[u], bv[u][q], acc[1][q]);
-                }
+            for (int q = 0; q < QN; ++q) bv[u][q] = Bs[row + q * 16 + li];
         }
-    } else {
-        for (int s = 0; s < steps; ++s) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                acc[0][q] = mfma16(ar[u], bv[u][q], acc[0][q]);
+                acc[1][q] = mfma16(ai[u], bv[u][q], acc[1][q]);
+            }
+    }
+    {
+        for (int s = s0; s < s_hi; ++s) {
             const int row = (4 * s + lg) * kRow64;
-            const float ar = Ar[row + wv * 16 + li], ai = Ai[row + wv * 16 + li];
+            const float ar = Ar[row + ab * 16 + li], ai = Ai[row + ab * 16 + li];
             float bv[QN];
 #pragma unroll
             for (int q = 0; q < QN; ++q) bv[q] = Bs[row + q * 16 + li];
@@ -1256,8 +1256,10 @@ __device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const
 // A = (S_r, -D_i | S_i, D_r), S = conj(Ex) v~(n) + Ex v~(n + L), D = Ex v~(n + L) - conj(Ex) v~(n).  Block: one
 // ring and a 64 x 64 tile of the plane; waves take 16-row blocks of a and all four 16-column blocks of b;
 // azimuths staged through LDS 16 at a time from the transposed tables ([n][node]), step s and lane group g
-// taking azimuth 2 s + g / 2 and part g % 2.  The next chunk's table values and v~ are loaded into registers
-// while the current chunk's products run.  Item (desc, box, ring, tile).
+// taking azimuth 2 s + g / 2 and part g % 2.  Where the tile has only one or two 16-row blocks of a (grids of
+// 16 or 32 nodes, edge tiles), the otherwise idle waves take a share of each chunk's steps, and their partial
+// sums are added to the first share's through LDS, in the order of the shares.  The next chunk's table values
+// and v~ are loaded into registers while the current chunk's products run.  Item (desc, box, ring, tile).
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
@@ -1268,13 +1270,19 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
     const int a0 = (wk.w / nta) * 64, b0 = (wk.w % nta) * 64;
     const int qn = min(4, (p - b0 + 15) / 16);   // column tiles of 16 inside the grid
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
-    __shared__ float Ar[32 * kRow64], Ai[32 * kRow64], Bs[32 * kRow64];
+    __shared__ float lds[3 * 32 * kRow64];
+    float *const Ar = lds, *const Ai = lds + 32 * kRow64, *const Bs = lds + 2 * 32 * kRow64;
     floatx4 acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[i][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const bool act = a0 + wv * 16 < p;
+    // row blocks of a in the tile, shares of the steps, this wave's row block and share
+    const int nab = min(4, (p - a0 + 15) / 16);
+    const int ks = nab == 1 ? 4 : (nab == 2 ? 2 : 1);
+    const int ab = wv % nab, kp = wv / nab;
+    const bool act = kp < ks;
+    constexpr int kStepsPerChunk = 8;
     const int64_t twoL = 2 * (int64_t)L;
     const gc2 ExT = gl(d.ExT) + (int64_t)mt * L * p, EyT = gl(d.EyT) + (int64_t)mt * L * p;
     // v~(m, n) and v~(m, n + L) in the antipodal-pair layout
@@ -1332,15 +1340,41 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
             // branch-free bodies for the common shapes, so that the LDS reads of later steps are issued
             // ahead of the products (rows past the chunk hold zeros in the partial last chunk)
             const int steps = (2 * cnt + 3) / 4;
+            const int s_lo = kp * (kStepsPerChunk / ks), s_hi = min(steps, s_lo + kStepsPerChunk / ks);
             switch (qn) {
-                case 4: phit_mma<4>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
-                case 3: phit_mma<3>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
-                case 2: phit_mma<2>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
-                default: phit_mma<1>(Ar, Ai, Bs, wv, li, lg, steps, acc); break;
+                case 4: phit_mma<4>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                case 3: phit_mma<3>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                case 2: phit_mma<2>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                default: phit_mma<1>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
             }
         }
     }
-    if (!act) return;
+    if (ks > 1) {
+        // shares 1 .. ks-1 through LDS (32 floats per lane and share: [part][column tile][row]), added to share 0
+        // in share order; at most 3 x 2048 floats, within the staging arrays
+        __syncthreads();
+        if (act && kp > 0) {
+            float *red = lds + ((kp - 1) * nab + ab) * 2048 + lane;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) red[((i * 4 + q) * 4 + r) * 64] = acc[i][q][r];
+        }
+        __syncthreads();
+        if (act && kp == 0)
+            for (int k = 1; k < ks; ++k) {
+                const float *red = lds + ((k - 1) * nab + ab) * 2048 + lane;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[i][q][r] += red[((i * 4 + q) * 4 + r) * 64];
+            }
+    }
+    if (!act || kp > 0) return;
     const gm2 Hb = gw(d.H) + ((int64_t)m * d.gnbox + tb) * p * p;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1348,7 +1382,7 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
         if (b >= p) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int a = a0 + wv * 16 + 4 * lg + r;
+            const int a = a0 + ab * 16 + 4 * lg + r;
             Hb[(int64_t)a * p + b] = v2f{acc[0][q][r], acc[1][q][r]};
         }
     }
