@@ -1085,6 +1085,175 @@ k_grid_phi(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
     }
 }
 
+// The MFMA steps of k_grid_phi_r: 16 P16 steps over all staged rows (groups of four whose LDS operands are read
+// together before their products), NT column tiles, the A operand (H rows) in registers.
+template <int P16, int NT>
+__device__ __forceinline__ void phi_steps_r(const float *bl, const float (&hr)[4 * P16], const float (&hi)[4 * P16],
+                                            floatx4 (&acc)[2][4]) {
+#pragma unroll
+    for (int g = 0; g < P16; ++g) {
+        float bv[4][NT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bv[u][t] = bl[4 * (4 * g + u) * kRow64 + t * 16];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                acc[0][t] = mfma16(hr[4 * g + u], bv[u][t], acc[0][t]);
+                acc[1][t] = mfma16(hi[4 * g + u], bv[u][t], acc[1][t]);
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The sums of k_grid_phi for grids of P = 16 P16 nodes, 64 < P <= 128: rounds of four 16-row blocks of a on
+// the outside, each wave's H rows over the whole of b loaded once per round into registers (4 P16 values per
+// lane and part), and every chunk of 32 azimuths staged with all of Ey's P rows.  The partial sums of a round
+// (over its rows, the two parts and the four lane groups, in that order) are added to u~ in round order by the
+// thread that owns the azimuth.  Item (desc, box, ring, 0).
+template <int P16>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_grid_phi_r(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    constexpr int P = 16 * P16, S = 4 * P16;        // nodes; MFMA steps (b = S g + s for lane group g, step s)
+    constexpr int kExRow = 68;                       // 32 complex azimuths + pad, in floats
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int sb = wk.y, m = wk.z;
+    const int L = d.L, mt = min(m, L - m);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    __shared__ float Bs[P * kRow64];
+    __shared__ float Exs[64 * kExRow];
+    __shared__ float4 red[4][4][32];                 // [wave][lane group][azimuth]
+    const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + sb) * P * P;
+    const gc2 Ey = gl(d.Ey) + (int64_t)mt * P * L;
+    const gc2 Ex = gl(d.Ex) + (int64_t)mt * P * L;
+    const gm2 ut = gw(reinterpret_cast<float2 *>(d.ut)) + (int64_t)sb * d.npair * 2;
+    const int64_t twoL = 2 * (int64_t)L;
+    const float *bl = Bs + lg * kRow64 + li;
+    for (int rd = 0; rd < (P16 + 3) / 4; ++rd) {
+        const int blk = rd * 4 + wv, nact = min(4, P16 - rd * 4), na = min(64, P - rd * 64);
+        const bool act = blk < P16;
+        float hr[S], hi[S];
+        if (act) {
+            const gc2 hrow = H + (int64_t)(blk * 16 + li) * P + S * lg;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const v2f h = hrow[s];
+                hr[s] = h.x;
+                hi[s] = h.y;
+            }
+        }
+        for (int n0 = 0; n0 < L; n0 += 32) {
+            const int ntile = min(4, (L - n0 + 7) / 8);
+            __syncthreads();
+            {
+                // Ey rows q < P and Ex rows q < na of this round, azimuth n0 + nl; loads in flight together
+                const int nl = threadIdx.x % 32, n = n0 + nl, q0 = threadIdx.x / 32;
+                v2f ey[P / 8], ex[8];
+#pragma unroll
+                for (int it = 0; it < P / 8; ++it) {
+                    const int q = q0 + 8 * it;
+                    ey[it] = n < L ? Ey[(int64_t)q * L + n] : v2f{0.f, 0.f};
+                }
+#pragma unroll
+                for (int it = 0; it < 8; ++it) {
+                    const int q = q0 + 8 * it;
+                    ex[it] = (q < na && n < L) ? Ex[(int64_t)(rd * 64 + q) * L + n] : v2f{0.f, 0.f};
+                }
+#pragma unroll
+                for (int it = 0; it < P / 8; ++it) {
+                    const int q = q0 + 8 * it;
+                    float *r = Bs + (4 * (q % S) + q / S) * kRow64 + (nl >> 3) * 16 + (nl & 7);
+                    r[0] = ey[it].x;
+                    r[8] = ey[it].y;
+                }
+#pragma unroll
+                for (int it = 0; it < 8; ++it)
+                    reinterpret_cast<float2 *>(Exs + (q0 + 8 * it) * kExRow)[nl] = make_float2(ex[it].x, ex[it].y);
+            }
+            __syncthreads();
+            float4 tot[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) tot[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (act) {
+                floatx4 acc[2][4];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc[i][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+                switch (ntile) {
+                    case 1: phi_steps_r<P16, 1>(bl, hr, hi, acc); break;
+                    case 2: phi_steps_r<P16, 2>(bl, hr, hi, acc); break;
+                    case 3: phi_steps_r<P16, 3>(bl, hr, hi, acc); break;
+                    default: phi_steps_r<P16, 4>(bl, hr, hi, acc); break;
+                }
+                const bool im = li >= 8;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (t >= ntile) continue;
+                    const int nl = 8 * t + (li & 7);
+                    float fr = 0.f, fi = 0.f, gr = 0.f, gi = 0.f;   // sum Ex z, sum conj(Ex) z over this lane's rows
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float2 ex = reinterpret_cast<const float2 *>(Exs + (wv * 16 + 4 * lg + r) * kExRow)[nl];
+                        const float x = acc[0][t][r], y = acc[1][t][r];
+                        fr = fmaf(ex.x, x, fmaf(-ex.y, y, fr));
+                        fi = fmaf(ex.x, y, fmaf(ex.y, x, fi));
+                        gr = fmaf(ex.x, x, fmaf(ex.y, y, gr));
+                        gi = fmaf(ex.x, y, fmaf(-ex.y, x, gi));
+                    }
+                    // the imaginary-part columns hold z1: contribute i F and -i G
+                    float t0 = im ? -fi : fr, t1 = im ? fr : fi, t2 = im ? gi : gr, t3 = im ? -gr : gi;
+                    t0 += __shfl_xor(t0, 8, 64);
+                    t1 += __shfl_xor(t1, 8, 64);
+                    t2 += __shfl_xor(t2, 8, 64);
+                    t3 += __shfl_xor(t3, 8, 64);
+                    tot[t] = make_float4(t0, t1, t2, t3);
+                }
+            }
+            if (li < 8) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) red[wv][lg][8 * t + li] = tot[t];
+            }
+            __syncthreads();
+            const int nl = threadIdx.x, n = n0 + nl;
+            if (nl < 32 && n < L) {
+                float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int w = 0; w < nact; ++w)
+                    for (int g = 0; g < 4; ++g) {
+                        const float4 b = red[w][g][nl];
+                        a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+                    }
+                // a.xy: u~(m, n), a.zw: u~(m, n + L), added to the earlier rounds' sums in the antipodal-pair layout
+                int64_t i1, i2;
+                if (2 * m < L) {
+                    i1 = (m * twoL + n) * 2;
+                    i2 = (m * twoL + n + L) * 2;
+                } else if (2 * m > L) {
+                    const int64_t m2 = L - m;
+                    i1 = (m2 * twoL + n + L) * 2 + 1;
+                    i2 = (m2 * twoL + n) * 2 + 1;
+                } else {
+                    i1 = (m * twoL + n) * 2;
+                    i2 = (m * twoL + n) * 2 + 1;
+                }
+                if (rd > 0) {
+                    const v2f o1 = ut[i1], o2 = ut[i2];
+                    a.x = o1.x + a.x;
+                    a.y = o1.y + a.y;
+                    a.z = o2.x + a.z;
+                    a.w = o2.y + a.w;
+                }
+                ut[i1] = v2f{a.x, a.y};
+                ut[i2] = v2f{a.z, a.w};
+            }
+        }
+    }
+}
+
 // Sums over the plane to the directions for grids of P = 16 P16 <= 64 nodes per axis: the products of
 // k_grid_phi with H staged once in LDS as the A operand ([b][a block, part, a % 16], b = 4 s + g for step s and
 // lane group g); each wave then runs on its own over its 8-azimuth column tiles (tiles w, w + 4, ...): the Ey
@@ -2010,12 +2179,16 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             }
         case K_GZ: return k_grid_z;
         case K_GPHI:
-            // a = p / 16 for grids of at most 64 nodes per axis, 0 otherwise
+            // a = p / 16 for grids of at most 128 nodes per axis, 0 otherwise
             switch (S.a) {
                 case 1: return k_grid_phi_s<1>;
                 case 2: return k_grid_phi_s<2>;
                 case 3: return k_grid_phi_s<3>;
                 case 4: return k_grid_phi_s<4>;
+                case 5: return k_grid_phi_r<5>;
+                case 6: return k_grid_phi_r<6>;
+                case 7: return k_grid_phi_r<7>;
+                case 8: return k_grid_phi_r<8>;
                 default: return k_grid_phi;
             }
         case K_GPHIT: return k_grid_phit;
@@ -2161,7 +2334,9 @@ std::string kernel_name(int kern, int a, int b) {
         case K_ZERO_OUT: return "k_zero_io";
         case K_GSPREAD: return a >= 4 && a <= 8 ? "k_grid_spread<" + std::to_string(a) + ">" : "";
         case K_GZ: return "k_grid_z";
-        case K_GPHI: return a >= 1 && a <= 4 ? "k_grid_phi_s<" + std::to_string(a) + ">" : "k_grid_phi";
+        case K_GPHI:
+            if (a >= 1 && a <= 4) return "k_grid_phi_s<" + std::to_string(a) + ">";
+            return a >= 5 && a <= 8 ? "k_grid_phi_r<" + std::to_string(a) + ">" : "k_grid_phi";
         case K_GPHIT: return "k_grid_phit";
         case K_GZT: return "k_grid_zt";
         case K_GINTERP: return a >= 4 && a <= 8 ? "k_grid_interp<" + std::to_string(a) + ">" : "";

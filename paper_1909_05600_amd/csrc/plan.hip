@@ -1226,7 +1226,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 // direction); grid form: spreading 0.29 ns per point plus 2.5 ns per (box, plane) launch item
                 // and interpolation 0.12 ns per point (w = 6; w^3 nodes per point), and the four sums on FP32
                 // MFMA (real multiply-adds as issued) at a fraction of the 78.6e12 per second peak that falls
-                // with narrower grids (measured 0.5 at 64 nodes, 0.44 at 48, 0.37 at 32; 0.35 above 64)
+                // with narrower grids (measured 0.5 at 64 nodes, 0.44 at 48, 0.37 at 32; 0.46 at 80 and 0.66 at
+                // 128 with the plane sums' rows held in registers, linear between; 0.35 above 128)
                 const double nbf = (double)LV.h_fwd.size(), nbt = (double)LV.h_tgt.size();
                 auto grid_cost = [&](int pp, int ww) {
                     const double ws = (double)ww / 6.0, p2 = (double)pp * pp, p3 = p2 * pp;
@@ -1234,7 +1235,9 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     const double macs = (nbf + nbt) * 4.0 * rings16 * p3 +                    // over z, both ways
                                         nbf * 4.0 * p2 * (L + 1.0) * 8.0 * ((L + 7) / 8) +    // plane to directions
                                         nbt * 4.0 * pp * tiles64 * (L + 1.0) * 2.0 * ((L + 1) / 2);   // and back
-                    const double eff = pp > 64 ? 0.35 : 0.5 * std::pow(pp / 64.0, 0.45);
+                    const double eff = pp > 128 ? 0.35
+                                       : pp > 64 ? 0.46 + 0.2 * (pp - 80) / 48.0
+                                                 : 0.5 * std::pow(pp / 64.0, 0.45);
                     return ws * ws * ws * (0.29e-9 * LV.pts_src + 0.12e-9 * LV.pts_tgt) + 2.5e-9 * nbf * pp +
                            macs / (eff * 78.6e12);
                 };
@@ -1691,7 +1694,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             LV.stages.push_back(make_stage(K_GSPREAD, LV.gw, 0, -1, l, 2 * sizeof(uint64_t) * std::min(p, 64) * std::min(p, 64),
                                            std::move(a1), st, SC));
             LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
-            LV.stages.push_back(make_stage(K_GPHI, p <= 64 ? p / 16 : 0, 0, s1, l, 0, std::move(a3), st, SC));
+            LV.stages.push_back(make_stage(K_GPHI, p <= 128 ? p / 16 : 0, 0, s1, l, 0, std::move(a3), st, SC));
             LV.stages.push_back(transfer_stage(l, LV, tg, s2, st, SC));
             for (int m : ring_order)
                 for (int32_t t : LV.h_tgt)

@@ -35,6 +35,25 @@ def test_grid_matches_oracle_and_dense(orc, n, k, seed, eps):
     assert np.array_equal(v, gpu_apply(gp, w.wu))
 
 
+@pytest.mark.parametrize("k", [280.0, 350.0, 415.0, 480.0])
+def test_grid_large_grids(orc, k):
+    """Level 2 on grids of 80 to 128 nodes per axis (wavenumbers of 280 to 480 on the unit sphere; the plane sums
+    hold each wave's grid rows in registers): within eps of FP64 dense rows, within eps / 4 of the direct GPU
+    transforms, bitwise repeatable."""
+    w = W.helmholtz_sphere(20000, seed=31, k=k, n_rows=512)
+    gp = gpu_plan(w.X, w.X, 1, w.k, w.eps, transforms="grid")
+    st = gp.stats()
+    assert st["tform"][2] == 3 and st["grid_nodes"][2] > 64, (st["tform"], st["grid_nodes"])
+    v = gpu_apply(gp, w.wu)
+    d = orc.dense_rows(w.X, w.X, w.wu, 1, w.k, w.rows)
+    vd = gpu_apply(gpu_plan(w.X, w.X, 1, w.k, w.eps, transforms="direct"), w.wu)
+    print("k %.0f: level-2 grid %d nodes (w = %d): vs dense %.3e vs direct GPU %.3e"
+          % (k, st["grid_nodes"][2], st["grid_width"][2], rel(v[w.rows], d), rel(v, vd)))
+    assert rel(v[w.rows], d) <= w.eps
+    assert rel(v, vd) < w.eps / 4
+    assert np.array_equal(v, gpu_apply(gp, w.wu))
+
+
 def test_grid_shifted_trees(orc):
     """Distinct source and target sets (translated root cubes, FP64 far test)."""
     rng = np.random.default_rng(21)
