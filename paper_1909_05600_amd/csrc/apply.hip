@@ -1381,9 +1381,9 @@ k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 // The products of steps s_lo .. s_hi - 1 of one staged chunk of k_grid_phit for the 16-row block ab of a: QN
 // column tiles of 16, in groups of four steps where the range allows (a group's LDS reads are all issued before
 // its products; rows past the staged azimuths of a partial chunk are zero), with no conditions inside a step.
-template <int QN>
+template <int QN, int RB, int QB>
 __device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const float *Bs, int ab, int li, int lg,
-                                         int s_lo, int s_hi, floatx4 (&acc)[2][4]) {
+                                         int s_lo, int s_hi, floatx4 (&acc)[2][QB]) {
     int s0 = s_lo;
 #pragma unroll 1
     for (; s0 + 4 <= s_hi; s0 += 4) {
@@ -1394,7 +1394,7 @@ __device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const
             ar[u] = Ar[row + ab * 16 + li];
             ai[u] = Ai[row + ab * 16 + li];
 #pragma unroll
-            for (int q = 0; q < QN; ++q) bv[u][q] = Bs[row + q * 16 + li];
+            for (int q = 0; q < QN; ++q) bv[u][q] = Bs[(4 * (s0 + u) + lg) * RB + q * 16 + li];
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1411,7 +1411,7 @@ __device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const
             const float ar = Ar[row + ab * 16 + li], ai = Ai[row + ab * 16 + li];
             float bv[QN];
 #pragma unroll
-            for (int q = 0; q < QN; ++q) bv[q] = Bs[row + q * 16 + li];
+            for (int q = 0; q < QN; ++q) bv[q] = Bs[(4 * s + lg) * RB + q * 16 + li];
 #pragma unroll
             for (int q = 0; q < QN; ++q) {
                 acc[0][q] = mfma16(ar, bv[q], acc[0][q]);
@@ -1428,24 +1428,28 @@ __device__ __forceinline__ void phit_mma(const float *Ar, const float *Ai, const
 // taking azimuth 2 s + g / 2 and part g % 2.  Where the tile has only one or two 16-row blocks of a (grids of
 // 16 or 32 nodes, edge tiles), the otherwise idle waves take a share of each chunk's steps, and their partial
 // sums are added to the first share's through LDS, in the order of the shares.  The next chunk's table values
-// and v~ are loaded into registers while the current chunk's products run.  Item (desc, box, ring, tile).
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
-k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
-    const int4 wk = work[blockIdx.x];
-    const LDesc &d = descs[wk.x];
+// and v~ are loaded into registers while the current chunk's products run.  Grids of 80, 96 and 112 nodes take
+// tiles of 64 rows of a by the whole of b (k_grid_phit_wide: up to eight 16-column blocks per wave), so that
+// no tile is a sliver and each chunk's A operand is staged once per 64 rows.  Item (desc, box, ring, tile).
+template <int BW>
+__device__ __forceinline__ void grid_phit_body(const int4 wk, const LDesc &d) {
+    constexpr int QB = BW / 16;                              // column blocks of 16 in a tile
+    constexpr int RB = BW == 64 ? kRow64 : kRow128;          // floats per staged row of B
+    constexpr int kStage = 2 * 32 * kRow64 + 32 * RB;        // A (two parts) and B
+    constexpr int kRed = 3 * 2 * QB * 4 * 64;                // at most three shares of partial sums
     const int tb = wk.y, m = wk.z;
     const int p = d.gp, L = d.L, mt = min(m, L - m);
     const int nta = (p + 63) / 64;
-    const int a0 = (wk.w / nta) * 64, b0 = (wk.w % nta) * 64;
-    const int qn = min(4, (p - b0 + 15) / 16);   // column tiles of 16 inside the grid
+    const int a0 = BW == 64 ? (wk.w / nta) * 64 : wk.w * 64, b0 = BW == 64 ? (wk.w % nta) * 64 : 0;
+    const int qn = min(QB, (p - b0 + 15) / 16);   // column tiles of 16 inside the grid
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
-    __shared__ float lds[3 * 32 * kRow64];
+    __shared__ float lds[kStage > kRed ? kStage : kRed];
     float *const Ar = lds, *const Ai = lds + 32 * kRow64, *const Bs = lds + 2 * 32 * kRow64;
-    floatx4 acc[2][4];
+    floatx4 acc[2][QB];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[i][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < QB; ++q) acc[i][q] = floatx4{0.f, 0.f, 0.f, 0.f};
     // row blocks of a in the tile, shares of the steps, this wave's row block and share
     const int nab = min(4, (p - a0 + 15) / 16);
     const int ks = nab == 1 ? 4 : (nab == 2 ? 2 : 1);
@@ -1470,20 +1474,21 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
     const int x = threadIdx.x % 64, nq = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     // v~ depends on the azimuth only, one per wave and step: scalar loads into scalar registers
     const kc2 vts = kcv(reinterpret_cast<const float2 *>(d.vt)) + (int64_t)tb * d.npair * 2;
-    v2f exv[4], eyv[4], v1v[4], v2v[4];
+    v2f exv[4], eyv[4], eyw[4], v1v[4], v2v[4];   // eyw: columns 64 .. 127 of wide tiles
     auto fetch = [&](int n0) {
         const int cnt = min(16, L - n0);
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int nl = nq + 4 * it, n = n0 + nl;
             const bool ok = nl < cnt;
-            exv[it] = eyv[it] = v1v[it] = v2v[it] = v2f{0.f, 0.f};
+            exv[it] = eyv[it] = eyw[it] = v1v[it] = v2v[it] = v2f{0.f, 0.f};
             if (ok) {
                 v1v[it] = vts[o1 + dn * n];
                 v2v[it] = vts[o2 + dn * n];
             }
             if (ok && a0 + x < p) exv[it] = ExT[(int64_t)n * p + a0 + x];
             if (ok && b0 + x < p) eyv[it] = EyT[(int64_t)n * p + b0 + x];
+            if (BW > 64 && ok && b0 + 64 + x < p) eyw[it] = EyT[(int64_t)n * p + b0 + 64 + x];
         }
     };
     fetch(0);
@@ -1500,8 +1505,12 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
             Ar[(2 * nl + 1) * kRow64 + x] = y1i - y2i;      // -D_i
             Ai[(2 * nl) * kRow64 + x] = y1i + y2i;          // S_i
             Ai[(2 * nl + 1) * kRow64 + x] = y2r - y1r;      // D_r
-            Bs[(2 * nl) * kRow64 + x] = eyv[it].x;
-            Bs[(2 * nl + 1) * kRow64 + x] = eyv[it].y;
+            Bs[(2 * nl) * RB + x] = eyv[it].x;
+            Bs[(2 * nl + 1) * RB + x] = eyv[it].y;
+            if (BW > 64) {
+                Bs[(2 * nl) * RB + 64 + x] = eyw[it].x;
+                Bs[(2 * nl + 1) * RB + 64 + x] = eyw[it].y;
+            }
         }
         if (n0 + 16 < L) fetch(n0 + 16);
         __syncthreads();
@@ -1510,43 +1519,53 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
             // ahead of the products (rows past the chunk hold zeros in the partial last chunk)
             const int steps = (2 * cnt + 3) / 4;
             const int s_lo = kp * (kStepsPerChunk / ks), s_hi = min(steps, s_lo + kStepsPerChunk / ks);
-            switch (qn) {
-                case 4: phit_mma<4>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
-                case 3: phit_mma<3>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
-                case 2: phit_mma<2>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
-                default: phit_mma<1>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+            if (BW == 64) {
+                switch (qn) {
+                    case 4: phit_mma<4, RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                    case 3: phit_mma<3, RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                    case 2: phit_mma<2, RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                    default: phit_mma<1, RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                }
+            } else {
+                switch (qn) {   // wide tiles cover grids of 80 .. 128 nodes: 5 .. 8 column blocks
+                    case 8: phit_mma<(QB < 8 ? QB : 8), RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                    case 7: phit_mma<(QB < 7 ? QB : 7), RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                    case 6: phit_mma<(QB < 6 ? QB : 6), RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                    default: phit_mma<(QB < 5 ? QB : 5), RB, QB>(Ar, Ai, Bs, ab, li, lg, s_lo, s_hi, acc); break;
+                }
             }
         }
     }
     if (ks > 1) {
-        // shares 1 .. ks-1 through LDS (32 floats per lane and share: [part][column tile][row]), added to share 0
-        // in share order; at most 3 x 2048 floats, within the staging arrays
+        // shares 1 .. ks-1 through LDS (8 QB floats per lane and share: [part][column tile][row]), added to share
+        // 0 in share order; (ks - 1) nab <= 3 shares, within the array
+        constexpr int kShare = 2 * QB * 4 * 64;
         __syncthreads();
         if (act && kp > 0) {
-            float *red = lds + ((kp - 1) * nab + ab) * 2048 + lane;
+            float *red = lds + ((kp - 1) * nab + ab) * kShare + lane;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < QB; ++q)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) red[((i * 4 + q) * 4 + r) * 64] = acc[i][q][r];
+                    for (int r = 0; r < 4; ++r) red[((i * QB + q) * 4 + r) * 64] = acc[i][q][r];
         }
         __syncthreads();
         if (act && kp == 0)
             for (int k = 1; k < ks; ++k) {
-                const float *red = lds + ((k - 1) * nab + ab) * 2048 + lane;
+                const float *red = lds + ((k - 1) * nab + ab) * kShare + lane;
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < QB; ++q)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[i][q][r] += red[((i * 4 + q) * 4 + r) * 64];
+                        for (int r = 0; r < 4; ++r) acc[i][q][r] += red[((i * QB + q) * 4 + r) * 64];
             }
     }
     if (!act || kp > 0) return;
     const gm2 Hb = gw(d.H) + ((int64_t)m * d.gnbox + tb) * p * p;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QB; ++q) {
         const int b = b0 + q * 16 + li;
         if (b >= p) continue;
 #pragma unroll
@@ -1555,6 +1574,18 @@ k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
             Hb[(int64_t)a * p + b] = v2f{acc[0][q][r], acc[1][q][r]};
         }
     }
+}
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    grid_phit_body<64>(wk, descs[wk.x]);
+}
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_grid_phit_wide(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    grid_phit_body<128>(wk, descs[wk.x]);
 }
 
 // Back over z: G'_pg[c][ab] = sum over (ring pair m, part pe) of A[c][(m, pe)] B[(m, pe)][(ab, pg)] with
@@ -2191,7 +2222,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
                 case 8: return k_grid_phi_r<8>;
                 default: return k_grid_phi;
             }
-        case K_GPHIT: return k_grid_phit;
+        case K_GPHIT: return S.a == 1 ? k_grid_phit_wide : k_grid_phit;
         case K_GZT: return k_grid_zt;
         case K_GINTERP:
             switch (S.a) {
@@ -2337,7 +2368,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_GPHI:
             if (a >= 1 && a <= 4) return "k_grid_phi_s<" + std::to_string(a) + ">";
             return a >= 5 && a <= 8 ? "k_grid_phi_r<" + std::to_string(a) + ">" : "k_grid_phi";
-        case K_GPHIT: return "k_grid_phit";
+        case K_GPHIT: return a == 1 ? "k_grid_phit_wide" : "k_grid_phit";
         case K_GZT: return "k_grid_zt";
         case K_GINTERP: return a >= 4 && a <= 8 ? "k_grid_interp<" + std::to_string(a) + ">" : "";
         default: return "";
