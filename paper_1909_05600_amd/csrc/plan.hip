@@ -268,56 +268,85 @@ __device__ __forceinline__ bool is_far(const FarTest &ft, int32_t t, int32_t s) 
     return m >= ft.two_dl;
 }
 
-// For every target box t of level l: the children of the near sources of its parent.
+// For every target box t of level l: the children of the near sources of its parent.  One wave per target
+// box; a step takes 8 near entries with 8 children slots each (lane = 8 entry + child), in the order of the
+// serial walk (near entries, then children), so ballots give each candidate's place in the lists.
+__device__ __forceinline__ void list_candidate(int64_t e, int64_t e1, int j, const int32_t *pnear_src,
+                                               const int32_t *child_y, bool &valid, int32_t &cs) {
+    valid = false;
+    cs = 0;
+    if (e < e1) {
+        const int32_t S = pnear_src[e];
+        const int32_t c0 = child_y[S];
+        if (j < child_y[S + 1] - c0) {
+            valid = true;
+            cs = c0 + j;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_list_count(int32_t nbx, const int32_t *parent_x, const int64_t *pnear_ptr, const int32_t *pnear_src,
              const int32_t *child_y, FarTest ft, int64_t *nfar, int64_t *nnear, int32_t *win_used) {
-    int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // the translation windows the fill marks start cleared
-    for (int32_t i = t; i < kWin3; i += gridDim.x * blockDim.x) win_used[i] = 0;
+    for (int64_t i = gid; i < kWin3; i += (int64_t)gridDim.x * blockDim.x) win_used[i] = 0;
+    const int32_t t = (int32_t)(gid >> 6);
+    const int lane = threadIdx.x & 63;
     if (t >= nbx) return;
     const int32_t T = parent_x[t];
+    const int64_t e0 = pnear_ptr[T], e1 = pnear_ptr[T + 1];
     int64_t cf = 0, cn = 0;
-    for (int64_t e = pnear_ptr[T]; e < pnear_ptr[T + 1]; ++e) {
-        const int32_t S = pnear_src[e];
-        for (int32_t cs = child_y[S]; cs < child_y[S + 1]; ++cs) {
-            if (is_far(ft, t, cs)) ++cf;
-            else ++cn;
-        }
+    for (int64_t eb = e0; eb < e1; eb += 8) {
+        bool valid;
+        int32_t cs;
+        list_candidate(eb + (lane >> 3), e1, lane & 7, pnear_src, child_y, valid, cs);
+        const bool far = valid && is_far(ft, t, cs);
+        cf += __popcll(__ballot(far));
+        cn += __popcll(__ballot(valid && !far));
     }
-    nfar[t] = cf;
-    nnear[t] = cn;
+    if (lane == 0) {
+        nfar[t] = cf;
+        nnear[t] = cn;
+    }
 }
 
 __global__ void __launch_bounds__(kThreads)
 k_list_fill(int32_t nbx, const int32_t *parent_x, const int64_t *pnear_ptr, const int32_t *pnear_src,
             const int32_t *child_y, FarTest ft, const int64_t *far_ptr, const int64_t *near_ptr, int32_t *far_src,
             int32_t *far_win, int32_t *near_src, int32_t *win_used, int *bad) {
-    int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = (int32_t)(gid >> 6);
+    const int lane = threadIdx.x & 63;
     if (t >= nbx) return;
     const int32_t T = parent_x[t];
+    const int64_t e0 = pnear_ptr[T], e1 = pnear_ptr[T + 1];
     int64_t pf = far_ptr[t], pn = near_ptr[t];
-    for (int64_t e = pnear_ptr[T]; e < pnear_ptr[T + 1]; ++e) {
-        const int32_t S = pnear_src[e];
-        for (int32_t cs = child_y[S]; cs < child_y[S + 1]; ++cs) {
-            if (is_far(ft, t, cs)) {
-                int w = 0;
-                for (int d = 0; d < 3; ++d) {
-                    int o = ft.ijk_t[3 * t + d] - ft.ijk_s[3 * cs + d] - ft.base[d];
-                    if (o < 0 || o >= kWin) {
-                        atomicOr(bad, 1);
-                        o = 0;
-                    }
-                    w = w * kWin + o;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int64_t eb = e0; eb < e1; eb += 8) {
+        bool valid;
+        int32_t cs;
+        list_candidate(eb + (lane >> 3), e1, lane & 7, pnear_src, child_y, valid, cs);
+        const bool far = valid && is_far(ft, t, cs), nr = valid && !far;
+        const unsigned long long mf = __ballot(far), mn = __ballot(nr);
+        if (far) {
+            int w = 0;
+            for (int d = 0; d < 3; ++d) {
+                int o = ft.ijk_t[3 * t + d] - ft.ijk_s[3 * cs + d] - ft.base[d];
+                if (o < 0 || o >= kWin) {
+                    atomicOr(bad, 1);
+                    o = 0;
                 }
-                far_src[pf] = cs;
-                far_win[pf] = w;
-                win_used[w] = 1;
-                ++pf;
-            } else {
-                near_src[pn++] = cs;
+                w = w * kWin + o;
             }
+            const int64_t at = pf + __popcll(mf & below);
+            far_src[at] = cs;
+            far_win[at] = w;
+            win_used[w] = 1;
         }
+        if (nr) near_src[pn + __popcll(mn & below)] = cs;
+        pf += __popcll(mf);
+        pn += __popcll(mn);
     }
 }
 
@@ -1108,7 +1137,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         }
         int64_t *cnt_f = SC.get<int64_t>(nbx + 1), *cnt_n = SC.get<int64_t>(nbx + 1);
         win_used[l] = SC.get<int32_t>(kWin3);
-        FFM_LAUNCH(k_list_count, nblocks(std::max<int64_t>(nbx, kWin3)), kThreads, 0, st, nbx, TX.lev[l].parent.p,
+        FFM_LAUNCH(k_list_count, nblocks(std::max<int64_t>((int64_t)nbx * 64, kWin3)), kThreads, 0, st, nbx, TX.lev[l].parent.p,
                    LP.near_ptr.p, LP.near_src.p, TY.lev[l - 1].child.p, ft, cnt_f, cnt_n, win_used[l]);
         LV.far_ptr.alloc(nbx + 1);
         LV.near_ptr.alloc(nbx + 1);
@@ -1120,7 +1149,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         LV.far_src.alloc(LV.nfar);
         LV.far_cls.alloc(LV.nfar);
         LV.near_src.alloc(std::max<int64_t>(LV.nnear, 1));
-        FFM_LAUNCH(k_list_fill, nblocks(nbx), kThreads, 0, st, nbx, TX.lev[l].parent.p, LP.near_ptr.p, LP.near_src.p,
+        FFM_LAUNCH(k_list_fill, nblocks((int64_t)nbx * 64), kThreads, 0, st, nbx, TX.lev[l].parent.p, LP.near_ptr.p, LP.near_src.p,
                    TY.lev[l - 1].child.p, ft, LV.far_ptr.p, LV.near_ptr.p, LV.far_src.p, LV.far_cls.p,
                    LV.near_src.p, win_used[l], bad);
         // compact translation classes (numbered in window order) on the device
