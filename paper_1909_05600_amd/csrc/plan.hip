@@ -1141,9 +1141,16 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                    LP.near_ptr.p, LP.near_src.p, TY.lev[l - 1].child.p, ft, cnt_f, cnt_n, win_used[l]);
         LV.far_ptr.alloc(nbx + 1);
         LV.near_ptr.alloc(nbx + 1);
-        // both list offsets in one scan; the two totals arrive in host-visible memory
+        // both list offsets in one scan; the two totals arrive in host-visible memory (a total still negative
+        // after the synchronisation, which never happens when the kernel's writes are visible, is read back
+        // from the device instead: the list buffers are sized by it)
+        tot_h[0] = tot_h[1] = -1;
         exclusive_scan2_i64(cnt_f, LV.far_ptr.p, cnt_n, LV.near_ptr.p, nbx, tot_h, st, SC);
         FFM_HIP(hipStreamSynchronize(st));
+        if (tot_h[0] < 0 || tot_h[1] < 0) {
+            FFM_HIP(hipMemcpy(&tot_h[0], LV.far_ptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost));
+            FFM_HIP(hipMemcpy(&tot_h[1], LV.near_ptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost));
+        }
         LV.nfar = tot_h[0];
         LV.nnear = tot_h[1];
         LV.far_src.alloc(LV.nfar);

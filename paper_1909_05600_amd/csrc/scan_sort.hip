@@ -263,9 +263,11 @@ k_scan_apply2(const T *a, T *oa, const T *b, T *ob, int64_t n, const T *bsum, in
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         oa[n] = offa + ta;
         ob[n] = offb + tb;
+        // host-visible memory: the caller reads it after synchronising the stream, and the kernel's
+        // completion makes its writes visible to the host (no fence here: a system-scope fence writes back
+        // the whole L2)
         host_tot[0] = offa + ta;
         host_tot[1] = offb + tb;
-        __threadfence_system();
     }
 }
 
