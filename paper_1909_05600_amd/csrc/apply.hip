@@ -1576,6 +1576,115 @@ __device__ __forceinline__ void grid_phit_body(const int4 wk, const LDesc &d) {
     }
 }
 
+// The mirror plane sums for grids of at most 32 nodes, rings m and L - m together (they share the tables ExT and
+// EyT; only v~ differs): the staged A operand holds both rings' 32 rows of a side by side (64 columns), B the
+// shared 32 columns of Ey, and wave w takes ring w / 2 and row block w % 2, so every wave has two full column
+// blocks of products.  Item (desc, box, ring m <= L / 2, 0).
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_grid_phit_pair(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int tb = wk.y, m = wk.z;
+    const int p = d.gp, L = d.L;                   // p <= 32, m <= L - m
+    const int mr[2] = {m, L - m};
+    const bool two = L - m != m;
+    const int qn = (p + 15) / 16;                  // column blocks of b (1 or 2)
+    const int nab = (p + 15) / 16;                 // row blocks of a per ring
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    const int rr = wv >> 1, ab = wv & 1;
+    const bool act = ab < nab && (rr == 0 || two);
+    __shared__ float Ar[32 * kRow64], Ai[32 * kRow64], Bs[32 * kRow64];
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[i][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int64_t twoL = 2 * (int64_t)L;
+    const gc2 ExT = gl(d.ExT) + (int64_t)m * L * p, EyT = gl(d.EyT) + (int64_t)m * L * p;
+    // v~(m', n) and v~(m', n + L) of both rings in the antipodal-pair layout: v1 at vt[o1 + 2 n], v2 at vt[o2 + 2 n]
+    int64_t o1[2], o2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int mm = mr[k];
+        if (2 * mm < L) {
+            o1[k] = (int64_t)mm * twoL * 2;
+            o2[k] = ((int64_t)mm * twoL + L) * 2;
+        } else if (2 * mm > L) {
+            o1[k] = ((int64_t)(L - mm) * twoL + L) * 2 + 1;
+            o2[k] = (int64_t)(L - mm) * twoL * 2 + 1;
+        } else {
+            o1[k] = (int64_t)mm * twoL * 2;
+            o2[k] = (int64_t)mm * twoL * 2 + 1;
+        }
+    }
+    // staging thread: column x of A is ring x / 32, row a = x % 32; columns x < 32 of B are b = x
+    const int x = threadIdx.x % 64, xr = x >> 5, xa = x & 31, nq = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const kc2 vts = kcv(reinterpret_cast<const float2 *>(d.vt)) + (int64_t)tb * d.npair * 2;
+    v2f exv[4], eyv[4], v1v[4], v2v[4];
+    auto fetch = [&](int n0) {
+        const int cnt = min(16, L - n0);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int nl = nq + 4 * it, n = n0 + nl;
+            const bool ok = nl < cnt;
+            exv[it] = eyv[it] = v1v[it] = v2v[it] = v2f{0.f, 0.f};
+            if (ok) {
+                // both rings' values by scalar loads, each lane keeping its own ring's
+                const v2f a1 = vts[o1[0] + 2 * n], a2 = vts[o2[0] + 2 * n];
+                v2f b1 = a1, b2 = a2;
+                if (two) {
+                    b1 = vts[o1[1] + 2 * n];
+                    b2 = vts[o2[1] + 2 * n];
+                }
+                v1v[it] = xr ? b1 : a1;
+                v2v[it] = xr ? b2 : a2;
+            }
+            if (ok && xa < p) exv[it] = ExT[(int64_t)n * p + xa];
+            if (ok && x < p) eyv[it] = EyT[(int64_t)n * p + x];
+        }
+    };
+    fetch(0);
+    for (int n0 = 0; n0 < L; n0 += 16) {
+        const int cnt = min(16, L - n0);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int nl = nq + 4 * it;
+            const v2f ex = exv[it], v1 = v1v[it], v2 = v2v[it];
+            const float y1r = fmaf(ex.x, v1.x, ex.y * v1.y), y1i = fmaf(ex.x, v1.y, -(ex.y * v1.x));   // conj(ex) v1
+            const float y2r = fmaf(ex.x, v2.x, -(ex.y * v2.y)), y2i = fmaf(ex.x, v2.y, ex.y * v2.x);   // ex v2
+            Ar[(2 * nl) * kRow64 + x] = y1r + y2r;          // S_r
+            Ar[(2 * nl + 1) * kRow64 + x] = y1i - y2i;      // -D_i
+            Ai[(2 * nl) * kRow64 + x] = y1i + y2i;          // S_i
+            Ai[(2 * nl + 1) * kRow64 + x] = y2r - y1r;      // D_r
+            Bs[(2 * nl) * kRow64 + x] = eyv[it].x;
+            Bs[(2 * nl + 1) * kRow64 + x] = eyv[it].y;
+        }
+        if (n0 + 16 < L) fetch(n0 + 16);
+        __syncthreads();
+        if (act) {
+            const int steps = (2 * cnt + 3) / 4;
+            // A's row block for this wave: ring rr's rows start at column 32 rr
+            if (qn == 2)
+                phit_mma<2, kRow64, 2>(Ar, Ai, Bs, 2 * rr + ab, li, lg, 0, steps, acc);
+            else
+                phit_mma<1, kRow64, 2>(Ar, Ai, Bs, 2 * rr + ab, li, lg, 0, steps, acc);
+        }
+    }
+    if (!act) return;
+    const gm2 Hb = gw(d.H) + ((int64_t)mr[rr] * d.gnbox + tb) * p * p;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int b = q * 16 + li;
+        if (q >= qn || b >= p) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = ab * 16 + 4 * lg + r;
+            Hb[(int64_t)a * p + b] = v2f{acc[0][q][r], acc[1][q][r]};
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_grid_phit(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
@@ -2222,7 +2331,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
                 case 8: return k_grid_phi_r<8>;
                 default: return k_grid_phi;
             }
-        case K_GPHIT: return S.a == 1 ? k_grid_phit_wide : k_grid_phit;
+        case K_GPHIT: return S.a == 1 ? k_grid_phit_wide : (S.a == 2 ? k_grid_phit_pair : k_grid_phit);
         case K_GZT: return k_grid_zt;
         case K_GINTERP:
             switch (S.a) {
@@ -2368,7 +2477,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_GPHI:
             if (a >= 1 && a <= 4) return "k_grid_phi_s<" + std::to_string(a) + ">";
             return a >= 5 && a <= 8 ? "k_grid_phi_r<" + std::to_string(a) + ">" : "k_grid_phi";
-        case K_GPHIT: return a == 1 ? "k_grid_phit_wide" : "k_grid_phit";
+        case K_GPHIT: return a == 1 ? "k_grid_phit_wide" : (a == 2 ? "k_grid_phit_pair" : "k_grid_phit");
         case K_GZT: return "k_grid_zt";
         case K_GINTERP: return a >= 4 && a <= 8 ? "k_grid_interp<" + std::to_string(a) + ">" : "";
         default: return "";

@@ -1736,16 +1736,23 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             // whose 64 x 64 tiles would leave slivers (measured 18.3 -> 13.7 ms at 80 nodes; 128 nodes keep full
             // 64 x 64 tiles, 14.6 against 15.1 ms wide)
             const bool phit_wide = p > 64 && p < 128;
+            // grids of at most 32 nodes: rings m and L - m in one block (they share their tables)
+            const bool phit_pair = p <= 32;
             const int phit_tiles = phit_wide ? nta : nta * nta;
-            for (int m : ring_order)
-                for (int32_t t : LV.h_tgt)
-                    for (int q = 0; q < phit_tiles; ++q) b1.push_back(make_int4(l, t, m, q));
+            if (phit_pair) {
+                for (int mt = 0; mt < LV.nrp; ++mt)
+                    for (int32_t t : LV.h_tgt) b1.push_back(make_int4(l, t, mt, 0));
+            } else {
+                for (int m : ring_order)
+                    for (int32_t t : LV.h_tgt)
+                        for (int q = 0; q < phit_tiles; ++q) b1.push_back(make_int4(l, t, m, q));
+            }
             for (int32_t t : LV.h_tgt) {
                 for (int q = 0; q < ncol; ++q)
                     for (int cc = 0; cc < nta; ++cc) b2.push_back(make_int4(l, t, q, cc));
                 for (int32_t i = sx[t]; i < sx[t + 1]; i += kThreads) b3.push_back(make_int4(l, t, i, 0));
             }
-            LV.stages.push_back(make_stage(K_GPHIT, phit_wide ? 1 : 0, 0, -1, l, 0, std::move(b1), st, SC));
+            LV.stages.push_back(make_stage(K_GPHIT, phit_wide ? 1 : (phit_pair ? 2 : 0), 0, -1, l, 0, std::move(b1), st, SC));
             LV.stages.push_back(make_stage(K_GZT, 0, 0, -1, l, 0, std::move(b2), st, SC));
             LV.stages.push_back(make_stage(K_GINTERP, LV.gw, 0, s3, l, 0, std::move(b3), st, SC));
         } else if (LV.method == kGegenbauer) {
