@@ -40,12 +40,13 @@ NEAR_SLOTS = {"k_near<false>": 10.0, "k_near<true>": 18.0}
 PEAKS = {"mfma": (157.3, "TFLOP/s"), "alu": (PEAK_ALU_TFLOPS, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
 
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
-# workload (profiles/traffic_grid_phit_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
+# workload (profiles/traffic_apply_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
 # kernel of known size (FETCH x 2.0, WRITE x 1.0), mean over the kernel's launches in one product.  Valid only
 # for the kernel source it was taken on.
-TRAFFIC_SOURCE_HASH = "5aff1f1138d5d8c4"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
+TRAFFIC_SOURCE_HASH = "d19c06e41360a2d6"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
 TRAFFIC = {
-    "k_grid_phit": ((79073.625 * 2.0 + 295680.0) + (39912.0 * 2.0 + 187136.0)) / 2 * 1024.0,
+    "k_near<true>": (382161.0 * 2.0 + 8833.875) * 1024.0,
+    "k_grid_phit": (79074.875 * 2.0 + 295680.0) * 1024.0,
 }
 
 
