@@ -414,7 +414,6 @@ void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream
 
 // device primitives (scan_sort.hip)
 // (temporaries come from the scratch list; nothing here synchronises the stream)
-void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st, Scratch &S);  // out[n] = total
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st, Scratch &S);  // out[n] = total
 // Both scans at once (n <= 4096 tiles of 2048); the two totals also go to host_tot[0..1] (host-visible memory,
 // valid once the stream has passed the scan).

@@ -273,9 +273,6 @@ k_scan_apply2(const T *a, T *oa, const T *b, T *ob, int64_t n, const T *bsum, in
 
 }  // namespace
 
-void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st, Scratch &S) {
-    exclusive_scan<int64_t>(in, out, n, st, S);
-}
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st, Scratch &S) {
     exclusive_scan<int32_t>(in, out, n, st, S);
 }
