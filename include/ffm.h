@@ -109,26 +109,62 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
                       void *hip_stream, ffm_plan_t *out);
 
 /*
- * ffm_apply -- v = FFM(wu): one descent over the plan's levels (per level:
- * source transform, transfer, target transform) and the leaf near field.
- *   wu     device, n_y elements of in_dtype, in the caller's source order.
- *          Real inputs are taken as complex with zero imaginary part.
+ * ffm_apply -- v = G W u, the matrix-vector product of Sec. 1 eq.
+ * (convolution_matrix), evaluated as Sec. 2.2 describes: one descent over the
+ * plan's levels (per level: source transform, transfer between the admissible
+ * box pairs, target transform; Sec. 2.2.2 and 2.2.3, the descent-only form of
+ * the remark closing Sec. 2.2.3) and the dense near field of the leaf level
+ * (Sec. 2.2.4).
+ *   wu     device, n_y elements of in_dtype, in the caller's source order:
+ *          the products w_j u_j of eq. (convolution_discrete).  Real inputs
+ *          are taken as complex with zero imaginary part.
  *   v      device, complex64 [n_x], in the caller's target order; overwritten.
  * Asynchronous on hip_stream: the caller keeps wu and v alive until the
  * stream passes the apply.  One apply per plan may be in flight at a time
  * (the plan's workspace is reused); a second apply on the same stream is
- * ordered after the first.  No allocation happens inside apply.
+ * ordered after the first.  No allocation happens inside apply.  Errors:
+ * FFM_EINVAL (NULL plan, NULL wu or v with a non-empty set, unknown dtype;
+ * nothing is enqueued), FFM_EDEVICE (a launch failed).
  */
 ffm_status_t ffm_apply(ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, void *v, void *hip_stream);
 
-/* ffm_destroy -- release the plan.  FFM_EBUSY (and nothing released) if an
- * apply on it has not completed yet.  NULL is accepted. */
+/*
+ * ffm_destroy -- release the plan and all its device memory.  Not in the
+ * paper, whose implementation rebuilds every structure at each product and
+ * keeps nothing between calls (its linear storage bound, Sec. 3); here a plan stays
+ * resident until this call.  FFM_EBUSY (and nothing released) if an apply on
+ * it, or a batched apply that includes it, has not completed yet, if it
+ * belongs to a batch (ffm_batch_create), or if server requests of it are
+ * pending.  NULL is accepted.
+ */
 ffm_status_t ffm_destroy(ffm_plan_t plan);
 
-/* Message of the last failing call on this thread ("" if none). */
+/*
+ * ffm_apply_batched -- v[i] = FFM_i(wu[i]) for n >= 1 distinct plans in one
+ * pass of merged launches (one launch per step kind for all instances,
+ * replayed from a HIP graph).  Not in the paper, which evaluates one product
+ * at a time; each instance computes bitwise what ffm_apply computes for it.
+ *   plans   host array of n plan handles (no plan twice, none in a batch made
+ *           by ffm_batch_create).
+ *   wu, v   host arrays of n device pointers with the layouts of ffm_apply;
+ *           wu[i] is complex64 (FFM_C64) [n_y of plan i].
+ * Asynchronous on hip_stream.  The merged launches are built on the first
+ * call for a plan set (host-synchronous, allocates) and kept for the next
+ * call with the same plans in the same order; a call with another set, and
+ * ffm_destroy, ffm_plan_set_tiles or ffm_batch_create on one of the plans,
+ * releases them.  While a batched apply is in flight, none of its plans may
+ * be applied on its own (they share the plan's workspace).  Errors:
+ * FFM_EINVAL (NULL arrays or entries, n <= 0, a repeated plan), FFM_EBUSY (a
+ * plan belongs to a batch), FFM_ENOMEM.
+ */
+ffm_status_t ffm_apply_batched(const ffm_plan_t *plans, const void *const *wu, void *const *v, int32_t n,
+                               void *hip_stream);
+
+/* Message of the last failing call on this thread ("" if none).  Not in the
+ * paper. */
 const char *ffm_last_error(void);
 
-/* Library version string. */
+/* Library version string.  Not in the paper. */
 const char *ffm_version(void);
 
 /* ---------------------------------------------------------------- statistics */
@@ -160,13 +196,22 @@ typedef struct {
     int64_t fwd_boxes[FFM_MAX_LEVELS];     /* source boxes transformed at level l         */
     int64_t bwd_boxes[FFM_MAX_LEVELS];     /* target boxes transformed at level l         */
     int32_t grid_width[FFM_MAX_LEVELS];    /* grid form: spreading kernel width w in nodes, else 0 */
+    double  grid_beta[FFM_MAX_LEVELS];     /* grid form: kernel shape beta, else 0 (the grid spacing is
+                                              h = d_l / (grid_nodes - 1 - grid_width))               */
+    double  grid_alias[FFM_MAX_LEVELS];    /* grid form: bound on the aliasing error of spreading one plane
+                                              wave along one axis, relative, for every direction, else 0 */
 } ffm_stats_t;
 
+/* ffm_plan_stats -- copy the plan's sizes and work counters to host memory.
+ * The counts are those of Sec. 3 (boxes per level, far and near pairs,
+ * translation classes of the proof of Prop. 1, quadrature sizes of eq.
+ * (gegenbauerQuadrature)); the byte counts are not in the paper. */
 ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out);
 
 /*
  * ffm_plan_export -- copy tree and list data to host memory for bit-exact
- * comparison (tests).  what selects the array; set 0 = targets, 1 = sources;
+ * comparison (tests): the octrees of Sec. 2.2.1 and the far and near lists of
+ * the descent of Sec. 2.2.2.  what selects the array; set 0 = targets, 1 = sources;
  * level l.  Returns the element count in *count; if dst is non-NULL it must
  * hold that many elements of the listed type.
  *   FFM_EXPORT_KEYS      uint64  sorted Morton keys (set)
@@ -186,7 +231,7 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
                              void *dst, int64_t *count);
 
 /*
- * ffm_plan_timing -- per-phase durations (milliseconds, HIP events on the
+ * ffm_plan_timing -- not in the paper: per-phase durations (milliseconds, HIP events on the
  * apply's stream) of the most recent apply of a plan made with
  * FFM_FLAG_TIMING; waits for that apply to finish.  ms has n >= 64 slots:
  *   [0] input permutation, [1 + 3(l-1) + 0/1/2] level l source transform /
@@ -197,7 +242,7 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
 ffm_status_t ffm_plan_timing(ffm_plan_t plan, float *ms, int32_t n);
 
 /*
- * ffm_plan_launch_timing -- the kernel launches of the most recent apply of a
+ * ffm_plan_launch_timing -- not in the paper: the kernel launches of the most recent apply of a
  * plan made with FFM_FLAG_TIMING, in launch order, each timed by its own pair
  * of HIP events on the apply's stream; waits for that apply to finish.  The
  * first min(n, launches) records are written to out (host memory); *count
@@ -215,14 +260,16 @@ typedef struct {
 ffm_status_t ffm_plan_launch_timing(ffm_plan_t plan, ffm_launch_t *out, int32_t n, int32_t *count);
 
 /*
- * ffm_kernel_name -- the symbol of a launch's kernel as profilers print it
+ * ffm_kernel_name -- not in the paper: the symbol of a launch's kernel as profilers print it
  * (template arguments included, namespaces and parameters left out), e.g.
  * "k_grid_phi_s<4>", written NUL-terminated into buf (host, n bytes, cut to
  * fit).  Returns the full length, or -1 for an unknown kernel.
  */
 int32_t ffm_kernel_name(int32_t kernel, int32_t variant_a, int32_t variant_b, char *buf, int32_t n);
 
-/* Device bytes held by the plan, and by its apply workspace. */
+/* Device bytes held by the plan, and by its apply workspace (every part
+ * aligned to 256 bytes; the same figure as ffm_stats_t.workspace_bytes and
+ * the server's admission).  The paper's storage bound is Sec. 3, Prop. 1. */
 size_t ffm_plan_bytes(ffm_plan_t plan);
 size_t ffm_workspace_bytes(ffm_plan_t plan);
 
@@ -303,7 +350,7 @@ ffm_status_t ffm_batch_destroy(ffm_batch_t batch);
 
 /* ------------------------------------------------------------------ serving
  * Not in the paper (its applications call the product repeatedly inside an
- * iterative solver, Sec. 5).  A server keeps plans resident and runs apply
+ * iterative solver, Sec. 4.2).  A server keeps plans resident and runs apply
  * requests submitted from any host thread: a scheduler thread admits queued
  * requests in submission order as soon as one of `slots` HIP streams is free
  * and the request's apply workspace (ffm_stats_t.workspace_bytes of its plan)
@@ -325,15 +372,17 @@ ffm_status_t ffm_server_create(const ffm_server_options_t *opts, ffm_server_t *o
 
 /*
  * ffm_server_submit -- queue v = FFM(wu) for a plan; returns at once with a
- * ticket.  wu and v are device pointers with the layouts of ffm_apply; wu must
- * already hold its values (the request runs on the server's own streams, with
- * no ordering against the caller's streams) and both must stay valid until
- * the request completes.  The plan may not be destroyed or retiled while it
+ * ticket.  wu and v are device pointers with the layouts of ffm_apply, valid
+ * until the request completes.  hip_stream is the caller's stream that
+ * produces wu: an event recorded on it at submission orders the request after
+ * everything enqueued there before this call (a device-side wait, no host
+ * synchronisation).  v is complete once ffm_server_wait returns, or
+ * ffm_server_poll reports the request done.  The plan may not be destroyed or retiled while it
  * has pending requests (FFM_EBUSY).  FFM_ENOMEM if the workspace exceeds the
  * whole budget.  Thread-safe.
  */
 ffm_status_t ffm_server_submit(ffm_server_t server, ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, void *v,
-                               int64_t *ticket);
+                               void *hip_stream, int64_t *ticket);
 
 /* Block until the request completes; *latency_ms (nullable) receives the
  * time from submission to observed completion.  Each ticket is waited for

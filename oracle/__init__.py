@@ -72,6 +72,9 @@ def lib():
             "orc_near": (None, [P, C.c_int, P, P]),
             "orc_level_method": (C.c_int, [P, C.c_int]),
             "orc_level_order": (C.c_int, [P, C.c_int]),
+            "orc_grid_forward": (None, [C.c_int, C.c_int, dbl, dbl, dbl, C.c_int, P, P, i64, P]),
+            "orc_grid_backward": (None, [C.c_int, C.c_int, dbl, dbl, dbl, C.c_int, P, P, i64, P]),
+            "orc_es_hat": (dbl, [C.c_int, dbl, dbl]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -85,9 +88,13 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+MAX_LEVELS = 21
+
+
 class _Options(C.Structure):
     _fields_ = [("n_leaf", C.c_int32), ("kappa", C.c_double), ("r1_override", C.c_int32),
-                ("max_level", C.c_int32)]
+                ("max_level", C.c_int32), ("grid_p", C.c_int32 * MAX_LEVELS), ("grid_w", C.c_int32 * MAX_LEVELS),
+                ("grid_beta", C.c_double * MAX_LEVELS)]
 
 
 def _ptr(a: np.ndarray):
@@ -164,15 +171,47 @@ def gegenbauer_diag(L: int, k: float, r0) -> np.ndarray:
     return D
 
 
+def es_hat(w: int, beta: float, xi: float) -> float:
+    """Fourier transform at xi of the grid form's spreading kernel exp(beta (sqrt(1 - (2t/w)^2) - 1)), |t| < w/2."""
+    return float(lib().orc_es_hat(int(w), float(beta), float(xi)))
+
+
+def grid_forward(p: int, w: int, beta: float, h: float, k: float, L: int, y, u) -> np.ndarray:
+    """Grid form of the source transform of one box: u~(q) for the level's quadrature (box-relative points y)."""
+    y = _coords(y)
+    uu = _complex128(u)
+    out = np.zeros(2 * L * (L + 1), dtype=np.complex128)
+    lib().orc_grid_forward(int(p), int(w), float(beta), float(h), float(k), int(L), _ptr(y), _ptr(uu), y.shape[0],
+                           _ptr(out))
+    return out
+
+
+def grid_backward(p: int, w: int, beta: float, h: float, k: float, L: int, vt, x) -> np.ndarray:
+    """Grid form of the target transform of one box: v_i = sum_q e^{ik s_q.x_i} vt(q) at box-relative points x."""
+    x = _coords(x)
+    v = _complex128(vt)
+    out = np.zeros(x.shape[0], dtype=np.complex128)
+    lib().orc_grid_backward(int(p), int(w), float(beta), float(h), float(k), int(L), _ptr(v), _ptr(x), x.shape[0],
+                            _ptr(out))
+    return out
+
+
 class Plan:
-    """The oracle's FFM plan: root cubes, two Morton-sorted octrees, descent lists, leaf."""
+    """The oracle's FFM plan: root cubes, two Morton-sorted octrees, descent lists, leaf.
+
+    ``grid`` maps a Gegenbauer level to the (p, w, beta) of its grid-form transforms; other levels use the
+    direct sums."""
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 64,
-                 kappa: float = 0.0, r1: int = 0, max_level: int = 20):
+                 kappa: float = 0.0, r1: int = 0, max_level: int = 20, grid: dict | None = None):
         self.X = _coords(X)
         self.Y = self.X if Y is X else _coords(Y)
         self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
         opt = _Options(int(n_leaf), float(kappa), int(r1), int(max_level))
+        for l, (gp, gw, gb) in (grid or {}).items():
+            opt.grid_p[int(l)] = int(gp)
+            opt.grid_w[int(l)] = int(gw)
+            opt.grid_beta[int(l)] = float(gb)
         self._h = lib().orc_plan_create(_ptr(self.X), self.X.shape[0], _ptr(self.Y), self.Y.shape[0],
                                         self.kernel, self.k, self.eps, C.byref(opt))
         if not self._h:

@@ -38,6 +38,10 @@
  *       equispaced phi = pi n / L, weight w_m pi / L  (n_Q = 2L(L+1)).
  *   R11 coincident points (r == 0) contribute nothing.
  *   R12 Morton keys: 21 bits per axis, x in the highest bit of each triple.
+ *   R16-R18 grid form of the transforms (optional per level, parameters given
+ *       by the caller): exponential-of-semicircle kernel of width w nodes and
+ *       shape beta on a p^3 grid of spacing h = d_l / (p - 1 - w) about the box
+ *       centre, the kernel's Fourier transform divided out per direction.
  */
 #include "ffm_oracle.h"
 
@@ -233,6 +237,210 @@ void orc_gegenbauer_diag(int L, double k, const double r0[3], double *D)
     gegenbauer_diag_q(L, k, r0, s, w, nq, (double complex *)D);
     free(s);
     free(w);
+}
+
+/* =========================================================================
+ * Grid form of the plane-wave transforms (readings R16-R18).  The remark closing
+ * Sec. 2.2.3 asks for the transforms of a Gegenbauer level to be evaluated fast
+ * rather than as full sums.  The reading taken: spread the points onto a uniform
+ * grid about the box centre with a smooth kernel phi, sum the grid values against
+ * the plane waves (separably: over z per ring of directions, then over the plane per
+ * direction), and divide by the kernel's Fourier transform.  By Poisson summation,
+ * sum_a phi((x_a - y)/h) e^{-i om x_a} = e^{-i om y} phihat(om h) + aliased terms,
+ * so each axis is exact up to the aliased terms.
+ * ========================================================================= */
+static double es_phi(double t, int w, double beta)
+{
+    double x = 2.0 * t / w, s = 1.0 - x * x;
+    return s > 0.0 ? exp(beta * (sqrt(s) - 1.0)) : 0.0;
+}
+
+/* integral over |t| < w/2 of phi(t) cos(xi t) dt, with t = (w/2) sin(theta): the integrand
+ * (w/2) cos(theta) exp(beta (cos(theta) - 1)) cos(xi t) is smooth on |theta| <= pi/2 */
+static double es_hat_nodes(int w, double beta, double xi, const double *gx, const double *gw, int n)
+{
+    double a = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double th = 0.5 * ORC_PI * gx[j];
+        double t = 0.5 * w * sin(th);
+        a += gw[j] * (0.5 * ORC_PI) * (0.5 * w) * cos(th) * exp(beta * (cos(th) - 1.0)) * cos(xi * t);
+    }
+    return a;
+}
+
+#define ES_HAT_NODES 96
+
+double orc_es_hat(int w, double beta, double xi)
+{
+    double gx[ES_HAT_NODES], gw[ES_HAT_NODES];
+    orc_gauss_legendre(ES_HAT_NODES, gx, gw);
+    return es_hat_nodes(w, beta, xi, gx, gw, ES_HAT_NODES);
+}
+
+typedef struct {
+    int p, w, L;
+    double beta, h, k;
+    int64_t nq;
+    double *s, *wq;    /* the level's quadrature directions and weights */
+    double *Phi;       /* Phi(q) = prod_d phihat(k s_qd h) */
+} gridlev_t;
+
+static void gridlev_init(gridlev_t *g, int p, int w, double beta, double h, double k, int L)
+{
+    g->p = p;
+    g->w = w;
+    g->L = L;
+    g->beta = beta;
+    g->h = h;
+    g->k = k;
+    g->nq = 2 * (int64_t)L * (L + 1);
+    g->s = malloc(sizeof(double) * 3 * g->nq);
+    g->wq = malloc(sizeof(double) * g->nq);
+    g->Phi = malloc(sizeof(double) * g->nq);
+    orc_sphere_quadrature(L, g->s, g->wq);
+    double gx[ES_HAT_NODES], gw[ES_HAT_NODES];
+    orc_gauss_legendre(ES_HAT_NODES, gx, gw);
+    for (int64_t q = 0; q < g->nq; ++q) {
+        double f = 1.0;
+        for (int d = 0; d < 3; ++d) f *= es_hat_nodes(w, beta, k * g->s[3 * q + d] * h, gx, gw, ES_HAT_NODES);
+        g->Phi[q] = f;
+    }
+}
+
+static void gridlev_free(gridlev_t *g)
+{
+    free(g->s);
+    free(g->wq);
+    free(g->Phi);
+}
+
+/* The w nodes whose kernel support holds grid coordinate t (node units): a with -w/2 < a - t <= w/2,
+ * kept inside the grid; their weights phi(a - t). */
+static int spread_nodes(double t, int p, int w, double beta, double *wt)
+{
+    int lo = (int)floor(t - 0.5 * w) + 1;
+    if (lo > p - w) lo = p - w;
+    if (lo < 0) lo = 0;
+    for (int i = 0; i < w; ++i) wt[i] = es_phi(lo + i - t, w, beta);
+    return lo;
+}
+
+static void grid_fwd(const gridlev_t *g, const double *y, const double complex *u, int64_t n, double complex *ut)
+{
+    const int p = g->p, w = g->w, nth = g->L + 1, nph = 2 * g->L;
+    const double half = 0.5 * (p - 1), h = g->h, k = g->k;
+    double complex *G = calloc((size_t)p * p * p, sizeof(double complex));
+    double wx[16], wy[16], wz[16];
+    /* spreading: G[a][b][c] = sum_j u_j phi phi phi */
+    for (int64_t j = 0; j < n; ++j) {
+        int a0 = spread_nodes(y[3 * j] / h + half, p, w, g->beta, wx);
+        int b0 = spread_nodes(y[3 * j + 1] / h + half, p, w, g->beta, wy);
+        int c0 = spread_nodes(y[3 * j + 2] / h + half, p, w, g->beta, wz);
+        for (int ia = 0; ia < w; ++ia)
+            for (int ib = 0; ib < w; ++ib)
+                for (int ic = 0; ic < w; ++ic)
+                    G[((size_t)(a0 + ia) * p + (b0 + ib)) * p + (c0 + ic)] += u[j] * wx[ia] * wy[ib] * wz[ic];
+    }
+    double complex *H = malloc(sizeof(double complex) * (size_t)p * p);
+    double complex *ex = malloc(sizeof(double complex) * p), *ey = malloc(sizeof(double complex) * p);
+    double complex *ez = malloc(sizeof(double complex) * p);
+    for (int m = 0; m < nth; ++m) {
+        /* sums over z for ring m (all its directions share cos(theta)) */
+        const double ct = g->s[3 * ((int64_t)m * nph) + 2];
+        for (int c = 0; c < p; ++c) ez[c] = cexp(-I * k * ct * ((c - half) * h));
+        for (int a = 0; a < p; ++a)
+            for (int b = 0; b < p; ++b) {
+                double complex acc = 0.0;
+                for (int c = 0; c < p; ++c) acc += ez[c] * G[((size_t)a * p + b) * p + c];
+                H[(size_t)a * p + b] = acc;
+            }
+        /* sums over the plane for every direction of the ring */
+        for (int nn = 0; nn < nph; ++nn) {
+            const int64_t q = (int64_t)m * nph + nn;
+            for (int a = 0; a < p; ++a) {
+                ex[a] = cexp(-I * k * g->s[3 * q] * ((a - half) * h));
+                ey[a] = cexp(-I * k * g->s[3 * q + 1] * ((a - half) * h));
+            }
+            double complex acc = 0.0;
+            for (int a = 0; a < p; ++a) {
+                double complex row = 0.0;
+                for (int b = 0; b < p; ++b) row += ey[b] * H[(size_t)a * p + b];
+                acc += ex[a] * row;
+            }
+            ut[q] = acc / g->Phi[q];
+        }
+    }
+    free(G);
+    free(H);
+    free(ex);
+    free(ey);
+    free(ez);
+}
+
+static void grid_bwd(const gridlev_t *g, const double complex *vt, const double *x, int64_t n, double complex *v)
+{
+    const int p = g->p, w = g->w, nth = g->L + 1, nph = 2 * g->L;
+    const double half = 0.5 * (p - 1), h = g->h, k = g->k;
+    double complex *F = calloc((size_t)p * p * p, sizeof(double complex));
+    double complex *K = malloc(sizeof(double complex) * (size_t)p * p);
+    double complex *ex = malloc(sizeof(double complex) * p), *ey = malloc(sizeof(double complex) * p);
+    double complex *ez = malloc(sizeof(double complex) * p);
+    for (int m = 0; m < nth; ++m) {
+        /* K[a][b] = sum over the ring's directions of e^{ik (s_x x_a + s_y y_b)} vt(q) / Phi(q) */
+        for (size_t i = 0; i < (size_t)p * p; ++i) K[i] = 0.0;
+        for (int nn = 0; nn < nph; ++nn) {
+            const int64_t q = (int64_t)m * nph + nn;
+            for (int a = 0; a < p; ++a) {
+                ex[a] = cexp(I * k * g->s[3 * q] * ((a - half) * h));
+                ey[a] = cexp(I * k * g->s[3 * q + 1] * ((a - half) * h));
+            }
+            const double complex f = vt[q] / g->Phi[q];
+            for (int a = 0; a < p; ++a)
+                for (int b = 0; b < p; ++b) K[(size_t)a * p + b] += ex[a] * ey[b] * f;
+        }
+        /* F[a][b][c] += e^{ik cos(theta) z_c} K[a][b] */
+        const double ct = g->s[3 * ((int64_t)m * nph) + 2];
+        for (int c = 0; c < p; ++c) ez[c] = cexp(I * k * ct * ((c - half) * h));
+        for (int a = 0; a < p; ++a)
+            for (int b = 0; b < p; ++b)
+                for (int c = 0; c < p; ++c) F[((size_t)a * p + b) * p + c] += ez[c] * K[(size_t)a * p + b];
+    }
+    /* interpolation at the targets with the same kernel */
+    double wx[16], wy[16], wz[16];
+    for (int64_t i = 0; i < n; ++i) {
+        int a0 = spread_nodes(x[3 * i] / h + half, p, w, g->beta, wx);
+        int b0 = spread_nodes(x[3 * i + 1] / h + half, p, w, g->beta, wy);
+        int c0 = spread_nodes(x[3 * i + 2] / h + half, p, w, g->beta, wz);
+        double complex acc = 0.0;
+        for (int ia = 0; ia < w; ++ia)
+            for (int ib = 0; ib < w; ++ib)
+                for (int ic = 0; ic < w; ++ic)
+                    acc += wx[ia] * wy[ib] * wz[ic] * F[((size_t)(a0 + ia) * p + (b0 + ib)) * p + (c0 + ic)];
+        v[i] += acc;
+    }
+    free(F);
+    free(K);
+    free(ex);
+    free(ey);
+    free(ez);
+}
+
+void orc_grid_forward(int p, int w, double beta, double h, double k, int L, const double *y, const double *u,
+                      int64_t n, double *ut)
+{
+    gridlev_t g;
+    gridlev_init(&g, p, w, beta, h, k, L);
+    grid_fwd(&g, y, (const double complex *)u, n, (double complex *)ut);
+    gridlev_free(&g);
+}
+
+void orc_grid_backward(int p, int w, double beta, double h, double k, int L, const double *vt, const double *x,
+                       int64_t n, double *v)
+{
+    gridlev_t g;
+    gridlev_init(&g, p, w, beta, h, k, L);
+    grid_bwd(&g, (const double complex *)vt, x, n, (double complex *)v);
+    gridlev_free(&g);
 }
 
 /* =========================================================================
@@ -449,6 +657,12 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
     p->opt.kappa = (opt && opt->kappa > 0) ? opt->kappa : ORC_PI;
     p->opt.r1_override = opt ? opt->r1_override : 0;
     p->opt.max_level = (opt && opt->max_level > 0 && opt->max_level <= 20) ? opt->max_level : 20;
+    if (opt)
+        for (int l = 0; l < ORC_MAX_LEVELS; ++l) {
+            p->opt.grid_p[l] = opt->grid_p[l];
+            p->opt.grid_w[l] = opt->grid_w[l];
+            p->opt.grid_beta[l] = opt->grid_beta[l];
+        }
     if (nx <= 0 || ny <= 0) {
         p->empty = 1;
         p->T[0].n = nx > 0 ? nx : 0;
@@ -735,12 +949,29 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     for (int64_t i = 0; i < F->n; ++i)
         if ((F->s[i] % stride) == 0) need[F->s[i]] = 1;
 
+    /* grid form of the transforms at this level (R16-R18), else the direct sums */
+    const int grid = p->opt.grid_p[l] > 0;
+    gridlev_t gl;
+    if (grid) {
+        int gp = p->opt.grid_p[l], gw = p->opt.grid_w[l];
+        gridlev_init(&gl, gp, gw, p->opt.grid_beta[l], ldexp(p->d0, -l) / (double)(gp - 1 - gw), k, L);
+    }
+
     /* forward transform u~_s(q) = sum_j e^{-ik s_q.(y_j - c_s)} u_j */
     double complex *ut = calloc((size_t)nby * nq, sizeof(double complex));
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t b = 0; b < nby; ++b) {
         if (!need[b]) continue;
         const double *c = TY->ctr[l] + 3 * b;
+        if (grid) {
+            int64_t j0 = TY->start[l][b], nb = TY->start[l][b + 1] - j0;
+            double *yr = malloc(sizeof(double) * 3 * (size_t)(nb + 1));
+            for (int64_t j = 0; j < nb; ++j)
+                for (int d = 0; d < 3; ++d) yr[3 * j + d] = TY->P[3 * (j0 + j) + d] - c[d];
+            grid_fwd(&gl, yr, u + j0, nb, ut + b * nq);
+            free(yr);
+            continue;
+        }
         for (int64_t j = TY->start[l][b]; j < TY->start[l][b + 1]; ++j) {
             double y0 = TY->P[3 * j] - c[0], y1 = TY->P[3 * j + 1] - c[1], y2 = TY->P[3 * j + 2] - c[2];
             for (int64_t q = 0; q < nq; ++q)
@@ -766,6 +997,16 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
             for (int64_t q = 0; q < nq; ++q) vt[q] += Dc[q] * us[q];
         }
         const double *c = TX->ctr[l] + 3 * t;
+        if (grid) {
+            int64_t i0 = TX->start[l][t], nt = TX->start[l][t + 1] - i0;
+            double *xr = malloc(sizeof(double) * 3 * (size_t)(nt + 1));
+            for (int64_t i = 0; i < nt; ++i)
+                for (int d = 0; d < 3; ++d) xr[3 * i + d] = TX->P[3 * (i0 + i) + d] - c[d];
+            grid_bwd(&gl, vt, xr, nt, v + i0);
+            free(xr);
+            free(vt);
+            continue;
+        }
         for (int64_t i = TX->start[l][t]; i < TX->start[l][t + 1]; ++i) {
             double x0 = TX->P[3 * i] - c[0], x1 = TX->P[3 * i + 1] - c[1], x2 = TX->P[3 * i + 2] - c[2];
             double complex acc = 0.0;
@@ -775,6 +1016,7 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
         }
         free(vt);
     }
+    if (grid) gridlev_free(&gl);
     free(D);
     classes_free(&C);
     free(ut);

@@ -48,14 +48,36 @@ int64_t orc_sphere_quadrature(int L, double *s, double *w);
 /* transfer diagonal D(q) = (ik/4pi) w_q T_{L,r0}(s_q) for one translation r0 (complex out, nq) */
 void orc_gegenbauer_diag(int L, double k, const double r0[3], double *D);
 
+/* Grid form of the plane-wave transforms of one box (reading R16-R18; the fast evaluation of the
+ * transforms asked for in the remark closing Sec. 2.2.3).  Grid: p nodes per axis at spacing h,
+ * node a at (a - (p-1)/2) h from the box centre; kernel phi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1)),
+ * |t| < w/2 (t in node units); directions: the level's quadrature (orc_sphere_quadrature(L)).
+ *   forward:  ut(q)  = Phi(q)^-1 sum_abc e^{-ik s_q.x_abc} sum_j u_j phi phi phi((x_abc - y_j)/h)
+ *   backward: v_i   += sum_abc phi phi phi((x_abc - x_i)/h) Phi(q)^-1 sum_q e^{ik s_q.x_abc} vt(q)
+ * with Phi(q) = prod_d phihat(k s_qd h), phihat(xi) = integral of phi(t) e^{-i xi t} dt.
+ * Points are box-relative (n x 3); u, ut, vt, v complex (interleaved); v is accumulated. */
+void orc_grid_forward(int p, int w, double beta, double h, double k, int L, const double *y, const double *u,
+                      int64_t n, double *ut);
+void orc_grid_backward(int p, int w, double beta, double h, double k, int L, const double *vt, const double *x,
+                       int64_t n, double *v);
+/* phihat(xi) of the kernel above (Gauss-Legendre after t = (w/2) sin(theta)) */
+double orc_es_hat(int w, double beta, double xi);
+
 /* ---- plan ----------------------------------------------------------------- */
 typedef struct orc_plan orc_plan;
+
+#define ORC_MAX_LEVELS 21
 
 typedef struct {
     int32_t n_leaf;       /* occupancy threshold of the stopping rule (default 64) */
     double  kappa;        /* Gegenbauer iff k*d_l >= kappa (default pi)             */
     int32_t r1_override;  /* > 0: Chebyshev nodes per axis at every Lagrange level */
     int32_t max_level;    /* depth cap (default 20)                                 */
+    /* Grid form of the plane-wave transforms of Gegenbauer level l (reading R16-R18): grid_p[l] > 0
+     * nodes per axis, kernel width grid_w[l] nodes, shape grid_beta[l]; 0 = direct sums. */
+    int32_t grid_p[ORC_MAX_LEVELS];
+    int32_t grid_w[ORC_MAX_LEVELS];
+    double  grid_beta[ORC_MAX_LEVELS];
 } orc_options;
 
 orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t ny,

@@ -28,7 +28,8 @@ EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_versi
             "ffm_plan_export", "ffm_plan_timing", "ffm_plan_bytes", "ffm_workspace_bytes",
             "ffm_plan_set_tiles", "ffm_plan_get_tiles", "ffm_batch_create", "ffm_batch_apply", "ffm_batch_info",
             "ffm_batch_destroy", "ffm_server_create", "ffm_server_submit", "ffm_server_wait", "ffm_server_poll",
-            "ffm_server_stats", "ffm_server_destroy", "ffm_plan_launch_timing", "ffm_kernel_name"]
+            "ffm_server_stats", "ffm_server_destroy", "ffm_plan_launch_timing", "ffm_kernel_name",
+            "ffm_apply_batched"]
 FFM_FLAG_TIMING = 1
 FFM_FLAG_DIRECT_TRANSFORMS = 2
 FFM_FLAG_GRID_TRANSFORMS = 4
@@ -61,7 +62,8 @@ class Stats(C.Structure):
                 ("bwd_points", C.c_double * _L), ("transform_terms", C.c_double),
                 ("transfer_macs", C.c_double), ("near_pairs", C.c_double), ("plan_bytes", C.c_double),
                 ("workspace_bytes", C.c_double), ("grid_nodes", C.c_int32 * _L), ("fwd_boxes", C.c_int64 * _L),
-                ("bwd_boxes", C.c_int64 * _L), ("grid_width", C.c_int32 * _L)]
+                ("bwd_boxes", C.c_int64 * _L), ("grid_width", C.c_int32 * _L), ("grid_beta", C.c_double * _L),
+                ("grid_alias", C.c_double * _L)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -126,7 +128,8 @@ def lib():
             "ffm_batch_info": (C.c_int, [P, P]),
             "ffm_batch_destroy": (C.c_int, [P]),
             "ffm_server_create": (C.c_int, [P, P]),
-            "ffm_server_submit": (C.c_int, [P, P, P, C.c_int, P, P]),
+            "ffm_server_submit": (C.c_int, [P, P, P, C.c_int, P, P, P]),
+            "ffm_apply_batched": (C.c_int, [P, P, P, i32, P]),
             "ffm_server_wait": (C.c_int, [P, i64, P]),
             "ffm_server_poll": (C.c_int, [P, i64, P]),
             "ffm_server_stats": (C.c_int, [P, P]),
@@ -169,6 +172,29 @@ def ffm_apply(plan: int, wu_ptr: int, in_dtype: int, v_ptr: int, stream: int = 0
 
 def ffm_destroy(plan: int) -> None:
     _check(lib().ffm_destroy(plan))
+
+
+def apply_batched(plans, wus, outs=None, stream=None):
+    """v[i] = FFM_i(wu[i]) for distinct plans in one pass of merged launches (ffm_apply_batched); complex64
+    inputs.  Returns the outputs (complex64, each instance's caller order)."""
+    import torch
+    n = len(plans)
+    if len(wus) != n or n == 0:
+        raise ValueError("one input per plan, at least one plan")
+    wus = [w.contiguous() for w in wus]
+    for p, w in zip(plans, wus):
+        if w.dtype != torch.complex64 or w.shape[0] != p.n_y or not w.is_cuda:
+            raise ValueError("wu[i] must be a complex64 CUDA tensor of length n_y of plan i")
+    if outs is None:
+        outs = [torch.empty(p.n_x, dtype=torch.complex64, device=p.device) for p in plans]
+    for p, o in zip(plans, outs):
+        if o.dtype != torch.complex64 or o.shape[0] != p.n_x or not o.is_contiguous():
+            raise ValueError("outs[i] must be a contiguous complex64 tensor of length n_x of plan i")
+    hp = (C.c_void_p * n)(*[p._h for p in plans])
+    wp = (C.c_void_p * n)(*[w.data_ptr() for w in wus])
+    vp = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(lib().ffm_apply_batched(hp, wp, vp, n, _stream(stream)))
+    return outs
 
 
 def ffm_version() -> str:
@@ -387,7 +413,9 @@ class Server:
         self._h = h.value
         self._live = {}
 
-    def submit(self, plan: Plan, wu, out=None):
+    def submit(self, plan: Plan, wu, out=None, stream=None):
+        """Queue one apply; the request is ordered after the work already enqueued on ``stream`` (default:
+        the current stream), which is where wu is expected to be produced."""
         import torch
         if wu.shape[0] != plan.n_y or not wu.is_cuda or not wu.is_contiguous():
             raise ValueError("wu must be a contiguous CUDA tensor of length n_y")
@@ -397,7 +425,7 @@ class Server:
             raise ValueError("out must be a contiguous complex64 tensor of length n_x")
         t = C.c_int64()
         _check(lib().ffm_server_submit(self._h, plan._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(),
-                                       C.byref(t)))
+                                       _stream(stream), C.byref(t)))
         self._live[t.value] = (plan, wu, out)     # keep the buffers alive until the request is waited for
         return t.value, out
 

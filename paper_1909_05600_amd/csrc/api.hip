@@ -199,9 +199,7 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
             for (auto &e : P.tev) FFM_HIP(hipEventCreate(&e));
         }
         P.stats.plan_bytes = (double)plan_device_bytes(P);
-        P.stats.workspace_bytes = (double)(P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() +
-                                           P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() + P.wbpart.bytes() +
-                                           P.wG.bytes() + P.wH.bytes());
+        P.stats.workspace_bytes = (double)apply_work_bytes(P);
         h = p.release();
     });
     if (rc == FFM_OK) *out = h;
@@ -224,6 +222,7 @@ ffm_status_t ffm_apply(ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, vo
 
 ffm_status_t ffm_destroy(ffm_plan_t plan) {
     if (!plan) return FFM_OK;
+    if (int rc = implicit_batch_drop(&plan->P, false)) return (ffm_status_t)rc;
     if (plan->P.batch_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: the plan belongs to a batch");
     if (plan->P.server_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: server requests of the plan are pending");
     if (plan->P.done && plan->P.applied) {
@@ -401,11 +400,6 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
 
 size_t ffm_plan_bytes(ffm_plan_t plan) { return plan ? plan_device_bytes(plan->P) : 0; }
 
-size_t ffm_workspace_bytes(ffm_plan_t plan) {
-    if (!plan) return 0;
-    const Plan &P = plan->P;
-    return P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() +
-           P.wpart.bytes();
-}
+size_t ffm_workspace_bytes(ffm_plan_t plan) { return plan ? apply_work_bytes(plan->P) : 0; }
 
 }  // extern "C"

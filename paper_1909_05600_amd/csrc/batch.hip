@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <tuple>
 
@@ -332,45 +333,15 @@ struct ffm_batch_s {
     Batch B;
 };
 
-extern "C" {
+namespace ffm {
+namespace {
 
-ffm_status_t ffm_plan_set_tiles(ffm_plan_t plan, const ffm_tiles_t *tiles, void *hip_stream) {
-    if (!plan || !tiles) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_set_tiles: NULL argument");
-    if ((tiles->ring_g != 2 && tiles->ring_g != 4) || (tiles->bwd_pt != 1 && tiles->bwd_pt != 2))
-        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_set_tiles: ring_g must be 2 or 4, bwd_pt 1 or 2");
-    Plan &P = plan->P;
-    if (P.batch_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: the plan belongs to a batch");
-    if (P.server_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: server requests of the plan are pending");
-    return (ffm_status_t)Guard::run([&] {
-        plan_sync_ready(P);
-        if (P.applied) FFM_HIP(hipEventSynchronize(P.done));
-        Tune t;
-        t.ring_g = tiles->ring_g;
-        t.bwd_pt = tiles->bwd_pt;
-        plan_set_tune(P, t, static_cast<hipStream_t>(hip_stream));
-    });
-}
-
-ffm_status_t ffm_plan_get_tiles(ffm_plan_t plan, ffm_tiles_t *tiles) {
-    if (!plan || !tiles) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_get_tiles: NULL argument");
-    tiles->ring_g = plan->P.tune.ring_g;
-    tiles->bwd_pt = plan->P.tune.bwd_pt;
-    return FFM_OK;
-}
-
-ffm_status_t ffm_batch_create(const ffm_plan_t *plans, int32_t n, uint32_t flags, const char *tile_cache,
-                              void *hip_stream, ffm_batch_t *out) {
-    if (!out) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: out is NULL");
-    *out = nullptr;
-    if (!plans || n <= 0) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: need at least one plan");
-    if (flags & ~(uint32_t)(FFM_BATCH_GRAPH | FFM_BATCH_AUTOTUNE))
-        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: unknown flags");
+int batch_create(const ffm_plan_t *plans, int32_t n, uint32_t flags, const char *tile_cache, void *hip_stream,
+                 ffm_batch_t *out) {
     for (int32_t i = 0; i < n; ++i) {
-        if (!plans[i]) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: NULL plan");
         for (int32_t j = 0; j < i; ++j)
-            if (plans[j] == plans[i]) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: a plan appears twice");
-        if (plans[i]->P.batch_refs > 0)
-            return (ffm_status_t)set_err(FFM_EBUSY, "ffm_batch_create: a plan already belongs to a batch");
+            if (plans[j] == plans[i]) return set_err(FFM_EINVAL, "ffm_batch_create: a plan appears twice");
+        if (plans[i]->P.batch_refs > 0) return set_err(FFM_EBUSY, "ffm_batch_create: a plan already belongs to a batch");
     }
     ffm_batch_s *h = nullptr;
     int rc = Guard::run([&] {
@@ -426,7 +397,82 @@ ffm_status_t ffm_batch_create(const ffm_plan_t *plans, int32_t n, uint32_t flags
         h = b.release();
     });
     if (rc == FFM_OK) *out = h;
-    return (ffm_status_t)rc;
+    return rc;
+}
+
+// The batch ffm_apply_batched builds for the plan set of its last call (graph-captured), kept for the next call
+// with the same plans in the same order.  Its plans count it in batch_refs like any batch; destroying,
+// retiling or batching one of them first releases it (implicit_batch_drop).
+std::mutex g_imx;
+ffm_batch_s *g_implicit = nullptr;
+std::vector<ffm_plan_t> g_implicit_plans;
+
+// with g_imx held: wait for the implicit batch's last apply and free it
+void implicit_free_locked() {
+    if (!g_implicit) return;
+    if (g_implicit->B.applied) FFM_HIP(hipEventSynchronize(g_implicit->B.done));
+    delete g_implicit;
+    g_implicit = nullptr;
+    g_implicit_plans.clear();
+}
+
+}  // namespace
+
+int implicit_batch_drop(const Plan *P, bool wait) {
+    std::lock_guard<std::mutex> lk(g_imx);
+    if (!g_implicit) return FFM_OK;
+    bool holds = false;
+    for (Plan *q : g_implicit->B.plans) holds = holds || q == P;
+    if (!holds) return FFM_OK;
+    if (!wait && g_implicit->B.applied && hipEventQuery(g_implicit->B.done) == hipErrorNotReady)
+        return set_err(FFM_EBUSY, "a batched apply of the plan is still in flight");
+    return Guard::run([&] { implicit_free_locked(); });
+}
+
+}  // namespace ffm
+
+extern "C" {
+
+ffm_status_t ffm_plan_set_tiles(ffm_plan_t plan, const ffm_tiles_t *tiles, void *hip_stream) {
+    if (!plan || !tiles) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_set_tiles: NULL argument");
+    if ((tiles->ring_g != 2 && tiles->ring_g != 4) || (tiles->bwd_pt != 1 && tiles->bwd_pt != 2))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_set_tiles: ring_g must be 2 or 4, bwd_pt 1 or 2");
+    Plan &P = plan->P;
+    if (int rc = implicit_batch_drop(&P, true)) return (ffm_status_t)rc;
+    if (P.batch_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: the plan belongs to a batch");
+    if (P.server_refs > 0) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_plan_set_tiles: server requests of the plan are pending");
+    return (ffm_status_t)Guard::run([&] {
+        plan_sync_ready(P);
+        if (P.applied) FFM_HIP(hipEventSynchronize(P.done));
+        Tune t;
+        t.ring_g = tiles->ring_g;
+        t.bwd_pt = tiles->bwd_pt;
+        plan_set_tune(P, t, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+ffm_status_t ffm_plan_get_tiles(ffm_plan_t plan, ffm_tiles_t *tiles) {
+    if (!plan || !tiles) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan_get_tiles: NULL argument");
+    tiles->ring_g = plan->P.tune.ring_g;
+    tiles->bwd_pt = plan->P.tune.bwd_pt;
+    return FFM_OK;
+}
+
+ffm_status_t ffm_batch_create(const ffm_plan_t *plans, int32_t n, uint32_t flags, const char *tile_cache,
+                              void *hip_stream, ffm_batch_t *out) {
+    if (!out) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: out is NULL");
+    *out = nullptr;
+    if (!plans || n <= 0) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: need at least one plan");
+    if (flags & ~(uint32_t)(FFM_BATCH_GRAPH | FFM_BATCH_AUTOTUNE))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: unknown flags");
+    for (int32_t i = 0; i < n; ++i)
+        if (!plans[i]) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_batch_create: NULL plan");
+    // a plan held only by the batch that ffm_apply_batched keeps is released from it
+    for (int32_t i = 0; i < n; ++i) {
+        int rc = implicit_batch_drop(&plans[i]->P, true);
+        if (rc != FFM_OK) return (ffm_status_t)rc;
+    }
+    return (ffm_status_t)batch_create(plans, n, flags, tile_cache, hip_stream, out);
 }
 
 ffm_status_t ffm_batch_apply(ffm_batch_t batch, const void *const *wu, const ffm_dtype_t *in_dtype, void *const *v,
@@ -483,6 +529,30 @@ ffm_status_t ffm_batch_destroy(ffm_batch_t batch) {
         if (q == hipErrorNotReady) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_batch_destroy: an apply is still in flight");
     }
     return (ffm_status_t)Guard::run([&] { delete batch; });
+}
+
+ffm_status_t ffm_apply_batched(const ffm_plan_t *plans, const void *const *wu, void *const *v, int32_t n,
+                               void *hip_stream) {
+    if (!plans || !wu || !v || n <= 0) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_apply_batched: NULL argument or n <= 0");
+    for (int32_t i = 0; i < n; ++i) {
+        if (!plans[i]) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_apply_batched: NULL plan");
+        if ((plans[i]->P.ny > 0 && !wu[i]) || (plans[i]->P.nx > 0 && !v[i]))
+            return (ffm_status_t)set_err(FFM_EINVAL, "ffm_apply_batched: NULL input or output");
+    }
+    std::lock_guard<std::mutex> lk(g_imx);
+    const bool same = g_implicit && (int32_t)g_implicit_plans.size() == n &&
+                      std::equal(g_implicit_plans.begin(), g_implicit_plans.end(), plans);
+    if (!same) {
+        int rc = Guard::run([&] { implicit_free_locked(); });
+        if (rc != FFM_OK) return (ffm_status_t)rc;
+        ffm_batch_t b = nullptr;
+        rc = batch_create(plans, n, FFM_BATCH_GRAPH, nullptr, hip_stream, &b);
+        if (rc != FFM_OK) return (ffm_status_t)rc;
+        g_implicit = b;
+        g_implicit_plans.assign(plans, plans + n);
+    }
+    std::vector<ffm_dtype_t> dt((size_t)n, FFM_C64);
+    return ffm_batch_apply(g_implicit, wu, dt.data(), v, hip_stream);
 }
 
 }  // extern "C"

@@ -321,6 +321,7 @@ struct Level {
     bool grid = false;
     int gp = 0, gw = 0;
     double gh = 0, gbeta = 0;
+    double galias = 0;                   // aliasing bound of one axis at the level's largest |k s_d h|
     DevBuf<float2> Ez, Ex, Ey;           // [nrp][p], [nrp][p][L], [nrp][p][L]
     DevBuf<float2> ExT, EyT;             // [nrp][L][p]
     DevBuf<int32_t> gperm, gzs;          // source points ordered by box and z-plane; [nbox_y][p + 1]
@@ -399,6 +400,19 @@ struct LevelWork {                     // apply workspace a descriptor points in
     float2 *ut2 = nullptr, *Z = nullptr, *bpart = nullptr;
     float2 *G = nullptr, *H = nullptr;
 };
+// Apply workspace laid out in one block (requests of the server, the static-scratch apply): its size in bytes
+// (every part aligned to 256 B; also what ffm_workspace_bytes and ffm_stats_t.workspace_bytes report), and the
+// part pointers for a block at base.
+struct WorkPtrs {
+    float2 *u = nullptr, *v = nullptr;   // sorted input, sorted output accumulator
+    float *amax = nullptr;
+    LevelWork lw;
+};
+size_t apply_work_bytes(const Plan &P);
+WorkPtrs carve_work(const Plan &P, char *base);
+// Release the batch kept by ffm_apply_batched if it holds plan P; a status code.  With wait, its last apply is
+// waited for; without, an apply still in flight gives FFM_EBUSY and nothing is released.
+int implicit_batch_drop(const Plan *P, bool wait);
 // concurrent blocks per CU of a kernel variant (occupancy) and the device's CU count
 int stage_blocks_per_cu(int kern, int a, int b);
 std::string kernel_name(int kern, int a, int b);

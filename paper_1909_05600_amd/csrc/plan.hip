@@ -732,7 +732,7 @@ double spread_alias_bound(int w, double beta, double kh) {
 // cost function rates cheapest.  Returns false if none qualifies.
 template <class Cost>
 bool grid_choice(double eps, double k, double dl, double kh_max, const Cost &cost, int &w, double &beta, int &p,
-                 double &h) {
+                 double &h, double &alias) {
     double best_cost = 1e300;
     bool found = false;
     const int p0 = ((int)std::ceil(dl * k / kh_max) + 4 + 1 + 15) / 16 * 16;
@@ -759,6 +759,7 @@ bool grid_choice(double eps, double k, double dl, double kh_max, const Cost &cos
                 beta = bb;
                 p = pp;
                 h = hh;
+                alias = bnd;
             }
             break;   // wider kernels on the same grid only cost more
         }
@@ -1280,8 +1281,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 // grids down to 1.5 nodes per half wavelength: k s_d h <= pi / 1.5, where the kernel's Fourier
                 // transform divided out stays above 0.3 per axis
                 int w = 0, p = 0;
-                double beta = 0.0, h = 0.0;
-                const bool have = grid_choice(P.eps, P.k, dl, M_PI / 1.5, grid_cost, w, beta, p, h);
+                double beta = 0.0, h = 0.0, alias = 0.0;
+                const bool have = grid_choice(P.eps, P.k, dl, M_PI / 1.5, grid_cost, w, beta, p, h, alias);
                 const double direct = (LV.pts_src + LV.pts_tgt) * (double)LV.nq * 9e-14;
                 const double gridc = have ? grid_cost(p, w) : 1e300;
                 const size_t gnb = (size_t)std::max(nbx, nby);
@@ -1295,6 +1296,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     LV.gp = p;
                     LV.gh = h;
                     LV.gbeta = beta;
+                    LV.galias = alias;
                     const int64_t nxy = (int64_t)LV.nrp * p * L;
                     LV.Ez.alloc((size_t)LV.nrp * p);
                     LV.Ex.alloc((size_t)nxy);
@@ -1506,6 +1508,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.bwd_points[l] = LV.pts_tgt;
         s.grid_nodes[l] = LV.method == kGegenbauer && LV.grid ? LV.gp : 0;
         s.grid_width[l] = LV.method == kGegenbauer && LV.grid ? LV.gw : 0;
+        s.grid_beta[l] = LV.method == kGegenbauer && LV.grid ? LV.gbeta : 0.0;
+        s.grid_alias[l] = LV.method == kGegenbauer && LV.grid ? LV.galias : 0.0;
         s.fwd_boxes[l] = (int64_t)LV.h_fwd.size();
         s.bwd_boxes[l] = (int64_t)LV.h_tgt.size();
         if (LV.method == kGegenbauer) {

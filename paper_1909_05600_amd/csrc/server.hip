@@ -30,13 +30,12 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 // Apply workspace of one request, carved from one device block.
 struct ReqWork {
     DevBuf<char> block;
-    float2 *u = nullptr, *v = nullptr, *Z = nullptr;
-    float4 *ut = nullptr, *vt = nullptr, *part = nullptr;
-    float2 *bpart = nullptr, *G = nullptr, *H = nullptr;
-    float *amax = nullptr;
+    WorkPtrs w;
 };
 
-size_t work_bytes(const Plan &P) {
+}  // namespace
+
+size_t apply_work_bytes(const Plan &P) {
     if (P.empty) return 0;
     return align256(sizeof(float2) * P.ny) + align256(sizeof(float2) * P.nx) + align256(sizeof(float4) * P.ws_src) +
            align256(sizeof(float4) * P.ws_tgt) + align256(sizeof(float2) * P.ws_z) +
@@ -44,10 +43,8 @@ size_t work_bytes(const Plan &P) {
            align256(sizeof(float2) * P.wG.n) + align256(sizeof(float2) * P.wH.n) + (P.any_fp16 || P.any_grid ? 256 : 0);
 }
 
-void carve(const Plan &P, ReqWork &w) {
-    const size_t b = work_bytes(P);
-    w.block.alloc(std::max<size_t>(b, 1));
-    char *p = w.block.p;
+WorkPtrs carve_work(const Plan &P, char *p) {
+    WorkPtrs w;
     auto take = [&](size_t bytes) {
         char *q = p;
         p += align256(bytes);
@@ -55,14 +52,24 @@ void carve(const Plan &P, ReqWork &w) {
     };
     w.u = reinterpret_cast<float2 *>(take(sizeof(float2) * P.ny));
     w.v = reinterpret_cast<float2 *>(take(sizeof(float2) * P.nx));
-    w.ut = reinterpret_cast<float4 *>(take(sizeof(float4) * P.ws_src));
-    w.vt = reinterpret_cast<float4 *>(take(sizeof(float4) * P.ws_tgt));
-    w.Z = reinterpret_cast<float2 *>(take(sizeof(float2) * P.ws_z));
-    w.part = reinterpret_cast<float4 *>(take(sizeof(float4) * P.wpart.n));
-    w.bpart = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wbpart.n));
-    w.G = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wG.n));
-    w.H = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wH.n));
+    w.lw.ut = reinterpret_cast<float4 *>(take(sizeof(float4) * P.ws_src));
+    w.lw.vt = reinterpret_cast<float4 *>(take(sizeof(float4) * P.ws_tgt));
+    w.lw.ut2 = reinterpret_cast<float2 *>(w.lw.ut);
+    w.lw.Z = reinterpret_cast<float2 *>(take(sizeof(float2) * P.ws_z));
+    w.lw.part = reinterpret_cast<float4 *>(take(sizeof(float4) * P.wpart.n));
+    w.lw.bpart = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wbpart.n));
+    w.lw.G = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wG.n));
+    w.lw.H = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wH.n));
     w.amax = P.any_fp16 || P.any_grid ? reinterpret_cast<float *>(take(sizeof(float))) : nullptr;
+    return w;
+}
+
+namespace {
+
+void carve(const Plan &P, ReqWork &w) {
+    const size_t b = apply_work_bytes(P);
+    w.block.alloc(std::max<size_t>(b, 1));
+    w.w = carve_work(P, w.block.p);
 }
 
 }  // namespace
@@ -83,6 +90,11 @@ struct Request {
     DevBuf<IoEntry> dio;
     void *pinned = nullptr;            // descriptors + I/O entry staging
     hipEvent_t ev = nullptr;
+    hipEvent_t ready = nullptr;        // recorded on the caller's stream at submission: wu is written
+    ~Request() {
+        if (ev) (void)hipEventDestroy(ev);
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
 struct Server {
@@ -116,30 +128,24 @@ void Server::start_one(Request *r, int slot) {
     r->t_start = Clock::now();
     FFM_HIP(hipEventCreateWithFlags(&r->ev, hipEventDisableTiming));
     if (P.empty) {
+        if (r->ready) FFM_HIP(hipStreamWaitEvent(st, r->ready, 0));
         // no sources or no targets: the output is zero
         if (P.nx > 0) FFM_HIP(hipMemsetAsync(r->io.vout, 0, sizeof(float2) * P.nx, st));
         FFM_HIP(hipEventRecord(r->ev, st));
         return;
     }
     carve(P, r->work);
-    LevelWork w;
-    w.ut = r->work.ut;
-    w.vt = r->work.vt;
-    w.part = r->work.part;
-    w.ut2 = reinterpret_cast<float2 *>(r->work.ut);
-    w.Z = r->work.Z;
-    w.bpart = r->work.bpart;
-    w.G = r->work.G;
-    w.H = r->work.H;
+    const WorkPtrs &w = r->work.w;
     const int nd = P.leaf + 1;
     const size_t db = sizeof(LDesc) * nd;
     r->pinned = pinned_alloc(db + sizeof(IoEntry));
     LDesc *hd = static_cast<LDesc *>(r->pinned);
-    for (int l = 0; l < nd; ++l) hd[l] = make_desc(P, l, 0, r->work.u, r->work.v, r->work.amax, w);
+    for (int l = 0; l < nd; ++l) hd[l] = make_desc(P, l, 0, w.u, w.v, w.amax, w.lw);
     IoEntry *hio = reinterpret_cast<IoEntry *>(static_cast<char *>(r->pinned) + db);
     *hio = r->io;
     r->ddesc.alloc(nd);
     r->dio.alloc(1);
+    if (r->ready) FFM_HIP(hipStreamWaitEvent(st, r->ready, 0));
     FFM_HIP(hipMemcpyAsync(r->ddesc.p, hd, db, hipMemcpyHostToDevice, st));
     FFM_HIP(hipMemcpyAsync(r->dio.p, hio, sizeof(IoEntry), hipMemcpyHostToDevice, st));
     for (const Stage &S : P.pre) run_stage(S, r->ddesc.p, r->dio.p, st);
@@ -154,6 +160,8 @@ void Server::finish_one(Request *r) {
     r->t_done = Clock::now();
     if (r->ev) (void)hipEventDestroy(r->ev);
     r->ev = nullptr;
+    if (r->ready) (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
     r->work.block.release();
     r->ddesc.release();
     r->dio.release();
@@ -285,14 +293,14 @@ ffm_status_t ffm_server_create(const ffm_server_options_t *opts, ffm_server_t *o
 }
 
 ffm_status_t ffm_server_submit(ffm_server_t server, ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, void *v,
-                               int64_t *ticket) {
+                               void *hip_stream, int64_t *ticket) {
     if (!server || !plan || !ticket) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_server_submit: NULL argument");
     Plan &P = plan->P;
     if (P.nx > 0 && !v) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_server_submit: NULL output");
     if (P.ny > 0 && !wu) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_server_submit: NULL input");
     if (in_dtype < FFM_C64 || in_dtype > FFM_C128) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_server_submit: bad dtype");
     Server &S = server->S;
-    const size_t bytes = work_bytes(P);
+    const size_t bytes = apply_work_bytes(P);
     if (bytes > S.budget)
         return (ffm_status_t)set_err(FFM_ENOMEM, "ffm_server_submit: the request's workspace exceeds the whole budget");
     return (ffm_status_t)Guard::run([&] {
@@ -303,6 +311,9 @@ ffm_status_t ffm_server_submit(ffm_server_t server, ffm_plan_t plan, const void 
         r->io.vout = static_cast<float2 *>(v);
         r->io.dtype = (int)in_dtype;
         r->bytes = bytes;
+        // the request starts only once the caller's stream has passed what it enqueued before submitting
+        FFM_HIP(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
+        FFM_HIP(hipEventRecord(r->ready, static_cast<hipStream_t>(hip_stream)));
         r->t_submit = Clock::now();
         std::lock_guard<std::mutex> lk(S.mx);
         FFM_CHECK(!S.stop, FFM_EINVAL, "ffm_server_submit: the server is shutting down");

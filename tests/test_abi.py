@@ -84,6 +84,10 @@ def test_batch_arguments_are_rejected_before_any_device_work(L):
     assert L.ffm_batch_create(arr, 2, 8, None, None, C.byref(h)) == -1    # unknown flag
     assert h.value is None
     assert L.ffm_batch_apply(None, None, None, None, None) == -1
+    ptrs = (C.c_void_p * 2)(None, None)
+    assert L.ffm_apply_batched(None, ptrs, ptrs, 2, None) == -1           # no plans
+    assert L.ffm_apply_batched(arr, ptrs, ptrs, 0, None) == -1            # n <= 0
+    assert L.ffm_apply_batched(arr, ptrs, ptrs, 2, None) == -1            # NULL plan
     assert L.ffm_batch_info(None, None) == -1
     assert L.ffm_batch_destroy(None) == 0
     t = ffm.Tiles(4, 2)
@@ -101,7 +105,7 @@ def test_server_arguments_are_rejected_before_any_device_work(L):
         assert L.ffm_server_create(C.byref(bad), C.byref(h)) == -1
     assert h.value is None
     t = C.c_int64()
-    assert L.ffm_server_submit(None, None, None, 0, None, C.byref(t)) == -1
+    assert L.ffm_server_submit(None, None, None, 0, None, None, C.byref(t)) == -1
     assert L.ffm_server_wait(None, 1, None) == -1
     d = C.c_int32()
     assert L.ffm_server_poll(None, 1, C.byref(d)) == -1

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import ffm_workloads as W
-from gpu_common import RTOL_FFM, gpu_apply, gpu_plan, rel
+from gpu_common import FP32_RTOL, gpu_apply, gpu_plan, oracle_like, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -95,14 +95,14 @@ def test_batch_matches_oracle(orc):
     torch.cuda.synchronize()
     for i in (0, 1, 2, 9, 10):          # 10: grid-form levels
         X, Y, kern, k, eps, kw, w = specs[i]
-        op = orc.Plan(X, X if Y is X else Y, kern, k, eps)
+        op = oracle_like(orc, plans[i], X, X if Y is X else Y, kern, k, eps)
         vo = op.apply(w)
         v = outs[i].cpu().numpy().astype(np.complex128)
         rows = np.arange(0, X.shape[0], max(1, X.shape[0] // 256))
         d = orc.dense_rows(X, X if Y is X else Y, w, kern, k, rows)
         print("instance %d (N=%d kernel %d k=%.2f): vs oracle %.3e vs dense %.3e"
               % (i, X.shape[0], kern, k, rel(v, vo), rel(v[rows], d)))
-        assert rel(v, vo) < RTOL_FFM[kern]
+        assert rel(v, vo) < FP32_RTOL
         assert rel(v[rows], d) <= eps
     b.destroy()
 
@@ -206,4 +206,37 @@ def test_cfg4_batch_256_instances(orc):
     print("cfg4: worst relative error vs dense over 256 instances %.3e" % worst)
     b.destroy()
     for p in plans:
+        p.destroy()
+
+
+def test_apply_batched_entry_point():
+    """ffm_apply_batched: complex64 inputs of a plan set in one pass of merged launches, bitwise equal to each
+    plan's own apply; a second call with the same set reuses the kept launches, a call with another set
+    replaces them, and destroying a plan of the kept set releases it (then the others still apply alone)."""
+    import torch
+    import paper_1909_05600_amd as ffm
+    plans, wus, _ = _mixed_instances()
+    wus = [w.to(torch.complex64) for w in wus]
+    ref = _standalone(plans, wus)
+    for rep in range(2):
+        outs = ffm.apply_batched(plans, wus)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, ref)):
+            assert np.array_equal(o.cpu().numpy(), r), (rep, i)
+    sub = plans[:4]
+    outs = ffm.apply_batched(sub, wus[:4])
+    torch.cuda.synchronize()
+    for i in range(4):
+        assert np.array_equal(outs[i].cpu().numpy(), ref[i]), i
+    with pytest.raises(ffm.FFMError) as e:
+        ffm.apply_batched([plans[0], plans[0]], [wus[0], wus[0]])      # a plan twice
+    assert e.value.code == -1
+    plans[0].destroy()                       # held by the kept launches: released first
+    assert np.array_equal(_standalone(plans[1:4], wus[1:4])[2], ref[3])
+    b = ffm.Batch(plans[1:3], graph=True)    # an explicit batch of plans the kept launches no longer hold
+    with pytest.raises(ffm.FFMError) as e:
+        ffm.apply_batched(plans[1:3], wus[1:3])
+    assert e.value.code == -4
+    b.destroy()
+    for p in plans[1:]:
         p.destroy()

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import ffm_workloads as W
-from gpu_common import RTOL_FFM, rel
+from gpu_common import FP32_RTOL, oracle_grid, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,7 @@ def test_matvec_parity(orc, ob, kernel, k, nt):
     s64 = sig.astype(np.complex128)
     w32 = p.w.astype(np.float32).astype(np.float64)            # the harness scales by FP32 weights
     # the oracle's FFM with identical parameters
-    op = orc.Plan(p.X, p.X, kernel, p.k, p.eps)
+    op = orc.Plan(p.X, p.X, kernel, p.k, p.eps, grid=oracle_grid(A.plan))
     lam0 = ob.single_layer_eigenvalue(0, p.k, p.radius)
     vo = op.apply(w32 * s64) + (lam0 - op.apply(w32.astype(np.complex128))) * s64
     # dense FP64 rows; the FFM meets eps on each of its two products
@@ -56,14 +56,14 @@ def test_matvec_parity(orc, ob, kernel, k, nt):
     gd = orc.dense_rows(p.X, p.X, w32.astype(np.complex128), kernel, p.k, rows)
     vd = sd + (lam0 - gd) * s64[rows]
     bound = p.eps * (np.linalg.norm(sd) + np.linalg.norm(gd) * np.abs(s64[rows]).max()) / np.linalg.norm(vd)
-    # FP32 against FP64 with identical parameters: RTOL_FFM bounds each of the two products relative to its
+    # FP32 against FP64 with identical parameters: FP32_RTOL bounds each of the two products relative to its
     # own size; the diagonal term cancels much of the second, so scale by the products' sizes
     so = op.apply(w32 * s64)
     go = op.apply(w32.astype(np.complex128)) * s64
     scale = (np.linalg.norm(so) + np.linalg.norm(go)) / np.linalg.norm(vo)
     print("N=%d kernel %d k=%.2f: vs oracle FFM %.3e (bound %.3e), vs dense %.3e (bound %.3e)"
-          % (p.n, kernel, p.k, rel(v, vo), RTOL_FFM[kernel] * scale, rel(v[rows], vd), bound))
-    assert rel(v, vo) < RTOL_FFM[kernel] * scale
+          % (p.n, kernel, p.k, rel(v, vo), FP32_RTOL * scale, rel(v[rows], vd), bound))
+    assert rel(v, vo) < FP32_RTOL * scale
     assert rel(v[rows], vd) <= bound
     A.destroy()
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import ffm_workloads as W
-from gpu_common import gpu_apply, gpu_plan, rel
+from gpu_common import FP32_RTOL, gpu_apply, gpu_plan, oracle_like, rel
 
 pytestmark = pytest.mark.gpu
 MIXED = 1
@@ -25,12 +25,12 @@ def test_mixed_laplace(orc, eps):
     expect_fp16 = eps >= 2.0 ** -11
     assert all(st["prec"][l] == (1 if expect_fp16 else 0) for l in lag), st["prec"]
     v = gpu_apply(gp, w.wu)
-    vo = orc.Plan(w.X, w.X, 0, 0.0, eps).apply(w.wu)
+    vo = oracle_like(orc, gp, w.X, w.X, 0, 0.0, eps).apply(w.wu)
     d = orc.dense_rows(w.X, w.X, w.wu, 0, 0.0, w.rows[:2048])
     e_o, e_d = rel(v, vo), rel(v[w.rows[:2048]], d)
     print("mixed laplace eps=%g fp16=%s: vs oracle %.3e vs dense %.3e" % (eps, expect_fp16, e_o, e_d))
     assert e_d <= eps
-    assert e_o <= (2.0 ** -11 if expect_fp16 else 2e-5)
+    assert e_o <= (2.0 ** -11 if expect_fp16 else FP32_RTOL)
     if not expect_fp16:
         # no FP16 level: the mixed plan runs exactly the FP32 kernels
         assert np.array_equal(v, gpu_apply(gpu_plan(w.X, w.X, 0, 0.0, eps), w.wu))
@@ -45,7 +45,7 @@ def test_mixed_helmholtz_low_frequency(orc):
     assert any(st["prec"][l] == 1 for l in range(1, st["leaf"] + 1))
     assert all(st["prec"][l] == 0 for l in range(1, st["leaf"] + 1) if st["method"][l] == 2)
     v = gpu_apply(gp, wu)
-    vo = orc.Plan(X, X, 1, 9.0, 1e-3).apply(wu)
+    vo = oracle_like(orc, gp, X, X, 1, 9.0, 1e-3).apply(wu)
     rows = np.arange(0, 20000, 13)
     d = orc.dense_rows(X, X, wu, 1, 9.0, rows)
     print("mixed helmholtz k=9: vs oracle %.3e vs dense %.3e" % (rel(v, vo), rel(v[rows], d)))

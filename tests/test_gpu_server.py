@@ -47,6 +47,8 @@ def test_mixed_requests_equal_standalone():
     reqs = []
     for rep in range(3):                       # three requests per plan, all submitted at once
         for i, (p, w) in enumerate(zip(plans, wus)):
+            # wr is written on the current stream; submit orders the request after it (a device-side wait on
+            # an event recorded at submission), with no host synchronisation in between
             wr = w * (1.0 + rep)
             t, out = srv.submit(p, wr)
             reqs.append((i, wr, t, out))

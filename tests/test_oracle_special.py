@@ -77,10 +77,37 @@ def test_lagrange_reproduces_polynomials(orc, r1):
     assert abs(np.dot(ell, nodes ** r1) - 0.3 ** r1) > 1e-6
 
 
-def test_gegenbauer_rank_values(orc):
-    # L = floor(|k| sqrt(3) d_l - ln eps), natural log; L >= 1
-    assert orc.gegenbauer_rank(181.499, 0.5, 1e-3) == math.floor(181.499 * math.sqrt(3) * 0.5 + math.log(1e3))
-    assert orc.gegenbauer_rank(0.0, 1.0, 0.9) == 1
+@pytest.mark.parametrize("kdl", [5.67, 11.3])
+def test_gegenbauer_rank_meets_eps_at_the_closest_offset(orc, kdl):
+    """The rank of eq. (gegenbauerRank) read with the natural log (reading R7) keeps the single-pair error of the
+    expansion below eps = 1e-3 for every sampled pair of points at the closest admissible offset (2, 0, 0), the
+    worst case of a level; the decimal-log reading, 4 orders fewer, fails it at the leaf-like level kd = 5.67.
+    Pinned against e^{ikr} / (4 pi r) itself, not against the formula."""
+    k, eps = 181.499, 1e-3
+    d = kdl / k
+
+    def worst(L):
+        s, _ = orc.sphere_quadrature(L)
+        r0 = np.array([2.0, 0.0, 0.0]) * d
+        D = orc.gegenbauer_diag(L, k, r0)
+        rng = np.random.default_rng(7)
+        xs = (rng.random((60, 3)) - 0.5) * d
+        ys = (rng.random((60, 3)) - 0.5) * d
+        e = 0.0
+        for x, y in zip(xs, ys):
+            r = np.linalg.norm(r0 + x - y)
+            exact = np.exp(1j * k * r) / (4 * math.pi * r)
+            approx = np.sum(np.exp(1j * k * (s @ x)) * D * np.exp(-1j * k * (s @ y)))
+            e = max(e, abs(approx - exact) / abs(exact))
+        return e
+
+    L = orc.gegenbauer_rank(k, d, eps)
+    assert worst(L) < eps
+    if kdl < 6:
+        assert worst(int(math.floor(k * math.sqrt(3) * d - math.log10(eps)))) > eps
+    # the rank grows with the box: one more level up needs more terms
+    assert orc.gegenbauer_rank(k, 2 * d, eps) > L
+    assert orc.gegenbauer_rank(0.0, 1.0, 0.9) == 1          # L >= 1
 
 
 @pytest.mark.parametrize("L", [1, 2, 5, 16, 40])

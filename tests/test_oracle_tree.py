@@ -189,6 +189,33 @@ def test_quadtree_counts_of_the_paper(orc):
     assert len({tuple(o) for o in off}) == n_tr
 
 
+def test_quadtree_counts_shifted_trees(orc):
+    """Shifted trees (Sec. 3.2, proof of Prop. 1, right-hand configuration): the source root is translated by half
+    a box of level 4 along x and y.  With the max-norm admissibility an interior target box then has 48 far
+    interactions, the paper's count for shifted trees (tests/golden).  The translations of the level are the
+    integer offsets plus the common half-box shift; over the whole level they number 65 (the reading recorded
+    next to the golden value: the paper's 48 matches the interactions of one box)."""
+    m = 16
+    X = _grid_points(m, 2, 5)
+    Y = _grid_points(m, 2, 6) + np.array([0.5 / m, 0.5 / m, 0.0])      # the bounding box moves by d_4 / 2
+    p = orc.Plan(X, Y, 0, 0.0, 1e-3, n_leaf=1, max_level=5)
+    assert p.leaf >= 4 and abs(p.corner(1)[0] - p.corner(0)[0] - 0.5 / m) < 1e-15
+    l = 4
+    t, s, off = p.far(l)
+    ijk = p.box_ijk(0, l)
+    counts = np.bincount(t, minlength=p.nbox(0, l))
+    # targets whose far candidates (offsets -4 .. 4 of the source grid) all exist
+    interior = np.all((ijk[:, :2] >= 5) & (ijk[:, :2] <= 10), axis=1)
+    assert interior.sum() >= 16
+    assert np.all(counts[interior] == _paper("quadtree_interior_far_interactions_shifted"))
+    assert counts.max() == 48
+    assert len({tuple(o) for o in off}) == 65
+    # the far test is taken in FP64 on the centres: every far pair is at max-norm distance >= 2 d_l
+    cx, cy = p.box_centre(0, l), p.box_centre(1, l)
+    dl = p.d0 / 2 ** l
+    assert np.all(np.abs(cx[t] - cy[s]).max(axis=1) >= 2 * dl)
+
+
 def test_octree_counts(orc):
     """3-D analogues: 6^3 - 3^3 = 189 interactions of an interior box, 7^3 - 3^3 = 316 translations."""
     P = _grid_points(16, 3, 4)
