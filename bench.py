@@ -23,21 +23,27 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = 39.3e12 VALU issue slots/s (FP32 non-packed,
-# the form this library is built for); reported as FMA-equivalent TFLOP/s = 2 x slots/s.
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = 39.3e12 FP32 lane operations/s without packed FP32 (this
+# library is built with packed FP32 disabled); an FMA counts 2 flops: 78.6 TFLOP/s.  The data-sheet 157.3 counts
+# the packed form and is reported beside it.
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 PEAK_ALU_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12          # 78.6
-# Minimal non-transcendental VALU slots of the plane-wave transforms as implemented (sin/cos run on the
-# transcendental unit at half rate, co-issued, and take FP32 phases unreduced; see profiles/peaks_mi355x.txt):
-#   direction-pair form: per (point, antipodal pair)   3 phase + 4 accumulate = 7 slots / 2 directions
-#   ring-pair form:      per (point, group of 4 dirs)   2 phase + 8 accumulate = 10 slots / 4 directions
-SLOTS_PER_DIRECTION = {1: 7 / 2, 2: 10 / 4}
-# Near field, per (target, source) pair: Laplace ~10 non-transcendental slots, Helmholtz ~18 (plus sin, cos and
-# reciprocal square root on the transcendental unit).
+PEAK_ALU_PACKED_TFLOPS = 157.3
+# Algorithmic flops (an FMA = 2, a sine, cosine or reciprocal square root = 1):
+#   plane-wave transforms, per (point, direction) term: 3 FMA of phase (6) + sin + cos (2) + a complex
+#     multiply-add (4 FMA = 7 flops after the shared phase): 15
+#   near field, per (target, source) pair: Laplace 14 (3 differences, |d|^2 in 3 FMA, rsqrt, 1/(4 pi) scale, a
+#     complex multiply-add), Helmholtz 24 (the same, k r, sin, cos, two products e^{ikr}/r and a complex
+#     multiply-add)
+FLOPS_PER_TERM = 15.0
+NEAR_FLOPS = {"k_near<false>": 14.0, "k_near<true>": 24.0}
+# VALU issue slots the implemented near-field loop needs per pair at least (transcendentals co-issue): the slot
+# utilisation is reported separately from the flop fraction
 NEAR_SLOTS = {"k_near<false>": 10.0, "k_near<true>": 18.0}
-# Published MI355X peaks per bound: dense FP32 MFMA 157.3 TFLOP/s, FP32 VALU (non-packed, FMA = 2) 78.6,
-# HBM3E 8 TB/s.
-PEAKS = {"mfma": (157.3, "TFLOP/s"), "alu": (PEAK_ALU_TFLOPS, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
+# Published MI355X peaks per bound: dense FP32 MFMA 157.3 TFLOP/s, dense FP16 MFMA 2500, FP32 VALU (non-packed,
+# FMA = 2) 78.6, HBM3E 8 TB/s.
+PEAKS = {"mfma": (157.3, "TFLOP/s"), "mfma16": (2500.0, "TFLOP/s"), "alu": (PEAK_ALU_TFLOPS, "TFLOP/s"),
+         "hbm": (8000.0, "GB/s")}
 
 # HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
 # workload (profiles/traffic_apply_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
@@ -64,13 +70,16 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-strides", type=str, default="64,128")
+    ap.add_argument("--cpu-strides", type=str, default="64,32")
+    ap.add_argument("--cpu-validate", type=int, default=0,
+                    help="only time the oracle at this N (Helmholtz sphere, ten points per wavelength): the sampled "
+                         "estimate and the full product")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-instance batched workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
-    ap.add_argument("--serving-matvecs", type=int, default=10,
-                    help="dependent matvecs per session in the serving workload (50 in the full study)")
-    ap.add_argument("--serving-loads", type=str, default="0.8",
-                    help="offered loads as fractions of the one-at-a-time capacity, e.g. 0.5,0.8,0.95")
+    ap.add_argument("--serving-matvecs", type=int, default=50,
+                    help="dependent matvecs per session in the serving workload (50, as in a GMRES solve)")
+    ap.add_argument("--serving-loads", type=str, default="0.8,1.25",
+                    help="offered loads as fractions of the one-at-a-time capacity, e.g. 0.5,0.8,0.95,1.25")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--mixed-study", action="store_true",
                     help="only run the 10M-point sphere + cube study (FP32 and mixed precision at eps 1e-3, 1e-4)")
@@ -84,31 +93,78 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, strides):
-    """The FP64 oracle as it stands, on the host cores: full tree and lists, then the per-box loops of
-    every level (transforms, transfers, near field) on every s-th box for two strides s; the time of the
-    full product is a + b with t(s) = a + b / s fitted through the two samples."""
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, usable
+
+
+def cpu_baseline(w, strides, validate_full=False):
+    """The FP64 oracle as it stands, on the host cores.  It builds the full tree, lists and tables, then runs
+    the product with only the points whose sorted index is a multiple of s in the per-point loops (source and
+    target transforms, near-field targets) for two strides s: every box, table and transfer is kept, so the
+    sample has the full product's parallel structure and its point work shrinks by s at every level.  The full product's time is a + b from
+    t(s) = a + b / s through the two samples, for the wall time on all threads and for the process's CPU time
+    (the core-seconds of the product, the estimate of its time on one core)."""
+    import resource
+    os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")     # idle threads sleep: CPU time counts work only
     import oracle
-    t0 = time.perf_counter()
+
+    def cpu():
+        r = resource.getrusage(resource.RUSAGE_SELF)
+        return r.ru_utime + r.ru_stime
+
+    t0, c0 = time.perf_counter(), cpu()
     p = oracle.Plan(w.X, w.X, w.kernel, w.k, w.eps)
-    t_plan = time.perf_counter() - t0
-    ts = []
+    t_plan, c_plan = time.perf_counter() - t0, cpu() - c0
+    p.apply(w.wu, stride=1024)       # untimed: starts the thread pool and touches the product's memory
+    ts, cs = [], []
     for s in strides:
-        t0 = time.perf_counter()
+        t0, c0 = time.perf_counter(), cpu()
         p.apply(w.wu, stride=s)
         ts.append(time.perf_counter() - t0)
-    (s1, s2), (t1, t2) = strides, ts
-    b = (t1 - t2) / (1.0 / s1 - 1.0 / s2)
-    a = t1 - b / s1
-    if b <= 0:          # degenerate fit: fall back to scaling the larger sample
-        a, b = 0.0, t1 * s1
-    t_full = t_plan + max(a, 0.0) + b
-    return {
+        cs.append(cpu() - c0)
+
+    def fit(y):
+        (s1, s2), (y1, y2) = strides, y
+        b = (y1 - y2) / (1.0 / s1 - 1.0 / s2)
+        a = y1 - b / s1
+        if b <= 0 or a < 0:          # degenerate fit: all of the sample scales
+            a, b = 0.0, y1 * s1
+        return a + b
+
+    t_full = t_plan + fit(ts)
+    c_full = c_plan + fit(cs)
+    model, usable = host_cpu()
+    out = {
         "value": w.n / t_full, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
-        "sample": "FP64 oracle FFM at N=%d: full tree/lists (%.1fs), per-box loops on every %d-th and "
-                  "every %d-th box (%.1fs, %.1fs); full product time a + b from t(s) = a + b/s, est. %.0fs"
-                  % (w.n, t_plan, s1, s2, t1, t2, t_full),
+        "one_core_points_per_s": w.n / c_full, "one_core_s_est": c_full, "all_cores_s_est": t_full,
+        "host_cpu": model, "host_cores_usable": usable,
+        "sample": "FP64 oracle FFM at N=%d (k=%.3f, eps=%g): full tree, lists and tables (%.1f s), then the product "
+                  "with every %d-th and every %d-th point (sorted order) in the per-point loops (%.1f s, %.1f s wall; "
+                  "%.1f, %.1f core-s); full product a + b from t(s) = a + b/s: %.0f s on %d threads, %.0f "
+                  "core-s (one-core estimate)"
+                  % (w.n, w.k, w.eps, t_plan, strides[0], strides[1], ts[0], ts[1], cs[0], cs[1], t_full,
+                     oracle.num_threads(), c_full),
     }
+    if validate_full:
+        t0, c0 = time.perf_counter(), cpu()
+        p.apply(w.wu, stride=1)
+        out["validation_full_s"] = t_plan + time.perf_counter() - t0
+        out["validation_full_core_s"] = c_plan + cpu() - c0
+    return out
 
 
 def dense_rows_device(X, wu, kernel, k, rows, chunk=1 << 15):
@@ -391,12 +447,13 @@ def kernel_totals(launches, steps):
 
 
 def launch_work(name, level, st):
-    """Algorithmic work of one launch of a kernel at a level: (amount, unit kind, definition), or None for
-    kernels without a model here.  mfma / alu amounts are flops (FMA = 2), hbm amounts bytes."""
+    """Algorithmic work of one launch of a kernel at a level: (amount, bound, definition), or None for kernels
+    without a model here.  mfma / alu amounts are flops (FMA = 2), hbm amounts bytes."""
     L, nq = st["order"][level], st["nq"][level]
-    p, nbf, nbt = st["grid_nodes"][level], st["fwd_boxes"][level], st["bwd_boxes"][level]
+    p, w = st["grid_nodes"][level], st["grid_width"][level]
+    nbf, nbt = st["fwd_boxes"][level], st["bwd_boxes"][level]
     if name.startswith("k_grid_phi"):
-        nb = nbt if name == "k_grid_phit" else nbf
+        nb = nbt if name.startswith("k_grid_phit") else nbf
         return (8.0 * nb * (L + 1) * p * p * L, "mfma",
                 "8 flops per (box, ring, node a, node b, azimuth): the four real products of the separable "
                 "plane sums, FP32 MFMA")
@@ -404,50 +461,93 @@ def launch_work(name, level, st):
         nb = nbf if name == "k_grid_z" else nbt
         return (8.0 * nb * ((L + 2) // 2) * p ** 3, "mfma",
                 "8 flops per (box, ring pair, plane, column): the four real products of the z sums, FP32 MFMA")
-    if name.startswith("k_pw_forward_rings") or name.startswith("k_pw_backward_rings"):
-        pts = st["fwd_points"][level] if "forward" in name else st["bwd_points"][level]
-        return (2.0 * SLOTS_PER_DIRECTION[2] * pts * nq, "alu",
-                "non-transcendental VALU issue slots x 2 of the ring-pair form: 10 per (point, 4 directions)")
+    if name.startswith("k_grid_spread"):
+        return (4.0 * w ** 3 * st["fwd_points"][level], "alu",
+                "4 flops per (point, grid node): the node weight times the complex input, VALU")
+    if name.startswith("k_grid_interp"):
+        return (4.0 * w ** 3 * st["bwd_points"][level], "alu",
+                "4 flops per (point, grid node): a real weight times the complex grid value, VALU")
     if name.startswith("k_pw_forward") or name.startswith("k_pw_backward"):
         pts = st["fwd_points"][level] if "forward" in name else st["bwd_points"][level]
-        return (2.0 * SLOTS_PER_DIRECTION[1] * pts * nq, "alu",
-                "non-transcendental VALU issue slots x 2 of the direction-pair form: 7 per (point, 2 directions)")
+        return (FLOPS_PER_TERM * pts * nq, "alu",
+                "15 flops per (point, direction) term of the plane-wave transforms, VALU + transcendental unit")
     if name.startswith("k_near"):
-        return (2.0 * NEAR_SLOTS[name] * st["near_pairs"], "alu",
-                "non-transcendental VALU issue slots x 2 per (target, source) pair of the near field")
+        return (NEAR_FLOPS[name] * st["near_pairs"], "alu",
+                "%d flops per (target, source) pair of the near field, VALU" % NEAR_FLOPS[name])
     if name.startswith("k_pw_transfer"):
         return (8.0 * nq * (nbf + st["nclass"][level] + nbt), "hbm",
                 "unique bytes: u~ of every source box, the class tables D and v~ of every target box, 8 per "
                 "direction each (the far-pair gathers re-read them from the caches)")
+    if name in ("k_lag_mfma", "k_lag_mfma16"):
+        r = L ** 3
+        return ((8.0 if st.get("_helm") else 4.0) * r * r * st["nfar"][level],
+                "mfma16" if name == "k_lag_mfma16" else "mfma",
+                "flops of T u~ per far pair, r = r1^3: 8 r^2 (complex T) or 4 r^2 (real T, complex u~); MFMA")
+    if name in ("k_lag_anterp", "k_lag_interp"):
+        r = L ** 3
+        pts = st["fwd_points"][level] if name == "k_lag_anterp" else st["bwd_points"][level]
+        return (4.0 * r * pts, "alu", "4 flops per (point, Chebyshev node): a real basis value times complex u, VALU")
     return None
 
 
 def roofline(launches, st, steps):
-    """Roofline of the dominant kernel: the kernel symbol with the most time per step among those with a
-    work model; achieved = its algorithmic work over all its launches / their HIP-event time."""
+    """Roofline of the dominant kernel (the kernel symbol with the most time per step among those with a work
+    model; achieved = its algorithmic work over all its launches / their HIP-event time), and the time-weighted
+    fraction of the whole apply, sum over launches of (work / peak of its bound) / the apply's measured time."""
     tot = kernel_totals(launches, steps)
-    for name in tot:
-        work, kind, definition, ms, n = 0.0, None, None, 0.0, 0
-        for step in launches:
-            for r in step:
-                if r["kernel"] != name:
-                    continue
-                m = launch_work(name, r["level"], st)
-                if m is None:
-                    break
-                work += m[0]
-                kind, definition = m[1], m[2]
-                ms += r["ms"]
-                n += 1
-        if kind is None or ms <= 0:
+    per = {}
+    apply_ms = sum(r["ms"] for step in launches for r in step) / steps
+    ideal_ms = 0.0
+    for step in launches:
+        for r in step:
+            m = launch_work(r["kernel"], r["level"], st)
+            e = per.setdefault(r["kernel"], {"ms": 0.0, "work": 0.0, "bound": m[1] if m else None,
+                                             "definition": m[2] if m else None})
+            e["ms"] += r["ms"] / steps
+            if m is None:
+                continue
+            e["work"] += m[0] / steps
+            peak, unit = PEAKS[m[1]]
+            ideal_ms += m[0] / (peak * (1e12 if unit == "TFLOP/s" else 1e9)) * 1e3 / steps
+    per_kernel = {}
+    for name, e in per.items():
+        if e["bound"] is None or e["ms"] <= 0:
+            per_kernel[name] = {"ms": round(e["ms"], 4), "bound": None}
             continue
-        peak, unit = PEAKS[kind]
-        rate = work / (ms * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
-        return name, {"bound": kind, "kernel": name, "achieved": rate, "peak": peak, "unit": unit,
-                      "frac": rate / peak, "launches": n // steps, "avg_launch_ms": ms / n,
-                      "work_per_step": work / steps, "work": definition}
+        peak, unit = PEAKS[e["bound"]]
+        rate = e["work"] / (e["ms"] * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
+        per_kernel[name] = {"ms": round(e["ms"], 4), "bound": e["bound"], "achieved": round(rate, 3),
+                            "unit": unit, "frac": round(rate / peak, 4)}
+    per_kernel = dict(sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms"]))
+    modelled_ms = sum(v["ms"] for v in per_kernel.values() if v["bound"])
+    time_weighted = {"frac": ideal_ms / apply_ms if apply_ms > 0 else 0.0, "apply_ms": apply_ms,
+                     "ideal_ms": ideal_ms, "modelled_time_frac": modelled_ms / apply_ms if apply_ms > 0 else 0.0,
+                     "definition": "sum over the apply's launches of (algorithmic work / peak of the launch's bound) "
+                                   "divided by the apply's measured time (HIP events); launches without a work model "
+                                   "count as zero work", "per_kernel": per_kernel}
+    for name in tot:
+        e = per.get(name)
+        if not e or e["bound"] is None or e["ms"] <= 0:
+            continue
+        peak, unit = PEAKS[e["bound"]]
+        rate = e["work"] / (e["ms"] * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
+        n = sum(1 for step in launches for r in step if r["kernel"] == name)
+        out = {"bound": "alu" if e["bound"] == "alu" else ("hbm" if e["bound"] == "hbm" else "mfma"),
+               "kernel": name, "achieved": rate, "peak": peak, "unit": unit, "frac": rate / peak,
+               "launches": n // steps, "avg_launch_ms": e["ms"] / max(1, n // steps),
+               "work_per_step": e["work"], "work": e["definition"], "time_weighted": time_weighted}
+        if e["bound"] == "alu":
+            out["peak_packed_fp32"] = PEAK_ALU_PACKED_TFLOPS
+            out["frac_of_packed_peak"] = rate / PEAK_ALU_PACKED_TFLOPS
+        if name in NEAR_SLOTS:
+            slots = NEAR_SLOTS[name] * st["near_pairs"]
+            out["issue_slot_utilisation"] = slots / (e["ms"] * 1e-3) / VALU_SLOTS_PER_S
+            out["issue_slot_definition"] = ("%d non-transcendental VALU issue slots per pair (the fewest the "
+                                            "implemented loop needs) over the 39.3e12 lane-slots/s of the chip"
+                                            % NEAR_SLOTS[name])
+        return name, out
     return "none", {"bound": "alu", "kernel": "none", "achieved": 0.0, "peak": PEAK_ALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": 0.0}
+                     "unit": "TFLOP/s", "frac": 0.0, "time_weighted": time_weighted}
 
 
 def main():
@@ -465,6 +565,14 @@ def main():
     if args.mixed_study:
         res = {"metric": "10M sphere + cube Helmholtz: points/s and error per precision mode",
                "mixed_study": mixed_study(args.mixed_n, args.mixed_rows)}
+        print(json.dumps(res), flush=True)
+        return
+
+    if args.cpu_validate:
+        wv = W.helmholtz_sphere(args.cpu_validate, seed=2, eps=args.eps)
+        strides = tuple(int(x) for x in args.cpu_strides.split(","))
+        res = {"metric": "oracle CPU time: sampled estimate against the full product",
+               "cpu_validate": cpu_baseline(wv, strides, validate_full=True)}
         print(json.dumps(res), flush=True)
         return
 
@@ -543,6 +651,7 @@ def main():
     step_ms = rec["latency_ms"]
 
     st = rec["stats"]
+    st["_helm"] = True          # the Helmholtz kernel: complex transfer tables at Lagrange levels
     ph = np.array(rec["phases"])          # [steps][64]
     leaf = st["leaf"]
     dom, roof = roofline(rec["launches"], st, args.steps)
@@ -587,6 +696,11 @@ def main():
                          traffic_unit="bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a "
                                       "1 GiB copy)"),
         "kernels_ms_per_step": {k: round(v, 4) for k, v in kernel_totals(rec["launches"], args.steps).items()},
+        "memory": {"plan_bytes": st["plan_bytes"], "workspace_bytes": st["workspace_bytes"],
+                   "plan_bytes_per_point": st["plan_bytes"] / w.n,
+                   "workspace_bytes_per_point": st["workspace_bytes"] / w.n,
+                   "paper": "O(N) storage (Sec. 3, Prop. 1); the paper's Table 1 lists about 100 bytes per point "
+                            "(Laplace, its own implementation, which keeps nothing between products)"},
         "levels": {"leaf": leaf, "nq": [int(x) for x in st["nq"][:leaf + 1]],
                    "transform_form": [int(x) for x in st["tform"][:leaf + 1]],
                    "grid_nodes": [int(x) for x in st["grid_nodes"][:leaf + 1]],

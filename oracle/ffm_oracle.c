@@ -67,6 +67,10 @@ static double complex green(int kernel, double k, double r)
     return cexp(I * (k * r)) / (4.0 * ORC_PI * r);
 }
 
+/* Timing samples (orc_apply with stride > 1) keep the points whose sorted index is a multiple of the stride:
+ * the first such index at or after i. */
+static int64_t first_sample(int64_t i, int64_t stride) { return (i + stride - 1) / stride * stride; }
+
 static double complex cload(const double *a, int64_t i) { return a[2 * i] + I * a[2 * i + 1]; }
 
 /* The plain definition (Sec. 1, eq. convolution_discrete) on sampled rows. */
@@ -858,18 +862,17 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
     orc_cheb_nodes(r1, nodes);
     int64_t nbx = TX->nbox[l], nby = TY->nbox[l];
 
-    /* sources that take part in a far pair (every stride-th of them when timing a sample) */
+    /* sources that take part in a far pair */
     char *need = calloc((size_t)nby, 1);
-    for (int64_t i = 0; i < F->n; ++i)
-        if ((F->s[i] % stride) == 0) need[F->s[i]] = 1;
+    for (int64_t i = 0; i < F->n; ++i) need[F->s[i]] = 1;
 
-    /* interpolated source vectors u~_s = L_Y u_s */
+    /* interpolated source vectors u~_s = L_Y u_s (every stride-th point of a box when timing a sample) */
     double complex *ut = calloc((size_t)nby * r, sizeof(double complex));
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < nby; ++s) {
         if (!need[s]) continue;
         double ex[64], ey[64], ez[64];
-        for (int64_t j = TY->start[l][s]; j < TY->start[l][s + 1]; ++j) {
+        for (int64_t j = first_sample(TY->start[l][s], stride); j < TY->start[l][s + 1]; j += stride) {
             orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j] - TY->ctr[l][3 * s]) / dl, ex);
             orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j + 1] - TY->ctr[l][3 * s + 1]) / dl, ey);
             orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j + 2] - TY->ctr[l][3 * s + 2]) / dl, ez);
@@ -899,7 +902,7 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
     int64_t *ptr = pairs_by_target(F, nbx);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nbx; ++t) {
-        if (ptr[t] == ptr[t + 1] || (t % stride) != 0) continue;
+        if (ptr[t] == ptr[t + 1]) continue;
         double complex *vt = calloc((size_t)r, sizeof(double complex));
         for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
             const double complex *Tc = Tm + (size_t)class_of(&C, F->off + 3 * e) * r * r;
@@ -911,7 +914,7 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
             }
         }
         double ex[64], ey[64], ez[64];
-        for (int64_t i = TX->start[l][t]; i < TX->start[l][t + 1]; ++i) {
+        for (int64_t i = first_sample(TX->start[l][t], stride); i < TX->start[l][t + 1]; i += stride) {
             orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i] - TX->ctr[l][3 * t]) / dl, ex);
             orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i + 1] - TX->ctr[l][3 * t + 1]) / dl, ey);
             orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i + 2] - TX->ctr[l][3 * t + 2]) / dl, ez);
@@ -943,11 +946,10 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     orc_sphere_quadrature(L, s, w);
     int64_t nbx = TX->nbox[l], nby = TY->nbox[l];
 
-    /* sources that take part in a far pair (every stride-th of them when timing a sample) */
+    /* sources that take part in a far pair */
     char *need = calloc((size_t)nby, 1);
     int64_t *ptr = pairs_by_target(F, nbx);
-    for (int64_t i = 0; i < F->n; ++i)
-        if ((F->s[i] % stride) == 0) need[F->s[i]] = 1;
+    for (int64_t i = 0; i < F->n; ++i) need[F->s[i]] = 1;
 
     /* grid form of the transforms at this level (R16-R18), else the direct sums */
     const int grid = p->opt.grid_p[l] > 0;
@@ -957,22 +959,28 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
         gridlev_init(&gl, gp, gw, p->opt.grid_beta[l], ldexp(p->d0, -l) / (double)(gp - 1 - gw), k, L);
     }
 
-    /* forward transform u~_s(q) = sum_j e^{-ik s_q.(y_j - c_s)} u_j */
+    /* forward transform u~_s(q) = sum_j e^{-ik s_q.(y_j - c_s)} u_j (every stride-th point of a box when timing
+     * a sample) */
     double complex *ut = calloc((size_t)nby * nq, sizeof(double complex));
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t b = 0; b < nby; ++b) {
         if (!need[b]) continue;
         const double *c = TY->ctr[l] + 3 * b;
         if (grid) {
-            int64_t j0 = TY->start[l][b], nb = TY->start[l][b + 1] - j0;
+            int64_t j0 = first_sample(TY->start[l][b], stride);
+            int64_t nb = TY->start[l][b + 1] > j0 ? (TY->start[l][b + 1] - j0 + stride - 1) / stride : 0;
             double *yr = malloc(sizeof(double) * 3 * (size_t)(nb + 1));
-            for (int64_t j = 0; j < nb; ++j)
-                for (int d = 0; d < 3; ++d) yr[3 * j + d] = TY->P[3 * (j0 + j) + d] - c[d];
-            grid_fwd(&gl, yr, u + j0, nb, ut + b * nq);
+            double complex *ub = malloc(sizeof(double complex) * (size_t)(nb + 1));
+            for (int64_t j = 0; j < nb; ++j) {
+                for (int d = 0; d < 3; ++d) yr[3 * j + d] = TY->P[3 * (j0 + j * stride) + d] - c[d];
+                ub[j] = u[j0 + j * stride];
+            }
+            grid_fwd(&gl, yr, ub, nb, ut + b * nq);
             free(yr);
+            free(ub);
             continue;
         }
-        for (int64_t j = TY->start[l][b]; j < TY->start[l][b + 1]; ++j) {
+        for (int64_t j = first_sample(TY->start[l][b], stride); j < TY->start[l][b + 1]; j += stride) {
             double y0 = TY->P[3 * j] - c[0], y1 = TY->P[3 * j + 1] - c[1], y2 = TY->P[3 * j + 2] - c[2];
             for (int64_t q = 0; q < nq; ++q)
                 ut[b * nq + q] += cexp(-I * k * (s[3 * q] * y0 + s[3 * q + 1] * y1 + s[3 * q + 2] * y2)) * u[j];
@@ -989,7 +997,7 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     /* v~_t(q) = sum_s D_ts(q) u~_s(q);  v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q) */
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nbx; ++t) {
-        if (ptr[t] == ptr[t + 1] || (t % stride) != 0) continue;
+        if (ptr[t] == ptr[t + 1]) continue;
         double complex *vt = calloc((size_t)nq, sizeof(double complex));
         for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
             const double complex *Dc = D + (size_t)class_of(&C, F->off + 3 * e) * nq;
@@ -998,16 +1006,20 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
         }
         const double *c = TX->ctr[l] + 3 * t;
         if (grid) {
-            int64_t i0 = TX->start[l][t], nt = TX->start[l][t + 1] - i0;
+            int64_t i0 = first_sample(TX->start[l][t], stride);
+            int64_t nt = TX->start[l][t + 1] > i0 ? (TX->start[l][t + 1] - i0 + stride - 1) / stride : 0;
             double *xr = malloc(sizeof(double) * 3 * (size_t)(nt + 1));
+            double complex *vb = calloc((size_t)(nt + 1), sizeof(double complex));
             for (int64_t i = 0; i < nt; ++i)
-                for (int d = 0; d < 3; ++d) xr[3 * i + d] = TX->P[3 * (i0 + i) + d] - c[d];
-            grid_bwd(&gl, vt, xr, nt, v + i0);
+                for (int d = 0; d < 3; ++d) xr[3 * i + d] = TX->P[3 * (i0 + i * stride) + d] - c[d];
+            grid_bwd(&gl, vt, xr, nt, vb);
+            for (int64_t i = 0; i < nt; ++i) v[i0 + i * stride] += vb[i];
             free(xr);
+            free(vb);
             free(vt);
             continue;
         }
-        for (int64_t i = TX->start[l][t]; i < TX->start[l][t + 1]; ++i) {
+        for (int64_t i = first_sample(TX->start[l][t], stride); i < TX->start[l][t + 1]; i += stride) {
             double x0 = TX->P[3 * i] - c[0], x1 = TX->P[3 * i + 1] - c[1], x2 = TX->P[3 * i + 2] - c[2];
             double complex acc = 0.0;
             for (int64_t q = 0; q < nq; ++q)
@@ -1036,10 +1048,9 @@ static void near_field(const orc_plan *p, const double complex *u, double comple
     int64_t *ptr = pairs_by_target(N, nbx);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nbx; ++t) {
-        if ((t % stride) != 0) continue;
         for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
             int64_t sb = N->s[e];
-            for (int64_t i = TX->start[l][t]; i < TX->start[l][t + 1]; ++i) {
+            for (int64_t i = first_sample(TX->start[l][t], stride); i < TX->start[l][t + 1]; i += stride) {
                 double complex acc = 0.0;
                 for (int64_t j = TY->start[l][sb]; j < TY->start[l][sb + 1]; ++j) {
                     double dx = TX->P[3 * i] - TY->P[3 * j], dy = TX->P[3 * i + 1] - TY->P[3 * j + 1],

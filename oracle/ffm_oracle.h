@@ -85,8 +85,9 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
 void orc_plan_free(orc_plan *p);
 
 /* apply: v (complex, user target order) = FFM(wu (complex, user source order)).
- * stride > 1 evaluates only every stride-th box in every per-box loop: a bounded
- * timing sample whose result is not the product. */
+ * stride > 1 evaluates, in every per-point loop (transforms, near-field targets),
+ * only the points whose sorted index is a multiple of stride, keeping every box,
+ * table and transfer: a bounded timing sample whose result is not the product. */
 void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride);
 
 /* ---- queries for bit-exact comparison ------------------------------------- */
