@@ -273,6 +273,24 @@ int32_t ffm_kernel_name(int32_t kernel, int32_t variant_a, int32_t variant_b, ch
 size_t ffm_plan_bytes(ffm_plan_t plan);
 size_t ffm_workspace_bytes(ffm_plan_t plan);
 
+/*
+ * ffm_apply_static -- ffm_apply over a workspace the library holds in static
+ * device memory instead of the plan's own: for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It calls no allocating routine; it copies its I/O entry and
+ * launches the plan's kernels, computing bitwise what ffm_apply computes.
+ * The workspace is FFM_STATIC_WORKSPACE_BYTES on every device the library
+ * runs on, held until the process ends; a plan whose apply workspace
+ * (ffm_workspace_bytes) is larger is rejected with FFM_EINVAL and a message
+ * naming both sizes.  Every call on a device shares that device's workspace,
+ * which keeps the last call's contents (the kernels clear what must start at
+ * zero): calls that overlap on one device, for the same plan or different
+ * plans, race; calls on one stream are ordered.  Arguments, layouts and
+ * stream semantics as ffm_apply.
+ */
+#define FFM_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
+ffm_status_t ffm_apply_static(ffm_plan_t plan, const void *wu, ffm_dtype_t in_dtype, void *v, void *hip_stream);
+
 /* ------------------------------------------------------------------ tiles and batches
  * Not in the paper: the paper evaluates one product at a time.  These entry
  * points apply many independent plans together (one launch per step kind for

@@ -29,7 +29,8 @@ EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_versi
             "ffm_plan_set_tiles", "ffm_plan_get_tiles", "ffm_batch_create", "ffm_batch_apply", "ffm_batch_info",
             "ffm_batch_destroy", "ffm_server_create", "ffm_server_submit", "ffm_server_wait", "ffm_server_poll",
             "ffm_server_stats", "ffm_server_destroy", "ffm_plan_launch_timing", "ffm_kernel_name",
-            "ffm_apply_batched"]
+            "ffm_apply_batched", "ffm_apply_static"]
+STATIC_WORKSPACE_BYTES = 128 << 20
 FFM_FLAG_TIMING = 1
 FFM_FLAG_DIRECT_TRANSFORMS = 2
 FFM_FLAG_GRID_TRANSFORMS = 4
@@ -130,6 +131,7 @@ def lib():
             "ffm_server_create": (C.c_int, [P, P]),
             "ffm_server_submit": (C.c_int, [P, P, P, C.c_int, P, P, P]),
             "ffm_apply_batched": (C.c_int, [P, P, P, i32, P]),
+            "ffm_apply_static": (C.c_int, [P, P, C.c_int, P, P]),
             "ffm_server_wait": (C.c_int, [P, i64, P]),
             "ffm_server_poll": (C.c_int, [P, i64, P]),
             "ffm_server_stats": (C.c_int, [P, P]),
@@ -268,6 +270,20 @@ class Plan:
         elif out.dtype != torch.complex64 or out.shape[0] != self.n_x or not out.is_contiguous():
             raise ValueError("out must be a contiguous complex64 tensor of length n_x")
         ffm_apply(self._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(), _stream(stream))
+        return out
+
+    def apply_static(self, wu, out=None, stream=None):
+        """apply() over the library's static device workspace (ffm_apply_static): no allocation inside the call
+        (pass ``out`` to keep the Python side allocation-free too).  Plans whose workspace exceeds
+        STATIC_WORKSPACE_BYTES are rejected; calls that overlap on one device race."""
+        import torch
+        if wu.shape[0] != self.n_y or not wu.is_cuda or not wu.is_contiguous():
+            raise ValueError("wu must be a contiguous CUDA tensor of length n_y")
+        if out is None:
+            out = torch.empty(self.n_x, dtype=torch.complex64, device=self.device)
+        elif out.dtype != torch.complex64 or out.shape[0] != self.n_x or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 tensor of length n_x")
+        _check(lib().ffm_apply_static(self._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(), _stream(stream)))
         return out
 
     def stats(self) -> dict:

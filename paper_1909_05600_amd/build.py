@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libffm.so")
 PEAKS = os.path.join(HERE, "ffm_peaks")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["scan_sort.hip", "plan.hip", "apply.hip", "batch.hip", "server.hip", "api.hip"]
+SOURCES = ["scan_sort.hip", "plan.hip", "apply.hip", "batch.hip", "server.hip", "static_apply.hip", "api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

@@ -229,11 +229,15 @@ ffm_status_t ffm_destroy(ffm_plan_t plan) {
         hipError_t q = hipEventQuery(plan->P.done);
         if (q == hipErrorNotReady) return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: an apply is still in flight");
     }
+    if (plan->P.sdone && plan->P.sapplied && hipEventQuery(plan->P.sdone) == hipErrorNotReady)
+        return (ffm_status_t)set_err(FFM_EBUSY, "ffm_destroy: a static-workspace apply is still in flight");
     return (ffm_status_t)Guard::run([&] {
         plan_sync_ready(plan->P);
         if (plan->P.ready) (void)hipEventDestroy(plan->P.ready);
         if (plan->P.done) (void)hipEventDestroy(plan->P.done);
+        if (plan->P.sdone) (void)hipEventDestroy(plan->P.sdone);
         if (plan->P.hio) pinned_free(plan->P.hio);
+        if (plan->P.spin) pinned_free(plan->P.spin);
         for (auto e : plan->P.tev)
             if (e) (void)hipEventDestroy(e);
         delete plan;

@@ -379,6 +379,14 @@ struct Plan {
     DevBuf<IoEntry> dio;
     IoEntry *hio = nullptr;              // pinned host copy of the I/O entry
     std::vector<Stage> pre, post;
+    // applies over the library's static workspace (ffm_apply_static): descriptors pointing into it, built with
+    // the plan when its workspace fits, the I/O entry, their pinned host block and the last such apply's event
+    DevBuf<LDesc> sdesc;
+    DevBuf<IoEntry> sdio;
+    void *spin = nullptr;
+    IoEntry *shio = nullptr;
+    hipEvent_t sdone = nullptr;
+    bool sapplied = false;
     Tune tune;
     // optional phase timing (FFM_FLAG_TIMING): events recorded at phase ends
     std::vector<hipEvent_t> tev;
@@ -410,6 +418,10 @@ struct WorkPtrs {
 };
 size_t apply_work_bytes(const Plan &P);
 WorkPtrs carve_work(const Plan &P, char *base);
+// The static workspace of ffm_apply_static: the device address of this device's copy (taken once per device),
+// and the plan's descriptors over it (nothing if the plan's workspace does not fit).
+char *static_work_base();
+void plan_static_setup(Plan &P, hipStream_t st);
 // Release the batch kept by ffm_apply_batched if it holds plan P; a status code.  With wait, its last apply is
 // waited for; without, an apply still in flight gives FFM_EBUSY and nothing is released.
 int implicit_batch_drop(const Plan *P, bool wait);

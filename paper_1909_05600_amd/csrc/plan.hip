@@ -1977,6 +1977,8 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     Scratch SC(st);
     upload(P.ddesc, P.hdesc, st, SC);
     if (keep) keep->adopt(SC);
+    P.stats.workspace_bytes = (double)apply_work_bytes(P);
+    plan_static_setup(P, st);
 }
 
 size_t plan_device_bytes(const Plan &P) {
