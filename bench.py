@@ -30,12 +30,16 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 PEAK_ALU_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12          # 78.6
 PEAK_ALU_PACKED_TFLOPS = 157.3
 # Algorithmic flops (an FMA = 2, a sine, cosine or reciprocal square root = 1):
-#   plane-wave transforms, per (point, direction) term: 3 FMA of phase (6) + sin + cos (2) + a complex
-#     multiply-add (4 FMA = 7 flops after the shared phase): 15
+#   plane-wave transforms in the forms implemented, which share phases between directions by the quadrature's
+#   symmetries: the direction-pair form, per (point, antipodal pair): 3 FMA of phase (6) + sin + cos (2) + the
+#   two directions' complex multiply-adds from one cos/sin pair (4 FMA, 8): 16 per 2 directions; the ring-pair
+#   form, per (point, 4 directions of two mirror rings and two opposite azimuths): 2 FMA of phase (4) + sin +
+#   cos (2) + 8 FMA (16): 22 per 4 directions.  (The plain per-term count, 3 FMA of phase + sin + cos + a
+#   complex multiply-add = 15 per direction, is what a form without the symmetries needs.)
 #   near field, per (target, source) pair: Laplace 14 (3 differences, |d|^2 in 3 FMA, rsqrt, 1/(4 pi) scale, a
 #     complex multiply-add), Helmholtz 24 (the same, k r, sin, cos, two products e^{ikr}/r and a complex
 #     multiply-add)
-FLOPS_PER_TERM = 15.0
+FLOPS_PER_DIRECTION = {"pair": 16.0 / 2, "ring": 22.0 / 4}
 NEAR_FLOPS = {"k_near<false>": 14.0, "k_near<true>": 24.0}
 # VALU issue slots the implemented near-field loop needs per pair at least (transcendentals co-issue): the slot
 # utilisation is reported separately from the flop fraction
@@ -469,8 +473,11 @@ def launch_work(name, level, st):
                 "4 flops per (point, grid node): a real weight times the complex grid value, VALU")
     if name.startswith("k_pw_forward") or name.startswith("k_pw_backward"):
         pts = st["fwd_points"][level] if "forward" in name else st["bwd_points"][level]
-        return (FLOPS_PER_TERM * pts * nq, "alu",
-                "15 flops per (point, direction) term of the plane-wave transforms, VALU + transcendental unit")
+        form = "ring" if "_rings" in name else "pair"
+        return (FLOPS_PER_DIRECTION[form] * pts * nq, "alu",
+                "flops per (point, direction) of the %s form: %s, VALU + transcendental unit"
+                % ("ring-pair" if form == "ring" else "direction-pair",
+                   "22 per 4 directions" if form == "ring" else "16 per 2 directions"))
     if name.startswith("k_near"):
         return (NEAR_FLOPS[name] * st["near_pairs"], "alu",
                 "%d flops per (target, source) pair of the near field, VALU" % NEAR_FLOPS[name])

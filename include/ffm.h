@@ -82,6 +82,12 @@ typedef struct {
  * fast evaluation the remark closing Sec. 2.2.3 calls for).  These bits force one form. */
 #define FFM_FLAG_DIRECT_TRANSFORMS 2u
 #define FFM_FLAG_GRID_TRANSFORMS   4u
+/* options.flags: adaptive cross approximation of the Lagrange transfer matrices (Sec. 2.2.2, eq.
+ * ffmACAmatvec: T ~ A B^T, applied as A (B^T u~)), at relative tolerance eps / 4.  By default the planner
+ * uses it at FP32 Lagrange levels with at least 5 Chebyshev nodes per axis where the ranks save a quarter of
+ * the transfer work; FFM_FLAG_NO_ACA never uses it, FFM_FLAG_ACA uses it at every FP32 Lagrange level. */
+#define FFM_FLAG_NO_ACA 8u
+#define FFM_FLAG_ACA    16u
 
 /*
  * ffm_plan -- build the two octrees, the descent lists and the transfer
@@ -200,6 +206,8 @@ typedef struct {
                                               h = d_l / (grid_nodes - 1 - grid_width))               */
     double  grid_alias[FFM_MAX_LEVELS];    /* grid form: bound on the aliasing error of spreading one plane
                                               wave along one axis, relative, for every direction, else 0 */
+    int32_t aca[FFM_MAX_LEVELS];           /* 1 if the level's transfers use the ACA factors                 */
+    double  aca_rank[FFM_MAX_LEVELS];      /* mean ACA rank over the level's classes where it was evaluated  */
 } ffm_stats_t;
 
 /* ffm_plan_stats -- copy the plan's sizes and work counters to host memory.
@@ -221,10 +229,11 @@ ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out);
  *   FFM_EXPORT_BOX_CTR   double  [nbox][3] box centres (set, l)
  *   FFM_EXPORT_FAR       int64   [nfar][5] (t, s, ox, oy, oz) sorted by (t, s) (l)
  *   FFM_EXPORT_NEAR      int64   [nnear][2] (t, s) sorted by (t, s) (l)
+ *   FFM_EXPORT_ACA_RANK  int64   [ncls][4] (ox, oy, oz, rank) of an ACA level l (count 0 elsewhere)
  */
 typedef enum {
     FFM_EXPORT_KEYS = 0, FFM_EXPORT_PERM = 1, FFM_EXPORT_BOX_START = 2, FFM_EXPORT_BOX_IJK = 3,
-    FFM_EXPORT_BOX_CTR = 4, FFM_EXPORT_FAR = 5, FFM_EXPORT_NEAR = 6
+    FFM_EXPORT_BOX_CTR = 4, FFM_EXPORT_FAR = 5, FFM_EXPORT_NEAR = 6, FFM_EXPORT_ACA_RANK = 7
 } ffm_export_t;
 
 ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t level,

@@ -75,6 +75,8 @@ def lib():
             "orc_grid_forward": (None, [C.c_int, C.c_int, dbl, dbl, dbl, C.c_int, P, P, i64, P]),
             "orc_grid_backward": (None, [C.c_int, C.c_int, dbl, dbl, dbl, C.c_int, P, P, i64, P]),
             "orc_es_hat": (dbl, [C.c_int, dbl, dbl]),
+            "orc_aca": (C.c_int, [C.c_int, P, dbl, P, P]),
+            "orc_aca_ranks": (C.c_int, [P, C.c_int, dbl, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -94,7 +96,7 @@ MAX_LEVELS = 21
 class _Options(C.Structure):
     _fields_ = [("n_leaf", C.c_int32), ("kappa", C.c_double), ("r1_override", C.c_int32),
                 ("max_level", C.c_int32), ("grid_p", C.c_int32 * MAX_LEVELS), ("grid_w", C.c_int32 * MAX_LEVELS),
-                ("grid_beta", C.c_double * MAX_LEVELS)]
+                ("grid_beta", C.c_double * MAX_LEVELS), ("aca_tol", C.c_double), ("aca", C.c_int32 * MAX_LEVELS)]
 
 
 def _ptr(a: np.ndarray):
@@ -196,14 +198,28 @@ def grid_backward(p: int, w: int, beta: float, h: float, k: float, L: int, vt, x
     return out
 
 
+def aca(T, tol: float):
+    """Adaptive cross approximation with complete pivoting of a square complex matrix: (A, B) with T ~ A B^T and
+    |T - A B^T|_F <= tol |T|_F."""
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.complex128))
+    r = T.shape[0]
+    A = np.zeros((r, r), dtype=np.complex128)
+    B = np.zeros((r, r), dtype=np.complex128)
+    k = lib().orc_aca(r, _ptr(T), float(tol), _ptr(A), _ptr(B))
+    # the C side stores column l contiguously: A[l][i] in this buffer is column l of A
+    return A[:k].T.copy(), B[:k].T.copy()
+
+
 class Plan:
     """The oracle's FFM plan: root cubes, two Morton-sorted octrees, descent lists, leaf.
 
     ``grid`` maps a Gegenbauer level to the (p, w, beta) of its grid-form transforms; other levels use the
-    direct sums."""
+    direct sums.  ``aca`` lists the Lagrange levels whose transfer matrices are compressed by ACA at relative
+    tolerance ``aca_tol``."""
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 64,
-                 kappa: float = 0.0, r1: int = 0, max_level: int = 20, grid: dict | None = None):
+                 kappa: float = 0.0, r1: int = 0, max_level: int = 20, grid: dict | None = None,
+                 aca=(), aca_tol: float = 0.0):
         self.X = _coords(X)
         self.Y = self.X if Y is X else _coords(Y)
         self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
@@ -212,6 +228,9 @@ class Plan:
             opt.grid_p[int(l)] = int(gp)
             opt.grid_w[int(l)] = int(gw)
             opt.grid_beta[int(l)] = float(gb)
+        opt.aca_tol = float(aca_tol)
+        for l in aca:
+            opt.aca[int(l)] = 1
         self._h = lib().orc_plan_create(_ptr(self.X), self.X.shape[0], _ptr(self.Y), self.Y.shape[0],
                                         self.kernel, self.k, self.eps, C.byref(opt))
         if not self._h:
@@ -294,3 +313,10 @@ class Plan:
 
     def order(self, l: int) -> int:
         return int(lib().orc_level_order(self._h, l))
+
+    def aca_ranks(self, l: int, tol: float) -> dict:
+        """ACA rank of every translation class of Lagrange level l: {(ox, oy, oz): rank}."""
+        off = np.zeros((400, 3), dtype=np.int32)
+        ranks = np.zeros(400, dtype=np.int32)
+        n = lib().orc_aca_ranks(self._h, l, float(tol), _ptr(off), _ptr(ranks))
+        return {tuple(int(x) for x in off[c]): int(ranks[c]) for c in range(n)}

@@ -448,6 +448,70 @@ void orc_grid_backward(int p, int w, double beta, double h, double k, int L, con
 }
 
 /* =========================================================================
+ * Adaptive cross approximation of a transfer matrix (Sec. 2.2.2, eq. ffmACAmatvec):
+ * T ~ A B^T with A, B of r_T columns, by Bebendorf's cross approximation with
+ * complete pivoting (reading R21).  Step k takes the largest entry (i_k, j_k) of the
+ * residual R_k = T - sum_{l<k} a_l b_l^T and sets a_k = R_k(:, j_k),
+ * b_k = R_k(i_k, :) / R_k(i_k, j_k); it stops as soon as |R_k|_F <= tol |T|_F, so the
+ * factors meet the tolerance exactly.  The pivot is the first entry in row-major
+ * order whose squared modulus is within a relative 2e-9 of the largest, so that
+ * entries equal up to rounding (the tensor grid is symmetric) pick the same pivot.
+ * ========================================================================= */
+typedef double complex (*entry_fn)(const void *ctx, int i, int j);
+
+/* A, B: r x r column-major (column l at A + l r); returns the rank. */
+static int aca_factor(int r, entry_fn entry, const void *ctx, double tol, double complex *A, double complex *B)
+{
+    double complex *R = malloc(sizeof(double complex) * (size_t)r * r);
+    double T2 = 0.0;
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+            R[(size_t)i * r + j] = entry(ctx, i, j);
+            T2 += creal(R[(size_t)i * r + j] * conj(R[(size_t)i * r + j]));
+        }
+    int k = 0;
+    while (k < r) {
+        double R2 = 0.0, m = 0.0;
+        for (size_t e = 0; e < (size_t)r * r; ++e) {
+            const double q = creal(R[e] * conj(R[e]));
+            R2 += q;
+            if (q > m) m = q;
+        }
+        if (R2 <= tol * tol * T2 || m == 0.0) break;
+        size_t piv = 0;
+        for (size_t e = 0; e < (size_t)r * r; ++e)
+            if (creal(R[e] * conj(R[e])) >= (1.0 - 2e-9) * m) {
+                piv = e;
+                break;
+            }
+        const int pi = (int)(piv / r), pj = (int)(piv % r);
+        const double complex pv = R[piv];
+        for (int q = 0; q < r; ++q) {
+            A[(size_t)k * r + q] = R[(size_t)q * r + pj];
+            B[(size_t)k * r + q] = R[(size_t)pi * r + q] / pv;
+        }
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) R[(size_t)i * r + j] -= A[(size_t)k * r + i] * B[(size_t)k * r + j];
+        ++k;
+    }
+    free(R);
+    return k;
+}
+
+static double complex dense_entry(const void *ctx, int i, int j)
+{
+    const double *T = ((const double *const *)ctx)[0];
+    const int r = (int)(intptr_t)((const void *const *)ctx)[1];
+    return T[2 * ((size_t)i * r + j)] + I * T[2 * ((size_t)i * r + j) + 1];
+}
+
+int orc_aca(int r, const double *T, double tol, double *A, double *B)
+{
+    const void *ctx[2] = {T, (const void *)(intptr_t)r};
+    return aca_factor(r, dense_entry, ctx, tol, (double complex *)A, (double complex *)B);
+}
+
+/* =========================================================================
  * Trees (Sec. 2.1, 2.2.1, 3.1)
  * ========================================================================= */
 typedef struct {
@@ -661,8 +725,10 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
     p->opt.kappa = (opt && opt->kappa > 0) ? opt->kappa : ORC_PI;
     p->opt.r1_override = opt ? opt->r1_override : 0;
     p->opt.max_level = (opt && opt->max_level > 0 && opt->max_level <= 20) ? opt->max_level : 20;
+    p->opt.aca_tol = opt ? opt->aca_tol : 0.0;
     if (opt)
         for (int l = 0; l < ORC_MAX_LEVELS; ++l) {
+            p->opt.aca[l] = opt->aca[l];
             p->opt.grid_p[l] = opt->grid_p[l];
             p->opt.grid_w[l] = opt->grid_w[l];
             p->opt.grid_beta[l] = opt->grid_beta[l];
@@ -851,6 +917,24 @@ static int class_of(const classes_t *C, const int32_t *o)
     return C->id[idx];
 }
 
+/* Transfer-matrix entry of a translation class: T[(abc), (a'b'c')] = G(xi_t - xi_s), xi = c + (d_l/2)(t_a, t_b, t_c). */
+typedef struct {
+    const double *r0, *nodes;
+    double dl, k;
+    int r1, kernel;
+} tentry_t;
+
+static double complex class_entry(const void *ctx, int i, int j)
+{
+    const tentry_t *e = (const tentry_t *)ctx;
+    const int r1 = e->r1;
+    int ia[3] = {i / (r1 * r1), (i / r1) % r1, i % r1};
+    int ja[3] = {j / (r1 * r1), (j / r1) % r1, j % r1};
+    double dd[3];
+    for (int d = 0; d < 3; ++d) dd[d] = e->r0[d] + 0.5 * e->dl * (e->nodes[ia[d]] - e->nodes[ja[d]]);
+    return green(e->kernel, e->k, sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
+}
+
 /* Lagrange level (Sec. 2.2.2): v_t += L_X^T (sum_s T_{ts} (L_Y u_s)). */
 static void level_lagrange(const orc_plan *p, int l, const double complex *u, double complex *v,
                            int64_t stride)
@@ -882,21 +966,35 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
         }
     }
 
-    /* transfer matrices T[(abc),(a'b'c')] = G(xi_t - xi_s), one per translation */
+    /* transfer matrices T[(abc),(a'b'c')] = G(xi_t - xi_s), one per translation; with ACA (eq. ffmACAmatvec)
+     * each is kept as its factors A (r x k_c), B (r x k_c) instead */
     classes_t C;
     classes_build(&C, p, l);
-    double complex *Tm = malloc(sizeof(double complex) * (size_t)C.n * r * r);
+    const int use_aca = p->opt.aca_tol > 0.0 && p->opt.aca[l];
+    double complex *Tm = NULL, **Af = NULL, **Bf = NULL;
+    int *kc = NULL;
+    if (!use_aca) {
+        Tm = malloc(sizeof(double complex) * (size_t)C.n * r * r);
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int c = 0; c < C.n; ++c)
-        for (int i = 0; i < r; ++i)
-            for (int j = 0; j < r; ++j) {
-                int ia[3] = {i / (r1 * r1), (i / r1) % r1, i % r1};
-                int ja[3] = {j / (r1 * r1), (j / r1) % r1, j % r1};
-                double dd[3];
-                for (int d = 0; d < 3; ++d) dd[d] = C.r0[c][d] + 0.5 * dl * (nodes[ia[d]] - nodes[ja[d]]);
-                Tm[((size_t)c * r + i) * r + j] =
-                    green(p->kernel, p->k, sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
-            }
+        for (int c = 0; c < C.n; ++c) {
+            tentry_t te = {C.r0[c], nodes, dl, p->k, r1, p->kernel};
+            for (int i = 0; i < r; ++i)
+                for (int j = 0; j < r; ++j) Tm[((size_t)c * r + i) * r + j] = class_entry(&te, i, j);
+        }
+    } else {
+        Af = calloc((size_t)C.n, sizeof(double complex *));
+        Bf = calloc((size_t)C.n, sizeof(double complex *));
+        kc = calloc((size_t)C.n, sizeof(int));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int c = 0; c < C.n; ++c) {
+            tentry_t te = {C.r0[c], nodes, dl, p->k, r1, p->kernel};
+            double complex *A = malloc(sizeof(double complex) * (size_t)r * r);
+            double complex *B = malloc(sizeof(double complex) * (size_t)r * r);
+            kc[c] = aca_factor(r, class_entry, &te, p->opt.aca_tol, A, B);
+            Af[c] = A;
+            Bf[c] = B;
+        }
+    }
 
     /* v~_t = sum_{s in far(t)} T_ts u~_s ;  v_i += sum L_i(x) v~_t */
     int64_t *ptr = pairs_by_target(F, nbx);
@@ -905,8 +1003,18 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
         if (ptr[t] == ptr[t + 1]) continue;
         double complex *vt = calloc((size_t)r, sizeof(double complex));
         for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
-            const double complex *Tc = Tm + (size_t)class_of(&C, F->off + 3 * e) * r * r;
+            const int c = class_of(&C, F->off + 3 * e);
             const double complex *us = ut + F->s[e] * r;
+            if (use_aca) {
+                /* v~ += A (B^T u~) */
+                for (int q = 0; q < kc[c]; ++q) {
+                    double complex z = 0.0;
+                    for (int j = 0; j < r; ++j) z += Bf[c][(size_t)q * r + j] * us[j];
+                    for (int i = 0; i < r; ++i) vt[i] += Af[c][(size_t)q * r + i] * z;
+                }
+                continue;
+            }
+            const double complex *Tc = Tm + (size_t)c * r * r;
             for (int i = 0; i < r; ++i) {
                 double complex acc = 0.0;
                 for (int j = 0; j < r; ++j) acc += Tc[i * r + j] * us[j];
@@ -928,9 +1036,45 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
     }
     free(ptr);
     free(Tm);
+    if (use_aca) {
+        for (int c = 0; c < C.n; ++c) {
+            free(Af[c]);
+            free(Bf[c]);
+        }
+        free(Af);
+        free(Bf);
+        free(kc);
+    }
     classes_free(&C);
     free(ut);
     free(need);
+}
+
+int orc_aca_ranks(const orc_plan *p, int l, double tol, int32_t *off, int32_t *ranks)
+{
+    if (p->empty || l < 1 || l > p->leaf || p->method[l] != 1) return 0;
+    classes_t C;
+    classes_build(&C, p, l);
+    int r1 = p->order[l], r = r1 * r1 * r1;
+    double dl = ldexp(p->d0, -l), nodes[64];
+    orc_cheb_nodes(r1, nodes);
+    const pairs_t *F = &p->far[l];
+    for (int64_t i = 0; i < F->n; ++i) {
+        const int c = class_of(&C, F->off + 3 * i);
+        for (int d = 0; d < 3; ++d) off[3 * c + d] = F->off[3 * i + d];
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < C.n; ++c) {
+        tentry_t te = {C.r0[c], nodes, dl, p->k, r1, p->kernel};
+        double complex *A = malloc(sizeof(double complex) * (size_t)r * r);
+        double complex *B = malloc(sizeof(double complex) * (size_t)r * r);
+        ranks[c] = aca_factor(r, class_entry, &te, tol, A, B);
+        free(A);
+        free(B);
+    }
+    const int n = C.n;
+    classes_free(&C);
+    return n;
 }
 
 /* Gegenbauer level (Sec. 2.2.3): v = F_{s->X} (D (F_{Y->s} u)) in box-centred coordinates (R9). */

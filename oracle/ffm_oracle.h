@@ -63,6 +63,11 @@ void orc_grid_backward(int p, int w, double beta, double h, double k, int L, con
 /* phihat(xi) of the kernel above (Gauss-Legendre after t = (w/2) sin(theta)) */
 double orc_es_hat(int w, double beta, double xi);
 
+/* Adaptive cross approximation with complete pivoting of an r x r complex matrix T (row-major, interleaved):
+ * T ~ A B^T, A and B r x rank column-major complex (caller provides r x r each); returns the rank, the
+ * fewest greedy cross terms with |T - A B^T|_F <= tol |T|_F (Sec. 2.2.2, eq. ffmACAmatvec; reading R21). */
+int orc_aca(int r, const double *T, double tol, double *A, double *B);
+
 /* ---- plan ----------------------------------------------------------------- */
 typedef struct orc_plan orc_plan;
 
@@ -78,6 +83,10 @@ typedef struct {
     int32_t grid_p[ORC_MAX_LEVELS];
     int32_t grid_w[ORC_MAX_LEVELS];
     double  grid_beta[ORC_MAX_LEVELS];
+    /* ACA of the Lagrange transfer matrices (Sec. 2.2.2, eq. ffmACAmatvec) at the levels with aca[l] != 0,
+     * relative tolerance aca_tol (reading R21); 0 = plain transfer matrices. */
+    double  aca_tol;
+    int32_t aca[ORC_MAX_LEVELS];
 } orc_options;
 
 orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t ny,
@@ -108,6 +117,9 @@ int64_t orc_nnear(const orc_plan *p, int l);                        /* near_l (v
 void    orc_near(const orc_plan *p, int l, int64_t *t, int64_t *s);
 int     orc_level_method(const orc_plan *p, int l);                 /* 0 none, 1 Lagrange, 2 Gegenbauer */
 int     orc_level_order(const orc_plan *p, int l);                  /* r1 or L                   */
+/* ACA ranks of the transfer matrices of Lagrange level l at tolerance tol: one per translation class, with
+ * its integer offset (off: n x 3); returns the number of classes n (caller sizes off and ranks >= 316). */
+int     orc_aca_ranks(const orc_plan *p, int l, double tol, int32_t *off, int32_t *ranks);
 
 #ifdef __cplusplus
 }

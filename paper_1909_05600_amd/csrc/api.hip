@@ -163,10 +163,12 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     if (!(k >= 0.0) || !std::isfinite(k)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: k must be finite and >= 0");
     ffm_options_t o{};
     if (opts) o = *opts;
-    if (o.flags & ~(FFM_FLAG_TIMING | FFM_FLAG_DIRECT_TRANSFORMS | FFM_FLAG_GRID_TRANSFORMS))
+    if (o.flags & ~(FFM_FLAG_TIMING | FFM_FLAG_DIRECT_TRANSFORMS | FFM_FLAG_GRID_TRANSFORMS | FFM_FLAG_NO_ACA | FFM_FLAG_ACA))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: unknown options.flags bits");
     if ((o.flags & FFM_FLAG_DIRECT_TRANSFORMS) && (o.flags & FFM_FLAG_GRID_TRANSFORMS))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: direct and grid transforms both forced");
+    if ((o.flags & FFM_FLAG_NO_ACA) && (o.flags & FFM_FLAG_ACA))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: ACA both forbidden and forced");
     if (o.n_leaf < 0 || o.max_level < 0 || o.max_level > kMaxLev || o.r1_override < 0 || o.r1_override > 8 ||
         !(o.kd_switch >= 0.0) || (o.precision != FFM_PREC_FP32 && o.precision != FFM_PREC_MIXED))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: invalid options");
@@ -394,6 +396,20 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
                         }
                         o += w;
                     }
+                break;
+            }
+            case FFM_EXPORT_ACA_RANK: {
+                const bool has = LV.method == kLagrange && LV.aca && level >= 1;
+                *count = has ? 4 * (int64_t)LV.ncls : 0;
+                if (dst && has) {
+                    int64_t *o = static_cast<int64_t *>(dst);
+                    for (int c = 0; c < LV.ncls; ++c) {
+                        o[4 * c] = LV.cls_off[3 * c];
+                        o[4 * c + 1] = LV.cls_off[3 * c + 1];
+                        o[4 * c + 2] = LV.cls_off[3 * c + 2];
+                        o[4 * c + 3] = LV.aca_ranks[c];
+                    }
+                }
                 break;
             }
             default:

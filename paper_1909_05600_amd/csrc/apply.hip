@@ -2005,6 +2005,143 @@ k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
     }
 }
 
+// Transfer of one class group through the ACA factors of its class (Sec. 2.2.2, eq. ffmACAmatvec): Z_e =
+// A_c (B_c^T u~_{s(e)}) for up to 16 pairs e, two products on MFMA with the operand layouts of k_lag_mfma.
+// Phase 1: Y (kp x 32) = B_c^T (kp x rp) U (rp x 32), one 32-row tile of the class's padded rank kp per wave
+// (the planner keeps kp <= 32 x waves); phase 2, once every wave has read U: Y is written over U in LDS and
+// C (rp x 32) = A_c (rp x kp) Y.  Complex factors are two planes, and the complex products are formed from the
+// real and imaginary columns as in k_lag_mfma.  Item (desc, group).
+__global__ void __launch_bounds__(256)
+k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    extern __shared__ float U[];   // [rp][32], then Y [kp][32]
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int g = wk.y;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+    const int rp = d.rp, helm = d.helm, kpm = d.kpm;
+    const int c = d.grp_cls[g];
+    const int kp = d.acaKp[c];
+    __shared__ int pe[16], ps[16];
+    if (tid < 16) {
+        const int e = d.grp_pair[(int64_t)g * 16 + tid];
+        pe[tid] = e;
+        ps[tid] = e >= 0 ? d.far_src[e] : -1;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < rp * 32; idx += blockDim.x) {
+        const int k = idx >> 5, col = idx & 31, m = col >> 1;
+        float val = 0.f;
+        if (ps[m] >= 0) {
+            const float2 w = d.ut2[(int64_t)ps[m] * rp + k];
+            val = (col & 1) ? w.y : w.x;
+        }
+        U[idx] = val;
+    }
+    __syncthreads();
+    const int planes = helm ? 2 : 1;
+    const int col = lane & 31, kh = lane >> 5;
+    // phase 1: B^T U, rank tile mt = wv
+    floatx16 y;
+    const bool has_tile = wv * 32 < kp;
+    if (has_tile) {
+        const float *Bre = d.acaB + (int64_t)c * planes * rp * kpm;
+        const float *Bim = Bre + (int64_t)rp * kpm;
+        const gcf BreG = gfl(Bre) + wv * 32 + col, BimG = gfl(Bim) + wv * 32 + col;
+        floatx16 acc1, acc2;
+        for (int v = 0; v < 16; ++v) {
+            acc1[v] = 0.f;
+            acc2[v] = 0.f;
+        }
+        float a1n[4], a2n[4];
+        auto load = [&](int kk0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 2 * (kk0 + u) + kh;
+                a1n[u] = BreG[(int64_t)k * kpm];
+                a2n[u] = 0.f;
+                if (helm) a2n[u] = BimG[(int64_t)k * kpm];
+            }
+        };
+        load(0);
+        for (int kk0 = 0; kk0 < rp / 2; kk0 += 4) {
+            float bv[4], a1[4], a2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bv[u] = U[(2 * (kk0 + u) + kh) * 32 + col];
+                a1[u] = a1n[u];
+                a2[u] = a2n[u];
+            }
+            if (kk0 + 4 < rp / 2) load(kk0 + 4);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[u], bv[u], acc1, 0, 0, 0);
+                if (helm) acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[u], bv[u], acc2, 0, 0, 0);
+            }
+        }
+        for (int v = 0; v < 16; ++v) {
+            float val = acc1[v];
+            if (helm) {
+                const float sw = __shfl_xor(acc2[v], 1, 64);
+                val = (col & 1) ? val + sw : val - sw;
+            }
+            y[v] = val;
+        }
+    }
+    __syncthreads();              // every wave is done with U
+    if (has_tile)
+        for (int v = 0; v < 16; ++v) U[(wv * 32 + 8 * (v >> 2) + 4 * kh + (v & 3)) * 32 + col] = y[v];
+    __syncthreads();
+    // phase 2: A Y
+    const float *Are = d.acaA + (int64_t)c * planes * kpm * rp;
+    const float *Aim = Are + (int64_t)kpm * rp;
+    const int e = pe[col >> 1];
+    for (int mt = wv; mt < rp / 32; mt += nwv) {
+        floatx16 acc1, acc2;
+        for (int v = 0; v < 16; ++v) {
+            acc1[v] = 0.f;
+            acc2[v] = 0.f;
+        }
+        const gcf AreG = gfl(Are) + mt * 32 + col, AimG = gfl(Aim) + mt * 32 + col;
+        float a1n[4], a2n[4];
+        auto load = [&](int kk0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 2 * (kk0 + u) + kh;
+                a1n[u] = AreG[(int64_t)k * rp];
+                a2n[u] = 0.f;
+                if (helm) a2n[u] = AimG[(int64_t)k * rp];
+            }
+        };
+        load(0);
+        for (int kk0 = 0; kk0 < kp / 2; kk0 += 4) {
+            float bv[4], a1[4], a2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bv[u] = U[(2 * (kk0 + u) + kh) * 32 + col];
+                a1[u] = a1n[u];
+                a2[u] = a2n[u];
+            }
+            if (kk0 + 4 < kp / 2) load(kk0 + 4);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[u], bv[u], acc1, 0, 0, 0);
+                if (helm) acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[u], bv[u], acc2, 0, 0, 0);
+            }
+        }
+        for (int v = 0; v < 16; ++v) {
+            const int i = mt * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+            float val = acc1[v];
+            if (helm) {
+                const float sw = __shfl_xor(acc2[v], 1, 64);
+                val = (col & 1) ? val + sw : val - sw;
+            }
+            if (e >= 0) reinterpret_cast<float *>(d.Z + (int64_t)e * rp + i)[col & 1] = val;
+        }
+    }
+}
+
 // Mixed precision: the same class-group products on FP16 MFMA (v_mfma_f32_32x32x8f16) with FP32
 // accumulation.  A[i][k] comes from lane i + 32 (k / 4) (element k % 4 of a half4), B[k][j] from lane
 // j + 32 (k / 4); D as for the FP32 instruction.  T16 = T * sT (plan time); the sources are scaled by a
@@ -2305,6 +2442,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         // a = waves per block (each takes its own 32-row tiles of T over the block's staged sources)
         case K_MFMA32: threads = 64 * std::max(1, S.a); return k_lag_mfma;
         case K_MFMA16: threads = 64 * std::max(1, S.a); return k_lag_mfma16;
+        case K_ACA: threads = 64 * std::max(1, S.a); return k_lag_aca;
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
         case K_ZERO_OUT: return k_zero_io;
@@ -2469,6 +2607,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_ANTERP: return "k_lag_anterp";
         case K_MFMA32: return "k_lag_mfma";
         case K_MFMA16: return "k_lag_mfma16";
+        case K_ACA: return "k_lag_aca";
         case K_INTERP: return "k_lag_interp";
         case K_NEAR: return "k_near<" + tf(b) + ">";
         case K_ZERO_OUT: return "k_zero_io";

@@ -220,6 +220,9 @@ struct LDesc {
     // Lagrange level
     const float *T, *lnodes, *lden;
     const _Float16 *T16;
+    const float *acaA, *acaB;              // ACA factors: A [class][plane][kpm][rp], B^T [class][plane][rp][kpm]
+    const int32_t *acaKp;                  // [class] rank padded to 32
+    int kpm;                               // largest padded rank
     const int32_t *grp_pair, *grp_cls;
     float2 *ut2, *Z;
     double two_over_dl;
@@ -242,7 +245,7 @@ struct LDesc {
 enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
     K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
-    K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP
+    K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA
 };
 
 struct Stage {
@@ -300,6 +303,13 @@ struct Level {
     bool fp16 = false;                   // transfer on FP16 MFMA (mixed precision)
     DevBuf<_Float16> T16;                // [ncls][rp][rp] (x2 re/im), row-major by target index, times sT
     float sT = 1.f;                      // power-of-two scale of T16
+    // ACA factors of the transfer matrices (T is not kept): ranks, padded ranks, their maximum
+    bool aca = false;
+    double aca_rank = 0.0;               // mean rank over the classes (whenever ACA was evaluated)
+    int kpm = 0;
+    std::vector<int32_t> aca_ranks;
+    DevBuf<float> acaA, acaB;
+    DevBuf<int32_t> acaKp;
     // Gegenbauer
     int L = 0;
     int64_t nq = 0, npair = 0;           // n_Q = 2L(L+1) directions, npair = n_Q / 2 antipodal pairs

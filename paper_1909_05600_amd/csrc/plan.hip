@@ -15,6 +15,7 @@
 #include <chrono>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <cmath>
 #include <complex>
@@ -814,6 +815,74 @@ void hankel_host(int L, double z, std::vector<std::complex<double>> &h) {
     for (int p = 1; p < L; ++p) h[p + 1] = (2.0 * p + 1.0) / z * h[p] - h[p - 1];
 }
 
+// ---- ACA of the transfer matrices of a Lagrange level (Sec. 2.2.2, eq. ffmACAmatvec): T_c ~ A_c B_c^T by cross
+// approximation with complete pivoting (Bebendorf), in FP64 on the host.  Step k takes the largest entry (i, j)
+// of the residual R = T - sum of the terms so far, a_k = R(:, j), b_k = R(i, :) / R(i, j), and the rank is the
+// first k with |R|_F <= tol |T|_F, so every class meets the tolerance exactly.  The pivot is the first entry in
+// row-major order whose squared modulus is within a relative 2e-9 of the largest, so that entries equal up to
+// rounding (the tensor grid is symmetric) pick the same pivot on every machine.
+namespace {
+typedef std::complex<double> cd;
+
+cd transfer_entry(const double *r0, const double *nodes, double dl, int r1, int helm, double k, int i, int j) {
+#pragma clang fp contract(off)
+    const int ia[3] = {i / (r1 * r1), (i / r1) % r1, i % r1};
+    const int ja[3] = {j / (r1 * r1), (j / r1) % r1, j % r1};
+    double dd[3];
+    for (int d = 0; d < 3; ++d) dd[d] = r0[d] + 0.5 * dl * (nodes[ia[d]] - nodes[ja[d]]);
+    const double rr = std::sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+    if (!helm) return cd(1.0 / (4.0 * M_PI * rr), 0.0);
+    return cd(std::cos(k * rr) / (4.0 * M_PI * rr), std::sin(k * rr) / (4.0 * M_PI * rr));
+}
+
+// Columns of A and B (r entries each, column after column); returns the rank.
+int aca_class(const double *r0, const double *nodes, double dl, int r1, int helm, double k, double tol,
+              std::vector<cd> &A, std::vector<cd> &B) {
+#pragma clang fp contract(off)
+    const int r = r1 * r1 * r1;
+    const size_t rr = (size_t)r * r;
+    A.clear();
+    B.clear();
+    std::vector<cd> R(rr);
+    double T2 = 0.0;
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+            const cd t = transfer_entry(r0, nodes, dl, r1, helm, k, i, j);
+            R[(size_t)i * r + j] = t;
+            T2 += t.real() * t.real() + t.imag() * t.imag();
+        }
+    int rank = 0;
+    while (rank < r) {
+        double R2 = 0.0, m = 0.0;
+        for (size_t e = 0; e < rr; ++e) {
+            const double q = R[e].real() * R[e].real() + R[e].imag() * R[e].imag();
+            R2 += q;
+            m = std::max(m, q);
+        }
+        if (R2 <= tol * tol * T2 || m == 0.0) break;
+        size_t piv = 0;
+        for (size_t e = 0; e < rr; ++e)
+            if (R[e].real() * R[e].real() + R[e].imag() * R[e].imag() >= (1.0 - 2e-9) * m) {
+                piv = e;
+                break;
+            }
+        const int pi = (int)(piv / r), pj = (int)(piv % r);
+        const cd pv = R[piv];
+        const size_t a0 = A.size();
+        for (int q = 0; q < r; ++q) {
+            A.push_back(R[(size_t)q * r + pj]);
+            B.push_back(R[(size_t)pi * r + q] / pv);
+        }
+        for (int i = 0; i < r; ++i) {
+            const cd ai = A[a0 + i];
+            for (int j = 0; j < r; ++j) R[(size_t)i * r + j] -= ai * B[a0 + j];
+        }
+        ++rank;
+    }
+    return rank;
+}
+}  // namespace
+
 int lagrange_r1(int kernel, double k, double dl, double eps, int override_r1) {
     if (override_r1 > 0) return override_r1;
     int r1 = (int)std::ceil(std::log(1.0 / eps) / std::log(3.0 + std::sqrt(8.0)));
@@ -1411,21 +1480,10 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             upload(dr0, r0, st, SC);
             const int helm = P.kernel == FFM_HELMHOLTZ ? 1 : 0;
             const int64_t per = (int64_t)LV.rp * LV.rp;
-            LV.T.alloc((size_t)per * LV.ncls * (helm ? 2 : 1));
-            FFM_LAUNCH(k_lagrange_T, nblocks(per * LV.ncls), kThreads, 0, st, LV.ncls, dr0.p, LV.r1, LV.rp, dnodes.p,
-                       0.5 * dl, helm, P.k, LV.T.p);
             // mixed precision: FP16 transfers where the FP16 rounding (2^-11 relative, twice that for the
             // oscillatory complex kernel) stays within eps; |T| <= 1 / (4 pi d_l) is scaled to <= 1
             const double cond = helm ? 2.0 : 1.0;
             LV.fp16 = P.opt.precision == FFM_PREC_MIXED && std::ldexp(1.0, -11) * cond <= P.eps;
-            if (LV.fp16) {
-                LV.sT = (float)std::ldexp(1.0, (int)std::floor(std::log2(4.0 * M_PI * dl)));
-                const int64_t planes = (int64_t)LV.ncls * (helm ? 2 : 1);
-                LV.T16.alloc((size_t)per * planes);
-                FFM_LAUNCH(k_to_half, nblocks(per * planes), kThreads, 0, st, LV.T.p, planes, LV.rp, LV.sT,
-                           LV.T16.p);
-                P.any_fp16 = true;
-            }
             // class groups of 16 pairs for the MFMA transfer
             DevBuf<int32_t> cnt(LV.ncls), cursor(LV.ncls);
             FFM_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * LV.ncls, st));
@@ -1441,6 +1499,77 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 g += ng;
             }
             LV.ngrp = g;
+            // ACA of the transfer matrices (eq. ffmACAmatvec, relative tolerance eps / 4) where it saves MFMA work:
+            // each class's rank padded to whole 32-row tiles, at most one tile per wave of the transfer block; a
+            // pair then costs 2 rp kp instead of rp^2 multiply-adds.  Not at FP16 levels (FP16 runs 16x the FP32
+            // rate on full matrices) nor below r1 = 5 (r = 64: one 32-row tile already costs as much as T).
+            LV.aca = false;
+            const int nwv = std::min(4, LV.rp / 32);
+            const bool force_aca = (P.opt.flags & FFM_FLAG_ACA) != 0;
+            if (!LV.fp16 && !(P.opt.flags & FFM_FLAG_NO_ACA) && (LV.r1 >= 5 || force_aca)) {
+                const double tol = P.eps / 4.0;
+                std::vector<std::vector<cd>> Af(LV.ncls), Bf(LV.ncls);
+                std::vector<int> rank(LV.ncls, 0);
+                std::atomic<int> next{0};
+                auto worker = [&] {
+                    for (int c = next++; c < LV.ncls; c = next++)
+                        rank[c] = aca_class(&r0[3 * (size_t)c], nodes.data(), dl, LV.r1, helm, P.k, tol, Af[c], Bf[c]);
+                };
+                const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+                std::vector<std::thread> pool;
+                for (int t = 1; t < nth; ++t) pool.emplace_back(worker);
+                worker();
+                for (auto &t : pool) t.join();
+                int kpm = 32;
+                double cost_t = 0.0, cost_a = 0.0, rank_sum = 0.0;
+                std::vector<int32_t> kp(LV.ncls);
+                for (int c = 0; c < LV.ncls; ++c) {
+                    kp[c] = std::max(32, (rank[c] + 31) / 32 * 32);
+                    kpm = std::max(kpm, kp[c]);
+                    const double ng = (hc[c] + 15) / 16;
+                    cost_t += ng * (double)per;
+                    cost_a += ng * 2.0 * LV.rp * kp[c];
+                    rank_sum += rank[c];
+                }
+                LV.aca = kpm <= 32 * nwv && (force_aca || cost_a <= 0.75 * cost_t);
+                LV.aca_rank = LV.ncls ? rank_sum / LV.ncls : 0.0;
+                if (LV.aca) {
+                    LV.kpm = kpm;
+                    LV.aca_ranks.assign(rank.begin(), rank.end());
+                    const int planes = helm ? 2 : 1;
+                    std::vector<float> ha((size_t)LV.ncls * planes * kpm * LV.rp, 0.f);
+                    std::vector<float> hb((size_t)LV.ncls * planes * LV.rp * kpm, 0.f);
+                    const int r = LV.r;
+                    for (int c = 0; c < LV.ncls; ++c)
+                        for (int q = 0; q < rank[c]; ++q)
+                            for (int i = 0; i < r; ++i) {
+                                const cd a = Af[c][(size_t)q * r + i], b = Bf[c][(size_t)q * r + i];
+                                // A: element (i, q) at [c][plane][q][i]; B^T: element (q, j = i) at [c][plane][j][q]
+                                ha[(((size_t)c * planes) * kpm + q) * LV.rp + i] = (float)a.real();
+                                hb[(((size_t)c * planes) * LV.rp + i) * kpm + q] = (float)b.real();
+                                if (helm) {
+                                    ha[(((size_t)c * planes + 1) * kpm + q) * LV.rp + i] = (float)a.imag();
+                                    hb[(((size_t)c * planes + 1) * LV.rp + i) * kpm + q] = (float)b.imag();
+                                }
+                            }
+                    upload(LV.acaA, ha, st, SC);
+                    upload(LV.acaB, hb, st, SC);
+                    upload(LV.acaKp, kp, st, SC);
+                }
+            }
+            if (!LV.aca) {
+                LV.T.alloc((size_t)per * LV.ncls * (helm ? 2 : 1));
+                FFM_LAUNCH(k_lagrange_T, nblocks(per * LV.ncls), kThreads, 0, st, LV.ncls, dr0.p, LV.r1, LV.rp, dnodes.p,
+                           0.5 * dl, helm, P.k, LV.T.p);
+            }
+            if (LV.fp16) {
+                LV.sT = (float)std::ldexp(1.0, (int)std::floor(std::log2(4.0 * M_PI * dl)));
+                const int64_t planes = (int64_t)LV.ncls * (helm ? 2 : 1);
+                LV.T16.alloc((size_t)per * planes);
+                FFM_LAUNCH(k_to_half, nblocks(per * planes), kThreads, 0, st, LV.T.p, planes, LV.rp, LV.sT,
+                           LV.T16.p);
+                P.any_fp16 = true;
+            }
             DevBuf<int32_t> dgs;
             upload(dgs, gstart, st, SC);
             upload(LV.grp_cls, gcls, st, SC);
@@ -1509,6 +1638,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.grid_nodes[l] = LV.method == kGegenbauer && LV.grid ? LV.gp : 0;
         s.grid_width[l] = LV.method == kGegenbauer && LV.grid ? LV.gw : 0;
         s.grid_beta[l] = LV.method == kGegenbauer && LV.grid ? LV.gbeta : 0.0;
+        s.aca[l] = LV.method == kLagrange && LV.aca ? 1 : 0;
+        s.aca_rank[l] = LV.method == kLagrange ? LV.aca_rank : 0.0;
         s.grid_alias[l] = LV.method == kGegenbauer && LV.grid ? LV.galias : 0.0;
         s.fwd_boxes[l] = (int64_t)LV.h_fwd.size();
         s.bwd_boxes[l] = (int64_t)LV.h_tgt.size();
@@ -1839,8 +1970,12 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             }
             for (int32_t t : LV.h_tgt) ip.push_back(make_int4(l, t, 0, 0));
             LV.stages.push_back(make_stage(K_ANTERP, 0, 0, s1, l, 0, std::move(an), st, SC));
-            LV.stages.push_back(make_stage(LV.fp16 ? K_MFMA16 : K_MFMA32, LV.fp16 ? 1 : std::min(4, LV.rp / 32), 0, s2, l,
-                                           (size_t)LV.rp * 32 * (LV.fp16 ? 2 : 4), std::move(mf), st, SC));
+            if (LV.aca)
+                LV.stages.push_back(make_stage(K_ACA, std::min(4, LV.rp / 32), 0, s2, l, (size_t)LV.rp * 32 * 4,
+                                               std::move(mf), st, SC));
+            else
+                LV.stages.push_back(make_stage(LV.fp16 ? K_MFMA16 : K_MFMA32, LV.fp16 ? 1 : std::min(4, LV.rp / 32), 0,
+                                               s2, l, (size_t)LV.rp * 32 * (LV.fp16 ? 2 : 4), std::move(mf), st, SC));
             LV.stages.push_back(make_stage(K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r, std::move(ip), st, SC));
         }
     }
@@ -1932,6 +2067,10 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.lnodes = LV.lnodes.p;
     d.lden = LV.lden.p;
     d.T16 = LV.T16.p;
+    d.acaA = LV.acaA.p;
+    d.acaB = LV.acaB.p;
+    d.acaKp = LV.acaKp.p;
+    d.kpm = LV.kpm;
     d.grp_pair = LV.grp_pair.p;
     d.grp_cls = LV.grp_cls.p;
     d.ut2 = w.ut2;
@@ -1996,7 +2135,8 @@ size_t plan_device_bytes(const Plan &P) {
         const Level &L = P.lev[l];
         b += L.far_ptr.bytes() + L.near_ptr.bytes() + L.far_src.bytes() + L.far_cls.bytes() + L.near_src.bytes() +
              L.T.bytes() + L.grp_pair.bytes() + L.grp_cls.bytes() + L.dirs.bytes() + L.dirs64.bytes() + L.D.bytes() +
-             L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes() + L.Ez.bytes() +
+             L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes() + L.acaA.bytes() +
+             L.acaB.bytes() + L.acaKp.bytes() + L.Ez.bytes() +
              L.Ex.bytes() + L.Ey.bytes() + L.ExT.bytes() + L.EyT.bytes() + L.gperm.bytes() + L.gzs.bytes() + L.gxyz.bytes() +
              L.tr_tgt.bytes();
     }

@@ -21,9 +21,15 @@ def oracle_grid(gp) -> dict:
             for l in range(1, st["leaf"] + 1) if st["tform"][l] == 3}
 
 
+def oracle_aca(gp) -> list:
+    """The levels of a GPU plan whose transfers use ACA factors (relative tolerance eps / 4)."""
+    st = gp.stats()
+    return [l for l in range(1, st["leaf"] + 1) if st["aca"][l]]
+
+
 def oracle_like(orc, gp, X, Y, kernel, k, eps, **kw):
-    """The oracle's plan with the GPU plan's parameters (its grid-form levels included)."""
-    return orc.Plan(X, Y, kernel, k, eps, grid=oracle_grid(gp), **kw)
+    """The oracle's plan with the GPU plan's parameters (its grid-form and ACA levels included)."""
+    return orc.Plan(X, Y, kernel, k, eps, grid=oracle_grid(gp), aca=oracle_aca(gp), aca_tol=eps / 4.0, **kw)
 
 
 def gpu_plan(X, Y, kernel, k, eps, **kw):
