@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--bie-study", action="store_true",
                     help="only run the single-layer sphere solve (GMRES with FFM products) at --bie-n nodes")
     ap.add_argument("--bie-n", type=int, default=1 << 20)
+    ap.add_argument("--aca-study", action="store_true",
+                    help="only run the ACA study (full transfer matrices against their ACA factors)")
     ap.add_argument("--bie-eps", type=float, default=1e-3)
     ap.add_argument("--bie-tol", type=float, default=1e-4)
     ap.add_argument("--mixed-rows", type=int, default=1024)
@@ -386,6 +388,74 @@ def mixed_study(n, n_rows, reps=3):
     return out
 
 
+def aca_study(n, reps=5):
+    """ACA of the Lagrange transfer matrices (Sec. 2.2.2, eq. ffmACAmatvec) against full matrices: apply and plan
+    times, transfer-kernel times and errors against FP64 dense rows, for N points on the sphere: Laplace at
+    eps = 1e-4 (six Chebyshev nodes per axis, r = 216) and Helmholtz k = 9 at eps = 1e-3 (Lagrange
+    levels with r = 216 and 125); and the 256-instance batched workload in FP32."""
+    import torch
+    import ffm_workloads as W
+    import paper_1909_05600_amd as ffm
+    out = {"n": n, "runs": []}
+    for kernel, k, eps, seed in ((0, 0.0, 1e-4, 1), (1, 9.0, 1e-3, 2)):
+        w = W.helmholtz_sphere(n, seed=seed, k=k, eps=eps, n_rows=256)
+        X = torch.from_numpy(w.X).cuda()
+        wu = torch.from_numpy(w.wu).cuda()
+        d = dense_rows_device(X, wu, kernel, k, w.rows)
+        for aca in ("off", "auto"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = ffm.Plan(X, X, kernel, k, eps, aca=aca, timing=True)
+            torch.cuda.synchronize()
+            t_plan = time.perf_counter() - t0
+            v = p.apply(wu)
+            t_apply = _sync_time(lambda: p.apply(wu, out=v), reps)
+            lt = p.launch_timing()
+            tr = sum(r["ms"] for r in lt if r["kernel"] in ("k_lag_mfma", "k_lag_aca"))
+            st = p.stats()
+            vv = v.cpu().numpy()[w.rows].astype(np.complex128)
+            r = {"kernel": "laplace" if kernel == 0 else "helmholtz", "k": k, "eps": eps, "aca": aca,
+                 "plan_s": t_plan, "apply_ms": t_apply * 1e3, "transfer_kernel_ms": tr,
+                 "aca_levels": [l for l in range(st["leaf"] + 1) if st["aca"][l]],
+                 "mean_rank": [round(st["aca_rank"][l], 1) for l in range(st["leaf"] + 1) if st["method"][l] == 1],
+                 "r": [st["order"][l] ** 3 for l in range(st["leaf"] + 1) if st["method"][l] == 1],
+                 "err": float(np.linalg.norm(vv - d) / np.linalg.norm(d)), "plan_mb": st["plan_bytes"] / 1e6}
+            out["runs"].append(r)
+            print("aca study %s eps=%g aca=%s: plan %.2fs apply %.2f ms (transfers %.2f ms) err %.2e"
+                  % (r["kernel"], eps, aca, t_plan, r["apply_ms"], tr, r["err"]), file=sys.stderr, flush=True)
+            p.destroy()
+        del X, wu
+        torch.cuda.empty_cache()
+    ws = W.batched_instances(256, seed=4)
+    Xs = [torch.from_numpy(w.X).cuda() for w in ws]
+    wus = [torch.from_numpy(w.wu).cuda() for w in ws]
+    n_tot = sum(w.n for w in ws)
+    for aca in ("off", "auto"):
+        t0 = time.perf_counter()
+        plans = [ffm.Plan(X, X, w.kernel, w.k, w.eps, aca=aca) for X, w in zip(Xs, ws)]
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        b = ffm.Batch(plans, graph=True)
+        o = b.apply(wus)
+        t = _sync_time(lambda: b.apply(wus, outs=o), reps)
+        errs = []
+        for w, X, u, oo in zip(ws, Xs, wus, o):
+            rows = w.rows[:16]
+            dd = dense_rows_device(X, u, w.kernel, w.k, rows)
+            vv = oo.cpu().numpy()[rows].astype(np.complex128)
+            errs.append(float(np.linalg.norm(vv - dd) / np.linalg.norm(dd)))
+        nlev = sum(sum(p.stats()["aca"]) for p in plans)
+        r = {"workload": "batched 256 instances, FP32 graph", "aca": aca, "points_per_s": n_tot / t,
+             "apply_ms": t * 1e3, "plan_s": t_plan, "aca_levels_total": nlev, "err_max": max(errs)}
+        out["runs"].append(r)
+        print("aca study batched aca=%s: %.3g points/s (%.1f ms), plan %.1fs, %d ACA levels, err max %.2e"
+              % (aca, r["points_per_s"], r["apply_ms"], t_plan, nlev, r["err_max"]), file=sys.stderr, flush=True)
+        b.destroy()
+        for p in plans:
+            p.destroy()
+    return out
+
+
 def bie_study(n, eps, tol, kernels=(0, 1)):
     """The single-layer equation on the unit sphere (reduced Gauss grid with about n nodes): GMRES with one FFM
     product per iteration, for Laplace (data: the potential of a point charge inside the sphere) and for
@@ -575,6 +645,12 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
+    if args.aca_study:
+        res = {"metric": "ACA of the Lagrange transfers: apply time and error against full matrices",
+               "aca_study": aca_study(args.n)}
+        print(json.dumps(res), flush=True)
+        return
+
     if args.cpu_validate:
         wv = W.helmholtz_sphere(args.cpu_validate, seed=2, eps=args.eps)
         strides = tuple(int(x) for x in args.cpu_strides.split(","))
@@ -704,8 +780,12 @@ def main():
                                       "1 GiB copy)"),
         "kernels_ms_per_step": {k: round(v, 4) for k, v in kernel_totals(rec["launches"], args.steps).items()},
         "memory": {"plan_bytes": st["plan_bytes"], "workspace_bytes": st["workspace_bytes"],
+                   "tables_bytes": st["plan_bytes"] - st["workspace_bytes"],
                    "plan_bytes_per_point": st["plan_bytes"] / w.n,
+                   "tables_bytes_per_point": (st["plan_bytes"] - st["workspace_bytes"]) / w.n,
                    "workspace_bytes_per_point": st["workspace_bytes"] / w.n,
+                   "definition": "plan_bytes: all device memory of a plan, its apply workspace included; tables: the "
+                                 "rest (trees, lists, operator tables, launch lists)",
                    "paper": "O(N) storage (Sec. 3, Prop. 1); the paper's Table 1 lists about 100 bytes per point "
                             "(Laplace, its own implementation, which keeps nothing between products)"},
         "levels": {"leaf": leaf, "nq": [int(x) for x in st["nq"][:leaf + 1]],
