@@ -43,7 +43,10 @@ extern "C" {
 
 typedef struct ffm_plan_s *ffm_plan_t;
 
-typedef enum { FFM_LAPLACE = 0, FFM_HELMHOLTZ = 1 } ffm_kernel_t;
+/* Kernels.  The _DN kernels are the normal derivative at the target, dG/dn_x (x, y) = n_x . grad_x G(x - y), of
+ * the adjoint double-layer operator (Sec. 4.2.1, eq. doubleLayer); they need options.target_normals and run
+ * their plane-wave levels with the direct transforms. */
+typedef enum { FFM_LAPLACE = 0, FFM_HELMHOLTZ = 1, FFM_LAPLACE_DN = 2, FFM_HELMHOLTZ_DN = 3 } ffm_kernel_t;
 
 typedef enum {
     FFM_OK = 0,
@@ -71,6 +74,8 @@ typedef struct {
     int32_t r1_override;  /* > 0: Chebyshev nodes per axis at every Lagrange level              */
     int32_t max_level;    /* depth cap, 1..20 (20)                                              */
     uint32_t flags;       /* FFM_FLAG_* bits; other bits must be 0                              */
+    const double *target_normals;   /* _DN kernels: device, FP64 [n_x][3] unit normals at the targets in the
+                                       caller's order, read while the plan is built; otherwise NULL     */
 } ffm_options_t;
 
 /* options.flags: record HIP events between the phases of every apply (see ffm_plan_timing). */
@@ -96,8 +101,9 @@ typedef struct {
  *   X      device, FP64 [n_x][3]: targets x_i.
  *   Y      device, FP64 [n_y][3]: sources y_j.  Y == X with n_y == n_x means
  *          the same set: one tree serves both.
- *   kernel FFM_LAPLACE or FFM_HELMHOLTZ; k >= 0 is the wavenumber (ignored for
- *          Laplace; Helmholtz with k = 0 equals Laplace).
+ *   kernel FFM_LAPLACE or FFM_HELMHOLTZ, or their normal derivatives at the
+ *          targets FFM_LAPLACE_DN, FFM_HELMHOLTZ_DN; k >= 0 is the wavenumber
+ *          (ignored for Laplace; Helmholtz with k = 0 equals Laplace).
  *   eps    prescribed accuracy, 1e-7 <= eps < 0.5.
  *   opts   host pointer or NULL.
  *   hip_stream  stream for the planning kernels.

@@ -21,6 +21,8 @@ _lib = None
 
 LAPLACE = 0
 HELMHOLTZ = 1
+LAPLACE_DN = 2          # normal derivative at the target: the adjoint double-layer kernel
+HELMHOLTZ_DN = 3
 
 
 def build(force: bool = True) -> str:
@@ -76,6 +78,8 @@ def lib():
             "orc_grid_backward": (None, [C.c_int, C.c_int, dbl, dbl, dbl, C.c_int, P, P, i64, P]),
             "orc_es_hat": (dbl, [C.c_int, dbl, dbl]),
             "orc_aca": (C.c_int, [C.c_int, P, dbl, P, P]),
+            "orc_dense_rows_dn": (None, [P, P, i64, P, C.c_int, dbl, P, P, i64, P]),
+            "orc_lagrange_basis_deriv": (None, [C.c_int, dbl, P]),
             "orc_aca_ranks": (C.c_int, [P, C.c_int, dbl, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -96,7 +100,8 @@ MAX_LEVELS = 21
 class _Options(C.Structure):
     _fields_ = [("n_leaf", C.c_int32), ("kappa", C.c_double), ("r1_override", C.c_int32),
                 ("max_level", C.c_int32), ("grid_p", C.c_int32 * MAX_LEVELS), ("grid_w", C.c_int32 * MAX_LEVELS),
-                ("grid_beta", C.c_double * MAX_LEVELS), ("aca_tol", C.c_double), ("aca", C.c_int32 * MAX_LEVELS)]
+                ("grid_beta", C.c_double * MAX_LEVELS), ("aca_tol", C.c_double), ("aca", C.c_int32 * MAX_LEVELS),
+                ("target_normals", C.c_void_p)]
 
 
 def _ptr(a: np.ndarray):
@@ -120,6 +125,24 @@ def dense_rows(X, Y, wu, kernel: int, k: float, rows) -> np.ndarray:
     lib().orc_dense_rows(_ptr(X), _ptr(Y), Y.shape[0], _ptr(w), int(kernel), float(k), _ptr(r), r.size,
                          _ptr(out))
     return out
+
+
+def dense_rows_dn(X, Y, wu, kernel: int, k: float, NX, rows) -> np.ndarray:
+    """FP64 direct sum of the normal derivative at the targets, v_i = sum_{j: r_ij > 0} n_i . grad_x G(x_i - y_j)
+    wu_j (the adjoint double-layer kernel), on the given rows; kernel is the base kernel (0 or 1)."""
+    X, Y, N = _coords(X), _coords(Y), _coords(NX)
+    w = _complex128(wu)
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).ravel())
+    out = np.zeros(r.size, dtype=np.complex128)
+    lib().orc_dense_rows_dn(_ptr(X), _ptr(Y), Y.shape[0], _ptr(w), int(kernel) & 1, float(k), _ptr(N), _ptr(r),
+                            r.size, _ptr(out))
+    return out
+
+
+def lagrange_basis_deriv(r1: int, t: float) -> np.ndarray:
+    e = np.zeros(r1)
+    lib().orc_lagrange_basis_deriv(r1, float(t), _ptr(e))
+    return e
 
 
 def gauss_legendre(n: int):
@@ -219,7 +242,7 @@ class Plan:
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 64,
                  kappa: float = 0.0, r1: int = 0, max_level: int = 20, grid: dict | None = None,
-                 aca=(), aca_tol: float = 0.0):
+                 aca=(), aca_tol: float = 0.0, normals=None):
         self.X = _coords(X)
         self.Y = self.X if Y is X else _coords(Y)
         self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
@@ -231,6 +254,11 @@ class Plan:
         opt.aca_tol = float(aca_tol)
         for l in aca:
             opt.aca[int(l)] = 1
+        if int(kernel) >= 2:
+            if normals is None:
+                raise ValueError("normal-derivative kernels need the target normals")
+            self._normals = _coords(normals)
+            opt.target_normals = self._normals.ctypes.data
         self._h = lib().orc_plan_create(_ptr(self.X), self.X.shape[0], _ptr(self.Y), self.Y.shape[0],
                                         self.kernel, self.k, self.eps, C.byref(opt))
         if not self._h:

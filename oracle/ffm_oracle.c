@@ -67,6 +67,18 @@ static double complex green(int kernel, double k, double r)
     return cexp(I * (k * r)) / (4.0 * ORC_PI * r);
 }
 
+/* Normal derivative at the target, n . grad_x G(x - y) with d = x - y (the adjoint double-layer kernel of
+ * Sec. 4.2.1, eq. doubleLayer): grad_x G = d G'(r) / r, G'(r) = -1 / (4 pi r^2) (Laplace) or
+ * (ikr - 1) e^{ikr} / (4 pi r^2) (Helmholtz). */
+static double complex green_dn(int kernel, double k, const double d[3], const double n[3])
+{
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+    const double r3 = 4.0 * ORC_PI * r * r * r;
+    if (kernel == ORC_LAPLACE) return -nd / r3;
+    return nd * (I * (k * r) - 1.0) * cexp(I * (k * r)) / r3;
+}
+
 /* Timing samples (orc_apply with stride > 1) keep the points whose sorted index is a multiple of the stride:
  * the first such index at or after i. */
 static int64_t first_sample(int64_t i, int64_t stride) { return (i + stride - 1) / stride * stride; }
@@ -105,6 +117,24 @@ void orc_legendre_p(int L, double t, double *P)
 }
 
 /* Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_n. */
+void orc_dense_rows_dn(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
+                       const double *NX, const int64_t *rows, int64_t nrows, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < nrows; ++a) {
+        const double *x = X + 3 * rows[a];
+        const double *n = NX + 3 * rows[a];
+        double complex acc = 0.0;
+        for (int64_t j = 0; j < ny; ++j) {
+            double d[3] = {x[0] - Y[3 * j], x[1] - Y[3 * j + 1], x[2] - Y[3 * j + 2]};
+            if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] == 0.0) continue;   /* R11 */
+            acc += green_dn(kernel, k, d, n) * cload(wu, j);
+        }
+        out[2 * a] = creal(acc);
+        out[2 * a + 1] = cimag(acc);
+    }
+}
+
 void orc_gauss_legendre(int n, double *x, double *w)
 {
     for (int i = 0; i < n; ++i) {
@@ -174,6 +204,27 @@ void orc_lagrange_basis(int r1, double t, double *ell)
         for (int b = 0; b < r1; ++b)
             if (b != a) v *= (t - nodes[b]) / (nodes[a] - nodes[b]);
         ell[a] = v;
+    }
+}
+
+/* Derivatives of the one-dimensional Lagrange polynomials at t:
+ * l_a'(t) = sum_{m != a} prod_{b != a, m} (t - t_b) / prod_{b != a} (t_a - t_b). */
+void orc_lagrange_basis_deriv(int r1, double t, double *dell)
+{
+    double nodes[64];
+    orc_cheb_nodes(r1, nodes);
+    for (int a = 0; a < r1; ++a) {
+        double den = 1.0, sum = 0.0;
+        for (int b = 0; b < r1; ++b)
+            if (b != a) den *= nodes[a] - nodes[b];
+        for (int m = 0; m < r1; ++m) {
+            if (m == a) continue;
+            double pr = 1.0;
+            for (int b = 0; b < r1; ++b)
+                if (b != a && b != m) pr *= t - nodes[b];
+            sum += pr;
+        }
+        dell[a] = sum / den;
     }
 }
 
@@ -535,7 +586,9 @@ typedef struct {
 } pairs_t;
 
 struct orc_plan {
-    int kernel;
+    int kernel;                /* ORC_LAPLACE or ORC_HELMHOLTZ */
+    int dn;                    /* 1: the normal derivative at the targets (adjoint double layer) */
+    double *NXs;               /* target normals in sorted order (dn plans) */
     double k, eps;
     orc_options opt;
     int empty;                 /* one of the sets is empty: v = 0 */
@@ -718,6 +771,8 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
                           int kernel, double k, double eps, const orc_options *opt)
 {
     orc_plan *p = calloc(1, sizeof(orc_plan));
+    p->dn = kernel >= 2;
+    kernel &= 1;
     p->kernel = kernel;
     p->k = k;
     p->eps = eps;
@@ -771,6 +826,11 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
     for (int e = 0; e < 2; ++e) {
         tree_build(&p->T[e], PS[e], NS[e], corner[e], p->S);
         tree_level(&p->T[e], 0, d0);
+    }
+    if (p->dn) {
+        p->NXs = malloc(sizeof(double) * 3 * (size_t)nx);
+        for (int64_t i = 0; i < nx; ++i)
+            for (int d = 0; d < 3; ++d) p->NXs[3 * i + d] = opt->target_normals[3 * p->T[0].perm[i] + d];
     }
 
     /* Descent (Sec. 2.2.2, 2.2.4, 3.2): near_0 = {(root, root)}; the child pairs of every near
@@ -840,6 +900,7 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
 void orc_plan_free(orc_plan *p)
 {
     if (!p) return;
+    free(p->NXs);
     if (!p->empty) {
         for (int e = 0; e < 2; ++e) tree_free(&p->T[e]);
         for (int l = 0; l <= BITS; ++l) {
@@ -1021,15 +1082,33 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
                 vt[i] += acc;
             }
         }
-        double ex[64], ey[64], ez[64];
+        double ex[64], ey[64], ez[64], dx[64], dy[64], dz[64];
         for (int64_t i = first_sample(TX->start[l][t], stride); i < TX->start[l][t + 1]; i += stride) {
-            orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i] - TX->ctr[l][3 * t]) / dl, ex);
-            orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i + 1] - TX->ctr[l][3 * t + 1]) / dl, ey);
-            orc_lagrange_basis(r1, 2.0 * (TX->P[3 * i + 2] - TX->ctr[l][3 * t + 2]) / dl, ez);
+            const double tx = 2.0 * (TX->P[3 * i] - TX->ctr[l][3 * t]) / dl;
+            const double ty = 2.0 * (TX->P[3 * i + 1] - TX->ctr[l][3 * t + 1]) / dl;
+            const double tz = 2.0 * (TX->P[3 * i + 2] - TX->ctr[l][3 * t + 2]) / dl;
+            orc_lagrange_basis(r1, tx, ex);
+            orc_lagrange_basis(r1, ty, ey);
+            orc_lagrange_basis(r1, tz, ez);
             double complex acc = 0.0;
-            for (int a = 0; a < r1; ++a)
-                for (int b = 0; b < r1; ++b)
-                    for (int c = 0; c < r1; ++c) acc += ex[a] * ey[b] * ez[c] * vt[(a * r1 + b) * r1 + c];
+            if (p->dn) {
+                /* n . grad of the interpolant; d/dx of l(2 (x - c) / d_l) is (2 / d_l) l' */
+                const double *n = p->NXs + 3 * i;
+                orc_lagrange_basis_deriv(r1, tx, dx);
+                orc_lagrange_basis_deriv(r1, ty, dy);
+                orc_lagrange_basis_deriv(r1, tz, dz);
+                for (int a = 0; a < r1; ++a)
+                    for (int b = 0; b < r1; ++b)
+                        for (int c = 0; c < r1; ++c) {
+                            const double g = n[0] * dx[a] * ey[b] * ez[c] + n[1] * ex[a] * dy[b] * ez[c] +
+                                             n[2] * ex[a] * ey[b] * dz[c];
+                            acc += (2.0 / dl) * g * vt[(a * r1 + b) * r1 + c];
+                        }
+            } else {
+                for (int a = 0; a < r1; ++a)
+                    for (int b = 0; b < r1; ++b)
+                        for (int c = 0; c < r1; ++c) acc += ex[a] * ey[b] * ez[c] * vt[(a * r1 + b) * r1 + c];
+            }
             v[i] += acc;
         }
         free(vt);
@@ -1096,7 +1175,7 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     for (int64_t i = 0; i < F->n; ++i) need[F->s[i]] = 1;
 
     /* grid form of the transforms at this level (R16-R18), else the direct sums */
-    const int grid = p->opt.grid_p[l] > 0;
+    const int grid = p->opt.grid_p[l] > 0 && !p->dn;   /* normal-derivative plans use the direct sums */
     gridlev_t gl;
     if (grid) {
         int gp = p->opt.grid_p[l], gw = p->opt.grid_w[l];
@@ -1166,8 +1245,16 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
         for (int64_t i = first_sample(TX->start[l][t], stride); i < TX->start[l][t + 1]; i += stride) {
             double x0 = TX->P[3 * i] - c[0], x1 = TX->P[3 * i + 1] - c[1], x2 = TX->P[3 * i + 2] - c[2];
             double complex acc = 0.0;
-            for (int64_t q = 0; q < nq; ++q)
-                acc += cexp(I * k * (s[3 * q] * x0 + s[3 * q + 1] * x1 + s[3 * q + 2] * x2)) * vt[q];
+            if (p->dn) {
+                /* n . grad_x e^{ik s.(x - c)} = ik (s . n) e^{ik s.(x - c)} */
+                const double *n = p->NXs + 3 * i;
+                for (int64_t q = 0; q < nq; ++q)
+                    acc += I * k * (s[3 * q] * n[0] + s[3 * q + 1] * n[1] + s[3 * q + 2] * n[2]) *
+                           cexp(I * k * (s[3 * q] * x0 + s[3 * q + 1] * x1 + s[3 * q + 2] * x2)) * vt[q];
+            } else {
+                for (int64_t q = 0; q < nq; ++q)
+                    acc += cexp(I * k * (s[3 * q] * x0 + s[3 * q + 1] * x1 + s[3 * q + 2] * x2)) * vt[q];
+            }
             v[i] += acc;
         }
         free(vt);
@@ -1201,7 +1288,12 @@ static void near_field(const orc_plan *p, const double complex *u, double comple
                            dz = TX->P[3 * i + 2] - TY->P[3 * j + 2];
                     double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 == 0.0) continue;   /* R11 */
-                    acc += green(p->kernel, p->k, sqrt(r2)) * u[j];
+                    if (p->dn) {
+                        const double d[3] = {dx, dy, dz};
+                        acc += green_dn(p->kernel, p->k, d, p->NXs + 3 * i) * u[j];
+                    } else {
+                        acc += green(p->kernel, p->k, sqrt(r2)) * u[j];
+                    }
                 }
                 v[i] += acc;
             }

@@ -30,11 +30,20 @@ extern "C" {
 
 #define ORC_LAPLACE 0
 #define ORC_HELMHOLTZ 1
+/* The normal derivative at the target, dG/dn_x (x, y) = n_x . grad_x G(x - y): the kernel of the adjoint
+ * double-layer operator (Sec. 4.2.1, eq. doubleLayer), for each base kernel; plans need target normals. */
+#define ORC_LAPLACE_DN 2
+#define ORC_HELMHOLTZ_DN 3
 
 /* ---- plain definition ---------------------------------------------------- */
 /* out[a] = sum_{j : |x_rows[a] - y_j| > 0} G(|x_rows[a] - y_j|) * wu[j]  (complex128 out) */
 void orc_dense_rows(const double *X, const double *Y, int64_t ny, const double *wu,
                     int kernel, double k, const int64_t *rows, int64_t nrows, double *out);
+
+/* out[a] = sum_{j : |x - y_j| > 0} n_x . grad_x G(x - y_j) wu[j] at x = x_rows[a] with normal NX[rows[a]];
+ * kernel ORC_LAPLACE or ORC_HELMHOLTZ (the base kernel) */
+void orc_dense_rows_dn(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
+                       const double *NX, const int64_t *rows, int64_t nrows, double *out);
 
 /* ---- building blocks, exported so the tests can pin them ----------------- */
 void orc_gauss_legendre(int n, double *x, double *w);
@@ -42,6 +51,7 @@ void orc_legendre_p(int L, double t, double *P);                 /* P_0..P_L at 
 void orc_sph_hankel1(int L, double z, double *h);                 /* h_0..h_L (complex) at z>0 */
 void orc_cheb_nodes(int r1, double *t);                           /* first-kind nodes         */
 void orc_lagrange_basis(int r1, double t, double *ell);            /* l_1..l_r1 at t           */
+void orc_lagrange_basis_deriv(int r1, double t, double *dell);     /* l_1'..l_r1' at t         */
 int  orc_gegenbauer_rank(double k, double d_l, double eps);
 /* quadrature of a Gegenbauer level: s (nq x 3), w (nq); returns nq = 2L(L+1) */
 int64_t orc_sphere_quadrature(int L, double *s, double *w);
@@ -87,6 +97,8 @@ typedef struct {
      * relative tolerance aca_tol (reading R21); 0 = plain transfer matrices. */
     double  aca_tol;
     int32_t aca[ORC_MAX_LEVELS];
+    /* ORC_*_DN kernels: unit normals at the targets, n_x x 3, user order (copied at plan creation) */
+    const double *target_normals;
 } orc_options;
 
 orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t ny,

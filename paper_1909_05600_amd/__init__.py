@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(HERE, "libffm.so")
 
 FFM_LAPLACE = 0
 FFM_HELMHOLTZ = 1
+FFM_LAPLACE_DN = 2          # normal derivative at the target (adjoint double-layer kernel)
+FFM_HELMHOLTZ_DN = 3
 FFM_C64, FFM_F32, FFM_F64, FFM_C128 = 0, 1, 2, 3
 FFM_PREC_FP32, FFM_PREC_MIXED = 0, 1
 FFM_EXPORT_KEYS, FFM_EXPORT_PERM, FFM_EXPORT_BOX_START, FFM_EXPORT_BOX_IJK = 0, 1, 2, 3
@@ -49,7 +51,8 @@ class FFMError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("n_leaf", C.c_int32), ("precision", C.c_int32), ("kd_switch", C.c_double),
-                ("r1_override", C.c_int32), ("max_level", C.c_int32), ("flags", C.c_uint32)]
+                ("r1_override", C.c_int32), ("max_level", C.c_int32), ("flags", C.c_uint32),
+                ("target_normals", C.c_void_p)]
 
 
 _L = MAX_LEVELS
@@ -239,7 +242,7 @@ class Plan:
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 0, precision: int = 0,
                  kd_switch: float = 0.0, r1_override: int = 0, max_level: int = 0, timing: bool = False,
-                 transforms: str = "auto", aca: str = "auto", stream=None):
+                 transforms: str = "auto", aca: str = "auto", normals=None, stream=None):
         import torch
         same = Y is X
         X = X.detach().contiguous()
@@ -258,6 +261,11 @@ class Plan:
                                                       "grid": FFM_FLAG_GRID_TRANSFORMS}[transforms] | \
             {"auto": 0, "off": FFM_FLAG_NO_ACA, "on": FFM_FLAG_ACA}[aca]
         opts = Options(int(n_leaf), int(precision), float(kd_switch), int(r1_override), int(max_level), flags)
+        if normals is not None:
+            normals = normals.detach().contiguous()
+            if normals.dtype != torch.float64 or normals.shape != X.shape or not normals.is_cuda:
+                raise TypeError("normals must be a CUDA float64 tensor shaped like X")
+            opts.target_normals = normals.data_ptr()
         self._h = None
         with torch.cuda.device(self.device):
             self._h = ffm_plan(X.data_ptr(), self.n_x, Y.data_ptr(), self.n_y, self.kernel, self.k, self.eps,

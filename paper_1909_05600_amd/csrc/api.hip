@@ -157,8 +157,11 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     if (n_x < 0 || n_y < 0 || n_x >= (int64_t(1) << 31) || n_y >= (int64_t(1) << 31))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: sizes must be in [0, 2^31)");
     if ((n_x > 0 && !X) || (n_y > 0 && !Y)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: NULL coordinates");
-    if (kernel != FFM_LAPLACE && kernel != FFM_HELMHOLTZ)
+    if (kernel != FFM_LAPLACE && kernel != FFM_HELMHOLTZ && kernel != FFM_LAPLACE_DN && kernel != FFM_HELMHOLTZ_DN)
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: unknown kernel");
+    const bool dn = kernel == FFM_LAPLACE_DN || kernel == FFM_HELMHOLTZ_DN;
+    if (dn && n_x > 0 && !(opts && opts->target_normals))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: normal-derivative kernels need options.target_normals");
     if (!(eps >= 1e-7 && eps < 0.5)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: eps must be in [1e-7, 0.5)");
     if (!(k >= 0.0) || !std::isfinite(k)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: k must be finite and >= 0");
     ffm_options_t o{};
@@ -180,8 +183,10 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     int rc = Guard::run([&] {
         std::unique_ptr<ffm_plan_s> p(new ffm_plan_s());
         Plan &P = p->P;
-        P.kernel = kernel;
-        P.k = kernel == FFM_HELMHOLTZ ? k : 0.0;
+        P.dn = dn;
+        P.user_normals = dn ? o.target_normals : nullptr;
+        P.kernel = (kernel == FFM_HELMHOLTZ || kernel == FFM_HELMHOLTZ_DN) ? FFM_HELMHOLTZ : FFM_LAPLACE;
+        P.k = P.kernel == FFM_HELMHOLTZ ? k : 0.0;
         P.eps = eps;
         P.opt = o;
         P.nx = n_x;
@@ -190,6 +195,7 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         P.empty = (n_x == 0 || n_y == 0);
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         plan_build(P, X, Y, st);
+        P.user_normals = nullptr;
         FFM_HIP(hipEventCreateWithFlags(&P.ready, hipEventDisableTiming));
         FFM_HIP(hipEventRecord(P.ready, st));
         FFM_HIP(hipEventCreateWithFlags(&P.done, hipEventDisableTiming));

@@ -344,11 +344,10 @@ k_pw_transfer_lds(const LDesc *__restrict__ descs, const IoEntry *__restrict__, 
 // Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q) and
 // B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Item (desc, target box, first point);
 // BS points per block (64 for levels of small boxes).
-template <int BS, bool P64>
-__global__ void __launch_bounds__(BS)
-k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
-    const int4 wk = work[blockIdx.x];
-    const LDesc &d = descs[wk.x];
+// With DN (the normal derivative at the target), every direction's term is multiplied by ik (s . n_i): the pair
+// (q, -q) contributes ik (s_q . n) (e^{iP} v~(q) - e^{-iP} v~(-q)), with k s_q . n from the scaled directions.
+template <int BS, bool P64, bool DN>
+__device__ __forceinline__ void pw_backward_body(const LDesc &d, const int4 wk) {
     const int t = wk.y;
     const int tid = threadIdx.x;
     const int i = wk.z + tid;
@@ -356,10 +355,17 @@ k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     const int64_t npair = d.npair;
     typedef typename std::conditional<P64, double, float>::type real;
     real x = 0, y = 0, z = 0;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
     if (valid) {
         x = (real)(d.txs[i] - d.tctr[3 * t]);
         y = (real)(d.tys[i] - d.tctr[3 * t + 1]);
         z = (real)(d.tzs[i] - d.tctr[3 * t + 2]);
+        if (DN) {
+            const float4 n = d.tn[i];
+            nx = n.x;
+            ny = n.y;
+            nz = n.z;
+        }
     }
     float are = 0.f, aim = 0.f;
     __shared__ real sdx[BS], sdy[BS], sdz[BS];
@@ -377,7 +383,8 @@ k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
                 sdx[tid] = w.x; sdy[tid] = w.y; sdz[tid] = w.z;
             }
             const float4 w = vb[q];
-            ab[tid] = make_float4(w.x + w.z, w.y + w.w, w.x - w.z, w.y - w.w);
+            ab[tid] = DN ? make_float4(w.x - w.z, w.y - w.w, w.x + w.z, w.y + w.w)
+                         : make_float4(w.x + w.z, w.y + w.w, w.x - w.z, w.y - w.w);
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; ++jj) {
@@ -392,8 +399,16 @@ k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
             float sn, cs;
             sincos_rev(f, sn, cs);
             const float4 w = ab[jj];
-            are = fmaf(cs, w.x, fmaf(-sn, w.w, are));
-            aim = fmaf(cs, w.y, fmaf(sn, w.z, aim));
+            if (DN) {
+                // k (s . n) = 2 pi (s k / 2 pi) . n; X + iY = e^{iP} v~(q) - e^{-iP} v~(-q); adds i k (s . n) (X + iY)
+                const float D = 6.2831853f * fmaf((float)sdx[jj], nx, fmaf((float)sdy[jj], ny, (float)sdz[jj] * nz));
+                const float X = fmaf(cs, w.x, -sn * w.w), Y = fmaf(cs, w.y, sn * w.z);
+                are = fmaf(-D, Y, are);
+                aim = fmaf(D, X, aim);
+            } else {
+                are = fmaf(cs, w.x, fmaf(-sn, w.w, are));
+                aim = fmaf(cs, w.y, fmaf(sn, w.z, aim));
+            }
         }
     }
     if (valid) {
@@ -402,6 +417,20 @@ k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
         o.y += aim;
         d.v[i] = o;
     }
+}
+
+template <int BS, bool P64>
+__global__ void __launch_bounds__(BS)
+k_pw_backward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    pw_backward_body<BS, P64, false>(descs[wk.x], wk);
+}
+
+template <int BS, bool P64>
+__global__ void __launch_bounds__(BS)
+k_pw_backward_dn(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    pw_backward_body<BS, P64, true>(descs[wk.x], wk);
 }
 
 // ------------------------------------------------------------------ Gegenbauer levels, ring-pair form
@@ -1856,6 +1885,21 @@ __device__ __forceinline__ void lagrange_1d(float t, int r1, const float *nodes,
     }
 }
 
+// Their derivatives: l_a'(t) = inv_den_a sum_{m != a} prod_{b != a, m} (t - t_b).
+__device__ __forceinline__ void lagrange_1d_deriv(float t, int r1, const float *nodes, const float *inv_den, float *dell) {
+    for (int a = 0; a < r1; ++a) {
+        float sum = 0.f;
+        for (int m = 0; m < r1; ++m) {
+            if (m == a) continue;
+            float pr = 1.f;
+            for (int b = 0; b < r1; ++b)
+                if (b != a && b != m) pr *= (t - nodes[b]);
+            sum += pr;
+        }
+        dell[a] = sum * inv_den[a];
+    }
+}
+
 // u~_s = L_Y u_s: u~_s[(a r1 + b) r1 + c] = sum_j l_a(t_x) l_b(t_y) l_c(t_z) u_j, t = 2 (y - c_s) / d_l.
 // Item (desc, source box).
 __global__ void __launch_bounds__(kThreads)
@@ -2007,9 +2051,10 @@ k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
 
 // Transfer of one class group through the ACA factors of its class (Sec. 2.2.2, eq. ffmACAmatvec): Z_e =
 // A_c (B_c^T u~_{s(e)}) for up to 16 pairs e, two products on MFMA with the operand layouts of k_lag_mfma.
-// Phase 1: Y (kp x 32) = B_c^T (kp x rp) U (rp x 32), one 32-row tile of the class's padded rank kp per wave
-// (the planner keeps kp <= 32 x waves); phase 2, once every wave has read U: Y is written over U in LDS and
-// C (rp x 32) = A_c (rp x kp) Y.  Complex factors are two planes, and the complex products are formed from the
+// Phase 1: Y (kp x 32) = B_c^T (kp x rp) U (rp x 32): the class's padded rank kp is at most one 32-row tile per
+// wave (the planner keeps kp <= 32 x waves), and each tile's K steps are split over the waves left, their
+// partial tiles added in LDS in a fixed order; phase 2, once every wave has read U: Y is written over U in LDS
+// and C (rp x 32) = A_c (rp x kp) Y.  Complex factors are two planes, and the complex products are formed from the
 // real and imaginary columns as in k_lag_mfma.  Item (desc, group).
 __global__ void __launch_bounds__(256)
 k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
@@ -2040,13 +2085,18 @@ k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
     __syncthreads();
     const int planes = helm ? 2 : 1;
     const int col = lane & 31, kh = lane >> 5;
-    // phase 1: B^T U, rank tile mt = wv
+    // phase 1: B^T U.  The kp / 32 rank tiles times nparts ranges of the K steps go to the waves (every wave
+    // busy when kp is one or two tiles); each range is a multiple of four steps, the last takes the rest
+    const int ntile = kp / 32, nparts = nwv / ntile, steps = rp / 2;
+    const int mt1 = wv % ntile, part = wv / ntile;
+    const bool active = part < nparts;
+    const int chunk = (steps / nparts) / 4 * 4;
+    const int k0 = part * chunk, k1 = part == nparts - 1 ? steps : k0 + chunk;
     floatx16 y;
-    const bool has_tile = wv * 32 < kp;
-    if (has_tile) {
+    if (active) {
         const float *Bre = d.acaB + (int64_t)c * planes * rp * kpm;
         const float *Bim = Bre + (int64_t)rp * kpm;
-        const gcf BreG = gfl(Bre) + wv * 32 + col, BimG = gfl(Bim) + wv * 32 + col;
+        const gcf BreG = gfl(Bre) + mt1 * 32 + col, BimG = gfl(Bim) + mt1 * 32 + col;
         floatx16 acc1, acc2;
         for (int v = 0; v < 16; ++v) {
             acc1[v] = 0.f;
@@ -2062,8 +2112,8 @@ k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
                 if (helm) a2n[u] = BimG[(int64_t)k * kpm];
             }
         };
-        load(0);
-        for (int kk0 = 0; kk0 < rp / 2; kk0 += 4) {
+        load(k0);
+        for (int kk0 = k0; kk0 < k1; kk0 += 4) {
             float bv[4], a1[4], a2[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -2071,7 +2121,7 @@ k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
                 a1[u] = a1n[u];
                 a2[u] = a2n[u];
             }
-            if (kk0 + 4 < rp / 2) load(kk0 + 4);
+            if (kk0 + 4 < k1) load(kk0 + 4);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -2088,9 +2138,22 @@ k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
             y[v] = val;
         }
     }
-    __syncthreads();              // every wave is done with U
-    if (has_tile)
-        for (int v = 0; v < 16; ++v) U[(wv * 32 + 8 * (v >> 2) + 4 * kh + (v & 3)) * 32 + col] = y[v];
+    __syncthreads();              // every wave is done with U: its space holds the partial tiles, then Y
+    if (active)
+        for (int v = 0; v < 16; ++v)
+            U[(part * ntile + mt1) * 1024 + (8 * (v >> 2) + 4 * kh + (v & 3)) * 32 + col] = y[v];
+    __syncthreads();
+    float ys[16];                 // kp x 32 entries of Y, at most 16 per thread; partial tiles added in order
+    int ny = 0;
+    for (int e = tid; e < kp * 32; e += blockDim.x, ++ny) {
+        const int tile = e >> 10, within = e & 1023;
+        float acc = 0.f;
+        for (int q = 0; q < nparts; ++q) acc += U[(q * ntile + tile) * 1024 + within];
+        ys[ny] = acc;
+    }
+    __syncthreads();
+    ny = 0;
+    for (int e = tid; e < kp * 32; e += blockDim.x, ++ny) U[e] = ys[ny];
     __syncthreads();
     // phase 2: A Y
     const float *Are = d.acaA + (int64_t)c * planes * kpm * rp;
@@ -2235,14 +2298,10 @@ k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     }
 }
 
-// v_i += L_X^T v~_t with v~_t = sum_{e in far(t)} Z_e (fixed order), t = 2 (x - c_t) / d_l.
-// Item (desc, target box).
-__global__ void __launch_bounds__(kThreads)
-k_lag_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+template <bool DN>
+__device__ __forceinline__ void lag_interp_body(const LDesc &d, const int4 wk) {
     extern __shared__ float2 vt[];   // [r]
     __shared__ float nodes[kMaxR1], den[kMaxR1];
-    const int4 wk = work[blockIdx.x];
-    const LDesc &d = descs[wk.x];
     const int t = wk.y;
     const int tid = threadIdx.x;
     const int r1 = d.r1, rp = d.rp, r = r1 * r1 * r1;
@@ -2265,30 +2324,77 @@ k_lag_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
     for (int i = d.tstart[t] + tid; i < d.tstart[t + 1]; i += kThreads) {
         float lx[kMaxR1], ly[kMaxR1], lz[kMaxR1];
-        lagrange_1d((float)((d.txs[i] - cx) * two_over_dl), r1, nodes, den, lx);
-        lagrange_1d((float)((d.tys[i] - cy) * two_over_dl), r1, nodes, den, ly);
-        lagrange_1d((float)((d.tzs[i] - cz) * two_over_dl), r1, nodes, den, lz);
+        const float tx = (float)((d.txs[i] - cx) * two_over_dl), ty = (float)((d.tys[i] - cy) * two_over_dl);
+        const float tz = (float)((d.tzs[i] - cz) * two_over_dl);
+        lagrange_1d(tx, r1, nodes, den, lx);
+        lagrange_1d(ty, r1, nodes, den, ly);
+        lagrange_1d(tz, r1, nodes, den, lz);
         float sre = 0.f, sim = 0.f;
-        for (int a = 0; a < r1; ++a) {
-            float bre = 0.f, bim = 0.f;
-            for (int bb = 0; bb < r1; ++bb) {
-                float cre = 0.f, cim = 0.f;
-                const float2 *row = vt + (a * r1 + bb) * r1;
-                for (int c = 0; c < r1; ++c) {
-                    cre = fmaf(lz[c], row[c].x, cre);
-                    cim = fmaf(lz[c], row[c].y, cim);
+        if (DN) {
+            // n . grad of the interpolant: (2 / d_l) (n_x l'_a l_b l_c + n_y l_a l'_b l_c + n_z l_a l_b l'_c) v~
+            float dx[kMaxR1], dy[kMaxR1], dz[kMaxR1];
+            lagrange_1d_deriv(tx, r1, nodes, den, dx);
+            lagrange_1d_deriv(ty, r1, nodes, den, dy);
+            lagrange_1d_deriv(tz, r1, nodes, den, dz);
+            const float4 n = d.tn[i];
+            for (int a = 0; a < r1; ++a) {
+                float b0r = 0.f, b0i = 0.f, b1r = 0.f, b1i = 0.f;
+                for (int bb = 0; bb < r1; ++bb) {
+                    float c0r = 0.f, c0i = 0.f, c1r = 0.f, c1i = 0.f;
+                    const float2 *row = vt + (a * r1 + bb) * r1;
+                    for (int c = 0; c < r1; ++c) {
+                        c0r = fmaf(lz[c], row[c].x, c0r);
+                        c0i = fmaf(lz[c], row[c].y, c0i);
+                        c1r = fmaf(dz[c], row[c].x, c1r);
+                        c1i = fmaf(dz[c], row[c].y, c1i);
+                    }
+                    b0r = fmaf(ly[bb], c0r, b0r);      // l_b l_c
+                    b0i = fmaf(ly[bb], c0i, b0i);
+                    b1r = fmaf(n.y * dy[bb], c0r, fmaf(n.z * ly[bb], c1r, b1r));   // n_y l'_b l_c + n_z l_b l'_c
+                    b1i = fmaf(n.y * dy[bb], c0i, fmaf(n.z * ly[bb], c1i, b1i));
                 }
-                bre = fmaf(ly[bb], cre, bre);
-                bim = fmaf(ly[bb], cim, bim);
+                sre = fmaf(n.x * dx[a], b0r, fmaf(lx[a], b1r, sre));
+                sim = fmaf(n.x * dx[a], b0i, fmaf(lx[a], b1i, sim));
             }
-            sre = fmaf(lx[a], bre, sre);
-            sim = fmaf(lx[a], bim, sim);
+            const float f = (float)two_over_dl;
+            sre *= f;
+            sim *= f;
+        } else {
+            for (int a = 0; a < r1; ++a) {
+                float bre = 0.f, bim = 0.f;
+                for (int bb = 0; bb < r1; ++bb) {
+                    float cre = 0.f, cim = 0.f;
+                    const float2 *row = vt + (a * r1 + bb) * r1;
+                    for (int c = 0; c < r1; ++c) {
+                        cre = fmaf(lz[c], row[c].x, cre);
+                        cim = fmaf(lz[c], row[c].y, cim);
+                    }
+                    bre = fmaf(ly[bb], cre, bre);
+                    bim = fmaf(ly[bb], cim, bim);
+                }
+                sre = fmaf(lx[a], bre, sre);
+                sim = fmaf(lx[a], bim, sim);
+            }
         }
         float2 o = d.v[i];
         o.x += sre;
         o.y += sim;
         d.v[i] = o;
     }
+}
+
+// v_i += L_X^T v~_t (or its normal derivative at x_i, k_lag_interp_dn) with v~_t = sum_{e in far(t)} Z_e (fixed
+// order), t = 2 (x - c_t) / d_l.  Item (desc, target box).
+__global__ void __launch_bounds__(kThreads)
+k_lag_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    lag_interp_body<false>(descs[wk.x], wk);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_lag_interp_dn(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    lag_interp_body<true>(descs[wk.x], wk);
 }
 
 // ------------------------------------------------------------------ near field (leaf)
@@ -2298,11 +2404,8 @@ k_lag_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 // Targets go through the lanes in passes of at most 64; a pass of nt targets gives each target R = 64 / nt
 // lanes, lane r of a target taking the staged sources r, r + R, ... (the chunk is padded with zero sources to
 // a multiple of R), and the R partial sums of a target are added in order of r.  Item (desc, target box).
-template <bool HELM>
-__global__ void __launch_bounds__(64)
-k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
-    const int4 wk = work[blockIdx.x];
-    const LDesc &d = descs[wk.x];
+template <bool HELM, bool DN>
+__device__ __forceinline__ void near_body(const LDesc &d, const int4 wk) {
     const int t = wk.y;
     const int lane = threadIdx.x;
     const float k_rev = d.k_rev;
@@ -2323,10 +2426,17 @@ k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 
         const bool valid = r < R;
         const int i = i0 + ti;
         double x = 0.0, y = 0.0, z = 0.0;
+        float nx = 0.f, ny = 0.f, nz = 0.f;
         if (valid) {
             x = d.txs[i] - cx;
             y = d.tys[i] - cy;
             z = d.tzs[i] - cz;
+            if (DN) {
+                const float4 n = d.tn[i];
+                nx = n.x;
+                ny = n.y;
+                nz = n.z;
+            }
         }
         float are = 0.f, aim = 0.f;
         auto pair = [&](int jj) {
@@ -2334,7 +2444,22 @@ k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 
             const float2 uu = su[jj];
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-            if (HELM) {
+            if (DN) {
+                // n . grad_x G: (n . d) G'(r) / r with G' = -1 / r^2 (Laplace), (ikr - 1) e^{ikr} / r^2 (Helmholtz)
+                const float i3 = inv * inv * inv * fmaf(nx, dx, fmaf(ny, dy, nz * dz));
+                if (HELM) {
+                    const float ph = r2 * inv * k_rev;
+                    float sn, cs;
+                    sincos_rev(__builtin_amdgcn_fractf(ph), sn, cs);
+                    const float kr = 6.2831853f * ph;
+                    const float gr = i3 * fmaf(-kr, sn, -cs), gi = i3 * fmaf(kr, cs, -sn);
+                    are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
+                    aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
+                } else {
+                    are = fmaf(-i3, uu.x, are);
+                    aim = fmaf(-i3, uu.y, aim);
+                }
+            } else if (HELM) {
                 const float ph = r2 * inv * k_rev;
                 float sn, cs;
                 sincos_rev(__builtin_amdgcn_fractf(ph), sn, cs);
@@ -2393,6 +2518,21 @@ k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 
     }
 }
 
+template <bool HELM>
+__global__ void __launch_bounds__(64)
+k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    near_body<HELM, false>(descs[wk.x], wk);
+}
+
+// The normal derivative at the target (the adjoint double-layer kernel), same blocks and lanes.
+template <bool HELM>
+__global__ void __launch_bounds__(64)
+k_near_dn(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    near_body<HELM, true>(descs[wk.x], wk);
+}
+
 typedef void (*KernelFn)(const LDesc *, const IoEntry *, const int4 *);
 
 KernelFn kernel_of(const Stage &S, int &threads) {
@@ -2445,6 +2585,14 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_ACA: threads = 64 * std::max(1, S.a); return k_lag_aca;
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
+        case K_NEAR_DN: threads = 64; return S.b ? k_near_dn<true> : k_near_dn<false>;
+        case K_INTERP_DN: return k_lag_interp_dn;
+        case K_BWD_PAIR_DN:
+            if (S.a == 100) {
+                threads = 64;
+                return S.b ? k_pw_backward_dn<64, true> : k_pw_backward_dn<64, false>;
+            }
+            return S.b ? k_pw_backward_dn<kThreads, true> : k_pw_backward_dn<kThreads, false>;
         case K_ZERO_OUT: return k_zero_io;
         case K_GSPREAD:
             switch (S.a) {
@@ -2610,6 +2758,9 @@ std::string kernel_name(int kern, int a, int b) {
         case K_ACA: return "k_lag_aca";
         case K_INTERP: return "k_lag_interp";
         case K_NEAR: return "k_near<" + tf(b) + ">";
+        case K_NEAR_DN: return "k_near_dn<" + tf(b) + ">";
+        case K_INTERP_DN: return "k_lag_interp_dn";
+        case K_BWD_PAIR_DN: return "k_pw_backward_dn<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
         case K_ZERO_OUT: return "k_zero_io";
         case K_GSPREAD: return a >= 4 && a <= 8 ? "k_grid_spread<" + std::to_string(a) + ">" : "";
         case K_GZ: return "k_grid_z";

@@ -43,10 +43,10 @@ int stage_role(const Stage &S) {
         case K_SUM: case K_GZ: return 1;
         case K_GPHI: return 2;
         case K_TRANSFER: case K_MFMA32: case K_MFMA16: case K_ACA: return 3;
-        case K_BWD_PAIR: case K_BWD_RING: case K_INTERP: case K_GPHIT: return 4;
+        case K_BWD_PAIR: case K_BWD_RING: case K_INTERP: case K_GPHIT: case K_BWD_PAIR_DN: case K_INTERP_DN: return 4;
         case K_BSUM: case K_GZT: return 5;
         case K_GINTERP: return 6;
-        case K_NEAR: case K_ZERO_OUT: return 0;
+        case K_NEAR: case K_NEAR_DN: case K_ZERO_OUT: return 0;
         case K_PERM_OUT: return 1;
         default: throw Error(FFM_EINTERNAL, "stage without a batch order");
     }

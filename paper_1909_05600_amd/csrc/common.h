@@ -220,6 +220,7 @@ struct LDesc {
     // Lagrange level
     const float *T, *lnodes, *lden;
     const _Float16 *T16;
+    const float4 *tn;                      // target normals in sorted order (normal-derivative kernels), or null
     const float *acaA, *acaB;              // ACA factors: A [class][plane][kpm][rp], B^T [class][plane][rp][kpm]
     const int32_t *acaKp;                  // [class] rank padded to 32
     int kpm;                               // largest padded rank
@@ -245,7 +246,7 @@ struct LDesc {
 enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
     K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
-    K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA
+    K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA, K_NEAR_DN, K_BWD_PAIR_DN, K_INTERP_DN
 };
 
 struct Stage {
@@ -349,7 +350,10 @@ struct Level {
 };
 
 struct Plan {
-    int kernel = 0;
+    int kernel = 0;                      // FFM_LAPLACE or FFM_HELMHOLTZ (the base kernel)
+    bool dn = false;                     // normal derivative at the targets (adjoint double layer)
+    const double *user_normals = nullptr;   // the caller's target normals, read while the plan is built
+    DevBuf<float4> tnrm;                 // target normals in sorted order (FP32)
     double k = 0, eps = 0;
     ffm_options_t opt{};
     bool empty = false;

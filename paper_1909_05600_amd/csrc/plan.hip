@@ -128,6 +128,15 @@ k_gather(const double *P, int64_t n, const int32_t *perm, double *xs, double *ys
     zs[i] = P[3 * j + 2];
 }
 
+// Target normals in sorted order, FP32 (the normal-derivative kernels); w unused.
+__global__ void __launch_bounds__(kThreads)
+k_gather_normals(const double *N, int64_t n, const int32_t *perm, float4 *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    out[i] = make_float4((float)N[3 * j], (float)N[3 * j + 1], (float)N[3 * j + 2], 0.f);
+}
+
 // First level at which point i starts a box: boxes of level l are the runs of key >> 3(21 - l).
 // 22 = never (equal keys).  Also a histogram of those levels (block-local, then one add per bin).
 __global__ void __launch_bounds__(kThreads)
@@ -1150,6 +1159,11 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     Scratch SC(st);
     P.tx.reset(new Tree());
     build_tree(*P.tx, X, nx, corner[0], P.S, st, SC);
+    if (P.dn) {
+        // read before the plan's next host wait, so the caller may free the normals when ffm_plan returns
+        P.tnrm.alloc(nx);
+        FFM_LAUNCH(k_gather_normals, nblocks(nx), kThreads, 0, st, P.user_normals, nx, P.tx->perm.p, P.tnrm.p);
+    }
     if (P.same) {
         P.ty = P.tx.get();
     } else {
@@ -1358,7 +1372,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
                 const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
                 const bool force_direct = (P.opt.flags & FFM_FLAG_DIRECT_TRANSFORMS) != 0;
-                LV.grid = have && !force_direct && L >= 8 && gbytes <= ((size_t)24 << 30) && (force_grid || gridc < direct);
+                LV.grid = have && !force_direct && !P.dn && L >= 8 && gbytes <= ((size_t)24 << 30) &&
+                          (force_grid || gridc < direct);
                 if (LV.grid) {
                     P.any_grid = true;
                     LV.gw = w;
@@ -1894,7 +1909,10 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             const int L = LV.L;
             LV.qG = L >= 64 ? tu.ring_g : (L >= 32 ? 2 : 0);
             if (LV.qG && (L + LV.qG - 1) / LV.qG > kThreads) LV.qG = 4;   // one ring must fit one block
-            LV.bwd_tile = LV.qG ? kThreads * tu.bwd_pt : kThreads;
+            // the normal derivative at the targets multiplies every direction by its own ik (s . n): the target
+            // transform runs in the direction-pair form
+            const bool ring_bwd = LV.qG && !P.dn;
+            LV.bwd_tile = ring_bwd ? kThreads * tu.bwd_pt : kThreads;
             std::vector<int4> fw;
             if (LV.qG) {
                 // ring-pair form; split each box's points into segments when boxes are too few to fill the chip
@@ -1931,22 +1949,23 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             std::vector<int4> bw;
             LV.stages.push_back(transfer_stage(l, LV, tg, s2, st, SC));
             // direction-pair target transform: 64-point blocks where target boxes are small
-            const bool small = !LV.qG && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
+            const bool small = !ring_bwd && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
             if (small) LV.bwd_tile = 64;
             int64_t tiles = 0;
             for (int32_t t : LV.h_tgt) tiles += (sx[t + 1] - sx[t] + LV.bwd_tile - 1) / LV.bwd_tile;
             // ring parts of the target transform: enough blocks for several rounds of the chip
-            LV.bSplit = LV.qG ? choose_split(tiles, conc_bwd[tu.bwd_pt == 2][LV.phase64], 8, LV.nrp) : 1;
+            LV.bSplit = ring_bwd ? choose_split(tiles, conc_bwd[tu.bwd_pt == 2][LV.phase64], 8, LV.nrp) : 1;
             if (LV.bSplit > 1) ws_bpart = std::max(ws_bpart, (size_t)LV.bSplit * P.nx);
             bw.reserve((size_t)(tiles * LV.bSplit));
             for (int g = 0; g < LV.bSplit; ++g)
                 for (int32_t t : LV.h_tgt)
                     for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) bw.push_back(make_int4(l, t, i, g));
-            if (LV.qG)
+            if (ring_bwd)
                 LV.stages.push_back(make_stage(K_BWD_RING, tu.bwd_pt, LV.phase64, LV.bSplit > 1 ? -1 : s3, l, 0,
                                                std::move(bw), st, SC));
             else
-                LV.stages.push_back(make_stage(K_BWD_PAIR, small ? 100 : 0, LV.phase64, s3, l, 0, std::move(bw), st, SC));
+                LV.stages.push_back(make_stage(P.dn ? K_BWD_PAIR_DN : K_BWD_PAIR, small ? 100 : 0, LV.phase64, s3, l, 0,
+                                               std::move(bw), st, SC));
             if (LV.bSplit > 1) {
                 std::vector<int4> bs;
                 for (int32_t t : LV.h_tgt)
@@ -1976,7 +1995,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             else
                 LV.stages.push_back(make_stage(LV.fp16 ? K_MFMA16 : K_MFMA32, LV.fp16 ? 1 : std::min(4, LV.rp / 32), 0,
                                                s2, l, (size_t)LV.rp * 32 * (LV.fp16 ? 2 : 4), std::move(mf), st, SC));
-            LV.stages.push_back(make_stage(K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r, std::move(ip), st, SC));
+            LV.stages.push_back(make_stage(P.dn ? K_INTERP_DN : K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r,
+                                           std::move(ip), st, SC));
         }
     }
     plog.mark("lev");
@@ -1987,7 +2007,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         std::vector<int4> nr, po;
         for (int32_t t : LL.h_near) nr.push_back(make_int4(P.leaf, t, 0, 0));
         for (int64_t i = 0; i < P.nx; i += kThreads) po.push_back(make_int4(0, (int)i, 0, 0));
-        P.post.push_back(make_stage(K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, 61, P.leaf, 0, std::move(nr), st, SC));
+        P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, 61, P.leaf, 0,
+                                    std::move(nr), st, SC));
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
     }
     // timing slot of every stage: a stage that closes no phase belongs to the next one that does
@@ -2067,6 +2088,7 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.lnodes = LV.lnodes.p;
     d.lden = LV.lden.p;
     d.T16 = LV.T16.p;
+    d.tn = P.tnrm.p;
     d.acaA = LV.acaA.p;
     d.acaB = LV.acaB.p;
     d.acaKp = LV.acaKp.p;
