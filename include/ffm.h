@@ -93,6 +93,11 @@ typedef struct {
  * the transfer work; FFM_FLAG_NO_ACA never uses it, FFM_FLAG_ACA uses it at every FP32 Lagrange level. */
 #define FFM_FLAG_NO_ACA 8u
 #define FFM_FLAG_ACA    16u
+/* options.flags: per-pair leaf rule (beyond the global stopping rule of Sec. 2.2.4): a near pair whose two boxes
+ * both hold at most n_leaf points is summed densely at its level instead of being refined, and a level where
+ * no near pair is left to refine is the leaf.  For clouds of uneven density (a dense cluster beside a sparse
+ * surface) the sparse regions stop descending early. */
+#define FFM_FLAG_ADAPTIVE_LEAVES 32u
 
 /*
  * ffm_plan -- build the two octrees, the descent lists and the transfer
@@ -214,6 +219,7 @@ typedef struct {
                                               wave along one axis, relative, for every direction, else 0 */
     int32_t aca[FFM_MAX_LEVELS];           /* 1 if the level's transfers use the ACA factors                 */
     double  aca_rank[FFM_MAX_LEVELS];      /* mean ACA rank over the level's classes where it was evaluated  */
+    int64_t nearly[FFM_MAX_LEVELS];        /* near pairs the per-pair leaf rule sums densely at level l      */
 } ffm_stats_t;
 
 /* ffm_plan_stats -- copy the plan's sizes and work counters to host memory.
@@ -236,10 +242,11 @@ ffm_status_t ffm_plan_stats(ffm_plan_t plan, ffm_stats_t *out);
  *   FFM_EXPORT_FAR       int64   [nfar][5] (t, s, ox, oy, oz) sorted by (t, s) (l)
  *   FFM_EXPORT_NEAR      int64   [nnear][2] (t, s) sorted by (t, s) (l)
  *   FFM_EXPORT_ACA_RANK  int64   [ncls][4] (ox, oy, oz, rank) of an ACA level l (count 0 elsewhere)
+ *   FFM_EXPORT_EARLY     int64   [nearly][2] (t, s) the per-pair leaf rule sums at level l, sorted by (t, s)
  */
 typedef enum {
     FFM_EXPORT_KEYS = 0, FFM_EXPORT_PERM = 1, FFM_EXPORT_BOX_START = 2, FFM_EXPORT_BOX_IJK = 3,
-    FFM_EXPORT_BOX_CTR = 4, FFM_EXPORT_FAR = 5, FFM_EXPORT_NEAR = 6, FFM_EXPORT_ACA_RANK = 7
+    FFM_EXPORT_BOX_CTR = 4, FFM_EXPORT_FAR = 5, FFM_EXPORT_NEAR = 6, FFM_EXPORT_ACA_RANK = 7, FFM_EXPORT_EARLY = 8
 } ffm_export_t;
 
 ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t level,

@@ -72,6 +72,8 @@ def lib():
             "orc_far": (None, [P, C.c_int, P, P, P]),
             "orc_nnear": (i64, [P, C.c_int]),
             "orc_near": (None, [P, C.c_int, P, P]),
+            "orc_nearly": (i64, [P, C.c_int]),
+            "orc_early": (None, [P, C.c_int, P, P]),
             "orc_level_method": (C.c_int, [P, C.c_int]),
             "orc_level_order": (C.c_int, [P, C.c_int]),
             "orc_grid_forward": (None, [C.c_int, C.c_int, dbl, dbl, dbl, C.c_int, P, P, i64, P]),
@@ -101,7 +103,7 @@ class _Options(C.Structure):
     _fields_ = [("n_leaf", C.c_int32), ("kappa", C.c_double), ("r1_override", C.c_int32),
                 ("max_level", C.c_int32), ("grid_p", C.c_int32 * MAX_LEVELS), ("grid_w", C.c_int32 * MAX_LEVELS),
                 ("grid_beta", C.c_double * MAX_LEVELS), ("aca_tol", C.c_double), ("aca", C.c_int32 * MAX_LEVELS),
-                ("target_normals", C.c_void_p)]
+                ("target_normals", C.c_void_p), ("adaptive", C.c_int32)]
 
 
 def _ptr(a: np.ndarray):
@@ -242,7 +244,7 @@ class Plan:
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 64,
                  kappa: float = 0.0, r1: int = 0, max_level: int = 20, grid: dict | None = None,
-                 aca=(), aca_tol: float = 0.0, normals=None):
+                 aca=(), aca_tol: float = 0.0, normals=None, adaptive: bool = False):
         self.X = _coords(X)
         self.Y = self.X if Y is X else _coords(Y)
         self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
@@ -254,6 +256,7 @@ class Plan:
         opt.aca_tol = float(aca_tol)
         for l in aca:
             opt.aca[int(l)] = 1
+        opt.adaptive = 1 if adaptive else 0
         if int(kernel) >= 2:
             if normals is None:
                 raise ValueError("normal-derivative kernels need the target normals")
@@ -334,6 +337,15 @@ class Plan:
         s = np.zeros(n, dtype=np.int64)
         if n:
             lib().orc_near(self._h, l, _ptr(t), _ptr(s))
+        return t, s
+
+    def early(self, l: int):
+        """Near pairs of level l that the per-pair leaf rule sums densely at that level: (t, s) sorted."""
+        n = lib().orc_nearly(self._h, l)
+        t = np.zeros(n, dtype=np.int64)
+        s = np.zeros(n, dtype=np.int64)
+        if n:
+            lib().orc_early(self._h, l, _ptr(t), _ptr(s))
         return t, s
 
     def method(self, l: int) -> int:

@@ -598,6 +598,7 @@ struct orc_plan {
     int leaf;
     pairs_t far[BITS + 1];
     pairs_t near[BITS + 1];
+    pairs_t early[BITS + 1];   /* per-pair leaf rule: near pairs of small boxes summed densely at level l */
     int method[BITS + 1];      /* 0 none, 1 Lagrange, 2 Gegenbauer */
     int order[BITS + 1];       /* r1 or L                          */
 };
@@ -781,6 +782,7 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
     p->opt.r1_override = opt ? opt->r1_override : 0;
     p->opt.max_level = (opt && opt->max_level > 0 && opt->max_level <= 20) ? opt->max_level : 20;
     p->opt.aca_tol = opt ? opt->aca_tol : 0.0;
+    p->opt.adaptive = opt ? opt->adaptive : 0;
     if (opt)
         for (int l = 0; l < ORC_MAX_LEVELS; ++l) {
             p->opt.aca[l] = opt->aca[l];
@@ -873,9 +875,37 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
         free(vn);
         /* Stopping rule (Sec. 2.2.4; reading R4). */
         int64_t nb = p->T[0].nbox[l] + p->T[1].nbox[l];
-        if (nn == 0 || nx + ny <= (int64_t)p->opt.n_leaf * nb) {
+        if (nn == 0 || nx + ny <= (int64_t)p->opt.n_leaf * nb || l == maxlev) {
             p->leaf = l;
             break;
+        }
+        /* Per-pair leaf rule (reading R22, beyond the paper's global rule): a near pair whose two boxes both hold
+         * at most n_leaf points is not refined but summed densely at this level; the level is the leaf if no
+         * near pair is left to refine. */
+        if (p->opt.adaptive) {
+            const pairs_t *N = &p->near[l];
+            pr_t *ve = malloc(sizeof(pr_t) * (size_t)(N->n + 1)), *vr = malloc(sizeof(pr_t) * (size_t)(N->n + 1));
+            int64_t ne = 0, nr = 0;
+            for (int64_t i = 0; i < N->n; ++i) {
+                const int64_t t = N->t[i], sb = N->s[i];
+                const int64_t cx = TX->start[l][t + 1] - TX->start[l][t], cy = TY->start[l][sb + 1] - TY->start[l][sb];
+                pr_t *dst = (cx <= p->opt.n_leaf && cy <= p->opt.n_leaf) ? &ve[ne++] : &vr[nr++];
+                dst->t = t;
+                dst->s = sb;
+            }
+            if (nr == 0) {
+                free(ve);
+                free(vr);
+                p->leaf = l;
+                break;
+            }
+            free(p->near[l].t);
+            free(p->near[l].s);
+            free(p->near[l].off);
+            pairs_set(&p->near[l], vr, nr, 0);
+            pairs_set(&p->early[l], ve, ne, 0);
+            free(ve);
+            free(vr);
         }
     }
     /* Compression form per level (Sec. 2.2.2-2.2.3; readings R5-R7). */
@@ -909,6 +939,8 @@ void orc_plan_free(orc_plan *p)
             free(p->far[l].off);
             free(p->near[l].t);
             free(p->near[l].s);
+            free(p->early[l].t);
+            free(p->early[l].s);
         }
     }
     free(p);
@@ -1269,12 +1301,22 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     free(w);
 }
 
-/* Dense remainder at the leaf (Sec. 2.2.4). */
+/* Dense remainder (Sec. 2.2.4): the near pairs of the leaf, and those the per-pair rule stopped earlier
+ * (level l < leaf, list early). */
+static void near_pairs_sum(const orc_plan *p, int l, const pairs_t *N, const double complex *u, double complex *v,
+                           int64_t stride);
+
 static void near_field(const orc_plan *p, const double complex *u, double complex *v, int64_t stride)
 {
+    for (int l = 1; l < p->leaf; ++l)
+        if (p->early[l].n) near_pairs_sum(p, l, &p->early[l], u, v, stride);
+    near_pairs_sum(p, p->leaf, &p->near[p->leaf], u, v, stride);
+}
+
+static void near_pairs_sum(const orc_plan *p, int l, const pairs_t *N, const double complex *u, double complex *v,
+                           int64_t stride)
+{
     const tree_t *TX = &p->T[0], *TY = &p->T[1];
-    int l = p->leaf;
-    const pairs_t *N = &p->near[l];
     int64_t nbx = TX->nbox[l];
     int64_t *ptr = pairs_by_target(N, nbx);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1371,6 +1413,12 @@ void orc_far(const orc_plan *p, int l, int64_t *t, int64_t *s, int32_t *off)
     memcpy(t, F->t, sizeof(int64_t) * (size_t)F->n);
     memcpy(s, F->s, sizeof(int64_t) * (size_t)F->n);
     memcpy(off, F->off, sizeof(int32_t) * 3 * (size_t)F->n);
+}
+int64_t orc_nearly(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->early[l].n; }
+void orc_early(const orc_plan *p, int l, int64_t *t, int64_t *s)
+{
+    memcpy(t, p->early[l].t, sizeof(int64_t) * p->early[l].n);
+    memcpy(s, p->early[l].s, sizeof(int64_t) * p->early[l].n);
 }
 int64_t orc_nnear(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->near[l].n; }
 void orc_near(const orc_plan *p, int l, int64_t *t, int64_t *s)

@@ -99,6 +99,9 @@ typedef struct {
     int32_t aca[ORC_MAX_LEVELS];
     /* ORC_*_DN kernels: unit normals at the targets, n_x x 3, user order (copied at plan creation) */
     const double *target_normals;
+    /* per-pair leaf rule (reading R22): near pairs whose boxes both hold <= n_leaf points are summed densely at
+     * their level instead of refined */
+    int32_t adaptive;
 } orc_options;
 
 orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t ny,
@@ -127,6 +130,8 @@ int64_t orc_nfar(const orc_plan *p, int l);
 void    orc_far(const orc_plan *p, int l, int64_t *t, int64_t *s, int32_t *off); /* off: nfar x 3 */
 int64_t orc_nnear(const orc_plan *p, int l);                        /* near_l (valid l <= leaf) */
 void    orc_near(const orc_plan *p, int l, int64_t *t, int64_t *s);
+int64_t orc_nearly(const orc_plan *p, int l);                       /* pairs the per-pair rule stopped at l */
+void    orc_early(const orc_plan *p, int l, int64_t *t, int64_t *s);
 int     orc_level_method(const orc_plan *p, int l);                 /* 0 none, 1 Lagrange, 2 Gegenbauer */
 int     orc_level_order(const orc_plan *p, int l);                  /* r1 or L                   */
 /* ACA ranks of the transfer matrices of Lagrange level l at tolerance tol: one per translation class, with

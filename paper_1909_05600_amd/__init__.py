@@ -20,7 +20,7 @@ FFM_HELMHOLTZ_DN = 3
 FFM_C64, FFM_F32, FFM_F64, FFM_C128 = 0, 1, 2, 3
 FFM_PREC_FP32, FFM_PREC_MIXED = 0, 1
 FFM_EXPORT_KEYS, FFM_EXPORT_PERM, FFM_EXPORT_BOX_START, FFM_EXPORT_BOX_IJK = 0, 1, 2, 3
-FFM_EXPORT_BOX_CTR, FFM_EXPORT_FAR, FFM_EXPORT_NEAR, FFM_EXPORT_ACA_RANK = 4, 5, 6, 7
+FFM_EXPORT_BOX_CTR, FFM_EXPORT_FAR, FFM_EXPORT_NEAR, FFM_EXPORT_ACA_RANK, FFM_EXPORT_EARLY = 4, 5, 6, 7, 8
 MAX_LEVELS = 21
 
 STATUS = {0: "FFM_OK", -1: "FFM_EINVAL", -2: "FFM_ENOMEM", -3: "FFM_EDEVICE", -4: "FFM_EBUSY", -5: "FFM_EINTERNAL"}
@@ -38,6 +38,7 @@ FFM_FLAG_DIRECT_TRANSFORMS = 2
 FFM_FLAG_GRID_TRANSFORMS = 4
 FFM_FLAG_NO_ACA = 8
 FFM_FLAG_ACA = 16
+FFM_FLAG_ADAPTIVE_LEAVES = 32
 FFM_BATCH_GRAPH = 1
 FFM_BATCH_AUTOTUNE = 2
 TIMING_SLOTS = 64
@@ -69,7 +70,8 @@ class Stats(C.Structure):
                 ("transfer_macs", C.c_double), ("near_pairs", C.c_double), ("plan_bytes", C.c_double),
                 ("workspace_bytes", C.c_double), ("grid_nodes", C.c_int32 * _L), ("fwd_boxes", C.c_int64 * _L),
                 ("bwd_boxes", C.c_int64 * _L), ("grid_width", C.c_int32 * _L), ("grid_beta", C.c_double * _L),
-                ("grid_alias", C.c_double * _L), ("aca", C.c_int32 * _L), ("aca_rank", C.c_double * _L)]
+                ("grid_alias", C.c_double * _L), ("aca", C.c_int32 * _L), ("aca_rank", C.c_double * _L),
+                ("nearly", C.c_int64 * _L)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -242,7 +244,7 @@ class Plan:
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 0, precision: int = 0,
                  kd_switch: float = 0.0, r1_override: int = 0, max_level: int = 0, timing: bool = False,
-                 transforms: str = "auto", aca: str = "auto", normals=None, stream=None):
+                 transforms: str = "auto", aca: str = "auto", normals=None, adaptive: bool = False, stream=None):
         import torch
         same = Y is X
         X = X.detach().contiguous()
@@ -259,7 +261,7 @@ class Plan:
         self.device = X.device
         flags = (FFM_FLAG_TIMING if timing else 0) | {"auto": 0, "direct": FFM_FLAG_DIRECT_TRANSFORMS,
                                                       "grid": FFM_FLAG_GRID_TRANSFORMS}[transforms] | \
-            {"auto": 0, "off": FFM_FLAG_NO_ACA, "on": FFM_FLAG_ACA}[aca]
+            {"auto": 0, "off": FFM_FLAG_NO_ACA, "on": FFM_FLAG_ACA}[aca] | (FFM_FLAG_ADAPTIVE_LEAVES if adaptive else 0)
         opts = Options(int(n_leaf), int(precision), float(kd_switch), int(r1_override), int(max_level), flags)
         if normals is not None:
             normals = normals.detach().contiguous()
@@ -316,7 +318,7 @@ class Plan:
             a = a.reshape(-1, 3)
         elif what == FFM_EXPORT_FAR:
             a = a.reshape(-1, 5)
-        elif what == FFM_EXPORT_NEAR:
+        elif what in (FFM_EXPORT_NEAR, FFM_EXPORT_EARLY):
             a = a.reshape(-1, 2)
         elif what == FFM_EXPORT_ACA_RANK:
             a = a.reshape(-1, 4)

@@ -166,7 +166,8 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     if (!(k >= 0.0) || !std::isfinite(k)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: k must be finite and >= 0");
     ffm_options_t o{};
     if (opts) o = *opts;
-    if (o.flags & ~(FFM_FLAG_TIMING | FFM_FLAG_DIRECT_TRANSFORMS | FFM_FLAG_GRID_TRANSFORMS | FFM_FLAG_NO_ACA | FFM_FLAG_ACA))
+    if (o.flags & ~(FFM_FLAG_TIMING | FFM_FLAG_DIRECT_TRANSFORMS | FFM_FLAG_GRID_TRANSFORMS | FFM_FLAG_NO_ACA | FFM_FLAG_ACA |
+                    FFM_FLAG_ADAPTIVE_LEAVES))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: unknown options.flags bits");
     if ((o.flags & FFM_FLAG_DIRECT_TRANSFORMS) && (o.flags & FFM_FLAG_GRID_TRANSFORMS))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: direct and grid transforms both forced");
@@ -401,6 +402,24 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
                             o[4] = LV.cls_off[3 * cls[e] + 2];
                         }
                         o += w;
+                    }
+                break;
+            }
+            case FFM_EXPORT_EARLY: {
+                const int64_t n = level >= 1 && level < P.leaf ? LV.nearly : 0;
+                *count = 2 * n;
+                if (!dst || n == 0) break;
+                const int32_t nbx = P.tx->lev[level].nbox;
+                std::vector<int64_t> ptr(nbx + 1);
+                std::vector<int32_t> src(n);
+                FFM_HIP(hipMemcpy(ptr.data(), LV.early_ptr.p, sizeof(int64_t) * (nbx + 1), hipMemcpyDeviceToHost));
+                FFM_HIP(hipMemcpy(src.data(), LV.early_src.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+                int64_t *o = static_cast<int64_t *>(dst);
+                for (int32_t t = 0; t < nbx; ++t)
+                    for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+                        o[0] = t;
+                        o[1] = src[e];
+                        o += 2;
                     }
                 break;
             }

@@ -290,6 +290,12 @@ struct Level {
     DevBuf<int64_t> far_ptr, near_ptr;   // [nbox_x + 1]
     DevBuf<int32_t> far_src, far_cls;    // [nfar]   (cls: compact translation class)
     DevBuf<int32_t> near_src;            // [nnear]
+    // per-pair leaf rule: the near pairs summed densely at this level (both boxes small), CSR by target box
+    int64_t nearly = 0;
+    DevBuf<int64_t> early_ptr;
+    DevBuf<int32_t> early_src;
+    std::vector<int32_t> h_early;        // target boxes with early pairs, largest first
+    double early_pairs = 0;              // their point pairs
     int32_t win_base[3] = {0, 0, 0};     // integer offset of window cell 0
     std::vector<int32_t> cls_off;        // [ncls][3] integer offsets of the classes
     int32_t ncls = 0;

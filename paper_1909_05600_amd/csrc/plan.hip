@@ -360,6 +360,38 @@ k_list_fill(int32_t nbx, const int32_t *parent_x, const int64_t *pnear_ptr, cons
     }
 }
 
+// Per-pair leaf rule: the near pairs of target box t whose two boxes both hold at most n_leaf points (early, summed
+// densely at this level) and the others (refined).  One thread per target box; order kept.
+__global__ void __launch_bounds__(kThreads)
+k_split_count(int32_t nbx, const int64_t *near_ptr, const int32_t *near_src, const int32_t *sx, const int32_t *sy,
+              int32_t n_leaf, int64_t *cnt_e, int64_t *cnt_r) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbx) return;
+    const bool small_t = sx[t + 1] - sx[t] <= n_leaf;
+    int64_t e = 0, r = 0;
+    for (int64_t q = near_ptr[t]; q < near_ptr[t + 1]; ++q) {
+        const int32_t s = near_src[q];
+        if (small_t && sy[s + 1] - sy[s] <= n_leaf) ++e;
+        else ++r;
+    }
+    cnt_e[t] = e;
+    cnt_r[t] = r;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_split_fill(int32_t nbx, const int64_t *near_ptr, const int32_t *near_src, const int32_t *sx, const int32_t *sy,
+             int32_t n_leaf, const int64_t *early_ptr, const int64_t *ref_ptr, int32_t *early_src, int32_t *ref_src) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbx) return;
+    const bool small_t = sx[t + 1] - sx[t] <= n_leaf;
+    int64_t e = early_ptr[t], r = ref_ptr[t];
+    for (int64_t q = near_ptr[t]; q < near_ptr[t + 1]; ++q) {
+        const int32_t s = near_src[q];
+        if (small_t && sy[s + 1] - sy[s] <= n_leaf) early_src[e++] = s;
+        else ref_src[r++] = s;
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) k_mark_sources(const int32_t *far_src, int64_t n, uint8_t *active) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) active[far_src[i]] = 1;
@@ -1084,6 +1116,36 @@ void build_work_lists(Plan &P, Level &LV, bool near, const WorkFetch &F) {
     LV.h_tgt = std::move(tgt);
 }
 
+// The early lists of a level (per-pair leaf rule): target boxes with early pairs (host, after the fetch) and their
+// point pairs.
+void fetch_early_lists(Level &LV, const TreeLevel &LX, const TreeLevel &LY, hipStream_t st, Scratch &SC, WorkFetch &F) {
+    F.nbx = LX.nbox;
+    F.nby = LY.nbox;
+    F.sx = SC.pin<int32_t>(LX.nbox + 1);
+    F.ptr = SC.pin<int64_t>(LX.nbox + 1);
+    FFM_HIP(hipMemcpyAsync(F.sx, LX.start.p, sizeof(int32_t) * (LX.nbox + 1), hipMemcpyDeviceToHost, st));
+    FFM_HIP(hipMemcpyAsync(F.ptr, LV.early_ptr.p, sizeof(int64_t) * (LX.nbox + 1), hipMemcpyDeviceToHost, st));
+    F.near_pairs = SC.pin<unsigned long long>(1);
+    *F.near_pairs = 0;
+    unsigned long long *dn = SC.get<unsigned long long>(1);
+    FFM_HIP(hipMemsetAsync(dn, 0, sizeof(unsigned long long), st));
+    FFM_LAUNCH(k_near_pairs, nblocks(LX.nbox), kThreads, 0, st, LV.early_ptr.p, LV.early_src.p, LX.nbox, LX.start.p,
+               LY.start.p, dn);
+    FFM_HIP(hipMemcpyAsync(F.near_pairs, dn, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+}
+
+void build_early_lists(Level &LV, const WorkFetch &F) {
+    std::vector<int32_t> tgt;
+    for (int32_t t = 0; t < F.nbx; ++t)
+        if (F.ptr[t + 1] > F.ptr[t]) tgt.push_back(t);
+    // boxes by decreasing point count (ties in index order)
+    std::stable_sort(tgt.begin(), tgt.end(), [&](int32_t a, int32_t b) {
+        return F.sx[a + 1] - F.sx[a] > F.sx[b + 1] - F.sx[b];
+    });
+    LV.h_early = std::move(tgt);
+    LV.early_pairs = (double)*F.near_pairs;
+}
+
 // FFM_LOG=1: host wall time of the plan phases on stderr (quiet by default)
 struct PhaseLog {
     bool on = std::getenv("FFM_LOG") && std::getenv("FFM_LOG")[0] == '1';
@@ -1251,14 +1313,48 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             P.leaf = l;
             break;
         }
+        // per-pair leaf rule (beyond the paper's global rule): near pairs whose two boxes both hold at most n_leaf
+        // points are summed densely at this level (the early list) instead of refined; the level is the leaf if
+        // nothing is left to refine
+        if (P.opt.flags & FFM_FLAG_ADAPTIVE_LEAVES) {
+            int64_t *cnt_e = SC.get<int64_t>(nbx + 1), *cnt_r = SC.get<int64_t>(nbx + 1);
+            FFM_LAUNCH(k_split_count, nblocks(nbx), kThreads, 0, st, nbx, LV.near_ptr.p, LV.near_src.p,
+                       TX.lev[l].start.p, TY.lev[l].start.p, P.opt.n_leaf, cnt_e, cnt_r);
+            DevBuf<int64_t> eptr(nbx + 1), rptr(nbx + 1);
+            tot_h[0] = tot_h[1] = -1;
+            exclusive_scan2_i64(cnt_e, eptr.p, cnt_r, rptr.p, nbx, tot_h, st, SC);
+            FFM_HIP(hipStreamSynchronize(st));
+            if (tot_h[0] < 0 || tot_h[1] < 0) {
+                FFM_HIP(hipMemcpy(&tot_h[0], eptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost));
+                FFM_HIP(hipMemcpy(&tot_h[1], rptr.p + nbx, sizeof(int64_t), hipMemcpyDeviceToHost));
+            }
+            if (tot_h[1] == 0) {
+                P.leaf = l;
+                break;
+            }
+            if (tot_h[0] > 0) {
+                DevBuf<int32_t> esrc(tot_h[0]), rsrc(tot_h[1]);
+                FFM_LAUNCH(k_split_fill, nblocks(nbx), kThreads, 0, st, nbx, LV.near_ptr.p, LV.near_src.p,
+                           TX.lev[l].start.p, TY.lev[l].start.p, P.opt.n_leaf, eptr.p, rptr.p, esrc.p, rsrc.p);
+                LV.nearly = tot_h[0];
+                LV.early_ptr = std::move(eptr);
+                LV.early_src = std::move(esrc);
+                LV.near_ptr = std::move(rptr);
+                LV.near_src = std::move(rsrc);
+                LV.nnear = tot_h[1];
+            }
+        }
     }
 
     plog.mark("lists");
     // the host side of every level's work lists, after one synchronisation
     std::vector<WorkFetch> wf(P.leaf + 1);
     WorkFetch wf_near;
-    for (int l = 1; l <= P.leaf; ++l)
+    std::vector<WorkFetch> wf_early(P.leaf + 1);
+    for (int l = 1; l <= P.leaf; ++l) {
         if (P.lev[l].nfar) fetch_work_lists(P.lev[l], TX.lev[l], TY.lev[l], false, st, SC, wf[l]);
+        if (l < P.leaf && P.lev[l].nearly) fetch_early_lists(P.lev[l], TX.lev[l], TY.lev[l], st, SC, wf_early[l]);
+    }
     fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near);
     int32_t *used_h = SC.pin<int32_t>((size_t)kWin3 * (P.leaf + 1) + 1);
     for (int l = 1; l <= P.leaf; ++l)
@@ -1600,6 +1696,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     }
     plog.mark("tables");
     build_work_lists(P, P.lev[P.leaf], true, wf_near);
+    for (int l = 1; l < P.leaf; ++l)
+        if (P.lev[l].nearly) build_early_lists(P.lev[l], wf_early[l]);
     (void)ws_part;
     P.ws_src = ws_src;
     P.ws_tgt = ws_tgt;
@@ -1628,6 +1726,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     const double near_pairs = s.near_pairs;
     std::memset(&s, 0, sizeof(s));
     s.near_pairs = near_pairs;
+    for (int l = 1; l < P.leaf; ++l) s.near_pairs += P.lev[l].early_pairs;
     s.leaf = P.leaf;
     s.same_set = P.same ? 1 : 0;
     s.d0 = d0;
@@ -1654,6 +1753,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         s.grid_width[l] = LV.method == kGegenbauer && LV.grid ? LV.gw : 0;
         s.grid_beta[l] = LV.method == kGegenbauer && LV.grid ? LV.gbeta : 0.0;
         s.aca[l] = LV.method == kLagrange && LV.aca ? 1 : 0;
+        s.nearly[l] = LV.nearly;
         s.aca_rank[l] = LV.method == kLagrange ? LV.aca_rank : 0.0;
         s.grid_alias[l] = LV.method == kGegenbauer && LV.grid ? LV.galias : 0.0;
         s.fwd_boxes[l] = (int64_t)LV.h_fwd.size();
@@ -2007,6 +2107,14 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         std::vector<int4> nr, po;
         for (int32_t t : LL.h_near) nr.push_back(make_int4(P.leaf, t, 0, 0));
         for (int64_t i = 0; i < P.nx; i += kThreads) po.push_back(make_int4(0, (int)i, 0, 0));
+        // near pairs the per-pair rule stopped above the leaf: the same kernel over each level's early list
+        for (int l = 1; l < P.leaf; ++l) {
+            if (P.lev[l].h_early.empty()) continue;
+            std::vector<int4> er;
+            for (int32_t t : P.lev[l].h_early) er.push_back(make_int4(l, t, 0, 0));
+            P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, -1, l, 0,
+                                        std::move(er), st, SC));
+        }
         P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, 61, P.leaf, 0,
                                     std::move(nr), st, SC));
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
@@ -2064,8 +2172,10 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.tr_tgt = LV.tr_tgt.p;
     d.ntr = (int)LV.h_tgt.size();
     d.ncls = LV.ncls;
-    d.near_ptr = LV.near_ptr.p;
-    d.near_src = LV.near_src.p;
+    // the near field of a level above the leaf sums that level's early pairs (per-pair leaf rule)
+    const bool early = l < P.leaf && LV.nearly > 0;
+    d.near_ptr = early ? LV.early_ptr.p : LV.near_ptr.p;
+    d.near_src = early ? LV.early_src.p : LV.near_src.p;
     d.dirs = LV.dirs.p;
     d.dirs64 = LV.dirs64.p;
     d.rings = LV.rings.p;

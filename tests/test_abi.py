@@ -58,7 +58,7 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
     for args in cases:
         assert L.ffm_plan(*args) == -1, args
         assert L.ffm_last_error().decode() != ""
-    bad = ffm.Options(0, 0, 0.0, 0, 0, 32)      # unknown flag bits
+    bad = ffm.Options(0, 0, 0.0, 0, 0, 64)      # unknown flag bits
     assert L.ffm_plan(dummy, 10, dummy, 10, 0, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1
     bad = ffm.Options(0, 0, 0.0, 0, 0, 24)      # ACA both forbidden and forced
     assert L.ffm_plan(dummy, 10, dummy, 10, 0, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1

@@ -240,3 +240,59 @@ def test_sphere_workload_sizes(orc):
         t, s, off = p.far(l)
         assert len({tuple(o) for o in off}) <= 316
         assert np.abs(off).max() == 3 and np.abs(off).max(axis=1).min() == 2
+
+
+@pytest.mark.parametrize("same", [True, False])
+def test_per_pair_leaf_rule(orc, same):
+    """Per-pair leaf rule (reading R22): a near pair whose two boxes both hold at most n_leaf points is summed
+    densely at its level (its early list) instead of being refined.  Every point pair is still covered exactly
+    once by the far lists, the early lists and the leaf's near list; the early pairs are exactly the near pairs
+    of small boxes; no early list at the leaf."""
+    rng = np.random.default_rng(31)
+    X = np.concatenate([W.sphere_points(700, rng), W.cube_points(500, rng, (0.3, -0.2, 0.1), 0.25)])
+    Y = X if same else np.concatenate([W.sphere_points(600, rng), W.cube_points(450, rng, (0.3, -0.2, 0.1), 0.25)])
+    n_leaf = 12
+    p = orc.Plan(X, Y, 1, 6.0, 1e-3, n_leaf=n_leaf, adaptive=True)
+    q = orc.Plan(X, Y, 1, 6.0, 1e-3, n_leaf=n_leaf)
+    early_total = 0
+    cover = np.zeros((X.shape[0], Y.shape[0]), dtype=np.int32)
+    px, py = p.perm(0), p.perm(1)
+
+    def add(l, t, s):
+        stx, sty = p.box_start(0, l), p.box_start(1, l)
+        for a, b in zip(t, s):
+            cover[np.ix_(px[stx[a]:stx[a + 1]], py[sty[b]:sty[b + 1]])] += 1
+
+    for l in range(1, p.leaf + 1):
+        add(l, *p.far(l)[:2])
+        et, es = p.early(l)
+        early_total += len(et)
+        if l == p.leaf:
+            assert len(et) == 0
+        stx, sty = p.box_start(0, l), p.box_start(1, l)
+        assert np.all(np.diff(stx)[et] <= n_leaf) and np.all(np.diff(sty)[es] <= n_leaf)
+        add(l, et, es)
+        if l < p.leaf:
+            nt, ns = p.near(l)        # the refined pairs: at least one box holds more than n_leaf points
+            assert np.all((np.diff(stx)[nt] > n_leaf) | (np.diff(sty)[ns] > n_leaf))
+            if early_total == len(et):
+                # the first level with early pairs: its early and refined pairs are the plain descent's near pairs
+                qt, qs = q.near(l)
+                assert sorted(zip(list(et) + list(nt), list(es) + list(ns))) == sorted(zip(qt, qs))
+    add(p.leaf, *p.near(p.leaf))
+    assert early_total > 0
+    assert cover.min() == 1 and cover.max() == 1
+
+
+def test_per_pair_leaf_rule_product(orc):
+    """The FFM with the per-pair rule on a non-uniform cloud (sphere plus a dense cube cluster): within eps of FP64
+    dense rows and close to the plain descent's product."""
+    w = W.sphere_plus_cube(30000, seed=3, n_rows=256)
+    pa = orc.Plan(w.X, w.X, 1, w.k, w.eps, adaptive=True)
+    pb = orc.Plan(w.X, w.X, 1, w.k, w.eps)
+    assert sum(len(pa.early(l)[0]) for l in range(1, pa.leaf + 1)) > 0
+    va, vb = pa.apply(w.wu), pb.apply(w.wu)
+    d = orc.dense_rows(w.X, w.X, w.wu, 1, w.k, w.rows)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    assert rel(va[w.rows], d) <= w.eps
+    assert rel(va, vb) <= w.eps
