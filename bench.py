@@ -358,10 +358,10 @@ def mixed_study(n, n_rows, reps=3):
     t_dense = time.perf_counter() - t0
     sph = w.rows < w.meta["n_sphere"]
     for eps in (1e-3, 1e-4):
-        for prec in (0, 1):
+        for prec, adaptive in ((0, False), (1, False), (0, True)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            p = ffm.Plan(X, X, 1, w.k, eps, precision=prec)
+            p = ffm.Plan(X, X, 1, w.k, eps, precision=prec, adaptive=adaptive)
             torch.cuda.synchronize()
             t_plan = time.perf_counter() - t0
             v = p.apply(wu)
@@ -371,7 +371,8 @@ def mixed_study(n, n_rows, reps=3):
 
             def rl(a, b):
                 return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-            r = {"eps": eps, "precision": "mixed" if prec else "fp32", "plan_s": t_plan, "apply_s": t_apply,
+            r = {"eps": eps, "precision": "mixed" if prec else "fp32", "adaptive_leaves": adaptive,
+                 "plan_s": t_plan, "apply_s": t_apply, "early_pairs": [int(x) for x in st["nearly"][:st["leaf"] + 1]],
                  "points_per_s": n / (t_plan + t_apply), "apply_points_per_s": n / t_apply,
                  "err": rl(vv, d), "err_sphere": rl(vv[sph], d[sph]), "err_cube": rl(vv[~sph], d[~sph]),
                  "leaf": st["leaf"], "methods": st["method"][:st["leaf"] + 1],
@@ -380,8 +381,9 @@ def mixed_study(n, n_rows, reps=3):
                  "plan_mb": st["plan_bytes"] / 1e6, "workspace_mb": st["workspace_bytes"] / 1e6,
                  "dense_rows_s": t_dense}
             out["runs"].append(r)
-            print("mixed study eps=%g %s: plan %.2fs apply %.3fs err %.2e (sphere %.2e cube %.2e)"
-                  % (eps, r["precision"], t_plan, t_apply, r["err"], r["err_sphere"], r["err_cube"]),
+            print("mixed study eps=%g %s%s: plan %.2fs apply %.3fs err %.2e (sphere %.2e cube %.2e)"
+                  % (eps, r["precision"], " adaptive" if adaptive else "", t_plan, t_apply, r["err"], r["err_sphere"],
+                     r["err_cube"]),
                   file=sys.stderr, flush=True)
             p.destroy()
             torch.cuda.empty_cache()
