@@ -39,11 +39,24 @@ PEAK_ALU_PACKED_TFLOPS = 157.3
 #   near field, per (target, source) pair: Laplace 14 (3 differences, |d|^2 in 3 FMA, rsqrt, 1/(4 pi) scale, a
 #     complex multiply-add), Helmholtz 24 (the same, k r, sin, cos, two products e^{ikr}/r and a complex
 #     multiply-add)
+#   normal derivative at the target, per pair: Laplace 21 (the Laplace count with n . d in 3 FMA and 1/r^3 in 3
+#     products instead of the scale), Helmholtz 35 (the same, k r, sin, cos, the two factors -(cos + kr sin),
+#     kr cos - sin and a complex multiply-add)
 FLOPS_PER_DIRECTION = {"pair": 16.0 / 2, "ring": 22.0 / 4}
-NEAR_FLOPS = {"k_near<false>": 14.0, "k_near<true>": 24.0}
-# VALU issue slots the implemented near-field loop needs per pair at least (transcendentals co-issue): the slot
-# utilisation is reported separately from the flop fraction
-NEAR_SLOTS = {"k_near<false>": 10.0, "k_near<true>": 18.0}
+NEAR_FLOPS = {"k_near<false": 14.0, "k_near<true": 24.0, "k_near_dn<false": 21.0, "k_near_dn<true": 35.0}
+# VALU issue slots the implemented near-field loop needs per pair at least (transcendentals co-issue): three FP64
+# differences and their conversions to FP32 (6), |d|^2 (3), then Laplace a complex multiply-add (2), Helmholtz
+# r = |d|^2 / |d| (1), cos / r and sin / r (2) and a complex multiply-add (4).  The slot utilisation is reported
+# separately from the flop fraction.
+NEAR_SLOTS = {"k_near<false": 11.0, "k_near<true": 16.0}
+
+
+def near_model(name, table):
+    """The entry of a near-field table for a kernel symbol (its first template argument names the kernel)."""
+    for key, v in table.items():
+        if name.startswith(key + ",") or name.startswith(key + ">"):
+            return v
+    return None
 # Published MI355X peaks per bound: dense FP32 MFMA 157.3 TFLOP/s, dense FP16 MFMA 2500, FP32 VALU (non-packed,
 # FMA = 2) 78.6, HBM3E 8 TB/s.
 PEAKS = {"mfma": (157.3, "TFLOP/s"), "mfma16": (2500.0, "TFLOP/s"), "alu": (PEAK_ALU_TFLOPS, "TFLOP/s"),
@@ -55,7 +68,7 @@ PEAKS = {"mfma": (157.3, "TFLOP/s"), "mfma16": (2500.0, "TFLOP/s"), "alu": (PEAK
 # for the kernel source it was taken on.
 TRAFFIC_SOURCE_HASH = "d19c06e41360a2d6"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
 TRAFFIC = {
-    "k_near<true>": (382161.0 * 2.0 + 8833.875) * 1024.0,
+    "k_near<true, false>": (382161.0 * 2.0 + 8833.875) * 1024.0,
     "k_grid_phit": (79074.875 * 2.0 + 295680.0) * 1024.0,
 }
 
@@ -551,8 +564,10 @@ def launch_work(name, level, st):
                 % ("ring-pair" if form == "ring" else "direction-pair",
                    "22 per 4 directions" if form == "ring" else "16 per 2 directions"))
     if name.startswith("k_near"):
-        return (NEAR_FLOPS[name] * st["near_pairs"], "alu",
-                "%d flops per (target, source) pair of the near field, VALU" % NEAR_FLOPS[name])
+        f = near_model(name, NEAR_FLOPS)
+        if f is None:
+            return None
+        return (f * st["near_pairs"], "alu", "%d flops per (target, source) pair of the near field, VALU" % f)
     if name.startswith("k_pw_transfer"):
         return (8.0 * nq * (nbf + st["nclass"][level] + nbt), "hbm",
                 "unique bytes: u~ of every source box, the class tables D and v~ of every target box, 8 per "
@@ -618,12 +633,12 @@ def roofline(launches, st, steps):
         if e["bound"] == "alu":
             out["peak_packed_fp32"] = PEAK_ALU_PACKED_TFLOPS
             out["frac_of_packed_peak"] = rate / PEAK_ALU_PACKED_TFLOPS
-        if name in NEAR_SLOTS:
-            slots = NEAR_SLOTS[name] * st["near_pairs"]
-            out["issue_slot_utilisation"] = slots / (e["ms"] * 1e-3) / VALU_SLOTS_PER_S
+        ns = near_model(name, NEAR_SLOTS)
+        if ns is not None:
+            out["issue_slot_utilisation"] = ns * st["near_pairs"] / (e["ms"] * 1e-3) / VALU_SLOTS_PER_S
             out["issue_slot_definition"] = ("%d non-transcendental VALU issue slots per pair (the fewest the "
                                             "implemented loop needs) over the 39.3e12 lane-slots/s of the chip"
-                                            % NEAR_SLOTS[name])
+                                            % ns)
         return name, out
     return "none", {"bound": "alu", "kernel": "none", "achieved": 0.0, "peak": PEAK_ALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": 0.0, "time_weighted": time_weighted}

@@ -2398,139 +2398,257 @@ k_lag_interp_dn(const LDesc *__restrict__ descs, const IoEntry *__restrict__, co
 }
 
 // ------------------------------------------------------------------ near field (leaf)
-// v_i += sum_{s in near(t)} sum_{j in s, r_ij > 0} G(r_ij) u_j.  One 64-lane block per target box; source
-// points are staged through LDS in FP64 relative to the target centre, and every pair's difference is
-// formed in FP64 and rounded once to FP32, so close pairs keep the full FP32 relative accuracy of r.
-// Targets go through the lanes in passes of at most 64; a pass of nt targets gives each target R = 64 / nt
-// lanes, lane r of a target taking the staged sources r, r + R, ... (the chunk is padded with zero sources to
-// a multiple of R), and the R partial sums of a target are added in order of r.  Item (desc, target box).
-template <bool HELM, bool DN>
-__device__ __forceinline__ void near_body(const LDesc &d, const int4 wk) {
-    const int t = wk.y;
-    const int lane = threadIdx.x;
-    const float k_rev = d.k_rev;
-    const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
-    __shared__ double spx[128], spy[128], spz[128];   // sources relative to c_t, zero-padded past the chunk
-    __shared__ float2 su[128];                         // u / (4 pi), zero past the chunk
-    __shared__ float2 part[64];
-    const float inv4pi = (float)(1.0 / (4.0 * M_PI));
-    const int64_t e0 = d.near_ptr[t], e1 = d.near_ptr[t + 1];
-    const int ta = d.tstart[t], tz = d.tstart[t + 1];
-    for (int k = lane; k < 128; k += 64) {
-        spx[k] = spy[k] = spz[k] = 0.0;
-        su[k] = make_float2(0.f, 0.f);
+// v_i += sum_{s in near(t)} sum_{j in s, r_ij > 0} G(r_ij) u_j.  One 64-lane block per target box.  Source points
+// are staged through LDS in chunks of 64, in FP64 relative to the target centre, and every pair's difference is
+// formed in FP64 and rounded once to FP32, so close pairs keep the full FP32 relative accuracy of r.  Helmholtz
+// coordinates are scaled by k / 2 pi when staged (r then reads in revolutions, the phase of e^{ikr}), and the
+// factors that scaling takes out of 1/r (and of the derivative's 1/r^3) go into the staged u.
+//
+// Targets go through the lanes in passes.  A pass of nt targets gives each lane T of them (T = 1, 2 or 4: g =
+// ceil(nt / T) target groups, group gi holding targets gi, gi + g, ...) and gives each group R = 64 / g lanes;
+// lane r of a group takes the contiguous range r * steps ... r * steps + steps - 1 of the chunk's staged sources
+// (steps = ceil(cnt / R); staged slots past the chunk hold zero sources).  A lane evaluates every staged source
+// against its T targets, so one set of LDS reads serves T pairs.  The R partial sums of a target are added in
+// order of r.  The pass sizes come from the box's target count alone, so the summation order is fixed.
+// Ranges of consecutive lanes start an odd number of 8-byte slots apart (slot r * (steps | 1) + q), so the R
+// distinct addresses of one read fall in distinct banks.  The r > 0 test runs only where coincident points can
+// occur: a box against itself when sources and targets are one set, every pair otherwise.
+constexpr int kNearSlots = 128;
+
+struct NearPass {
+    int nt, T;
+};
+
+// Pass sizes for rem remaining targets: a full pass (64 m targets, m = 1, 2, 4, four per lane on 4 / m lanes
+// each) is taken while it beats a single partial pass over everything left; cost = pairs per lane per staged
+// source.  Equal costs go to four targets per lane, whose LDS reads serve four pairs.
+__device__ __forceinline__ float near_pass_cost(int n, int T) {
+    const int g = (n + T - 1) / T;
+    return g > 64 ? 1e30f : (float)T / (float)(64 / g);
+}
+
+__device__ __forceinline__ NearPass near_next_pass(int rem) {
+    float best = 1e30f;
+    int bt = 1;
+    for (int T = 1; T <= 4; T *= 2) {
+        const float c = near_pass_cost(rem, T);
+        if (c <= best) {
+            best = c;
+            bt = T;
+        }
     }
-    for (int i0 = ta; i0 < tz; i0 += 64) {
-        const int nt = min(64, tz - i0), R = 64 / nt;
-        const int r = lane / nt, ti = lane - r * nt;
-        const bool valid = r < R;
-        const int i = i0 + ti;
-        double x = 0.0, y = 0.0, z = 0.0;
-        float nx = 0.f, ny = 0.f, nz = 0.f;
-        if (valid) {
-            x = d.txs[i] - cx;
-            y = d.tys[i] - cy;
-            z = d.tzs[i] - cz;
+    NearPass out{rem, bt};
+    for (int m = 4; m >= 1; m /= 2) {
+        const int full = 64 * m;
+        if (rem <= full) continue;
+        float rest = 1e30f;
+        for (int T2 = 1; T2 <= 4; T2 *= 2) rest = fminf(rest, near_pass_cost(rem - full, T2));
+        if (rest > 1e29f) rest = (float)((rem - full + 255) / 256) * 4.f;   // more full passes follow
+        if ((float)m + rest < best) {
+            best = (float)m + rest;
+            out = NearPass{full, 4};
+        }
+    }
+    return out;
+}
+
+struct NearSmem {
+    double x[kNearSlots], y[kNearSlots], z[kNearSlots];   // part[] reuses x and y after the last chunk
+    float2 u[kNearSlots];
+};
+
+template <bool HELM, bool DN, bool BIG, bool CHK>
+__device__ __forceinline__ void near_pair(double x, double y, double z, float nx, float ny, float nz, double sx,
+                                          double sy, double sz, float2 uu, float &are, float &aim) {
+    const float dx = (float)(x - sx), dy = (float)(y - sy), dz = (float)(z - sz);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float inv = __builtin_amdgcn_rsqf(r2);
+    if (CHK) inv = r2 > 0.f ? inv : 0.f;
+    if (DN) {
+        // n . grad_x G: (n . d) G'(r) / r with G' = -1 / r^2 (Laplace), (ikr - 1) e^{ikr} / r^2 (Helmholtz)
+        const float i3 = inv * inv * inv * fmaf(nx, dx, fmaf(ny, dy, nz * dz));
+        if (HELM) {
+            const float rr = r2 * inv;
+            float sn, cs;
+            sincos_rev(BIG ? __builtin_amdgcn_fractf(rr) : rr, sn, cs);
+            const float kr = 6.2831853f * rr;
+            const float gr = i3 * fmaf(-kr, sn, -cs), gi = i3 * fmaf(kr, cs, -sn);
+            are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
+            aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
+        } else {
+            are = fmaf(-i3, uu.x, are);
+            aim = fmaf(-i3, uu.y, aim);
+        }
+    } else if (HELM) {
+        const float rr = r2 * inv;
+        float sn, cs;
+        sincos_rev(BIG ? __builtin_amdgcn_fractf(rr) : rr, sn, cs);
+        const float gr = cs * inv, gi = sn * inv;
+        are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
+        aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
+    } else {
+        are = fmaf(inv, uu.x, are);
+        aim = fmaf(inv, uu.y, aim);
+    }
+}
+
+// steps staged sources from slot base against the lane's T targets
+template <bool HELM, bool DN, bool BIG, bool CHK, int T>
+__device__ __forceinline__ void near_range(const NearSmem &sm, int base, int steps, const double (&x)[T],
+                                           const double (&y)[T], const double (&z)[T], const float (&nx)[T],
+                                           const float (&ny)[T], const float (&nz)[T], float (&are)[T],
+                                           float (&aim)[T]) {
+    constexpr int U = 4 / T;
+    int q = 0;
+    for (; q + U <= steps; q += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = base + q + u;
+            const double sx = sm.x[s], sy = sm.y[s], sz = sm.z[s];
+            const float2 uu = sm.u[s];
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                near_pair<HELM, DN, BIG, CHK>(x[t], y[t], z[t], nx[t], ny[t], nz[t], sx, sy, sz, uu, are[t], aim[t]);
+        }
+    }
+    for (; q < steps; ++q) {
+        const int s = base + q;
+        const double sx = sm.x[s], sy = sm.y[s], sz = sm.z[s];
+        const float2 uu = sm.u[s];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            near_pair<HELM, DN, BIG, CHK>(x[t], y[t], z[t], nx[t], ny[t], nz[t], sx, sy, sz, uu, are[t], aim[t]);
+    }
+}
+
+// One pass: targets i0 ... i0 + nt - 1 of box t, T per lane.
+template <bool HELM, bool DN, bool BIG, int T>
+__device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, int t, int i0, int nt, double scale,
+                                          float uscale) {
+    const int lane = threadIdx.x;
+    const int g = __builtin_amdgcn_readfirstlane((nt + T - 1) / T), R = __builtin_amdgcn_readfirstlane(64 / g);
+    const int r = lane / g, gi = lane - r * g;
+    const bool valid = r < R;
+    const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
+    double x[T], y[T], z[T];
+    float nx[T], ny[T], nz[T], are[T], aim[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int ti = gi + g * k;
+        x[k] = y[k] = z[k] = 0.0;
+        nx[k] = ny[k] = nz[k] = 0.f;
+        are[k] = aim[k] = 0.f;
+        if (valid && ti < nt) {
+            const int i = i0 + ti;
+            x[k] = (d.txs[i] - cx) * scale;
+            y[k] = (d.tys[i] - cy) * scale;
+            z[k] = (d.tzs[i] - cz) * scale;
             if (DN) {
                 const float4 n = d.tn[i];
-                nx = n.x;
-                ny = n.y;
-                nz = n.z;
+                nx[k] = n.x;
+                ny[k] = n.y;
+                nz[k] = n.z;
             }
         }
-        float are = 0.f, aim = 0.f;
-        auto pair = [&](int jj) {
-            const float dx = (float)(x - spx[jj]), dy = (float)(y - spy[jj]), dz = (float)(z - spz[jj]);
-            const float2 uu = su[jj];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-            if (DN) {
-                // n . grad_x G: (n . d) G'(r) / r with G' = -1 / r^2 (Laplace), (ikr - 1) e^{ikr} / r^2 (Helmholtz)
-                const float i3 = inv * inv * inv * fmaf(nx, dx, fmaf(ny, dy, nz * dz));
-                if (HELM) {
-                    const float ph = r2 * inv * k_rev;
-                    float sn, cs;
-                    sincos_rev(__builtin_amdgcn_fractf(ph), sn, cs);
-                    const float kr = 6.2831853f * ph;
-                    const float gr = i3 * fmaf(-kr, sn, -cs), gi = i3 * fmaf(kr, cs, -sn);
-                    are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
-                    aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
-                } else {
-                    are = fmaf(-i3, uu.x, are);
-                    aim = fmaf(-i3, uu.y, aim);
-                }
-            } else if (HELM) {
-                const float ph = r2 * inv * k_rev;
-                float sn, cs;
-                sincos_rev(__builtin_amdgcn_fractf(ph), sn, cs);
-                const float gr = cs * inv, gi = sn * inv;
-                are = fmaf(gr, uu.x, fmaf(-gi, uu.y, are));
-                aim = fmaf(gr, uu.y, fmaf(gi, uu.x, aim));
-            } else {
-                are = fmaf(inv, uu.x, are);
-                aim = fmaf(inv, uu.y, aim);
-            }
-        };
-        for (int64_t e = e0; e < e1; ++e) {
-            const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
-            const int j0 = __builtin_amdgcn_readfirstlane(d.sstart[s]), j1 = __builtin_amdgcn_readfirstlane(d.sstart[s + 1]);
-            for (int c0 = j0; c0 < j1; c0 += 64) {
-                const int cnt = min(64, j1 - c0), steps = (cnt + R - 1) / R;
-                __syncthreads();
-                {
-                    const int j = c0 + lane;
-                    if (lane < cnt) {
-                        spx[lane] = d.sxs[j] - cx;
-                        spy[lane] = d.sys[j] - cy;
-                        spz[lane] = d.szs[j] - cz;
+    }
+    const int64_t e0 = d.near_ptr[t], e1 = d.near_ptr[t + 1];
+    const bool same = d.same != 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
+        const int j0 = __builtin_amdgcn_readfirstlane(d.sstart[s]), j1 = __builtin_amdgcn_readfirstlane(d.sstart[s + 1]);
+        const bool chk = !same || s == t;
+        for (int c0 = j0; c0 < j1; c0 += 64) {
+            const int cnt = min(64, j1 - c0);
+            const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
+            const uint32_t mul = (65536u + (uint32_t)steps - 1u) / (uint32_t)steps;   // jj / steps for jj < 128
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int jj = lane + 64 * h;
+                if (jj < R * steps) {
+                    const int qd = (int)(((uint32_t)jj * mul) >> 16);
+                    const int slot = qd * so + (jj - qd * steps);
+                    if (jj < cnt) {
+                        const int j = c0 + jj;
+                        sm.x[slot] = (d.sxs[j] - cx) * scale;
+                        sm.y[slot] = (d.sys[j] - cy) * scale;
+                        sm.z[slot] = (d.szs[j] - cz) * scale;
                         const float2 uu = d.u[j];
-                        su[lane] = make_float2(uu.x * inv4pi, uu.y * inv4pi);
+                        sm.u[slot] = make_float2(uu.x * uscale, uu.y * uscale);
                     } else {
-                        su[lane] = make_float2(0.f, 0.f);    // padding: zero sources
+                        sm.x[slot] = sm.y[slot] = sm.z[slot] = 0.0;   // padding: zero sources
+                        sm.u[slot] = make_float2(0.f, 0.f);
                     }
                 }
-                __syncthreads();
-                // lane r of a target: sources r + R q, q < steps (entries past cnt are zero sources)
-                int q = 0;
-                for (; q + 4 <= steps; q += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) pair(r + R * (q + u));
-                }
-                for (; q < steps; ++q) pair(r + R * q);
             }
+            __syncthreads();
+            const int base = valid ? r * so : 0;     // idle lanes read staged slots and discard their sums
+            if (chk)
+                near_range<HELM, DN, BIG, true, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
+            else
+                near_range<HELM, DN, BIG, false, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
         }
-        // the R partial sums of each target, added in order of r
-        __syncthreads();
-        part[lane] = make_float2(are, aim);
-        __syncthreads();
-        if (lane < nt) {
-            float2 a = part[lane];
+    }
+    // the R partial sums of each target, added in order of r
+    float2 *part = reinterpret_cast<float2 *>(sm.x);   // [T][64], over x and y
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < T; ++k) part[k * 64 + lane] = make_float2(are[k], aim[k]);
+    __syncthreads();
+    if (lane < g) {
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            const int ti = lane + g * k;
+            if (ti >= nt) break;
+            float2 a = part[k * 64 + lane];
             for (int rr = 1; rr < R; ++rr) {
-                const float2 b = part[lane + rr * nt];
+                const float2 b = part[k * 64 + lane + rr * g];
                 a.x += b.x;
                 a.y += b.y;
             }
-            float2 o = d.v[i];
+            float2 o = d.v[i0 + ti];
             o.x += a.x;
             o.y += a.y;
-            d.v[i] = o;
+            d.v[i0 + ti] = o;
         }
     }
 }
 
-template <bool HELM>
+template <bool HELM, bool DN, bool BIG>
+__device__ __forceinline__ void near_body(const LDesc &d, const int4 wk) {
+    __shared__ NearSmem sm;
+    const int t = wk.y;
+    const int ta = d.tstart[t], tz = d.tstart[t + 1];
+    // Helmholtz: coordinates in units of 2 pi / k; 1/r = (k / 2 pi) / r', 1/r^3 = (k / 2 pi)^3 / r'^3 and
+    // n . d = (2 pi / k) n . d'
+    const double kr = (double)d.k_rev;
+    const double scale = HELM ? kr : 1.0;
+    const float uscale = (float)((1.0 / (4.0 * M_PI)) * (HELM ? (DN ? kr * kr : kr) : 1.0));
+    for (int i0 = ta; i0 < tz;) {
+        const NearPass ps = near_next_pass(tz - i0);
+        if (ps.T == 1)
+            near_pass<HELM, DN, BIG, 1>(d, sm, t, i0, ps.nt, scale, uscale);
+        else if (ps.T == 2)
+            near_pass<HELM, DN, BIG, 2>(d, sm, t, i0, ps.nt, scale, uscale);
+        else
+            near_pass<HELM, DN, BIG, 4>(d, sm, t, i0, ps.nt, scale, uscale);
+        i0 += ps.nt;
+    }
+}
+
+template <bool HELM, bool BIG>
 __global__ void __launch_bounds__(64)
 k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
-    near_body<HELM, false>(descs[wk.x], wk);
+    near_body<HELM, false, BIG>(descs[wk.x], wk);
 }
 
 // The normal derivative at the target (the adjoint double-layer kernel), same blocks and lanes.
-template <bool HELM>
+template <bool HELM, bool BIG>
 __global__ void __launch_bounds__(64)
 k_near_dn(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
-    near_body<HELM, true>(descs[wk.x], wk);
+    near_body<HELM, true, BIG>(descs[wk.x], wk);
 }
 
 typedef void (*KernelFn)(const LDesc *, const IoEntry *, const int4 *);
@@ -2584,8 +2702,10 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_MFMA16: threads = 64 * std::max(1, S.a); return k_lag_mfma16;
         case K_ACA: threads = 64 * std::max(1, S.a); return k_lag_aca;
         case K_INTERP: return k_lag_interp;
-        case K_NEAR: threads = 64; return S.b ? k_near<true> : k_near<false>;
-        case K_NEAR_DN: threads = 64; return S.b ? k_near_dn<true> : k_near_dn<false>;
+        case K_NEAR: threads = 64; return S.b ? (S.a ? k_near<true, true> : k_near<true, false>) : k_near<false, false>;
+        case K_NEAR_DN:
+            threads = 64;
+            return S.b ? (S.a ? k_near_dn<true, true> : k_near_dn<true, false>) : k_near_dn<false, false>;
         case K_INTERP_DN: return k_lag_interp_dn;
         case K_BWD_PAIR_DN:
             if (S.a == 100) {
@@ -2757,8 +2877,8 @@ std::string kernel_name(int kern, int a, int b) {
         case K_MFMA16: return "k_lag_mfma16";
         case K_ACA: return "k_lag_aca";
         case K_INTERP: return "k_lag_interp";
-        case K_NEAR: return "k_near<" + tf(b) + ">";
-        case K_NEAR_DN: return "k_near_dn<" + tf(b) + ">";
+        case K_NEAR: return "k_near<" + tf(b) + ", " + tf(b && a) + ">";
+        case K_NEAR_DN: return "k_near_dn<" + tf(b) + ", " + tf(b && a) + ">";
         case K_INTERP_DN: return "k_lag_interp_dn";
         case K_BWD_PAIR_DN: return "k_pw_backward_dn<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
         case K_ZERO_OUT: return "k_zero_io";

@@ -198,6 +198,7 @@ struct LDesc {
     float2 *u, *v;                    // sorted input, sorted output accumulator
     float *amax;                      // max |u| of the apply (FP16 scaling), or null
     float k_rev;                      // k / (2 pi)
+    int same;                         // sources and targets are one set (one tree)
     // level
     const double *txs, *tys, *tzs, *tctr;
     const int32_t *tstart;

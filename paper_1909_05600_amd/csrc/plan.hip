@@ -2107,16 +2107,22 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         std::vector<int4> nr, po;
         for (int32_t t : LL.h_near) nr.push_back(make_int4(P.leaf, t, 0, 0));
         for (int64_t i = 0; i < P.nx; i += kThreads) po.push_back(make_int4(0, (int)i, 0, 0));
+        // Helmholtz near field (k > 0; k = 0 is the Laplace kernel): phases k r / 2 pi of a level's near pairs
+        // stay below 4 sqrt(3) k d_l / 2 pi revolutions (adjacent boxes, either tree); beyond 128 revolutions
+        // they are reduced to [0, 1) before the hardware sine and cosine
+        const bool nhelm = P.kernel == FFM_HELMHOLTZ && P.k > 0.0;
+        auto big = [&](int l) {
+            return nhelm && P.k / (2.0 * M_PI) * 4.0 * std::sqrt(3.0) * std::ldexp(P.d0, -l) > 128.0 ? 1 : 0;
+        };
         // near pairs the per-pair rule stopped above the leaf: the same kernel over each level's early list
         for (int l = 1; l < P.leaf; ++l) {
             if (P.lev[l].h_early.empty()) continue;
             std::vector<int4> er;
             for (int32_t t : P.lev[l].h_early) er.push_back(make_int4(l, t, 0, 0));
-            P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, -1, l, 0,
-                                        std::move(er), st, SC));
+            P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, big(l), nhelm, -1, l, 0, std::move(er), st, SC));
         }
-        P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, 0, P.kernel == FFM_HELMHOLTZ, 61, P.leaf, 0,
-                                    std::move(nr), st, SC));
+        P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, big(P.leaf), nhelm, 61, P.leaf, 0, std::move(nr),
+                                    st, SC));
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
     }
     // timing slot of every stage: a stage that closes no phase belongs to the next one that does
@@ -2154,6 +2160,7 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.v = v;
     d.amax = amax;
     d.k_rev = (float)(P.k / (2.0 * M_PI));
+    d.same = P.same ? 1 : 0;
     const TreeLevel &LX = P.tx->lev[l], &LY = P.ty->lev[l];
     d.txs = P.tx->xs.p;
     d.tys = P.tx->ys.p;

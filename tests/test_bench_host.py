@@ -24,8 +24,11 @@ def test_launch_work_models():
     st = {"order": [0, 0, 10], "nq": [0, 0, 220], "grid_nodes": [0, 0, 32], "grid_width": [0, 0, 5],
           "fwd_boxes": [0, 0, 7], "bwd_boxes": [0, 0, 9], "fwd_points": [0, 0, 1000.0], "bwd_points": [0, 0, 900.0],
           "method": [0, 0, 2], "near_pairs": 5e6, "nclass": [0, 0, 316], "nfar": [0, 0, 100], "_helm": True}
-    assert bench.launch_work("k_near<true>", 0, st)[0] == 24 * 5e6
-    assert bench.launch_work("k_near<false>", 0, st)[0] == 14 * 5e6
+    assert bench.launch_work("k_near<true, false>", 0, st)[0] == 24 * 5e6
+    assert bench.launch_work("k_near<false, false>", 0, st)[0] == 14 * 5e6
+    assert bench.launch_work("k_near<true, true>", 0, st)[0] == 24 * 5e6
+    assert bench.launch_work("k_near_dn<true, false>", 0, st)[0] == 35 * 5e6
+    assert bench.launch_work("k_near_dn<false, false>", 0, st)[0] == 21 * 5e6
     assert bench.launch_work("k_pw_forward_rings<2, false>", 2, st)[0] == 5.5 * 1000 * 220
     assert bench.launch_work("k_pw_backward<256, false>", 2, st)[0] == 8 * 900 * 220
     assert bench.launch_work("k_grid_phit", 2, st)[0] == 8 * 9 * 11 * 32 * 32 * 10
