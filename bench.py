@@ -43,7 +43,8 @@ PEAK_ALU_PACKED_TFLOPS = 157.3
 #     products instead of the scale), Helmholtz 35 (the same, k r, sin, cos, the two factors -(cos + kr sin),
 #     kr cos - sin and a complex multiply-add)
 FLOPS_PER_DIRECTION = {"pair": 16.0 / 2, "ring": 22.0 / 4}
-NEAR_FLOPS = {"k_near<false": 14.0, "k_near<true": 24.0, "k_near_dn<false": 21.0, "k_near_dn<true": 35.0}
+NEAR_FLOPS = {"k_near<false": 14.0, "k_near<true": 24.0, "k_near_dn<false": 21.0, "k_near_dn<true": 35.0,
+              "k_near_sym<false": 14.0, "k_near_sym<true": 24.0}
 # VALU issue slots the implemented near-field loop needs per pair at least (transcendentals co-issue): three FP64
 # differences and their conversions to FP32 (6), |d|^2 (3), then Laplace a complex multiply-add (2), Helmholtz
 # r = |d|^2 / |d| (1), cos / r and sin / r (2) and a complex multiply-add (4).  The slot utilisation is reported

@@ -2455,7 +2455,43 @@ __device__ __forceinline__ NearPass near_next_pass(int rem) {
 struct NearSmem {
     double x[kNearSlots], y[kNearSlots], z[kNearSlots];   // part[] reuses x and y after the last chunk
     float2 u[kNearSlots];
+    float2 sp[kNearSlots];                                 // source-side sums of a chunk (symmetric pairs)
 };
+
+// Stage the chunk's sources c0 ... c0 + cnt - 1 (relative to the target centre, scaled) for R lane rows of
+// `steps` sources each: source jj at slot (jj / steps) * so + jj % steps, zero sources in the slots of
+// cnt <= jj < R * steps (at most 127).  d.two_over_dl is 2 / d_l of the descriptor's level.
+__device__ __forceinline__ void near_stage_chunk(const LDesc &d, NearSmem &sm, int c0, int cnt, int R, int steps,
+                                                 int so, double cx, double cy, double cz, double scale,
+                                                 float uscale) {
+    const int lane = threadIdx.x;
+    // zero sources sit at (2, 2, 2) d_l from the target centre: no target is there (each lies within d_l / 2 of
+    // its centre on every axis), so every pair with them has r > 0 and adds exactly zero, and their phases stay
+    // within the bound of the level's near pairs
+    const double pad = 4.0 / d.two_over_dl * scale;
+    const uint32_t mul = (65536u + (uint32_t)steps - 1u) / (uint32_t)steps;   // jj / steps for jj < 128
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int jj = lane + 64 * h;
+        if (jj < R * steps) {
+            const int qd = (int)(((uint32_t)jj * mul) >> 16);
+            const int slot = qd * so + (jj - qd * steps);
+            if (jj < cnt) {
+                const int j = c0 + jj;
+                sm.x[slot] = (d.sxs[j] - cx) * scale;
+                sm.y[slot] = (d.sys[j] - cy) * scale;
+                sm.z[slot] = (d.szs[j] - cz) * scale;
+                const float2 uu = d.u[j];
+                sm.u[slot] = make_float2(uu.x * uscale, uu.y * uscale);
+            } else {
+                sm.x[slot] = sm.y[slot] = sm.z[slot] = pad;   // padding: zero sources
+                sm.u[slot] = make_float2(0.f, 0.f);
+            }
+        }
+    }
+    __syncthreads();
+}
 
 template <bool HELM, bool DN, bool BIG, bool CHK>
 __device__ __forceinline__ void near_pair(double x, double y, double z, float nx, float ny, float nz, double sx,
@@ -2498,7 +2534,7 @@ __device__ __forceinline__ void near_range(const NearSmem &sm, int base, int ste
                                            const double (&y)[T], const double (&z)[T], const float (&nx)[T],
                                            const float (&ny)[T], const float (&nz)[T], float (&are)[T],
                                            float (&aim)[T]) {
-    constexpr int U = 4 / T;
+    constexpr int U = T >= 4 ? 1 : 4 / T;
     int q = 0;
     for (; q + U <= steps; q += U) {
 #pragma unroll
@@ -2560,28 +2596,7 @@ __device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, int t, i
         for (int c0 = j0; c0 < j1; c0 += 64) {
             const int cnt = min(64, j1 - c0);
             const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
-            const uint32_t mul = (65536u + (uint32_t)steps - 1u) / (uint32_t)steps;   // jj / steps for jj < 128
-            __syncthreads();
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int jj = lane + 64 * h;
-                if (jj < R * steps) {
-                    const int qd = (int)(((uint32_t)jj * mul) >> 16);
-                    const int slot = qd * so + (jj - qd * steps);
-                    if (jj < cnt) {
-                        const int j = c0 + jj;
-                        sm.x[slot] = (d.sxs[j] - cx) * scale;
-                        sm.y[slot] = (d.sys[j] - cy) * scale;
-                        sm.z[slot] = (d.szs[j] - cz) * scale;
-                        const float2 uu = d.u[j];
-                        sm.u[slot] = make_float2(uu.x * uscale, uu.y * uscale);
-                    } else {
-                        sm.x[slot] = sm.y[slot] = sm.z[slot] = 0.0;   // padding: zero sources
-                        sm.u[slot] = make_float2(0.f, 0.f);
-                    }
-                }
-            }
-            __syncthreads();
+            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale);
             const int base = valid ? r * so : 0;     // idle lanes read staged slots and discard their sums
             if (chk)
                 near_range<HELM, DN, BIG, true, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
@@ -2651,6 +2666,206 @@ k_near_dn(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
     near_body<HELM, true, BIG>(descs[wk.x], wk);
 }
 
+// ------------------------------------------------------------------ near field, one set (symmetric pairs)
+// Sources and targets one set: G(x, y) = G(y, x), so an unordered pair of distinct neighbour boxes {t, s} is
+// evaluated once, by the block of the lower box index: each pair's kernel value gives both v_i += G u_j (target
+// side, in the lane's registers as above) and w_j += G u_i (source side).  The lanes form 4 rows of 16; a row
+// holds 16 T targets (T = 1 ... 8 per lane, target slot gi + 16 k) and takes a contiguous range of the staged
+// sources.  The source-side sums of a staged source over the row's 16 lanes are added in a fixed tree
+// (data-parallel shifts within the row), and the chunk's sums are written, in order, to the entry's slice of a
+// buffer (offset near_off[e]); passes after the first add to it.  The box itself (ordered, with the r > 0
+// test) and lower neighbours without a reverse entry are evaluated as in k_near; lower neighbours with one are
+// skipped here and added afterwards from the buffer by k_near_gather, in list order.  Passes hold up to 80
+// targets (T <= 5: more targets per lane would cost registers, hence resident waves, more than they save).
+template <int N>
+__device__ __forceinline__ float dpp_row_shr(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 | N, 0xF, 0xF,
+                                                                  true));
+}
+
+// inclusive sum over each 16-lane row: the row's total in its last lane
+__device__ __forceinline__ float row_sum16(float v) {
+    v += dpp_row_shr<1>(v);
+    v += dpp_row_shr<2>(v);
+    v += dpp_row_shr<4>(v);
+    v += dpp_row_shr<8>(v);
+    return v;
+}
+
+// nuy = -us.y and nty = -ut.y keep every product an FMA without a negation
+template <bool HELM, bool BIG>
+__device__ __forceinline__ void near_pair_sym(double x, double y, double z, float2 ut, float nty, double sx, double sy,
+                                              double sz, float2 us, float nuy, float &are, float &aim, float &sre,
+                                              float &sim) {
+    const float dx = (float)(x - sx), dy = (float)(y - sy), dz = (float)(z - sz);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float inv = __builtin_amdgcn_rsqf(r2);   // distinct boxes of one set, padding far away: r > 0
+    if (HELM) {
+        const float rr = r2 * inv;
+        float sn, cs;
+        sincos_rev(BIG ? __builtin_amdgcn_fractf(rr) : rr, sn, cs);
+        const float gr = cs * inv, gi = sn * inv;
+        are = fmaf(gi, nuy, fmaf(gr, us.x, are));
+        aim = fmaf(gi, us.x, fmaf(gr, us.y, aim));
+        sre = fmaf(gi, nty, fmaf(gr, ut.x, sre));
+        sim = fmaf(gi, ut.x, fmaf(gr, ut.y, sim));
+    } else {
+        are = fmaf(inv, us.x, are);
+        aim = fmaf(inv, us.y, aim);
+        sre = fmaf(inv, ut.x, sre);
+        sim = fmaf(inv, ut.y, sim);
+    }
+}
+
+template <bool HELM, bool BIG, int T>
+__device__ __forceinline__ void near_pass_sym(const LDesc &d, NearSmem &sm, int t, int i0, int nt, bool first,
+                                              double scale, float uscale) {
+    constexpr int g = 16, R = 4;
+    const int lane = threadIdx.x;
+    const int r = lane >> 4, gi = lane & 15;
+    const bool last = gi == g - 1;
+    const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
+    double x[T], y[T], z[T];
+    float nx[T], ny[T], nz[T], are[T], aim[T], nty[T];
+    float2 ut[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        // a slot past nt repeats target 0 with zero input: its source-side terms are zero, its own sums discarded
+        const int ti = gi + g * k;
+        const int i = i0 + (ti < nt ? ti : 0);
+        x[k] = (d.txs[i] - cx) * scale;
+        y[k] = (d.tys[i] - cy) * scale;
+        z[k] = (d.tzs[i] - cz) * scale;
+        nx[k] = ny[k] = nz[k] = 0.f;
+        are[k] = aim[k] = 0.f;
+        const float2 uu = d.u[i];
+        ut[k] = ti < nt ? make_float2(uu.x * uscale, uu.y * uscale) : make_float2(0.f, 0.f);
+        nty[k] = -ut[k].y;
+    }
+    const int64_t e0 = d.near_ptr[t], e1 = d.near_ptr[t + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+        const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
+        const int64_t off = d.near_off[e];
+        if (s < t && off >= 0) continue;          // the block of box s evaluates this pair of boxes
+        const int j0 = __builtin_amdgcn_readfirstlane(d.sstart[s]), j1 = __builtin_amdgcn_readfirstlane(d.sstart[s + 1]);
+        for (int c0 = j0; c0 < j1; c0 += 64) {
+            const int cnt = min(64, j1 - c0);
+            const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
+            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale);
+            const int base = r * so;
+            if (s == t) {
+                near_range<HELM, false, BIG, true, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
+            } else if (s < t) {
+                near_range<HELM, false, BIG, false, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
+            } else {
+                const int jb = r * steps;
+                for (int q = 0; q < steps; ++q) {
+                    const int sl = base + q;
+                    const double sx = sm.x[sl], sy = sm.y[sl], sz = sm.z[sl];
+                    const float2 us = sm.u[sl];
+                    const float nuy = -us.y;
+                    float sre = 0.f, sim = 0.f;
+#pragma unroll
+                    for (int k = 0; k < T; ++k)
+                        near_pair_sym<HELM, BIG>(x[k], y[k], z[k], ut[k], nty[k], sx, sy, sz, us, nuy, are[k], aim[k],
+                                                 sre, sim);
+                    sre = row_sum16(sre);
+                    sim = row_sum16(sim);
+                    if (last) sm.sp[jb + q] = make_float2(sre, sim);   // slots past cnt are never read
+                }
+                __syncthreads();
+                if (lane < cnt) {
+                    float2 *o = d.nsym + off + (c0 - j0) + lane;
+                    float2 a = sm.sp[lane];
+                    if (!first) {
+                        const float2 b = *o;
+                        a.x += b.x;
+                        a.y += b.y;
+                    }
+                    *o = a;
+                }
+            }
+        }
+    }
+    float2 *part = reinterpret_cast<float2 *>(sm.x);   // [T][64] over x, y, z and u (T <= 5)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < T; ++k) part[k * 64 + lane] = make_float2(are[k], aim[k]);
+    __syncthreads();
+    if (lane < g) {
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            const int ti = lane + g * k;
+            if (ti >= nt) break;
+            float2 a = part[k * 64 + lane];
+#pragma unroll
+            for (int rr = 1; rr < R; ++rr) {
+                const float2 b = part[k * 64 + lane + rr * g];
+                a.x += b.x;
+                a.y += b.y;
+            }
+            float2 o = d.v[i0 + ti];
+            o.x += a.x;
+            o.y += a.y;
+            d.v[i0 + ti] = o;
+        }
+    }
+}
+
+template <bool HELM, bool BIG>
+__global__ void __launch_bounds__(64)
+k_near_sym(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    __shared__ NearSmem sm;
+    static_assert(sizeof(NearSmem) >= 5 * 64 * sizeof(float2) + sizeof(float2) * kNearSlots, "part[] must fit");
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
+    const int ta = d.tstart[t], tz = d.tstart[t + 1];
+    const double kr = (double)d.k_rev;
+    const double scale = HELM ? kr : 1.0;
+    const float uscale = (float)((1.0 / (4.0 * M_PI)) * (HELM ? kr : 1.0));
+    for (int i0 = ta; i0 < tz;) {
+        const int nt = min(80, tz - i0);
+        const int T = (nt + 15) >> 4;
+        const bool first = i0 == ta;
+        switch (T) {
+            case 1: near_pass_sym<HELM, BIG, 1>(d, sm, t, i0, nt, first, scale, uscale); break;
+            case 2: near_pass_sym<HELM, BIG, 2>(d, sm, t, i0, nt, first, scale, uscale); break;
+            case 3: near_pass_sym<HELM, BIG, 3>(d, sm, t, i0, nt, first, scale, uscale); break;
+            case 4: near_pass_sym<HELM, BIG, 4>(d, sm, t, i0, nt, first, scale, uscale); break;
+            default: near_pass_sym<HELM, BIG, 5>(d, sm, t, i0, nt, first, scale, uscale); break;
+        }
+        i0 += nt;
+    }
+}
+
+// v_i += the source-side sums that lower neighbour boxes computed for box b's points (list order).  Item
+// (desc, box b).
+__global__ void __launch_bounds__(64)
+k_near_gather(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int b = wk.y;
+    const int ta = d.tstart[b], tz = d.tstart[b + 1];
+    const int64_t e0 = d.near_ptr[b], e1 = d.near_ptr[b + 1];
+    for (int i = ta + (int)threadIdx.x; i < tz; i += 64) {
+        float2 a = make_float2(0.f, 0.f);
+        for (int64_t e = e0; e < e1; ++e) {
+            const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
+            const int64_t off = d.near_off[e];
+            if (s < b && off >= 0) {
+                const float2 w = d.nsym[off + (i - ta)];
+                a.x += w.x;
+                a.y += w.y;
+            }
+        }
+        float2 o = d.v[i];
+        o.x += a.x;
+        o.y += a.y;
+        d.v[i] = o;
+    }
+}
+
 typedef void (*KernelFn)(const LDesc *, const IoEntry *, const int4 *);
 
 KernelFn kernel_of(const Stage &S, int &threads) {
@@ -2703,6 +2918,10 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_ACA: threads = 64 * std::max(1, S.a); return k_lag_aca;
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? (S.a ? k_near<true, true> : k_near<true, false>) : k_near<false, false>;
+        case K_NEAR_SYM:
+            threads = 64;
+            return S.b ? (S.a ? k_near_sym<true, true> : k_near_sym<true, false>) : k_near_sym<false, false>;
+        case K_NEAR_GATHER: threads = 64; return k_near_gather;
         case K_NEAR_DN:
             threads = 64;
             return S.b ? (S.a ? k_near_dn<true, true> : k_near_dn<true, false>) : k_near_dn<false, false>;
@@ -2878,6 +3097,8 @@ std::string kernel_name(int kern, int a, int b) {
         case K_ACA: return "k_lag_aca";
         case K_INTERP: return "k_lag_interp";
         case K_NEAR: return "k_near<" + tf(b) + ", " + tf(b && a) + ">";
+        case K_NEAR_SYM: return "k_near_sym<" + tf(b) + ", " + tf(b && a) + ">";
+        case K_NEAR_GATHER: return "k_near_gather";
         case K_NEAR_DN: return "k_near_dn<" + tf(b) + ", " + tf(b && a) + ">";
         case K_INTERP_DN: return "k_lag_interp_dn";
         case K_BWD_PAIR_DN: return "k_pw_backward_dn<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";

@@ -46,8 +46,12 @@ int stage_role(const Stage &S) {
         case K_BWD_PAIR: case K_BWD_RING: case K_INTERP: case K_GPHIT: case K_BWD_PAIR_DN: case K_INTERP_DN: return 4;
         case K_BSUM: case K_GZT: return 5;
         case K_GINTERP: return 6;
-        case K_NEAR: case K_NEAR_DN: case K_ZERO_OUT: return 0;
-        case K_PERM_OUT: return 1;
+        // after the levels: the near fields of the early lists and the leaf in level order (they add into the same
+        // outputs), the symmetric pairs' source-side sums, then the output permutation
+        case K_ZERO_OUT: return 0;
+        case K_NEAR: case K_NEAR_DN: case K_NEAR_SYM: return 1 + S.level;
+        case K_NEAR_GATHER: return 1 + kMaxLev + 1;
+        case K_PERM_OUT: return 1 + kMaxLev + 2;
         default: throw Error(FFM_EINTERNAL, "stage without a batch order");
     }
 }

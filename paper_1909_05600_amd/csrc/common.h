@@ -206,6 +206,10 @@ struct LDesc {
     const int32_t *sstart;
     const int64_t *far_ptr, *near_ptr;
     const int32_t *far_src, *far_cls, *near_src;
+    const int64_t *near_off;               // leaf of one set: per near entry, the offset of the pair's
+                                           // source-side sums in nsym (s > t), or of the reverse entry's (s < t
+                                           // with a reverse entry), else -1
+    float2 *nsym;                          // source-side sums of the symmetric near pairs
     const int32_t *tr_tgt;                 // target boxes of the transfers, in Morton order
     int ntr, ncls;                         // their number; translation classes
     // Gegenbauer level
@@ -247,7 +251,8 @@ struct LDesc {
 enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
     K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
-    K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA, K_NEAR_DN, K_BWD_PAIR_DN, K_INTERP_DN
+    K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA, K_NEAR_DN, K_BWD_PAIR_DN, K_INTERP_DN,
+    K_NEAR_SYM, K_NEAR_GATHER
 };
 
 struct Stage {
@@ -289,6 +294,7 @@ struct Level {
     // descent lists, CSR by target box of this level; sources ascending
     int64_t nfar = 0, nnear = 0;
     DevBuf<int64_t> far_ptr, near_ptr;   // [nbox_x + 1]
+    DevBuf<int64_t> near_off;            // leaf of one set: per near entry (LDesc::near_off)
     DevBuf<int32_t> far_src, far_cls;    // [nfar]   (cls: compact translation class)
     DevBuf<int32_t> near_src;            // [nnear]
     // per-pair leaf rule: the near pairs summed densely at this level (both boxes small), CSR by target box
@@ -379,6 +385,9 @@ struct Plan {
     DevBuf<float4> wpart;                // forward-transform partial sums of point segments
     DevBuf<float2> wbpart;               // target-transform partial sums of ring parts
     DevBuf<float2> wG, wH;               // grid-form workspaces (grid values, ring sums)
+    bool near_sym = false;               // leaf near field over unordered box pairs (one set, G symmetric)
+    int64_t nsym = 0;                    // source-side sums of those pairs (points of the higher boxes)
+    DevBuf<float2> wnsym;
     bool any_grid = false;
     DevBuf<float> amax;                  // max |Re u|, |Im u| of the current apply (FP16 scaling)
     bool any_fp16 = false;
@@ -428,6 +437,7 @@ struct LevelWork {                     // apply workspace a descriptor points in
     float4 *ut = nullptr, *vt = nullptr, *part = nullptr;
     float2 *ut2 = nullptr, *Z = nullptr, *bpart = nullptr;
     float2 *G = nullptr, *H = nullptr;
+    float2 *nsym = nullptr;
 };
 // Apply workspace laid out in one block (requests of the server, the static-scratch apply): its size in bytes
 // (every part aligned to 256 B; also what ffm_workspace_bytes and ffm_stats_t.workspace_bytes report), and the
@@ -462,8 +472,8 @@ void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream
 // device primitives (scan_sort.hip)
 // (temporaries come from the scratch list; nothing here synchronises the stream)
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t st, Scratch &S);  // out[n] = total
-// Both scans at once (n <= 4096 tiles of 2048); the two totals also go to host_tot[0..1] (host-visible memory,
-// valid once the stream has passed the scan).
+// Both scans at once (n <= 4096 tiles of 2048): oa and ob hold n + 1 elements, the totals going to oa[n] and
+// ob[n] and also to host_tot[0..1] (host-visible memory, valid once the stream has passed the scan).
 void exclusive_scan2_i64(const int64_t *a, int64_t *oa, const int64_t *b, int64_t *ob, int64_t n, int64_t *host_tot,
                          hipStream_t st, Scratch &S);
 void radix_sort_u64_u32(uint64_t *keys, int32_t *vals, int64_t n, hipStream_t st, Scratch &S);      // stable

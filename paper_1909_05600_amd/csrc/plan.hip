@@ -410,6 +410,54 @@ k_near_pairs(const int64_t *ptr, const int32_t *src, int32_t nbx, const int32_t 
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
+// Symmetric near field of one set (leaf): per target box t, the points of its higher neighbours (the lengths of
+// the source-side slices its block writes) ...
+__global__ void __launch_bounds__(kThreads)
+k_sym_box_count(const int64_t *ptr, const int32_t *src, int32_t nb, const int32_t *start, int64_t *cnt) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    int64_t c = 0;
+    for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+        const int32_t s = src[e];
+        if (s > t) c += start[s + 1] - start[s];
+    }
+    cnt[t] = c;
+}
+
+// ... the slice of each entry with s > t (in list order from the box's scanned offset), -1 for the others ...
+__global__ void __launch_bounds__(kThreads)
+k_sym_fill(const int64_t *ptr, const int32_t *src, int32_t nb, const int32_t *start, const int64_t *boff,
+           int64_t *off) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    int64_t o = boff[t];
+    for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+        const int32_t s = src[e];
+        if (s > t) {
+            off[e] = o;
+            o += start[s + 1] - start[s];
+        } else {
+            off[e] = -1;
+        }
+    }
+}
+
+// ... and for an entry with s < t, the slice of the reverse entry (t in the list of s) if there is one.
+__global__ void __launch_bounds__(kThreads)
+k_sym_reverse(const int64_t *ptr, const int32_t *src, int32_t nb, int64_t *off) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+        const int32_t s = src[e];
+        if (s >= t) continue;
+        for (int64_t f = ptr[s]; f < ptr[s + 1]; ++f)
+            if (src[f] == t) {
+                off[e] = off[f];
+                break;
+            }
+    }
+}
+
 // Far-list windows to class numbers: every block numbers the used windows itself (in window order, a block
 // scan of the flags into LDS), then maps its entries.
 __global__ void __launch_bounds__(kThreads) k_remap(int32_t *cls, int64_t n, const int32_t *used) {
@@ -1026,11 +1074,12 @@ struct WorkFetch {
     int64_t *ptr = nullptr;
     uint8_t *act = nullptr;
     unsigned long long *near_pairs = nullptr;
+    int64_t *sym_tot = nullptr;          // symmetric leaf near field: length of the source-side buffer
     int nbx = 0, nby = 0;
 };
 
 void fetch_work_lists(Level &LV, const TreeLevel &LX, const TreeLevel &LY, bool near, hipStream_t st, Scratch &SC,
-                      WorkFetch &F) {
+                      WorkFetch &F, bool sym = false) {
     F.nbx = LX.nbox;
     F.nby = LY.nbox;
     F.sx = SC.pin<int32_t>(LX.nbox + 1);
@@ -1049,6 +1098,22 @@ void fetch_work_lists(Level &LV, const TreeLevel &LX, const TreeLevel &LY, bool 
             FFM_LAUNCH(k_near_pairs, nblocks(LX.nbox), kThreads, 0, st, LV.near_ptr.p, LV.near_src.p, LX.nbox,
                        LX.start.p, LY.start.p, dn);
             FFM_HIP(hipMemcpyAsync(F.near_pairs, dn, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        }
+        if (sym && LV.nnear) {
+            // offsets of the symmetric pairs' source-side slices (one tree: LX is LY)
+            // the scan writes its totals after the last element: outputs of nbox + 1
+            int64_t *cnt = SC.get<int64_t>(LX.nbox), *boff = SC.get<int64_t>(LX.nbox + 1);
+            int64_t *boff2 = SC.get<int64_t>(LX.nbox + 1);
+            F.sym_tot = SC.pin<int64_t>(2);
+            F.sym_tot[0] = F.sym_tot[1] = 0;
+            FFM_LAUNCH(k_sym_box_count, nblocks(LX.nbox), kThreads, 0, st, LV.near_ptr.p, LV.near_src.p, LX.nbox,
+                       LX.start.p, cnt);
+            exclusive_scan2_i64(cnt, boff, cnt, boff2, LX.nbox, F.sym_tot, st, SC);
+            LV.near_off.alloc((size_t)LV.nnear);
+            FFM_LAUNCH(k_sym_fill, nblocks(LX.nbox), kThreads, 0, st, LV.near_ptr.p, LV.near_src.p, LX.nbox,
+                       LX.start.p, boff, LV.near_off.p);
+            FFM_LAUNCH(k_sym_reverse, nblocks(LX.nbox), kThreads, 0, st, LV.near_ptr.p, LV.near_src.p, LX.nbox,
+                       LV.near_off.p);
         }
     } else {
         uint8_t *dact = SC.get<uint8_t>(std::max(LY.nbox, 1));
@@ -1355,7 +1420,10 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         if (P.lev[l].nfar) fetch_work_lists(P.lev[l], TX.lev[l], TY.lev[l], false, st, SC, wf[l]);
         if (l < P.leaf && P.lev[l].nearly) fetch_early_lists(P.lev[l], TX.lev[l], TY.lev[l], st, SC, wf_early[l]);
     }
-    fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near);
+    // one set: the leaf near field evaluates each unordered pair of distinct boxes once (G is symmetric; the
+    // normal derivative at the target is not)
+    P.near_sym = P.same && !P.dn;
+    fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near, P.near_sym);
     int32_t *used_h = SC.pin<int32_t>((size_t)kWin3 * (P.leaf + 1) + 1);
     for (int l = 1; l <= P.leaf; ++l)
         FFM_HIP(hipMemcpyAsync(used_h + (size_t)kWin3 * l, win_used[l], sizeof(int32_t) * kWin3,
@@ -1696,6 +1764,9 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     }
     plog.mark("tables");
     build_work_lists(P, P.lev[P.leaf], true, wf_near);
+    P.nsym = wf_near.sym_tot ? wf_near.sym_tot[0] : 0;
+    if (!wf_near.sym_tot) P.near_sym = false;
+    P.wnsym.alloc((size_t)std::max<int64_t>(P.nsym, 0));
     for (int l = 1; l < P.leaf; ++l)
         if (P.lev[l].nearly) build_early_lists(P.lev[l], wf_early[l]);
     (void)ws_part;
@@ -2121,8 +2192,14 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             for (int32_t t : P.lev[l].h_early) er.push_back(make_int4(l, t, 0, 0));
             P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, big(l), nhelm, -1, l, 0, std::move(er), st, SC));
         }
-        P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, big(P.leaf), nhelm, 61, P.leaf, 0, std::move(nr),
-                                    st, SC));
+        if (P.near_sym) {
+            std::vector<int4> ga = nr;
+            P.post.push_back(make_stage(K_NEAR_SYM, big(P.leaf), nhelm, -1, P.leaf, 0, std::move(nr), st, SC));
+            P.post.push_back(make_stage(K_NEAR_GATHER, 0, 0, 61, P.leaf, 0, std::move(ga), st, SC));
+        } else {
+            P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, big(P.leaf), nhelm, 61, P.leaf, 0, std::move(nr),
+                                        st, SC));
+        }
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
     }
     // timing slot of every stage: a stage that closes no phase belongs to the next one that does
@@ -2183,6 +2260,8 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     const bool early = l < P.leaf && LV.nearly > 0;
     d.near_ptr = early ? LV.early_ptr.p : LV.near_ptr.p;
     d.near_src = early ? LV.early_src.p : LV.near_src.p;
+    d.near_off = l == P.leaf && P.near_sym ? LV.near_off.p : nullptr;
+    d.nsym = l == P.leaf && P.near_sym ? w.nsym : nullptr;
     d.dirs = LV.dirs.p;
     d.dirs64 = LV.dirs64.p;
     d.rings = LV.rings.p;
@@ -2214,7 +2293,7 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.grp_cls = LV.grp_cls.p;
     d.ut2 = w.ut2;
     d.Z = w.Z;
-    d.two_over_dl = l > 0 ? 2.0 / std::ldexp(P.d0, -l) : 0.0;
+    d.two_over_dl = 2.0 / std::ldexp(P.d0, -l);
     d.r1 = LV.r1;
     d.rp = LV.rp;
     d.maxpts = LV.max_src_pts;
@@ -2250,6 +2329,7 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     w.bpart = P.wbpart.p;
     w.G = P.wG.p;
     w.H = P.wH.p;
+    w.nsym = P.wnsym.p;
     P.hdesc.clear();
     for (int l = 0; l <= P.leaf; ++l) P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
@@ -2277,10 +2357,10 @@ size_t plan_device_bytes(const Plan &P) {
              L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes() + L.acaA.bytes() +
              L.acaB.bytes() + L.acaKp.bytes() + L.Ez.bytes() +
              L.Ex.bytes() + L.Ey.bytes() + L.ExT.bytes() + L.EyT.bytes() + L.gperm.bytes() + L.gzs.bytes() + L.gxyz.bytes() +
-             L.tr_tgt.bytes();
+             L.tr_tgt.bytes() + L.near_off.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
-         P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes();
+         P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes() + P.wnsym.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
     b += P.items.bytes();
     return b;

@@ -40,7 +40,8 @@ size_t apply_work_bytes(const Plan &P) {
     return align256(sizeof(float2) * P.ny) + align256(sizeof(float2) * P.nx) + align256(sizeof(float4) * P.ws_src) +
            align256(sizeof(float4) * P.ws_tgt) + align256(sizeof(float2) * P.ws_z) +
            align256(sizeof(float4) * P.wpart.n) + align256(sizeof(float2) * P.wbpart.n) +
-           align256(sizeof(float2) * P.wG.n) + align256(sizeof(float2) * P.wH.n) + (P.any_fp16 || P.any_grid ? 256 : 0);
+           align256(sizeof(float2) * P.wG.n) + align256(sizeof(float2) * P.wH.n) + align256(sizeof(float2) * P.wnsym.n) +
+           (P.any_fp16 || P.any_grid ? 256 : 0);
 }
 
 WorkPtrs carve_work(const Plan &P, char *p) {
@@ -60,6 +61,7 @@ WorkPtrs carve_work(const Plan &P, char *p) {
     w.lw.bpart = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wbpart.n));
     w.lw.G = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wG.n));
     w.lw.H = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wH.n));
+    w.lw.nsym = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wnsym.n));
     w.amax = P.any_fp16 || P.any_grid ? reinterpret_cast<float *>(take(sizeof(float))) : nullptr;
     return w;
 }
