@@ -273,6 +273,70 @@ k_pw_transfer_grp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, 
     transfer_target<1, 64>(d, __builtin_amdgcn_readfirstlane(d.tr_tgt[ti]), (int64_t)wk.z * 64 + (threadIdx.x & 63));
 }
 
+// The transfer by sibling group (one tree): wave w of a block takes group 4 item.y + w, up to four targets of one
+// parent box, on a tile of 64 pairs.  The group's far sources are visited once each (in position order): u~_s is read
+// once and applied to every sibling whose far list holds s, with that pair's D.  Item (desc, block of four
+// groups, tile).
+__global__ void __launch_bounds__(kThreads)
+k_pw_transfer_sib(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int g = __builtin_amdgcn_readfirstlane(wk.y * 4 + (int)(threadIdx.x >> 6));
+    if (g >= d.nsibg) return;
+    const int64_t npair = d.npair;
+    const int64_t p0 = (int64_t)wk.z * 64 + (threadIdx.x & 63);
+    const bool active = p0 < npair;
+    const int64_t p = active ? p0 : npair - 1;       // idle lanes read a valid pair and store nothing
+    const float4 *__restrict__ D = d.D;
+    const float4 *__restrict__ ut = d.ut;
+    float4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int n = __builtin_amdgcn_readfirstlane(d.sib_cnt[g]);
+    const int32_t *src = d.sib_src + (int64_t)216 * g;
+    const uint2 *cls = d.sib_cls + (int64_t)216 * g;
+    const int lane = threadIdx.x & 63;
+    // the group's slots in chunks of 64, one per lane (one load and wait per chunk), then taken from the lanes'
+    // registers slot by slot
+    for (int c0 = 0; c0 < n; c0 += 64) {
+        const int nch = min(64, n - c0);
+        int src_l = 0;
+        uint2 cls_l = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+        if (lane < nch) {
+            src_l = src[c0 + lane];
+            cls_l = cls[c0 + lane];
+        }
+        for (int k = 0; k < nch; ++k) {
+            const int64_t sv = __builtin_amdgcn_readlane(src_l, k);
+            const uint32_t wds[2] = {(uint32_t)__builtin_amdgcn_readlane((int)cls_l.x, k),
+                                     (uint32_t)__builtin_amdgcn_readlane((int)cls_l.y, k)};
+            const float4 w = ut[sv * npair + p];
+            float4 q[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = (int)(int16_t)(wds[j >> 1] >> (16 * (j & 1)));
+                if (c >= 0) q[j] = D[(int64_t)c * npair + p];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = (int)(int16_t)(wds[j >> 1] >> (16 * (j & 1)));
+                if (c >= 0) {
+                    acc[j].x = fmaf(q[j].x, w.x, fmaf(-q[j].y, w.y, acc[j].x));
+                    acc[j].y = fmaf(q[j].x, w.y, fmaf(q[j].y, w.x, acc[j].y));
+                    acc[j].z = fmaf(q[j].z, w.z, fmaf(-q[j].w, w.w, acc[j].z));
+                    acc[j].w = fmaf(q[j].z, w.w, fmaf(q[j].w, w.z, acc[j].w));
+                }
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int t = __builtin_amdgcn_readfirstlane(d.sib_tgt[4 * g + j]);
+        if (t >= 0) d.vt[(int64_t)t * npair + p0] = acc[j];
+    }
+}
+
 // The same transfer for levels with many direction pairs per box.  Block: a
 // tile of QT direction pairs for 256 / QT target boxes (consecutive in Morton order); the tile of every class's
 // D is staged in LDS once per block, so each far pair reads D from LDS and only u~ from memory.  Four far pairs
@@ -2896,6 +2960,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
                 case 1001: return k_pw_transfer_lds<1>;
                 case 101: threads = 64; return k_pw_transfer<1, 64>;
                 case 201: return k_pw_transfer_grp;
+                case 301: return k_pw_transfer_sib;
                 case 2: return k_pw_transfer<2, kThreads>;
                 default: return k_pw_transfer<1, kThreads>;
             }
@@ -3086,6 +3151,7 @@ std::string kernel_name(int kern, int a, int b) {
             if (a > 1000) return "k_pw_transfer_lds<" + std::to_string(a - 1000) + ">";
             if (a == 101) return "k_pw_transfer<1, 64>";
             if (a == 201) return "k_pw_transfer_grp";
+            if (a == 301) return "k_pw_transfer_sib";
             return "k_pw_transfer<" + std::to_string(a == 2 ? 2 : 1) + ", 256>";
         case K_BWD_PAIR: return "k_pw_backward<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
         case K_BWD_RING:

@@ -212,6 +212,9 @@ struct LDesc {
     float2 *nsym;                          // source-side sums of the symmetric near pairs
     const int32_t *tr_tgt;                 // target boxes of the transfers, in Morton order
     int ntr, ncls;                         // their number; translation classes
+    const int32_t *sib_tgt, *sib_src, *sib_cnt;   // transfers by sibling group (Level::sib_*)
+    const uint2 *sib_cls;
+    int nsibg;
     // Gegenbauer level
     const float4 *dirs;
     const double *dirs64;
@@ -331,6 +334,13 @@ struct Level {
     DevBuf<double> dirs64;               // [npair][3] direction * k / (2 pi), FP64
     DevBuf<float4> D;                    // [ncls][npair] (D(s_p), D(-s_p)) as two complex
     DevBuf<int32_t> tr_tgt;              // target boxes with far work in Morton order (transfer slots)
+    // transfers by sibling group (one tree): up to four targets of one parent box, [ngroup][4] (-1 past the
+    // last); the sources of their far pairs, [ngroup][216] by position relative to the parent (compacted,
+    // sib_cnt per group), with each sibling's class ([ngroup][216] x 4 int16, -1 where that pair is not far)
+    int32_t nsibg = 0;
+    DevBuf<int32_t> sib_tgt, sib_src, sib_cnt;
+    DevBuf<uint2> sib_cls;
+    std::vector<int32_t> h_par;          // parent of every target box (one tree, far levels)
     bool phase64 = false;                // FP64 phase reduction at this level
     // ring-pair form of the transforms: ring m and its antipodal ring share one in-plane phase
     int nrp = 0;                         // ring pairs: (L+1)/2 rounded up (the equator ring when L is even)
