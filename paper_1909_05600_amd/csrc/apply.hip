@@ -25,7 +25,9 @@ constexpr int kThreads = 256;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 using gch4 = const __attribute__((address_space(1))) half4_t *;
+using gch8 = const __attribute__((address_space(1))) half8_t *;
 
 // sin(2 pi x), cos(2 pi x) for x in revolutions.  The hardware reduces its argument itself over
 // |x| <= 256 revolutions; against an exact reduction to [0, 1) first it differs by at most 2.4e-7
@@ -2269,9 +2271,9 @@ k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
     }
 }
 
-// Mixed precision: the same class-group products on FP16 MFMA (v_mfma_f32_32x32x8f16) with FP32
-// accumulation.  A[i][k] comes from lane i + 32 (k / 4) (element k % 4 of a half4), B[k][j] from lane
-// j + 32 (k / 4); D as for the FP32 instruction.  T16 = T * sT (plan time); the sources are scaled by a
+// Mixed precision: the same class-group products on FP16 MFMA (v_mfma_f32_32x32x16_f16, K = 16 per
+// instruction) with FP32 accumulation.  A[i][k] comes from lane i + 32 (k / 8) (element k % 8 of a half8),
+// B[k][j] from lane j + 32 (k / 8); D as for the FP32 instruction.  T16 = T * sT (plan time); the sources are scaled by a
 // power of two s_u derived on the device from max |u| so that |u~ s_u| < 6e4; Z = C / (sT s_u).
 __device__ __forceinline__ float u_scale(float amax, int maxpts) {
     // |u~| <= (Lebesgue constant of the tensor grid, <= 8) * points * max|u|
@@ -2319,35 +2321,35 @@ k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
             acc2[v] = 0.f;
         }
         const int i = mt * 32 + col;
-        // groups of four steps (rp is a multiple of 32), operands loaded before the group's products
-        const gch4 TreG = (gch4) reinterpret_cast<const half4_t *>(Tre + (int64_t)i * rp + 4 * kh);
-        const gch4 TimG = (gch4) reinterpret_cast<const half4_t *>(Tim + (int64_t)i * rp + 4 * kh);
+        // groups of two steps of 16 (rp is a multiple of 32), operands loaded before the group's products
+        const gch8 TreG = (gch8) reinterpret_cast<const half8_t *>(Tre + (int64_t)i * rp + 8 * kh);
+        const gch8 TimG = (gch8) reinterpret_cast<const half8_t *>(Tim + (int64_t)i * rp + 8 * kh);
         // double-buffered as in the FP32 kernel
-        half4_t a1n[4], a2n[4];
+        half8_t a1n[2], a2n[2];
         auto load = [&](int k00) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k0 = k00 + 8 * u;
-                a1n[u] = TreG[k0 / 4];
+            for (int u = 0; u < 2; ++u) {
+                const int k0 = k00 + 16 * u;
+                a1n[u] = TreG[k0 / 8];
                 a2n[u] = a1n[u];
-                if (helm) a2n[u] = TimG[k0 / 4];   // Laplace tables have no imaginary part
+                if (helm) a2n[u] = TimG[k0 / 8];   // Laplace tables have no imaginary part
             }
         };
         load(0);
         for (int k00 = 0; k00 < rp; k00 += 32) {
-            half4_t bv[4], a1[4], a2[4];
+            half8_t bv[2], a1[2], a2[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                bv[u] = *reinterpret_cast<const half4_t *>(U16 + col * rp + k00 + 8 * u + 4 * kh);
+            for (int u = 0; u < 2; ++u) {
+                bv[u] = *reinterpret_cast<const half8_t *>(U16 + col * rp + k00 + 16 * u + 8 * kh);
                 a1[u] = a1n[u];
                 a2[u] = a2n[u];
             }
             if (k00 + 32 < rp) load(k00 + 32);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(a1[u], bv[u], acc1, 0, 0, 0);
-                if (helm) acc2 = __builtin_amdgcn_mfma_f32_32x32x8f16(a2[u], bv[u], acc2, 0, 0, 0);
+            for (int u = 0; u < 2; ++u) {
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[u], bv[u], acc1, 0, 0, 0);
+                if (helm) acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2[u], bv[u], acc2, 0, 0, 0);
             }
         }
         for (int v = 0; v < 16; ++v) {
