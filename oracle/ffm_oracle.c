@@ -1381,51 +1381,61 @@ int orc_num_threads(void)
 #endif
 }
 
+/* memcpy of n bytes that accepts an absent source when there is nothing to copy (empty plans keep no arrays) */
+static void copy_out(void *dst, const void *src, size_t n)
+{
+    if (n > 0 && src) memcpy(dst, src, n);
+}
+
 int orc_leaf(const orc_plan *p) { return p->empty ? 0 : p->leaf; }
 double orc_d0(const orc_plan *p) { return p->d0; }
 void orc_corner(const orc_plan *p, int set, double *c3) { memcpy(c3, p->T[set].corner, sizeof(double) * 3); }
 int64_t orc_npoints(const orc_plan *p, int set) { return p->T[set].n; }
 void orc_keys(const orc_plan *p, int set, uint64_t *keys)
 {
-    memcpy(keys, p->T[set].key, sizeof(uint64_t) * (size_t)p->T[set].n);
+    copy_out(keys, p->T[set].key, sizeof(uint64_t) * (size_t)p->T[set].n);
 }
 void orc_perm(const orc_plan *p, int set, int64_t *perm)
 {
-    memcpy(perm, p->T[set].perm, sizeof(int64_t) * (size_t)p->T[set].n);
+    copy_out(perm, p->T[set].perm, sizeof(int64_t) * (size_t)p->T[set].n);
 }
 int64_t orc_nbox(const orc_plan *p, int set, int l) { return p->empty ? 0 : p->T[set].nbox[l]; }
 void orc_box_start(const orc_plan *p, int set, int l, int64_t *start)
 {
-    memcpy(start, p->T[set].start[l], sizeof(int64_t) * (size_t)(p->T[set].nbox[l] + 1));
+    if (p->empty) {
+        start[0] = 0;
+        return;
+    }
+    copy_out(start, p->T[set].start[l], sizeof(int64_t) * (size_t)(p->T[set].nbox[l] + 1));
 }
 void orc_box_ijk(const orc_plan *p, int set, int l, int32_t *ijk)
 {
-    memcpy(ijk, p->T[set].ijk[l], sizeof(int32_t) * 3 * (size_t)p->T[set].nbox[l]);
+    if (!p->empty) copy_out(ijk, p->T[set].ijk[l], sizeof(int32_t) * 3 * (size_t)p->T[set].nbox[l]);
 }
 void orc_box_centre(const orc_plan *p, int set, int l, double *c)
 {
-    memcpy(c, p->T[set].ctr[l], sizeof(double) * 3 * (size_t)p->T[set].nbox[l]);
+    if (!p->empty) copy_out(c, p->T[set].ctr[l], sizeof(double) * 3 * (size_t)p->T[set].nbox[l]);
 }
 int64_t orc_nfar(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->far[l].n; }
 void orc_far(const orc_plan *p, int l, int64_t *t, int64_t *s, int32_t *off)
 {
     const pairs_t *F = &p->far[l];
-    memcpy(t, F->t, sizeof(int64_t) * (size_t)F->n);
-    memcpy(s, F->s, sizeof(int64_t) * (size_t)F->n);
-    memcpy(off, F->off, sizeof(int32_t) * 3 * (size_t)F->n);
+    copy_out(t, F->t, sizeof(int64_t) * (size_t)F->n);
+    copy_out(s, F->s, sizeof(int64_t) * (size_t)F->n);
+    copy_out(off, F->off, sizeof(int32_t) * 3 * (size_t)F->n);
 }
 int64_t orc_nearly(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->early[l].n; }
 void orc_early(const orc_plan *p, int l, int64_t *t, int64_t *s)
 {
-    memcpy(t, p->early[l].t, sizeof(int64_t) * p->early[l].n);
-    memcpy(s, p->early[l].s, sizeof(int64_t) * p->early[l].n);
+    copy_out(t, p->early[l].t, sizeof(int64_t) * (size_t)p->early[l].n);
+    copy_out(s, p->early[l].s, sizeof(int64_t) * (size_t)p->early[l].n);
 }
 int64_t orc_nnear(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->near[l].n; }
 void orc_near(const orc_plan *p, int l, int64_t *t, int64_t *s)
 {
     const pairs_t *N = &p->near[l];
-    memcpy(t, N->t, sizeof(int64_t) * (size_t)N->n);
-    memcpy(s, N->s, sizeof(int64_t) * (size_t)N->n);
+    copy_out(t, N->t, sizeof(int64_t) * (size_t)N->n);
+    copy_out(s, N->s, sizeof(int64_t) * (size_t)N->n);
 }
 int orc_level_method(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->method[l]; }
 int orc_level_order(const orc_plan *p, int l) { return (p->empty || l > p->leaf) ? 0 : p->order[l]; }
