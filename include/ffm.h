@@ -295,6 +295,12 @@ int32_t ffm_kernel_name(int32_t kernel, int32_t variant_a, int32_t variant_b, ch
 size_t ffm_plan_bytes(ffm_plan_t plan);
 size_t ffm_workspace_bytes(ffm_plan_t plan);
 
+/* Device bytes the library holds in live allocations (plans, batches, server
+ * workspaces), not counting freed blocks it keeps cached for reuse.  Not in
+ * the paper: memory accounting for callers, and the check that a failed call
+ * (FFM_ENOMEM included) leaves nothing allocated. */
+size_t ffm_device_bytes_live(void);
+
 /*
  * ffm_apply_static -- ffm_apply over a workspace the library holds in static
  * device memory instead of the plan's own: for callers that cannot allocate

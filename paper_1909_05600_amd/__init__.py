@@ -31,7 +31,7 @@ EXPORTED = ["ffm_plan", "ffm_apply", "ffm_destroy", "ffm_last_error", "ffm_versi
             "ffm_plan_set_tiles", "ffm_plan_get_tiles", "ffm_batch_create", "ffm_batch_apply", "ffm_batch_info",
             "ffm_batch_destroy", "ffm_server_create", "ffm_server_submit", "ffm_server_wait", "ffm_server_poll",
             "ffm_server_stats", "ffm_server_destroy", "ffm_plan_launch_timing", "ffm_kernel_name",
-            "ffm_apply_batched", "ffm_apply_static"]
+            "ffm_apply_batched", "ffm_apply_static", "ffm_device_bytes_live"]
 STATIC_WORKSPACE_BYTES = 128 << 20
 FFM_FLAG_TIMING = 1
 FFM_FLAG_DIRECT_TRANSFORMS = 2
@@ -129,6 +129,7 @@ def lib():
             "ffm_plan_timing": (C.c_int, [P, P, i32]),
             "ffm_plan_bytes": (C.c_size_t, [P]),
             "ffm_workspace_bytes": (C.c_size_t, [P]),
+            "ffm_device_bytes_live": (C.c_size_t, []),
             "ffm_plan_set_tiles": (C.c_int, [P, P, P]),
             "ffm_plan_get_tiles": (C.c_int, [P, P]),
             "ffm_batch_create": (C.c_int, [P, i32, C.c_uint32, C.c_char_p, P, P]),
@@ -223,6 +224,11 @@ def _dtype_code(t) -> int:
     if t.dtype not in _DTYPES:
         raise TypeError("wu must be complex64, complex128, float32 or float64")
     return _DTYPES[t.dtype]
+
+
+def device_bytes_live() -> int:
+    """Device bytes the library holds in live allocations (its cache of freed blocks excluded)."""
+    return int(lib().ffm_device_bytes_live())
 
 
 def kernel_name(kernel: int, variant_a: int = 0, variant_b: int = 0) -> str:

@@ -64,7 +64,7 @@ void release_cache_locked() {
 void *dev_alloc(size_t bytes) {
     const long long n = g_alloc_count.fetch_add(1);
     const long long lim = fail_after();
-    if (lim >= 0 && n >= lim) throw Error(FFM_ENOMEM, "device allocation refused by FFM_TEST_FAIL_ALLOC_AFTER");
+    if (lim >= 0 && n == lim) throw Error(FFM_ENOMEM, "device allocation refused by FFM_TEST_FAIL_ALLOC_AFTER");
     const size_t sz = round_size(bytes);
     std::lock_guard<std::mutex> lk(g_mx);
     auto it = g_free.find(sz);
@@ -446,5 +446,7 @@ ffm_status_t ffm_plan_export(ffm_plan_t plan, int32_t what, int32_t set, int32_t
 size_t ffm_plan_bytes(ffm_plan_t plan) { return plan ? plan_device_bytes(plan->P) : 0; }
 
 size_t ffm_workspace_bytes(ffm_plan_t plan) { return plan ? apply_work_bytes(plan->P) : 0; }
+
+size_t ffm_device_bytes_live(void) { return dev_bytes_live(); }
 
 }  // extern "C"

@@ -64,7 +64,8 @@ struct Guard {
         }                                                                                           \
     } while (0)
 
-// Test hook: FFM_TEST_FAIL_ALLOC_AFTER=n makes the (n+1)-th device allocation fail.
+// Test hook: FFM_TEST_FAIL_ALLOC_AFTER=n makes the (n+1)-th device allocation of the process fail (that one
+// only: later allocations go through).
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
 size_t dev_bytes_live();
