@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--bie-study", action="store_true",
                     help="only run the single-layer sphere solve (GMRES with FFM products) at --bie-n nodes")
     ap.add_argument("--bie-n", type=int, default=1 << 20)
+    ap.add_argument("--nufft-study", action="store_true",
+                    help="bake-off of the grid form's separable sums against an FFT-based type-2 NUFFT")
     ap.add_argument("--aca-study", action="store_true",
                     help="only run the ACA study (full transfer matrices against their ACA factors)")
     ap.add_argument("--bie-eps", type=float, default=1e-3)
@@ -404,6 +406,132 @@ def mixed_study(n, n_rows, reps=3):
     return out
 
 
+def _es(u, w, beta):
+    """Exponential-of-semicircle kernel exp(beta (sqrt(1 - (2u/w)^2) - 1)) on |u| < w/2 (FP64, numpy)."""
+    z = 1.0 - (2.0 * u / w) ** 2
+    return np.where(np.abs(u) < w / 2, np.exp(beta * (np.sqrt(np.maximum(z, 0.0)) - 1.0)), 0.0)
+
+
+def nufft_study(n, reps=3):
+    """Bake-off of the directions-from-grid step of the grid form (after spreading, which both forms share): the
+    separable MFMA sums of this library against the paper's suggested NUFFT route (remark closing Sec. 2.2.3), a
+    type-2 NUFFT from the box's grid to the quadrature frequencies k s_q: divide the grid by the frequency
+    kernel's inverse transform, zero-pad to (sigma p)^3, 3-D FFT (rocFFT through torch), interpolate the
+    spectrum at k s_q with an ES kernel of width wf (a sparse matrix product, hipSPARSE through torch).  Same
+    grids, boxes and directions as the 1M-sphere headline plan; times with HIP events, errors against the direct
+    sum over the grid in FP64 on 256 directions of one box."""
+    import torch
+    import ffm_workloads as W
+    import paper_1909_05600_amd as ffm
+    w = W.helmholtz_sphere(n, seed=2, eps=1e-3)
+    X = torch.from_numpy(w.X).cuda()
+    wu = torch.from_numpy(w.wu).cuda()
+    plan = ffm.Plan(X, X, ffm.FFM_HELMHOLTZ, w.k, w.eps, timing=True)
+    ours = {}
+    for _ in range(reps):
+        plan.apply(wu)
+        torch.cuda.synchronize()
+        for r in plan.launch_timing():
+            ours.setdefault((r["kernel"], r["level"]), []).append(r["ms"])
+    st = plan.stats()
+    out = {"n": n, "k": w.k, "levels": []}
+    dev = torch.device("cuda:0")
+
+    def timed(fn):
+        ts = []
+        res = None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            res = fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts)), res
+
+    for l in range(1, st["leaf"] + 1):
+        if st["tform"][l] != 3:
+            continue
+        pg, wg, L = st["grid_nodes"][l], st["grid_width"][l], st["order"][l]
+        nb = st["fwd_boxes"][l]
+        dl = st["d0"] / 2.0 ** l
+        h = dl / (pg - 1 - wg)
+        xg, wgl = np.polynomial.legendre.leggauss(L + 1)
+        phi = np.pi * np.arange(2 * L) / L
+        ct = np.repeat(xg, 2 * L)
+        stt = np.sqrt(1.0 - ct ** 2)
+        ph = np.tile(phi, L + 1)
+        om = w.k * np.stack([stt * np.cos(ph), stt * np.sin(ph), ct], axis=1)     # [nq, 3]
+        nq = om.shape[0]
+        mine = sum(np.median(v) for (name, lev), v in ours.items()
+                   if lev == l and (name.startswith("k_grid_z") and not name.startswith("k_grid_zt")
+                                    or name.startswith("k_grid_phi_")))
+        lev = {"level": l, "p": pg, "w_spread": wg, "L": L, "nq": nq, "boxes": nb, "kh": w.k * h,
+               "grid_form_ms": float(mine), "nufft": []}
+        gen = torch.Generator(device=dev).manual_seed(l)
+        G = torch.complex(torch.randn((nb, pg, pg, pg), device=dev, generator=gen),
+                          torch.randn((nb, pg, pg, pg), device=dev, generator=gen))
+        xs = (np.arange(pg) - (pg - 1) / 2) * h
+        q0 = np.arange(0, nq, max(1, nq // 256))[:256]
+        Eq = [torch.from_numpy(np.exp(-1j * np.outer(om[q0, d], xs))).to(dev) for d in range(3)]
+        exact = torch.einsum("abc,qa,qb,qc->q", G[0].to(torch.complex128), Eq[0], Eq[1], Eq[2]).cpu().numpy()
+        for sigma, wf in ((2, 5), (2, 6)):
+            P = sigma * pg
+            Delta = 2 * np.pi / (P * h)
+            beta = 2.30 * wf
+            tq, wq = np.polynomial.legendre.leggauss(64)
+            u = tq * wf / 2
+            xsh = (np.arange(pg) - pg // 2) * h                    # grid relative to index pg/2
+            phic = (wf / 2) * np.sum(wq[None, :] * _es(u, wf, beta)[None, :] * np.cos(np.outer(xsh, u) * Delta), 1)
+            c = torch.from_numpy(1.0 / phic).to(dev, torch.float32)
+            t = om / Delta
+            m0 = np.floor(t - wf / 2).astype(np.int64) + 1       # [nq, 3]
+            offs = np.arange(wf)
+            ms = m0[:, :, None] + offs[None, None, :]              # [nq, 3, wf]
+            wts = _es(t[:, :, None] - ms, wf, beta)                # [nq, 3, wf]
+            mi = ms % P
+            flat = (mi[:, 0, :, None, None] * P + mi[:, 1, None, :, None]) * P + mi[:, 2, None, None, :]
+            ww = wts[:, 0, :, None, None] * wts[:, 1, None, :, None] * wts[:, 2, None, None, :]
+            rows = np.repeat(np.arange(nq), wf ** 3)
+            Wsp = torch.sparse_coo_tensor(torch.from_numpy(np.stack([rows, flat.reshape(-1)])),
+                                          torch.from_numpy(ww.reshape(-1).astype(np.float32)), (nq, P ** 3),
+                                          device=dev).coalesce().to_sparse_csr()
+            shift = torch.from_numpy(np.exp(-1j * om.sum(1) * h / 2)).to(dev, torch.complex64)
+
+            def prep():
+                pad = torch.zeros((nb, P, P, P), dtype=torch.complex64, device=dev)
+                pad[:, :pg, :pg, :pg] = G * c[None, :, None, None] * c[None, None, :, None] * c[None, None, None, :]
+                return torch.roll(pad, shifts=(-(pg // 2),) * 3, dims=(1, 2, 3))
+
+            t_prep, pad = timed(prep)
+            t_fft, F = timed(lambda: torch.fft.fftn(pad, dim=(1, 2, 3)))
+            del pad
+            Fm = F.reshape(nb, P ** 3)
+
+            def interp():
+                Ft = Fm.transpose(0, 1)
+                re = torch.sparse.mm(Wsp, Ft.real.contiguous())
+                im = torch.sparse.mm(Wsp, Ft.imag.contiguous())
+                return torch.complex(re, im) * shift[:, None]          # [nq, nb]
+
+            t_int, res = timed(interp)
+            got = res[q0, 0].cpu().numpy()
+            err = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+            del F, Fm, res, Wsp
+            torch.cuda.empty_cache()
+            lev["nufft"].append({"sigma": sigma, "wf": wf, "prep_ms": t_prep, "fft_ms": t_fft, "interp_ms": t_int,
+                                 "total_ms": t_prep + t_fft + t_int, "err": err,
+                                 "grid_bytes": nb * P ** 3 * 8})
+            print("nufft study level %d p=%d boxes %d nq %d: grid form %.3f ms; NUFFT sigma %d wf %d: prep %.3f fft %.3f "
+                  "interp %.3f ms, err %.2e" % (l, pg, nb, nq, mine, sigma, wf, t_prep, t_fft, t_int, err),
+                  file=sys.stderr, flush=True)
+        out["levels"].append(lev)
+        del G
+        torch.cuda.empty_cache()
+    plan.destroy()
+    return out
+
+
 def aca_study(n, reps=5):
     """ACA of the Lagrange transfer matrices (Sec. 2.2.2, eq. ffmACAmatvec) against full matrices: apply and plan
     times, transfer-kernel times and errors against FP64 dense rows, for N points on the sphere: Laplace at
@@ -660,6 +788,12 @@ def main():
     if args.mixed_study:
         res = {"metric": "10M sphere + cube Helmholtz: points/s and error per precision mode",
                "mixed_study": mixed_study(args.mixed_n, args.mixed_rows)}
+        print(json.dumps(res), flush=True)
+        return
+
+    if args.nufft_study:
+        res = {"metric": "plane-wave transforms from the grid: separable MFMA sums against an FFT-based NUFFT",
+               "nufft_study": nufft_study(args.n)}
         print(json.dumps(res), flush=True)
         return
 
