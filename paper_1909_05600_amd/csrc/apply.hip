@@ -869,7 +869,7 @@ k_grid_spread(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     }
     __syncthreads();
     const double inv_scale = ldexp(1.0, e - 61);
-    float2 *G = d.G + ((int64_t)sb * p + c) * p * p;
+    float2 *G = d.G + ((int64_t)d.gslot_s[sb] * p + c) * p * p;
     for (int kk = threadIdx.x; kk < ncell; kk += kThreads) {
         const int al = kk / nb, bl = kk % nb;
         G[(int64_t)(a0 + al) * p + b0 + bl] = make_float2((float)((double)(long long)acc0[kk] * inv_scale),
@@ -926,7 +926,7 @@ k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int
 #pragma unroll
             for (int k = 0; k < 2; ++k) acc[i][j][k] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int ab = ab0 + wv * 16 + li;
-    const gc2 G = gl(d.G) + (int64_t)sb * p * p2 + min(ab, p2 - 1);
+    const gc2 G = gl(d.G) + (int64_t)d.gslot_s[sb] * p * p2 + min(ab, p2 - 1);
     const gc2 Ez = gl(d.Ez);
     const float gkeep = ab < p2 ? 1.f : 0.f;
     for (int c0 = 0; c0 < p; c0 += 64) {
@@ -980,6 +980,7 @@ k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int
     }
     if (ab >= p2) return;
     const gm2 H = gw(d.H);
+    const int hslot = d.gslot_s[sb];
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi) {
         if (mi >= nmbg) continue;
@@ -988,8 +989,8 @@ k_grid_z(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int
             const int m = (mb0 + mi) * 16 + 4 * lg + r;
             if (m >= nrp) continue;
             const float q1 = acc[mi][0][0][r], q3 = acc[mi][0][1][r], q4 = acc[mi][1][0][r], q2 = acc[mi][1][1][r];
-            H[((int64_t)m * d.gnbox + sb) * p2 + ab] = v2f{q1 - q2, q3 + q4};
-            if (L - m != m) H[((int64_t)(L - m) * d.gnbox + sb) * p2 + ab] = v2f{q1 + q2, q3 - q4};
+            H[((int64_t)m * d.gnbox + hslot) * p2 + ab] = v2f{q1 - q2, q3 + q4};
+            if (L - m != m) H[((int64_t)(L - m) * d.gnbox + hslot) * p2 + ab] = v2f{q1 + q2, q3 - q4};
         }
     }
 }
@@ -1048,7 +1049,7 @@ k_grid_phi(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
     __shared__ float Bs[64 * kRow64];
     __shared__ float Exs[64 * kExRow];
     __shared__ float4 red[4][4][32];         // [wave][lane group][azimuth]
-    const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + sb) * p * p;
+    const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + d.gslot_s[sb]) * p * p;
     const gc2 Ey = gl(d.Ey) + (int64_t)mt * p * L;
     const gc2 Ex = gl(d.Ex) + (int64_t)mt * p * L;
     const int nab = p / 16, rounds = (nab + 3) / 4;
@@ -1222,7 +1223,7 @@ k_grid_phi_r(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     __shared__ float Bs[P * kRow64];
     __shared__ float Exs[64 * kExRow];
     __shared__ float4 red[4][4][32];                 // [wave][lane group][azimuth]
-    const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + sb) * P * P;
+    const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + d.gslot_s[sb]) * P * P;
     const gc2 Ey = gl(d.Ey) + (int64_t)mt * P * L;
     const gc2 Ex = gl(d.Ex) + (int64_t)mt * P * L;
     const gm2 ut = gw(reinterpret_cast<float2 *>(d.ut)) + (int64_t)sb * d.npair * 2;
@@ -1367,7 +1368,7 @@ k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     __shared__ float As[P * kRow128];
     __shared__ float Exw[4][P * kExR];
     {
-        const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + sb) * P * P;
+        const gc2 H = gl(d.H) + ((int64_t)m * d.gnbox + d.gslot_s[sb]) * P * P;
         v2f hv[P16 * P16];
 #pragma unroll
         for (int it = 0; it < P16 * P16; ++it) hv[it] = H[threadIdx.x + it * kThreads];
@@ -1658,7 +1659,7 @@ __device__ __forceinline__ void grid_phit_body(const int4 wk, const LDesc &d) {
             }
     }
     if (!act || kp > 0) return;
-    const gm2 Hb = gw(d.H) + ((int64_t)m * d.gnbox + tb) * p * p;
+    const gm2 Hb = gw(d.H) + ((int64_t)m * d.gnbox + d.gslot_t[tb]) * p * p;
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
         const int b = b0 + q * 16 + li;
@@ -1767,7 +1768,7 @@ k_grid_phit_pair(const LDesc *__restrict__ descs, const IoEntry *__restrict__, c
         }
     }
     if (!act) return;
-    const gm2 Hb = gw(d.H) + ((int64_t)mr[rr] * d.gnbox + tb) * p * p;
+    const gm2 Hb = gw(d.H) + ((int64_t)mr[rr] * d.gnbox + d.gslot_t[tb]) * p * p;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int b = q * 16 + li;
@@ -1810,6 +1811,7 @@ k_grid_zt(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
     for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = floatx4{0.f, 0.f, 0.f, 0.f};
     const bool act = c0 + wv * 16 < p;
     const gc2 H = gl(d.H), Ez = gl(d.Ez);
+    const int hslot = d.gslot_t[tb];
     for (int mp0 = 0; mp0 < nrp; mp0 += 16) {
         const int mc = min(16, nrp - mp0);
         __syncthreads();
@@ -1823,8 +1825,8 @@ k_grid_zt(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
                 if (ml < mc) {
                     if (c0 + x < p) ev[it] = Ez[(int64_t)mp * p + c0 + x];
                     if (ab < p2) {
-                        h1v[it] = H[((int64_t)mp * d.gnbox + tb) * p2 + ab];
-                        if (m2 != mp) h2v[it] = H[((int64_t)m2 * d.gnbox + tb) * p2 + ab];
+                        h1v[it] = H[((int64_t)mp * d.gnbox + hslot) * p2 + ab];
+                        if (m2 != mp) h2v[it] = H[((int64_t)m2 * d.gnbox + hslot) * p2 + ab];
                     }
                 }
             }
@@ -1871,7 +1873,7 @@ k_grid_zt(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
         }
     }
     if (!act) return;
-    const gm2 G = gw(d.G) + (int64_t)tb * p * p2;
+    const gm2 G = gw(d.G) + (int64_t)hslot * p * p2;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int ab = ab0 + q * 16 + li;
@@ -1910,7 +1912,7 @@ k_grid_interp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
         wy[k] = es_phi((float)(blo + k) - yg, k1, k2);
         wz[k] = es_phi((float)(clo + k) - zg, k1, k2);
     }
-    const gc2 G = gl(d.G) + (int64_t)t * p * p * p + ((int64_t)clo * p + alo) * p + blo;
+    const gc2 G = gl(d.G) + (int64_t)d.gslot_t[t] * p * p * p + ((int64_t)clo * p + alo) * p + blo;
     float sr = 0.f, si = 0.f;
 #pragma unroll
     for (int kc = 0; kc < W; ++kc) {

@@ -124,7 +124,8 @@ void batch_build(Batch &B, hipStream_t st) {
     typedef std::tuple<int, int, int, int, int, int, size_t> Key;
     std::map<Key, std::vector<int4>> groups;
     auto add = [&](int phase, const Stage &S, int db) {
-        std::vector<int4> &v = groups[Key(phase, phase == 1 ? S.level : 0, stage_role(S), S.kern, S.a, S.b, S.shmem)];
+        std::vector<int4> &v =
+            groups[Key(phase, phase == 1 ? S.level : 0, stage_role(S) + S.role_add, S.kern, S.a, S.b, S.shmem)];
         for (int4 it : S.items) {
             it.x += db;
             v.push_back(it);

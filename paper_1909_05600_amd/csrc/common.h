@@ -154,6 +154,7 @@ struct Scratch {
 // ---------------------------------------------------------------- plan data
 constexpr int kBits = 21;                 // Morton bits per axis
 constexpr int kMaxLev = 20;               // deepest level
+constexpr size_t kGridBatchBytes = (size_t)512 << 20;   // grid form: G and H of the boxes in flight at one level
 constexpr int kWin = 12;                  // translation window per axis
 constexpr int kWin3 = kWin * kWin * kWin; // window cells per level
 
@@ -243,7 +244,9 @@ struct LDesc {
     int gp, gw;
     float gbeta;                           // kernel shape
     double ginv_h;                         // 1 / h
-    int64_t gnbox;                         // boxes in the grid arrays of this level
+    int64_t gnbox;                         // box slots in the grid arrays of this level
+    const int32_t *gslot_s, *gslot_t;      // source / target box -> its slot in G and H (boxes go through the
+                                           // grid stages in batches of at most gnbox, each batch reusing the slots)
     float2 *G, *H;                         // G [box][c][a][b] grid values, H [m][box][a][b] ring sums
     const float2 *Ez, *Ex, *Ey;            // [nrp][p], [nrp][p][L], [nrp][p][L]
     const float2 *ExT, *EyT;               // [nrp][L][p] (Ex, Ey transposed)
@@ -261,6 +264,8 @@ enum Kern {
 
 struct Stage {
     int kern = 0, a = 0, b = 0;       // kernel and its template parameters
+    int role_add = 0;                 // added to the stage's order among its level's stages in a batch (box batches
+                                      // of the grid form follow one another)
     int slot = -1;                    // timing slot (FFM_TIMING layout) closed by this stage, or -1
     int tslot = -1;                   // timing slot the stage's time belongs to
     int level = 0;                    // level (ordering of target-side stages in batches)
@@ -360,6 +365,8 @@ struct Level {
     DevBuf<float2> Ez, Ex, Ey;           // [nrp][p], [nrp][p][L], [nrp][p][L]
     DevBuf<float2> ExT, EyT;             // [nrp][L][p]
     DevBuf<int32_t> gperm, gzs;          // source points ordered by box and z-plane; [nbox_y][p + 1]
+    int32_t gcap = 0;                    // box slots of the grid workspace (G, H) at this level
+    DevBuf<int32_t> gslot_s, gslot_t;    // source / target box -> slot within its batch
     DevBuf<float4> gxyz;                 // grid coordinates of the source points, gperm order
     // Lagrange node tables (FP32): Chebyshev nodes and 1 / prod_{b != a}(t_a - t_b)
     DevBuf<float> lnodes, lden;

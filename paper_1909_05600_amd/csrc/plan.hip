@@ -458,6 +458,17 @@ k_sym_reverse(const int64_t *ptr, const int32_t *src, int32_t nb, int64_t *off) 
     }
 }
 
+// Grid-form workspace per level (G and H of the boxes in flight); test hook FFM_TEST_GRID_BATCH_BYTES lowers it so
+// that the box batches can be tested on small problems.
+size_t grid_batch_bytes() {
+    static const size_t v = [] {
+        const char *e = std::getenv("FFM_TEST_GRID_BATCH_BYTES");
+        const long long x = e ? std::atoll(e) : 0;
+        return x > 0 ? (size_t)x : kGridBatchBytes;
+    }();
+    return v;
+}
+
 // Sibling-group transfer tables (one tree): block g takes up to four targets of one parent box and places the
 // sources of their far pairs by position relative to the parent (a far source's parent is adjacent to the
 // targets' parent, so the position s_ijk - 2 P_ijk lies in [-2, 3]^3: 216 slots), with each sibling's class;
@@ -1623,8 +1634,11 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                     const std::vector<double> &tab = phi_hat_table(w, LV.gbeta, dphat_step);
                     dphat = keep(SC, tab, st);
                     nphat = (int)tab.size();
-                    ws_gG = std::max(ws_gG, gnb * p * p * p);
-                    ws_gH = std::max(ws_gH, gnb * (size_t)(L + 1) * p * p);
+                    // boxes go through the grid stages in batches whose G and H fit kGridBatchBytes
+                    const size_t per_box = ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
+                    LV.gcap = (int32_t)std::max<size_t>(1, std::min<size_t>(gnb, grid_batch_bytes() / per_box));
+                    ws_gG = std::max(ws_gG, (size_t)LV.gcap * p * p * p);
+                    ws_gH = std::max(ws_gH, (size_t)LV.gcap * (L + 1) * p * p);
                 }
             }
             plog.mark("tab.grid");
@@ -2114,19 +2128,46 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
                 ring_order.push_back(mt);
                 if (L - mt != mt) ring_order.push_back(L - mt);
             }
-            for (int32_t b : LV.h_fwd) {
-                for (int c = 0; c < p; ++c)
-                    for (int t = 0; t < nta * nta; ++t) a1.push_back(make_int4(l, b, c, t));
-                for (int t = 0; t < ncol; ++t)
-                    for (int g = 0; g < zng; ++g) a2.push_back(make_int4(l, b, t, g));
+            // boxes in batches of gcap: each batch's grids and ring sums reuse the same slots of G and H, so a batch's
+            // stages run after the previous batch's (stage order; in merged batches, by role_add)
+            const int cap = std::max(1, LV.gcap);
+            const int nbf = (int)((LV.h_fwd.size() + cap - 1) / cap), nbt = (int)((LV.h_tgt.size() + cap - 1) / cap);
+            {
+                std::vector<int32_t> slot((size_t)P.ty->lev[l].nbox, 0);
+                for (size_t i = 0; i < LV.h_fwd.size(); ++i) slot[(size_t)LV.h_fwd[i]] = (int32_t)(i % cap);
+                upload(LV.gslot_s, slot, st, SC);
+                std::vector<int32_t> tslot((size_t)P.tx->lev[l].nbox, 0);
+                for (size_t i = 0; i < LV.h_tgt.size(); ++i) tslot[(size_t)LV.h_tgt[i]] = (int32_t)(i % cap);
+                upload(LV.gslot_t, tslot, st, SC);
             }
-            for (int m : ring_order)
-                for (int32_t b : LV.h_fwd) a3.push_back(make_int4(l, b, m, 0));
-            LV.stages.push_back(make_stage(K_GSPREAD, LV.gw, 0, -1, l, 2 * sizeof(uint64_t) * std::min(p, 64) * std::min(p, 64),
-                                           std::move(a1), st, SC));
-            LV.stages.push_back(make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC));
-            LV.stages.push_back(make_stage(K_GPHI, p <= 128 ? p / 16 : 0, 0, s1, l, 0, std::move(a3), st, SC));
-            LV.stages.push_back(transfer_stage(P, l, LV, tg, s2, st, SC));
+            for (int bi = 0; bi < nbf; ++bi) {
+                const size_t i0 = (size_t)bi * cap, i1 = std::min(LV.h_fwd.size(), i0 + cap);
+                for (size_t i = i0; i < i1; ++i) {
+                    const int32_t b = LV.h_fwd[i];
+                    for (int c = 0; c < p; ++c)
+                        for (int t = 0; t < nta * nta; ++t) a1.push_back(make_int4(l, b, c, t));
+                    for (int t = 0; t < ncol; ++t)
+                        for (int g = 0; g < zng; ++g) a2.push_back(make_int4(l, b, t, g));
+                }
+                for (int m : ring_order)
+                    for (size_t i = i0; i < i1; ++i) a3.push_back(make_int4(l, LV.h_fwd[i], m, 0));
+                Stage S1 = make_stage(K_GSPREAD, LV.gw, 0, -1, l, 2 * sizeof(uint64_t) * std::min(p, 64) * std::min(p, 64),
+                                      std::move(a1), st, SC);
+                Stage S2 = make_stage(K_GZ, 0, 0, -1, l, 0, std::move(a2), st, SC);
+                Stage S3 = make_stage(K_GPHI, p <= 128 ? p / 16 : 0, 0, bi + 1 == nbf ? s1 : -1, l, 0, std::move(a3), st, SC);
+                S1.role_add = S2.role_add = S3.role_add = 16 * bi;
+                LV.stages.push_back(std::move(S1));
+                LV.stages.push_back(std::move(S2));
+                LV.stages.push_back(std::move(S3));
+                a1.clear();
+                a2.clear();
+                a3.clear();
+            }
+            {
+                Stage S = transfer_stage(P, l, LV, tg, s2, st, SC);
+                S.role_add = 16 * (nbf - 1);
+                LV.stages.push_back(std::move(S));
+            }
             // mirror plane sums: 64 x 64 tiles, or 64 rows by the whole plane for grids of 80, 96 and 112 nodes,
             // whose 64 x 64 tiles would leave slivers (measured 18.3 -> 13.7 ms at 80 nodes; 128 nodes keep full
             // 64 x 64 tiles, 14.6 against 15.1 ms wide)
@@ -2134,22 +2175,33 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             // grids of at most 32 nodes: rings m and L - m in one block (they share their tables)
             const bool phit_pair = p <= 32;
             const int phit_tiles = phit_wide ? nta : nta * nta;
-            if (phit_pair) {
-                for (int mt = 0; mt < LV.nrp; ++mt)
-                    for (int32_t t : LV.h_tgt) b1.push_back(make_int4(l, t, mt, 0));
-            } else {
-                for (int m : ring_order)
-                    for (int32_t t : LV.h_tgt)
-                        for (int q = 0; q < phit_tiles; ++q) b1.push_back(make_int4(l, t, m, q));
+            for (int bi = 0; bi < nbt; ++bi) {
+                const size_t i0 = (size_t)bi * cap, i1 = std::min(LV.h_tgt.size(), i0 + cap);
+                if (phit_pair) {
+                    for (int mt = 0; mt < LV.nrp; ++mt)
+                        for (size_t i = i0; i < i1; ++i) b1.push_back(make_int4(l, LV.h_tgt[i], mt, 0));
+                } else {
+                    for (int m : ring_order)
+                        for (size_t i = i0; i < i1; ++i)
+                            for (int q = 0; q < phit_tiles; ++q) b1.push_back(make_int4(l, LV.h_tgt[i], m, q));
+                }
+                for (size_t i = i0; i < i1; ++i) {
+                    const int32_t t = LV.h_tgt[i];
+                    for (int q = 0; q < ncol; ++q)
+                        for (int cc = 0; cc < nta; ++cc) b2.push_back(make_int4(l, t, q, cc));
+                    for (int32_t j = sx[t]; j < sx[t + 1]; j += kThreads) b3.push_back(make_int4(l, t, j, 0));
+                }
+                Stage T1 = make_stage(K_GPHIT, phit_wide ? 1 : (phit_pair ? 2 : 0), 0, -1, l, 0, std::move(b1), st, SC);
+                Stage T2 = make_stage(K_GZT, 0, 0, -1, l, 0, std::move(b2), st, SC);
+                Stage T3 = make_stage(K_GINTERP, LV.gw, 0, bi + 1 == nbt ? s3 : -1, l, 0, std::move(b3), st, SC);
+                T1.role_add = T2.role_add = T3.role_add = 16 * (nbf - 1) + 16 * bi;
+                LV.stages.push_back(std::move(T1));
+                LV.stages.push_back(std::move(T2));
+                LV.stages.push_back(std::move(T3));
+                b1.clear();
+                b2.clear();
+                b3.clear();
             }
-            for (int32_t t : LV.h_tgt) {
-                for (int q = 0; q < ncol; ++q)
-                    for (int cc = 0; cc < nta; ++cc) b2.push_back(make_int4(l, t, q, cc));
-                for (int32_t i = sx[t]; i < sx[t + 1]; i += kThreads) b3.push_back(make_int4(l, t, i, 0));
-            }
-            LV.stages.push_back(make_stage(K_GPHIT, phit_wide ? 1 : (phit_pair ? 2 : 0), 0, -1, l, 0, std::move(b1), st, SC));
-            LV.stages.push_back(make_stage(K_GZT, 0, 0, -1, l, 0, std::move(b2), st, SC));
-            LV.stages.push_back(make_stage(K_GINTERP, LV.gw, 0, s3, l, 0, std::move(b3), st, SC));
         } else if (LV.method == kGegenbauer) {
             const int L = LV.L;
             LV.qG = L >= 64 ? tu.ring_g : (L >= 32 ? 2 : 0);
@@ -2381,7 +2433,9 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.gw = LV.gw;
     d.gbeta = (float)LV.gbeta;
     d.ginv_h = LV.grid ? 1.0 / LV.gh : 0.0;
-    d.gnbox = std::max(LX.nbox, LY.nbox);
+    d.gnbox = LV.gcap;
+    d.gslot_s = LV.gslot_s.p;
+    d.gslot_t = LV.gslot_t.p;
     d.G = w.G;
     d.H = w.H;
     d.Ez = LV.Ez.p;
@@ -2436,7 +2490,7 @@ size_t plan_device_bytes(const Plan &P) {
              L.lnodes.bytes() + L.lden.bytes() + L.rings.bytes() + L.phis.bytes() + L.T16.bytes() + L.acaA.bytes() +
              L.acaB.bytes() + L.acaKp.bytes() + L.Ez.bytes() +
              L.Ex.bytes() + L.Ey.bytes() + L.ExT.bytes() + L.EyT.bytes() + L.gperm.bytes() + L.gzs.bytes() + L.gxyz.bytes() +
-             L.tr_tgt.bytes() + L.near_off.bytes() + L.sib_tgt.bytes() + L.sib_src.bytes() + L.sib_cnt.bytes() +
+             L.tr_tgt.bytes() + L.gslot_s.bytes() + L.gslot_t.bytes() + L.near_off.bytes() + L.sib_tgt.bytes() + L.sib_src.bytes() + L.sib_cnt.bytes() +
              L.sib_cls.bytes();
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
