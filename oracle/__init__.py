@@ -23,6 +23,8 @@ LAPLACE = 0
 HELMHOLTZ = 1
 LAPLACE_DN = 2          # normal derivative at the target: the adjoint double-layer kernel
 HELMHOLTZ_DN = 3
+LAPLACE_DL = 4          # normal derivative at the source: the double-layer kernel
+HELMHOLTZ_DL = 5
 
 
 def build(force: bool = True) -> str:
@@ -81,6 +83,7 @@ def lib():
             "orc_es_hat": (dbl, [C.c_int, dbl, dbl]),
             "orc_aca": (C.c_int, [C.c_int, P, dbl, P, P]),
             "orc_dense_rows_dn": (None, [P, P, i64, P, C.c_int, dbl, P, P, i64, P]),
+            "orc_dense_rows_dl": (None, [P, P, i64, P, C.c_int, dbl, P, P, i64, P]),
             "orc_lagrange_basis_deriv": (None, [C.c_int, dbl, P]),
             "orc_aca_ranks": (C.c_int, [P, C.c_int, dbl, P, P]),
         }
@@ -103,7 +106,7 @@ class _Options(C.Structure):
     _fields_ = [("n_leaf", C.c_int32), ("kappa", C.c_double), ("r1_override", C.c_int32),
                 ("max_level", C.c_int32), ("grid_p", C.c_int32 * MAX_LEVELS), ("grid_w", C.c_int32 * MAX_LEVELS),
                 ("grid_beta", C.c_double * MAX_LEVELS), ("aca_tol", C.c_double), ("aca", C.c_int32 * MAX_LEVELS),
-                ("target_normals", C.c_void_p), ("adaptive", C.c_int32)]
+                ("target_normals", C.c_void_p), ("adaptive", C.c_int32), ("source_normals", C.c_void_p)]
 
 
 def _ptr(a: np.ndarray):
@@ -137,6 +140,18 @@ def dense_rows_dn(X, Y, wu, kernel: int, k: float, NX, rows) -> np.ndarray:
     r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).ravel())
     out = np.zeros(r.size, dtype=np.complex128)
     lib().orc_dense_rows_dn(_ptr(X), _ptr(Y), Y.shape[0], _ptr(w), int(kernel) & 1, float(k), _ptr(N), _ptr(r),
+                            r.size, _ptr(out))
+    return out
+
+
+def dense_rows_dl(X, Y, wu, kernel: int, k: float, NY, rows) -> np.ndarray:
+    """FP64 direct sum of the normal derivative at the sources, v_i = sum_{j: r_ij > 0} n_j . grad_y G(x_i - y_j)
+    wu_j (the double-layer kernel), on the given rows; kernel is the base kernel (0 or 1)."""
+    X, Y, N = _coords(X), _coords(Y), _coords(NY)
+    w = _complex128(wu)
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).ravel())
+    out = np.zeros(r.size, dtype=np.complex128)
+    lib().orc_dense_rows_dl(_ptr(X), _ptr(Y), Y.shape[0], _ptr(w), int(kernel) & 1, float(k), _ptr(N), _ptr(r),
                             r.size, _ptr(out))
     return out
 
@@ -244,7 +259,7 @@ class Plan:
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 64,
                  kappa: float = 0.0, r1: int = 0, max_level: int = 20, grid: dict | None = None,
-                 aca=(), aca_tol: float = 0.0, normals=None, adaptive: bool = False):
+                 aca=(), aca_tol: float = 0.0, normals=None, adaptive: bool = False, source_normals=None):
         self.X = _coords(X)
         self.Y = self.X if Y is X else _coords(Y)
         self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
@@ -257,11 +272,16 @@ class Plan:
         for l in aca:
             opt.aca[int(l)] = 1
         opt.adaptive = 1 if adaptive else 0
-        if int(kernel) >= 2:
+        if int(kernel) in (LAPLACE_DN, HELMHOLTZ_DN):
             if normals is None:
                 raise ValueError("normal-derivative kernels need the target normals")
             self._normals = _coords(normals)
             opt.target_normals = self._normals.ctypes.data
+        if int(kernel) in (LAPLACE_DL, HELMHOLTZ_DL):
+            if source_normals is None:
+                raise ValueError("double-layer kernels need the source normals")
+            self._snormals = _coords(source_normals)
+            opt.source_normals = self._snormals.ctypes.data
         self._h = lib().orc_plan_create(_ptr(self.X), self.X.shape[0], _ptr(self.Y), self.Y.shape[0],
                                         self.kernel, self.k, self.eps, C.byref(opt))
         if not self._h:

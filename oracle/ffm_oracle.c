@@ -79,6 +79,14 @@ static double complex green_dn(int kernel, double k, const double d[3], const do
     return nd * (I * (k * r) - 1.0) * cexp(I * (k * r)) / r3;
 }
 
+/* Normal derivative at the source, n . grad_y G(x - y) with d = x - y (the double-layer kernel of Sec. 4.2.1,
+ * eq. doubleLayer): grad_y G(x - y) = -grad_x G(x - y), so it is green_dn with the source normal and the
+ * opposite sign. */
+static double complex green_dl(int kernel, double k, const double d[3], const double n[3])
+{
+    return -green_dn(kernel, k, d, n);
+}
+
 /* Timing samples (orc_apply with stride > 1) keep the points whose sorted index is a multiple of the stride:
  * the first such index at or after i. */
 static int64_t first_sample(int64_t i, int64_t stride) { return (i + stride - 1) / stride * stride; }
@@ -129,6 +137,23 @@ void orc_dense_rows_dn(const double *X, const double *Y, int64_t ny, const doubl
             double d[3] = {x[0] - Y[3 * j], x[1] - Y[3 * j + 1], x[2] - Y[3 * j + 2]};
             if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] == 0.0) continue;   /* R11 */
             acc += green_dn(kernel, k, d, n) * cload(wu, j);
+        }
+        out[2 * a] = creal(acc);
+        out[2 * a + 1] = cimag(acc);
+    }
+}
+
+void orc_dense_rows_dl(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
+                       const double *NY, const int64_t *rows, int64_t nrows, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < nrows; ++a) {
+        const double *x = X + 3 * rows[a];
+        double complex acc = 0.0;
+        for (int64_t j = 0; j < ny; ++j) {
+            double d[3] = {x[0] - Y[3 * j], x[1] - Y[3 * j + 1], x[2] - Y[3 * j + 2]};
+            if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] == 0.0) continue;   /* R11 */
+            acc += green_dl(kernel, k, d, NY + 3 * j) * cload(wu, j);
         }
         out[2 * a] = creal(acc);
         out[2 * a + 1] = cimag(acc);
@@ -588,6 +613,8 @@ typedef struct {
 struct orc_plan {
     int kernel;                /* ORC_LAPLACE or ORC_HELMHOLTZ */
     int dn;                    /* 1: the normal derivative at the targets (adjoint double layer) */
+    int dl;                    /* 1: the normal derivative at the sources (double layer) */
+    double *NYs;               /* source normals in sorted order (dl plans) */
     double *NXs;               /* target normals in sorted order (dn plans) */
     double k, eps;
     orc_options opt;
@@ -772,7 +799,8 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
                           int kernel, double k, double eps, const orc_options *opt)
 {
     orc_plan *p = calloc(1, sizeof(orc_plan));
-    p->dn = kernel >= 2;
+    p->dn = kernel == ORC_LAPLACE_DN || kernel == ORC_HELMHOLTZ_DN;
+    p->dl = kernel == ORC_LAPLACE_DL || kernel == ORC_HELMHOLTZ_DL;
     kernel &= 1;
     p->kernel = kernel;
     p->k = k;
@@ -833,6 +861,11 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
         p->NXs = malloc(sizeof(double) * 3 * (size_t)nx);
         for (int64_t i = 0; i < nx; ++i)
             for (int d = 0; d < 3; ++d) p->NXs[3 * i + d] = opt->target_normals[3 * p->T[0].perm[i] + d];
+    }
+    if (p->dl) {
+        p->NYs = malloc(sizeof(double) * 3 * (size_t)ny);
+        for (int64_t j = 0; j < ny; ++j)
+            for (int d = 0; d < 3; ++d) p->NYs[3 * j + d] = opt->source_normals[3 * p->T[1].perm[j] + d];
     }
 
     /* Descent (Sec. 2.2.2, 2.2.4, 3.2): near_0 = {(root, root)}; the child pairs of every near
@@ -931,6 +964,7 @@ void orc_plan_free(orc_plan *p)
 {
     if (!p) return;
     free(p->NXs);
+    free(p->NYs);
     if (!p->empty) {
         for (int e = 0; e < 2; ++e) tree_free(&p->T[e]);
         for (int l = 0; l <= BITS; ++l) {
@@ -1048,11 +1082,30 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < nby; ++s) {
         if (!need[s]) continue;
-        double ex[64], ey[64], ez[64];
+        double ex[64], ey[64], ez[64], gx[64], gy[64], gz[64];
         for (int64_t j = first_sample(TY->start[l][s], stride); j < TY->start[l][s + 1]; j += stride) {
-            orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j] - TY->ctr[l][3 * s]) / dl, ex);
-            orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j + 1] - TY->ctr[l][3 * s + 1]) / dl, ey);
-            orc_lagrange_basis(r1, 2.0 * (TY->P[3 * j + 2] - TY->ctr[l][3 * s + 2]) / dl, ez);
+            const double tx = 2.0 * (TY->P[3 * j] - TY->ctr[l][3 * s]) / dl;
+            const double ty = 2.0 * (TY->P[3 * j + 1] - TY->ctr[l][3 * s + 1]) / dl;
+            const double tz = 2.0 * (TY->P[3 * j + 2] - TY->ctr[l][3 * s + 2]) / dl;
+            orc_lagrange_basis(r1, tx, ex);
+            orc_lagrange_basis(r1, ty, ey);
+            orc_lagrange_basis(r1, tz, ez);
+            if (p->dl) {
+                /* G(x, y) ~ sum_nodes G(x, y_node) L_node(y): its derivative along n_y weights the nodes by
+                 * n_y . grad L_node(y), d/dy of l(2 (y - c) / d_l) being (2 / d_l) l' */
+                const double *n = p->NYs + 3 * j;
+                orc_lagrange_basis_deriv(r1, tx, gx);
+                orc_lagrange_basis_deriv(r1, ty, gy);
+                orc_lagrange_basis_deriv(r1, tz, gz);
+                for (int a = 0; a < r1; ++a)
+                    for (int b = 0; b < r1; ++b)
+                        for (int c = 0; c < r1; ++c) {
+                            const double g = n[0] * gx[a] * ey[b] * ez[c] + n[1] * ex[a] * gy[b] * ez[c] +
+                                             n[2] * ex[a] * ey[b] * gz[c];
+                            ut[s * r + (a * r1 + b) * r1 + c] += (2.0 / dl) * g * u[j];
+                        }
+                continue;
+            }
             for (int a = 0; a < r1; ++a)
                 for (int b = 0; b < r1; ++b)
                     for (int c = 0; c < r1; ++c) ut[s * r + (a * r1 + b) * r1 + c] += ex[a] * ey[b] * ez[c] * u[j];
@@ -1207,7 +1260,7 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     for (int64_t i = 0; i < F->n; ++i) need[F->s[i]] = 1;
 
     /* grid form of the transforms at this level (R16-R18), else the direct sums */
-    const int grid = p->opt.grid_p[l] > 0 && !p->dn;   /* normal-derivative plans use the direct sums */
+    const int grid = p->opt.grid_p[l] > 0 && !p->dn && !p->dl;   /* normal-derivative plans use the direct sums */
     gridlev_t gl;
     if (grid) {
         int gp = p->opt.grid_p[l], gw = p->opt.grid_w[l];
@@ -1237,6 +1290,14 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
         }
         for (int64_t j = first_sample(TY->start[l][b], stride); j < TY->start[l][b + 1]; j += stride) {
             double y0 = TY->P[3 * j] - c[0], y1 = TY->P[3 * j + 1] - c[1], y2 = TY->P[3 * j + 2] - c[2];
+            if (p->dl) {
+                /* n . grad_y e^{-ik s.(y - c)} = -ik (s . n) e^{-ik s.(y - c)} */
+                const double *n = p->NYs + 3 * j;
+                for (int64_t q = 0; q < nq; ++q)
+                    ut[b * nq + q] += -I * k * (s[3 * q] * n[0] + s[3 * q + 1] * n[1] + s[3 * q + 2] * n[2]) *
+                                      cexp(-I * k * (s[3 * q] * y0 + s[3 * q + 1] * y1 + s[3 * q + 2] * y2)) * u[j];
+                continue;
+            }
             for (int64_t q = 0; q < nq; ++q)
                 ut[b * nq + q] += cexp(-I * k * (s[3 * q] * y0 + s[3 * q + 1] * y1 + s[3 * q + 2] * y2)) * u[j];
         }
@@ -1333,6 +1394,9 @@ static void near_pairs_sum(const orc_plan *p, int l, const pairs_t *N, const dou
                     if (p->dn) {
                         const double d[3] = {dx, dy, dz};
                         acc += green_dn(p->kernel, p->k, d, p->NXs + 3 * i) * u[j];
+                    } else if (p->dl) {
+                        const double d[3] = {dx, dy, dz};
+                        acc += green_dl(p->kernel, p->k, d, p->NYs + 3 * j) * u[j];
                     } else {
                         acc += green(p->kernel, p->k, sqrt(r2)) * u[j];
                     }

@@ -34,6 +34,10 @@ extern "C" {
  * double-layer operator (Sec. 4.2.1, eq. doubleLayer), for each base kernel; plans need target normals. */
 #define ORC_LAPLACE_DN 2
 #define ORC_HELMHOLTZ_DN 3
+/* The normal derivative at the source, dG/dn_y (x, y) = n_y . grad_y G(x - y): the kernel of the double-layer
+ * operator (Sec. 4.2.1, eq. doubleLayer), for each base kernel; plans need source normals. */
+#define ORC_LAPLACE_DL 4
+#define ORC_HELMHOLTZ_DL 5
 
 /* ---- plain definition ---------------------------------------------------- */
 /* out[a] = sum_{j : |x_rows[a] - y_j| > 0} G(|x_rows[a] - y_j|) * wu[j]  (complex128 out) */
@@ -44,6 +48,10 @@ void orc_dense_rows(const double *X, const double *Y, int64_t ny, const double *
  * kernel ORC_LAPLACE or ORC_HELMHOLTZ (the base kernel) */
 void orc_dense_rows_dn(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
                        const double *NX, const int64_t *rows, int64_t nrows, double *out);
+/* out[a] = sum_{j : |x - y_j| > 0} n_j . grad_y G(x - y_j) wu[j] at x = x_rows[a] with source normals NY (ny x 3);
+ * kernel ORC_LAPLACE or ORC_HELMHOLTZ (the base kernel) */
+void orc_dense_rows_dl(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
+                       const double *NY, const int64_t *rows, int64_t nrows, double *out);
 
 /* ---- building blocks, exported so the tests can pin them ----------------- */
 void orc_gauss_legendre(int n, double *x, double *w);
@@ -102,6 +110,8 @@ typedef struct {
     /* per-pair leaf rule (reading R22): near pairs whose boxes both hold <= n_leaf points are summed densely at
      * their level instead of refined */
     int32_t adaptive;
+    /* ORC_*_DL kernels: unit normals at the sources, n_y x 3, user order (copied at plan creation) */
+    const double *source_normals;
 } orc_options;
 
 orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t ny,

@@ -1,8 +1,8 @@
 /*
  * Driver for a host-sanitizer build of the oracle (AddressSanitizer + UndefinedBehaviorSanitizer, gcc): it
  * runs every entry point of oracle/ffm_oracle.c on small synthetic inputs (both kernels, Lagrange and
- * Gegenbauer levels, direct and grid transforms, ACA, the normal derivative, the per-pair leaf rule,
- * distinct and empty sets) and checks that the products are finite and agree with the dense definition.
+ * Gegenbauer levels, direct and grid transforms, ACA, the normal derivatives at the target and at the source,
+ * the per-pair leaf rule, distinct and empty sets) and checks that the products are finite and agree with the dense definition.
  * Any out-of-bounds access, use after free, leak or undefined operation aborts the run.
  *
  * Test infrastructure: built and run by tests/test_oracle_sanitize.py only.
@@ -114,8 +114,10 @@ static void run(const char *name, const double *X, int64_t nx, const double *Y, 
         int64_t *rows = malloc(sizeof(int64_t) * (size_t)nr);
         for (int64_t a = 0; a < nr; ++a) rows[a] = (a * 7919) % nx;
         double *d = malloc(sizeof(double) * 2 * (size_t)nr);
-        if (kernel >= ORC_LAPLACE_DN)
-            orc_dense_rows_dn(X, Y, ny, wu, kernel - 2, k, normals, rows, nr, d);
+        if (kernel == ORC_LAPLACE_DL || kernel == ORC_HELMHOLTZ_DL)
+            orc_dense_rows_dl(X, Y, ny, wu, kernel & 1, k, normals, rows, nr, d);
+        else if (kernel >= ORC_LAPLACE_DN)
+            orc_dense_rows_dn(X, Y, ny, wu, kernel & 1, k, normals, rows, nr, d);
         else
             orc_dense_rows(X, Y, ny, wu, kernel, k, rows, nr, d);
         check(name, v, d, rows, nr, eps);
@@ -167,6 +169,12 @@ int main(void) {
     o.target_normals = N;
     run("laplace dn", X, n, X, n, ORC_LAPLACE_DN, 0.0, 1e-3, &o, N);
     run("helmholtz dn", X, n, X, n, ORC_HELMHOLTZ_DN, 25.0, 1e-3, &o, N);
+
+    /* normal derivative at the source (double layer) */
+    memset(&o, 0, sizeof(o));
+    o.source_normals = N;
+    run("laplace dl", X, n, X, n, ORC_LAPLACE_DL, 0.0, 1e-3, &o, N);
+    run("helmholtz dl", X, n, X, n, ORC_HELMHOLTZ_DL, 25.0, 1e-3, &o, N);
 
     /* per-pair leaf rule on a sphere with a dense cluster */
     double *Z = malloc(sizeof(double) * 3 * n);
