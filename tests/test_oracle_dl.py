@@ -5,7 +5,7 @@ The FFM differentiates only its source side: the near field uses the derivative 
 derivatives of the anterpolation polynomials (chain factor 2 / d_l), Gegenbauer levels the factor -ik (s . n) of
 each plane wave.  Pins: the dense rows equal central differences of the potential under a shift of the sources
 along their normals; Gauss's law for the Laplace double layer of a closed surface (-1 inside, 0 outside, with
-G = 1/r and weights dS / 4 pi); the Helmholtz double layer of a uniform sphere from the n = 0 term of the
+G = 1 / (4 pi r) and area weights); the Helmholtz double layer of a uniform sphere from the n = 0 term of the
 addition theorem; the transpose relation with the target-side derivative, densely and, to rounding, through the
 two FFMs; the FFM within eps of dense rows.
 """
@@ -37,8 +37,8 @@ def test_dense_rows_are_the_derivative_along_source_normals(orc, kernel, k):
 
 @pytest.mark.parametrize("rho", [0.0, 0.3, 0.7, 1.6, 3.0])
 def test_laplace_gauss_law(orc, rho):
-    """sum_j n_j . grad_y (1/|x - y_j|) w_j over a quadrature of the unit sphere (weights summing to 1, outward
-    normals) is -1 for x inside and 0 outside, wherever x is."""
+    """sum_j n_j . grad_y G(x - y_j) w_j over an area quadrature of the unit sphere (outward normals) is -1 for x
+    inside and 0 outside, wherever x is."""
     Y, w = W.shell_grid(64, 128)
     rng = np.random.default_rng(9)
     T = W.sphere_points(12, rng) * rho
@@ -66,8 +66,9 @@ def _j0p(z):
 @pytest.mark.parametrize("k", [0.9, 3.7, 12.25])
 @pytest.mark.parametrize("rho", [0.4, 2.0])
 def test_helmholtz_shell_double_layer(orc, k, rho):
-    """With G = e^{ikr}/r the sphere average of G over |y| = a is ik j0(k r<) h0(k r>); its derivative in a at
-    a = 1 gives i k^2 j0(k rho) h0'(k) inside and i k^2 h0(k rho) j0'(k) outside."""
+    """With G = e^{ikr} / (4 pi r), the integral of G(x - a y) dS(y) over the unit sphere is ik j0(k r<) h0(k r>)
+    (r< and r> the smaller and the larger of a and |x|); its derivative in a at a = 1 gives
+    i k^2 j0(k rho) h0'(k) inside and i k^2 h0(k rho) j0'(k) outside."""
     Y, w = W.shell_grid(64, 128)
     rng = np.random.default_rng(4)
     T = W.sphere_points(20, rng) * rho
