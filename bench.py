@@ -41,10 +41,14 @@ PEAK_ALU_PACKED_TFLOPS = 157.3
 #     multiply-add)
 #   normal derivative at the target, per pair: Laplace 21 (the Laplace count with n . d in 3 FMA and 1/r^3 in 3
 #     products instead of the scale), Helmholtz 35 (the same, k r, sin, cos, the two factors -(cos + kr sin),
-#     kr cos - sin and a complex multiply-add)
-FLOPS_PER_DIRECTION = {"pair": 16.0 / 2, "ring": 22.0 / 4}
+#     kr cos - sin and a complex multiply-add); at the source the same counts (the normal is the source's)
+#   normal derivative at the source, source transforms: the direction-pair form adds k (s . n) (2 FMA and
+#     2 products, 6) and its product with u (2): 24 per 2 directions; the Lagrange anterpolation weights
+#     n . grad of the node polynomial (4 products and 2 FMA, 8) before the complex multiply-add (4): 12 per
+#     (point, node)
+FLOPS_PER_DIRECTION = {"pair": 16.0 / 2, "ring": 22.0 / 4, "pair_dl": 24.0 / 2}
 NEAR_FLOPS = {"k_near<false": 14.0, "k_near<true": 24.0, "k_near_dn<false": 21.0, "k_near_dn<true": 35.0,
-              "k_near_sym<false": 14.0, "k_near_sym<true": 24.0}
+              "k_near_dl<false": 21.0, "k_near_dl<true": 35.0, "k_near_sym<false": 14.0, "k_near_sym<true": 24.0}
 # VALU issue slots the implemented near-field loop needs per pair at least (transcendentals co-issue): three FP64
 # differences and their conversions to FP32 (6), |d|^2 (3), then Laplace a complex multiply-add (2), Helmholtz
 # r = |d|^2 / |d| (1), cos / r and sin / r (2) and a complex multiply-add (4).  The slot utilisation is reported
@@ -691,11 +695,12 @@ def launch_work(name, level, st):
                 "4 flops per (point, grid node): a real weight times the complex grid value, VALU")
     if name.startswith("k_pw_forward") or name.startswith("k_pw_backward"):
         pts = st["fwd_points"][level] if "forward" in name else st["bwd_points"][level]
-        form = "ring" if "_rings" in name else "pair"
+        form = "ring" if "_rings" in name else ("pair_dl" if name.startswith("k_pw_forward_dl") else "pair")
         return (FLOPS_PER_DIRECTION[form] * pts * nq, "alu",
                 "flops per (point, direction) of the %s form: %s, VALU + transcendental unit"
                 % ("ring-pair" if form == "ring" else "direction-pair",
-                   "22 per 4 directions" if form == "ring" else "16 per 2 directions"))
+                   {"ring": "22 per 4 directions", "pair": "16 per 2 directions",
+                    "pair_dl": "24 per 2 directions"}[form]))
     if name.startswith("k_near"):
         f = near_model(name, NEAR_FLOPS)
         if f is None:
@@ -714,6 +719,10 @@ def launch_work(name, level, st):
         r = L ** 3
         pts = st["fwd_points"][level] if name == "k_lag_anterp" else st["bwd_points"][level]
         return (4.0 * r * pts, "alu", "4 flops per (point, Chebyshev node): a real basis value times complex u, VALU")
+    if name == "k_lag_anterp_dl":
+        return (12.0 * L ** 3 * st["fwd_points"][level], "alu",
+                "12 flops per (point, Chebyshev node): the normal derivative of the node polynomial times complex "
+                "u, VALU")
     return None
 
 

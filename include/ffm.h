@@ -45,8 +45,14 @@ typedef struct ffm_plan_s *ffm_plan_t;
 
 /* Kernels.  The _DN kernels are the normal derivative at the target, dG/dn_x (x, y) = n_x . grad_x G(x - y), of
  * the adjoint double-layer operator (Sec. 4.2.1, eq. doubleLayer); they need options.target_normals and run
- * their plane-wave levels with the direct transforms. */
-typedef enum { FFM_LAPLACE = 0, FFM_HELMHOLTZ = 1, FFM_LAPLACE_DN = 2, FFM_HELMHOLTZ_DN = 3 } ffm_kernel_t;
+ * their plane-wave levels with the direct transforms.  The _DL kernels are the normal derivative at the source,
+ * dG/dn_y (x, y) = n_y . grad_y G(x - y), of the double-layer operator (same equation); they need
+ * options.source_normals, run their plane-wave levels with the direct transforms (source side in the
+ * direction-pair form) and their Lagrange transfers in FP32 whatever options.precision asks. */
+typedef enum {
+    FFM_LAPLACE = 0, FFM_HELMHOLTZ = 1, FFM_LAPLACE_DN = 2, FFM_HELMHOLTZ_DN = 3, FFM_LAPLACE_DL = 4,
+    FFM_HELMHOLTZ_DL = 5
+} ffm_kernel_t;
 
 typedef enum {
     FFM_OK = 0,
@@ -76,6 +82,9 @@ typedef struct {
     uint32_t flags;       /* FFM_FLAG_* bits; other bits must be 0                              */
     const double *target_normals;   /* _DN kernels: device, FP64 [n_x][3] unit normals at the targets in the
                                        caller's order, read while the plan is built; otherwise NULL     */
+    const double *source_normals;   /* _DL kernels: device, FP64 [n_y][3] unit normals at the sources in the
+                                       caller's order, read while the plan is built; read for no other
+                                       kernel                                                          */
 } ffm_options_t;
 
 /* options.flags: record HIP events between the phases of every apply (see ffm_plan_timing). */
@@ -107,7 +116,8 @@ typedef struct {
  *   Y      device, FP64 [n_y][3]: sources y_j.  Y == X with n_y == n_x means
  *          the same set: one tree serves both.
  *   kernel FFM_LAPLACE or FFM_HELMHOLTZ, or their normal derivatives at the
- *          targets FFM_LAPLACE_DN, FFM_HELMHOLTZ_DN; k >= 0 is the wavenumber
+ *          targets FFM_LAPLACE_DN, FFM_HELMHOLTZ_DN or at the sources
+ *          FFM_LAPLACE_DL, FFM_HELMHOLTZ_DL; k >= 0 is the wavenumber
  *          (ignored for Laplace; Helmholtz with k = 0 equals Laplace).
  *   eps    prescribed accuracy, 1e-7 <= eps < 0.5.
  *   opts   host pointer or NULL.

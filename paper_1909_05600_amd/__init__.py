@@ -17,6 +17,8 @@ FFM_LAPLACE = 0
 FFM_HELMHOLTZ = 1
 FFM_LAPLACE_DN = 2          # normal derivative at the target (adjoint double-layer kernel)
 FFM_HELMHOLTZ_DN = 3
+FFM_LAPLACE_DL = 4          # normal derivative at the source (double-layer kernel)
+FFM_HELMHOLTZ_DL = 5
 FFM_C64, FFM_F32, FFM_F64, FFM_C128 = 0, 1, 2, 3
 FFM_PREC_FP32, FFM_PREC_MIXED = 0, 1
 FFM_EXPORT_KEYS, FFM_EXPORT_PERM, FFM_EXPORT_BOX_START, FFM_EXPORT_BOX_IJK = 0, 1, 2, 3
@@ -53,7 +55,7 @@ class FFMError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("n_leaf", C.c_int32), ("precision", C.c_int32), ("kd_switch", C.c_double),
                 ("r1_override", C.c_int32), ("max_level", C.c_int32), ("flags", C.c_uint32),
-                ("target_normals", C.c_void_p)]
+                ("target_normals", C.c_void_p), ("source_normals", C.c_void_p)]
 
 
 _L = MAX_LEVELS
@@ -250,7 +252,8 @@ class Plan:
 
     def __init__(self, X, Y, kernel: int, k: float, eps: float, n_leaf: int = 0, precision: int = 0,
                  kd_switch: float = 0.0, r1_override: int = 0, max_level: int = 0, timing: bool = False,
-                 transforms: str = "auto", aca: str = "auto", normals=None, adaptive: bool = False, stream=None):
+                 transforms: str = "auto", aca: str = "auto", normals=None, adaptive: bool = False, stream=None,
+                 source_normals=None):
         import torch
         same = Y is X
         X = X.detach().contiguous()
@@ -274,6 +277,11 @@ class Plan:
             if normals.dtype != torch.float64 or normals.shape != X.shape or not normals.is_cuda:
                 raise TypeError("normals must be a CUDA float64 tensor shaped like X")
             opts.target_normals = normals.data_ptr()
+        if source_normals is not None:
+            source_normals = source_normals.detach().contiguous()
+            if source_normals.dtype != torch.float64 or source_normals.shape != Y.shape or not source_normals.is_cuda:
+                raise TypeError("source_normals must be a CUDA float64 tensor shaped like Y")
+            opts.source_normals = source_normals.data_ptr()
         self._h = None
         with torch.cuda.device(self.device):
             self._h = ffm_plan(X.data_ptr(), self.n_x, Y.data_ptr(), self.n_y, self.kernel, self.k, self.eps,

@@ -157,11 +157,15 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     if (n_x < 0 || n_y < 0 || n_x >= (int64_t(1) << 31) || n_y >= (int64_t(1) << 31))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: sizes must be in [0, 2^31)");
     if ((n_x > 0 && !X) || (n_y > 0 && !Y)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: NULL coordinates");
-    if (kernel != FFM_LAPLACE && kernel != FFM_HELMHOLTZ && kernel != FFM_LAPLACE_DN && kernel != FFM_HELMHOLTZ_DN)
+    if (kernel != FFM_LAPLACE && kernel != FFM_HELMHOLTZ && kernel != FFM_LAPLACE_DN && kernel != FFM_HELMHOLTZ_DN &&
+        kernel != FFM_LAPLACE_DL && kernel != FFM_HELMHOLTZ_DL)
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: unknown kernel");
     const bool dn = kernel == FFM_LAPLACE_DN || kernel == FFM_HELMHOLTZ_DN;
+    const bool dl = kernel == FFM_LAPLACE_DL || kernel == FFM_HELMHOLTZ_DL;
     if (dn && n_x > 0 && !(opts && opts->target_normals))
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: normal-derivative kernels need options.target_normals");
+    if (dl && n_y > 0 && !(opts && opts->source_normals))
+        return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: double-layer kernels need options.source_normals");
     if (!(eps >= 1e-7 && eps < 0.5)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: eps must be in [1e-7, 0.5)");
     if (!(k >= 0.0) || !std::isfinite(k)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: k must be finite and >= 0");
     ffm_options_t o{};
@@ -186,7 +190,10 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         Plan &P = p->P;
         P.dn = dn;
         P.user_normals = dn ? o.target_normals : nullptr;
-        P.kernel = (kernel == FFM_HELMHOLTZ || kernel == FFM_HELMHOLTZ_DN) ? FFM_HELMHOLTZ : FFM_LAPLACE;
+        P.dl = dl;
+        P.user_snormals = dl ? o.source_normals : nullptr;
+        P.kernel = (kernel == FFM_HELMHOLTZ || kernel == FFM_HELMHOLTZ_DN || kernel == FFM_HELMHOLTZ_DL) ? FFM_HELMHOLTZ
+                                                                                                          : FFM_LAPLACE;
         P.k = P.kernel == FFM_HELMHOLTZ ? k : 0.0;
         P.eps = eps;
         P.opt = o;
@@ -197,6 +204,7 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         plan_build(P, X, Y, st);
         P.user_normals = nullptr;
+        P.user_snormals = nullptr;
         FFM_HIP(hipEventCreateWithFlags(&P.ready, hipEventDisableTiming));
         FFM_HIP(hipEventRecord(P.ready, st));
         FFM_HIP(hipEventCreateWithFlags(&P.done, hipEventDisableTiming));

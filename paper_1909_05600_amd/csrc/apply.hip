@@ -112,11 +112,11 @@ k_perm_out(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, cons
 // Forward transform u~_s(q) = sum_{j in s} e^{-ik s_q.(y_j - c_s)} u_j for an antipodal pair (q, -q): with
 // S = sum cos(th) u, T = sum sin(th) u, u~(q) = S - iT and u~(-q) = S + iT.
 // Item (desc, source box, tile of 256 PPT pairs); the box's points stream through LDS.
-template <int PPT, int BS, bool P64>
-__global__ void __launch_bounds__(BS)
-k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
-    const int4 wk = work[blockIdx.x];
-    const LDesc &d = descs[wk.x];
+// With DL (the normal derivative at the sources), every direction's term is multiplied by -ik (s . n_j): with
+// a_j = k (s_q . n_j) u_j and S, T now the sums of cos(th) a and sin(th) a, u~(q) = -i (S - iT) and
+// u~(-q) = i (S + iT).
+template <int PPT, int BS, bool P64, bool DL>
+__device__ __forceinline__ void pw_forward_body(const LDesc &d, const int4 wk) {
     const int b = wk.y;
     const int tid = threadIdx.x;
     const int64_t npair = d.npair;
@@ -139,6 +139,7 @@ k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     const double cx = d.sctr[3 * b], cy = d.sctr[3 * b + 1], cz = d.sctr[3 * b + 2];
     __shared__ real px[BS], py[BS], pz[BS];
     __shared__ float2 us[BS];
+    __shared__ float4 ns[DL ? BS : 1];
     const int i0 = d.sstart[b], i1 = d.sstart[b + 1];
     for (int s0 = i0; s0 < i1; s0 += BS) {
         const int cnt = min(BS, i1 - s0);
@@ -149,6 +150,7 @@ k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
             py[tid] = (real)(d.sys[i] - cy);
             pz[tid] = (real)(d.szs[i] - cz);
             us[tid] = d.u[i];
+            if (DL) ns[tid] = d.sn[i];
         }
         __syncthreads();
         for (int jj = 0; jj < cnt; ++jj) {
@@ -166,19 +168,44 @@ k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
                 }
                 float sn, cs;
                 sincos_rev(f, sn, cs);
-                Sre[j] = fmaf(cs, uu.x, Sre[j]);
-                Sim[j] = fmaf(cs, uu.y, Sim[j]);
-                Tre[j] = fmaf(sn, uu.x, Tre[j]);
-                Tim[j] = fmaf(sn, uu.y, Tim[j]);
+                float ax = uu.x, ay = uu.y;
+                if (DL) {
+                    // k (s . n) = 2 pi (s k / 2 pi) . n
+                    const float4 n = ns[jj];
+                    const float D = 6.2831853f * fmaf((float)sx[j], n.x, fmaf((float)sy[j], n.y, (float)sz[j] * n.z));
+                    ax *= D;
+                    ay *= D;
+                }
+                Sre[j] = fmaf(cs, ax, Sre[j]);
+                Sim[j] = fmaf(cs, ay, Sim[j]);
+                Tre[j] = fmaf(sn, ax, Tre[j]);
+                Tim[j] = fmaf(sn, ay, Tim[j]);
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int64_t p = p0 + (int64_t)j * BS;
-        if (p < npair)
-            d.ut[(int64_t)b * npair + p] = make_float4(Sre[j] + Tim[j], Sim[j] - Tre[j], Sre[j] - Tim[j], Sim[j] + Tre[j]);
+        if (p < npair) {
+            d.ut[(int64_t)b * npair + p] =
+                DL ? make_float4(Sim[j] - Tre[j], -(Sre[j] + Tim[j]), -(Sim[j] + Tre[j]), Sre[j] - Tim[j])
+                   : make_float4(Sre[j] + Tim[j], Sim[j] - Tre[j], Sre[j] - Tim[j], Sim[j] + Tre[j]);
+        }
     }
+}
+
+template <int PPT, int BS, bool P64>
+__global__ void __launch_bounds__(BS)
+k_pw_forward(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    pw_forward_body<PPT, BS, P64, false>(descs[wk.x], wk);
+}
+
+template <int PPT, int BS, bool P64>
+__global__ void __launch_bounds__(BS)
+k_pw_forward_dl(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    pw_forward_body<PPT, BS, P64, true>(descs[wk.x], wk);
 }
 
 // Diagonal transfer v~_t(q) = sum_{s in far(t)} D_{c(t,s)}(q) u~_s(q) (both directions of a pair), for
@@ -1969,16 +1996,16 @@ __device__ __forceinline__ void lagrange_1d_deriv(float t, int r1, const float *
 }
 
 // u~_s = L_Y u_s: u~_s[(a r1 + b) r1 + c] = sum_j l_a(t_x) l_b(t_y) l_c(t_z) u_j, t = 2 (y - c_s) / d_l.
-// Item (desc, source box).
-__global__ void __launch_bounds__(kThreads)
-k_lag_anterp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
-    const int4 wk = work[blockIdx.x];
-    const LDesc &d = descs[wk.x];
+// With DL (the normal derivative at the sources) the weight of node (a, b, c) is n_j . grad_y of its polynomial:
+// (2 / d_l) (n_x l'_a l_b l_c + n_y l_a l'_b l_c + n_z l_a l_b l'_c); the staged derivative tables carry the
+// factors (2 / d_l) n.  Item (desc, source box).
+template <bool DL>
+__device__ __forceinline__ void lag_anterp_body(const LDesc &d, const int4 wk) {
     const int b = wk.y;
     const int tid = threadIdx.x;
     const int r1 = d.r1, rp = d.rp, r = r1 * r1 * r1;
     const double two_over_dl = d.two_over_dl;
-    __shared__ float ell[kAnterpChunk][3 * kMaxR1];
+    __shared__ float ell[kAnterpChunk][(DL ? 6 : 3) * kMaxR1];
     __shared__ float2 us[kAnterpChunk];
     __shared__ float nodes[kMaxR1], den[kMaxR1];
     if (tid < r1) {
@@ -2008,6 +2035,19 @@ k_lag_anterp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
             lagrange_1d((float)((d.sxs[j] - cx) * two_over_dl), r1, nodes, den, &ell[tid][0]);
             lagrange_1d((float)((d.sys[j] - cy) * two_over_dl), r1, nodes, den, &ell[tid][r1]);
             lagrange_1d((float)((d.szs[j] - cz) * two_over_dl), r1, nodes, den, &ell[tid][2 * r1]);
+            if (DL) {
+                const float4 n = d.sn[j];
+                const float f = (float)two_over_dl;
+                float *g = &ell[tid][3 * r1];
+                lagrange_1d_deriv((float)((d.sxs[j] - cx) * two_over_dl), r1, nodes, den, g);
+                lagrange_1d_deriv((float)((d.sys[j] - cy) * two_over_dl), r1, nodes, den, g + r1);
+                lagrange_1d_deriv((float)((d.szs[j] - cz) * two_over_dl), r1, nodes, den, g + 2 * r1);
+                for (int a = 0; a < r1; ++a) {
+                    g[a] *= f * n.x;
+                    g[r1 + a] *= f * n.y;
+                    g[2 * r1 + a] *= f * n.z;
+                }
+            }
             us[tid] = d.u[j];
         }
         __syncthreads();
@@ -2016,7 +2056,14 @@ k_lag_anterp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 #pragma unroll
             for (int o = 0; o < kOut; ++o) {
                 if (o < nout) {
-                    const float w = ell[jj][ia[o]] * ell[jj][r1 + ib[o]] * ell[jj][2 * r1 + ic[o]];
+                    const float *e = ell[jj];
+                    float w;
+                    if (DL) {
+                        const float ex = e[ia[o]], ey = e[r1 + ib[o]], ez = e[2 * r1 + ic[o]];
+                        w = fmaf(e[3 * r1 + ia[o]], ey * ez, fmaf(ex, e[4 * r1 + ib[o]] * ez, ex * ey * e[5 * r1 + ic[o]]));
+                    } else {
+                        w = e[ia[o]] * e[r1 + ib[o]] * e[2 * r1 + ic[o]];
+                    }
                     acc[o].x = fmaf(w, uu.x, acc[o].x);
                     acc[o].y = fmaf(w, uu.y, acc[o].y);
                 }
@@ -2030,6 +2077,18 @@ k_lag_anterp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
         if (o < nout && i < rp) ut[i] = (i < r) ? acc[o] : make_float2(0.f, 0.f);
     }
     for (int i = r + tid; i < rp; i += kThreads) ut[i] = make_float2(0.f, 0.f);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_lag_anterp(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    lag_anterp_body<false>(descs[wk.x], wk);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_lag_anterp_dl(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    lag_anterp_body<true>(descs[wk.x], wk);
 }
 
 // Transfer products of one class group on MFMA: Z_e = T_c u~_{s(e)} for up to 16 pairs e.
@@ -2528,10 +2587,11 @@ struct NearSmem {
 
 // Stage the chunk's sources c0 ... c0 + cnt - 1 (relative to the target centre, scaled) for R lane rows of
 // `steps` sources each: source jj at slot (jj / steps) * so + jj % steps, zero sources in the slots of
-// cnt <= jj < R * steps (at most 127).  d.two_over_dl is 2 / d_l of the descriptor's level.
+// cnt <= jj < R * steps (at most 127).  d.two_over_dl is 2 / d_l of the descriptor's level.  With snm (the
+// double layer) the negated source normals go to snm[slot]: n_y . grad_y G(x - y) = (-n_y) . grad_x G(x - y).
 __device__ __forceinline__ void near_stage_chunk(const LDesc &d, NearSmem &sm, int c0, int cnt, int R, int steps,
                                                  int so, double cx, double cy, double cz, double scale,
-                                                 float uscale) {
+                                                 float uscale, float4 *snm) {
     const int lane = threadIdx.x;
     // zero sources sit at (2, 2, 2) d_l from the target centre: no target is there (each lies within d_l / 2 of
     // its centre on every axis), so every pair with them has r > 0 and adds exactly zero, and their phases stay
@@ -2552,9 +2612,14 @@ __device__ __forceinline__ void near_stage_chunk(const LDesc &d, NearSmem &sm, i
                 sm.z[slot] = (d.szs[j] - cz) * scale;
                 const float2 uu = d.u[j];
                 sm.u[slot] = make_float2(uu.x * uscale, uu.y * uscale);
+                if (snm) {
+                    const float4 n = d.sn[j];
+                    snm[slot] = make_float4(-n.x, -n.y, -n.z, 0.f);
+                }
             } else {
                 sm.x[slot] = sm.y[slot] = sm.z[slot] = pad;   // padding: zero sources
                 sm.u[slot] = make_float2(0.f, 0.f);
+                if (snm) snm[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
     }
@@ -2596,39 +2661,47 @@ __device__ __forceinline__ void near_pair(double x, double y, double z, float nx
     }
 }
 
+// One staged source against the lane's T targets.  NRM: 0 the kernel itself, 1 the normal derivative at the
+// targets (their normals in nx, ny, nz), 2 at the sources (the staged negated normal of slot s).
+template <bool HELM, int NRM, bool BIG, bool CHK, int T>
+__device__ __forceinline__ void near_source(const NearSmem &sm, const float4 *snm, int s, const double (&x)[T],
+                                            const double (&y)[T], const double (&z)[T], const float (&nx)[T],
+                                            const float (&ny)[T], const float (&nz)[T], float (&are)[T],
+                                            float (&aim)[T]) {
+    const double sx = sm.x[s], sy = sm.y[s], sz = sm.z[s];
+    const float2 uu = sm.u[s];
+    if (NRM == 2) {
+        const float4 n = snm[s];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            near_pair<HELM, true, BIG, CHK>(x[t], y[t], z[t], n.x, n.y, n.z, sx, sy, sz, uu, are[t], aim[t]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            near_pair<HELM, NRM == 1, BIG, CHK>(x[t], y[t], z[t], nx[t], ny[t], nz[t], sx, sy, sz, uu, are[t], aim[t]);
+    }
+}
+
 // steps staged sources from slot base against the lane's T targets
-template <bool HELM, bool DN, bool BIG, bool CHK, int T>
-__device__ __forceinline__ void near_range(const NearSmem &sm, int base, int steps, const double (&x)[T],
-                                           const double (&y)[T], const double (&z)[T], const float (&nx)[T],
-                                           const float (&ny)[T], const float (&nz)[T], float (&are)[T],
-                                           float (&aim)[T]) {
+template <bool HELM, int NRM, bool BIG, bool CHK, int T>
+__device__ __forceinline__ void near_range(const NearSmem &sm, const float4 *snm, int base, int steps,
+                                           const double (&x)[T], const double (&y)[T], const double (&z)[T],
+                                           const float (&nx)[T], const float (&ny)[T], const float (&nz)[T],
+                                           float (&are)[T], float (&aim)[T]) {
     constexpr int U = T >= 4 ? 1 : 4 / T;
     int q = 0;
     for (; q + U <= steps; q += U) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int s = base + q + u;
-            const double sx = sm.x[s], sy = sm.y[s], sz = sm.z[s];
-            const float2 uu = sm.u[s];
-#pragma unroll
-            for (int t = 0; t < T; ++t)
-                near_pair<HELM, DN, BIG, CHK>(x[t], y[t], z[t], nx[t], ny[t], nz[t], sx, sy, sz, uu, are[t], aim[t]);
-        }
+        for (int u = 0; u < U; ++u)
+            near_source<HELM, NRM, BIG, CHK, T>(sm, snm, base + q + u, x, y, z, nx, ny, nz, are, aim);
     }
-    for (; q < steps; ++q) {
-        const int s = base + q;
-        const double sx = sm.x[s], sy = sm.y[s], sz = sm.z[s];
-        const float2 uu = sm.u[s];
-#pragma unroll
-        for (int t = 0; t < T; ++t)
-            near_pair<HELM, DN, BIG, CHK>(x[t], y[t], z[t], nx[t], ny[t], nz[t], sx, sy, sz, uu, are[t], aim[t]);
-    }
+    for (; q < steps; ++q) near_source<HELM, NRM, BIG, CHK, T>(sm, snm, base + q, x, y, z, nx, ny, nz, are, aim);
 }
 
 // One pass: targets i0 ... i0 + nt - 1 of box t, T per lane.
-template <bool HELM, bool DN, bool BIG, int T>
-__device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, int t, int i0, int nt, double scale,
-                                          float uscale) {
+template <bool HELM, int NRM, bool BIG, int T>
+__device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, float4 *snm, int t, int i0, int nt,
+                                          double scale, float uscale) {
     const int lane = threadIdx.x;
     const int g = __builtin_amdgcn_readfirstlane((nt + T - 1) / T), R = __builtin_amdgcn_readfirstlane(64 / g);
     const int r = lane / g, gi = lane - r * g;
@@ -2647,7 +2720,7 @@ __device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, int t, i
             x[k] = (d.txs[i] - cx) * scale;
             y[k] = (d.tys[i] - cy) * scale;
             z[k] = (d.tzs[i] - cz) * scale;
-            if (DN) {
+            if (NRM == 1) {
                 const float4 n = d.tn[i];
                 nx[k] = n.x;
                 ny[k] = n.y;
@@ -2664,12 +2737,12 @@ __device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, int t, i
         for (int c0 = j0; c0 < j1; c0 += 64) {
             const int cnt = min(64, j1 - c0);
             const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
-            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale);
+            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale, NRM == 2 ? snm : nullptr);
             const int base = valid ? r * so : 0;     // idle lanes read staged slots and discard their sums
             if (chk)
-                near_range<HELM, DN, BIG, true, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
+                near_range<HELM, NRM, BIG, true, T>(sm, snm, base, steps, x, y, z, nx, ny, nz, are, aim);
             else
-                near_range<HELM, DN, BIG, false, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
+                near_range<HELM, NRM, BIG, false, T>(sm, snm, base, steps, x, y, z, nx, ny, nz, are, aim);
         }
     }
     // the R partial sums of each target, added in order of r
@@ -2697,24 +2770,25 @@ __device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, int t, i
     }
 }
 
-template <bool HELM, bool DN, bool BIG>
+template <bool HELM, int NRM, bool BIG>
 __device__ __forceinline__ void near_body(const LDesc &d, const int4 wk) {
     __shared__ NearSmem sm;
+    __shared__ float4 snm[NRM == 2 ? kNearSlots : 1];   // staged source normals (double layer)
     const int t = wk.y;
     const int ta = d.tstart[t], tz = d.tstart[t + 1];
     // Helmholtz: coordinates in units of 2 pi / k; 1/r = (k / 2 pi) / r', 1/r^3 = (k / 2 pi)^3 / r'^3 and
     // n . d = (2 pi / k) n . d'
     const double kr = (double)d.k_rev;
     const double scale = HELM ? kr : 1.0;
-    const float uscale = (float)((1.0 / (4.0 * M_PI)) * (HELM ? (DN ? kr * kr : kr) : 1.0));
+    const float uscale = (float)((1.0 / (4.0 * M_PI)) * (HELM ? (NRM ? kr * kr : kr) : 1.0));
     for (int i0 = ta; i0 < tz;) {
         const NearPass ps = near_next_pass(tz - i0);
         if (ps.T == 1)
-            near_pass<HELM, DN, BIG, 1>(d, sm, t, i0, ps.nt, scale, uscale);
+            near_pass<HELM, NRM, BIG, 1>(d, sm, snm, t, i0, ps.nt, scale, uscale);
         else if (ps.T == 2)
-            near_pass<HELM, DN, BIG, 2>(d, sm, t, i0, ps.nt, scale, uscale);
+            near_pass<HELM, NRM, BIG, 2>(d, sm, snm, t, i0, ps.nt, scale, uscale);
         else
-            near_pass<HELM, DN, BIG, 4>(d, sm, t, i0, ps.nt, scale, uscale);
+            near_pass<HELM, NRM, BIG, 4>(d, sm, snm, t, i0, ps.nt, scale, uscale);
         i0 += ps.nt;
     }
 }
@@ -2723,7 +2797,7 @@ template <bool HELM, bool BIG>
 __global__ void __launch_bounds__(64)
 k_near(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
-    near_body<HELM, false, BIG>(descs[wk.x], wk);
+    near_body<HELM, 0, BIG>(descs[wk.x], wk);
 }
 
 // The normal derivative at the target (the adjoint double-layer kernel), same blocks and lanes.
@@ -2731,7 +2805,15 @@ template <bool HELM, bool BIG>
 __global__ void __launch_bounds__(64)
 k_near_dn(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
-    near_body<HELM, true, BIG>(descs[wk.x], wk);
+    near_body<HELM, 1, BIG>(descs[wk.x], wk);
+}
+
+// The normal derivative at the source (the double-layer kernel), same blocks and lanes.
+template <bool HELM, bool BIG>
+__global__ void __launch_bounds__(64)
+k_near_dl(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    near_body<HELM, 2, BIG>(descs[wk.x], wk);
 }
 
 // ------------------------------------------------------------------ near field, one set (symmetric pairs)
@@ -2819,12 +2901,12 @@ __device__ __forceinline__ void near_pass_sym(const LDesc &d, NearSmem &sm, int 
         for (int c0 = j0; c0 < j1; c0 += 64) {
             const int cnt = min(64, j1 - c0);
             const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
-            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale);
+            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale, nullptr);
             const int base = r * so;
             if (s == t) {
-                near_range<HELM, false, BIG, true, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
+                near_range<HELM, 0, BIG, true, T>(sm, nullptr, base, steps, x, y, z, nx, ny, nz, are, aim);
             } else if (s < t) {
-                near_range<HELM, false, BIG, false, T>(sm, base, steps, x, y, z, nx, ny, nz, are, aim);
+                near_range<HELM, 0, BIG, false, T>(sm, nullptr, base, steps, x, y, z, nx, ny, nz, are, aim);
             } else {
                 const int jb = r * steps;
                 for (int q = 0; q < steps; ++q) {
@@ -2951,6 +3033,14 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             if (S.a == 4) return S.b ? k_pw_forward<4, kThreads, true> : k_pw_forward<4, kThreads, false>;
             if (S.a == 2) return S.b ? k_pw_forward<2, kThreads, true> : k_pw_forward<2, kThreads, false>;
             return S.b ? k_pw_forward<1, kThreads, true> : k_pw_forward<1, kThreads, false>;
+        case K_FWD_PAIR_DL:
+            if (S.a == 101) {
+                threads = 64;
+                return S.b ? k_pw_forward_dl<1, 64, true> : k_pw_forward_dl<1, 64, false>;
+            }
+            if (S.a == 4) return S.b ? k_pw_forward_dl<4, kThreads, true> : k_pw_forward_dl<4, kThreads, false>;
+            if (S.a == 2) return S.b ? k_pw_forward_dl<2, kThreads, true> : k_pw_forward_dl<2, kThreads, false>;
+            return S.b ? k_pw_forward_dl<1, kThreads, true> : k_pw_forward_dl<1, kThreads, false>;
         case K_FWD_RING:
             if (S.a == 4) return S.b ? k_pw_forward_rings<4, true> : k_pw_forward_rings<4, false>;
             return S.b ? k_pw_forward_rings<2, true> : k_pw_forward_rings<2, false>;
@@ -2981,6 +3071,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             return S.b ? k_pw_backward_rings<1, 4, true> : k_pw_backward_rings<1, 4, false>;
         case K_BSUM: return k_sum_parts;
         case K_ANTERP: return k_lag_anterp;
+        case K_ANTERP_DL: return k_lag_anterp_dl;
         // a = waves per block (each takes its own 32-row tiles of T over the block's staged sources)
         case K_MFMA32: threads = 64 * std::max(1, S.a); return k_lag_mfma;
         case K_MFMA16: threads = 64 * std::max(1, S.a); return k_lag_mfma16;
@@ -2991,6 +3082,9 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             threads = 64;
             return S.b ? (S.a ? k_near_sym<true, true> : k_near_sym<true, false>) : k_near_sym<false, false>;
         case K_NEAR_GATHER: threads = 64; return k_near_gather;
+        case K_NEAR_DL:
+            threads = 64;
+            return S.b ? (S.a ? k_near_dl<true, true> : k_near_dl<true, false>) : k_near_dl<false, false>;
         case K_NEAR_DN:
             threads = 64;
             return S.b ? (S.a ? k_near_dn<true, true> : k_near_dn<true, false>) : k_near_dn<false, false>;
@@ -3149,6 +3243,9 @@ std::string kernel_name(int kern, int a, int b) {
         case K_FWD_PAIR:
             if (a == 101) return "k_pw_forward<1, 64, " + tf(b) + ">";
             return "k_pw_forward<" + std::to_string(a == 4 || a == 2 ? a : 1) + ", 256, " + tf(b) + ">";
+        case K_FWD_PAIR_DL:
+            if (a == 101) return "k_pw_forward_dl<1, 64, " + tf(b) + ">";
+            return "k_pw_forward_dl<" + std::to_string(a == 4 || a == 2 ? a : 1) + ", 256, " + tf(b) + ">";
         case K_FWD_RING: return "k_pw_forward_rings<" + std::to_string(a == 4 ? 4 : 2) + ", " + tf(b) + ">";
         case K_SUM: return "k_sum_segments";
         case K_TRANSFER:
@@ -3162,6 +3259,7 @@ std::string kernel_name(int kern, int a, int b) {
             return a == 2 ? "k_pw_backward_rings<2, 2, " + tf(b) + ">" : "k_pw_backward_rings<1, 4, " + tf(b) + ">";
         case K_BSUM: return "k_sum_parts";
         case K_ANTERP: return "k_lag_anterp";
+        case K_ANTERP_DL: return "k_lag_anterp_dl";
         case K_MFMA32: return "k_lag_mfma";
         case K_MFMA16: return "k_lag_mfma16";
         case K_ACA: return "k_lag_aca";
@@ -3170,6 +3268,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_NEAR_SYM: return "k_near_sym<" + tf(b) + ", " + tf(b && a) + ">";
         case K_NEAR_GATHER: return "k_near_gather";
         case K_NEAR_DN: return "k_near_dn<" + tf(b) + ", " + tf(b && a) + ">";
+        case K_NEAR_DL: return "k_near_dl<" + tf(b) + ", " + tf(b && a) + ">";
         case K_INTERP_DN: return "k_lag_interp_dn";
         case K_BWD_PAIR_DN: return "k_pw_backward_dn<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
         case K_ZERO_OUT: return "k_zero_io";

@@ -39,7 +39,7 @@ int stage_role(const Stage &S) {
     switch (S.kern) {
         case K_PERM_IN: return 0;
         case K_AMAX: return S.a ? 1 : 2;
-        case K_FWD_PAIR: case K_FWD_RING: case K_ANTERP: case K_GSPREAD: return 0;
+        case K_FWD_PAIR: case K_FWD_RING: case K_ANTERP: case K_GSPREAD: case K_FWD_PAIR_DL: case K_ANTERP_DL: return 0;
         case K_SUM: case K_GZ: return 1;
         case K_GPHI: return 2;
         case K_TRANSFER: case K_MFMA32: case K_MFMA16: case K_ACA: return 3;
@@ -49,7 +49,7 @@ int stage_role(const Stage &S) {
         // after the levels: the near fields of the early lists and the leaf in level order (they add into the same
         // outputs), the symmetric pairs' source-side sums, then the output permutation
         case K_ZERO_OUT: return 0;
-        case K_NEAR: case K_NEAR_DN: case K_NEAR_SYM: return 1 + S.level;
+        case K_NEAR: case K_NEAR_DN: case K_NEAR_DL: case K_NEAR_SYM: return 1 + S.level;
         case K_NEAR_GATHER: return 1 + kMaxLev + 1;
         case K_PERM_OUT: return 1 + kMaxLev + 2;
         default: throw Error(FFM_EINTERNAL, "stage without a batch order");

@@ -231,6 +231,7 @@ struct LDesc {
     const float *T, *lnodes, *lden;
     const _Float16 *T16;
     const float4 *tn;                      // target normals in sorted order (normal-derivative kernels), or null
+    const float4 *sn;                      // source normals in sorted order (double-layer kernels), or null
     const float *acaA, *acaB;              // ACA factors: A [class][plane][kpm][rp], B^T [class][plane][rp][kpm]
     const int32_t *acaKp;                  // [class] rank padded to 32
     int kpm;                               // largest padded rank
@@ -259,7 +260,7 @@ enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
     K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
     K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA, K_NEAR_DN, K_BWD_PAIR_DN, K_INTERP_DN,
-    K_NEAR_SYM, K_NEAR_GATHER
+    K_NEAR_SYM, K_NEAR_GATHER, K_NEAR_DL, K_ANTERP_DL, K_FWD_PAIR_DL
 };
 
 struct Stage {
@@ -385,6 +386,9 @@ struct Plan {
     bool dn = false;                     // normal derivative at the targets (adjoint double layer)
     const double *user_normals = nullptr;   // the caller's target normals, read while the plan is built
     DevBuf<float4> tnrm;                 // target normals in sorted order (FP32)
+    bool dl = false;                     // normal derivative at the sources (double layer)
+    const double *user_snormals = nullptr;  // the caller's source normals, read while the plan is built
+    DevBuf<float4> snrm;                 // source normals in sorted order (FP32)
     double k = 0, eps = 0;
     ffm_options_t opt{};
     bool empty = false;

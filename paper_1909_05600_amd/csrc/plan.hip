@@ -128,7 +128,7 @@ k_gather(const double *P, int64_t n, const int32_t *perm, double *xs, double *ys
     zs[i] = P[3 * j + 2];
 }
 
-// Target normals in sorted order, FP32 (the normal-derivative kernels); w unused.
+// Target (or source) normals in sorted order, FP32 (the normal-derivative kernels); w unused.
 __global__ void __launch_bounds__(kThreads)
 k_gather_normals(const double *N, int64_t n, const int32_t *perm, float4 *out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1361,6 +1361,10 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         build_tree(*P.ty_own, Y, ny, corner[1], P.S, st, SC);
         P.ty = P.ty_own.get();
     }
+    if (P.dl) {
+        P.snrm.alloc(ny);
+        FFM_LAUNCH(k_gather_normals, nblocks(ny), kThreads, 0, st, P.user_snormals, ny, P.ty->perm.p, P.snrm.p);
+    }
     Tree &TX = *P.tx, &TY = *P.ty;
     LevelScratch SX, SY;
     SX.sc = SY.sc = &SC;
@@ -1484,8 +1488,8 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
         if (l < P.leaf && P.lev[l].nearly) fetch_early_lists(P.lev[l], TX.lev[l], TY.lev[l], st, SC, wf_early[l]);
     }
     // one set: the leaf near field evaluates each unordered pair of distinct boxes once (G is symmetric; the
-    // normal derivative at the target is not)
-    P.near_sym = P.same && !P.dn;
+    // normal derivatives are not)
+    P.near_sym = P.same && !P.dn && !P.dl;
     fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near, P.near_sym);
     int32_t *used_h = SC.pin<int32_t>((size_t)kWin3 * (P.leaf + 1) + 1);
     for (int l = 1; l <= P.leaf; ++l)
@@ -1599,7 +1603,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
                 const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
                 const bool force_direct = (P.opt.flags & FFM_FLAG_DIRECT_TRANSFORMS) != 0;
-                LV.grid = have && !force_direct && !P.dn && L >= 8 && gbytes <= ((size_t)24 << 30) &&
+                LV.grid = have && !force_direct && !P.dn && !P.dl && L >= 8 && gbytes <= ((size_t)24 << 30) &&
                           (force_grid || gridc < direct);
                 if (LV.grid) {
                     P.any_grid = true;
@@ -1728,7 +1732,9 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             // mixed precision: FP16 transfers where the FP16 rounding (2^-11 relative, twice that for the
             // oscillatory complex kernel) stays within eps; |T| <= 1 / (4 pi d_l) is scaled to <= 1
             const double cond = helm ? 2.0 : 1.0;
-            LV.fp16 = P.opt.precision == FFM_PREC_MIXED && std::ldexp(1.0, -11) * cond <= P.eps;
+            // (the double layer's anterpolated u~ carries the factor 2 / d_l of the derivative, beyond the
+            // range the FP16 scaling of the sources provides for: its transfers stay FP32)
+            LV.fp16 = P.opt.precision == FFM_PREC_MIXED && !P.dl && std::ldexp(1.0, -11) * cond <= P.eps;
             // class groups of 16 pairs for the MFMA transfer
             DevBuf<int32_t> cnt(LV.ncls), cursor(LV.ncls);
             FFM_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * LV.ncls, st));
@@ -2211,7 +2217,9 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             const bool ring_bwd = LV.qG && !P.dn;
             LV.bwd_tile = ring_bwd ? kThreads * tu.bwd_pt : kThreads;
             std::vector<int4> fw;
-            if (LV.qG) {
+            // the normal derivative at the sources multiplies every direction by its own -ik (s . n): the source
+            // transform runs in the direction-pair form (the ring form still serves the target transform)
+            if (LV.qG && !P.dl) {
                 // ring-pair form; split each box's points into segments when boxes are too few to fill the chip
                 LV.Tr = (L + LV.qG - 1) / LV.qG;
                 LV.R = std::max(1, std::min({16, kThreads / LV.Tr, LV.nrp}));
@@ -2240,8 +2248,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
                 fw.reserve((size_t)(LV.h_fwd.size() * nt));
                 for (int32_t b : LV.h_fwd)
                     for (int64_t t = 0; t < nt; ++t) fw.push_back(make_int4(l, b, (int)t, 0));
-                LV.stages.push_back(make_stage(K_FWD_PAIR, ppt + (bs == 64 ? 100 : 0), LV.phase64, s1, l, 0,
-                                               std::move(fw), st, SC));
+                LV.stages.push_back(make_stage(P.dl ? K_FWD_PAIR_DL : K_FWD_PAIR, ppt + (bs == 64 ? 100 : 0),
+                                               LV.phase64, s1, l, 0, std::move(fw), st, SC));
             }
             std::vector<int4> bw;
             LV.stages.push_back(transfer_stage(P, l, LV, tg, s2, st, SC));
@@ -2285,7 +2293,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
                     }
             }
             for (int32_t t : LV.h_tgt) ip.push_back(make_int4(l, t, 0, 0));
-            LV.stages.push_back(make_stage(K_ANTERP, 0, 0, s1, l, 0, std::move(an), st, SC));
+            LV.stages.push_back(make_stage(P.dl ? K_ANTERP_DL : K_ANTERP, 0, 0, s1, l, 0, std::move(an), st, SC));
             if (LV.aca)
                 LV.stages.push_back(make_stage(K_ACA, std::min(4, LV.rp / 32), 0, s2, l, (size_t)LV.rp * 32 * 4,
                                                std::move(mf), st, SC));
@@ -2311,20 +2319,20 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         auto big = [&](int l) {
             return nhelm && P.k / (2.0 * M_PI) * 4.0 * std::sqrt(3.0) * std::ldexp(P.d0, -l) > 128.0 ? 1 : 0;
         };
+        const int near_kern = P.dn ? K_NEAR_DN : (P.dl ? K_NEAR_DL : K_NEAR);
         // near pairs the per-pair rule stopped above the leaf: the same kernel over each level's early list
         for (int l = 1; l < P.leaf; ++l) {
             if (P.lev[l].h_early.empty()) continue;
             std::vector<int4> er;
             for (int32_t t : P.lev[l].h_early) er.push_back(make_int4(l, t, 0, 0));
-            P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, big(l), nhelm, -1, l, 0, std::move(er), st, SC));
+            P.post.push_back(make_stage(near_kern, big(l), nhelm, -1, l, 0, std::move(er), st, SC));
         }
         if (P.near_sym) {
             std::vector<int4> ga = nr;
             P.post.push_back(make_stage(K_NEAR_SYM, big(P.leaf), nhelm, -1, P.leaf, 0, std::move(nr), st, SC));
             P.post.push_back(make_stage(K_NEAR_GATHER, 0, 0, 61, P.leaf, 0, std::move(ga), st, SC));
         } else {
-            P.post.push_back(make_stage(P.dn ? K_NEAR_DN : K_NEAR, big(P.leaf), nhelm, 61, P.leaf, 0, std::move(nr),
-                                        st, SC));
+            P.post.push_back(make_stage(near_kern, big(P.leaf), nhelm, 61, P.leaf, 0, std::move(nr), st, SC));
         }
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
     }
@@ -2416,6 +2424,7 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.lden = LV.lden.p;
     d.T16 = LV.T16.p;
     d.tn = P.tnrm.p;
+    d.sn = P.snrm.p;
     d.acaA = LV.acaA.p;
     d.acaB = LV.acaB.p;
     d.acaKp = LV.acaKp.p;
@@ -2495,6 +2504,7 @@ size_t plan_device_bytes(const Plan &P) {
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
          P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes() + P.wnsym.bytes();
+    b += P.tnrm.bytes() + P.snrm.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
     b += P.items.bytes();
     return b;

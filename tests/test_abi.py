@@ -54,6 +54,8 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
         (dummy, 10, dummy, 10, 0, 0.0, 1e-9, None, None, C.byref(h)),   # eps too small
         (dummy, 10, dummy, 10, 0, 0.0, 0.7, None, None, C.byref(h)),    # eps too large
         (dummy, 1 << 31, dummy, 10, 0, 0.0, 1e-3, None, None, C.byref(h)),
+        (dummy, 10, dummy, 10, 2, 0.0, 1e-3, None, None, C.byref(h)),   # _DN without target normals
+        (dummy, 10, dummy, 10, 5, 3.0, 1e-3, None, None, C.byref(h)),   # _DL without source normals
     ]
     for args in cases:
         assert L.ffm_plan(*args) == -1, args
@@ -68,6 +70,10 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
     assert L.ffm_plan(dummy, 10, dummy, 10, 0, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1
     bad = ffm.Options(0, 0, 0.0, 0, 25, 0)      # depth cap above 20
     assert L.ffm_plan(dummy, 10, dummy, 10, 0, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1
+    bad = ffm.Options(0, 0, 0.0, 0, 0, 0)       # target normals do not stand in for source normals
+    bad.target_normals = dummy.value
+    assert L.ffm_plan(dummy, 10, dummy, 10, 4, 0.0, 1e-3, C.byref(bad), None, C.byref(h)) == -1
+    assert "source_normals" in L.ffm_last_error().decode()
     assert L.ffm_apply(None, dummy, 0, dummy, None) == -1
     assert L.ffm_destroy(None) == 0
     assert L.ffm_plan_stats(None, None) == -1
@@ -138,6 +144,10 @@ def test_kernel_names_and_launch_timing_validation(L):
     assert ffm.kernel_name(18, 4, 0) == "k_grid_phi_s<4>"
     assert ffm.kernel_name(18, 0, 0) == "k_grid_phi"
     assert ffm.kernel_name(16, 8, 0) == "k_grid_spread<8>"
+    assert ffm.kernel_name(28, 1, 1) == "k_near_dl<true, true>"
+    assert ffm.kernel_name(29) == "k_lag_anterp_dl"
+    assert ffm.kernel_name(30, 101, 0) == "k_pw_forward_dl<1, 64, false>"
+    assert ffm.kernel_name(30, 4, 1) == "k_pw_forward_dl<4, 256, true>"
     buf = C.create_string_buffer(6)
     assert L.ffm_kernel_name(18, 4, 0, buf, 6) == len("k_grid_phi_s<4>")
     assert buf.value == b"k_gri"                       # cut to fit, NUL-terminated

@@ -29,6 +29,10 @@ def test_launch_work_models():
     assert bench.launch_work("k_near<true, true>", 0, st)[0] == 24 * 5e6
     assert bench.launch_work("k_near_dn<true, false>", 0, st)[0] == 35 * 5e6
     assert bench.launch_work("k_near_dn<false, false>", 0, st)[0] == 21 * 5e6
+    assert bench.launch_work("k_near_dl<true, true>", 0, st)[0] == 35 * 5e6
+    assert bench.launch_work("k_near_dl<false, false>", 0, st)[0] == 21 * 5e6
+    assert bench.launch_work("k_pw_forward_dl<1, 256, false>", 2, st)[0] == 12 * 1000 * 220
+    assert bench.launch_work("k_pw_forward<1, 256, false>", 2, st)[0] == 8 * 1000 * 220
     assert bench.launch_work("k_pw_forward_rings<2, false>", 2, st)[0] == 5.5 * 1000 * 220
     assert bench.launch_work("k_pw_backward<256, false>", 2, st)[0] == 8 * 900 * 220
     assert bench.launch_work("k_grid_phit", 2, st)[0] == 8 * 9 * 11 * 32 * 32 * 10

@@ -1,0 +1,134 @@
+"""The normal derivative at the source, dG/dn_y (x, y) = n_y . grad_y G(x - y): the kernel of the double-layer
+operator (Sec. 4.2.1, eq. doubleLayer), on the GPU through the C ABI (FFM_LAPLACE_DL, FFM_HELMHOLTZ_DL with
+source normals).
+
+Only the source side differs from the potential: the near-field kernel, the derivatives of the Lagrange
+polynomials at the sources, and the factor -ik (s . n) of every plane wave (direct transforms, the source side in
+direction pairs).  Element-wise against the oracle FFM of the same kernel with identical parameters (FP32_RTOL),
+within eps of FP64 dense rows, bitwise repeatable, inside a batch, with the per-pair leaf rule, unchanged by
+the mixed-precision option (its transfers stay FP32), against the transpose of the target-side derivative, and
+the missing-normals error.  Plans report the ring form (2) for Gegenbauer levels whose target side takes it.
+"""
+import numpy as np
+import pytest
+
+import ffm_workloads as W
+from gpu_common import FP32_RTOL, compare_trees, gpu_apply, oracle_like, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(X, Y, kernel, k, eps, N, **kw):
+    import torch
+    import paper_1909_05600_amd as ffm
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    Yd = Xd if Y is X else torch.from_numpy(np.ascontiguousarray(Y)).cuda()
+    Nd = torch.from_numpy(np.ascontiguousarray(N)).cuda()
+    return ffm.Plan(Xd, Yd, kernel, k, eps, source_normals=Nd, **kw)
+
+
+@pytest.mark.parametrize("kernel,k,eps", [(4, 0.0, 1e-3), (4, 0.0, 1e-4), (5, 9.0, 1e-3), (5, 45.0, 1e-3),
+                                          (5, 20.0, 1e-4)])
+def test_dl_matches_oracle_and_dense(orc, kernel, k, eps):
+    rng = np.random.default_rng(int(k) + 17)
+    Y = W.sphere_points(20000, rng)                   # sources on the unit sphere with their outward normals
+    X = W.sphere_points(15000, rng) * 0.985           # targets just inside
+    wu = ((rng.standard_normal(20000) + 1j * rng.standard_normal(20000)) / 20000).astype(np.complex64)
+    print("dl kernel %d k=%g eps=%g" % (kernel, k, eps), flush=True)
+    gp = _plan(X, Y, kernel, k, eps, Y)
+    st = gp.stats()
+    op = oracle_like(orc, gp, X, Y, kernel, k, eps, source_normals=Y)
+    compare_trees(gp, op)
+    v = gpu_apply(gp, wu)
+    vo = op.apply(wu)
+    rows = np.arange(0, 15000, 29)
+    d = orc.dense_rows_dl(X, Y, wu, kernel - 4, k, Y, rows)
+    print("dl kernel %d k=%g eps=%g: methods %s forms %s aca %s: vs oracle %.3e, vs dense %.3e (oracle %.3e)"
+          % (kernel, k, eps, st["method"][:st["leaf"] + 1], st["tform"][:st["leaf"] + 1], st["aca"][:st["leaf"] + 1],
+             rel(v, vo), rel(v[rows], d), rel(vo[rows], d)))
+    assert 3 not in st["tform"]                           # direct transforms (the source side in direction pairs)
+    if k >= 45:
+        assert 2 in st["tform"]                           # the target side of the coarse levels in ring pairs
+    assert rel(v, vo) < FP32_RTOL
+    assert rel(v[rows], d) <= eps
+    assert np.array_equal(v, gpu_apply(gp, wu))
+
+
+def test_dl_mixed_precision_is_fp32():
+    """A Laplace plan asking for mixed precision: its Lagrange transfers stay FP32, so the product is bitwise
+    that of the FP32 plan."""
+    rng = np.random.default_rng(5)
+    Y = W.sphere_points(30000, rng)
+    X = W.sphere_points(20000, rng) * 1.01
+    wu = ((rng.standard_normal(30000) + 1j * rng.standard_normal(30000)) / 30000).astype(np.complex64)
+    print("dl mixed precision", flush=True)
+    a = _plan(X, Y, 4, 0.0, 1e-3, Y)
+    b = _plan(X, Y, 4, 0.0, 1e-3, Y, precision=1)
+    assert not any(b.stats()["prec"])
+    assert np.array_equal(gpu_apply(a, wu), gpu_apply(b, wu))
+
+
+def test_dl_same_set_adaptive_and_batch(orc):
+    """One set with its own normals (the self term excluded) under the per-pair leaf rule (the early lists use the
+    same derivative kernel), and a batch mixing it with a potential plan: each instance bitwise its own apply."""
+    import torch
+    import paper_1909_05600_amd as ffm
+    w = W.sphere_plus_cube(40000, seed=6, eps=1e-3, n_rows=256)
+    rng = np.random.default_rng(8)
+    N = W.sphere_points(w.X.shape[0], rng)                 # unit normals in random directions
+    Xd = torch.from_numpy(w.X).cuda()
+    Nd = torch.from_numpy(N).cuda()
+    print("dl same set adaptive", flush=True)
+    gp = ffm.Plan(Xd, Xd, 5, w.k, 1e-3, source_normals=Nd, adaptive=True)
+    st = gp.stats()
+    assert sum(st["nearly"]) > 0
+    v = gpu_apply(gp, w.wu)
+    vo = oracle_like(orc, gp, w.X, w.X, 5, w.k, 1e-3, source_normals=N, adaptive=True).apply(w.wu)
+    d = orc.dense_rows_dl(w.X, w.X, w.wu, 1, w.k, N, w.rows)
+    print("same set adaptive: vs oracle %.3e, vs dense %.3e" % (rel(v, vo), rel(v[w.rows], d)))
+    assert rel(v, vo) < FP32_RTOL
+    assert rel(v[w.rows], d) <= 1e-3
+    other = ffm.Plan(Xd, Xd, 1, w.k, 1e-3)
+    ref_other = gpu_apply(other, w.wu)
+    u = torch.from_numpy(w.wu).cuda()
+    b = ffm.Batch([gp, other], graph=True)
+    outs = b.apply([u, u])
+    torch.cuda.synchronize()
+    assert np.array_equal(outs[0].cpu().numpy().astype(np.complex128), v)
+    assert np.array_equal(outs[1].cpu().numpy().astype(np.complex128), ref_other)
+    b.destroy()
+
+
+@pytest.mark.parametrize("kernel,k", [(0, 0.0), (1, 25.0)])
+def test_dl_is_transpose_of_dn(kernel, k):
+    """<u, DL w> = <w, DN u> with the sets exchanged and the same normals: the two GPU products agree to the
+    FP32 rounding of their sums (the oracle's FFMs satisfy it to FP64 rounding)."""
+    import torch
+    import paper_1909_05600_amd as ffm
+    rng = np.random.default_rng(9)
+    Y = W.sphere_points(25000, rng)
+    X = W.sphere_points(18000, rng) * 0.97
+    w = ((rng.standard_normal(25000) + 1j * rng.standard_normal(25000)) / 25000).astype(np.complex64)
+    u = ((rng.standard_normal(18000) + 1j * rng.standard_normal(18000)) / 18000).astype(np.complex64)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    print("dl transpose kernel %d k=%g" % (kernel, k), flush=True)
+    dl = ffm.Plan(Xd, Yd, kernel + 4, k, 1e-4, source_normals=Yd)
+    dn = ffm.Plan(Yd, Xd, kernel + 2, k, 1e-4, normals=Yd)
+    a = np.dot(u.astype(np.complex128), gpu_apply(dl, w))
+    v2 = gpu_apply(dn, u)
+    b = np.dot(w.astype(np.complex128), v2)
+    scale = np.linalg.norm(w) * np.linalg.norm(v2)
+    print("transpose: %.3e of |w| |DN u|" % (abs(a - b) / scale))
+    assert abs(a - b) < 1e-5 * scale
+
+
+def test_dl_needs_normals():
+    import torch
+    import paper_1909_05600_amd as ffm
+    X = torch.from_numpy(W.sphere_points(500, np.random.default_rng(1))).cuda()
+    with pytest.raises(ffm.FFMError) as e:
+        ffm.Plan(X, X, ffm.FFM_HELMHOLTZ_DL, 5.0, 1e-3)
+    assert e.value.code == -1 and "normals" in str(e.value)
+    # target normals do not stand in for source normals
+    with pytest.raises(ffm.FFMError):
+        ffm.Plan(X, X, ffm.FFM_LAPLACE_DL, 0.0, 1e-3, normals=X)
