@@ -1382,12 +1382,15 @@ k_grid_phi_r(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
 // lane group g); each wave then runs on its own over its 8-azimuth column tiles (tiles w, w + 4, ...): the Ey
 // values a lane needs come from memory straight into registers one tile ahead, Ex goes through a
 // wave-private LDS slice, and the sums over a are completed inside the wave (its 4 rows per lane, then across
-// the two parts and the four lane groups).  Item (desc, box, ring, 0).
+// the two parts and the four lane groups).  Steps go in groups of two (their LDS reads issued together), and
+// the kernel keeps to 53 KB of LDS and the registers of three waves per SIMD, so that three blocks share a CU
+// (64 nodes: 0.58 -> 0.53 ms on the 1M-point sphere's level 2 against groups of four steps at two blocks per
+// CU).  Item (desc, box, ring, 0).
 template <int P16>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     constexpr int P = 16 * P16, S = 4 * P16, NX = P / 8;   // nodes, MFMA steps, Ex values per lane and tile
-    constexpr int kExR = 20;                                // floats per Ex row: 8 complex azimuths + pad
+    constexpr int kExR = 16;                                // floats per Ex row: 8 complex azimuths
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int sb = wk.y, m = wk.z, L = d.L, mt = min(m, L - m);
@@ -1442,22 +1445,22 @@ k_grid_phi_s(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
         for (int q = 0; q < P16; ++q) acc[q][0] = acc[q][1] = floatx4{0.f, 0.f, 0.f, 0.f};
         const float *al = As + lg * kRow128 + li;
 #pragma unroll
-        for (int g = 0; g < P16; ++g) {
-            float av[4][P16][2];
+        for (int g = 0; g < 2 * P16; ++g) {
+            float av[2][P16][2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
                 for (int q = 0; q < P16; ++q) {
-                    av[u][q][0] = al[4 * (4 * g + u) * kRow128 + q * 32];
-                    av[u][q][1] = al[4 * (4 * g + u) * kRow128 + q * 32 + 16];
+                    av[u][q][0] = al[4 * (2 * g + u) * kRow128 + q * 32];
+                    av[u][q][1] = al[4 * (2 * g + u) * kRow128 + q * 32 + 16];
                 }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
                 for (int q = 0; q < P16; ++q) {
-                    acc[q][0] = mfma16(av[u][q][0], bv[4 * g + u], acc[q][0]);
-                    acc[q][1] = mfma16(av[u][q][1], bv[4 * g + u], acc[q][1]);
+                    acc[q][0] = mfma16(av[u][q][0], bv[2 * g + u], acc[q][0]);
+                    acc[q][1] = mfma16(av[u][q][1], bv[2 * g + u], acc[q][1]);
                 }
             __builtin_amdgcn_sched_barrier(0);
         }

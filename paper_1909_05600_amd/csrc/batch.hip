@@ -268,7 +268,7 @@ void cache_write(const std::string &path, const std::map<std::string, CacheEntry
 bool batch_has_rings(const Batch &B) {
     for (const Plan *P : B.plans)
         for (int l = 1; l <= P->leaf; ++l)
-            if (P->lev[l].method == kGegenbauer && P->lev[l].L >= 32) return true;
+            if (P->lev[l].method == kGegenbauer && P->lev[l].L >= kRingMinL) return true;
     return false;
 }
 

@@ -284,6 +284,11 @@ void upload_stage_items(const std::vector<Stage *> &stages, DevBuf<int4> &arena,
 // Ring-pair blocks (16 ring pairs each) per work item of the grid form's sums over z: at most four per item,
 // balanced over the items.
 // Direction pairs per transfer tile: the tile of every class's D is staged in LDS (at most 48 KB).
+// Gegenbauer levels of at least this order run the direct transforms in the ring-pair form (measured on the
+// 1M-point sphere: L = 26 0.48 against 0.54 ms for both transforms in direction pairs; L = 16 0.59 against
+// 0.24 ms)
+constexpr int kRingMinL = 24;
+
 __host__ __device__ inline int transfer_qt(int ncls) {
     return ncls * 4 * 16 <= 49152 ? 4 : (ncls * 2 * 16 <= 49152 ? 2 : 1);
 }

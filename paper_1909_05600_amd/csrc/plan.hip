@@ -2210,7 +2210,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             }
         } else if (LV.method == kGegenbauer) {
             const int L = LV.L;
-            LV.qG = L >= 64 ? tu.ring_g : (L >= 32 ? 2 : 0);
+            LV.qG = L >= 64 ? tu.ring_g : (L >= kRingMinL ? 2 : 0);
             if (LV.qG && (L + LV.qG - 1) / LV.qG > kThreads) LV.qG = 4;   // one ring must fit one block
             // the normal derivative at the targets multiplies every direction by its own ik (s . n): the target
             // transform runs in the direction-pair form
