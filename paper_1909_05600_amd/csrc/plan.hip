@@ -2215,7 +2215,9 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             // the normal derivative at the targets multiplies every direction by its own ik (s . n): the target
             // transform runs in the direction-pair form
             const bool ring_bwd = LV.qG && !P.dn;
-            LV.bwd_tile = ring_bwd ? kThreads * tu.bwd_pt : kThreads;
+            // two target points per thread only where the target boxes hold more than a block's worth on average
+            const int bpt = LV.pts_tgt > (double)kThreads * (double)std::max<size_t>(1, LV.h_tgt.size()) ? tu.bwd_pt : 1;
+            LV.bwd_tile = ring_bwd ? kThreads * bpt : kThreads;
             std::vector<int4> fw;
             // the normal derivative at the sources multiplies every direction by its own -ik (s . n): the source
             // transform runs in the direction-pair form (the ring form still serves the target transform)
@@ -2259,14 +2261,14 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             int64_t tiles = 0;
             for (int32_t t : LV.h_tgt) tiles += (sx[t + 1] - sx[t] + LV.bwd_tile - 1) / LV.bwd_tile;
             // ring parts of the target transform: enough blocks for several rounds of the chip
-            LV.bSplit = ring_bwd ? choose_split(tiles, conc_bwd[tu.bwd_pt == 2][LV.phase64], 8, LV.nrp) : 1;
+            LV.bSplit = ring_bwd ? choose_split(tiles, conc_bwd[bpt == 2][LV.phase64], 8, LV.nrp) : 1;
             if (LV.bSplit > 1) ws_bpart = std::max(ws_bpart, (size_t)LV.bSplit * P.nx);
             bw.reserve((size_t)(tiles * LV.bSplit));
             for (int g = 0; g < LV.bSplit; ++g)
                 for (int32_t t : LV.h_tgt)
                     for (int32_t i = sx[t]; i < sx[t + 1]; i += LV.bwd_tile) bw.push_back(make_int4(l, t, i, g));
             if (ring_bwd)
-                LV.stages.push_back(make_stage(K_BWD_RING, tu.bwd_pt, LV.phase64, LV.bSplit > 1 ? -1 : s3, l, 0,
+                LV.stages.push_back(make_stage(K_BWD_RING, bpt, LV.phase64, LV.bSplit > 1 ? -1 : s3, l, 0,
                                                std::move(bw), st, SC));
             else
                 LV.stages.push_back(make_stage(P.dn ? K_BWD_PAIR_DN : K_BWD_PAIR, small ? 100 : 0, LV.phase64, s3, l, 0,
