@@ -25,6 +25,8 @@ LAPLACE_DN = 2          # normal derivative at the target: the adjoint double-la
 HELMHOLTZ_DN = 3
 LAPLACE_DL = 4          # normal derivative at the source: the double-layer kernel
 HELMHOLTZ_DL = 5
+LAPLACE_GRAD = 6        # gradient at the target: three components per target
+HELMHOLTZ_GRAD = 7
 
 
 def build(force: bool = True) -> str:
@@ -84,6 +86,7 @@ def lib():
             "orc_aca": (C.c_int, [C.c_int, P, dbl, P, P]),
             "orc_dense_rows_dn": (None, [P, P, i64, P, C.c_int, dbl, P, P, i64, P]),
             "orc_dense_rows_dl": (None, [P, P, i64, P, C.c_int, dbl, P, P, i64, P]),
+            "orc_dense_rows_grad": (None, [P, P, i64, P, C.c_int, dbl, P, i64, P]),
             "orc_lagrange_basis_deriv": (None, [C.c_int, dbl, P]),
             "orc_aca_ranks": (C.c_int, [P, C.c_int, dbl, P, P]),
         }
@@ -153,6 +156,18 @@ def dense_rows_dl(X, Y, wu, kernel: int, k: float, NY, rows) -> np.ndarray:
     out = np.zeros(r.size, dtype=np.complex128)
     lib().orc_dense_rows_dl(_ptr(X), _ptr(Y), Y.shape[0], _ptr(w), int(kernel) & 1, float(k), _ptr(N), _ptr(r),
                             r.size, _ptr(out))
+    return out
+
+
+def dense_rows_grad(X, Y, wu, kernel: int, k: float, rows) -> np.ndarray:
+    """FP64 direct sum of the gradient at the targets, v_i = sum_{j: r_ij > 0} grad_x G(x_i - y_j) wu_j, on the
+    given rows: complex128 (rows, 3); kernel is the base kernel (0 or 1)."""
+    X, Y = _coords(X), _coords(Y)
+    w = _complex128(wu)
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).ravel())
+    out = np.zeros((r.size, 3), dtype=np.complex128)
+    lib().orc_dense_rows_grad(_ptr(X), _ptr(Y), Y.shape[0], _ptr(w), int(kernel) & 1, float(k), _ptr(r), r.size,
+                              _ptr(out))
     return out
 
 
@@ -294,8 +309,10 @@ class Plan:
             self._h = None
 
     def apply(self, wu, stride: int = 1) -> np.ndarray:
+        """The product: complex128 (n_x,), or (n_x, 3) for the gradient kernels."""
         w = _complex128(wu)
-        v = np.zeros(self.X.shape[0], dtype=np.complex128)
+        grad = self.kernel in (LAPLACE_GRAD, HELMHOLTZ_GRAD)
+        v = np.zeros((self.X.shape[0], 3) if grad else self.X.shape[0], dtype=np.complex128)
         lib().orc_apply(self._h, _ptr(w), _ptr(v), int(stride))
         return v
 

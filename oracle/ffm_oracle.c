@@ -143,6 +143,26 @@ void orc_dense_rows_dn(const double *X, const double *Y, int64_t ny, const doubl
     }
 }
 
+void orc_dense_rows_grad(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
+                         const int64_t *rows, int64_t nrows, double *out)
+{
+    static const double axis[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < nrows; ++a) {
+        const double *x = X + 3 * rows[a];
+        double complex acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < ny; ++j) {
+            double d[3] = {x[0] - Y[3 * j], x[1] - Y[3 * j + 1], x[2] - Y[3 * j + 2]};
+            if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] == 0.0) continue;   /* R11 */
+            for (int c = 0; c < 3; ++c) acc[c] += green_dn(kernel, k, d, axis[c]) * cload(wu, j);
+        }
+        for (int c = 0; c < 3; ++c) {
+            out[2 * (3 * a + c)] = creal(acc[c]);
+            out[2 * (3 * a + c) + 1] = cimag(acc[c]);
+        }
+    }
+}
+
 void orc_dense_rows_dl(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
                        const double *NY, const int64_t *rows, int64_t nrows, double *out)
 {
@@ -614,6 +634,7 @@ struct orc_plan {
     int kernel;                /* ORC_LAPLACE or ORC_HELMHOLTZ */
     int dn;                    /* 1: the normal derivative at the targets (adjoint double layer) */
     int dl;                    /* 1: the normal derivative at the sources (double layer) */
+    int grad;                  /* 1: the gradient at the targets: the dn machinery once per axis, NXs = that axis */
     double *NYs;               /* source normals in sorted order (dl plans) */
     double *NXs;               /* target normals in sorted order (dn plans) */
     double k, eps;
@@ -799,7 +820,8 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
                           int kernel, double k, double eps, const orc_options *opt)
 {
     orc_plan *p = calloc(1, sizeof(orc_plan));
-    p->dn = kernel == ORC_LAPLACE_DN || kernel == ORC_HELMHOLTZ_DN;
+    p->grad = kernel == ORC_LAPLACE_GRAD || kernel == ORC_HELMHOLTZ_GRAD;
+    p->dn = kernel == ORC_LAPLACE_DN || kernel == ORC_HELMHOLTZ_DN || p->grad;
     p->dl = kernel == ORC_LAPLACE_DL || kernel == ORC_HELMHOLTZ_DL;
     kernel &= 1;
     p->kernel = kernel;
@@ -858,9 +880,11 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
         tree_level(&p->T[e], 0, d0);
     }
     if (p->dn) {
-        p->NXs = malloc(sizeof(double) * 3 * (size_t)nx);
-        for (int64_t i = 0; i < nx; ++i)
-            for (int d = 0; d < 3; ++d) p->NXs[3 * i + d] = opt->target_normals[3 * p->T[0].perm[i] + d];
+        /* gradient plans: set per axis by orc_apply */
+        p->NXs = calloc(3 * (size_t)nx, sizeof(double));
+        if (!p->grad)
+            for (int64_t i = 0; i < nx; ++i)
+                for (int d = 0; d < 3; ++d) p->NXs[3 * i + d] = opt->target_normals[3 * p->T[0].perm[i] + d];
     }
     if (p->dl) {
         p->NYs = malloc(sizeof(double) * 3 * (size_t)ny);
@@ -1408,26 +1432,40 @@ static void near_pairs_sum(const orc_plan *p, int l, const pairs_t *N, const dou
     free(ptr);
 }
 
-void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride)
+/* the product in tree order: vs += every level's far pairs, in order (Sec. 2.2), then the near field */
+static void apply_sorted(const orc_plan *p, const double complex *u, double complex *vs, int64_t stride)
 {
-    if (stride < 1) stride = 1;
-    int64_t nx = p->T[0].n, ny = p->T[1].n;
-    memset(v, 0, sizeof(double) * 2 * (size_t)nx);
-    if (p->empty) return;
-    /* permute the input into source tree order */
-    double complex *u = malloc(sizeof(double complex) * (size_t)ny);
-    for (int64_t j = 0; j < ny; ++j) u[j] = cload(wu, p->T[1].perm[j]);
-    double complex *vs = calloc((size_t)nx, sizeof(double complex));
-    /* descent: every level's far pairs, in order (Sec. 2.2) */
     for (int l = 1; l <= p->leaf; ++l) {
         if (p->method[l] == 1) level_lagrange(p, l, u, vs, stride);
         else if (p->method[l] == 2) level_gegenbauer(p, l, u, vs, stride);
     }
     near_field(p, u, vs, stride);
-    /* back to the user's target order */
-    for (int64_t i = 0; i < nx; ++i) {
-        v[2 * p->T[0].perm[i]] = creal(vs[i]);
-        v[2 * p->T[0].perm[i] + 1] = cimag(vs[i]);
+}
+
+void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride)
+{
+    if (stride < 1) stride = 1;
+    int64_t nx = p->T[0].n, ny = p->T[1].n;
+    const int ncomp = p->grad ? 3 : 1;
+    memset(v, 0, sizeof(double) * 2 * (size_t)nx * ncomp);
+    if (p->empty) return;
+    /* permute the input into source tree order */
+    double complex *u = malloc(sizeof(double complex) * (size_t)ny);
+    for (int64_t j = 0; j < ny; ++j) u[j] = cload(wu, p->T[1].perm[j]);
+    double complex *vs = malloc(sizeof(double complex) * (size_t)(nx > 0 ? nx : 1));
+    for (int c = 0; c < ncomp; ++c) {
+        /* gradient: component c is the derivative along axis c, the normal derivative with n = e_c */
+        if (p->grad)
+            for (int64_t i = 0; i < nx; ++i)
+                for (int d = 0; d < 3; ++d) p->NXs[3 * i + d] = d == c ? 1.0 : 0.0;
+        for (int64_t i = 0; i < nx; ++i) vs[i] = 0.0;
+        apply_sorted(p, u, vs, stride);
+        /* back to the user's target order */
+        for (int64_t i = 0; i < nx; ++i) {
+            const int64_t o = ncomp * p->T[0].perm[i] + c;
+            v[2 * o] = creal(vs[i]);
+            v[2 * o + 1] = cimag(vs[i]);
+        }
     }
     free(vs);
     free(u);

@@ -38,6 +38,10 @@ extern "C" {
  * operator (Sec. 4.2.1, eq. doubleLayer), for each base kernel; plans need source normals. */
 #define ORC_LAPLACE_DL 4
 #define ORC_HELMHOLTZ_DL 5
+/* The gradient at the target, grad_x G(x - y) (three components per target; the vector kernels of the
+ * integral operators of Sec. 4.2.2), for each base kernel; plans write v as n_x x 3 complex values. */
+#define ORC_LAPLACE_GRAD 6
+#define ORC_HELMHOLTZ_GRAD 7
 
 /* ---- plain definition ---------------------------------------------------- */
 /* out[a] = sum_{j : |x_rows[a] - y_j| > 0} G(|x_rows[a] - y_j|) * wu[j]  (complex128 out) */
@@ -50,6 +54,10 @@ void orc_dense_rows_dn(const double *X, const double *Y, int64_t ny, const doubl
                        const double *NX, const int64_t *rows, int64_t nrows, double *out);
 /* out[a] = sum_{j : |x - y_j| > 0} n_j . grad_y G(x - y_j) wu[j] at x = x_rows[a] with source normals NY (ny x 3);
  * kernel ORC_LAPLACE or ORC_HELMHOLTZ (the base kernel) */
+/* out[a][c] = sum_{j : |x - y_j| > 0} d/dx_c G(x - y_j) wu[j] at x = x_rows[a], c = 0, 1, 2 (out: nrows x 3
+ * complex); kernel ORC_LAPLACE or ORC_HELMHOLTZ (the base kernel) */
+void orc_dense_rows_grad(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
+                         const int64_t *rows, int64_t nrows, double *out);
 void orc_dense_rows_dl(const double *X, const double *Y, int64_t ny, const double *wu, int kernel, double k,
                        const double *NY, const int64_t *rows, int64_t nrows, double *out);
 
@@ -118,7 +126,8 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
                           int kernel, double k, double eps, const orc_options *opt);
 void orc_plan_free(orc_plan *p);
 
-/* apply: v (complex, user target order) = FFM(wu (complex, user source order)).
+/* apply: v (complex, user target order) = FFM(wu (complex, user source order)); gradient plans write n_x x 3
+ * values, v[3 i + c] the c-th component at target i.
  * stride > 1 evaluates, in every per-point loop (transforms, near-field targets),
  * only the points whose sorted index is a multiple of stride, keeping every box,
  * table and transfer: a bounded timing sample whose result is not the product. */

@@ -2,7 +2,7 @@
  * Driver for a host-sanitizer build of the oracle (AddressSanitizer + UndefinedBehaviorSanitizer, gcc): it
  * runs every entry point of oracle/ffm_oracle.c on small synthetic inputs (both kernels, Lagrange and
  * Gegenbauer levels, direct and grid transforms, ACA, the normal derivatives at the target and at the source,
- * the per-pair leaf rule, distinct and empty sets) and checks that the products are finite and agree with the dense definition.
+ * the gradient, the per-pair leaf rule, distinct and empty sets) and checks that the products are finite and agree with the dense definition.
  * Any out-of-bounds access, use after free, leak or undefined operation aborts the run.
  *
  * Test infrastructure: built and run by tests/test_oracle_sanitize.py only.
@@ -69,8 +69,10 @@ static void check(const char *name, const double *v, const double *d, const int6
 
 static void run(const char *name, const double *X, int64_t nx, const double *Y, int64_t ny, int kernel, double k,
                 double eps, const orc_options *opt, const double *normals) {
+    const int grad = kernel == ORC_LAPLACE_GRAD || kernel == ORC_HELMHOLTZ_GRAD;
+    const int nc = grad ? 3 : 1;
     double *wu = malloc(sizeof(double) * 2 * (size_t)(ny > 0 ? ny : 1));
-    double *v = malloc(sizeof(double) * 2 * (size_t)(nx > 0 ? nx : 1));
+    double *v = malloc(sizeof(double) * 2 * (size_t)nc * (nx > 0 ? nx : 1));
     input(wu, ny);
     orc_plan *p = orc_plan_create(X, nx, Y, ny, kernel, k, eps, opt);
     if (!p) {
@@ -113,7 +115,22 @@ static void run(const char *name, const double *X, int64_t nx, const double *Y, 
         const int64_t nr = nx < 40 ? nx : 40;
         int64_t *rows = malloc(sizeof(int64_t) * (size_t)nr);
         for (int64_t a = 0; a < nr; ++a) rows[a] = (a * 7919) % nx;
-        double *d = malloc(sizeof(double) * 2 * (size_t)nr);
+        double *d = malloc(sizeof(double) * 2 * (size_t)nr * nc);
+        if (grad) {
+            /* component by component: rows 3 r + c of the product against entries 3 a + c */
+            int64_t *r3 = malloc(sizeof(int64_t) * 3 * (size_t)nr);
+            for (int64_t a = 0; a < nr; ++a)
+                for (int c = 0; c < 3; ++c) r3[3 * a + c] = 3 * rows[a] + c;
+            orc_dense_rows_grad(X, Y, ny, wu, kernel & 1, k, rows, nr, d);
+            check(name, v, d, r3, 3 * nr, eps);
+            free(r3);
+            free(rows);
+            free(d);
+            orc_plan_free(p);
+            free(wu);
+            free(v);
+            return;
+        }
         if (kernel == ORC_LAPLACE_DL || kernel == ORC_HELMHOLTZ_DL)
             orc_dense_rows_dl(X, Y, ny, wu, kernel & 1, k, normals, rows, nr, d);
         else if (kernel >= ORC_LAPLACE_DN)
@@ -169,6 +186,11 @@ int main(void) {
     o.target_normals = N;
     run("laplace dn", X, n, X, n, ORC_LAPLACE_DN, 0.0, 1e-3, &o, N);
     run("helmholtz dn", X, n, X, n, ORC_HELMHOLTZ_DN, 25.0, 1e-3, &o, N);
+
+    /* gradient at the target */
+    memset(&o, 0, sizeof(o));
+    run("laplace grad", X, n, X, n, ORC_LAPLACE_GRAD, 0.0, 1e-3, &o, NULL);
+    run("helmholtz grad distinct sets", X, n, Y, 2000, ORC_HELMHOLTZ_GRAD, 20.0, 1e-3, &o, NULL);
 
     /* normal derivative at the source (double layer) */
     memset(&o, 0, sizeof(o));
