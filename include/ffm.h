@@ -48,10 +48,14 @@ typedef struct ffm_plan_s *ffm_plan_t;
  * their plane-wave levels with the direct transforms.  The _DL kernels are the normal derivative at the source,
  * dG/dn_y (x, y) = n_y . grad_y G(x - y), of the double-layer operator (same equation); they need
  * options.source_normals, run their plane-wave levels with the direct transforms (source side in the
- * direction-pair form) and their Lagrange transfers in FP32 whatever options.precision asks. */
+ * direction-pair form) and their Lagrange transfers in FP32 whatever options.precision asks.  The _GRAD kernels
+ * are the gradient at the target, grad_x G(x - y), three components per target (the vector kernels the integral
+ * operators of Sec. 4.2.2 are built from): their products v hold n_x x 3 values, v[3 i + c] the derivative
+ * along axis c at target i; the source transforms and transfers are shared by the three components, whose
+ * target transforms and near field run as those of the _DN kernels with n = e_c. */
 typedef enum {
     FFM_LAPLACE = 0, FFM_HELMHOLTZ = 1, FFM_LAPLACE_DN = 2, FFM_HELMHOLTZ_DN = 3, FFM_LAPLACE_DL = 4,
-    FFM_HELMHOLTZ_DL = 5
+    FFM_HELMHOLTZ_DL = 5, FFM_LAPLACE_GRAD = 6, FFM_HELMHOLTZ_GRAD = 7
 } ffm_kernel_t;
 
 typedef enum {
@@ -117,7 +121,8 @@ typedef struct {
  *          the same set: one tree serves both.
  *   kernel FFM_LAPLACE or FFM_HELMHOLTZ, or their normal derivatives at the
  *          targets FFM_LAPLACE_DN, FFM_HELMHOLTZ_DN or at the sources
- *          FFM_LAPLACE_DL, FFM_HELMHOLTZ_DL; k >= 0 is the wavenumber
+ *          FFM_LAPLACE_DL, FFM_HELMHOLTZ_DL, or their gradients at the targets
+ *          FFM_LAPLACE_GRAD, FFM_HELMHOLTZ_GRAD; k >= 0 is the wavenumber
  *          (ignored for Laplace; Helmholtz with k = 0 equals Laplace).
  *   eps    prescribed accuracy, 1e-7 <= eps < 0.5.
  *   opts   host pointer or NULL.
@@ -145,7 +150,8 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
  *   wu     device, n_y elements of in_dtype, in the caller's source order:
  *          the products w_j u_j of eq. (convolution_discrete).  Real inputs
  *          are taken as complex with zero imaginary part.
- *   v      device, complex64 [n_x], in the caller's target order; overwritten.
+ *   v      device, complex64 [n_x] ([n_x][3] for the _GRAD kernels), in the
+ *          caller's target order; overwritten.
  * Asynchronous on hip_stream: the caller keeps wu and v alive until the
  * stream passes the apply.  One apply per plan may be in flight at a time
  * (the plan's workspace is reused); a second apply on the same stream is

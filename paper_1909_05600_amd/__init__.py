@@ -19,6 +19,8 @@ FFM_LAPLACE_DN = 2          # normal derivative at the target (adjoint double-la
 FFM_HELMHOLTZ_DN = 3
 FFM_LAPLACE_DL = 4          # normal derivative at the source (double-layer kernel)
 FFM_HELMHOLTZ_DL = 5
+FFM_LAPLACE_GRAD = 6        # gradient at the target (three components per target)
+FFM_HELMHOLTZ_GRAD = 7
 FFM_C64, FFM_F32, FFM_F64, FFM_C128 = 0, 1, 2, 3
 FFM_PREC_FP32, FFM_PREC_MIXED = 0, 1
 FFM_EXPORT_KEYS, FFM_EXPORT_PERM, FFM_EXPORT_BOX_START, FFM_EXPORT_BOX_IJK = 0, 1, 2, 3
@@ -197,11 +199,8 @@ def apply_batched(plans, wus, outs=None, stream=None):
     for p, w in zip(plans, wus):
         if w.dtype != torch.complex64 or w.shape[0] != p.n_y or not w.is_cuda:
             raise ValueError("wu[i] must be a complex64 CUDA tensor of length n_y of plan i")
-    if outs is None:
-        outs = [torch.empty(p.n_x, dtype=torch.complex64, device=p.device) for p in plans]
-    for p, o in zip(plans, outs):
-        if o.dtype != torch.complex64 or o.shape[0] != p.n_x or not o.is_contiguous():
-            raise ValueError("outs[i] must be a contiguous complex64 tensor of length n_x of plan i")
+    outs = [_out(p, None, "outs[i]") for p in plans] if outs is None else \
+        [_out(p, o, "outs[i]") for p, o in zip(plans, outs)]
     hp = (C.c_void_p * n)(*[p._h for p in plans])
     wp = (C.c_void_p * n)(*[w.data_ptr() for w in wus])
     vp = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
@@ -242,6 +241,17 @@ def kernel_name(kernel: int, variant_a: int = 0, variant_b: int = 0) -> str:
     return buf.value.decode()
 
 
+def _out(plan, o, what="out"):
+    """The output tensor of a product of ``plan`` (allocated when o is None): complex64 (n_x,), or (n_x, 3)
+    for the gradient kernels, contiguous on the plan's device."""
+    import torch
+    if o is None:
+        return torch.empty(plan.out_shape, dtype=torch.complex64, device=plan.device)
+    if o.dtype != torch.complex64 or o.numel() != plan.n_x * plan.ncomp or not o.is_contiguous():
+        raise ValueError("%s must be a contiguous complex64 tensor of n_x (x 3 for gradient plans) elements" % what)
+    return o
+
+
 class Plan:
     """An FFM plan over device coordinates X (targets) and Y (sources).
 
@@ -267,6 +277,8 @@ class Plan:
                 raise TypeError("Y must be a CUDA float64 tensor of shape (n, 3)")
         self.n_x, self.n_y = int(X.shape[0]), int(Y.shape[0])
         self.kernel, self.k, self.eps = int(kernel), float(k), float(eps)
+        self.ncomp = 3 if self.kernel in (FFM_LAPLACE_GRAD, FFM_HELMHOLTZ_GRAD) else 1
+        self.out_shape = (self.n_x, 3) if self.ncomp == 3 else (self.n_x,)
         self.device = X.device
         flags = (FFM_FLAG_TIMING if timing else 0) | {"auto": 0, "direct": FFM_FLAG_DIRECT_TRANSFORMS,
                                                       "grid": FFM_FLAG_GRID_TRANSFORMS}[transforms] | \
@@ -292,10 +304,7 @@ class Plan:
         if wu.shape[0] != self.n_y or not wu.is_cuda:
             raise ValueError("wu must be a CUDA tensor of length n_y")
         wu = wu.contiguous()
-        if out is None:
-            out = torch.empty(self.n_x, dtype=torch.complex64, device=self.device)
-        elif out.dtype != torch.complex64 or out.shape[0] != self.n_x or not out.is_contiguous():
-            raise ValueError("out must be a contiguous complex64 tensor of length n_x")
+        out = _out(self, out)
         ffm_apply(self._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(), _stream(stream))
         return out
 
@@ -306,10 +315,7 @@ class Plan:
         import torch
         if wu.shape[0] != self.n_y or not wu.is_cuda or not wu.is_contiguous():
             raise ValueError("wu must be a contiguous CUDA tensor of length n_y")
-        if out is None:
-            out = torch.empty(self.n_x, dtype=torch.complex64, device=self.device)
-        elif out.dtype != torch.complex64 or out.shape[0] != self.n_x or not out.is_contiguous():
-            raise ValueError("out must be a contiguous complex64 tensor of length n_x")
+        out = _out(self, out)
         _check(lib().ffm_apply_static(self._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(), _stream(stream)))
         return out
 
@@ -413,11 +419,8 @@ class Batch:
         for p, w in zip(self.plans, wus):
             if w.shape[0] != p.n_y or not w.is_cuda:
                 raise ValueError("wu[i] must be a CUDA tensor of length n_y of plan i")
-        if outs is None:
-            outs = [torch.empty(p.n_x, dtype=torch.complex64, device=p.device) for p in self.plans]
-        for p, o in zip(self.plans, outs):
-            if o.dtype != torch.complex64 or o.shape[0] != p.n_x or not o.is_contiguous():
-                raise ValueError("outs[i] must be a contiguous complex64 tensor of length n_x of plan i")
+        outs = [_out(p, None, "outs[i]") for p in self.plans] if outs is None else \
+            [_out(p, o, "outs[i]") for p, o in zip(self.plans, outs)]
         wp = (C.c_void_p * n)(*[w.data_ptr() for w in wus])
         dt = (C.c_int32 * n)(*[_dtype_code(w) for w in wus])
         vp = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
@@ -464,10 +467,7 @@ class Server:
         import torch
         if wu.shape[0] != plan.n_y or not wu.is_cuda or not wu.is_contiguous():
             raise ValueError("wu must be a contiguous CUDA tensor of length n_y")
-        if out is None:
-            out = torch.empty(plan.n_x, dtype=torch.complex64, device=plan.device)
-        elif out.dtype != torch.complex64 or out.shape[0] != plan.n_x or not out.is_contiguous():
-            raise ValueError("out must be a contiguous complex64 tensor of length n_x")
+        out = _out(plan, out)
         t = C.c_int64()
         _check(lib().ffm_server_submit(self._h, plan._h, wu.data_ptr(), _dtype_code(wu), out.data_ptr(),
                                        _stream(stream), C.byref(t)))

@@ -158,8 +158,10 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: sizes must be in [0, 2^31)");
     if ((n_x > 0 && !X) || (n_y > 0 && !Y)) return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: NULL coordinates");
     if (kernel != FFM_LAPLACE && kernel != FFM_HELMHOLTZ && kernel != FFM_LAPLACE_DN && kernel != FFM_HELMHOLTZ_DN &&
-        kernel != FFM_LAPLACE_DL && kernel != FFM_HELMHOLTZ_DL)
+        kernel != FFM_LAPLACE_DL && kernel != FFM_HELMHOLTZ_DL && kernel != FFM_LAPLACE_GRAD &&
+        kernel != FFM_HELMHOLTZ_GRAD)
         return (ffm_status_t)set_err(FFM_EINVAL, "ffm_plan: unknown kernel");
+    const bool grad = kernel == FFM_LAPLACE_GRAD || kernel == FFM_HELMHOLTZ_GRAD;
     const bool dn = kernel == FFM_LAPLACE_DN || kernel == FFM_HELMHOLTZ_DN;
     const bool dl = kernel == FFM_LAPLACE_DL || kernel == FFM_HELMHOLTZ_DL;
     if (dn && n_x > 0 && !(opts && opts->target_normals))
@@ -188,12 +190,13 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     int rc = Guard::run([&] {
         std::unique_ptr<ffm_plan_s> p(new ffm_plan_s());
         Plan &P = p->P;
-        P.dn = dn;
+        P.dn = dn || grad;
+        P.grad = grad;
         P.user_normals = dn ? o.target_normals : nullptr;
         P.dl = dl;
         P.user_snormals = dl ? o.source_normals : nullptr;
-        P.kernel = (kernel == FFM_HELMHOLTZ || kernel == FFM_HELMHOLTZ_DN || kernel == FFM_HELMHOLTZ_DL) ? FFM_HELMHOLTZ
-                                                                                                          : FFM_LAPLACE;
+        P.kernel = (kernel == FFM_HELMHOLTZ || kernel == FFM_HELMHOLTZ_DN || kernel == FFM_HELMHOLTZ_DL ||
+                    kernel == FFM_HELMHOLTZ_GRAD) ? FFM_HELMHOLTZ : FFM_LAPLACE;
         P.k = P.kernel == FFM_HELMHOLTZ ? k : 0.0;
         P.eps = eps;
         P.opt = o;

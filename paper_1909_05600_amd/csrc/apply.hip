@@ -61,7 +61,8 @@ k_perm_in(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const
         }
         d.u[i] = r;
     }
-    if (i < d.nx) d.v[i] = make_float2(0.f, 0.f);
+    if (i < d.nx)
+        for (int c = 0; c < d.ncomp; ++c) d.v[(int64_t)c * d.nx + i] = make_float2(0.f, 0.f);
 }
 
 // max over |Re u|, |Im u| (non-negative floats compare as their bit patterns); item (desc, first index),
@@ -90,22 +91,28 @@ __global__ void __launch_bounds__(kThreads) k_zero_out(float2 *v, int64_t n) {
     if (i < n) v[i] = make_float2(0.f, 0.f);
 }
 
-// item (desc, first index): vout[i] = 0 for i < nx (an instance without sources inside a batch)
+// item (desc, first index): vout[i] = 0 for i < nx ncomp (an instance without sources inside a batch)
 __global__ void __launch_bounds__(kThreads)
 k_zero_io(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int64_t i = (int64_t)wk.y + threadIdx.x;
-    if (i < d.nx) io[d.inst].vout[i] = make_float2(0.f, 0.f);
+    if (i < d.nx * d.ncomp) io[d.inst].vout[i] = make_float2(0.f, 0.f);
 }
 
-// item (desc, first index): vout[perm_x[i]] = v[i]
+// item (desc, first index): vout[perm_x[i]] = v[i]; gradient plans: vout[3 perm_x[i] + c] = v[c nx + i]
 __global__ void __launch_bounds__(kThreads)
 k_perm_out(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const int4 *__restrict__ work) {
     const int4 wk = work[blockIdx.x];
     const LDesc &d = descs[wk.x];
     const int64_t i = (int64_t)wk.y + threadIdx.x;
-    if (i < d.nx) io[d.inst].vout[d.perm_x[i]] = d.v[i];
+    if (i >= d.nx) return;
+    if (d.ncomp == 1) {
+        io[d.inst].vout[d.perm_x[i]] = d.v[i];
+        return;
+    }
+    const int64_t o = 3 * (int64_t)d.perm_x[i];
+    for (int c = 0; c < 3; ++c) io[d.inst].vout[o + c] = d.v[(int64_t)c * d.nx + i];
 }
 
 // ------------------------------------------------------------------ Gegenbauer levels, direction pairs
@@ -454,7 +461,7 @@ __device__ __forceinline__ void pw_backward_body(const LDesc &d, const int4 wk) 
         y = (real)(d.tys[i] - d.tctr[3 * t + 1]);
         z = (real)(d.tzs[i] - d.tctr[3 * t + 2]);
         if (DN) {
-            const float4 n = d.tn[i];
+            const float4 n = d.tn ? d.tn[i] : d.tnc;
             nx = n.x;
             ny = n.y;
             nz = n.z;
@@ -2466,7 +2473,7 @@ __device__ __forceinline__ void lag_interp_body(const LDesc &d, const int4 wk) {
             lagrange_1d_deriv(tx, r1, nodes, den, dx);
             lagrange_1d_deriv(ty, r1, nodes, den, dy);
             lagrange_1d_deriv(tz, r1, nodes, den, dz);
-            const float4 n = d.tn[i];
+            const float4 n = d.tn ? d.tn[i] : d.tnc;
             for (int a = 0; a < r1; ++a) {
                 float b0r = 0.f, b0i = 0.f, b1r = 0.f, b1i = 0.f;
                 for (int bb = 0; bb < r1; ++bb) {
@@ -2724,7 +2731,7 @@ __device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, float4 *
             y[k] = (d.tys[i] - cy) * scale;
             z[k] = (d.tzs[i] - cz) * scale;
             if (NRM == 1) {
-                const float4 n = d.tn[i];
+                const float4 n = d.tn ? d.tn[i] : d.tnc;
                 nx[k] = n.x;
                 ny[k] = n.y;
                 nz[k] = n.z;
@@ -3201,7 +3208,8 @@ void plan_apply(Plan &P, const void *wu, int dtype, float2 *v, hipStream_t st) {
     P.tused = 0;
     if (P.empty) {
         P.mark(-1, st);
-        if (P.nx > 0) FFM_LAUNCH(k_zero_out, (int)((P.nx + kThreads - 1) / kThreads), kThreads, 0, st, v, P.nx);
+        const int64_t nv = P.nx * P.ncomp();
+        if (nv > 0) FFM_LAUNCH(k_zero_out, (int)((nv + kThreads - 1) / kThreads), kThreads, 0, st, v, nv);
         return;
     }
     // this apply's input and output go to the plan's I/O entry (pinned, copied in stream order); the

@@ -111,11 +111,12 @@ void batch_build(Batch &B, hipStream_t st) {
             std::memset(&d, 0, sizeof(d));
             d.inst = i;
             d.nx = P.nx;
+            d.ncomp = P.ncomp();
             B.hdesc.push_back(d);
             continue;
         }
-        for (int l = 0; l <= P.leaf; ++l) {
-            LDesc d = P.hdesc[l];
+        for (const LDesc &h : P.hdesc) {
+            LDesc d = h;
             d.inst = i;
             B.hdesc.push_back(d);
         }
@@ -137,7 +138,7 @@ void batch_build(Batch &B, hipStream_t st) {
             if (P.nx == 0) continue;
             Stage z;
             z.kern = K_ZERO_OUT;
-            for (int64_t j = 0; j < P.nx; j += kThreadsB) z.items.push_back(make_int4(0, (int)j, 0, 0));
+            for (int64_t j = 0; j < P.nx * P.ncomp(); j += kThreadsB) z.items.push_back(make_int4(0, (int)j, 0, 0));
             add(2, z, base[i]);
             continue;
         }
@@ -283,7 +284,7 @@ Tune autotune(Batch &B, hipStream_t st) {
     int64_t maxny = 1, sumnx = 0;
     for (const Plan *P : B.plans) {
         maxny = std::max(maxny, P->ny);
-        sumnx += P->nx;
+        sumnx += P->nx * P->ncomp();
     }
     DevBuf<float2> in(maxny), out(std::max<int64_t>(sumnx, 1));
     FFM_HIP(hipMemsetAsync(in.p, 0, in.bytes(), st));
@@ -292,7 +293,7 @@ Tune autotune(Batch &B, hipStream_t st) {
         B.hio[i].wu = in.p;
         B.hio[i].vout = out.p + off;
         B.hio[i].dtype = FFM_C64;
-        off += B.plans[i]->nx;
+        off += B.plans[i]->nx * B.plans[i]->ncomp();
     }
     FFM_HIP(hipMemcpyAsync(B.dio.p, B.hio, B.plans.size() * sizeof(IoEntry), hipMemcpyHostToDevice, st));
     hipEvent_t e0, e1;

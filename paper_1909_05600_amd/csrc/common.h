@@ -232,6 +232,10 @@ struct LDesc {
     const _Float16 *T16;
     const float4 *tn;                      // target normals in sorted order (normal-derivative kernels), or null
     const float4 *sn;                      // source normals in sorted order (double-layer kernels), or null
+    float4 tnc;                            // the target normal of every point where tn is null (gradient plans:
+                                           // the axis of the descriptor's component)
+    int ncomp;                             // output components per target: 1, or 3 (gradient plans; component c
+                                           // of sorted target i at v[c nx + i] of the level-0 descriptor's v)
     const float *acaA, *acaB;              // ACA factors: A [class][plane][kpm][rp], B^T [class][plane][rp][kpm]
     const int32_t *acaKp;                  // [class] rank padded to 32
     int kpm;                               // largest padded rank
@@ -391,6 +395,8 @@ struct Plan {
     bool dn = false;                     // normal derivative at the targets (adjoint double layer)
     const double *user_normals = nullptr;   // the caller's target normals, read while the plan is built
     DevBuf<float4> tnrm;                 // target normals in sorted order (FP32)
+    bool grad = false;                   // gradient at the targets: the dn stages once per axis (dn also set)
+    int ncomp() const { return grad ? 3 : 1; }
     bool dl = false;                     // normal derivative at the sources (double layer)
     const double *user_snormals = nullptr;  // the caller's source normals, read while the plan is built
     DevBuf<float4> snrm;                 // source normals in sorted order (FP32)
@@ -488,6 +494,10 @@ int stage_blocks_per_cu(int kern, int a, int b);
 std::string kernel_name(int kern, int a, int b);
 int device_cus();
 LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w);
+// A plan's descriptors: one per level, and for gradient plans two more sets (components 1 and 2: descriptor
+// k serves level k mod (leaf + 1), component k / (leaf + 1), with its own output plane and axis).
+int plan_ndesc(const Plan &P);
+LDesc plan_desc(const Plan &P, int k, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w);
 // rebuild the stages and descriptors of a built plan for a tile choice (the plan must be idle)
 void plan_set_tune(Plan &P, const Tune &t, hipStream_t st, Scratch *keep = nullptr);
 // Wait on the host until the plan's own GPU work is complete (plans return with their last tables and launch

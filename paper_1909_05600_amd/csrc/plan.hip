@@ -1349,7 +1349,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     Scratch SC(st);
     P.tx.reset(new Tree());
     build_tree(*P.tx, X, nx, corner[0], P.S, st, SC);
-    if (P.dn) {
+    if (P.dn && !P.grad) {
         // read before the plan's next host wait, so the caller may free the normals when ffm_plan returns
         P.tnrm.alloc(nx);
         FFM_LAUNCH(k_gather_normals, nblocks(nx), kThreads, 0, st, P.user_normals, nx, P.tx->perm.p, P.tnrm.p);
@@ -1846,7 +1846,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.ws_tgt = ws_tgt;
     P.ws_z = ws_z;
     P.u_sorted.alloc(ny);
-    P.v_sorted.alloc(nx);
+    P.v_sorted.alloc(nx * P.ncomp());
     P.wsrc.alloc(ws_src);
     P.wtgt.alloc(ws_tgt);
     P.wz.alloc(ws_z);
@@ -2338,6 +2338,33 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         }
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
     }
+    // gradient plans: the target-side stages of the normal derivative once more for components 1 and 2, over
+    // their own descriptors (same work, items pointing at descriptor k + c (leaf + 1)); the last copy closes
+    // the original's timing slot
+    if (P.grad) {
+        auto triple = [&](std::vector<Stage> &v) {
+            std::vector<Stage> out;
+            for (Stage &S : v) {
+                const bool tgt = S.kern == K_INTERP_DN || S.kern == K_BWD_PAIR_DN || S.kern == K_NEAR_DN;
+                if (!tgt) {
+                    out.push_back(std::move(S));
+                    continue;
+                }
+                const Stage orig = S;
+                S.slot = -1;
+                out.push_back(std::move(S));
+                for (int c = 1; c < 3; ++c) {
+                    Stage C = orig;
+                    for (int4 &x : C.items) x.x += c * (P.leaf + 1);
+                    C.slot = c == 2 ? orig.slot : -1;
+                    out.push_back(std::move(C));
+                }
+            }
+            v = std::move(out);
+        };
+        for (int l = 1; l <= P.leaf; ++l) triple(P.lev[l].stages);
+        triple(P.post);
+    }
     // timing slot of every stage: a stage that closes no phase belongs to the next one that does
     auto fill = [](std::vector<Stage> &v) {
         int next = -1;
@@ -2427,6 +2454,8 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.T16 = LV.T16.p;
     d.tn = P.tnrm.p;
     d.sn = P.snrm.p;
+    d.tnc = make_float4(1.f, 0.f, 0.f, 0.f);
+    d.ncomp = P.ncomp();
     d.acaA = LV.acaA.p;
     d.acaB = LV.acaB.p;
     d.acaKp = LV.acaKp.p;
@@ -2460,6 +2489,15 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     return d;
 }
 
+int plan_ndesc(const Plan &P) { return (P.leaf + 1) * P.ncomp(); }
+
+LDesc plan_desc(const Plan &P, int k, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w) {
+    const int l = k % (P.leaf + 1), c = k / (P.leaf + 1);
+    LDesc d = make_desc(P, l, inst, u, v + (int64_t)c * P.nx, amax, w);
+    d.tnc = make_float4(c == 0 ? 1.f : 0.f, c == 1 ? 1.f : 0.f, c == 2 ? 1.f : 0.f, 0.f);
+    return d;
+}
+
 void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     plan_stages(P, tu, st, keep);
     P.tune = tu;
@@ -2475,7 +2513,7 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     w.H = P.wH.p;
     w.nsym = P.wnsym.p;
     P.hdesc.clear();
-    for (int l = 0; l <= P.leaf; ++l) P.hdesc.push_back(make_desc(P, l, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
+    for (int k = 0; k < plan_ndesc(P); ++k) P.hdesc.push_back(plan_desc(P, k, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
     upload(P.ddesc, P.hdesc, st, SC);
     if (keep) keep->adopt(SC);

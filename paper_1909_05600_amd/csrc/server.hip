@@ -37,7 +37,7 @@ struct ReqWork {
 
 size_t apply_work_bytes(const Plan &P) {
     if (P.empty) return 0;
-    return align256(sizeof(float2) * P.ny) + align256(sizeof(float2) * P.nx) + align256(sizeof(float4) * P.ws_src) +
+    return align256(sizeof(float2) * P.ny) + align256(sizeof(float2) * P.nx * P.ncomp()) + align256(sizeof(float4) * P.ws_src) +
            align256(sizeof(float4) * P.ws_tgt) + align256(sizeof(float2) * P.ws_z) +
            align256(sizeof(float4) * P.wpart.n) + align256(sizeof(float2) * P.wbpart.n) +
            align256(sizeof(float2) * P.wG.n) + align256(sizeof(float2) * P.wH.n) + align256(sizeof(float2) * P.wnsym.n) +
@@ -52,7 +52,7 @@ WorkPtrs carve_work(const Plan &P, char *p) {
         return q;
     };
     w.u = reinterpret_cast<float2 *>(take(sizeof(float2) * P.ny));
-    w.v = reinterpret_cast<float2 *>(take(sizeof(float2) * P.nx));
+    w.v = reinterpret_cast<float2 *>(take(sizeof(float2) * P.nx * P.ncomp()));
     w.lw.ut = reinterpret_cast<float4 *>(take(sizeof(float4) * P.ws_src));
     w.lw.vt = reinterpret_cast<float4 *>(take(sizeof(float4) * P.ws_tgt));
     w.lw.ut2 = reinterpret_cast<float2 *>(w.lw.ut);
@@ -132,17 +132,17 @@ void Server::start_one(Request *r, int slot) {
     if (P.empty) {
         if (r->ready) FFM_HIP(hipStreamWaitEvent(st, r->ready, 0));
         // no sources or no targets: the output is zero
-        if (P.nx > 0) FFM_HIP(hipMemsetAsync(r->io.vout, 0, sizeof(float2) * P.nx, st));
+        if (P.nx > 0) FFM_HIP(hipMemsetAsync(r->io.vout, 0, sizeof(float2) * P.nx * P.ncomp(), st));
         FFM_HIP(hipEventRecord(r->ev, st));
         return;
     }
     carve(P, r->work);
     const WorkPtrs &w = r->work.w;
-    const int nd = P.leaf + 1;
+    const int nd = plan_ndesc(P);
     const size_t db = sizeof(LDesc) * nd;
     r->pinned = pinned_alloc(db + sizeof(IoEntry));
     LDesc *hd = static_cast<LDesc *>(r->pinned);
-    for (int l = 0; l < nd; ++l) hd[l] = make_desc(P, l, 0, w.u, w.v, w.amax, w.lw);
+    for (int k = 0; k < nd; ++k) hd[k] = plan_desc(P, k, 0, w.u, w.v, w.amax, w.lw);
     IoEntry *hio = reinterpret_cast<IoEntry *>(static_cast<char *>(r->pinned) + db);
     *hio = r->io;
     r->ddesc.alloc(nd);

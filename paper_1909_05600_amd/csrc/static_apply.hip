@@ -61,11 +61,11 @@ void plan_static_setup(Plan &P, hipStream_t st) {
     if (P.empty || apply_work_bytes(P) > kScratchBytes) return;
     char *base = static_work_base();
     const WorkPtrs w = carve_work(P, base);
-    const int nd = P.leaf + 1;
+    const int nd = plan_ndesc(P);
     // pinned host block held by the plan: the descriptors (copied once, here) and the I/O entry of each apply
     P.spin = pinned_alloc(sizeof(LDesc) * nd + sizeof(IoEntry));
     LDesc *hd = static_cast<LDesc *>(P.spin);
-    for (int l = 0; l < nd; ++l) hd[l] = make_desc(P, l, 0, w.u, w.v, w.amax, w.lw);
+    for (int k = 0; k < nd; ++k) hd[k] = plan_desc(P, k, 0, w.u, w.v, w.amax, w.lw);
     P.shio = reinterpret_cast<IoEntry *>(hd + nd);
     std::memset(P.shio, 0, sizeof(IoEntry));
     P.sdesc.alloc((size_t)nd);
@@ -97,7 +97,8 @@ ffm_status_t ffm_apply_static(ffm_plan_t plan, const void *wu, ffm_dtype_t in_dt
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         if (P.empty) {
             if (P.nx > 0)
-                FFM_LAUNCH(k_fill_zero, (int)((P.nx + 255) / 256), 256, 0, st, static_cast<float2 *>(v), P.nx);
+                FFM_LAUNCH(k_fill_zero, (int)((P.nx * P.ncomp() + 255) / 256), 256, 0, st, static_cast<float2 *>(v),
+                           P.nx * P.ncomp());
             return;
         }
         // the pinned I/O entry is read by the previous static apply's copy until that apply's event completes

@@ -47,7 +47,8 @@ def test_invalid_arguments_are_rejected_before_any_device_work(L):
         (dummy, 10, dummy, 10, 0, 0.0, 1e-3, None, None, None),         # out == NULL
         (dummy, -1, dummy, 10, 0, 0.0, 1e-3, None, None, C.byref(h)),   # negative size
         (None, 10, dummy, 10, 0, 0.0, 1e-3, None, None, C.byref(h)),    # NULL X
-        (dummy, 10, dummy, 10, 7, 0.0, 1e-3, None, None, C.byref(h)),   # unknown kernel
+        (dummy, 10, dummy, 10, 8, 0.0, 1e-3, None, None, C.byref(h)),   # unknown kernel
+        (dummy, 10, dummy, 10, -1, 0.0, 1e-3, None, None, C.byref(h)),  # unknown kernel
         (dummy, 10, dummy, 10, 1, -2.0, 1e-3, None, None, C.byref(h)),  # k < 0
         (dummy, 10, dummy, 10, 1, float("nan"), 1e-3, None, None, C.byref(h)),
         (dummy, 10, dummy, 10, 0, 0.0, 0.0, None, None, C.byref(h)),    # eps <= 0
@@ -144,6 +145,7 @@ def test_kernel_names_and_launch_timing_validation(L):
     assert ffm.kernel_name(18, 4, 0) == "k_grid_phi_s<4>"
     assert ffm.kernel_name(18, 0, 0) == "k_grid_phi"
     assert ffm.kernel_name(16, 8, 0) == "k_grid_spread<8>"
+    assert ffm.FFM_LAPLACE_GRAD == 6 and ffm.FFM_HELMHOLTZ_GRAD == 7
     assert ffm.kernel_name(28, 1, 1) == "k_near_dl<true, true>"
     assert ffm.kernel_name(29) == "k_lag_anterp_dl"
     assert ffm.kernel_name(30, 101, 0) == "k_pw_forward_dl<1, 64, false>"
