@@ -634,7 +634,8 @@ struct orc_plan {
     int kernel;                /* ORC_LAPLACE or ORC_HELMHOLTZ */
     int dn;                    /* 1: the normal derivative at the targets (adjoint double layer) */
     int dl;                    /* 1: the normal derivative at the sources (double layer) */
-    int grad;                  /* 1: the gradient at the targets: the dn machinery once per axis, NXs = that axis */
+    int grad;                  /* 1: the gradient at the targets, one axis at a time (axis; NXs = that axis) */
+    int axis;
     double *NYs;               /* source normals in sorted order (dl plans) */
     double *NXs;               /* target normals in sorted order (dn plans) */
     double k, eps;
@@ -821,7 +822,7 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
 {
     orc_plan *p = calloc(1, sizeof(orc_plan));
     p->grad = kernel == ORC_LAPLACE_GRAD || kernel == ORC_HELMHOLTZ_GRAD;
-    p->dn = kernel == ORC_LAPLACE_DN || kernel == ORC_HELMHOLTZ_DN || p->grad;
+    p->dn = kernel == ORC_LAPLACE_DN || kernel == ORC_HELMHOLTZ_DN;
     p->dl = kernel == ORC_LAPLACE_DL || kernel == ORC_HELMHOLTZ_DL;
     kernel &= 1;
     p->kernel = kernel;
@@ -879,7 +880,7 @@ orc_plan *orc_plan_create(const double *X, int64_t nx, const double *Y, int64_t 
         tree_build(&p->T[e], PS[e], NS[e], corner[e], p->S);
         tree_level(&p->T[e], 0, d0);
     }
-    if (p->dn) {
+    if (p->dn || p->grad) {
         /* gradient plans: set per axis by orc_apply */
         p->NXs = calloc(3 * (size_t)nx, sizeof(double));
         if (!p->grad)
@@ -1200,7 +1201,7 @@ static void level_lagrange(const orc_plan *p, int l, const double complex *u, do
             orc_lagrange_basis(r1, ty, ey);
             orc_lagrange_basis(r1, tz, ez);
             double complex acc = 0.0;
-            if (p->dn) {
+            if (p->dn || p->grad) {
                 /* n . grad of the interpolant; d/dx of l(2 (x - c) / d_l) is (2 / d_l) l' */
                 const double *n = p->NXs + 3 * i;
                 orc_lagrange_basis_deriv(r1, tx, dx);
@@ -1344,6 +1345,10 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
             const double complex *us = ut + F->s[e] * nq;
             for (int64_t q = 0; q < nq; ++q) vt[q] += Dc[q] * us[q];
         }
+        /* gradient, component axis: d/dx_axis e^{ik s.(x - c)} = ik s_axis e^{ik s.(x - c)}, so the target
+         * transform (direct or grid) of ik s_axis v~ */
+        if (p->grad)
+            for (int64_t q = 0; q < nq; ++q) vt[q] *= I * k * s[3 * q + p->axis];
         const double *c = TX->ctr[l] + 3 * t;
         if (grid) {
             int64_t i0 = first_sample(TX->start[l][t], stride);
@@ -1415,7 +1420,7 @@ static void near_pairs_sum(const orc_plan *p, int l, const pairs_t *N, const dou
                            dz = TX->P[3 * i + 2] - TY->P[3 * j + 2];
                     double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 == 0.0) continue;   /* R11 */
-                    if (p->dn) {
+                    if (p->dn || p->grad) {
                         const double d[3] = {dx, dy, dz};
                         acc += green_dn(p->kernel, p->k, d, p->NXs + 3 * i) * u[j];
                     } else if (p->dl) {
@@ -1454,10 +1459,13 @@ void orc_apply(orc_plan *p, const double *wu, double *v, int64_t stride)
     for (int64_t j = 0; j < ny; ++j) u[j] = cload(wu, p->T[1].perm[j]);
     double complex *vs = malloc(sizeof(double complex) * (size_t)(nx > 0 ? nx : 1));
     for (int c = 0; c < ncomp; ++c) {
-        /* gradient: component c is the derivative along axis c, the normal derivative with n = e_c */
-        if (p->grad)
+        /* gradient: component c is the derivative along axis c (the normal derivative with n = e_c at Lagrange
+         * levels and in the near field) */
+        if (p->grad) {
+            p->axis = c;
             for (int64_t i = 0; i < nx; ++i)
                 for (int d = 0; d < 3; ++d) p->NXs[3 * i + d] = d == c ? 1.0 : 0.0;
+        }
         for (int64_t i = 0; i < nx; ++i) vs[i] = 0.0;
         apply_sorted(p, u, vs, stride);
         /* back to the user's target order */

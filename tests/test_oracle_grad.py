@@ -81,3 +81,26 @@ def test_ffm_gradient_within_eps(orc, kernel, k):
     comb = (prod[1e-3] * N).sum(axis=1)
     print("n . grad against the normal-derivative product: %.2e" % (np.linalg.norm(comb - dn) / np.linalg.norm(dn)))
     assert np.linalg.norm(comb - dn) <= 1e-12 * np.linalg.norm(dn)
+
+
+def test_ffm_gradient_grid_form(orc):
+    """The gradient through the grid form of the plane-wave transforms (level 2): component c is the grid form's
+    target transform of ik s_c v~, within eps of dense rows and of the direct form."""
+    rng = np.random.default_rng(24)
+    Y = W.sphere_points(4000, rng)
+    X = W.sphere_points(3000, rng) * 0.98
+    wu = (rng.standard_normal(4000) + 1j * rng.standard_normal(4000)) / 4000
+    rows = np.arange(0, 3000, 7)
+    d = oracle.dense_rows_grad(X, Y, wu, 1, 30.0, rows)
+    direct = oracle.Plan(X, Y, 7, 30.0, 1e-3, n_leaf=32)
+    assert direct.method(2) == 2
+    g = oracle.Plan(X, Y, 7, 30.0, 1e-3, n_leaf=32, grid={2: (32, 6, 2.3 * 6)})
+    vg, vd = g.apply(wu), direct.apply(wu)
+    eg, ed = rel_err(vg[rows], d), rel_err(vd[rows], d)
+    print("grid form %.2e, direct %.2e, grid against direct %.2e" % (eg, ed, rel_err(vg, vd)))
+    assert eg <= 1e-3 and ed <= 1e-3 and rel_err(vg, vd) <= 1e-3
+    assert rel_err(vg, vd) > 1e-12          # the grid form did run
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
