@@ -190,7 +190,7 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
     int rc = Guard::run([&] {
         std::unique_ptr<ffm_plan_s> p(new ffm_plan_s());
         Plan &P = p->P;
-        P.dn = dn || grad;
+        P.dn = dn;
         P.grad = grad;
         P.user_normals = dn ? o.target_normals : nullptr;
         P.dl = dl;

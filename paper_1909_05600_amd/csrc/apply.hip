@@ -441,6 +441,25 @@ k_pw_transfer_lds(const LDesc *__restrict__ descs, const IoEntry *__restrict__, 
     d.vt[(int64_t)t * npair + q] = acc;
 }
 
+// Gradient plans: the target transform of component c is that of ik s_c v~, so the plain transforms (direct,
+// ring or grid form) give the derivative along axis c.  For the pair (q, -q) (s(-q) = -s(q)):
+// ik s_c v~(q) = f (-Im, Re) and -ik s_c v~(-q) = f (Im, -Re), f = k s_c = 2 pi (k s / 2 pi)_c.  Components 1 and 2
+// go to the descriptor's vtx planes, component 0 replaces v~.  Item (desc, target box, tile of 256 pairs).
+__global__ void __launch_bounds__(kThreads)
+k_dir_scale(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int64_t p = (int64_t)wk.z * kThreads + threadIdx.x;
+    if (p >= d.npair) return;
+    const int64_t o = (int64_t)wk.y * d.npair + p;
+    const float4 w = d.vt[o];
+    const float4 s = d.dirs[p];
+    auto sc = [&](float f) { return make_float4(-f * w.y, f * w.x, f * w.w, -f * w.z); };
+    d.vtx[o] = sc(6.2831853f * s.y);
+    d.vtx[d.vtstride + o] = sc(6.2831853f * s.z);
+    d.vt[o] = sc(6.2831853f * s.x);
+}
+
 // Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q) and
 // B = v~(q) - v~(-q), the pair contributes cos(th) A + i sin(th) B.  Item (desc, target box, first point);
 // BS points per block (64 for levels of small boxes).
@@ -3082,6 +3101,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_BSUM: return k_sum_parts;
         case K_ANTERP: return k_lag_anterp;
         case K_ANTERP_DL: return k_lag_anterp_dl;
+        case K_DIRSCALE: return k_dir_scale;
         // a = waves per block (each takes its own 32-row tiles of T over the block's staged sources)
         case K_MFMA32: threads = 64 * std::max(1, S.a); return k_lag_mfma;
         case K_MFMA16: threads = 64 * std::max(1, S.a); return k_lag_mfma16;
@@ -3271,6 +3291,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_BSUM: return "k_sum_parts";
         case K_ANTERP: return "k_lag_anterp";
         case K_ANTERP_DL: return "k_lag_anterp_dl";
+        case K_DIRSCALE: return "k_dir_scale";
         case K_MFMA32: return "k_lag_mfma";
         case K_MFMA16: return "k_lag_mfma16";
         case K_ACA: return "k_lag_aca";

@@ -1349,7 +1349,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     Scratch SC(st);
     P.tx.reset(new Tree());
     build_tree(*P.tx, X, nx, corner[0], P.S, st, SC);
-    if (P.dn && !P.grad) {
+    if (P.dn) {
         // read before the plan's next host wait, so the caller may free the normals when ffm_plan returns
         P.tnrm.alloc(nx);
         FFM_LAUNCH(k_gather_normals, nblocks(nx), kThreads, 0, st, P.user_normals, nx, P.tx->perm.p, P.tnrm.p);
@@ -1489,7 +1489,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     }
     // one set: the leaf near field evaluates each unordered pair of distinct boxes once (G is symmetric; the
     // normal derivatives are not)
-    P.near_sym = P.same && !P.dn && !P.dl;
+    P.near_sym = P.same && !P.dn && !P.dl && !P.grad;
     fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near, P.near_sym);
     int32_t *used_h = SC.pin<int32_t>((size_t)kWin3 * (P.leaf + 1) + 1);
     for (int l = 1; l <= P.leaf; ++l)
@@ -1849,6 +1849,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.v_sorted.alloc(nx * P.ncomp());
     P.wsrc.alloc(ws_src);
     P.wtgt.alloc(ws_tgt);
+    if (P.grad) P.wtgtx.alloc(2 * ws_tgt);
     P.wz.alloc(ws_z);
     P.wG.alloc(ws_gG);
     P.wH.alloc(ws_gH);
@@ -2034,6 +2035,15 @@ static void pick_pair_tile(int64_t npair, int ppt_max, int &bs, int &ppt) {
 
 // The transfer stage of a Gegenbauer level: class tables in LDS where boxes have many direction pairs
 // (measured faster from n_pair ~ 4096 on), one target per block otherwise.
+// Gradient plans: v~ of the three components of a Gegenbauer level (k_dir_scale), over the level's target boxes.
+static Stage dir_scale_stage(int l, const Level &LV, hipStream_t st, Scratch &SC) {
+    std::vector<int4> it;
+    const int nt = (int)((LV.npair + kThreads - 1) / kThreads);
+    for (int32_t t : LV.h_tgt)
+        for (int q = 0; q < nt; ++q) it.push_back(make_int4(l, t, q, 0));
+    return make_stage(K_DIRSCALE, 0, 0, -1, l, 0, std::move(it), st, SC);
+}
+
 static Stage transfer_stage(const Plan &P, int l, Level &LV, const std::vector<int32_t> &tg, int slot,
                             hipStream_t st, Scratch &SC) {
     if (LV.npair >= 4096) {
@@ -2173,6 +2183,11 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
                 Stage S = transfer_stage(P, l, LV, tg, s2, st, SC);
                 S.role_add = 16 * (nbf - 1);
                 LV.stages.push_back(std::move(S));
+                if (P.grad) {
+                    Stage D = dir_scale_stage(l, LV, st, SC);
+                    D.role_add = 16 * (nbf - 1);
+                    LV.stages.push_back(std::move(D));
+                }
             }
             // mirror plane sums: 64 x 64 tiles, or 64 rows by the whole plane for grids of 80, 96 and 112 nodes,
             // whose 64 x 64 tiles would leave slivers (measured 18.3 -> 13.7 ms at 80 nodes; 128 nodes keep full
@@ -2255,6 +2270,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             }
             std::vector<int4> bw;
             LV.stages.push_back(transfer_stage(P, l, LV, tg, s2, st, SC));
+            if (P.grad) LV.stages.push_back(dir_scale_stage(l, LV, st, SC));
             // direction-pair target transform: 64-point blocks where target boxes are small
             const bool small = !ring_bwd && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
             if (small) LV.bwd_tile = 64;
@@ -2302,7 +2318,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             else
                 LV.stages.push_back(make_stage(LV.fp16 ? K_MFMA16 : K_MFMA32, LV.fp16 ? 1 : std::min(4, LV.rp / 32), 0,
                                                s2, l, (size_t)LV.rp * 32 * (LV.fp16 ? 2 : 4), std::move(mf), st, SC));
-            LV.stages.push_back(make_stage(P.dn ? K_INTERP_DN : K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r,
+            LV.stages.push_back(make_stage(P.dn || P.grad ? K_INTERP_DN : K_INTERP, 0, 0, s3, l, sizeof(float2) * LV.r,
                                            std::move(ip), st, SC));
         }
     }
@@ -2321,7 +2337,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         auto big = [&](int l) {
             return nhelm && P.k / (2.0 * M_PI) * 4.0 * std::sqrt(3.0) * std::ldexp(P.d0, -l) > 128.0 ? 1 : 0;
         };
-        const int near_kern = P.dn ? K_NEAR_DN : (P.dl ? K_NEAR_DL : K_NEAR);
+        const int near_kern = P.dn || P.grad ? K_NEAR_DN : (P.dl ? K_NEAR_DL : K_NEAR);
         // near pairs the per-pair rule stopped above the leaf: the same kernel over each level's early list
         for (int l = 1; l < P.leaf; ++l) {
             if (P.lev[l].h_early.empty()) continue;
@@ -2338,32 +2354,43 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         }
         P.post.push_back(make_stage(K_PERM_OUT, 0, 0, 62, 0, 0, std::move(po), st, SC));
     }
-    // gradient plans: the target-side stages of the normal derivative once more for components 1 and 2, over
-    // their own descriptors (same work, items pointing at descriptor k + c (leaf + 1)); the last copy closes
-    // the original's timing slot
+    // gradient plans: each level's target side (from its first target-transform stage on) once more for components
+    // 1 and 2, over their own descriptors (items pointing at descriptor k + c (leaf + 1)) and after component 0's
+    // (a batch orders them by role: they share the level's target workspace); the near field's stages likewise,
+    // each right after itself (they share nothing).  Component 2's copies close the original timing slots.
     if (P.grad) {
-        auto triple = [&](std::vector<Stage> &v) {
-            std::vector<Stage> out;
-            for (Stage &S : v) {
-                const bool tgt = S.kern == K_INTERP_DN || S.kern == K_BWD_PAIR_DN || S.kern == K_NEAR_DN;
-                if (!tgt) {
-                    out.push_back(std::move(S));
-                    continue;
-                }
-                const Stage orig = S;
-                S.slot = -1;
-                out.push_back(std::move(S));
-                for (int c = 1; c < 3; ++c) {
-                    Stage C = orig;
-                    for (int4 &x : C.items) x.x += c * (P.leaf + 1);
-                    C.slot = c == 2 ? orig.slot : -1;
-                    out.push_back(std::move(C));
-                }
-            }
-            v = std::move(out);
+        constexpr int kRoleComp = 4096;
+        auto copy = [&](Stage S, int c) {
+            for (int4 &x : S.items) x.x += c * (P.leaf + 1);
+            S.role_add += c * kRoleComp;
+            if (c < 2) S.slot = -1;
+            return S;
         };
-        for (int l = 1; l <= P.leaf; ++l) triple(P.lev[l].stages);
-        triple(P.post);
+        for (int l = 1; l <= P.leaf; ++l) {
+            std::vector<Stage> &v = P.lev[l].stages;
+            size_t k0 = 0;
+            while (k0 < v.size() && v[k0].kern != K_BWD_PAIR && v[k0].kern != K_BWD_RING && v[k0].kern != K_GPHIT &&
+                   v[k0].kern != K_INTERP_DN)
+                ++k0;
+            const std::vector<Stage> tail(v.begin() + (std::ptrdiff_t)k0, v.end());
+            v.resize(k0);
+            for (int c = 0; c < 3; ++c)
+                for (const Stage &S : tail) v.push_back(copy(S, c));
+        }
+        std::vector<Stage> out;
+        for (Stage &S : P.post) {
+            if (S.kern != K_NEAR_DN) {
+                out.push_back(std::move(S));
+                continue;
+            }
+            const Stage orig = S;
+            for (int c = 0; c < 3; ++c) {
+                Stage C = copy(orig, c);
+                C.role_add = orig.role_add;      // independent output planes: merging with the original is safe
+                out.push_back(std::move(C));
+            }
+        }
+        P.post = std::move(out);
     }
     // timing slot of every stage: a stage that closes no phase belongs to the next one that does
     auto fill = [](std::vector<Stage> &v) {
@@ -2437,6 +2464,8 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.D = LV.D.p;
     d.ut = w.ut;
     d.vt = w.vt;
+    d.vtx = w.vtx;
+    d.vtstride = (int64_t)P.ws_tgt;
     d.part = w.part;
     d.npair = LV.npair;
     d.part_stride = (int64_t)LY.nbox * LV.npair;
@@ -2495,6 +2524,7 @@ LDesc plan_desc(const Plan &P, int k, int inst, float2 *u, float2 *v, float *ama
     const int l = k % (P.leaf + 1), c = k / (P.leaf + 1);
     LDesc d = make_desc(P, l, inst, u, v + (int64_t)c * P.nx, amax, w);
     d.tnc = make_float4(c == 0 ? 1.f : 0.f, c == 1 ? 1.f : 0.f, c == 2 ? 1.f : 0.f, 0.f);
+    if (c > 0 && w.vtx) d.vt = w.vtx + (int64_t)(c - 1) * P.ws_tgt;   // v~ of this component (Gegenbauer levels)
     return d;
 }
 
@@ -2512,6 +2542,7 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     w.G = P.wG.p;
     w.H = P.wH.p;
     w.nsym = P.wnsym.p;
+    w.vtx = P.wtgtx.p;
     P.hdesc.clear();
     for (int k = 0; k < plan_ndesc(P); ++k) P.hdesc.push_back(plan_desc(P, k, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
@@ -2544,7 +2575,7 @@ size_t plan_device_bytes(const Plan &P) {
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
          P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes() + P.wnsym.bytes();
-    b += P.tnrm.bytes() + P.snrm.bytes();
+    b += P.tnrm.bytes() + P.snrm.bytes() + P.wtgtx.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
     b += P.items.bytes();
     return b;
