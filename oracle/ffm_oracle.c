@@ -1285,7 +1285,8 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     for (int64_t i = 0; i < F->n; ++i) need[F->s[i]] = 1;
 
     /* grid form of the transforms at this level (R16-R18), else the direct sums */
-    const int grid = p->opt.grid_p[l] > 0 && !p->dn && !p->dl;   /* normal-derivative plans use the direct sums */
+    /* grid form where asked; the double layer keeps the direct sums (its source transform is differentiated) */
+    const int grid = p->opt.grid_p[l] > 0 && !p->dl;
     gridlev_t gl;
     if (grid) {
         int gp = p->opt.grid_p[l], gw = p->opt.grid_w[l];
@@ -1357,8 +1358,20 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
             double complex *vb = calloc((size_t)(nt + 1), sizeof(double complex));
             for (int64_t i = 0; i < nt; ++i)
                 for (int d = 0; d < 3; ++d) xr[3 * i + d] = TX->P[3 * (i0 + i * stride) + d] - c[d];
-            grid_bwd(&gl, vt, xr, nt, vb);
-            for (int64_t i = 0; i < nt; ++i) v[i0 + i * stride] += vb[i];
+            if (p->dn) {
+                /* n . grad: the grid form's target transforms of ik s_c v~, c = 0, 1, 2, combined with n_c */
+                double complex *vc = malloc(sizeof(double complex) * (size_t)nq);
+                for (int ax = 0; ax < 3; ++ax) {
+                    for (int64_t q = 0; q < nq; ++q) vc[q] = I * k * s[3 * q + ax] * vt[q];
+                    for (int64_t i = 0; i < nt; ++i) vb[i] = 0.0;
+                    grid_bwd(&gl, vc, xr, nt, vb);
+                    for (int64_t i = 0; i < nt; ++i) v[i0 + i * stride] += p->NXs[3 * (i0 + i * stride) + ax] * vb[i];
+                }
+                free(vc);
+            } else {
+                grid_bwd(&gl, vt, xr, nt, vb);
+                for (int64_t i = 0; i < nt; ++i) v[i0 + i * stride] += vb[i];
+            }
             free(xr);
             free(vb);
             free(vt);

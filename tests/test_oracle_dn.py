@@ -5,7 +5,8 @@ The FFM differentiates only its target side: the near field uses the derivative 
 derivatives of the interpolation polynomials (chain factor 2 / d_l), Gegenbauer levels the factor ik (s . n) of
 each plane wave.  Pins: the polynomial derivatives reproduce those of polynomials of degree < r1; the dense
 rows equal central differences of the potential along n; the radial derivative of a uniform shell's potential
-(closed forms from the n = 0 term of the addition theorem) inside and outside; the FFM within eps of dense rows.
+(closed forms from the n = 0 term of the addition theorem) inside and outside; the FFM within eps of dense rows,
+also through the grid form (n . the target transforms of ik s_c v~).
 """
 import math
 
@@ -87,3 +88,23 @@ def test_ffm_normal_derivative_within_eps(orc, kernel, k):
         print("kernel %d k %g eps %g: methods %s, error %.2e" % (kernel, k, eps, meth, errs[-1]))
         assert errs[-1] <= eps
     assert errs[1] < errs[0]
+
+
+def test_ffm_normal_derivative_grid_form(orc):
+    """The normal derivative at the targets through the grid form (level 2): n . (the grid form's target
+    transforms of ik s_c v~), within eps of dense rows and of the direct form."""
+    rng = np.random.default_rng(26)
+    Y = W.sphere_points(4000, rng)
+    N = W.sphere_points(3000, rng)
+    X = N * 0.98
+    wu = (rng.standard_normal(4000) + 1j * rng.standard_normal(4000)) / 4000
+    rows = np.arange(0, 3000, 7)
+    d = oracle.dense_rows_dn(X, Y, wu, 1, 30.0, N, rows)
+    direct = oracle.Plan(X, Y, 3, 30.0, 1e-3, n_leaf=32, normals=N)
+    assert direct.method(2) == 2
+    g = oracle.Plan(X, Y, 3, 30.0, 1e-3, n_leaf=32, normals=N, grid={2: (32, 6, 2.3 * 6)})
+    vg, vd = g.apply(wu), direct.apply(wu)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print("grid form %.2e, direct %.2e, grid against direct %.2e" % (rel(vg[rows], d), rel(vd[rows], d), rel(vg, vd)))
+    assert rel(vg[rows], d) <= 1e-3 and rel(vd[rows], d) <= 1e-3 and rel(vg, vd) <= 1e-3
+    assert rel(vg, vd) > 1e-12          # the grid form did run
