@@ -61,8 +61,11 @@ k_perm_in(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const
         }
         d.u[i] = r;
     }
-    if (i < d.nx)
+    if (i < d.nx) {
         for (int c = 0; c < d.ncomp; ++c) d.v[(int64_t)c * d.nx + i] = make_float2(0.f, 0.f);
+        if (d.vtmp)
+            for (int c = 0; c < 3; ++c) d.vtmp[(int64_t)c * d.nx + i] = make_float2(0.f, 0.f);
+    }
 }
 
 // max over |Re u|, |Im u| (non-negative floats compare as their bit patterns); item (desc, first index),
@@ -458,6 +461,24 @@ k_dir_scale(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
     d.vtx[o] = sc(6.2831853f * s.y);
     d.vtx[d.vtstride + o] = sc(6.2831853f * s.z);
     d.vt[o] = sc(6.2831853f * s.x);
+}
+
+// Split normal derivative at the targets: v_i += n_i . (T_0, T_1, T_2)_i over the axis planes of a level's
+// target transforms, which are cleared for the next level.  Item (desc, target box, first point), 256 points.
+__global__ void __launch_bounds__(kThreads)
+k_dn_combine(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int i = wk.z + threadIdx.x;
+    if (i >= d.tstart[wk.y + 1]) return;
+    const float4 n = d.tn[i];
+    float2 *t0 = d.vtmp + i, *t1 = t0 + d.nx, *t2 = t1 + d.nx;
+    const float2 a = *t0, b = *t1, c = *t2;
+    float2 o = d.v[i];
+    o.x = fmaf(n.x, a.x, fmaf(n.y, b.x, fmaf(n.z, c.x, o.x)));
+    o.y = fmaf(n.x, a.y, fmaf(n.y, b.y, fmaf(n.z, c.y, o.y)));
+    d.v[i] = o;
+    *t0 = *t1 = *t2 = make_float2(0.f, 0.f);
 }
 
 // Backward transform v_i += sum_q e^{ik s_q.(x_i - c_t)} v~_t(q): per pair, with A = v~(q) + v~(-q) and
@@ -3102,6 +3123,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_ANTERP: return k_lag_anterp;
         case K_ANTERP_DL: return k_lag_anterp_dl;
         case K_DIRSCALE: return k_dir_scale;
+        case K_DNCOMBINE: return k_dn_combine;
         // a = waves per block (each takes its own 32-row tiles of T over the block's staged sources)
         case K_MFMA32: threads = 64 * std::max(1, S.a); return k_lag_mfma;
         case K_MFMA16: threads = 64 * std::max(1, S.a); return k_lag_mfma16;
@@ -3292,6 +3314,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_ANTERP: return "k_lag_anterp";
         case K_ANTERP_DL: return "k_lag_anterp_dl";
         case K_DIRSCALE: return "k_dir_scale";
+        case K_DNCOMBINE: return "k_dn_combine";
         case K_MFMA32: return "k_lag_mfma";
         case K_MFMA16: return "k_lag_mfma16";
         case K_ACA: return "k_lag_aca";

@@ -43,7 +43,8 @@ int stage_role(const Stage &S) {
         case K_SUM: case K_GZ: return 1;
         case K_GPHI: return 2;
         case K_TRANSFER: case K_MFMA32: case K_MFMA16: case K_ACA: case K_DIRSCALE: return 3;
-        case K_BWD_PAIR: case K_BWD_RING: case K_INTERP: case K_GPHIT: case K_BWD_PAIR_DN: case K_INTERP_DN: return 4;
+        case K_BWD_PAIR: case K_BWD_RING: case K_INTERP: case K_GPHIT: case K_BWD_PAIR_DN: case K_INTERP_DN:
+        case K_DNCOMBINE: return 4;
         case K_BSUM: case K_GZT: return 5;
         case K_GINTERP: return 6;
         // after the levels: the near fields of the early lists and the leaf in level order (they add into the same

@@ -238,6 +238,7 @@ struct LDesc {
                                            // of sorted target i at v[c nx + i] of the level-0 descriptor's v)
     float4 *vtx;                           // gradient plans: v~ of components 1 and 2, vtstride apart
     int64_t vtstride;
+    float2 *vtmp;                          // split normal derivative: the three axis planes (nx apart), or null
     const float *acaA, *acaB;              // ACA factors: A [class][plane][kpm][rp], B^T [class][plane][rp][kpm]
     const int32_t *acaKp;                  // [class] rank padded to 32
     int kpm;                               // largest padded rank
@@ -266,7 +267,7 @@ enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
     K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
     K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA, K_NEAR_DN, K_BWD_PAIR_DN, K_INTERP_DN,
-    K_NEAR_SYM, K_NEAR_GATHER, K_NEAR_DL, K_ANTERP_DL, K_FWD_PAIR_DL, K_DIRSCALE
+    K_NEAR_SYM, K_NEAR_GATHER, K_NEAR_DL, K_ANTERP_DL, K_FWD_PAIR_DL, K_DIRSCALE, K_DNCOMBINE
 };
 
 struct Stage {
@@ -398,7 +399,9 @@ struct Plan {
     const double *user_normals = nullptr;   // the caller's target normals, read while the plan is built
     DevBuf<float4> tnrm;                 // target normals in sorted order (FP32)
     bool grad = false;                   // gradient at the targets: target side once per axis
-    DevBuf<float4> wtgtx;                // gradient plans: v~ of target components 1 and 2
+    DevBuf<float4> wtgtx;                // gradient plans, split normal derivative: v~ of components 1 and 2
+    bool dnsplit = false;                // normal derivative with levels whose target side runs once per axis
+    DevBuf<float2> wtmp;                 // their three axis planes of the sorted targets
     int ncomp() const { return grad ? 3 : 1; }
     bool dl = false;                     // normal derivative at the sources (double layer)
     const double *user_snormals = nullptr;  // the caller's source normals, read while the plan is built
@@ -475,6 +478,7 @@ struct LevelWork {                     // apply workspace a descriptor points in
     float2 *G = nullptr, *H = nullptr;
     float2 *nsym = nullptr;
     float4 *vtx = nullptr;                // gradient plans: v~ of target components 1 and 2 (2 x ws_tgt)
+    float2 *vtmp = nullptr;               // split normal derivative: three axis planes of the sorted targets
 };
 // Apply workspace laid out in one block (requests of the server, the static-scratch apply): its size in bytes
 // (every part aligned to 256 B; also what ffm_workspace_bytes and ffm_stats_t.workspace_bytes report), and the

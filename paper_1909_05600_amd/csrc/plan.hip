@@ -1603,7 +1603,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
                 const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
                 const bool force_direct = (P.opt.flags & FFM_FLAG_DIRECT_TRANSFORMS) != 0;
-                LV.grid = have && !force_direct && !P.dn && !P.dl && L >= 8 && gbytes <= ((size_t)24 << 30) &&
+                LV.grid = have && !force_direct && !P.dl && L >= 8 && gbytes <= ((size_t)24 << 30) &&
                           (force_grid || gridc < direct);
                 if (LV.grid) {
                     P.any_grid = true;
@@ -1849,7 +1849,14 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     P.v_sorted.alloc(nx * P.ncomp());
     P.wsrc.alloc(ws_src);
     P.wtgt.alloc(ws_tgt);
-    if (P.grad) P.wtgtx.alloc(2 * ws_tgt);
+    // the normal derivative at the targets splits, like the gradient, the levels whose target transform takes the
+    // grid or the ring-pair form (k s . n = sum_c k s_c n_c: three plain target transforms, combined with n)
+    P.dnsplit = false;
+    if (P.dn)
+        for (int l = 1; l <= P.leaf; ++l)
+            if (P.lev[l].method == kGegenbauer && (P.lev[l].grid || P.lev[l].L >= kRingMinL)) P.dnsplit = true;
+    if (P.grad || P.dnsplit) P.wtgtx.alloc(2 * ws_tgt);
+    if (P.dnsplit) P.wtmp.alloc(3 * nx);
     P.wz.alloc(ws_z);
     P.wG.alloc(ws_gG);
     P.wH.alloc(ws_gH);
@@ -2183,7 +2190,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
                 Stage S = transfer_stage(P, l, LV, tg, s2, st, SC);
                 S.role_add = 16 * (nbf - 1);
                 LV.stages.push_back(std::move(S));
-                if (P.grad) {
+                if (P.grad || P.dn) {
                     Stage D = dir_scale_stage(l, LV, st, SC);
                     D.role_add = 16 * (nbf - 1);
                     LV.stages.push_back(std::move(D));
@@ -2229,7 +2236,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             if (LV.qG && (L + LV.qG - 1) / LV.qG > kThreads) LV.qG = 4;   // one ring must fit one block
             // the normal derivative at the targets multiplies every direction by its own ik (s . n): the target
             // transform runs in the direction-pair form
-            const bool ring_bwd = LV.qG && !P.dn;
+            const bool ring_bwd = LV.qG != 0;
             // two target points per thread only where the target boxes hold more than a block's worth on average
             const int bpt = LV.pts_tgt > (double)kThreads * (double)std::max<size_t>(1, LV.h_tgt.size()) ? tu.bwd_pt : 1;
             LV.bwd_tile = ring_bwd ? kThreads * bpt : kThreads;
@@ -2270,7 +2277,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             }
             std::vector<int4> bw;
             LV.stages.push_back(transfer_stage(P, l, LV, tg, s2, st, SC));
-            if (P.grad) LV.stages.push_back(dir_scale_stage(l, LV, st, SC));
+            if (P.grad || (P.dn && ring_bwd)) LV.stages.push_back(dir_scale_stage(l, LV, st, SC));
             // direction-pair target transform: 64-point blocks where target boxes are small
             const bool small = !ring_bwd && LV.pts_tgt <= 96.0 * (double)std::max<size_t>(1, LV.h_tgt.size());
             if (small) LV.bwd_tile = 64;
@@ -2358,24 +2365,27 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     // 1 and 2, over their own descriptors (items pointing at descriptor k + c (leaf + 1)) and after component 0's
     // (a batch orders them by role: they share the level's target workspace); the near field's stages likewise,
     // each right after itself (they share nothing).  Component 2's copies close the original timing slots.
+    // Split normal derivative: at the levels with a k_dir_scale stage, the target side three times over the axis
+    // descriptors (sets 1 to 3, into the axis planes), then k_dn_combine, which closes the original slot.
+    constexpr int kRoleComp = 4096;
+    auto copy = [&](Stage S, int set, bool keep_slot) {
+        for (int4 &x : S.items) x.x += set * (P.leaf + 1);
+        S.role_add += set * kRoleComp;
+        if (!keep_slot) S.slot = -1;
+        return S;
+    };
+    auto tgt_kind = [](int k) {
+        return k == K_BWD_PAIR || k == K_BWD_RING || k == K_GPHIT || k == K_INTERP_DN;
+    };
     if (P.grad) {
-        constexpr int kRoleComp = 4096;
-        auto copy = [&](Stage S, int c) {
-            for (int4 &x : S.items) x.x += c * (P.leaf + 1);
-            S.role_add += c * kRoleComp;
-            if (c < 2) S.slot = -1;
-            return S;
-        };
         for (int l = 1; l <= P.leaf; ++l) {
             std::vector<Stage> &v = P.lev[l].stages;
             size_t k0 = 0;
-            while (k0 < v.size() && v[k0].kern != K_BWD_PAIR && v[k0].kern != K_BWD_RING && v[k0].kern != K_GPHIT &&
-                   v[k0].kern != K_INTERP_DN)
-                ++k0;
+            while (k0 < v.size() && !tgt_kind(v[k0].kern)) ++k0;
             const std::vector<Stage> tail(v.begin() + (std::ptrdiff_t)k0, v.end());
             v.resize(k0);
             for (int c = 0; c < 3; ++c)
-                for (const Stage &S : tail) v.push_back(copy(S, c));
+                for (const Stage &S : tail) v.push_back(copy(S, c, c == 2));
         }
         std::vector<Stage> out;
         for (Stage &S : P.post) {
@@ -2385,12 +2395,38 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             }
             const Stage orig = S;
             for (int c = 0; c < 3; ++c) {
-                Stage C = copy(orig, c);
+                Stage C = copy(orig, c, c == 2);
                 C.role_add = orig.role_add;      // independent output planes: merging with the original is safe
                 out.push_back(std::move(C));
             }
         }
         P.post = std::move(out);
+    }
+    if (P.dnsplit) {
+        for (int l = 1; l <= P.leaf; ++l) {
+            std::vector<Stage> &v = P.lev[l].stages;
+            bool split = false;
+            for (const Stage &S : v) split = split || S.kern == K_DIRSCALE;
+            if (!split) continue;
+            size_t k0 = 0;
+            while (k0 < v.size() && !tgt_kind(v[k0].kern)) ++k0;
+            const std::vector<Stage> tail(v.begin() + (std::ptrdiff_t)k0, v.end());
+            int slot = -1, role = 0;
+            for (const Stage &S : tail) {
+                if (S.slot >= 0) slot = S.slot;
+                role = std::max(role, S.role_add);
+            }
+            v.resize(k0);
+            for (int c = 0; c < 3; ++c)
+                for (const Stage &S : tail) v.push_back(copy(S, 1 + c, false));
+            std::vector<int4> it;
+            const std::vector<int32_t> &sx = P.lev[l].h_sx;
+            for (int32_t t : P.lev[l].h_tgt)
+                for (int32_t i = sx[t]; i < sx[t + 1]; i += kThreads) it.push_back(make_int4(l, t, i, 0));
+            Stage C = make_stage(K_DNCOMBINE, 0, 0, slot, l, 0, std::move(it), st, SC);
+            C.role_add = role + 4 * kRoleComp;
+            v.push_back(std::move(C));
+        }
     }
     // timing slot of every stage: a stage that closes no phase belongs to the next one that does
     auto fill = [](std::vector<Stage> &v) {
@@ -2466,6 +2502,7 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.vt = w.vt;
     d.vtx = w.vtx;
     d.vtstride = (int64_t)P.ws_tgt;
+    d.vtmp = w.vtmp;
     d.part = w.part;
     d.npair = LV.npair;
     d.part_stride = (int64_t)LY.nbox * LV.npair;
@@ -2518,13 +2555,17 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     return d;
 }
 
-int plan_ndesc(const Plan &P) { return (P.leaf + 1) * P.ncomp(); }
+int plan_ndesc(const Plan &P) { return (P.leaf + 1) * (P.grad ? 3 : (P.dnsplit ? 4 : 1)); }
 
 LDesc plan_desc(const Plan &P, int k, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w) {
-    const int l = k % (P.leaf + 1), c = k / (P.leaf + 1);
-    LDesc d = make_desc(P, l, inst, u, v + (int64_t)c * P.nx, amax, w);
+    const int l = k % (P.leaf + 1), set = k / (P.leaf + 1);
+    if (!P.grad && set == 0) return make_desc(P, l, inst, u, v, amax, w);
+    // gradient: set c is axis c into output plane c; split normal derivative: set 1 + c is axis c into the
+    // combine's plane c
+    const int c = P.grad ? set : set - 1;
+    LDesc d = make_desc(P, l, inst, u, P.grad ? v + (int64_t)c * P.nx : w.vtmp + (int64_t)c * P.nx, amax, w);
     d.tnc = make_float4(c == 0 ? 1.f : 0.f, c == 1 ? 1.f : 0.f, c == 2 ? 1.f : 0.f, 0.f);
-    if (c > 0 && w.vtx) d.vt = w.vtx + (int64_t)(c - 1) * P.ws_tgt;   // v~ of this component (Gegenbauer levels)
+    if (c > 0 && w.vtx) d.vt = w.vtx + (int64_t)(c - 1) * P.ws_tgt;   // v~ of this axis (Gegenbauer levels)
     return d;
 }
 
@@ -2543,6 +2584,7 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     w.H = P.wH.p;
     w.nsym = P.wnsym.p;
     w.vtx = P.wtgtx.p;
+    w.vtmp = P.wtmp.p;
     P.hdesc.clear();
     for (int k = 0; k < plan_ndesc(P); ++k) P.hdesc.push_back(plan_desc(P, k, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
@@ -2575,7 +2617,7 @@ size_t plan_device_bytes(const Plan &P) {
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
          P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes() + P.wnsym.bytes();
-    b += P.tnrm.bytes() + P.snrm.bytes() + P.wtgtx.bytes();
+    b += P.tnrm.bytes() + P.snrm.bytes() + P.wtgtx.bytes() + P.wtmp.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
     b += P.items.bytes();
     return b;

@@ -41,7 +41,7 @@ size_t apply_work_bytes(const Plan &P) {
            align256(sizeof(float4) * P.ws_tgt) + align256(sizeof(float2) * P.ws_z) +
            align256(sizeof(float4) * P.wpart.n) + align256(sizeof(float2) * P.wbpart.n) +
            align256(sizeof(float2) * P.wG.n) + align256(sizeof(float2) * P.wH.n) + align256(sizeof(float2) * P.wnsym.n) +
-           align256(sizeof(float4) * P.wtgtx.n) +
+           align256(sizeof(float4) * P.wtgtx.n) + align256(sizeof(float2) * P.wtmp.n) +
            (P.any_fp16 || P.any_grid ? 256 : 0);
 }
 
@@ -64,6 +64,7 @@ WorkPtrs carve_work(const Plan &P, char *p) {
     w.lw.H = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wH.n));
     w.lw.nsym = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wnsym.n));
     w.lw.vtx = reinterpret_cast<float4 *>(take(sizeof(float4) * P.wtgtx.n));
+    w.lw.vtmp = P.wtmp.n ? reinterpret_cast<float2 *>(take(sizeof(float2) * P.wtmp.n)) : nullptr;
     w.amax = P.any_fp16 || P.any_grid ? reinterpret_cast<float *>(take(sizeof(float))) : nullptr;
     return w;
 }

@@ -3,9 +3,10 @@ double-layer operator (Sec. 4.2.1, eq. doubleLayer), on the GPU through the C AB
 FFM_HELMHOLTZ_DN with target normals).
 
 Only the target side differs from the potential: the near-field kernel, the derivatives of the Lagrange
-polynomials at the targets, and the factor ik (s . n) of every plane wave (direct transforms).  Element-wise
-against the oracle FFM of the same kernel with identical parameters (FP32_RTOL), within eps of FP64 dense rows,
-bitwise repeatable, inside a batch, and the missing-normals error.
+polynomials at the targets, and the factor ik (s . n) of every plane wave: in direction pairs, or, where the
+target transform takes the ring-pair or the grid form, as n . (the plain target transforms of ik s_c v~, c = 0, 1,
+2).  Element-wise against the oracle FFM of the same kernel with identical parameters, grid-form levels included
+(FP32_RTOL), within eps of FP64 dense rows, bitwise repeatable, inside a batch, and the missing-normals error.
 """
 import numpy as np
 import pytest
@@ -25,15 +26,17 @@ def _plan(X, Y, kernel, k, eps, N, **kw):
     return ffm.Plan(Xd, Yd, kernel, k, eps, normals=Nd, **kw)
 
 
-@pytest.mark.parametrize("kernel,k,eps", [(2, 0.0, 1e-3), (2, 0.0, 1e-4), (3, 9.0, 1e-3), (3, 45.0, 1e-3),
-                                          (3, 20.0, 1e-4)])
-def test_dn_matches_oracle_and_dense(orc, kernel, k, eps):
+@pytest.mark.parametrize("kernel,k,eps,tf", [(2, 0.0, 1e-3, "auto"), (2, 0.0, 1e-4, "auto"), (3, 9.0, 1e-3, "auto"),
+                                             (3, 45.0, 1e-3, "auto"), (3, 20.0, 1e-4, "auto"), (3, 45.0, 1e-3, "grid"),
+                                             (3, 60.0, 1e-4, "grid")])
+def test_dn_matches_oracle_and_dense(orc, kernel, k, eps, tf):
     rng = np.random.default_rng(int(k) + 7)
     Y = W.sphere_points(20000, rng)
     N = W.sphere_points(15000, rng)
     X = N * 0.985                                     # targets just inside the sources' sphere, radial normals
     wu = ((rng.standard_normal(20000) + 1j * rng.standard_normal(20000)) / 20000).astype(np.complex64)
-    gp = _plan(X, Y, kernel, k, eps, N)
+    print("dn kernel %d k=%g eps=%g transforms %s" % (kernel, k, eps, tf), flush=True)
+    gp = _plan(X, Y, kernel, k, eps, N, transforms=tf)
     st = gp.stats()
     op = oracle_like(orc, gp, X, Y, kernel, k, eps, normals=N)
     compare_trees(gp, op)
@@ -44,7 +47,8 @@ def test_dn_matches_oracle_and_dense(orc, kernel, k, eps):
     print("dn kernel %d k=%g eps=%g: methods %s forms %s aca %s: vs oracle %.3e, vs dense %.3e (oracle %.3e)"
           % (kernel, k, eps, st["method"][:st["leaf"] + 1], st["tform"][:st["leaf"] + 1], st["aca"][:st["leaf"] + 1],
              rel(v, vo), rel(v[rows], d), rel(vo[rows], d)))
-    assert 3 not in st["tform"]                           # direct transforms (the target side in direction pairs)
+    if tf == "grid":
+        assert 3 in st["tform"], st["tform"]
     assert rel(v, vo) < FP32_RTOL
     assert rel(v[rows], d) <= eps
     assert np.array_equal(v, gpu_apply(gp, wu))
