@@ -1285,8 +1285,8 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
     for (int64_t i = 0; i < F->n; ++i) need[F->s[i]] = 1;
 
     /* grid form of the transforms at this level (R16-R18), else the direct sums */
-    /* grid form where asked; the double layer keeps the direct sums (its source transform is differentiated) */
-    const int grid = p->opt.grid_p[l] > 0 && !p->dl;
+    /* grid form of the transforms where asked */
+    const int grid = p->opt.grid_p[l] > 0;
     gridlev_t gl;
     if (grid) {
         int gp = p->opt.grid_p[l], gw = p->opt.grid_w[l];
@@ -1305,11 +1305,22 @@ static void level_gegenbauer(const orc_plan *p, int l, const double complex *u, 
             int64_t nb = TY->start[l][b + 1] > j0 ? (TY->start[l][b + 1] - j0 + stride - 1) / stride : 0;
             double *yr = malloc(sizeof(double) * 3 * (size_t)(nb + 1));
             double complex *ub = malloc(sizeof(double complex) * (size_t)(nb + 1));
-            for (int64_t j = 0; j < nb; ++j) {
+            for (int64_t j = 0; j < nb; ++j)
                 for (int d = 0; d < 3; ++d) yr[3 * j + d] = TY->P[3 * (j0 + j * stride) + d] - c[d];
-                ub[j] = u[j0 + j * stride];
+            if (p->dl) {
+                /* n . grad_y: -ik sum_c s_c (the grid form's source transform of the density u n_c) */
+                double complex *uc = calloc((size_t)nq, sizeof(double complex));
+                for (int ax = 0; ax < 3; ++ax) {
+                    for (int64_t j = 0; j < nb; ++j) ub[j] = u[j0 + j * stride] * p->NYs[3 * (j0 + j * stride) + ax];
+                    for (int64_t q = 0; q < nq; ++q) uc[q] = 0.0;
+                    grid_fwd(&gl, yr, ub, nb, uc);
+                    for (int64_t q = 0; q < nq; ++q) ut[b * nq + q] += -I * k * s[3 * q + ax] * uc[q];
+                }
+                free(uc);
+            } else {
+                for (int64_t j = 0; j < nb; ++j) ub[j] = u[j0 + j * stride];
+                grid_fwd(&gl, yr, ub, nb, ut + b * nq);
             }
-            grid_fwd(&gl, yr, ub, nb, ut + b * nq);
             free(yr);
             free(ub);
             continue;

@@ -7,7 +7,8 @@ each plane wave.  Pins: the dense rows equal central differences of the potentia
 along their normals; Gauss's law for the Laplace double layer of a closed surface (-1 inside, 0 outside, with
 G = 1 / (4 pi r) and area weights); the Helmholtz double layer of a uniform sphere from the n = 0 term of the
 addition theorem; the transpose relation with the target-side derivative, densely and, to rounding, through the
-two FFMs; the FFM within eps of dense rows.
+two FFMs; the FFM within eps of dense rows, also through the grid form (-ik sum_c s_c times the source transforms
+of u n_c).
 """
 import math
 
@@ -126,3 +127,22 @@ def test_ffm_double_layer_within_eps(orc, kernel, k):
     scale = np.linalg.norm(u) * np.linalg.norm(prod[1e-3])
     print("transpose relation: %.2e of |u| |DL w|" % (abs(a - b) / scale))
     assert abs(a - b) < 1e-12 * scale
+
+
+def test_ffm_double_layer_grid_form(orc):
+    """The double layer through the grid form (level 2): -ik sum_c s_c (the grid form's source transforms of the
+    densities u n_c), within eps of dense rows and of the direct form."""
+    rng = np.random.default_rng(27)
+    Y = W.sphere_points(4000, rng)
+    X = W.sphere_points(3000, rng) * 0.98
+    wu = (rng.standard_normal(4000) + 1j * rng.standard_normal(4000)) / 4000
+    rows = np.arange(0, 3000, 7)
+    d = oracle.dense_rows_dl(X, Y, wu, 1, 30.0, Y, rows)
+    direct = oracle.Plan(X, Y, 5, 30.0, 1e-3, n_leaf=32, source_normals=Y)
+    assert direct.method(2) == 2
+    g = oracle.Plan(X, Y, 5, 30.0, 1e-3, n_leaf=32, source_normals=Y, grid={2: (32, 6, 2.3 * 6)})
+    vg, vd = g.apply(wu), direct.apply(wu)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print("grid form %.2e, direct %.2e, grid against direct %.2e" % (rel(vg[rows], d), rel(vd[rows], d), rel(vg, vd)))
+    assert rel(vg[rows], d) <= 1e-3 and rel(vd[rows], d) <= 1e-3 and rel(vg, vd) <= 1e-3
+    assert rel(vg, vd) > 1e-12          # the grid form did run
