@@ -60,6 +60,13 @@ k_perm_in(const LDesc *__restrict__ descs, const IoEntry *__restrict__ io, const
             }
         }
         d.u[i] = r;
+        if (d.ucomp) {
+            // split double layer: the densities u n_c
+            const float4 n = d.sn[i];
+            d.ucomp[i] = make_float2(r.x * n.x, r.y * n.x);
+            d.ucomp[d.ny + i] = make_float2(r.x * n.y, r.y * n.y);
+            d.ucomp[2 * d.ny + i] = make_float2(r.x * n.z, r.y * n.z);
+        }
     }
     if (i < d.nx) {
         for (int c = 0; c < d.ncomp; ++c) d.v[(int64_t)c * d.nx + i] = make_float2(0.f, 0.f);
@@ -461,6 +468,24 @@ k_dir_scale(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const 
     d.vtx[o] = sc(6.2831853f * s.y);
     d.vtx[d.vtstride + o] = sc(6.2831853f * s.z);
     d.vt[o] = sc(6.2831853f * s.x);
+}
+
+// Split double layer: u~(q) = -ik sum_c s_c u~_c(q) from the source transforms u~_c of the densities u n_c (in
+// place of u~_0); for the pair (q, -q), with f_c = k s_c(q) = 2 pi (k s / 2 pi)_c:
+// u~(q) = sum_c f_c (Im, -Re) u~_c(q) and u~(-q) = sum_c f_c (-Im, Re) u~_c(-q).  Item (desc, source box, tile of
+// 256 pairs).
+__global__ void __launch_bounds__(kThreads)
+k_dl_combine(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int64_t p = (int64_t)wk.z * kThreads + threadIdx.x;
+    if (p >= d.npair) return;
+    const int64_t o = (int64_t)wk.y * d.npair + p;
+    const float4 a = d.ut[o], b = d.utx[o], c = d.utx[d.utstride + o];
+    const float4 s = d.dirs[p];
+    const float fx = 6.2831853f * s.x, fy = 6.2831853f * s.y, fz = 6.2831853f * s.z;
+    d.ut[o] = make_float4(fmaf(fx, a.y, fmaf(fy, b.y, fz * c.y)), -fmaf(fx, a.x, fmaf(fy, b.x, fz * c.x)),
+                          -fmaf(fx, a.w, fmaf(fy, b.w, fz * c.w)), fmaf(fx, a.z, fmaf(fy, b.z, fz * c.z)));
 }
 
 // Split normal derivative at the targets: v_i += n_i . (T_0, T_1, T_2)_i over the axis planes of a level's
@@ -3124,6 +3149,7 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_ANTERP_DL: return k_lag_anterp_dl;
         case K_DIRSCALE: return k_dir_scale;
         case K_DNCOMBINE: return k_dn_combine;
+        case K_DLCOMBINE: return k_dl_combine;
         // a = waves per block (each takes its own 32-row tiles of T over the block's staged sources)
         case K_MFMA32: threads = 64 * std::max(1, S.a); return k_lag_mfma;
         case K_MFMA16: threads = 64 * std::max(1, S.a); return k_lag_mfma16;
@@ -3315,6 +3341,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_ANTERP_DL: return "k_lag_anterp_dl";
         case K_DIRSCALE: return "k_dir_scale";
         case K_DNCOMBINE: return "k_dn_combine";
+        case K_DLCOMBINE: return "k_dl_combine";
         case K_MFMA32: return "k_lag_mfma";
         case K_MFMA16: return "k_lag_mfma16";
         case K_ACA: return "k_lag_aca";

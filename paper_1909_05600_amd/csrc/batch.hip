@@ -40,7 +40,7 @@ int stage_role(const Stage &S) {
         case K_PERM_IN: return 0;
         case K_AMAX: return S.a ? 1 : 2;
         case K_FWD_PAIR: case K_FWD_RING: case K_ANTERP: case K_GSPREAD: case K_FWD_PAIR_DL: case K_ANTERP_DL: return 0;
-        case K_SUM: case K_GZ: return 1;
+        case K_SUM: case K_GZ: case K_DLCOMBINE: return 1;
         case K_GPHI: return 2;
         case K_TRANSFER: case K_MFMA32: case K_MFMA16: case K_ACA: case K_DIRSCALE: return 3;
         case K_BWD_PAIR: case K_BWD_RING: case K_INTERP: case K_GPHIT: case K_BWD_PAIR_DN: case K_INTERP_DN:

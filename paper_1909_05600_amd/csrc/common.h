@@ -239,6 +239,9 @@ struct LDesc {
     float4 *vtx;                           // gradient plans: v~ of components 1 and 2, vtstride apart
     int64_t vtstride;
     float2 *vtmp;                          // split normal derivative: the three axis planes (nx apart), or null
+    float2 *ucomp;                         // split double layer: the densities u n_c (ny apart), or null
+    float4 *utx;                           // split double layer: u~ of the densities u n_1, u n_2, utstride apart
+    int64_t utstride;
     const float *acaA, *acaB;              // ACA factors: A [class][plane][kpm][rp], B^T [class][plane][rp][kpm]
     const int32_t *acaKp;                  // [class] rank padded to 32
     int kpm;                               // largest padded rank
@@ -267,7 +270,7 @@ enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
     K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
     K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA, K_NEAR_DN, K_BWD_PAIR_DN, K_INTERP_DN,
-    K_NEAR_SYM, K_NEAR_GATHER, K_NEAR_DL, K_ANTERP_DL, K_FWD_PAIR_DL, K_DIRSCALE, K_DNCOMBINE
+    K_NEAR_SYM, K_NEAR_GATHER, K_NEAR_DL, K_ANTERP_DL, K_FWD_PAIR_DL, K_DIRSCALE, K_DNCOMBINE, K_DLCOMBINE
 };
 
 struct Stage {
@@ -402,6 +405,9 @@ struct Plan {
     DevBuf<float4> wtgtx;                // gradient plans, split normal derivative: v~ of components 1 and 2
     bool dnsplit = false;                // normal derivative with levels whose target side runs once per axis
     DevBuf<float2> wtmp;                 // their three axis planes of the sorted targets
+    bool dlsplit = false;                // double layer with levels whose source side runs once per axis
+    DevBuf<float2> wucomp;               // the densities u n_c of the sorted sources
+    DevBuf<float4> wsrcx;                // u~ of the densities of axes 1 and 2
     int ncomp() const { return grad ? 3 : 1; }
     bool dl = false;                     // normal derivative at the sources (double layer)
     const double *user_snormals = nullptr;  // the caller's source normals, read while the plan is built
@@ -479,6 +485,8 @@ struct LevelWork {                     // apply workspace a descriptor points in
     float2 *nsym = nullptr;
     float4 *vtx = nullptr;                // gradient plans: v~ of target components 1 and 2 (2 x ws_tgt)
     float2 *vtmp = nullptr;               // split normal derivative: three axis planes of the sorted targets
+    float2 *ucomp = nullptr;              // split double layer: densities u n_c of the sorted sources
+    float4 *utx = nullptr;                // split double layer: u~ of the densities of axes 1 and 2 (2 x ws_src)
 };
 // Apply workspace laid out in one block (requests of the server, the static-scratch apply): its size in bytes
 // (every part aligned to 256 B; also what ffm_workspace_bytes and ffm_stats_t.workspace_bytes report), and the

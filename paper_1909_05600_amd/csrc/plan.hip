@@ -1603,7 +1603,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
                 const size_t gbytes = gnb * ((size_t)p * p * p + (size_t)(L + 1) * p * p) * sizeof(float2);
                 const bool force_grid = (P.opt.flags & FFM_FLAG_GRID_TRANSFORMS) != 0;
                 const bool force_direct = (P.opt.flags & FFM_FLAG_DIRECT_TRANSFORMS) != 0;
-                LV.grid = have && !force_direct && !P.dl && L >= 8 && gbytes <= ((size_t)24 << 30) &&
+                LV.grid = have && !force_direct && L >= 8 && gbytes <= ((size_t)24 << 30) &&
                           (force_grid || gridc < direct);
                 if (LV.grid) {
                     P.any_grid = true;
@@ -1857,6 +1857,16 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
             if (P.lev[l].method == kGegenbauer && (P.lev[l].grid || P.lev[l].L >= kRingMinL)) P.dnsplit = true;
     if (P.grad || P.dnsplit) P.wtgtx.alloc(2 * ws_tgt);
     if (P.dnsplit) P.wtmp.alloc(3 * nx);
+    // the double layer splits the levels whose source transform takes the grid or the ring-pair form: three plain
+    // source transforms of the densities u n_c, combined with -ik s_c
+    P.dlsplit = false;
+    if (P.dl)
+        for (int l = 1; l <= P.leaf; ++l)
+            if (P.lev[l].method == kGegenbauer && (P.lev[l].grid || P.lev[l].L >= kRingMinL)) P.dlsplit = true;
+    if (P.dlsplit) {
+        P.wucomp.alloc(3 * ny);
+        P.wsrcx.alloc(2 * ws_src);
+    }
     P.wz.alloc(ws_z);
     P.wG.alloc(ws_gG);
     P.wH.alloc(ws_gH);
@@ -2241,9 +2251,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             const int bpt = LV.pts_tgt > (double)kThreads * (double)std::max<size_t>(1, LV.h_tgt.size()) ? tu.bwd_pt : 1;
             LV.bwd_tile = ring_bwd ? kThreads * bpt : kThreads;
             std::vector<int4> fw;
-            // the normal derivative at the sources multiplies every direction by its own -ik (s . n): the source
-            // transform runs in the direction-pair form (the ring form still serves the target transform)
-            if (LV.qG && !P.dl) {
+            // (the double layer splits its ring-pair source transform by axis, like the grid form's)
+            if (LV.qG) {
                 // ring-pair form; split each box's points into segments when boxes are too few to fill the chip
                 LV.Tr = (L + LV.qG - 1) / LV.qG;
                 LV.R = std::max(1, std::min({16, kThreads / LV.Tr, LV.nrp}));
@@ -2402,6 +2411,38 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         }
         P.post = std::move(out);
     }
+    if (P.dlsplit) {
+        // split double layer: at the levels whose source side is the grid or the ring-pair form, the source stages
+        // (everything before the transfer) three times over the axis descriptors (sets 1 to 3: density u n_c
+        // into u~_c), then k_dl_combine into u~; a batch orders the rest of the level after them
+        for (int l = 1; l <= P.leaf; ++l) {
+            std::vector<Stage> &v = P.lev[l].stages;
+            if (P.lev[l].method != kGegenbauer || !(P.lev[l].grid || P.lev[l].qG)) continue;
+            size_t k1 = 0;
+            while (k1 < v.size() && v[k1].kern != K_TRANSFER) ++k1;
+            const std::vector<Stage> head(v.begin(), v.begin() + (std::ptrdiff_t)k1);
+            std::vector<Stage> rest(v.begin() + (std::ptrdiff_t)k1, v.end());
+            int slot = -1, role = 0;
+            for (const Stage &S : head) {
+                if (S.slot >= 0) slot = S.slot;
+                role = std::max(role, S.role_add);
+            }
+            v.clear();
+            for (int c = 0; c < 3; ++c)
+                for (const Stage &S : head) v.push_back(copy(S, 1 + c, false));
+            std::vector<int4> it;
+            const int nt = (int)((P.lev[l].npair + kThreads - 1) / kThreads);
+            for (int32_t b : P.lev[l].h_fwd)
+                for (int q = 0; q < nt; ++q) it.push_back(make_int4(l, b, q, 0));
+            Stage C = make_stage(K_DLCOMBINE, 0, 0, slot, l, 0, std::move(it), st, SC);
+            C.role_add = role + 4 * kRoleComp;
+            v.push_back(std::move(C));
+            for (Stage &S : rest) {
+                S.role_add += 5 * kRoleComp;
+                v.push_back(std::move(S));
+            }
+        }
+    }
     if (P.dnsplit) {
         for (int l = 1; l <= P.leaf; ++l) {
             std::vector<Stage> &v = P.lev[l].stages;
@@ -2503,6 +2544,9 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.vtx = w.vtx;
     d.vtstride = (int64_t)P.ws_tgt;
     d.vtmp = w.vtmp;
+    d.ucomp = w.ucomp;
+    d.utx = w.utx;
+    d.utstride = (int64_t)P.ws_src;
     d.part = w.part;
     d.npair = LV.npair;
     d.part_stride = (int64_t)LY.nbox * LV.npair;
@@ -2555,11 +2599,22 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     return d;
 }
 
-int plan_ndesc(const Plan &P) { return (P.leaf + 1) * (P.grad ? 3 : (P.dnsplit ? 4 : 1)); }
+int plan_ndesc(const Plan &P) { return (P.leaf + 1) * (P.grad ? 3 : (P.dnsplit || P.dlsplit ? 4 : 1)); }
 
 LDesc plan_desc(const Plan &P, int k, int inst, float2 *u, float2 *v, float *amax, const LevelWork &w) {
     const int l = k % (P.leaf + 1), set = k / (P.leaf + 1);
     if (!P.grad && set == 0) return make_desc(P, l, inst, u, v, amax, w);
+    if (P.dlsplit) {
+        // split double layer: set 1 + c is the density u n_c into u~_c
+        const int c = set - 1;
+        LDesc d = make_desc(P, l, inst, w.ucomp + (int64_t)c * P.ny, v, amax, w);
+        d.ucomp = nullptr;
+        if (c > 0) {
+            d.ut = w.utx + (int64_t)(c - 1) * P.ws_src;
+            d.ut2 = reinterpret_cast<float2 *>(d.ut);
+        }
+        return d;
+    }
     // gradient: set c is axis c into output plane c; split normal derivative: set 1 + c is axis c into the
     // combine's plane c
     const int c = P.grad ? set : set - 1;
@@ -2585,6 +2640,8 @@ void plan_set_tune(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     w.nsym = P.wnsym.p;
     w.vtx = P.wtgtx.p;
     w.vtmp = P.wtmp.p;
+    w.ucomp = P.wucomp.p;
+    w.utx = P.wsrcx.p;
     P.hdesc.clear();
     for (int k = 0; k < plan_ndesc(P); ++k) P.hdesc.push_back(plan_desc(P, k, 0, P.u_sorted.p, P.v_sorted.p, P.amax.p, w));
     Scratch SC(st);
@@ -2617,7 +2674,7 @@ size_t plan_device_bytes(const Plan &P) {
     }
     b += P.u_sorted.bytes() + P.v_sorted.bytes() + P.wsrc.bytes() + P.wtgt.bytes() + P.wz.bytes() + P.wpart.bytes() +
          P.wbpart.bytes() + P.wG.bytes() + P.wH.bytes() + P.wnsym.bytes();
-    b += P.tnrm.bytes() + P.snrm.bytes() + P.wtgtx.bytes() + P.wtmp.bytes();
+    b += P.tnrm.bytes() + P.snrm.bytes() + P.wtgtx.bytes() + P.wtmp.bytes() + P.wucomp.bytes() + P.wsrcx.bytes();
     b += P.ddesc.bytes() + P.dio.bytes();
     b += P.items.bytes();
     return b;

@@ -42,6 +42,7 @@ size_t apply_work_bytes(const Plan &P) {
            align256(sizeof(float4) * P.wpart.n) + align256(sizeof(float2) * P.wbpart.n) +
            align256(sizeof(float2) * P.wG.n) + align256(sizeof(float2) * P.wH.n) + align256(sizeof(float2) * P.wnsym.n) +
            align256(sizeof(float4) * P.wtgtx.n) + align256(sizeof(float2) * P.wtmp.n) +
+           align256(sizeof(float2) * P.wucomp.n) + align256(sizeof(float4) * P.wsrcx.n) +
            (P.any_fp16 || P.any_grid ? 256 : 0);
 }
 
@@ -65,6 +66,8 @@ WorkPtrs carve_work(const Plan &P, char *p) {
     w.lw.nsym = reinterpret_cast<float2 *>(take(sizeof(float2) * P.wnsym.n));
     w.lw.vtx = reinterpret_cast<float4 *>(take(sizeof(float4) * P.wtgtx.n));
     w.lw.vtmp = P.wtmp.n ? reinterpret_cast<float2 *>(take(sizeof(float2) * P.wtmp.n)) : nullptr;
+    w.lw.ucomp = P.wucomp.n ? reinterpret_cast<float2 *>(take(sizeof(float2) * P.wucomp.n)) : nullptr;
+    w.lw.utx = P.wsrcx.n ? reinterpret_cast<float4 *>(take(sizeof(float4) * P.wsrcx.n)) : nullptr;
     w.amax = P.any_fp16 || P.any_grid ? reinterpret_cast<float *>(take(sizeof(float))) : nullptr;
     return w;
 }

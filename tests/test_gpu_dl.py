@@ -3,11 +3,13 @@ operator (Sec. 4.2.1, eq. doubleLayer), on the GPU through the C ABI (FFM_LAPLAC
 source normals).
 
 Only the source side differs from the potential: the near-field kernel, the derivatives of the Lagrange
-polynomials at the sources, and the factor -ik (s . n) of every plane wave (direct transforms, the source side in
-direction pairs).  Element-wise against the oracle FFM of the same kernel with identical parameters (FP32_RTOL),
+polynomials at the sources, and the factor -ik (s . n) of every plane wave: in direction pairs, or, where the
+source transform takes the ring-pair or the grid form, as -ik sum_c s_c (the plain source transforms of the
+densities u n_c).  Element-wise against the oracle FFM of the same kernel with identical parameters, grid-form
+levels included (FP32_RTOL),
 within eps of FP64 dense rows, bitwise repeatable, inside a batch, with the per-pair leaf rule, unchanged by
 the mixed-precision option (its transfers stay FP32), against the transpose of the target-side derivative, and
-the missing-normals error.  Plans report the ring form (2) for Gegenbauer levels whose target side takes it.
+the missing-normals error.
 """
 import numpy as np
 import pytest
@@ -27,15 +29,16 @@ def _plan(X, Y, kernel, k, eps, N, **kw):
     return ffm.Plan(Xd, Yd, kernel, k, eps, source_normals=Nd, **kw)
 
 
-@pytest.mark.parametrize("kernel,k,eps", [(4, 0.0, 1e-3), (4, 0.0, 1e-4), (5, 9.0, 1e-3), (5, 45.0, 1e-3),
-                                          (5, 20.0, 1e-4)])
-def test_dl_matches_oracle_and_dense(orc, kernel, k, eps):
+@pytest.mark.parametrize("kernel,k,eps,tf", [(4, 0.0, 1e-3, "auto"), (4, 0.0, 1e-4, "auto"), (5, 9.0, 1e-3, "auto"),
+                                             (5, 45.0, 1e-3, "auto"), (5, 20.0, 1e-4, "auto"), (5, 45.0, 1e-3, "grid"),
+                                             (5, 60.0, 1e-4, "grid")])
+def test_dl_matches_oracle_and_dense(orc, kernel, k, eps, tf):
     rng = np.random.default_rng(int(k) + 17)
     Y = W.sphere_points(20000, rng)                   # sources on the unit sphere with their outward normals
     X = W.sphere_points(15000, rng) * 0.985           # targets just inside
     wu = ((rng.standard_normal(20000) + 1j * rng.standard_normal(20000)) / 20000).astype(np.complex64)
-    print("dl kernel %d k=%g eps=%g" % (kernel, k, eps), flush=True)
-    gp = _plan(X, Y, kernel, k, eps, Y)
+    print("dl kernel %d k=%g eps=%g transforms %s" % (kernel, k, eps, tf), flush=True)
+    gp = _plan(X, Y, kernel, k, eps, Y, transforms=tf)
     st = gp.stats()
     op = oracle_like(orc, gp, X, Y, kernel, k, eps, source_normals=Y)
     compare_trees(gp, op)
@@ -46,9 +49,10 @@ def test_dl_matches_oracle_and_dense(orc, kernel, k, eps):
     print("dl kernel %d k=%g eps=%g: methods %s forms %s aca %s: vs oracle %.3e, vs dense %.3e (oracle %.3e)"
           % (kernel, k, eps, st["method"][:st["leaf"] + 1], st["tform"][:st["leaf"] + 1], st["aca"][:st["leaf"] + 1],
              rel(v, vo), rel(v[rows], d), rel(vo[rows], d)))
-    assert 3 not in st["tform"]                           # direct transforms (the source side in direction pairs)
-    if k >= 45:
-        assert 2 in st["tform"]                           # the target side of the coarse levels in ring pairs
+    if tf == "grid":
+        assert 3 in st["tform"], st["tform"]
+    elif k >= 45:
+        assert 2 in st["tform"]                           # the coarse levels in ring pairs
     assert rel(v, vo) < FP32_RTOL
     assert rel(v[rows], d) <= eps
     assert np.array_equal(v, gpu_apply(gp, wu))
