@@ -44,15 +44,13 @@ extern "C" {
 typedef struct ffm_plan_s *ffm_plan_t;
 
 /* Kernels.  The _DN kernels are the normal derivative at the target, dG/dn_x (x, y) = n_x . grad_x G(x - y), of
- * the adjoint double-layer operator (Sec. 4.2.1, eq. doubleLayer); they need options.target_normals and run
- * their plane-wave levels with the direct transforms.  The _DL kernels are the normal derivative at the source,
- * dG/dn_y (x, y) = n_y . grad_y G(x - y), of the double-layer operator (same equation); they need
- * options.source_normals, run their plane-wave levels with the direct transforms (source side in the
- * direction-pair form) and their Lagrange transfers in FP32 whatever options.precision asks.  The _GRAD kernels
- * are the gradient at the target, grad_x G(x - y), three components per target (the vector kernels the integral
- * operators of Sec. 4.2.2 are built from): their products v hold n_x x 3 values, v[3 i + c] the derivative
- * along axis c at target i; the source transforms and transfers are shared by the three components, whose
- * target transforms and near field run as those of the _DN kernels with n = e_c. */
+ * the adjoint double-layer operator (Sec. 4.2.1, eq. doubleLayer); they need options.target_normals.  The _DL
+ * kernels are the normal derivative at the source, dG/dn_y (x, y) = n_y . grad_y G(x - y), of the double-layer
+ * operator (same equation); they need options.source_normals and run their Lagrange transfers in FP32 whatever
+ * options.precision asks.  The _GRAD kernels are the gradient at the target, grad_x G(x - y), three components
+ * per target (the vector kernels the integral operators of Sec. 4.2.2 are built from): their products v hold
+ * n_x x 3 values, v[3 i + c] the derivative along axis c at target i.  Where a plane-wave level's differentiated
+ * transform takes the ring-pair or the grid form it runs once per axis (k s . n = sum_c k s_c n_c). */
 typedef enum {
     FFM_LAPLACE = 0, FFM_HELMHOLTZ = 1, FFM_LAPLACE_DN = 2, FFM_HELMHOLTZ_DN = 3, FFM_LAPLACE_DL = 4,
     FFM_HELMHOLTZ_DL = 5, FFM_LAPLACE_GRAD = 6, FFM_HELMHOLTZ_GRAD = 7
