@@ -212,7 +212,7 @@ ffm_status_t ffm_plan(const double *X, int64_t n_x, const double *Y, int64_t n_y
         FFM_HIP(hipEventRecord(P.ready, st));
         FFM_HIP(hipEventCreateWithFlags(&P.done, hipEventDisableTiming));
         if (o.flags & FFM_FLAG_TIMING) {
-            P.tev.resize(12 * kMaxLev + 16, nullptr);   // one event per launch, every form of every level
+            P.tev.resize(12 * kMaxLev + 16, nullptr);   // one event per launch (more are made as needed)
             P.tphase.assign(P.tev.size(), -1);
             P.tkern.assign(P.tev.size(), make_int4(-1, 0, 0, 0));
             P.tblocks.assign(P.tev.size(), 0);

@@ -3264,7 +3264,15 @@ void run_stage(const Stage &S, const LDesc *ddesc, const IoEntry *dio, hipStream
 // Record the end of a phase (timing plans only): the first call opens the apply.
 void Plan::mark(int phase, hipStream_t st, const Stage *S) {
     if (tev.empty()) return;
-    FFM_CHECK(tused < (int)tev.size(), FFM_EINTERNAL, "timing events exhausted");
+    if (tused == (int)tev.size()) {
+        // more launches than the events made with the plan (box batches, per-axis passes): one more event
+        hipEvent_t e = nullptr;
+        FFM_HIP(hipEventCreate(&e));
+        tev.push_back(e);
+        tphase.push_back(-1);
+        tkern.push_back(make_int4(-1, 0, 0, 0));
+        tblocks.push_back(0);
+    }
     FFM_HIP(hipEventRecord(tev[tused], st));
     tphase[tused] = phase;
     tkern[tused] = S ? make_int4(S->kern, S->a, S->b, S->level) : make_int4(-1, 0, 0, 0);
