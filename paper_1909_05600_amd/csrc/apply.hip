@@ -730,9 +730,60 @@ k_sum_segments(const LDesc *__restrict__ descs, const IoEntry *__restrict__, con
 
 // Backward transform in ring-pair form: per target point and ring pair m,
 //   v += e^{iC} sum_n [e^{iP} v~(m,n) + e^{-iP} v~(m,n+L)] + e^{-iC} sum_n [e^{iP} v~(L-m,n) + e^{-iP} v~(L-m,n+L)]
-// PT target points per thread; item (desc, target box, first point).
-template <int PT, int U, bool P64>
-__global__ void __launch_bounds__(kThreads)
+// PT target points per thread, BS threads per block; item (desc, target box, first point).  The staged entries of a ring pair are
+// padded with zeros to a multiple of U (a zero term leaves every sum unchanged), so the inner loop runs in
+// unrolled steps of U with immediate LDS offsets.  Where a ring's padded azimuths fit one block's worth, the
+// entries of as many ring pairs as fit kBkStage go to LDS at once (one load round and one barrier pair for
+// all of them); otherwise ring pair by ring pair in chunks of kThreads azimuths.  Either way each ring pair's
+// sums run over the same terms in the same order.
+constexpr int kBkStage = 512;
+
+// entries of ring pair m, azimuth n: (v~(m,n) + v~(m,n+L), i-free difference) pairs as the inner sums use them
+__device__ __forceinline__ void bk_stage_entry(const float4 *vb, int L, int m, int n, float4 &e01, float4 &e23) {
+    const float4 p1 = vb[(int64_t)m * 2 * L + n];
+    if (2 * m == L) {
+        e01 = make_float4(p1.x + p1.z, p1.y + p1.w, p1.x - p1.z, p1.y - p1.w);
+        e23 = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        const float4 p2 = vb[(int64_t)m * 2 * L + n + L];
+        e01 = make_float4(p1.x + p2.x, p1.y + p2.y, p1.x - p2.x, p1.y - p2.y);
+        e23 = make_float4(p2.z + p1.z, p2.w + p1.w, p2.z - p1.z, p2.w - p1.w);
+    }
+}
+
+template <int PT, int U, bool P64, typename real>
+__device__ __forceinline__ void bk_ring_terms(const float4 *s01, const float4 *s23, const real *scf, const real *ssf,
+                                              int cnt4, const real *A, const real *B, float *xre, float *xim,
+                                              float *yre, float *yim) {
+    for (int j0 = 0; j0 < cnt4; j0 += U) {
+#pragma unroll
+        for (int ju = 0; ju < U; ++ju) {
+            const int jj = j0 + ju;
+            const real cfn = scf[jj], sfn = ssf[jj];
+            const float4 a = s01[jj], c = s23[jj];
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                float f;
+                if (P64) {
+                    const double P = fma((double)A[q], (double)cfn, (double)B[q] * (double)sfn);
+                    f = (float)__builtin_amdgcn_fract(P);
+                } else {
+                    const float P = fmaf((float)A[q], (float)cfn, (float)B[q] * (float)sfn);
+                    f = P;
+                }
+                float sn, cs;
+                sincos_rev(f, sn, cs);
+                xre[q] = fmaf(cs, a.x, fmaf(-sn, a.w, xre[q]));
+                xim[q] = fmaf(cs, a.y, fmaf(sn, a.z, xim[q]));
+                yre[q] = fmaf(cs, c.x, fmaf(-sn, c.w, yre[q]));
+                yim[q] = fmaf(cs, c.y, fmaf(sn, c.z, yim[q]));
+            }
+        }
+    }
+}
+
+template <int PT, int U, bool P64, int BS = kThreads>
+__global__ void __launch_bounds__(BS)
 k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
     typedef typename std::conditional<P64, double, float>::type real;
     const int4 wk = work[blockIdx.x];
@@ -747,97 +798,98 @@ k_pw_backward_rings(const LDesc *__restrict__ descs, const IoEntry *__restrict__
     float vr[PT], vi[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-        const int i = wk.z + tid + q * kThreads;
+        const int i = wk.z + tid + q * BS;
         valid[q] = i < iend;
         xr[q] = valid[q] ? d.txs[i] - d.tctr[3 * t] : 0.0;
         yr[q] = valid[q] ? d.tys[i] - d.tctr[3 * t + 1] : 0.0;
         zr[q] = valid[q] ? d.tzs[i] - d.tctr[3 * t + 2] : 0.0;
         vr[q] = vi[q] = 0.f;
     }
-    __shared__ float4 s01[kThreads], s23[kThreads];
+    __shared__ float4 s01[kBkStage], s23[kBkStage];
     __shared__ real scf[kThreads], ssf[kThreads];
     const float4 *vb = d.vt + (int64_t)t * npair;
     // this block's ring pairs (part wk.w of bsplit)
     const int mper = (nrp + d.bsplit - 1) / d.bsplit;
     const int mb = wk.w * mper, me = min(nrp, mb + mper);
-    for (int m = mb; m < me; ++m) {
-        const double2 rg = d.rings[m];
-        const bool eq = 2 * m == L;
-        real A[PT], B[PT];
-        float ecs[PT], esn[PT], xre[PT], xim[PT], yre[PT], yim[PT];
+    const int Lp = (L + U - 1) / U * U;
+    // per ring pair: the point factors, then the sums over its azimuths (staged at e01, e23), then the
+    // ring's contribution to v
+    auto ring = [&](int m, const float4 *e01, const float4 *e23, int n0, int cnt4, bool first, bool last,
+                    float *xre, float *xim, float *yre, float *yim, float *ecs, float *esn, real *A, real *B) {
+        if (first) {
+            const double2 rg = d.rings[m];
 #pragma unroll
-        for (int q = 0; q < PT; ++q) {
-            A[q] = (real)(rg.x * xr[q]);
-            B[q] = (real)(rg.x * yr[q]);
-            const double C = rg.y * zr[q];
-            sincos_rev((float)(C - floor(C)), esn[q], ecs[q]);
-            xre[q] = xim[q] = yre[q] = yim[q] = 0.f;
+            for (int q = 0; q < PT; ++q) {
+                A[q] = (real)(rg.x * xr[q]);
+                B[q] = (real)(rg.x * yr[q]);
+                const double C = rg.y * zr[q];
+                sincos_rev((float)(C - floor(C)), esn[q], ecs[q]);
+                xre[q] = xim[q] = yre[q] = yim[q] = 0.f;
+            }
         }
-        for (int n0 = 0; n0 < L; n0 += kThreads) {
-            const int cnt = min(kThreads, L - n0);
-            // staged entries padded with zeros to a multiple of U (a zero term leaves every sum unchanged),
-            // so the inner loop runs in unrolled steps of U with immediate LDS offsets
-            const int cnt4 = (cnt + U - 1) / U * U;
+        bk_ring_terms<PT, U, P64, real>(e01, e23, scf + n0, ssf + n0, cnt4, A, B, xre, xim, yre, yim);
+        if (last) {
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                // explicit fused forms, so every points-per-thread variant rounds identically
+                vr[q] = fmaf(ecs[q], xre[q] + yre[q], fmaf(-esn[q], xim[q] - yim[q], vr[q]));
+                vi[q] = fmaf(ecs[q], xim[q] + yim[q], fmaf(esn[q], xre[q] - yre[q], vi[q]));
+            }
+        }
+    };
+    real A[PT], B[PT];
+    float ecs[PT], esn[PT], xre[PT], xim[PT], yre[PT], yim[PT];
+    if (Lp <= kThreads) {
+        // whole rings: the azimuth tables once, then groups of ring pairs
+        for (int e = tid; e < Lp; e += BS) {
+            scf[e] = e < L ? (real)d.phis[e].x : (real)0;
+            ssf[e] = e < L ? (real)d.phis[e].y : (real)0;
+        }
+        const int rps = kBkStage / Lp;
+        for (int g0 = mb; g0 < me; g0 += rps) {
+            const int ng = min(rps, me - g0);
             __syncthreads();
-            if (tid < cnt4) {
-                const int n = n0 + tid;
-                if (tid >= cnt) {
-                    s01[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    s23[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    scf[tid] = (real)0;
-                    ssf[tid] = (real)0;
+            for (int e = tid; e < ng * Lp; e += BS) {
+                const int r = e / Lp, n = e - r * Lp;
+                if (n >= L) {
+                    s01[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    s23[e] = make_float4(0.f, 0.f, 0.f, 0.f);
                 } else {
-                    const float4 p1 = vb[(int64_t)m * 2 * L + n];
-                    if (eq) {
-                        s01[tid] = make_float4(p1.x + p1.z, p1.y + p1.w, p1.x - p1.z, p1.y - p1.w);
-                        s23[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    } else {
-                        const float4 p2 = vb[(int64_t)m * 2 * L + n + L];
-                        s01[tid] = make_float4(p1.x + p2.x, p1.y + p2.y, p1.x - p2.x, p1.y - p2.y);
-                        s23[tid] = make_float4(p2.z + p1.z, p2.w + p1.w, p2.z - p1.z, p2.w - p1.w);
-                    }
-                    scf[tid] = (real)d.phis[n].x;
-                    ssf[tid] = (real)d.phis[n].y;
+                    bk_stage_entry(vb, L, g0 + r, n, s01[e], s23[e]);
                 }
             }
             __syncthreads();
-            for (int j0 = 0; j0 < cnt4; j0 += U) {
-#pragma unroll
-                for (int ju = 0; ju < U; ++ju) {
-                    const int jj = j0 + ju;
-                    const real cfn = scf[jj], sfn = ssf[jj];
-                    const float4 a = s01[jj], c = s23[jj];
-#pragma unroll
-                    for (int q = 0; q < PT; ++q) {
-                        float f;
-                        if (P64) {
-                            const double P = fma((double)A[q], (double)cfn, (double)B[q] * (double)sfn);
-                            f = (float)__builtin_amdgcn_fract(P);
-                        } else {
-                            const float P = fmaf((float)A[q], (float)cfn, (float)B[q] * (float)sfn);
-                            f = P;
-                        }
-                        float sn, cs;
-                        sincos_rev(f, sn, cs);
-                        xre[q] = fmaf(cs, a.x, fmaf(-sn, a.w, xre[q]));
-                        xim[q] = fmaf(cs, a.y, fmaf(sn, a.z, xim[q]));
-                        yre[q] = fmaf(cs, c.x, fmaf(-sn, c.w, yre[q]));
-                        yim[q] = fmaf(cs, c.y, fmaf(sn, c.z, yim[q]));
+            for (int r = 0; r < ng; ++r)
+                ring(g0 + r, s01 + r * Lp, s23 + r * Lp, 0, Lp, true, true, xre, xim, yre, yim, ecs, esn, A, B);
+        }
+    } else {
+        for (int m = mb; m < me; ++m) {
+            for (int n0 = 0; n0 < L; n0 += BS) {
+                const int cnt = min(BS, L - n0);
+                const int cnt4 = (cnt + U - 1) / U * U;
+                __syncthreads();
+                if (tid < cnt4) {
+                    const int n = n0 + tid;
+                    if (tid >= cnt) {
+                        s01[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        s23[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        scf[tid] = (real)0;
+                        ssf[tid] = (real)0;
+                    } else {
+                        bk_stage_entry(vb, L, m, n, s01[tid], s23[tid]);
+                        scf[tid] = (real)d.phis[n].x;
+                        ssf[tid] = (real)d.phis[n].y;
                     }
                 }
+                __syncthreads();
+                ring(m, s01, s23, 0, cnt4, n0 == 0, n0 + BS >= L, xre, xim, yre, yim, ecs, esn, A, B);
             }
-        }
-#pragma unroll
-        for (int q = 0; q < PT; ++q) {
-            // explicit fused forms, so every points-per-thread variant rounds identically
-            vr[q] = fmaf(ecs[q], xre[q] + yre[q], fmaf(-esn[q], xim[q] - yim[q], vr[q]));
-            vi[q] = fmaf(ecs[q], xim[q] + yim[q], fmaf(esn[q], xre[q] - yre[q], vi[q]));
         }
     }
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
         if (!valid[q]) continue;
-        const int i = wk.z + tid + q * kThreads;
+        const int i = wk.z + tid + q * BS;
         if (d.bsplit > 1) {
             d.bpart[(int64_t)wk.w * d.nx + i] = make_float2(vr[q], vi[q]);
         } else {
@@ -3142,6 +3194,11 @@ KernelFn kernel_of(const Stage &S, int &threads) {
             return S.b ? k_pw_backward<kThreads, true> : k_pw_backward<kThreads, false>;
         case K_BWD_RING:
             // inner loop unrolled by 4 (one point per thread) or 2 (two points per thread)
+            // (a = 102: two points per thread in 128-thread blocks)
+            if (S.a == 102) {
+                threads = 128;
+                return S.b ? k_pw_backward_rings<2, 2, true, 128> : k_pw_backward_rings<2, 2, false, 128>;
+            }
             if (S.a == 2) return S.b ? k_pw_backward_rings<2, 2, true> : k_pw_backward_rings<2, 2, false>;
             return S.b ? k_pw_backward_rings<1, 4, true> : k_pw_backward_rings<1, 4, false>;
         case K_BSUM: return k_sum_parts;
@@ -3343,6 +3400,7 @@ std::string kernel_name(int kern, int a, int b) {
             return "k_pw_transfer<" + std::to_string(a == 2 ? 2 : 1) + ", 256>";
         case K_BWD_PAIR: return "k_pw_backward<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
         case K_BWD_RING:
+            if (a == 102) return "k_pw_backward_rings<2, 2, " + tf(b) + ", 128>";
             return a == 2 ? "k_pw_backward_rings<2, 2, " + tf(b) + ">" : "k_pw_backward_rings<1, 4, " + tf(b) + ">";
         case K_BSUM: return "k_sum_parts";
         case K_ANTERP: return "k_lag_anterp";

@@ -2247,9 +2247,12 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             // the normal derivative at the targets multiplies every direction by its own ik (s . n): the target
             // transform runs in the direction-pair form
             const bool ring_bwd = LV.qG != 0;
-            // two target points per thread only where the target boxes hold more than a block's worth on average
-            const int bpt = LV.pts_tgt > (double)kThreads * (double)std::max<size_t>(1, LV.h_tgt.size()) ? tu.bwd_pt : 1;
-            LV.bwd_tile = ring_bwd ? kThreads * bpt : kThreads;
+            // two target points per thread in blocks of kThreads where the target boxes hold more than a block's
+            // worth on average, else (bpt = 102) in blocks of 128 threads, so that a box's points fill one block
+            // while each staged azimuth entry still serves two points
+            const bool big_tgt = LV.pts_tgt > (double)kThreads * (double)std::max<size_t>(1, LV.h_tgt.size());
+            const int bpt = big_tgt ? tu.bwd_pt : (tu.bwd_pt == 2 ? 102 : 1);
+            LV.bwd_tile = ring_bwd ? (bpt == 102 ? 256 : kThreads * bpt) : kThreads;
             std::vector<int4> fw;
             // (the double layer splits its ring-pair source transform by axis, like the grid form's)
             if (LV.qG) {
@@ -2293,7 +2296,9 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             int64_t tiles = 0;
             for (int32_t t : LV.h_tgt) tiles += (sx[t + 1] - sx[t] + LV.bwd_tile - 1) / LV.bwd_tile;
             // ring parts of the target transform: enough blocks for several rounds of the chip
-            LV.bSplit = ring_bwd ? choose_split(tiles, conc_bwd[bpt == 2][LV.phase64], 8, LV.nrp) : 1;
+            const int conc_b = bpt == 102 ? cus * stage_blocks_per_cu(K_BWD_RING, 102, LV.phase64)
+                                          : conc_bwd[bpt == 2][LV.phase64];
+            LV.bSplit = ring_bwd ? choose_split(tiles, conc_b, 8, LV.nrp) : 1;
             if (LV.bSplit > 1) ws_bpart = std::max(ws_bpart, (size_t)LV.bSplit * P.nx);
             bw.reserve((size_t)(tiles * LV.bSplit));
             for (int g = 0; g < LV.bSplit; ++g)

@@ -3,8 +3,9 @@
 // The sort orders (key, index) pairs by the full 63-bit key with ties kept in
 // index order: eight 8-bit passes, each a histogram, a digit-major scan and a
 // stable scatter.  Stability inside a tile comes from ranking a wavefront's
-// lanes by ballot matching of their digits, wave by wave and round by round in
-// element order, so equal keys leave in the order they came in.
+// lanes by ballot matching of their digits, round by round in element order,
+// so equal keys leave in the order they came in; the tile is sorted in LDS and
+// leaves as contiguous runs of equal digits.
 #include "common.h"
 
 namespace ffm {
@@ -127,9 +128,27 @@ void exclusive_scan(const T *in, T *out, int64_t n, hipStream_t st, Scratch &S) 
 }
 
 // ------------------------------------------------------------------ radix sort
+// A block takes a tile of 4096 keys.  In the scatter, wave w of the block takes the tile's items
+// w 1024 ... w 1024 + 1023, 64 consecutive items per round, so the tile's element order is (wave, round,
+// lane).  Every lane loads its 16 items first; the lanes of one round that share a digit find each other by
+// ballots over the digit's bits, and the lowest of them adds their number to the wave's count of that digit.
 constexpr int kRsThreads = 256;
+constexpr int kRsWaves = kRsThreads / 64;
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int kRsWaveTile = 64 * kRsItems;
+
+// the lanes of the wave holding a valid item whose digit is d
+__device__ __forceinline__ uint64_t rs_peers(int d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
 
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_hist(const uint64_t *keys, int64_t n, int shift, int32_t *counts, int nblk) {
@@ -138,59 +157,89 @@ k_rs_hist(const uint64_t *keys, int64_t n, int shift, int32_t *counts, int nblk)
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     for (int j = 0; j < kRsItems; ++j) {
-        int64_t i = base + (int64_t)j * kRsThreads + threadIdx.x;
+        const int64_t i = base + (int64_t)j * kRsThreads + threadIdx.x;
         if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & 255u)], 1);
     }
     __syncthreads();
     counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile: each item's place within its digit's run of the tile is the number of items
+// of that digit before it in element order (earlier waves, then earlier rounds of its wave, then lower
+// lanes of its round).  The tile is put in digit order in LDS and written out run by run, consecutive
+// threads to consecutive places; offs[d nblk + b] is where block b's run of digit d starts.
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout, int64_t n, int shift,
              const int32_t *offs, int nblk) {
-    __shared__ int run[256];
-    __shared__ int wc[kRsThreads / 64][256];
-    __shared__ int gbase[256];
+    __shared__ int wcnt[kRsWaves][256];     // the wave's count of each digit, then the digit's items before the wave
+    __shared__ int dstart[256];              // start of each digit's run in the sorted tile
+    __shared__ int gstart[256];
+    __shared__ int wsum[kRsWaves];
+    __shared__ uint64_t sk[kRsTile];
+    __shared__ int32_t sv[kRsTile];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    run[t] = 0;
-    gbase[t] = offs[(int64_t)t * nblk + blockIdx.x];
-    for (int ww = 0; ww < kRsThreads / 64; ++ww) wc[ww][t] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRsTile;
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
+    for (int ww = 0; ww < kRsWaves; ++ww) wcnt[ww][t] = 0;
+    gstart[t] = offs[(int64_t)t * nblk + blockIdx.x];
+    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+    const int64_t base = tile0 + (int64_t)w * kRsWaveTile + lane;
+    uint64_t key[kRsItems];
+    int32_t val[kRsItems];
+#pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
-        const int64_t i = base + (int64_t)r * kRsThreads + t;
-        const bool valid = i < n;
-        const uint64_t key = valid ? kin[i] : 0ull;
-        const int32_t val = valid ? vin[i] : 0;
-        const int d = (int)((key >> shift) & 255u);
-        uint64_t mask = __ballot(valid);
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t bal = __ballot(bit);
-            mask &= bit ? bal : ~bal;
-        }
-        const int rank = __popcll(mask & lt);
-        if (valid && rank == 0) wc[w][d] = __popcll(mask);
-        __syncthreads();
-        {
-            int acc = run[t];
-            for (int ww = 0; ww < kRsThreads / 64; ++ww) {
-                int c = wc[ww][t];
-                wc[ww][t] = acc;
-                acc += c;
-            }
-            run[t] = acc;
-        }
-        __syncthreads();
-        if (valid) {
-            const int pos = gbase[d] + wc[w][d] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        for (int ww = 0; ww < kRsThreads / 64; ++ww) wc[ww][t] = 0;
-        __syncthreads();
+        const int64_t i = base + r * 64;
+        key[r] = i < n ? kin[i] : 0ull;
+        val[r] = i < n ? vin[i] : 0;
+    }
+    __syncthreads();
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int pos[kRsItems];                       // digit << 16 | place among the wave's items of that digit; -1: none
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const bool valid = base + r * 64 < n;
+        const int d = (int)((key[r] >> shift) & 255u);
+        const uint64_t m = rs_peers(d, valid);
+        const int rank = __popcll(m & lt);
+        // every lane reads the count before the lowest lane of its digit writes it: one wave, in program order
+        const int before = wcnt[w][d];
+        if (valid && rank == 0) wcnt[w][d] = before + __popcll(m);
+        pos[r] = valid ? (d << 16) | (before + rank) : -1;
+    }
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < kRsWaves; ++ww) {
+        const int c = wcnt[ww][t];
+        wcnt[ww][t] = tot;
+        tot += c;
+    }
+    int incl = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int off = 0;
+    for (int ww = 0; ww < w; ++ww) off += wsum[ww];
+    dstart[t] = off + incl - tot;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        if (pos[r] < 0) continue;
+        const int d = pos[r] >> 16;
+        const int loc = dstart[d] + wcnt[w][d] + (pos[r] & 0xffff);
+        sk[loc] = key[r];
+        sv[loc] = val[r];
+    }
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(kRsTile, n - tile0);
+    for (int i = t; i < cnt; i += kRsThreads) {
+        const uint64_t k = sk[i];
+        const int d = (int)((k >> shift) & 255u);
+        const int dst = gstart[d] + (i - dstart[d]);
+        kout[dst] = k;
+        vout[dst] = sv[i];
     }
 }
 
