@@ -118,6 +118,8 @@ def parse():
                     help="bake-off of the grid form's separable sums against an FFT-based type-2 NUFFT")
     ap.add_argument("--aca-study", action="store_true",
                     help="only run the ACA study (full transfer matrices against their ACA factors)")
+    ap.add_argument("--deriv-study", action="store_true",
+                    help="only time the derivative kernels (normal derivatives, gradient) beside the potential")
     ap.add_argument("--bie-eps", type=float, default=1e-3)
     ap.add_argument("--bie-tol", type=float, default=1e-4)
     ap.add_argument("--mixed-rows", type=int, default=1024)
@@ -541,6 +543,39 @@ def nufft_study(n, reps=3):
     return out
 
 
+def deriv_study(n, reps=5):
+    """Apply times of the derivative kernels (Sec. 4.2: the normal derivative at the targets, the double layer,
+    the gradient) beside the potential, one plan each over the same N points on the unit sphere with radial unit
+    normals and the same input, at the headline wavenumber; each time is the median of reps applies, wall clock
+    around a synchronised apply."""
+    import torch
+    import ffm_workloads as W
+    import paper_1909_05600_amd as ffm
+    w = W.helmholtz_sphere(n, seed=2, eps=1e-3)
+    X = torch.from_numpy(w.X).cuda()
+    wu = torch.from_numpy(w.wu).cuda()
+    out = {"n": n, "k": w.k, "eps": w.eps, "runs": []}
+    for name, kernel, kw in (("potential", ffm.FFM_HELMHOLTZ, {}),
+                             ("normal_derivative", ffm.FFM_HELMHOLTZ_DN, {"normals": X}),
+                             ("double_layer", ffm.FFM_HELMHOLTZ_DL, {"source_normals": X}),
+                             ("gradient", ffm.FFM_HELMHOLTZ_GRAD, {})):
+        p = ffm.Plan(X, X, kernel, w.k, w.eps, **kw)
+        v = p.apply(wu)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            p.apply(wu, out=v)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        st = p.stats()
+        out["runs"].append({"kernel": name, "apply_ms": round(float(np.median(ts)), 3),
+                            "transform_form": st["tform"][:st["leaf"] + 1], "plan_mb": round(p.plan_bytes() / 1e6, 1)})
+        print("%-18s apply %.2f ms (median of %d)" % (name, float(np.median(ts)), reps), file=sys.stderr, flush=True)
+        p.destroy()
+    return out
+
+
 def aca_study(n, reps=5):
     """ACA of the Lagrange transfer matrices (Sec. 2.2.2, eq. ffmACAmatvec) against full matrices: apply and plan
     times, transfer-kernel times and errors against FP64 dense rows, for N points on the sphere: Laplace at
@@ -814,6 +849,12 @@ def main():
     if args.aca_study:
         res = {"metric": "ACA of the Lagrange transfers: apply time and error against full matrices",
                "aca_study": aca_study(args.n)}
+        print(json.dumps(res), flush=True)
+        return
+
+    if args.deriv_study:
+        res = {"metric": "apply time of the derivative kernels beside the potential (N points on the sphere)",
+               "deriv_study": deriv_study(args.n)}
         print(json.dumps(res), flush=True)
         return
 

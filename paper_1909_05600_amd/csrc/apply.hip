@@ -3401,7 +3401,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_BWD_PAIR: return "k_pw_backward<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";
         case K_BWD_RING:
             if (a == 102) return "k_pw_backward_rings<2, 2, " + tf(b) + ", 128>";
-            return a == 2 ? "k_pw_backward_rings<2, 2, " + tf(b) + ">" : "k_pw_backward_rings<1, 4, " + tf(b) + ">";
+            return a == 2 ? "k_pw_backward_rings<2, 2, " + tf(b) + ", 256>" : "k_pw_backward_rings<1, 4, " + tf(b) + ", 256>";
         case K_BSUM: return "k_sum_parts";
         case K_ANTERP: return "k_lag_anterp";
         case K_ANTERP_DL: return "k_lag_anterp_dl";

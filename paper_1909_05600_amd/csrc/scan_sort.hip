@@ -4,8 +4,7 @@
 // index order: eight 8-bit passes, each a histogram, a digit-major scan and a
 // stable scatter.  Stability inside a tile comes from ranking a wavefront's
 // lanes by ballot matching of their digits, round by round in element order,
-// so equal keys leave in the order they came in; the tile is sorted in LDS and
-// leaves as contiguous runs of equal digits.
+// so equal keys leave in the order they came in.
 #include "common.h"
 
 namespace ffm {
@@ -164,25 +163,21 @@ k_rs_hist(const uint64_t *keys, int64_t n, int shift, int32_t *counts, int nblk)
     counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile: each item's place within its digit's run of the tile is the number of items
-// of that digit before it in element order (earlier waves, then earlier rounds of its wave, then lower
-// lanes of its round).  The tile is put in digit order in LDS and written out run by run, consecutive
-// threads to consecutive places; offs[d nblk + b] is where block b's run of digit d starts.
+// Stable scatter of one tile: each item's place within its digit's run of the tile is the number of items of
+// that digit before it in element order (earlier waves, then earlier rounds of its wave, then lower lanes of its
+// round); offs[d nblk + b] is where block b's run of digit d starts.  Items go from registers straight to their
+// places: the kernel holds only the per-wave digit counts in LDS, so that its blocks fit beside other work on
+// a busy device.
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *vout, int64_t n, int shift,
              const int32_t *offs, int nblk) {
-    __shared__ int wcnt[kRsWaves][256];     // the wave's count of each digit, then the digit's items before the wave
-    __shared__ int dstart[256];              // start of each digit's run in the sorted tile
+    __shared__ int wcnt[kRsWaves][256];     // the wave's count of each digit, then the place of its first item
     __shared__ int gstart[256];
-    __shared__ int wsum[kRsWaves];
-    __shared__ uint64_t sk[kRsTile];
-    __shared__ int32_t sv[kRsTile];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
 #pragma unroll
     for (int ww = 0; ww < kRsWaves; ++ww) wcnt[ww][t] = 0;
     gstart[t] = offs[(int64_t)t * nblk + blockIdx.x];
-    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
-    const int64_t base = tile0 + (int64_t)w * kRsWaveTile + lane;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveTile + lane;
     uint64_t key[kRsItems];
     int32_t val[kRsItems];
 #pragma unroll
@@ -206,40 +201,21 @@ k_rs_scatter(const uint64_t *kin, const int32_t *vin, uint64_t *kout, int32_t *v
         pos[r] = valid ? (d << 16) | (before + rank) : -1;
     }
     __syncthreads();
-    int tot = 0;
+    int tot = gstart[t];
 #pragma unroll
     for (int ww = 0; ww < kRsWaves; ++ww) {
         const int c = wcnt[ww][t];
         wcnt[ww][t] = tot;
         tot += c;
     }
-    int incl = tot;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    int off = 0;
-    for (int ww = 0; ww < w; ++ww) off += wsum[ww];
-    dstart[t] = off + incl - tot;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         if (pos[r] < 0) continue;
         const int d = pos[r] >> 16;
-        const int loc = dstart[d] + wcnt[w][d] + (pos[r] & 0xffff);
-        sk[loc] = key[r];
-        sv[loc] = val[r];
-    }
-    __syncthreads();
-    const int cnt = (int)min<int64_t>(kRsTile, n - tile0);
-    for (int i = t; i < cnt; i += kRsThreads) {
-        const uint64_t k = sk[i];
-        const int d = (int)((k >> shift) & 255u);
-        const int dst = gstart[d] + (i - dstart[d]);
-        kout[dst] = k;
-        vout[dst] = sv[i];
+        const int dst = wcnt[w][d] + (pos[r] & 0xffff);
+        kout[dst] = key[r];
+        vout[dst] = val[r];
     }
 }
 

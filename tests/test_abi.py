@@ -138,7 +138,7 @@ def test_kernel_names_and_launch_timing_validation(L):
     # (kernel id, variants) -> symbol, ids in the library's launch order of kinds
     assert ffm.kernel_name(0) == "k_perm_in"
     assert ffm.kernel_name(3, 4, 0) == "k_pw_forward_rings<4, false>"
-    assert ffm.kernel_name(7, 2, 1) == "k_pw_backward_rings<2, 2, true>"
+    assert ffm.kernel_name(7, 2, 1) == "k_pw_backward_rings<2, 2, true, 256>"
     assert ffm.kernel_name(7, 102, 0) == "k_pw_backward_rings<2, 2, false, 128>"
     assert ffm.kernel_name(12, 0, 1) == "k_near<true, false>"
     assert ffm.kernel_name(12, 1, 1) == "k_near<true, true>"
