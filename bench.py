@@ -71,15 +71,15 @@ PEAKS = {"mfma": (157.3, "TFLOP/s"), "mfma16": (2500.0, "TFLOP/s"), "alu": (PEAK
 # workload (profiles/traffic_apply_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
 # kernel of known size (FETCH x 2.0, WRITE x 1.0), mean over the kernel's launches in one product.  Valid only
 # for the kernel source it was taken on.
-TRAFFIC_SOURCE_HASH = "d43afa1c3375bb21"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
+TRAFFIC_SOURCE_HASH = "d739a119b1e78f43"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
 TRAFFIC = {
-    "k_pw_forward_rings<2, false>": (35359.219 * 2.0 + 84612.156) * 1024.0,
-    "k_grid_phi_s<4>": (202941.562 * 2.0 + 24856.500) * 1024.0,
-    "k_grid_phit": (79140.312 * 2.0 + 295680.000) * 1024.0,
-    "k_near_sym<true, false>": (202135.188 * 2.0 + 84411.719) * 1024.0,
-    "k_pw_transfer_sib": (182515.167 * 2.0 + 56244.031) * 1024.0,
-    "k_pw_backward_rings<2, 2, false>": (85083.750 * 2.0 + 24772.812) * 1024.0,
-    "k_pw_backward_rings<1, 4, false>": (81279.125 * 2.0 + 25059.656) * 1024.0,
+    "k_pw_forward_rings<2, false>": (35349.500 * 2.0 + 84611.688) * 1024.0,
+    "k_grid_phi_s<4>": (202946.125 * 2.0 + 24819.688) * 1024.0,
+    "k_grid_phit": (79105.438 * 2.0 + 295680.000) * 1024.0,
+    "k_near_sym<true, false>": (202001.875 * 2.0 + 84432.406) * 1024.0,
+    "k_pw_transfer_sib": (181814.625 * 2.0 + 56244.031) * 1024.0,
+    "k_pw_backward_rings<2, 2, false, 256>": (85140.812 * 2.0 + 24771.656) * 1024.0,
+    "k_pw_backward_rings<2, 2, false, 128>": (81293.875 * 2.0 + 25058.750) * 1024.0,
 }
 
 
