@@ -42,13 +42,18 @@ PEAK_ALU_PACKED_TFLOPS = 157.3
 #   normal derivative at the target, per pair: Laplace 21 (the Laplace count with n . d in 3 FMA and 1/r^3 in 3
 #     products instead of the scale), Helmholtz 35 (the same, k r, sin, cos, the two factors -(cos + kr sin),
 #     kr cos - sin and a complex multiply-add); at the source the same counts (the normal is the source's)
+#   gradient at the target, per pair and all three components: Laplace 27 (3 differences, |d|^2 in 3 FMA, rsqrt,
+#     1/r^3 in 2 products, then per component d_c / r^3 and its real-by-complex multiply-add: 3 x 5), Helmholtz
+#     53 (the same up to 1/r^3, k r in 2 products, sin, cos, the two factors in 2 FMA, then per component d_c / r^3,
+#     its two products with the factors and a complex multiply-add: 3 x 11)
 #   normal derivative at the source, source transforms: the direction-pair form adds k (s . n) (2 FMA and
 #     2 products, 6) and its product with u (2): 24 per 2 directions; the Lagrange anterpolation weights
 #     n . grad of the node polynomial (4 products and 2 FMA, 8) before the complex multiply-add (4): 12 per
 #     (point, node)
 FLOPS_PER_DIRECTION = {"pair": 16.0 / 2, "ring": 22.0 / 4, "pair_dl": 24.0 / 2}
 NEAR_FLOPS = {"k_near<false": 14.0, "k_near<true": 24.0, "k_near_dn<false": 21.0, "k_near_dn<true": 35.0,
-              "k_near_dl<false": 21.0, "k_near_dl<true": 35.0, "k_near_sym<false": 14.0, "k_near_sym<true": 24.0}
+              "k_near_dl<false": 21.0, "k_near_dl<true": 35.0, "k_near_sym<false": 14.0, "k_near_sym<true": 24.0,
+              "k_near_grad<false": 27.0, "k_near_grad<true": 53.0}
 # VALU issue slots the implemented near-field loop needs per pair at least (transcendentals co-issue): three FP64
 # differences and their conversions to FP32 (6), |d|^2 (3), then Laplace a complex multiply-add (2), Helmholtz
 # r = |d|^2 / |d| (1), cos / r and sin / r (2) and a complex multiply-add (4).  The slot utilisation is reported

@@ -2943,6 +2943,157 @@ k_near_dl(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
     near_body<HELM, 2, BIG>(descs[wk.x], wk);
 }
 
+// The gradient at the targets: grad_x G(x - y) = d G'(r) / r, d = x - y.  The three components share r, 1/r^3
+// and the phase; each component is formed as the normal derivative along its axis would form it (the same
+// operations in the same order), so component c equals that pass with n = e_c.
+template <bool HELM, bool BIG, bool CHK>
+__device__ __forceinline__ void near_pair_grad(double x, double y, double z, double sx, double sy, double sz,
+                                               float2 uu, float &ar0, float &ai0, float &ar1, float &ai1,
+                                               float &ar2, float &ai2) {
+    const float dx = (float)(x - sx), dy = (float)(y - sy), dz = (float)(z - sz);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float inv = __builtin_amdgcn_rsqf(r2);
+    if (CHK) inv = r2 > 0.f ? inv : 0.f;
+    const float i3 = inv * inv * inv;
+    const float f0 = i3 * dx, f1 = i3 * dy, f2 = i3 * dz;
+    if (HELM) {
+        const float rr = r2 * inv;
+        float sn, cs;
+        sincos_rev(BIG ? __builtin_amdgcn_fractf(rr) : rr, sn, cs);
+        const float kr = 6.2831853f * rr;
+        const float hr = fmaf(-kr, sn, -cs), hi = fmaf(kr, cs, -sn);
+        float gr = f0 * hr, gi = f0 * hi;
+        ar0 = fmaf(gr, uu.x, fmaf(-gi, uu.y, ar0));
+        ai0 = fmaf(gr, uu.y, fmaf(gi, uu.x, ai0));
+        gr = f1 * hr;
+        gi = f1 * hi;
+        ar1 = fmaf(gr, uu.x, fmaf(-gi, uu.y, ar1));
+        ai1 = fmaf(gr, uu.y, fmaf(gi, uu.x, ai1));
+        gr = f2 * hr;
+        gi = f2 * hi;
+        ar2 = fmaf(gr, uu.x, fmaf(-gi, uu.y, ar2));
+        ai2 = fmaf(gr, uu.y, fmaf(gi, uu.x, ai2));
+    } else {
+        ar0 = fmaf(-f0, uu.x, ar0);
+        ai0 = fmaf(-f0, uu.y, ai0);
+        ar1 = fmaf(-f1, uu.x, ar1);
+        ai1 = fmaf(-f1, uu.y, ai1);
+        ar2 = fmaf(-f2, uu.x, ar2);
+        ai2 = fmaf(-f2, uu.y, ai2);
+    }
+}
+
+// steps staged sources from slot base against the lane's T targets, three components each
+template <bool HELM, bool BIG, bool CHK, int T>
+__device__ __forceinline__ void near_range_grad(const NearSmem &sm, int base, int steps, const double (&x)[T],
+                                                const double (&y)[T], const double (&z)[T], float (&ar)[3][T],
+                                                float (&ai)[3][T]) {
+    for (int q = 0; q < steps; ++q) {
+        const int s = base + q;
+        const double sx = sm.x[s], sy = sm.y[s], sz = sm.z[s];
+        const float2 uu = sm.u[s];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            near_pair_grad<HELM, BIG, CHK>(x[t], y[t], z[t], sx, sy, sz, uu, ar[0][t], ai[0][t], ar[1][t], ai[1][t],
+                                           ar[2][t], ai[2][t]);
+    }
+}
+
+// One pass of the gradient near field: the lanes and sources of near_pass; component c of target i is added
+// to output plane c (d.v + c n_x).
+template <bool HELM, bool BIG, int T>
+__device__ __forceinline__ void near_pass_grad(const LDesc &d, NearSmem &sm, int t, int i0, int nt, double scale,
+                                               float uscale) {
+    const int lane = threadIdx.x;
+    const int g = __builtin_amdgcn_readfirstlane((nt + T - 1) / T), R = __builtin_amdgcn_readfirstlane(64 / g);
+    const int r = lane / g, gi = lane - r * g;
+    const bool valid = r < R;
+    const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
+    double x[T], y[T], z[T];
+    float ar[3][T], ai[3][T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int ti = gi + g * k;
+        x[k] = y[k] = z[k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ar[c][k] = ai[c][k] = 0.f;
+        if (valid && ti < nt) {
+            const int i = i0 + ti;
+            x[k] = (d.txs[i] - cx) * scale;
+            y[k] = (d.tys[i] - cy) * scale;
+            z[k] = (d.tzs[i] - cz) * scale;
+        }
+    }
+    const int64_t e0 = d.near_ptr[t], e1 = d.near_ptr[t + 1];
+    const bool same = d.same != 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
+        const int j0 = __builtin_amdgcn_readfirstlane(d.sstart[s]), j1 = __builtin_amdgcn_readfirstlane(d.sstart[s + 1]);
+        const bool chk = !same || s == t;
+        for (int c0 = j0; c0 < j1; c0 += 64) {
+            const int cnt = min(64, j1 - c0);
+            const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
+            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale, nullptr);
+            const int base = valid ? r * so : 0;     // idle lanes read staged slots and discard their sums
+            if (chk)
+                near_range_grad<HELM, BIG, true, T>(sm, base, steps, x, y, z, ar, ai);
+            else
+                near_range_grad<HELM, BIG, false, T>(sm, base, steps, x, y, z, ar, ai);
+        }
+    }
+    // per component: the R partial sums of each target, added in order of r
+    float2 *part = reinterpret_cast<float2 *>(sm.x);   // [T][64], over x and y
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < T; ++k) part[k * 64 + lane] = make_float2(ar[c][k], ai[c][k]);
+        __syncthreads();
+        if (lane < g) {
+            float2 *vc = d.v + (int64_t)c * d.nx;
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const int ti = lane + g * k;
+                if (ti >= nt) break;
+                float2 a = part[k * 64 + lane];
+                for (int rr = 1; rr < R; ++rr) {
+                    const float2 b = part[k * 64 + lane + rr * g];
+                    a.x += b.x;
+                    a.y += b.y;
+                }
+                float2 o = vc[i0 + ti];
+                o.x += a.x;
+                o.y += a.y;
+                vc[i0 + ti] = o;
+            }
+        }
+    }
+}
+
+// The gradient at the targets, all three components in one pass over the near pairs.  Item (desc, target box).
+template <bool HELM, bool BIG>
+__global__ void __launch_bounds__(64)
+k_near_grad(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    __shared__ NearSmem sm;
+    const int t = wk.y;
+    const int ta = d.tstart[t], tz = d.tstart[t + 1];
+    const double kr = (double)d.k_rev;
+    const double scale = HELM ? kr : 1.0;
+    const float uscale = (float)((1.0 / (4.0 * M_PI)) * (HELM ? kr * kr : 1.0));
+    for (int i0 = ta; i0 < tz;) {
+        const NearPass ps = near_next_pass(tz - i0);
+        if (ps.T == 1)
+            near_pass_grad<HELM, BIG, 1>(d, sm, t, i0, ps.nt, scale, uscale);
+        else if (ps.T == 2)
+            near_pass_grad<HELM, BIG, 2>(d, sm, t, i0, ps.nt, scale, uscale);
+        else
+            near_pass_grad<HELM, BIG, 4>(d, sm, t, i0, ps.nt, scale, uscale);
+        i0 += ps.nt;
+    }
+}
+
 // ------------------------------------------------------------------ near field, one set (symmetric pairs)
 // Sources and targets one set: G(x, y) = G(y, x), so an unordered pair of distinct neighbour boxes {t, s} is
 // evaluated once, by the block of the lower box index: each pair's kernel value gives both v_i += G u_j (target
@@ -3223,6 +3374,9 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_NEAR_DN:
             threads = 64;
             return S.b ? (S.a ? k_near_dn<true, true> : k_near_dn<true, false>) : k_near_dn<false, false>;
+        case K_NEAR_GRAD:
+            threads = 64;
+            return S.b ? (S.a ? k_near_grad<true, true> : k_near_grad<true, false>) : k_near_grad<false, false>;
         case K_INTERP_DN: return k_lag_interp_dn;
         case K_BWD_PAIR_DN:
             if (S.a == 100) {
@@ -3416,6 +3570,7 @@ std::string kernel_name(int kern, int a, int b) {
         case K_NEAR_SYM: return "k_near_sym<" + tf(b) + ", " + tf(b && a) + ">";
         case K_NEAR_GATHER: return "k_near_gather";
         case K_NEAR_DN: return "k_near_dn<" + tf(b) + ", " + tf(b && a) + ">";
+        case K_NEAR_GRAD: return "k_near_grad<" + tf(b) + ", " + tf(b && a) + ">";
         case K_NEAR_DL: return "k_near_dl<" + tf(b) + ", " + tf(b && a) + ">";
         case K_INTERP_DN: return "k_lag_interp_dn";
         case K_BWD_PAIR_DN: return "k_pw_backward_dn<" + std::to_string(a == 100 ? 64 : 256) + ", " + tf(b) + ">";

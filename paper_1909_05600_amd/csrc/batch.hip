@@ -50,7 +50,7 @@ int stage_role(const Stage &S) {
         // after the levels: the near fields of the early lists and the leaf in level order (they add into the same
         // outputs), the symmetric pairs' source-side sums, then the output permutation
         case K_ZERO_OUT: return 0;
-        case K_NEAR: case K_NEAR_DN: case K_NEAR_DL: case K_NEAR_SYM: return 1 + S.level;
+        case K_NEAR: case K_NEAR_DN: case K_NEAR_DL: case K_NEAR_SYM: case K_NEAR_GRAD: return 1 + S.level;
         case K_NEAR_GATHER: return 1 + kMaxLev + 1;
         case K_PERM_OUT: return 1 + kMaxLev + 2;
         default: throw Error(FFM_EINTERNAL, "stage without a batch order");

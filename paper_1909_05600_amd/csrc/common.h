@@ -270,7 +270,8 @@ enum Kern {
     K_PERM_IN = 0, K_AMAX, K_FWD_PAIR, K_FWD_RING, K_SUM, K_TRANSFER, K_BWD_PAIR, K_BWD_RING,
     K_ANTERP, K_MFMA32, K_MFMA16, K_INTERP, K_NEAR, K_PERM_OUT, K_ZERO_OUT, K_BSUM,
     K_GSPREAD, K_GZ, K_GPHI, K_GPHIT, K_GZT, K_GINTERP, K_ACA, K_NEAR_DN, K_BWD_PAIR_DN, K_INTERP_DN,
-    K_NEAR_SYM, K_NEAR_GATHER, K_NEAR_DL, K_ANTERP_DL, K_FWD_PAIR_DL, K_DIRSCALE, K_DNCOMBINE, K_DLCOMBINE
+    K_NEAR_SYM, K_NEAR_GATHER, K_NEAR_DL, K_ANTERP_DL, K_FWD_PAIR_DL, K_DIRSCALE, K_DNCOMBINE, K_DLCOMBINE,
+    K_NEAR_GRAD
 };
 
 struct Stage {

@@ -2358,7 +2358,7 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         auto big = [&](int l) {
             return nhelm && P.k / (2.0 * M_PI) * 4.0 * std::sqrt(3.0) * std::ldexp(P.d0, -l) > 128.0 ? 1 : 0;
         };
-        const int near_kern = P.dn || P.grad ? K_NEAR_DN : (P.dl ? K_NEAR_DL : K_NEAR);
+        const int near_kern = P.grad ? K_NEAR_GRAD : (P.dn ? K_NEAR_DN : (P.dl ? K_NEAR_DL : K_NEAR));
         // near pairs the per-pair rule stopped above the leaf: the same kernel over each level's early list
         for (int l = 1; l < P.leaf; ++l) {
             if (P.lev[l].h_early.empty()) continue;
@@ -2377,8 +2377,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
     }
     // gradient plans: each level's target side (from its first target-transform stage on) once more for components
     // 1 and 2, over their own descriptors (items pointing at descriptor k + c (leaf + 1)) and after component 0's
-    // (a batch orders them by role: they share the level's target workspace); the near field's stages likewise,
-    // each right after itself (they share nothing).  Component 2's copies close the original timing slots.
+    // (a batch orders them by role: they share the level's target workspace); component 2's copies close the
+    // original timing slots.  The near field (k_near_grad) writes all three components in one pass.
     // Split normal derivative: at the levels with a k_dir_scale stage, the target side three times over the axis
     // descriptors (sets 1 to 3, into the axis planes), then k_dn_combine, which closes the original slot.
     constexpr int kRoleComp = 4096;
@@ -2401,20 +2401,6 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
             for (int c = 0; c < 3; ++c)
                 for (const Stage &S : tail) v.push_back(copy(S, c, c == 2));
         }
-        std::vector<Stage> out;
-        for (Stage &S : P.post) {
-            if (S.kern != K_NEAR_DN) {
-                out.push_back(std::move(S));
-                continue;
-            }
-            const Stage orig = S;
-            for (int c = 0; c < 3; ++c) {
-                Stage C = copy(orig, c, c == 2);
-                C.role_add = orig.role_add;      // independent output planes: merging with the original is safe
-                out.push_back(std::move(C));
-            }
-        }
-        P.post = std::move(out);
     }
     if (P.dlsplit) {
         // split double layer: at the levels whose source side is the grid or the ring-pair form, the source stages

@@ -149,6 +149,7 @@ def test_kernel_names_and_launch_timing_validation(L):
     assert ffm.FFM_LAPLACE_GRAD == 6 and ffm.FFM_HELMHOLTZ_GRAD == 7
     assert ffm.kernel_name(28, 1, 1) == "k_near_dl<true, true>"
     assert ffm.kernel_name(29) == "k_lag_anterp_dl"
+    assert ffm.kernel_name(34, 0, 1) == "k_near_grad<true, false>"
     assert ffm.kernel_name(30, 101, 0) == "k_pw_forward_dl<1, 64, false>"
     assert ffm.kernel_name(30, 4, 1) == "k_pw_forward_dl<4, 256, true>"
     buf = C.create_string_buffer(6)
