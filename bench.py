@@ -62,7 +62,12 @@ NEAR_SLOTS = {"k_near<false": 11.0, "k_near<true": 16.0}
 
 
 def near_model(name, table):
-    """The entry of a near-field table for a kernel symbol (its first template argument names the kernel)."""
+    """The entry of a near-field table for a kernel symbol (its first template argument names the kernel; the
+    symmetric derivative pass k_near_sym_d<HELM, BIG, NRM> counts as the ordered kernel it replaces)."""
+    if name.startswith("k_near_sym_d<"):
+        args = [a.strip() for a in name[len("k_near_sym_d<"):].rstrip(">").split(",")]
+        base = {"1": "k_near_dn<", "2": "k_near_dl<", "3": "k_near_grad<"}.get(args[-1])
+        return table.get(base + args[0]) if base else None
     for key, v in table.items():
         if name.startswith(key + ",") or name.startswith(key + ">"):
             return v

@@ -2714,11 +2714,13 @@ struct NearSmem {
 
 // Stage the chunk's sources c0 ... c0 + cnt - 1 (relative to the target centre, scaled) for R lane rows of
 // `steps` sources each: source jj at slot (jj / steps) * so + jj % steps, zero sources in the slots of
-// cnt <= jj < R * steps (at most 127).  d.two_over_dl is 2 / d_l of the descriptor's level.  With snm (the
-// double layer) the negated source normals go to snm[slot]: n_y . grad_y G(x - y) = (-n_y) . grad_x G(x - y).
+// cnt <= jj < R * steps (at most 127).  d.two_over_dl is 2 / d_l of the descriptor's level.  With snm, the
+// source normals nsrc[j] times nsign go to snm[slot] (the double layer stages the negated source normals:
+// n_y . grad_y G(x - y) = (-n_y) . grad_x G(x - y)).
 __device__ __forceinline__ void near_stage_chunk(const LDesc &d, NearSmem &sm, int c0, int cnt, int R, int steps,
                                                  int so, double cx, double cy, double cz, double scale,
-                                                 float uscale, float4 *snm) {
+                                                 float uscale, float4 *snm, const float4 *nsrc = nullptr,
+                                                 float nsign = -1.f) {
     const int lane = threadIdx.x;
     // zero sources sit at (2, 2, 2) d_l from the target centre: no target is there (each lies within d_l / 2 of
     // its centre on every axis), so every pair with them has r > 0 and adds exactly zero, and their phases stay
@@ -2740,8 +2742,8 @@ __device__ __forceinline__ void near_stage_chunk(const LDesc &d, NearSmem &sm, i
                 const float2 uu = d.u[j];
                 sm.u[slot] = make_float2(uu.x * uscale, uu.y * uscale);
                 if (snm) {
-                    const float4 n = d.sn[j];
-                    snm[slot] = make_float4(-n.x, -n.y, -n.z, 0.f);
+                    const float4 n = nsrc[j];
+                    snm[slot] = make_float4(nsign * n.x, nsign * n.y, nsign * n.z, 0.f);
                 }
             } else {
                 sm.x[slot] = sm.y[slot] = sm.z[slot] = pad;   // padding: zero sources
@@ -2864,7 +2866,7 @@ __device__ __forceinline__ void near_pass(const LDesc &d, NearSmem &sm, float4 *
         for (int c0 = j0; c0 < j1; c0 += 64) {
             const int cnt = min(64, j1 - c0);
             const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
-            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale, NRM == 2 ? snm : nullptr);
+            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale, NRM == 2 ? snm : nullptr, d.sn);
             const int base = valid ? r * so : 0;     // idle lanes read staged slots and discard their sums
             if (chk)
                 near_range<HELM, NRM, BIG, true, T>(sm, snm, base, steps, x, y, z, nx, ny, nz, are, aim);
@@ -3267,6 +3269,236 @@ k_near_sym(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
     }
 }
 
+// The symmetric pairs of the derivative kernels (one set), NRM 1: the normal derivative at the targets, 2: at the
+// sources, 3: the gradient.  With d = x_i - x_j, grad_x G(x_i - x_j) = d h(r) and grad_x G(x_j - x_i) = -d h(r):
+//   NRM 1: target i gets (n_i . d) h u_j, source j gets -(n_j . d) h u_i;
+//   NRM 2: target i gets -(n_j . d) h u_j, source j gets (n_i . d) h u_i (the staged normals are -n_j);
+//   NRM 3: target i gets d h u_j, source j gets -d h u_i (three components).
+// h = -1 / r^3 (Laplace), (ikr - 1) e^{ikr} / r^3 (Helmholtz), in the scaled units of the ordered kernels.
+template <bool HELM, bool BIG, int NRM, int NC>
+__device__ __forceinline__ void near_pair_symd(double x, double y, double z, float tnx, float tny, float tnz,
+                                               float2 ut, double sx, double sy, double sz, float4 sn, float2 us,
+                                               float (&are)[NC], float (&aim)[NC], float (&sre)[NC],
+                                               float (&sim)[NC]) {
+    const float dx = (float)(x - sx), dy = (float)(y - sy), dz = (float)(z - sz);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float inv = __builtin_amdgcn_rsqf(r2);   // distinct boxes of one set, padding far away: r > 0
+    const float i3 = inv * inv * inv;
+    float hr = -1.f, hi = 0.f;
+    if (HELM) {
+        const float rr = r2 * inv;
+        float sn_, cs;
+        sincos_rev(BIG ? __builtin_amdgcn_fractf(rr) : rr, sn_, cs);
+        const float kr = 6.2831853f * rr;
+        hr = fmaf(-kr, sn_, -cs);
+        hi = fmaf(kr, cs, -sn_);
+    }
+    if (NRM == 3) {
+        const float dd[3] = {dx, dy, dz};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const float f = i3 * dd[c];
+            if (HELM) {
+                const float gr = f * hr, gi = f * hi;
+                are[c] = fmaf(gr, us.x, fmaf(-gi, us.y, are[c]));
+                aim[c] = fmaf(gr, us.y, fmaf(gi, us.x, aim[c]));
+                sre[c] = fmaf(-gr, ut.x, fmaf(gi, ut.y, sre[c]));
+                sim[c] = fmaf(-gr, ut.y, fmaf(-gi, ut.x, sim[c]));
+            } else {
+                are[c] = fmaf(-f, us.x, are[c]);
+                aim[c] = fmaf(-f, us.y, aim[c]);
+                sre[c] = fmaf(f, ut.x, sre[c]);
+                sim[c] = fmaf(f, ut.y, sim[c]);
+            }
+        }
+    } else {
+        const float a = fmaf(tnx, dx, fmaf(tny, dy, tnz * dz));       // n_i . d
+        const float b = fmaf(sn.x, dx, fmaf(sn.y, dy, sn.z * dz));      // staged normal . d
+        const float ft = NRM == 1 ? i3 * a : i3 * b, fs = NRM == 1 ? -(i3 * b) : i3 * a;
+        if (HELM) {
+            float gr = ft * hr, gi = ft * hi;
+            are[0] = fmaf(gr, us.x, fmaf(-gi, us.y, are[0]));
+            aim[0] = fmaf(gr, us.y, fmaf(gi, us.x, aim[0]));
+            gr = fs * hr;
+            gi = fs * hi;
+            sre[0] = fmaf(gr, ut.x, fmaf(-gi, ut.y, sre[0]));
+            sim[0] = fmaf(gr, ut.y, fmaf(gi, ut.x, sim[0]));
+        } else {
+            are[0] = fmaf(-ft, us.x, are[0]);
+            aim[0] = fmaf(-ft, us.y, aim[0]);
+            sre[0] = fmaf(-fs, ut.x, sre[0]);
+            sim[0] = fmaf(-fs, ut.y, sim[0]);
+        }
+    }
+}
+
+// One pass of the symmetric derivative near field: the lanes, rows, lists and buffer of near_pass_sym; the
+// sources' normals are staged beside them (NRM 1: n_j, NRM 2: -n_j), and a gradient's three components have
+// their own accumulators, source-side sums, buffer planes (nsym + c nsymn) and output planes (v + c n_x).
+template <bool HELM, bool BIG, int NRM, int T>
+__device__ __forceinline__ void near_pass_symd(const LDesc &d, NearSmem &sm, float4 *snm, float2 (*sp12)[kNearSlots],
+                                               int t, int i0, int nt, bool first, double scale, float uscale) {
+    constexpr int g = 16, R = 4, NC = NRM == 3 ? 3 : 1;
+    const int lane = threadIdx.x;
+    const int r = lane >> 4, gi = lane & 15;
+    const bool last = gi == g - 1;
+    const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
+    const float4 *nrm = NRM == 1 ? d.tn : d.sn;   // one set: a target's normal is its source normal
+    double x[T], y[T], z[T];
+    float nx[T], ny[T], nz[T];
+    float are[NC][T], aim[NC][T];
+    float2 ut[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        // a slot past nt repeats target 0 with zero input: its source-side terms are zero, its own sums discarded
+        const int ti = gi + g * k;
+        const int i = i0 + (ti < nt ? ti : 0);
+        x[k] = (d.txs[i] - cx) * scale;
+        y[k] = (d.tys[i] - cy) * scale;
+        z[k] = (d.tzs[i] - cz) * scale;
+        nx[k] = ny[k] = nz[k] = 0.f;
+        if (NRM != 3) {
+            const float4 n = nrm[i];
+            nx[k] = n.x;
+            ny[k] = n.y;
+            nz[k] = n.z;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) are[c][k] = aim[c][k] = 0.f;
+        const float2 uu = d.u[i];
+        ut[k] = ti < nt ? make_float2(uu.x * uscale, uu.y * uscale) : make_float2(0.f, 0.f);
+    }
+    const int64_t e0 = d.near_ptr[t], e1 = d.near_ptr[t + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+        const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
+        const int64_t off = d.near_off[e];
+        if (s < t && off >= 0) continue;          // the block of box s evaluates this pair of boxes
+        const int j0 = __builtin_amdgcn_readfirstlane(d.sstart[s]), j1 = __builtin_amdgcn_readfirstlane(d.sstart[s + 1]);
+        for (int c0 = j0; c0 < j1; c0 += 64) {
+            const int cnt = min(64, j1 - c0);
+            const int steps = __builtin_amdgcn_readfirstlane((cnt + R - 1) / R), so = steps | 1;
+            near_stage_chunk(d, sm, c0, cnt, R, steps, so, cx, cy, cz, scale, uscale, NRM == 3 ? nullptr : snm,
+                             nrm, NRM == 1 ? 1.f : -1.f);
+            const int base = r * so;
+            if (s <= t) {
+                // the box itself (r > 0 test) and lower neighbours without a reverse entry: ordered pairs
+                if constexpr (NRM == 3) {
+                    if (s == t)
+                        near_range_grad<HELM, BIG, true, T>(sm, base, steps, x, y, z, are, aim);
+                    else
+                        near_range_grad<HELM, BIG, false, T>(sm, base, steps, x, y, z, are, aim);
+                } else {
+                    if (s == t)
+                        near_range<HELM, NRM, BIG, true, T>(sm, snm, base, steps, x, y, z, nx, ny, nz, are[0], aim[0]);
+                    else
+                        near_range<HELM, NRM, BIG, false, T>(sm, snm, base, steps, x, y, z, nx, ny, nz, are[0], aim[0]);
+                }
+            } else {
+                const int jb = r * steps;
+                for (int q = 0; q < steps; ++q) {
+                    const int sl = base + q;
+                    const double sx = sm.x[sl], sy = sm.y[sl], sz = sm.z[sl];
+                    const float2 us = sm.u[sl];
+                    const float4 sn = NRM == 3 ? make_float4(0.f, 0.f, 0.f, 0.f) : snm[sl];
+                    float sre[NC], sim[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sre[c] = sim[c] = 0.f;
+#pragma unroll
+                    for (int k = 0; k < T; ++k) {
+                        float ar[NC], ai[NC];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            ar[c] = are[c][k];
+                            ai[c] = aim[c][k];
+                        }
+                        near_pair_symd<HELM, BIG, NRM, NC>(x[k], y[k], z[k], nx[k], ny[k], nz[k], ut[k], sx, sy, sz,
+                                                           sn, us, ar, ai, sre, sim);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            are[c][k] = ar[c];
+                            aim[c][k] = ai[c];
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const float a = row_sum16(sre[c]), b = row_sum16(sim[c]);
+                        if (last) (c == 0 ? sm.sp : sp12[c - 1])[jb + q] = make_float2(a, b);
+                    }
+                }
+                __syncthreads();
+                if (lane < cnt) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        float2 *o = d.nsym + (int64_t)c * d.nsymn + off + (c0 - j0) + lane;
+                        float2 a = (c == 0 ? sm.sp : sp12[c - 1])[lane];
+                        if (!first) {
+                            const float2 b = *o;
+                            a.x += b.x;
+                            a.y += b.y;
+                        }
+                        *o = a;
+                    }
+                }
+            }
+        }
+    }
+    float2 *part = reinterpret_cast<float2 *>(sm.x);   // [T][64] over x, y, z and u (T <= 5)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < T; ++k) part[k * 64 + lane] = make_float2(are[c][k], aim[c][k]);
+        __syncthreads();
+        if (lane < g) {
+            float2 *vc = d.v + (int64_t)c * d.nx;
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const int ti = lane + g * k;
+                if (ti >= nt) break;
+                float2 a = part[k * 64 + lane];
+#pragma unroll
+                for (int rr = 1; rr < R; ++rr) {
+                    const float2 b = part[k * 64 + lane + rr * g];
+                    a.x += b.x;
+                    a.y += b.y;
+                }
+                float2 o = vc[i0 + ti];
+                o.x += a.x;
+                o.y += a.y;
+                vc[i0 + ti] = o;
+            }
+        }
+    }
+}
+
+template <bool HELM, bool BIG, int NRM>
+__global__ void __launch_bounds__(64)
+k_near_sym_d(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const int4 *__restrict__ work) {
+    __shared__ NearSmem sm;
+    __shared__ float4 snm[NRM == 3 ? 1 : kNearSlots];
+    __shared__ float2 sp12[NRM == 3 ? 2 : 1][kNearSlots];
+    const int4 wk = work[blockIdx.x];
+    const LDesc &d = descs[wk.x];
+    const int t = wk.y;
+    const int ta = d.tstart[t], tz = d.tstart[t + 1];
+    const double kr = (double)d.k_rev;
+    const double scale = HELM ? kr : 1.0;
+    const float uscale = (float)((1.0 / (4.0 * M_PI)) * (HELM ? kr * kr : 1.0));
+    for (int i0 = ta; i0 < tz;) {
+        const int nt = min(80, tz - i0);
+        const int T = (nt + 15) >> 4;
+        const bool first = i0 == ta;
+        switch (T) {
+            case 1: near_pass_symd<HELM, BIG, NRM, 1>(d, sm, snm, sp12, t, i0, nt, first, scale, uscale); break;
+            case 2: near_pass_symd<HELM, BIG, NRM, 2>(d, sm, snm, sp12, t, i0, nt, first, scale, uscale); break;
+            case 3: near_pass_symd<HELM, BIG, NRM, 3>(d, sm, snm, sp12, t, i0, nt, first, scale, uscale); break;
+            case 4: near_pass_symd<HELM, BIG, NRM, 4>(d, sm, snm, sp12, t, i0, nt, first, scale, uscale); break;
+            default: near_pass_symd<HELM, BIG, NRM, 5>(d, sm, snm, sp12, t, i0, nt, first, scale, uscale); break;
+        }
+        i0 += nt;
+    }
+}
+
 // v_i += the source-side sums that lower neighbour boxes computed for box b's points (list order).  Item
 // (desc, box b).
 __global__ void __launch_bounds__(64)
@@ -3276,21 +3508,25 @@ k_near_gather(const LDesc *__restrict__ descs, const IoEntry *__restrict__, cons
     const int b = wk.y;
     const int ta = d.tstart[b], tz = d.tstart[b + 1];
     const int64_t e0 = d.near_ptr[b], e1 = d.near_ptr[b + 1];
-    for (int i = ta + (int)threadIdx.x; i < tz; i += 64) {
-        float2 a = make_float2(0.f, 0.f);
-        for (int64_t e = e0; e < e1; ++e) {
-            const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
-            const int64_t off = d.near_off[e];
-            if (s < b && off >= 0) {
-                const float2 w = d.nsym[off + (i - ta)];
-                a.x += w.x;
-                a.y += w.y;
+    for (int c = 0; c < d.ncomp; ++c) {
+        const float2 *ns = d.nsym + (int64_t)c * d.nsymn;
+        float2 *vc = d.v + (int64_t)c * d.nx;
+        for (int i = ta + (int)threadIdx.x; i < tz; i += 64) {
+            float2 a = make_float2(0.f, 0.f);
+            for (int64_t e = e0; e < e1; ++e) {
+                const int s = __builtin_amdgcn_readfirstlane(d.near_src[e]);
+                const int64_t off = d.near_off[e];
+                if (s < b && off >= 0) {
+                    const float2 w = ns[off + (i - ta)];
+                    a.x += w.x;
+                    a.y += w.y;
+                }
             }
+            float2 o = vc[i];
+            o.x += a.x;
+            o.y += a.y;
+            vc[i] = o;
         }
-        float2 o = d.v[i];
-        o.x += a.x;
-        o.y += a.y;
-        d.v[i] = o;
     }
 }
 
@@ -3365,8 +3601,22 @@ KernelFn kernel_of(const Stage &S, int &threads) {
         case K_INTERP: return k_lag_interp;
         case K_NEAR: threads = 64; return S.b ? (S.a ? k_near<true, true> : k_near<true, false>) : k_near<false, false>;
         case K_NEAR_SYM:
+            // a = BIG + 2 NRM (NRM 0: the kernel itself, 1: normal derivative at the targets, 2: at the sources,
+            // 3: the gradient)
             threads = 64;
-            return S.b ? (S.a ? k_near_sym<true, true> : k_near_sym<true, false>) : k_near_sym<false, false>;
+            switch (S.a >> 1) {
+                case 1:
+                    return S.b ? ((S.a & 1) ? k_near_sym_d<true, true, 1> : k_near_sym_d<true, false, 1>)
+                               : k_near_sym_d<false, false, 1>;
+                case 2:
+                    return S.b ? ((S.a & 1) ? k_near_sym_d<true, true, 2> : k_near_sym_d<true, false, 2>)
+                               : k_near_sym_d<false, false, 2>;
+                case 3:
+                    return S.b ? ((S.a & 1) ? k_near_sym_d<true, true, 3> : k_near_sym_d<true, false, 3>)
+                               : k_near_sym_d<false, false, 3>;
+                default:
+                    return S.b ? ((S.a & 1) ? k_near_sym<true, true> : k_near_sym<true, false>) : k_near_sym<false, false>;
+            }
         case K_NEAR_GATHER: threads = 64; return k_near_gather;
         case K_NEAR_DL:
             threads = 64;
@@ -3567,7 +3817,10 @@ std::string kernel_name(int kern, int a, int b) {
         case K_ACA: return "k_lag_aca";
         case K_INTERP: return "k_lag_interp";
         case K_NEAR: return "k_near<" + tf(b) + ", " + tf(b && a) + ">";
-        case K_NEAR_SYM: return "k_near_sym<" + tf(b) + ", " + tf(b && a) + ">";
+        case K_NEAR_SYM:
+            if (a >> 1)
+                return "k_near_sym_d<" + tf(b) + ", " + tf(b && (a & 1)) + ", " + std::to_string(a >> 1) + ">";
+            return "k_near_sym<" + tf(b) + ", " + tf(b && a) + ">";
         case K_NEAR_GATHER: return "k_near_gather";
         case K_NEAR_DN: return "k_near_dn<" + tf(b) + ", " + tf(b && a) + ">";
         case K_NEAR_GRAD: return "k_near_grad<" + tf(b) + ", " + tf(b && a) + ">";

@@ -212,6 +212,7 @@ struct LDesc {
                                            // source-side sums in nsym (s > t), or of the reverse entry's (s < t
                                            // with a reverse entry), else -1
     float2 *nsym;                          // source-side sums of the symmetric near pairs
+    int64_t nsymn;                         // entries of one component's plane of nsym (gradients: three planes)
     const int32_t *tr_tgt;                 // target boxes of the transfers, in Morton order
     int ntr, ncls;                         // their number; translation classes
     const int32_t *sib_tgt, *sib_src, *sib_cnt;   // transfers by sibling group (Level::sib_*)

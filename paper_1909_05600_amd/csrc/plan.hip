@@ -1489,7 +1489,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     }
     // one set: the leaf near field evaluates each unordered pair of distinct boxes once (G is symmetric; the
     // normal derivatives are not)
-    P.near_sym = P.same && !P.dn && !P.dl && !P.grad;
+    P.near_sym = P.same;
     fetch_work_lists(P.lev[P.leaf], TX.lev[P.leaf], TY.lev[P.leaf], true, st, SC, wf_near, P.near_sym);
     int32_t *used_h = SC.pin<int32_t>((size_t)kWin3 * (P.leaf + 1) + 1);
     for (int l = 1; l <= P.leaf; ++l)
@@ -1838,7 +1838,7 @@ void plan_build(Plan &P, const double *X, const double *Y, hipStream_t st) {
     build_work_lists(P, P.lev[P.leaf], true, wf_near);
     P.nsym = wf_near.sym_tot ? wf_near.sym_tot[0] : 0;
     if (!wf_near.sym_tot) P.near_sym = false;
-    P.wnsym.alloc((size_t)std::max<int64_t>(P.nsym, 0));
+    P.wnsym.alloc((size_t)std::max<int64_t>(P.nsym, 0) * P.ncomp());
     for (int l = 1; l < P.leaf; ++l)
         if (P.lev[l].nearly) build_early_lists(P.lev[l], wf_early[l]);
     (void)ws_part;
@@ -2368,7 +2368,8 @@ void plan_stages(Plan &P, const Tune &tu, hipStream_t st, Scratch *keep) {
         }
         if (P.near_sym) {
             std::vector<int4> ga = nr;
-            P.post.push_back(make_stage(K_NEAR_SYM, big(P.leaf), nhelm, -1, P.leaf, 0, std::move(nr), st, SC));
+            const int nrm = P.grad ? 3 : (P.dn ? 1 : (P.dl ? 2 : 0));
+            P.post.push_back(make_stage(K_NEAR_SYM, big(P.leaf) + 2 * nrm, nhelm, -1, P.leaf, 0, std::move(nr), st, SC));
             P.post.push_back(make_stage(K_NEAR_GATHER, 0, 0, 61, P.leaf, 0, std::move(ga), st, SC));
         } else {
             P.post.push_back(make_stage(near_kern, big(P.leaf), nhelm, 61, P.leaf, 0, std::move(nr), st, SC));
@@ -2525,6 +2526,7 @@ LDesc make_desc(const Plan &P, int l, int inst, float2 *u, float2 *v, float *ama
     d.near_src = early ? LV.early_src.p : LV.near_src.p;
     d.near_off = l == P.leaf && P.near_sym ? LV.near_off.p : nullptr;
     d.nsym = l == P.leaf && P.near_sym ? w.nsym : nullptr;
+    d.nsymn = P.nsym;
     d.dirs = LV.dirs.p;
     d.dirs64 = LV.dirs64.p;
     d.rings = LV.rings.p;
