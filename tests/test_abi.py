@@ -150,6 +150,9 @@ def test_kernel_names_and_launch_timing_validation(L):
     assert ffm.kernel_name(28, 1, 1) == "k_near_dl<true, true>"
     assert ffm.kernel_name(29) == "k_lag_anterp_dl"
     assert ffm.kernel_name(34, 0, 1) == "k_near_grad<true, false>"
+    assert ffm.kernel_name(26, 0, 1) == "k_near_sym<true, false>"
+    assert ffm.kernel_name(26, 7, 1) == "k_near_sym_d<true, true, 3>"
+    assert ffm.kernel_name(26, 2, 0) == "k_near_sym_d<false, false, 1>"
     assert ffm.kernel_name(30, 101, 0) == "k_pw_forward_dl<1, 64, false>"
     assert ffm.kernel_name(30, 4, 1) == "k_pw_forward_dl<4, 256, true>"
     buf = C.create_string_buffer(6)
