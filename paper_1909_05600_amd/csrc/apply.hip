@@ -2552,51 +2552,64 @@ k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
     }
 }
 
-template <bool DN>
-__device__ __forceinline__ void lag_interp_body(const LDesc &d, const int4 wk) {
-    extern __shared__ float2 vt[];   // [r]
-    __shared__ float nodes[kMaxR1], den[kMaxR1];
+// R1 nodes per axis (a compile-time constant, so the basis arrays stay in registers with constant indices).
+// v~_t = sum_{e in far(t)} Z_e in list order; the loads of eight entries are issued before their additions.
+template <bool DN, int R1>
+__device__ __forceinline__ void lag_interp_r1(const LDesc &d, const int4 wk, float2 *vt, const float *nodes,
+                                              const float *den) {
+    constexpr int r = R1 * R1 * R1;
     const int t = wk.y;
     const int tid = threadIdx.x;
-    const int r1 = d.r1, rp = d.rp, r = r1 * r1 * r1;
+    const int rp = d.rp;
     const double two_over_dl = d.two_over_dl;
-    if (tid < r1) {
-        nodes[tid] = d.lnodes[tid];
-        den[tid] = d.lden[tid];
-    }
     const int64_t e0 = d.far_ptr[t], e1 = d.far_ptr[t + 1];
+    const gc2 Z = gl(d.Z);
     for (int i = tid; i < r; i += kThreads) {
-        float2 a = make_float2(0.f, 0.f);
-        for (int64_t e = e0; e < e1; ++e) {
-            const float2 z = d.Z[e * rp + i];
-            a.x += z.x;
-            a.y += z.y;
+        float ax = 0.f, ay = 0.f;
+        int64_t e = e0;
+        for (; e + 8 <= e1; e += 8) {
+            v2f z[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) z[u] = Z[(e + u) * rp + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                ax += z[u].x;
+                ay += z[u].y;
+            }
         }
-        vt[i] = a;
+        for (; e < e1; ++e) {
+            const v2f z = Z[e * rp + i];
+            ax += z.x;
+            ay += z.y;
+        }
+        vt[i] = make_float2(ax, ay);
     }
     __syncthreads();
     const double cx = d.tctr[3 * t], cy = d.tctr[3 * t + 1], cz = d.tctr[3 * t + 2];
     for (int i = d.tstart[t] + tid; i < d.tstart[t + 1]; i += kThreads) {
-        float lx[kMaxR1], ly[kMaxR1], lz[kMaxR1];
+        float lx[R1], ly[R1], lz[R1];
         const float tx = (float)((d.txs[i] - cx) * two_over_dl), ty = (float)((d.tys[i] - cy) * two_over_dl);
         const float tz = (float)((d.tzs[i] - cz) * two_over_dl);
-        lagrange_1d(tx, r1, nodes, den, lx);
-        lagrange_1d(ty, r1, nodes, den, ly);
-        lagrange_1d(tz, r1, nodes, den, lz);
+        lagrange_1d(tx, R1, nodes, den, lx);
+        lagrange_1d(ty, R1, nodes, den, ly);
+        lagrange_1d(tz, R1, nodes, den, lz);
         float sre = 0.f, sim = 0.f;
         if (DN) {
             // n . grad of the interpolant: (2 / d_l) (n_x l'_a l_b l_c + n_y l_a l'_b l_c + n_z l_a l_b l'_c) v~
-            float dx[kMaxR1], dy[kMaxR1], dz[kMaxR1];
-            lagrange_1d_deriv(tx, r1, nodes, den, dx);
-            lagrange_1d_deriv(ty, r1, nodes, den, dy);
-            lagrange_1d_deriv(tz, r1, nodes, den, dz);
+            float dx[R1], dy[R1], dz[R1];
+            lagrange_1d_deriv(tx, R1, nodes, den, dx);
+            lagrange_1d_deriv(ty, R1, nodes, den, dy);
+            lagrange_1d_deriv(tz, R1, nodes, den, dz);
             const float4 n = d.tn ? d.tn[i] : d.tnc;
-            for (int a = 0; a < r1; ++a) {
+#pragma unroll
+            for (int a = 0; a < R1; ++a) {
                 float b0r = 0.f, b0i = 0.f, b1r = 0.f, b1i = 0.f;
-                for (int bb = 0; bb < r1; ++bb) {
+#pragma unroll
+                for (int bb = 0; bb < R1; ++bb) {
                     float c0r = 0.f, c0i = 0.f, c1r = 0.f, c1i = 0.f;
-                    const float2 *row = vt + (a * r1 + bb) * r1;
-                    for (int c = 0; c < r1; ++c) {
+                    const float2 *row = vt + (a * R1 + bb) * R1;
+#pragma unroll
+                    for (int c = 0; c < R1; ++c) {
                         c0r = fmaf(lz[c], row[c].x, c0r);
                         c0i = fmaf(lz[c], row[c].y, c0i);
                         c1r = fmaf(dz[c], row[c].x, c1r);
@@ -2614,12 +2627,15 @@ __device__ __forceinline__ void lag_interp_body(const LDesc &d, const int4 wk) {
             sre *= f;
             sim *= f;
         } else {
-            for (int a = 0; a < r1; ++a) {
+#pragma unroll
+            for (int a = 0; a < R1; ++a) {
                 float bre = 0.f, bim = 0.f;
-                for (int bb = 0; bb < r1; ++bb) {
+#pragma unroll
+                for (int bb = 0; bb < R1; ++bb) {
                     float cre = 0.f, cim = 0.f;
-                    const float2 *row = vt + (a * r1 + bb) * r1;
-                    for (int c = 0; c < r1; ++c) {
+                    const float2 *row = vt + (a * R1 + bb) * R1;
+#pragma unroll
+                    for (int c = 0; c < R1; ++c) {
                         cre = fmaf(lz[c], row[c].x, cre);
                         cim = fmaf(lz[c], row[c].y, cim);
                     }
@@ -2634,6 +2650,28 @@ __device__ __forceinline__ void lag_interp_body(const LDesc &d, const int4 wk) {
         o.x += sre;
         o.y += sim;
         d.v[i] = o;
+    }
+}
+
+template <bool DN>
+__device__ __forceinline__ void lag_interp_body(const LDesc &d, const int4 wk) {
+    extern __shared__ float2 vt[];   // [r]
+    __shared__ float nodes[kMaxR1], den[kMaxR1];
+    const int tid = threadIdx.x;
+    if (tid < d.r1) {
+        nodes[tid] = d.lnodes[tid];
+        den[tid] = d.lden[tid];
+    }
+    // (the reduction into vt below does not read nodes or den; the barrier after it orders their writes)
+    switch (d.r1) {
+        case 1: lag_interp_r1<DN, 1>(d, wk, vt, nodes, den); break;
+        case 2: lag_interp_r1<DN, 2>(d, wk, vt, nodes, den); break;
+        case 3: lag_interp_r1<DN, 3>(d, wk, vt, nodes, den); break;
+        case 4: lag_interp_r1<DN, 4>(d, wk, vt, nodes, den); break;
+        case 5: lag_interp_r1<DN, 5>(d, wk, vt, nodes, den); break;
+        case 6: lag_interp_r1<DN, 6>(d, wk, vt, nodes, den); break;
+        case 7: lag_interp_r1<DN, 7>(d, wk, vt, nodes, den); break;
+        default: lag_interp_r1<DN, 8>(d, wk, vt, nodes, den); break;
     }
 }
 
