@@ -2126,20 +2126,19 @@ __device__ __forceinline__ void lagrange_1d_deriv(float t, int r1, const float *
 // With DL (the normal derivative at the sources) the weight of node (a, b, c) is n_j . grad_y of its polynomial:
 // (2 / d_l) (n_x l'_a l_b l_c + n_y l_a l'_b l_c + n_z l_a l_b l'_c); the staged derivative tables carry the
 // factors (2 / d_l) n.  Item (desc, source box).
-template <bool DL>
-__device__ __forceinline__ void lag_anterp_body(const LDesc &d, const int4 wk) {
+template <bool DL, int R1>
+__device__ __forceinline__ void lag_anterp_r1(const LDesc &d, const int4 wk, float (*ell)[(DL ? 6 : 3) * kMaxR1],
+                                              float2 *us, float *nodes, float *den) {
     const int b = wk.y;
     const int tid = threadIdx.x;
-    const int r1 = d.r1, rp = d.rp, r = r1 * r1 * r1;
+    constexpr int r1 = R1, r = R1 * R1 * R1;
+    const int rp = d.rp;
     const double two_over_dl = d.two_over_dl;
-    __shared__ float ell[kAnterpChunk][(DL ? 6 : 3) * kMaxR1];
-    __shared__ float2 us[kAnterpChunk];
-    __shared__ float nodes[kMaxR1], den[kMaxR1];
     if (tid < r1) {
         nodes[tid] = d.lnodes[tid];
         den[tid] = d.lden[tid];
     }
-    constexpr int kOut = (kMaxR1 * kMaxR1 * kMaxR1 + kThreads - 1) / kThreads;
+    constexpr int kOut = (r + kThreads - 1) / kThreads;
     float2 acc[kOut];
     int ia[kOut], ib[kOut], ic[kOut];
 #pragma unroll
@@ -2151,7 +2150,7 @@ __device__ __forceinline__ void lag_anterp_body(const LDesc &d, const int4 wk) {
         ib[o] = (ii / r1) % r1;
         ic[o] = ii % r1;
     }
-    const int nout = (r + kThreads - 1) / kThreads;
+    constexpr int nout = kOut;
     const double cx = d.sctr[3 * b], cy = d.sctr[3 * b + 1], cz = d.sctr[3 * b + 2];
     const int i0 = d.sstart[b], i1 = d.sstart[b + 1];
     for (int s0 = i0; s0 < i1; s0 += kAnterpChunk) {
@@ -2178,6 +2177,7 @@ __device__ __forceinline__ void lag_anterp_body(const LDesc &d, const int4 wk) {
             us[tid] = d.u[j];
         }
         __syncthreads();
+#pragma unroll 4
         for (int jj = 0; jj < cnt; ++jj) {
             const float2 uu = us[jj];
 #pragma unroll
@@ -2204,6 +2204,24 @@ __device__ __forceinline__ void lag_anterp_body(const LDesc &d, const int4 wk) {
         if (o < nout && i < rp) ut[i] = (i < r) ? acc[o] : make_float2(0.f, 0.f);
     }
     for (int i = r + tid; i < rp; i += kThreads) ut[i] = make_float2(0.f, 0.f);
+}
+
+template <bool DL>
+__device__ __forceinline__ void lag_anterp_body(const LDesc &d, const int4 wk) {
+    __shared__ float ell[kAnterpChunk][(DL ? 6 : 3) * kMaxR1];
+    __shared__ float2 us[kAnterpChunk];
+    __shared__ float nodes[kMaxR1], den[kMaxR1];
+    // the node count as a compile-time constant: the basis loops unroll and the outputs per thread are fixed
+    switch (d.r1) {
+        case 1: lag_anterp_r1<DL, 1>(d, wk, ell, us, nodes, den); break;
+        case 2: lag_anterp_r1<DL, 2>(d, wk, ell, us, nodes, den); break;
+        case 3: lag_anterp_r1<DL, 3>(d, wk, ell, us, nodes, den); break;
+        case 4: lag_anterp_r1<DL, 4>(d, wk, ell, us, nodes, den); break;
+        case 5: lag_anterp_r1<DL, 5>(d, wk, ell, us, nodes, den); break;
+        case 6: lag_anterp_r1<DL, 6>(d, wk, ell, us, nodes, den); break;
+        case 7: lag_anterp_r1<DL, 7>(d, wk, ell, us, nodes, den); break;
+        default: lag_anterp_r1<DL, 8>(d, wk, ell, us, nodes, den); break;
+    }
 }
 
 __global__ void __launch_bounds__(kThreads)
