@@ -2236,6 +2236,33 @@ k_lag_anterp_dl(const LDesc *__restrict__ descs, const IoEntry *__restrict__, co
     lag_anterp_body<true>(descs[wk.x], wk);
 }
 
+// U[k][2m + part] = part of u~_{s_m}[k] for the 16 pairs m of a class group (zero where the slot is empty): both
+// parts of an entry come from one 8-byte load, and each thread issues eight loads before it writes them to LDS.
+__device__ __forceinline__ void stage_group_sources(const float2 *ut2, const int *ps, int rp, float *U) {
+    const int nel = rp * 16, nth = blockDim.x, tid = threadIdx.x;
+    const gc2 src = gl(ut2);
+    for (int base = 0; base < nel; base += 8 * nth) {
+        v2f w[8];
+        int sm[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sm[u] = ps[(base + u * nth + tid) & 15];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * nth + tid, k = idx >> 4;
+            w[u] = v2f{0.f, 0.f};
+            if (idx < nel && sm[u] >= 0) w[u] = src[(int64_t)sm[u] * rp + k];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * nth + tid;
+            if (idx < nel) {
+                U[2 * idx] = w[u].x;
+                U[2 * idx + 1] = w[u].y;
+            }
+        }
+    }
+}
+
 // Transfer products of one class group on MFMA: Z_e = T_c u~_{s(e)} for up to 16 pairs e.
 // C (rp x 32) = T_c (rp x rp) x U (rp x 32), U[k][2m + part] = part of u~_{s(e_m)}[k].
 // v_mfma_f32_32x32x2f32 operands: A[i][k] from lane i + 32 k, B[k][j] from lane j + 32 k,
@@ -2256,15 +2283,7 @@ k_lag_mfma(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const i
         ps[tid] = e >= 0 ? d.far_src[e] : -1;
     }
     __syncthreads();
-    for (int idx = tid; idx < rp * 32; idx += blockDim.x) {
-        const int k = idx >> 5, col = idx & 31, m = col >> 1;
-        float val = 0.f;
-        if (ps[m] >= 0) {
-            const float2 w = d.ut2[(int64_t)ps[m] * rp + k];
-            val = (col & 1) ? w.y : w.x;
-        }
-        U[idx] = val;
-    }
+    stage_group_sources(d.ut2, ps, rp, U);
     __syncthreads();
     const int64_t per = (int64_t)rp * rp;
     const float *Tre = d.T + (int64_t)c * (helm ? 2 : 1) * per;
@@ -2345,15 +2364,7 @@ k_lag_aca(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const in
         ps[tid] = e >= 0 ? d.far_src[e] : -1;
     }
     __syncthreads();
-    for (int idx = tid; idx < rp * 32; idx += blockDim.x) {
-        const int k = idx >> 5, col = idx & 31, m = col >> 1;
-        float val = 0.f;
-        if (ps[m] >= 0) {
-            const float2 w = d.ut2[(int64_t)ps[m] * rp + k];
-            val = (col & 1) ? w.y : w.x;
-        }
-        U[idx] = val;
-    }
+    stage_group_sources(d.ut2, ps, rp, U);
     __syncthreads();
     const int planes = helm ? 2 : 1;
     const int col = lane & 31, kh = lane >> 5;
