@@ -2515,14 +2515,34 @@ k_lag_mfma16(const LDesc *__restrict__ descs, const IoEntry *__restrict__, const
         ps[tid] = e >= 0 ? d.far_src[e] : -1;
     }
     __syncthreads();
-    for (int idx = tid; idx < rp * 32; idx += blockDim.x) {
-        const int col = idx / rp, k = idx % rp, m = col >> 1;
-        float val = 0.f;
-        if (ps[m] >= 0) {
-            const float2 w = d.ut2[(int64_t)ps[m] * rp + k];
-            val = ((col & 1) ? w.y : w.x) * su;
+    {
+        // entry (m, k): both parts of u~_{s_m}[k] from one 8-byte load (consecutive threads, consecutive k), eight
+        // loads in flight per thread before the LDS writes
+        const int nel = rp * 16, nth = blockDim.x;
+        const gc2 src = gl(d.ut2);
+        for (int base = 0; base < nel; base += 8 * nth) {
+            v2f w[8];
+            int sm[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * nth + tid;
+                sm[u] = idx < nel ? ps[idx / rp] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * nth + tid, m = idx / rp, k = idx - m * rp;
+                w[u] = v2f{0.f, 0.f};
+                if (sm[u] >= 0) w[u] = src[(int64_t)sm[u] * rp + k];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * nth + tid, m = idx / rp, k = idx - m * rp;
+                if (idx < nel) {
+                    U16[(2 * m) * rp + k] = (_Float16)(w[u].x * su);
+                    U16[(2 * m + 1) * rp + k] = (_Float16)(w[u].y * su);
+                }
+            }
         }
-        U16[idx] = (_Float16)val;
     }
     __syncthreads();
     const int64_t per = (int64_t)rp * rp;
