@@ -81,15 +81,15 @@ PEAKS = {"mfma": (157.3, "TFLOP/s"), "mfma16": (2500.0, "TFLOP/s"), "alu": (PEAK
 # workload (profiles/traffic_apply_helmholtz_sphere_1M.md), scaled by what the counters read for a copy
 # kernel of known size (FETCH x 2.0, WRITE x 1.0), mean over the kernel's launches in one product.  Valid only
 # for the kernel source it was taken on.
-TRAFFIC_SOURCE_HASH = "cac6fcf4412628c0"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
+TRAFFIC_SOURCE_HASH = "30968b3507c02672"      # sha256 prefix of paper_1909_05600_amd/csrc/apply.hip
 TRAFFIC = {
-    "k_pw_forward_rings<2, false>": (35362.062 * 2.0 + 84612.375) * 1024.0,
-    "k_grid_phi_s<4>": (202950.000 * 2.0 + 24817.500) * 1024.0,
-    "k_grid_phit": (79125.688 * 2.0 + 295680.000) * 1024.0,
-    "k_near_sym<true, false>": (202149.750 * 2.0 + 84407.094) * 1024.0,
-    "k_pw_transfer_sib": (180764.083 * 2.0 + 56244.031) * 1024.0,
-    "k_pw_backward_rings<2, 2, false, 256>": (85138.812 * 2.0 + 24771.188) * 1024.0,
-    "k_pw_backward_rings<2, 2, false, 128>": (81294.750 * 2.0 + 25059.406) * 1024.0,
+    "k_pw_forward_rings<2, false>": (35356.281 * 2.0 + 84612.281) * 1024.0,
+    "k_grid_phi_s<4>": (202948.312 * 2.0 + 24879.312) * 1024.0,
+    "k_grid_phit": (79157.688 * 2.0 + 295680.000) * 1024.0,
+    "k_near_sym<true, false>": (201922.000 * 2.0 + 84416.875) * 1024.0,
+    "k_pw_transfer_sib": (182038.625 * 2.0 + 56244.031) * 1024.0,
+    "k_pw_backward_rings<2, 2, false, 256>": (85142.188 * 2.0 + 24771.500) * 1024.0,
+    "k_pw_backward_rings<2, 2, false, 128>": (81293.750 * 2.0 + 25059.125) * 1024.0,
 }
 
 
